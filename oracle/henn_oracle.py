@@ -1,0 +1,423 @@
+"""FP64 CPU oracle for HENN (arXiv 2505.17368) -- test infrastructure only.
+
+Only the test suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this module.  It shares no code with the HIP library
+and never imports it.  The heavy loops live in ``henn_oracle.c`` (plain C,
+FP64, built with gcc by :func:`build`); this module drives them in the order
+of the paper's algorithms:
+
+* :func:`eps_of` -- Eq. (1): eps(s) = c0 * d * log(s) / s * 2^m (natural log).
+* :func:`build_index` -- Alg. 1 (BuildHENN): layer i is an eps-net of layer
+  i-1 drawn by Alg. 2 (BuildEpsNetSampling, samples with replacement) and
+  verified against ``r`` sampled ring ranges (App. B.1 "Practical
+  Implementation", App. G.2); each layer then gets an exact kNN navigable
+  graph (App. B.2, App. G.4).  Layer sizes follow Cor. "layer-size":
+  ceil(|L_{i-1}| / 2^m) draws per layer.
+* :func:`search` -- Alg. 4 (Query) from the root down, ef=1 greedy on the
+  upper layers and a beam of max(ef, k) candidates on layer 0 (Sec. 2.2).
+* :func:`brute_force_knn` -- exact k-NN of the problem setting (Sec. 2).
+
+Readings where the paper is silent (all listed in the design notes):
+the entry node is the smallest id of the root layer; rings are the minimal
+heavy rings (a uniformly drawn centre in L_{i-1} and a uniformly drawn rank
+window of width floor(eps*s)+1); rings are fixed per layer and the sample is
+redrawn per attempt; after ``max_attempts`` failures the attempt with the
+most hits is kept and the layer is marked not verified; the layer loop stops
+before a layer whose draw count would fall below degree+1.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+import threading
+from concurrent.futures import ThreadPoolExecutor
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "henn_oracle.c")
+_LIB = os.path.join(_HERE, "libhenn_oracle.so")
+_lib = None
+_lock = threading.Lock()
+
+TAG_SAMPLE, TAG_RING_CENTRE, TAG_RING_START = 1, 2, 3
+L2, IP = 0, 1
+
+
+def build() -> str:
+    """Compile the C oracle with gcc (strict FP64: no contraction, no fast-math)."""
+    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-shared",
+           "-fPIC", "-o", _LIB + ".tmp", _SRC, "-lm"]
+    subprocess.check_call(cmd)
+    os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.POINTER
+        c_i64p, c_i32p, c_f64p, c_f32p = (P(ctypes.c_int64), P(ctypes.c_int32),
+                                          P(ctypes.c_double), P(ctypes.c_float))
+        lib.ho_philox4x64_10.argtypes = [P(ctypes.c_uint64), P(ctypes.c_uint64),
+                                         P(ctypes.c_uint64)]
+        lib.ho_stream_word.restype = ctypes.c_uint64
+        lib.ho_stream_word.argtypes = [ctypes.c_uint64] * 5
+        lib.ho_uniform_index.restype = ctypes.c_uint64
+        lib.ho_uniform_index.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+        lib.ho_draw_indices.argtypes = [ctypes.c_uint64] * 4 + [ctypes.c_int64, ctypes.c_int64,
+                                                                c_i64p]
+        lib.ho_distance.restype = ctypes.c_double
+        lib.ho_distance.argtypes = [c_f32p, c_f32p, ctypes.c_int, ctypes.c_int]
+        lib.ho_ring_members.restype = ctypes.c_int
+        lib.ho_ring_members.argtypes = [c_f32p, ctypes.c_int, ctypes.c_int, c_i32p,
+                                        ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                                        ctypes.c_int64, c_i64p, c_f64p]
+        lib.ho_knn_graph.restype = ctypes.c_int
+        lib.ho_knn_graph.argtypes = [c_f32p, ctypes.c_int, ctypes.c_int, c_i32p, ctypes.c_int64,
+                                     ctypes.c_int64, ctypes.c_int64, ctypes.c_int, c_i32p, c_f64p,
+                                     c_f64p, c_f64p]
+        lib.ho_search.restype = ctypes.c_int
+        lib.ho_search.argtypes = [c_f32p, ctypes.c_int, ctypes.c_int, ctypes.c_int, c_i64p,
+                                  P(c_i32p), P(c_i32p), c_i32p, P(c_f64p), c_f32p,
+                                  ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
+                                  ctypes.c_int, c_i32p, c_f64p, c_f64p, c_f64p, c_i64p]
+        lib.ho_brute_knn.restype = ctypes.c_int
+        lib.ho_brute_knn.argtypes = [c_f32p, ctypes.c_int64, ctypes.c_int, ctypes.c_int, c_f32p,
+                                     ctypes.c_int64, ctypes.c_int64, ctypes.c_int, c_i32p, c_f64p]
+        _lib = lib
+        return lib
+
+
+def _ptr(a: np.ndarray, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def default_threads() -> int:
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def _parallel(nitems: int, fn, threads: int | None = None, min_chunk: int = 1):
+    """Run fn(begin, end) over [0, nitems) in contiguous chunks on threads."""
+    threads = threads or default_threads()
+    if nitems <= 0:
+        return
+    nch = max(1, min(threads * 4, (nitems + min_chunk - 1) // min_chunk))
+    bounds = np.linspace(0, nitems, nch + 1).astype(np.int64)
+    if threads == 1 or nch == 1:
+        for b, e in zip(bounds[:-1], bounds[1:]):
+            fn(int(b), int(e))
+        return
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        futs = [ex.submit(fn, int(b), int(e)) for b, e in zip(bounds[:-1], bounds[1:]) if e > b]
+        for f in futs:
+            f.result()
+
+
+# ---------------------------------------------------------------------------
+# Randomness: Philox4x64-10, word q of stream (tag, layer, attempt)
+# ---------------------------------------------------------------------------
+
+def philox_block(counter, key):
+    lib = _load()
+    c = np.asarray(counter, dtype=np.uint64)
+    k = np.asarray(key, dtype=np.uint64)
+    out = np.zeros(4, dtype=np.uint64)
+    lib.ho_philox4x64_10(_ptr(c, ctypes.c_uint64), _ptr(k, ctypes.c_uint64),
+                         _ptr(out, ctypes.c_uint64))
+    return out
+
+
+def stream_word(seed, tag, layer, attempt, q) -> int:
+    return int(_load().ho_stream_word(seed, tag, layer, attempt, q))
+
+
+def uniform_index(w: int, s: int) -> int:
+    return int(_load().ho_uniform_index(w, s))
+
+
+def draw_indices(seed, tag, layer, attempt, s, count) -> np.ndarray:
+    out = np.zeros(max(count, 0), dtype=np.int64)
+    if count > 0:
+        _load().ho_draw_indices(seed, tag, layer, attempt, s, count, _ptr(out, ctypes.c_int64))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Eq. (1) and the layer schedule
+# ---------------------------------------------------------------------------
+
+def eps_of(s: int, d: int, m: int, c0: float) -> float:
+    """Eq. (1): eps(s) = c0 * d * log(s) / s * 2^m, natural logarithm."""
+    return c0 * d * math.log(s) / s * (2 ** m)
+
+
+def window_of(eps: float, s: int) -> int:
+    """Fewest points a heavy ring can hold: |R| > eps*s  <=>  |R| >= floor(eps*s)+1."""
+    return int(math.floor(eps * s)) + 1
+
+
+@dataclass
+class BuildParams:
+    metric: int = L2
+    max_layers: int = -1         # upper layers allowed; < 0: until the draw count
+                                 # would drop below degree+1
+    m: int = 4                   # exponential decay, 2^m = 16
+    c0: float = 1.0
+    eps_override: float = 0.0
+    num_rings: int = 64          # r, the "range size" hyperparameter
+    max_attempts: int = 64
+    degree: int = 16
+    seed: int = 0
+
+
+@dataclass
+class LayerInfo:
+    size: int
+    draws: int
+    eps: float
+    window: int
+    attempts: int
+    hits: int
+    status: str                  # "base", "vacuous", "verified", "not_verified"
+    ring_margin: float = math.inf
+
+
+@dataclass
+class OracleIndex:
+    X: np.ndarray
+    metric: int
+    degree: int
+    members: list = field(default_factory=list)     # int32 ascending global ids per layer
+    adj: list = field(default_factory=list)         # int32 [size, degree] local indices, -1 pad
+    adj_dist: list = field(default_factory=list)    # float64 [size, degree]
+    adj_margin: list = field(default_factory=list)  # float64 [size] margin at the R / R+1 cut
+    order_margin: list = field(default_factory=list)  # float64 [size] min margin in first R+1
+    info: list = field(default_factory=list)
+
+    @property
+    def num_layers(self) -> int:
+        return len(self.members)
+
+
+def ring_members(X, metric, members, centre_local, a, w):
+    """Local indices of ring ranks [a, a+w-1] around L[centre_local] (rank 0 = centre)."""
+    lib = _load()
+    out = np.zeros(w, dtype=np.int64)
+    mg = np.zeros(1, dtype=np.float64)
+    rc = lib.ho_ring_members(_ptr(X, ctypes.c_float), X.shape[1], metric,
+                             _ptr(members, ctypes.c_int32), len(members), centre_local, a, w,
+                             _ptr(out, ctypes.c_int64), _ptr(mg, ctypes.c_double))
+    if rc != 0:
+        raise ValueError(f"ring_members failed ({rc})")
+    return out, float(mg[0])
+
+
+def sample_layer(X, prev, layer, d, p: BuildParams, threads=None):
+    """Alg. 2 with the practical IsEpsNet of App. B.1 for one layer.
+
+    Returns (local indices of the accepted sample, ascending, distinct), LayerInfo.
+    """
+    s = len(prev)
+    D = -(-s // (2 ** p.m))
+    eps = p.eps_override if p.eps_override > 0 else eps_of(s, d, p.m, p.c0)
+    w = window_of(eps, s)
+    if w > s:
+        draws = draw_indices(p.seed, TAG_SAMPLE, layer, 0, s, D)
+        return np.unique(draws), LayerInfo(0, D, eps, w, 1, 0, "vacuous")
+    r = p.num_rings
+    centres = draw_indices(p.seed, TAG_RING_CENTRE, layer, 0, s, r)
+    starts = draw_indices(p.seed, TAG_RING_START, layer, 0, s - w + 1, r)
+    rings = [None] * r
+    margins = np.zeros(r)
+
+    def one(b, e):
+        for j in range(b, e):
+            rings[j], margins[j] = ring_members(X, p.metric, prev, int(centres[j]),
+                                                int(starts[j]), w)
+    _parallel(r, one, threads)
+    best_t, best_hits, best = -1, -1, None
+    for t in range(p.max_attempts):
+        draws = draw_indices(p.seed, TAG_SAMPLE, layer, t, s, D)
+        sel = np.zeros(s, dtype=bool)
+        sel[draws] = True
+        hits = int(sum(bool(sel[ring].any()) for ring in rings))
+        if hits > best_hits:
+            best_t, best_hits, best = t, hits, draws
+        if hits == r:
+            return np.unique(draws), LayerInfo(0, D, eps, w, t + 1, hits, "verified",
+                                               float(margins.min()))
+    return np.unique(best), LayerInfo(0, D, eps, w, p.max_attempts, best_hits, "not_verified",
+                                      float(margins.min()))
+
+
+def knn_graph(X, metric, members, R, threads=None):
+    """Exact kNN graph of one layer (App. B.2): local indices, (dist, id) order.
+
+    Returns (adjacency, FP64 distances, cut margin, order margin)."""
+    lib = _load()
+    s = len(members)
+    adj = np.full((s, R), -1, dtype=np.int32)
+    ad = np.full((s, R), np.inf)
+    cut = np.full(s, np.inf)
+    order = np.full(s, np.inf)
+
+    def one(b, e):
+        rc = lib.ho_knn_graph(_ptr(X, ctypes.c_float), X.shape[1], metric,
+                              _ptr(members, ctypes.c_int32), s, b, e, R,
+                              _ptr(adj, ctypes.c_int32), _ptr(ad, ctypes.c_double),
+                              _ptr(cut, ctypes.c_double), _ptr(order, ctypes.c_double))
+        if rc != 0:
+            raise RuntimeError("knn_graph failed")
+    _parallel(s, one, threads, min_chunk=16)
+    return adj, ad, cut, order
+
+
+def build_layers(X: np.ndarray, p: BuildParams, threads=None):
+    """Alg. 1 layer loop: returns ascending member lists and per-layer info."""
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    n, d = X.shape
+    members = [np.arange(n, dtype=np.int32)]
+    infos = [LayerInfo(n, n, 0.0, 0, 0, 0, "base")]
+    i = 1
+    while True:
+        s = len(members[-1])
+        D = -(-s // (2 ** p.m))
+        if D < p.degree + 1 or (p.max_layers >= 0 and i > p.max_layers):
+            break
+        local, info = sample_layer(X, members[-1], i, d, p, threads)
+        members.append(members[-1][local].astype(np.int32))
+        info.size = len(local)
+        infos.append(info)
+        i += 1
+    return members, infos
+
+
+def build_index(X: np.ndarray, p: BuildParams | None = None, threads=None) -> OracleIndex:
+    """Alg. 1 (BuildHENN) with exact kNN graphs per layer."""
+    p = p or BuildParams()
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    members, infos = build_layers(X, p, threads)
+    idx = OracleIndex(X=X, metric=p.metric, degree=p.degree, members=members, info=infos)
+    for mb in members:
+        a, ad, cut, order = knn_graph(X, p.metric, mb, p.degree, threads)
+        idx.adj.append(a)
+        idx.adj_dist.append(ad)
+        idx.adj_margin.append(cut)
+        idx.order_margin.append(order)
+    return idx
+
+
+def index_from_arrays(X, metric, members, adj, degree=None) -> OracleIndex:
+    """Wrap an index given as data (e.g. exported by another builder)."""
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    members = [np.ascontiguousarray(m, dtype=np.int32) for m in members]
+    adj = [np.ascontiguousarray(a, dtype=np.int32) for a in adj]
+    deg = degree if degree is not None else adj[0].shape[1]
+    return OracleIndex(X=X, metric=metric, degree=deg, members=members, adj=adj)
+
+
+@dataclass
+class SearchResult:
+    ids: np.ndarray          # int32 [nq, k]
+    dist: np.ndarray         # float64 [nq, k]
+    margin: np.ndarray       # float64 [nq] min decision margin over the trace
+    adj_margin: np.ndarray   # float64 [nq] min adjacency margin of expanded nodes
+    counters: np.ndarray     # int64 [nq, 4]: expansions, evals (all layers), (layer 0)
+
+
+def search(idx: OracleIndex, Q: np.ndarray, k: int, ef: int, ef_upper: int = 1,
+           threads=None, q_range=None) -> SearchResult:
+    """Alg. 4 Query with the Sec. 2.2 candidate set; see module docstring."""
+    lib = _load()
+    Q = np.ascontiguousarray(Q, dtype=np.float32)
+    X = idx.X
+    nq = Q.shape[0]
+    L = idx.num_layers
+    sizes = np.array([len(m) for m in idx.members], dtype=np.int64)
+    degs = np.array([a.shape[1] for a in idx.adj], dtype=np.int32)
+    P32 = ctypes.POINTER(ctypes.c_int32)
+    PF64 = ctypes.POINTER(ctypes.c_double)
+    mem_arr = (P32 * L)(*[_ptr(m, ctypes.c_int32) for m in idx.members])
+    adj_arr = (P32 * L)(*[_ptr(a, ctypes.c_int32) for a in idx.adj])
+    if idx.adj_margin:
+        am_arr = (PF64 * L)(*[_ptr(a, ctypes.c_double) for a in idx.adj_margin])
+    else:
+        am_arr = None
+    ids = np.full((nq, k), -1, dtype=np.int32)
+    dist = np.full((nq, k), np.inf)
+    margin = np.full(nq, np.inf)
+    amargin = np.full(nq, np.inf)
+    counters = np.zeros((nq, 4), dtype=np.int64)
+    b0, e0 = (0, nq) if q_range is None else q_range
+
+    def one(b, e):
+        rc = lib.ho_search(_ptr(X, ctypes.c_float), X.shape[1], idx.metric, L,
+                           _ptr(sizes, ctypes.c_int64), mem_arr, adj_arr,
+                           _ptr(degs, ctypes.c_int32), am_arr, _ptr(Q, ctypes.c_float),
+                           b0 + b, b0 + e, k, ef, ef_upper, _ptr(ids, ctypes.c_int32),
+                           _ptr(dist, ctypes.c_double), _ptr(margin, ctypes.c_double),
+                           _ptr(amargin, ctypes.c_double), _ptr(counters, ctypes.c_int64))
+        if rc != 0:
+            raise RuntimeError(f"search failed ({rc})")
+    _parallel(e0 - b0, one, threads, min_chunk=4)
+    return SearchResult(ids, dist, margin, amargin, counters)
+
+
+def brute_force_knn(X: np.ndarray, Q: np.ndarray, k: int, metric: int = L2, threads=None):
+    """Exact k-NN by FP64 brute force, ties by id (Sec. 2 problem setting)."""
+    lib = _load()
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    Q = np.ascontiguousarray(Q, dtype=np.float32)
+    nq = Q.shape[0]
+    ids = np.full((nq, k), -1, dtype=np.int32)
+    dist = np.full((nq, k), np.inf)
+
+    def one(b, e):
+        rc = lib.ho_brute_knn(_ptr(X, ctypes.c_float), X.shape[0], X.shape[1], metric,
+                              _ptr(Q, ctypes.c_float), b, e, k, _ptr(ids, ctypes.c_int32),
+                              _ptr(dist, ctypes.c_double))
+        if rc != 0:
+            raise RuntimeError("brute_knn failed")
+    _parallel(nq, one, threads)
+    return ids, dist
+
+
+def distance(a: np.ndarray, b: np.ndarray, metric: int = L2) -> float:
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    b = np.ascontiguousarray(b, dtype=np.float32)
+    return float(_load().ho_distance(_ptr(a, ctypes.c_float), _ptr(b, ctypes.c_float),
+                                     a.shape[0], metric))
+
+
+def recall_at_k(found_ids: np.ndarray, true_dist: np.ndarray, X: np.ndarray, Q: np.ndarray,
+                metric: int = L2) -> float:
+    """Tie-tolerant Recall@k (Sec. 2): a returned id counts when its exact FP64
+    distance is at most the true k-th distance."""
+    nq, k = found_ids.shape
+    hits = 0
+    for i in range(nq):
+        kth = true_dist[i, k - 1]
+        for j in range(k):
+            u = int(found_ids[i, j])
+            if u < 0:
+                continue
+            if distance(Q[i], X[u], metric) <= kth:
+                hits += 1
+    return hits / float(nq * k)
+
+
+def near_tie(res: SearchResult, tol: float = 1e-5) -> np.ndarray:
+    """Queries whose trace holds a decision with relative margin <= tol, or
+    that expanded a node whose R-th / (R+1)-th neighbour are that close (a
+    near tie inside a list cannot matter: the order of neighbours within one
+    expansion does not change the result)."""
+    return (res.margin <= tol) | (res.adj_margin <= tol)

@@ -1,0 +1,408 @@
+"""Pins of the FP64 oracle against things other than itself.
+
+Each test ties one oracle function to the paper's definitions, a closed form,
+an independent library routine or a brute-force recomputation:
+
+* Philox4x64-10 against NumPy's ``numpy.random.Philox`` (an independent
+  implementation of Salmon et al., SC'11; NumPy increments its counter before
+  the first block, so block B(x) is NumPy's first output for counter x-1).
+* Eq. (1) against hand-computed values.
+* Alg. 2 layer samples against ``np.unique`` of NumPy-Philox draws.
+* Ring ranges (Def. Ring Ranges) and the hit test against a NumPy lexsort.
+* The exact kNN graph (App. B.2) against NumPy all-pairs + lexsort.
+* Search: complete graph => exact k-NN (App. B.2: the complete graph is
+  trivially navigable); ef >= reachable set => exact k-NN over that set;
+  ef = 1 => Alg. 4 GreedySearch written out separately; the equivalences the
+  GPU kernel relies on (flagged result list, any neighbour order, a lossy
+  visited table) against a separate implementation.
+* Brute-force k-NN and the tie-tolerant Recall@k (Sec. 2).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as wl
+
+MASK64 = (1 << 64) - 1
+
+
+def numpy_block(counter, key):
+    x = sum(int(c) << (64 * i) for i, c in enumerate(counter))
+    x = (x - 1) % (1 << 256)
+    c = np.array([(x >> (64 * i)) & MASK64 for i in range(4)], dtype=np.uint64)
+    bg = np.random.Philox(key=np.array(key, dtype=np.uint64), counter=c)
+    return [int(v) for v in bg.random_raw(4)]
+
+
+def numpy_stream(seed, tag, layer, attempt, count):
+    """Words 0..count-1 of stream (tag, layer, attempt) from NumPy's Philox."""
+    x = (0 + (layer << 64) + (attempt << 128) + (tag << 192) - 1) % (1 << 256)
+    c = np.array([(x >> (64 * i)) & MASK64 for i in range(4)], dtype=np.uint64)
+    bg = np.random.Philox(key=np.array([seed, 0], dtype=np.uint64), counter=c)
+    nblk = (count + 3) // 4
+    return [int(v) for v in bg.random_raw(4 * nblk)[:count]]
+
+
+def numpy_uindex(words, s):
+    return np.array([(w * s) >> 64 for w in words], dtype=np.int64)
+
+
+def d64_seq(a, b, metric=0):
+    """FP64 distance summed in coordinate order (same rounding as the C loop)."""
+    acc = 0.0
+    if metric == 0:
+        for x, y in zip(a.tolist(), b.tolist()):
+            t = float(x) - float(y)
+            acc += t * t
+        return acc
+    for x, y in zip(a.tolist(), b.tolist()):
+        acc += float(x) * float(y)
+    return -acc
+
+
+# ---------------------------------------------------------------- Philox ---
+
+@pytest.mark.parametrize("counter,key", [
+    ([0, 0, 0, 0], [0, 0]),
+    ([1, 0, 0, 0], [5, 0]),
+    ([0, 3, 7, 1], [123456789, 0]),
+    ([MASK64, MASK64, 2, 3], [2**63 + 11, 0]),
+    ([17, 0, 0, 2], [MASK64, 0]),
+])
+def test_philox_block_matches_numpy(oracle, counter, key):
+    got = [int(v) for v in oracle.philox_block(counter, key)]
+    assert got == numpy_block(counter, key)
+
+
+def test_stream_words_and_uniform_index(oracle):
+    for seed, tag, layer, attempt in [(0, 1, 1, 0), (7, 2, 3, 0), (99, 1, 2, 5)]:
+        ref = numpy_stream(seed, tag, layer, attempt, 23)
+        got = [oracle.stream_word(seed, tag, layer, attempt, q) for q in range(23)]
+        assert got == ref
+        for s in (1, 2, 17, 10_000, 2**31 - 1, 2**40 + 3):
+            got_u = oracle.draw_indices(seed, tag, layer, attempt, s, 23)
+            assert np.array_equal(got_u, numpy_uindex(ref, s))
+            assert got_u.min() >= 0 and got_u.max() < s
+
+
+def test_uniform_index_closed_form(oracle):
+    assert oracle.uniform_index(0, 10) == 0
+    assert oracle.uniform_index(MASK64, 10) == 9
+    assert oracle.uniform_index(1 << 63, 10) == 5
+    assert oracle.uniform_index(MASK64, 1) == 0
+
+
+# ---------------------------------------------------------------- Eq. (1) --
+
+def test_eps_schedule_values(oracle):
+    # eps(s) = c0 * d * ln(s) / s * 2^m
+    assert oracle.eps_of(10_000, 32, 4, 1.0) == pytest.approx(32 * math.log(1e4) / 1e4 * 16)
+    assert oracle.eps_of(10_000, 32, 4, 1.0) == pytest.approx(0.471569, abs=1e-6)
+    assert oracle.window_of(oracle.eps_of(10_000, 32, 4, 1.0), 10_000) == 4716
+    assert oracle.eps_of(1_000_000, 128, 4, 1.0) == pytest.approx(0.0282942, abs=1e-6)
+    # a heavy ring holds more than eps*s points
+    assert oracle.window_of(0.5, 10) == 6
+    assert oracle.window_of(0.05, 100) == 6
+
+
+# ------------------------------------------------------- Alg. 2 sampling --
+
+def _brute_rings(X, members, centres, starts, w, metric=0):
+    rings = []
+    for c, a in zip(centres, starts):
+        dc = np.array([d64_seq(X[members[c]], X[members[j]], metric)
+                       for j in range(len(members))])
+        order = np.lexsort((members, dc))
+        rings.append(set(order[a:a + w].tolist()))
+    return rings
+
+
+def test_layer_sample_vacuous_matches_numpy_unique(oracle):
+    X = wl.uniform(3000, 32, 0)
+    p = oracle.BuildParams(degree=8, seed=11)
+    members, infos = oracle.build_layers(X, p)
+    assert len(members) >= 2
+    for i in range(1, len(members)):
+        s = len(members[i - 1])
+        D = -(-s // 16)
+        assert infos[i].status == "vacuous"      # c0 = 1 makes eps >= 1 at this size
+        draws = numpy_uindex(numpy_stream(11, 1, i, 0, D), s)
+        assert np.array_equal(members[i], members[i - 1][np.unique(draws)])
+        assert np.all(np.diff(members[i]) > 0)
+        assert np.isin(members[i], members[i - 1]).all()     # nesting L_i in L_{i-1}
+
+
+def test_layer_sample_verified_las_vegas(oracle):
+    """With a small eps the Las-Vegas loop repeats; the accepted attempt is the
+    first whose sample hits every sampled ring (checked by brute force)."""
+    X = wl.uniform(2000, 3, 0)
+    s, D = 2000, 125
+    p = oracle.BuildParams(degree=8, seed=3, eps_override=0.031, num_rings=64,
+                           max_layers=1)
+    members, infos = oracle.build_layers(X, p)
+    info = infos[1]
+    w = oracle.window_of(0.031, s)
+    assert info.window == w == 63
+    r = 64
+    centres = numpy_uindex(numpy_stream(3, 2, 1, 0, r), s)
+    starts = numpy_uindex(numpy_stream(3, 3, 1, 0, r), s - w + 1)
+    rings = _brute_rings(X, members[0], centres, starts, w)
+    accepted = None
+    for t in range(p.max_attempts):
+        draws = set(numpy_uindex(numpy_stream(3, 1, 1, t, D), s).tolist())
+        hits = sum(1 for ring in rings if ring & draws)
+        if hits == r:
+            accepted = t
+            break
+    assert accepted is not None and accepted >= 1, "fixture must exercise a repeat"
+    assert info.status == "verified" and info.attempts == accepted + 1
+    draws = numpy_uindex(numpy_stream(3, 1, 1, accepted, D), s)
+    assert np.array_equal(members[1], np.unique(draws).astype(np.int32))
+
+
+def test_layer_sample_not_verified_keeps_best(oracle):
+    X = wl.uniform(800, 2, 0)
+    p = oracle.BuildParams(degree=8, seed=5, eps_override=0.002, num_rings=64,
+                           max_attempts=4, max_layers=1)
+    members, infos = oracle.build_layers(X, p)
+    s, D = 800, 50
+    w = infos[1].window
+    centres = numpy_uindex(numpy_stream(5, 2, 1, 0, 64), s)
+    starts = numpy_uindex(numpy_stream(5, 3, 1, 0, 64), s - w + 1)
+    rings = _brute_rings(X, members[0], centres, starts, w)
+    hits = []
+    for t in range(4):
+        draws = set(numpy_uindex(numpy_stream(5, 1, 1, t, D), s).tolist())
+        hits.append(sum(1 for ring in rings if ring & draws))
+    assert max(hits) < 64
+    best = int(np.argmax(hits))      # lowest attempt with the most hits
+    assert infos[1].status == "not_verified" and infos[1].hits == hits[best]
+    draws = numpy_uindex(numpy_stream(5, 1, 1, best, D), s)
+    assert np.array_equal(members[1], np.unique(draws).astype(np.int32))
+
+
+def test_ring_members_brute_force(oracle):
+    X = wl.uniform(500, 5, 3)
+    members = np.arange(0, 500, 2, dtype=np.int32)      # a layer = every other point
+    for c, a, w in [(0, 0, 10), (17, 5, 40), (249, 200, 50), (3, 0, 250)]:
+        got, _ = oracle.ring_members(X, 0, members, c, a, w)
+        ref = _brute_rings(X, members, [c], [a], w)[0]
+        assert set(got.tolist()) == ref
+        if a == 0:
+            assert got[0] == c        # rank 0 is the centre itself
+
+
+def test_eps_net_property_exhaustive_on_tiny_input(oracle):
+    """When every point-centred minimal heavy ring is checked, an accepted
+    sample is an eps-net for those rings (Def. eps-net, App. B.1)."""
+    X = wl.uniform(160, 2, 9)
+    s = 160
+    eps = 0.2
+    w = oracle.window_of(eps, s)
+    # exhaustive verification: one ring per (centre, start)
+    members = np.arange(s, dtype=np.int32)
+    rings = [set(oracle.ring_members(X, 0, members, c, a, w)[0].tolist())
+             for c in range(s) for a in range(0, s - w + 1)]
+    D = 60
+    for t in range(64):
+        draws = set(oracle.draw_indices(1, 1, 1, t, s, D).tolist())
+        if all(r & draws for r in rings):
+            break
+    else:
+        pytest.fail("no attempt verified")
+    # the accepted sample hits every heavy ring whose centre is a data point
+    # and whose size exceeds eps*s (bigger rings contain a minimal one)
+    for c in range(0, s, 7):
+        dc = np.array([d64_seq(X[c], X[j]) for j in range(s)])
+        order = np.lexsort((np.arange(s), dc))
+        for a in range(0, s - w, 9):
+            for extra in (0, 5):
+                if a + w + extra <= s:
+                    assert set(order[a:a + w + extra].tolist()) & draws
+
+
+# --------------------------------------------------------- kNN graph -------
+
+@pytest.mark.parametrize("metric", [0, 1])
+def test_knn_graph_matches_numpy(oracle, metric):
+    X = wl.uniform(300, 8, 4) - 0.5
+    members = np.arange(0, 300, 1, dtype=np.int32)[::3].copy()
+    R = 6
+    adj, ad, cut, order = oracle.knn_graph(X, metric, members, R)
+    Y = X[members].astype(np.float64)
+    if metric == 0:
+        D = ((Y[:, None, :] - Y[None, :, :]) ** 2).sum(-1)
+    else:
+        D = -(Y @ Y.T)
+    for v in range(len(members)):
+        dv = D[v].copy()
+        dv[v] = np.inf
+        ref = np.lexsort((np.arange(len(members)), dv))[:R]
+        assert np.array_equal(adj[v], ref)
+        assert np.allclose(ad[v], dv[ref], rtol=1e-12, atol=1e-12)
+
+
+def test_knn_graph_small_layer_pads(oracle):
+    X = wl.uniform(5, 3, 1)
+    adj, _, _, _ = oracle.knn_graph(X, 0, np.arange(5, dtype=np.int32), 6)
+    assert (adj[:, 4:] == -1).all() and (adj[:, :4] >= 0).all()
+
+
+# --------------------------------------------------------- search ----------
+
+def _one_layer_index(oracle, X, R, metric=0):
+    p = oracle.BuildParams(degree=R, max_layers=0, metric=metric)
+    return oracle.build_index(X, p)
+
+
+@pytest.mark.parametrize("metric", [0, 1])
+def test_complete_graph_gives_exact_knn(oracle, metric):
+    X = wl.uniform(60, 6, 2) - 0.3
+    Q = wl.uniform(25, 6, 3) - 0.3
+    idx = _one_layer_index(oracle, X, 59, metric)
+    assert idx.num_layers == 1
+    res = oracle.search(idx, Q, k=10, ef=10)
+    for i in range(len(Q)):
+        dq = np.array([d64_seq(Q[i], X[j], metric) for j in range(60)])
+        ref = np.lexsort((np.arange(60), dq))[:10]
+        assert np.array_equal(res.ids[i], ref)
+        assert np.array_equal(res.dist[i], dq[ref])
+
+
+def test_large_ef_gives_exact_knn_over_reachable_set(oracle):
+    X = wl.uniform(150, 5, 5)
+    Q = wl.uniform(20, 5, 6)
+    idx = _one_layer_index(oracle, X, 3)
+    adj = idx.adj[0]
+    seen, stack = {0}, [0]
+    while stack:
+        v = stack.pop()
+        for u in adj[v]:
+            if u >= 0 and u not in seen:
+                seen.add(int(u))
+                stack.append(int(u))
+    reach = np.array(sorted(seen))
+    res = oracle.search(idx, Q, k=8, ef=200)
+    for i in range(len(Q)):
+        dq = np.array([d64_seq(Q[i], X[j]) for j in reach])
+        ref = reach[np.lexsort((reach, dq))][:8]
+        assert np.array_equal(res.ids[i, :len(ref)], ref)
+        if len(ref) < 8:
+            assert (res.ids[i, len(ref):] == -1).all()
+
+
+def _greedy_alg4(X, members, adj, q, v_global):
+    """Alg. 4 GreedySearch on one layer under the (dist, id) order."""
+    pos = {int(g): i for i, g in enumerate(members)}
+    nxt = v_global
+    while True:
+        cur = nxt
+        key_cur = (d64_seq(q, X[cur]), cur)
+        nbrs = [int(members[u]) for u in adj[pos[cur]] if u >= 0]
+        if not nbrs:
+            return cur
+        nxt = min(nbrs, key=lambda u: (d64_seq(q, X[u]), u))
+        if (d64_seq(q, X[nxt]), nxt) >= key_cur:
+            return cur
+
+
+def test_ef1_is_alg4_greedy_search(oracle):
+    X = wl.uniform(4000, 4, 7)
+    Q = wl.uniform(40, 4, 8)
+    idx = oracle.build_index(X, oracle.BuildParams(degree=8, seed=1))
+    assert idx.num_layers >= 3
+    res = oracle.search(idx, Q, k=1, ef=1, ef_upper=1)
+    for i in range(len(Q)):
+        v = int(idx.members[-1][0])          # smallest id of the root layer
+        for lay in range(idx.num_layers - 1, -1, -1):
+            v = _greedy_alg4(X, idx.members[lay], idx.adj[lay], Q[i], v)
+        assert res.ids[i, 0] == v
+
+
+def _flagged_w_search(X, members, adj, q, entry_local, ef, perm_rng, vis_slots):
+    """Single-layer beam search in the form the GPU kernel uses: one sorted
+    result list W with an 'expanded' flag per entry, a lossy direct-mapped
+    visited table, duplicate check against W, neighbours in random order."""
+    def key(l):
+        return (d64_seq(q, X[members[l]]), int(members[l]))
+    table = [-1] * vis_slots
+    W = [(key(entry_local), entry_local, False)]
+    table[entry_local % vis_slots] = entry_local
+    while True:
+        pos = next((i for i, w in enumerate(W) if not w[2]), None)
+        if pos is None:
+            break
+        kc, c, _ = W[pos]
+        W[pos] = (kc, c, True)
+        nb = [int(u) for u in adj[c] if u >= 0]
+        perm_rng.shuffle(nb)
+        for u in nb:
+            if table[(u * 2654435761) % vis_slots] == u:
+                continue
+            table[(u * 2654435761) % vis_slots] = u
+            ku = key(u)
+            if any(w[1] == u for w in W):
+                continue
+            if len(W) < ef or ku < W[-1][0]:
+                W.append((ku, u, False))
+                W.sort(key=lambda t: t[0])
+                del W[ef:]
+    return W
+
+
+@pytest.mark.parametrize("vis_slots", [4096, 7])
+def test_flagged_list_and_lossy_visited_equivalence(oracle, vis_slots):
+    X = wl.uniform(250, 4, 10)
+    Q = wl.uniform(15, 4, 11)
+    idx = _one_layer_index(oracle, X, 5)
+    res = oracle.search(idx, Q, k=6, ef=12)
+    rng = np.random.default_rng(0)
+    for i in range(len(Q)):
+        W = _flagged_w_search(X, idx.members[0], idx.adj[0], Q[i], 0, 12, rng, vis_slots)
+        got = [int(idx.members[0][w[1]]) for w in W[:6]]
+        assert got == res.ids[i].tolist()
+
+
+def test_counters_and_margins(oracle):
+    X = wl.uniform(500, 4, 12)
+    X[7] = X[3]          # an exact duplicate forces a zero-margin decision
+    Q = np.repeat(X[3:4] + 1e-3, 4, axis=0)
+    idx = oracle.build_index(X, oracle.BuildParams(degree=8))
+    res = oracle.search(idx, Q, k=5, ef=16)
+    assert oracle.near_tie(res).all()
+    assert (res.counters[:, 0] >= 1).all()
+    assert (res.counters[:, 1] >= res.counters[:, 0]).all()
+    assert (res.counters[:, 2] <= res.counters[:, 0]).all()
+
+
+# ------------------------------------------------- brute force, recall ----
+
+@pytest.mark.parametrize("metric", [0, 1])
+def test_brute_force_knn_matches_numpy(oracle, metric):
+    X = wl.uniform(400, 7, 13) - 0.5
+    Q = wl.uniform(30, 7, 14) - 0.5
+    ids, dist = oracle.brute_force_knn(X, Q, 12, metric)
+    Xd, Qd = X.astype(np.float64), Q.astype(np.float64)
+    D = ((Qd[:, None, :] - Xd[None, :, :]) ** 2).sum(-1) if metric == 0 else -(Qd @ Xd.T)
+    for i in range(len(Q)):
+        ref = np.lexsort((np.arange(400), D[i]))[:12]
+        assert np.array_equal(ids[i], ref)
+        assert np.allclose(dist[i], D[i][ref], rtol=1e-12, atol=1e-12)
+
+
+def test_brute_force_pads_when_k_exceeds_n(oracle):
+    X = wl.uniform(3, 2, 1)
+    ids, dist = oracle.brute_force_knn(X, X[:1], 5)
+    assert ids[0, 0] == 0 and (ids[0, 3:] == -1).all() and np.isinf(dist[0, 3:]).all()
+
+
+def test_recall_tie_tolerant(oracle):
+    X = np.array([[0, 0], [1, 0], [0, 1], [3, 3]], dtype=np.float32)
+    Q = np.array([[0, 0]], dtype=np.float32)
+    _, td = oracle.brute_force_knn(X, Q, 2)
+    # ids 1 and 2 tie at distance 1: either one completes the top-2
+    assert oracle.recall_at_k(np.array([[0, 2]]), td, X, Q) == 1.0
+    assert oracle.recall_at_k(np.array([[0, 1]]), td, X, Q) == 1.0
+    assert oracle.recall_at_k(np.array([[0, 3]]), td, X, Q) == 0.5
+    assert oracle.recall_at_k(np.array([[-1, 3]]), td, X, Q) == 0.0
