@@ -1,0 +1,182 @@
+/*
+ * henn.h -- C ABI of the MI355X (gfx950) HENN library.
+ *
+ * HENN (arXiv 2505.17368) answers k-nearest-neighbour queries over points
+ * X in R^d (Sec. 2, "Data Model" and "Problem setting") with a hierarchy of
+ * layers L_0 = X, L_1, ..., L_L where each L_i is an eps-net of L_{i-1} for
+ * ring ranges (Def. HENN, Def. Ring Ranges, Alg. 1), each layer carries a
+ * navigable graph (App. B.2; here the exact kNN graph of App. G.4), and a
+ * query descends greedily from the root to layer 0 (Alg. 4, Sec. 2.2).
+ *
+ * Conventions for every entry point:
+ *  - C linkage; no exception crosses the boundary.
+ *  - Every call returns a henn_status.  On error the outputs are untouched
+ *    and henn_last_error() (thread-local) describes the failure.
+ *  - Device pointers are HIP device addresses (e.g. a torch tensor's
+ *    data_ptr()); host pointers are ordinary process memory.  Each argument
+ *    below says which one it is.
+ *  - hip_stream is a hipStream_t (0 = the null stream).  Work is enqueued on
+ *    it; henn_search_batch returns without waiting.
+ *  - Distances returned are squared L2 (the paper's l2 norm with the
+ *    monotone square root dropped) or -<q, x> for inner product (the angular
+ *    metric of App. G.4 on unit vectors).  Every ordering is by the
+ *    lexicographic key (distance, point id), so ties go to the lower id.
+ */
+#ifndef HENN_H
+#define HENN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct henn_index henn_index; /* opaque; owned by the library */
+
+typedef enum {
+  HENN_OK = 0,
+  HENN_E_INVAL = 1,       /* bad argument: sizes, null pointers, struct_size */
+  HENN_E_NOMEM = 2,       /* device or host allocation failed */
+  HENN_E_DEVICE = 3,      /* a HIP runtime call failed */
+  HENN_E_UNSUPPORTED = 4, /* valid but not supported by this build */
+  HENN_W_NOT_VERIFIED = 100 /* warning: index usable, some layer kept its best
+                               unverified sample (Alg. 2 attempt cap reached) */
+} henn_status;
+
+typedef enum { HENN_L2 = 0, HENN_IP = 1 } henn_metric;
+
+/* Storage of the vectors the search traverses.  F32 is the plain path.
+ * BF16 and FP8_E4M3 (OCP, max 448) keep one FP32 scale per vector, compute
+ * distances in FP32, and keep an FP32 copy for the final re-rank. */
+typedef enum { HENN_F32 = 0, HENN_BF16 = 1, HENN_FP8_E4M3 = 2 } henn_storage;
+
+/* Navigable graph per layer (App. B.2): exact kNN, or kNN plus reverse
+ * edges (deduplicated, kept in (distance, id) order, capped at max_degree). */
+typedef enum { HENN_GRAPH_KNN = 0, HENN_GRAPH_KNN_SYM = 1 } henn_graph;
+
+#define HENN_MAX_LAYERS 16
+
+typedef struct {
+  uint32_t struct_size;   /* = sizeof(henn_build_params) */
+  int32_t metric;         /* henn_metric */
+  int32_t max_layers;     /* L of Alg. 1: upper layers allowed; < 0: build until
+                             ceil(|L_{i-1}| / 2^m) < degree + 1 */
+  int32_t m;              /* exponential decay of Eq. (1) / Lemma "layer-size";
+                             each layer draws ceil(|L_{i-1}| / 2^m) samples */
+  double c0;              /* constant of Eq. (1), natural logarithm */
+  double eps_override;    /* > 0: use this eps on every layer instead of Eq. (1) */
+  int32_t num_rings;      /* r: ring ranges checked per layer (App. G.2) */
+  int32_t max_attempts;   /* Las-Vegas cap of Alg. 2's repeat loop */
+  int32_t degree;         /* R: kNN graph degree */
+  int32_t max_degree;     /* row capacity for HENN_GRAPH_KNN_SYM (>= degree) */
+  int32_t graph;          /* henn_graph */
+  int32_t storage;        /* henn_storage */
+  uint64_t seed;          /* key word 0 of the Philox4x64-10 stream (word 1 = 0) */
+} henn_build_params;
+
+/* Search flags */
+#define HENN_SEARCH_COUNTERS 1u   /* fill counters[] */
+#define HENN_SEARCH_PERSISTENT 2u /* one persistent launch pulling queries from a
+                                     device work counter (batched form) */
+
+typedef struct {
+  uint32_t struct_size;   /* = sizeof(henn_search_params) */
+  uint32_t flags;         /* HENN_SEARCH_* */
+  const int32_t *k;       /* device [nq] per-query k, or NULL -> k_all */
+  const int32_t *ef;      /* device [nq] per-query beam width, or NULL -> ef_all */
+  int32_t k_all;          /* k when k == NULL */
+  int32_t ef_all;         /* beam width when ef == NULL */
+  int32_t k_max;          /* output row stride; >= every k */
+  int32_t ef_max;         /* upper bound of every ef (sizes on-chip lists) */
+  int32_t ef_upper;       /* beam width on layers L..1 (1 = Alg. 4 greedy) */
+  int32_t rerank_factor;  /* precision forms: re-rank min(|W|, factor*k) in FP32 */
+  int32_t *counters;      /* device [nq][4] or NULL: expansions, distance
+                             evaluations, layer-0 expansions, layer-0 evaluations */
+  int32_t lanes_per_vec;  /* 0 = autotuned; else 4, 8, 16, 32 or 64 lanes
+                             cooperate on one neighbour vector */
+  int32_t waves_per_block;/* 0 = autotuned; else 1, 2, 4 or 8 */
+} henn_search_params;
+
+typedef struct {
+  int64_t size;           /* |L_i| */
+  int64_t draws;          /* samples drawn (with replacement) */
+  double eps;             /* eps_i used (Eq. (1) or override) */
+  int64_t window;         /* minimal heavy ring size floor(eps*s)+1 */
+  int32_t attempts;       /* Las-Vegas attempts made */
+  int32_t hits;           /* rings hit by the kept attempt */
+  int32_t status;         /* 0 base, 1 vacuous (window > s), 2 verified,
+                             3 not verified (best attempt kept) */
+  int32_t degree;         /* adjacency row stride of the layer */
+  int32_t fallback_rows;  /* rows whose shortlist was re-solved exactly */
+  int32_t reserved;
+} henn_layer_info;
+
+/* Fills *p with the defaults: L2, max_layers -1, m 4, c0 1, no override,
+ * 64 rings, 64 attempts, degree 16, max_degree 32, kNN graph, F32, seed 0. */
+henn_status henn_default_build_params(henn_build_params *p);
+
+/* Defaults: no per-query arrays, k_all 10, ef_all 32, k_max 10, ef_max 32,
+ * ef_upper 1, rerank_factor 4, no counters, autotuned launch shape. */
+henn_status henn_default_search_params(henn_search_params *p);
+
+/* Alg. 1 (BuildHENN) on the GPU.
+ *   X: device, FP32 row-major [n][d]; copied into library memory, so the
+ *      caller may free it on return.
+ *   n in [1, 2^31 - 1]; d in [1, 4096].
+ *   *out: receives a new index owned by the library (free with henn_free).
+ * Blocks: the Las-Vegas decisions of Alg. 2 are taken on the host, so the
+ * call synchronises hip_stream.  Returns HENN_W_NOT_VERIFIED (index usable)
+ * when a layer kept its best unverified attempt. */
+henn_status henn_build(const float *X, int64_t n, int32_t d, const henn_build_params *p,
+                       void *hip_stream, henn_index **out);
+
+/* Batched k-NN search (Alg. 4 Query; beam of max(ef, k) on layer 0, Sec. 2.2).
+ *   Q: device, FP32 row-major [nq][d] (d of the index).
+ *   out_ids: device int32 [nq][k_max]; out_dist: device float [nq][k_max].
+ *   Row i holds the first k_i results in ascending (distance, id) order,
+ *   padded with id -1 and distance +inf (also when fewer than k_i points are
+ *   reachable).  nq = 0 is a no-op.  Enqueued on hip_stream; results are
+ *   valid once the stream has reached this point.  The index is read-only;
+ *   concurrent searches on several streams are safe. */
+henn_status henn_search_batch(const henn_index *idx, const float *Q, int64_t nq,
+                              const henn_search_params *sp, int32_t *out_ids, float *out_dist,
+                              void *hip_stream);
+
+/* Releases the index.  No enqueued work may still use it.  NULL is a no-op. */
+void henn_free(henn_index *idx);
+
+/* Thread-local message of the last failing call on this thread ("" if none). */
+const char *henn_last_error(void);
+
+/* Number of layers (L + 1, layer 0 included) and the point dimension. */
+henn_status henn_index_shape(const henn_index *idx, int32_t *num_layers, int64_t *n,
+                             int32_t *d);
+
+/* Build record of layer i (host struct). */
+henn_status henn_layer_info_get(const henn_index *idx, int32_t layer, henn_layer_info *info);
+
+/* Copies layer i to host memory:
+ *   ids_host: int32 [|L_i|] ascending point ids (may be NULL);
+ *   adj_host: int32 [|L_i|][degree] neighbour positions within the layer's
+ *             id list, in (distance, id) order, -1 padded (may be NULL).
+ * Synchronous. */
+henn_status henn_export_layer(const henn_index *idx, int32_t layer, int32_t *ids_host,
+                              int32_t *adj_host);
+
+/* Builds an index from given layers instead of sampling them (for parity
+ * runs on a hierarchy produced elsewhere).
+ *   X: device FP32 [n][d] (copied).  p: metric, storage and degree are used.
+ *   sizes[i], ids_host[i] (int32 [sizes[i]], ascending, ids_host[0] may be
+ *   NULL meaning 0..n-1), adj_host[i] (int32 [sizes[i]][adj_stride], local
+ *   positions, -1 padded): host arrays for i < num_layers.
+ * Synchronous. */
+henn_status henn_import(const float *X, int64_t n, int32_t d, const henn_build_params *p,
+                        int32_t num_layers, const int64_t *sizes,
+                        const int32_t *const *ids_host, const int32_t *const *adj_host,
+                        int32_t adj_stride, void *hip_stream, henn_index **out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HENN_H */

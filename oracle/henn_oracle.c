@@ -207,6 +207,72 @@ int ho_knn_graph(const float *X, int d, int metric, const int32_t *members, int6
 }
 
 /* ------------------------------------------------------------------ */
+/* kNN graph plus reverse edges (the kNN_SYM navigable graph): row v is   */
+/* the first max_deg of the deduplicated union of v's out-neighbours and  */
+/* the nodes that list v, in ascending (dist(v,u), u) order.  adj_knn is  */
+/* the layer's kNN adjacency (local indices, R per row, -1 padded).       */
+/* cut/order margins as in ho_knn_graph, over the union's sorted list.    */
+/* ------------------------------------------------------------------ */
+int ho_knn_sym(const float *X, int d, int metric, const int32_t *members, int64_t s,
+               const int32_t *adj_knn, int R, int max_deg, int32_t *adj, double *cut_margin,
+               double *order_margin) {
+  int64_t *indeg = (int64_t *)calloc((size_t)s + 1, sizeof(int64_t));
+  if (!indeg) return -2;
+  for (int64_t v = 0; v < s; ++v)
+    for (int r = 0; r < R; ++r) {
+      int32_t u = adj_knn[(size_t)v * R + r];
+      if (u >= 0) indeg[u + 1]++;
+    }
+  for (int64_t v = 0; v < s; ++v) indeg[v + 1] += indeg[v];
+  int64_t total = indeg[s];
+  int32_t *inl = (int32_t *)malloc(sizeof(int32_t) * (size_t)(total > 0 ? total : 1));
+  int64_t *cur = (int64_t *)malloc(sizeof(int64_t) * (size_t)(s > 0 ? s : 1));
+  if (!inl || !cur) { free(indeg); free(inl); free(cur); return -2; }
+  for (int64_t v = 0; v < s; ++v) cur[v] = indeg[v];
+  for (int64_t v = 0; v < s; ++v)
+    for (int r = 0; r < R; ++r) {
+      int32_t u = adj_knn[(size_t)v * R + r];
+      if (u >= 0) inl[cur[u]++] = (int32_t)v;
+    }
+  int64_t maxc = 0;
+  for (int64_t v = 0; v < s; ++v)
+    if (indeg[v + 1] - indeg[v] > maxc) maxc = indeg[v + 1] - indeg[v];
+  dkey *keys = (dkey *)malloc(sizeof(dkey) * (size_t)(maxc + R + 1));
+  if (!keys) { free(indeg); free(inl); free(cur); return -2; }
+  for (int64_t v = 0; v < s; ++v) {
+    const float *xv = X + (size_t)members[v] * (size_t)d;
+    int64_t cnt = 0;
+    for (int r = 0; r < R; ++r) {
+      int32_t u = adj_knn[(size_t)v * R + r];
+      if (u < 0) continue;
+      keys[cnt].d = dist64(xv, X + (size_t)members[u] * (size_t)d, d, metric);
+      keys[cnt].id = u;
+      ++cnt;
+    }
+    for (int64_t j = indeg[v]; j < indeg[v + 1]; ++j) {
+      int32_t u = inl[j];
+      int dup = 0;
+      for (int r = 0; r < R; ++r)
+        if (adj_knn[(size_t)v * R + r] == u) dup = 1;
+      if (dup) continue;
+      keys[cnt].d = dist64(xv, X + (size_t)members[u] * (size_t)d, d, metric);
+      keys[cnt].id = u;
+      ++cnt;
+    }
+    qsort(keys, (size_t)cnt, sizeof(dkey), key_cmp);
+    double mg = INFINITY;
+    int64_t lim = cnt < (int64_t)max_deg + 1 ? cnt : (int64_t)max_deg + 1;
+    for (int64_t r = 1; r < lim; ++r) mg = fmin(mg, margin_l2(keys[r - 1].d, keys[r].d));
+    for (int r = 0; r < max_deg; ++r) adj[(size_t)v * max_deg + r] = r < cnt ? (int32_t)keys[r].id : -1;
+    if (cut_margin)
+      cut_margin[v] = cnt > max_deg ? margin_l2(keys[max_deg - 1].d, keys[max_deg].d) : INFINITY;
+    if (order_margin) order_margin[v] = mg;
+  }
+  free(keys); free(indeg); free(inl); free(cur);
+  return 0;
+}
+
+/* ------------------------------------------------------------------ */
 /* Binary heaps over dkey.                                              */
 /* ------------------------------------------------------------------ */
 typedef struct {
@@ -362,7 +428,7 @@ static int64_t search_layer(trace *t, const int32_t *members, int64_t size, cons
 int ho_search(const float *X, int d, int metric, int num_layers, const int64_t *sizes,
               const int32_t *const *members, const int32_t *const *adj, const int32_t *deg,
               const double *const *adj_margin, const float *Q, int64_t q_begin, int64_t q_end,
-              int k, int ef, int ef_upper, int32_t *out_ids, double *out_dist,
+              int k, int ef, int ef_upper, int root_complete, int32_t *out_ids, double *out_dist,
               double *out_margin, double *out_adj_margin, int64_t *counters) {
   if (num_layers < 1 || k < 1 || ef < 1 || ef_upper < 1) return -1;
   int ef0 = ef > k ? ef : k;
@@ -383,6 +449,27 @@ int ho_search(const float *X, int d, int metric, int num_layers, const int64_t *
     int64_t entry_local = 0; /* smallest id of the root layer */
     int64_t m = 0;
     int64_t e0 = 0, v0 = 0;
+    if (root_complete && top >= 1) {
+      /* complete graph on the root (App. B.2: trivially navigable): greedy
+       * search from any node reaches the exact nearest root member */
+      dkey best = {INFINITY, -1}, second = {INFINITY, -1};
+      for (int64_t j = 0; j < sizes[top]; ++j) {
+        dkey u = {dist64(t.q, X + (size_t)members[top][j] * (size_t)d, d, metric),
+                  members[top][j]};
+        t.evals++;
+        if (best.id < 0 || key_less(u, best)) { second = best; best = u; }
+        else if (second.id < 0 || key_less(u, second)) second = u;
+      }
+      if (second.id >= 0) note(&t, best, second);
+      const int32_t *mb = members[top - 1];
+      int64_t lo = 0, hi = sizes[top - 1] - 1;
+      while (lo < hi) {
+        int64_t mid = (lo + hi) / 2;
+        if (mb[mid] < best.id) lo = mid + 1; else hi = mid;
+      }
+      entry_local = lo;
+      top = top - 1;
+    }
     for (int i = top; i >= 0; --i) {
       ++gen;
       if (gen == INT32_MAX) { memset(stamp, 0, sizeof(int32_t) * (size_t)maxsize); gen = 1; }

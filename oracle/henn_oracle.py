@@ -15,6 +15,8 @@ of the paper's algorithms:
   ceil(|L_{i-1}| / 2^m) draws per layer.
 * :func:`search` -- Alg. 4 (Query) from the root down, ef=1 greedy on the
   upper layers and a beam of max(ef, k) candidates on layer 0 (Sec. 2.2).
+  When the root carries the complete graph (App. B.2: trivially navigable),
+  greedy search on it is the exhaustive scan for the root's nearest member.
 * :func:`brute_force_knn` -- exact k-NN of the problem setting (Sec. 2).
 
 Readings where the paper is silent (all listed in the design notes):
@@ -89,7 +91,11 @@ def _load():
         lib.ho_search.argtypes = [c_f32p, ctypes.c_int, ctypes.c_int, ctypes.c_int, c_i64p,
                                   P(c_i32p), P(c_i32p), c_i32p, P(c_f64p), c_f32p,
                                   ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
-                                  ctypes.c_int, c_i32p, c_f64p, c_f64p, c_f64p, c_i64p]
+                                  ctypes.c_int, ctypes.c_int, c_i32p, c_f64p, c_f64p, c_f64p,
+                                  c_i64p]
+        lib.ho_knn_sym.restype = ctypes.c_int
+        lib.ho_knn_sym.argtypes = [c_f32p, ctypes.c_int, ctypes.c_int, c_i32p, ctypes.c_int64,
+                                   c_i32p, ctypes.c_int, ctypes.c_int, c_i32p, c_f64p, c_f64p]
         lib.ho_brute_knn.restype = ctypes.c_int
         lib.ho_brute_knn.argtypes = [c_f32p, ctypes.c_int64, ctypes.c_int, ctypes.c_int, c_f32p,
                                      ctypes.c_int64, ctypes.c_int64, ctypes.c_int, c_i32p, c_f64p]
@@ -177,6 +183,10 @@ class BuildParams:
     max_attempts: int = 64
     degree: int = 16
     seed: int = 0
+    graph: int = 0               # 0: exact kNN; 1: kNN plus reverse edges (kNN_SYM)
+    max_degree: int = 32         # row cap of kNN_SYM
+    root_complete_max: int = 0   # > 0: stop adding layers once a layer holds at most
+                                 # this many points and give that root the complete graph
 
 
 @dataclass
@@ -196,6 +206,7 @@ class OracleIndex:
     X: np.ndarray
     metric: int
     degree: int
+    root_complete: bool = False
     members: list = field(default_factory=list)     # int32 ascending global ids per layer
     adj: list = field(default_factory=list)         # int32 [size, degree] local indices, -1 pad
     adj_dist: list = field(default_factory=list)    # float64 [size, degree]
@@ -281,6 +292,26 @@ def knn_graph(X, metric, members, R, threads=None):
     return adj, ad, cut, order
 
 
+def knn_rows(X, metric, members, rows, R):
+    """Exact kNN lists of selected rows of a layer (same definition as
+    :func:`knn_graph`): returns (adjacency [len(rows), R], cut margin, order
+    margin)."""
+    lib = _load()
+    s = len(members)
+    adj = np.full((s, R), -1, dtype=np.int32)
+    cut = np.full(s, np.inf)
+    order = np.full(s, np.inf)
+    for r in rows:
+        rc = lib.ho_knn_graph(_ptr(X, ctypes.c_float), X.shape[1], metric,
+                              _ptr(members, ctypes.c_int32), s, int(r), int(r) + 1, R,
+                              _ptr(adj, ctypes.c_int32), None, _ptr(cut, ctypes.c_double),
+                              _ptr(order, ctypes.c_double))
+        if rc != 0:
+            raise RuntimeError("knn_graph failed")
+    rows = np.asarray(rows)
+    return adj[rows], cut[rows], order[rows]
+
+
 def build_layers(X: np.ndarray, p: BuildParams, threads=None):
     """Alg. 1 layer loop: returns ascending member lists and per-layer info."""
     X = np.ascontiguousarray(X, dtype=np.float32)
@@ -292,6 +323,8 @@ def build_layers(X: np.ndarray, p: BuildParams, threads=None):
         s = len(members[-1])
         D = -(-s // (2 ** p.m))
         if D < p.degree + 1 or (p.max_layers >= 0 and i > p.max_layers):
+            break
+        if p.root_complete_max > 0 and s <= p.root_complete_max:
             break
         local, info = sample_layer(X, members[-1], i, d, p, threads)
         members.append(members[-1][local].astype(np.int32))
@@ -306,23 +339,50 @@ def build_index(X: np.ndarray, p: BuildParams | None = None, threads=None) -> Or
     p = p or BuildParams()
     X = np.ascontiguousarray(X, dtype=np.float32)
     members, infos = build_layers(X, p, threads)
-    idx = OracleIndex(X=X, metric=p.metric, degree=p.degree, members=members, info=infos)
+    root_complete = p.root_complete_max > 0 and len(members) >= 2
+    idx = OracleIndex(X=X, metric=p.metric, degree=p.degree, members=members, info=infos,
+                      root_complete=root_complete)
     for mb in members:
         a, ad, cut, order = knn_graph(X, p.metric, mb, p.degree, threads)
+        if p.graph == 1:
+            a, cut, order = knn_sym(X, p.metric, mb, a, p.max_degree)
+            ad = None
         idx.adj.append(a)
         idx.adj_dist.append(ad)
         idx.adj_margin.append(cut)
         idx.order_margin.append(order)
+    if root_complete:
+        # the root's decisions are the exhaustive scan's, not its list's
+        idx.adj_margin[-1] = np.full(len(members[-1]), np.inf)
     return idx
 
 
-def index_from_arrays(X, metric, members, adj, degree=None) -> OracleIndex:
+def knn_sym(X, metric, members, adj_knn, max_deg):
+    """kNN plus reverse edges: first max_deg of the deduplicated union of
+    out- and in-neighbours in (distance, id) order (cut / order margins)."""
+    lib = _load()
+    s = len(members)
+    adj_knn = np.ascontiguousarray(adj_knn, dtype=np.int32)
+    out = np.full((s, max_deg), -1, dtype=np.int32)
+    cut = np.full(s, np.inf)
+    order = np.full(s, np.inf)
+    rc = lib.ho_knn_sym(_ptr(X, ctypes.c_float), X.shape[1], metric,
+                        _ptr(members, ctypes.c_int32), s, _ptr(adj_knn, ctypes.c_int32),
+                        adj_knn.shape[1], max_deg, _ptr(out, ctypes.c_int32),
+                        _ptr(cut, ctypes.c_double), _ptr(order, ctypes.c_double))
+    if rc != 0:
+        raise RuntimeError("knn_sym failed")
+    return out, cut, order
+
+
+def index_from_arrays(X, metric, members, adj, degree=None, root_complete=False) -> OracleIndex:
     """Wrap an index given as data (e.g. exported by another builder)."""
     X = np.ascontiguousarray(X, dtype=np.float32)
     members = [np.ascontiguousarray(m, dtype=np.int32) for m in members]
     adj = [np.ascontiguousarray(a, dtype=np.int32) for a in adj]
     deg = degree if degree is not None else adj[0].shape[1]
-    return OracleIndex(X=X, metric=metric, degree=deg, members=members, adj=adj)
+    return OracleIndex(X=X, metric=metric, degree=deg, members=members, adj=adj,
+                       root_complete=bool(root_complete) and len(members) >= 2)
 
 
 @dataclass
@@ -363,7 +423,8 @@ def search(idx: OracleIndex, Q: np.ndarray, k: int, ef: int, ef_upper: int = 1,
         rc = lib.ho_search(_ptr(X, ctypes.c_float), X.shape[1], idx.metric, L,
                            _ptr(sizes, ctypes.c_int64), mem_arr, adj_arr,
                            _ptr(degs, ctypes.c_int32), am_arr, _ptr(Q, ctypes.c_float),
-                           b0 + b, b0 + e, k, ef, ef_upper, _ptr(ids, ctypes.c_int32),
+                           b0 + b, b0 + e, k, ef, ef_upper, int(idx.root_complete),
+                           _ptr(ids, ctypes.c_int32),
                            _ptr(dist, ctypes.c_double), _ptr(margin, ctypes.c_double),
                            _ptr(amargin, ctypes.c_double), _ptr(counters, ctypes.c_int64))
         if rc != 0:

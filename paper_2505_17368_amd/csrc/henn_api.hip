@@ -1,0 +1,588 @@
+// henn_api.hip -- host runtime behind the C ABI of include/henn.h.
+//
+// henn_build runs Alg. 1 (BuildHENN): for i = 1, 2, ... it draws
+// ceil(|L_{i-1}| / 2^m) samples with replacement from L_{i-1} (Alg. 2,
+// Cor. "layer-size"), takes eps_i from Eq. (1) (natural log), and accepts the
+// first attempt whose sample hits every one of r sampled ring ranges (the
+// practical IsEpsNet of App. B.1 / App. G.2; rings are minimal heavy rings:
+// a uniform centre in L_{i-1} and a uniform rank window of floor(eps*s)+1
+// points).  The decision is taken on the host after each attempt.  Each
+// layer then gets its exact kNN graph (App. B.2) and, for the precision
+// forms, a BF16 / FP8 traversal copy.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cstdlib>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "henn_device.h"
+#include "henn_internal.h"
+
+namespace henn {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+static henn_status fail(henn_status s, const std::string& msg) {
+  set_error(msg);
+  return s;
+}
+
+static henn_status from_hip(const HipError& e) {
+  set_error(std::string("HIP error ") + hipGetErrorString(e.e) + " in " + e.what);
+  if (e.e == hipErrorOutOfMemory || e.e == hipErrorMemoryAllocation) return HENN_E_NOMEM;
+  if (e.e == hipErrorNotSupported) return HENN_E_UNSUPPORTED;
+  return HENN_E_DEVICE;
+}
+
+static void free_layer(LayerDev& L) {
+  (void)hipFree(L.vec32);
+  (void)hipFree(L.vecq);
+  (void)hipFree(L.scale);
+  (void)hipFree(L.adj);
+  (void)hipFree(L.ids);
+  (void)hipFree(L.down);
+  L = LayerDev{};
+}
+
+template <typename T>
+static T* dalloc(int64_t count) {
+  T* p = nullptr;
+  if (count <= 0) count = 1;
+  HENN_HIP(hipMalloc(&p, sizeof(T) * (size_t)count));
+  return p;
+}
+
+static int storage_bytes(int storage) {
+  return storage == HENN_F32 ? 4 : storage == HENN_BF16 ? 2 : 1;
+}
+
+static bool valid_build_params(const henn_build_params* p, std::string* why) {
+  if (!p) { *why = "null build params"; return false; }
+  if (p->struct_size != sizeof(henn_build_params)) { *why = "build params struct_size mismatch"; return false; }
+  if (p->metric != HENN_L2 && p->metric != HENN_IP) { *why = "metric"; return false; }
+  if (p->m < 1 || p->m > 30) { *why = "m must be in [1, 30]"; return false; }
+  if (!(p->c0 > 0.0)) { *why = "c0 must be positive"; return false; }
+  if (p->num_rings < 1 || p->num_rings > 4096) { *why = "num_rings in [1, 4096]"; return false; }
+  if (p->max_attempts < 1) { *why = "max_attempts >= 1"; return false; }
+  if (p->degree < 1 || p->degree > 32) { *why = "degree in [1, 32]"; return false; }
+  if (p->graph != HENN_GRAPH_KNN && p->graph != HENN_GRAPH_KNN_SYM) { *why = "graph"; return false; }
+  if (p->graph == HENN_GRAPH_KNN_SYM && (p->max_degree < p->degree || p->max_degree > 64)) {
+    *why = "max_degree in [degree, 64]"; return false;
+  }
+  if (p->storage < HENN_F32 || p->storage > HENN_FP8_E4M3) { *why = "storage"; return false; }
+  return true;
+}
+
+// Finishes a layer: graph (+ optional symmetrisation) and traversal copy.
+static void finish_layer(henn_index* ix, int i, hipStream_t st) {
+  LayerDev& L = ix->L[i];
+  const henn_build_params& p = ix->params;
+  int lpn, cpl;
+  pick_lanes(ix->nchunks, 0, &lpn, &cpl);
+  const int R = p.degree;
+  int32_t* adj = dalloc<int32_t>(L.size * R);
+  try {
+    L.info.fallback_rows =
+        (int32_t)build_knn_graph(L.vec32, L.size, ix->dpad, ix->nchunks, ix->metric, R, lpn, cpl,
+                                 adj, st);
+  } catch (...) {
+    (void)hipFree(adj);
+    throw;
+  }
+  if (p.graph == HENN_GRAPH_KNN_SYM) {
+    int32_t* adj2 = dalloc<int32_t>(L.size * p.max_degree);
+    try {
+      symmetrize_graph(L.vec32, L.size, ix->dpad, ix->nchunks, ix->metric, adj, R, adj2,
+                       p.max_degree, lpn, cpl, st);
+    } catch (...) {
+      (void)hipFree(adj);
+      (void)hipFree(adj2);
+      throw;
+    }
+    (void)hipFree(adj);
+    L.adj = adj2;
+    L.deg = p.max_degree;
+  } else {
+    L.adj = adj;
+    L.deg = R;
+  }
+  L.info.degree = L.deg;
+  if (ix->storage != HENN_F32) {
+    L.vecq = dalloc<uint8_t>(L.size * ix->dpad * storage_bytes(ix->storage));
+    if (ix->storage == HENN_FP8_E4M3) L.scale = dalloc<float>(L.size);
+    launch_quantize(ix->storage, L.vec32, L.size, ix->dpad, L.vecq, L.scale, st);
+  }
+  HENN_HIP(hipStreamSynchronize(st));
+}
+
+// One eps-net layer (Alg. 2 with the ring check).  Returns the accepted
+// attempt and fills info.
+static int sample_layer(henn_index* ix, int i, hipStream_t st, int32_t* local_out,
+                        int64_t* count_out) {
+  const henn_build_params& p = ix->params;
+  LayerDev& prev = ix->L[i - 1];
+  const int64_t s = prev.size;
+  const int64_t D = (s + (1ll << p.m) - 1) >> p.m;
+  const double eps = p.eps_override > 0.0
+                         ? p.eps_override
+                         : p.c0 * (double)ix->d * log((double)s) / (double)s * (double)(1ll << p.m);
+  const int64_t w = (int64_t)floor(eps * (double)s) + 1;
+  henn_layer_info& info = ix->L[i].info;
+  info.draws = D;
+  info.eps = eps;
+  info.window = w;
+  int lpn, cpl;
+  pick_lanes(ix->nchunks, 0, &lpn, &cpl);
+  int accepted = 0;
+  if (w > s) {
+    info.status = 1;  // vacuous: no ring can be heavy
+    info.attempts = 1;
+    info.hits = 0;
+  } else {
+    const int r = p.num_rings;
+    std::vector<int32_t> centres((size_t)r);
+    std::vector<int64_t> ranks((size_t)(2 * r));
+    for (int j = 0; j < r; ++j) {
+      centres[(size_t)j] = (int32_t)uniform_index(stream_word(p.seed, kTagRingCentre, i, 0, j),
+                                                  (uint64_t)s);
+      const int64_t a = (int64_t)uniform_index(stream_word(p.seed, kTagRingStart, i, 0, j),
+                                               (uint64_t)(s - w + 1));
+      ranks[(size_t)(2 * j)] = a;
+      ranks[(size_t)(2 * j + 1)] = a + w - 1;
+    }
+    int32_t* d_centres = dalloc<int32_t>(r);
+    uint64_t* keys = nullptr;
+    uint64_t* d_lohi = dalloc<uint64_t>(2 * r);
+    uint32_t* d_hits = dalloc<uint32_t>(r);
+    try {
+      keys = dalloc<uint64_t>((int64_t)r * s);
+      HENN_HIP(hipMemcpyAsync(d_centres, centres.data(), sizeof(int32_t) * r,
+                              hipMemcpyHostToDevice, st));
+      launch_ring_keys(lpn, cpl, prev.vec32, ix->dpad, ix->nchunks, ix->metric, s, d_centres, r,
+                       keys, st);
+      std::vector<uint64_t> ends((size_t)(2 * r));
+      launch_radix_select(keys, s, r, ranks.data(), ends.data(), st);
+      (void)hipFree(keys);
+      keys = nullptr;
+      std::vector<uint64_t> lohi((size_t)(2 * r));
+      for (int j = 0; j < r; ++j) {
+        lohi[(size_t)j] = ends[(size_t)(2 * j)];
+        lohi[(size_t)(r + j)] = ends[(size_t)(2 * j + 1)];
+      }
+      HENN_HIP(hipMemcpyAsync(d_lohi, lohi.data(), sizeof(uint64_t) * 2 * r,
+                              hipMemcpyHostToDevice, st));
+      int best_t = -1, best_hits = -1;
+      std::vector<uint32_t> hits((size_t)r);
+      int t = 0;
+      for (; t < p.max_attempts; ++t) {
+        HENN_HIP(hipMemsetAsync(d_hits, 0, sizeof(uint32_t) * r, st));
+        launch_ring_hits(lpn, cpl, prev.vec32, ix->dpad, ix->nchunks, ix->metric, s, p.seed, i,
+                         t, D, d_centres, d_lohi, d_lohi + r, r, d_hits, st);
+        HENN_HIP(hipMemcpyAsync(hits.data(), d_hits, sizeof(uint32_t) * r, hipMemcpyDeviceToHost,
+                                st));
+        HENN_HIP(hipStreamSynchronize(st));
+        int h = 0;
+        for (int j = 0; j < r; ++j) h += hits[(size_t)j] != 0;
+        if (h > best_hits) {
+          best_hits = h;
+          best_t = t;
+        }
+        if (h == r) break;
+      }
+      if (best_hits == r) {
+        info.status = 2;
+        info.attempts = t + 1;
+      } else {
+        info.status = 3;
+        info.attempts = p.max_attempts;
+      }
+      info.hits = best_hits;
+      accepted = best_t;
+    } catch (...) {
+      (void)hipFree(keys);
+      (void)hipFree(d_centres);
+      (void)hipFree(d_lohi);
+      (void)hipFree(d_hits);
+      throw;
+    }
+    (void)hipFree(d_centres);
+    (void)hipFree(d_lohi);
+    (void)hipFree(d_hits);
+  }
+  const int64_t nwords = (s + 31) / 32;
+  uint32_t* bitmap = dalloc<uint32_t>(nwords);
+  try {
+    HENN_HIP(hipMemsetAsync(bitmap, 0, sizeof(uint32_t) * nwords, st));
+    launch_draw_mark(p.seed, i, accepted, s, D, bitmap, st);
+    *count_out = compact_bitmap(bitmap, s, local_out, st);
+  } catch (...) {
+    (void)hipFree(bitmap);
+    throw;
+  }
+  (void)hipFree(bitmap);
+  return accepted;
+}
+
+static void destroy(henn_index* ix) {
+  if (!ix) return;
+  for (int i = 0; i < HENN_MAX_LAYERS; ++i) free_layer(ix->L[i]);
+  delete ix;
+}
+
+static henn_index* new_index(const float* X, int64_t n, int32_t d, const henn_build_params* p,
+                             hipStream_t st) {
+  henn_index* ix = new henn_index();
+  ix->n = n;
+  ix->d = d;
+  ix->dpad = (d + 7) / 8 * 8;
+  ix->nchunks = ix->dpad / 8;
+  ix->metric = p->metric;
+  ix->storage = p->storage;
+  ix->params = *p;
+  (void)hipGetDevice(&ix->device);
+  try {
+    LayerDev& L0 = ix->L[0];
+    L0.size = n;
+    L0.vec32 = dalloc<float>(n * ix->dpad);
+    launch_copy_rows(X, d, nullptr, n, d, L0.vec32, ix->dpad, st);
+    HENN_HIP(hipGetLastError());
+    L0.info.size = n;
+    L0.info.draws = n;
+    L0.info.status = 0;
+    ix->num_layers = 1;
+  } catch (...) {
+    destroy(ix);
+    throw;
+  }
+  return ix;
+}
+
+static henn_status check_common(const float* X, int64_t n, int32_t d, henn_index** out) {
+  if (!X) return fail(HENN_E_INVAL, "X is null");
+  if (!out) return fail(HENN_E_INVAL, "out is null");
+  if (n < 1 || n > 2147483647ll) return fail(HENN_E_INVAL, "n must be in [1, 2^31-1]");
+  if (d < 1 || d > 1024) return fail(HENN_E_INVAL, "d must be in [1, 1024]");
+  return HENN_OK;
+}
+
+}  // namespace henn
+
+using namespace henn;
+
+extern "C" {
+
+const char* henn_last_error(void) { return g_last_error.c_str(); }
+
+henn_status henn_default_build_params(henn_build_params* p) {
+  if (!p) return fail(HENN_E_INVAL, "null params");
+  memset(p, 0, sizeof(*p));
+  p->struct_size = sizeof(henn_build_params);
+  p->metric = HENN_L2;
+  p->max_layers = -1;
+  p->m = 4;
+  p->c0 = 1.0;
+  p->eps_override = 0.0;
+  p->num_rings = 64;
+  p->max_attempts = 64;
+  p->degree = 16;
+  p->max_degree = 32;
+  p->graph = HENN_GRAPH_KNN;
+  p->storage = HENN_F32;
+  p->seed = 0;
+  return HENN_OK;
+}
+
+henn_status henn_default_search_params(henn_search_params* p) {
+  if (!p) return fail(HENN_E_INVAL, "null params");
+  memset(p, 0, sizeof(*p));
+  p->struct_size = sizeof(henn_search_params);
+  p->k_all = 10;
+  p->ef_all = 32;
+  p->k_max = 10;
+  p->ef_max = 32;
+  p->ef_upper = 1;
+  p->rerank_factor = 4;
+  return HENN_OK;
+}
+
+henn_status henn_build(const float* X, int64_t n, int32_t d, const henn_build_params* p,
+                       void* hip_stream, henn_index** out) {
+  henn_status cs = check_common(X, n, d, out);
+  if (cs != HENN_OK) return cs;
+  std::string why;
+  if (!valid_build_params(p, &why)) return fail(HENN_E_INVAL, why);
+  if ((d + 7) / 8 * 8 > 128) return fail(HENN_E_UNSUPPORTED, "GPU graph build supports d <= 128");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  henn_index* ix = nullptr;
+  int32_t* local = nullptr;
+  try {
+    ix = new_index(X, n, d, p, st);
+    bool unverified = false;
+    for (int i = 1; i < HENN_MAX_LAYERS; ++i) {
+      const int64_t s = ix->L[i - 1].size;
+      const int64_t D = (s + (1ll << p->m) - 1) >> p->m;
+      if (D < (int64_t)p->degree + 1) break;
+      if (p->max_layers >= 0 && i > p->max_layers) break;
+      local = dalloc<int32_t>(s);
+      int64_t cnt = 0;
+      sample_layer(ix, i, st, local, &cnt);
+      LayerDev& L = ix->L[i];
+      L.size = cnt;
+      L.info.size = cnt;
+      L.ids = dalloc<int32_t>(cnt);
+      L.down = dalloc<int32_t>(cnt);
+      launch_map_ids(ix->L[i - 1].ids, local, cnt, L.ids, L.down, st);
+      L.vec32 = dalloc<float>(cnt * ix->dpad);
+      launch_copy_rows(ix->L[i - 1].vec32, ix->dpad, local, cnt, ix->dpad, L.vec32, ix->dpad, st);
+      HENN_HIP(hipStreamSynchronize(st));
+      (void)hipFree(local);
+      local = nullptr;
+      ix->num_layers = i + 1;
+      if (L.info.status == 3) unverified = true;
+    }
+    for (int i = 0; i < ix->num_layers; ++i) finish_layer(ix, i, st);
+    *out = ix;
+    return unverified ? fail(HENN_W_NOT_VERIFIED, "a layer kept its best unverified attempt")
+                      : HENN_OK;
+  } catch (const HipError& e) {
+    (void)hipFree(local);
+    destroy(ix);
+    return from_hip(e);
+  } catch (const std::bad_alloc&) {
+    (void)hipFree(local);
+    destroy(ix);
+    return fail(HENN_E_NOMEM, "host allocation failed");
+  }
+}
+
+henn_status henn_import(const float* X, int64_t n, int32_t d, const henn_build_params* p,
+                        int32_t num_layers, const int64_t* sizes, const int32_t* const* ids_host,
+                        const int32_t* const* adj_host, int32_t adj_stride, void* hip_stream,
+                        henn_index** out) {
+  henn_status cs = check_common(X, n, d, out);
+  if (cs != HENN_OK) return cs;
+  std::string why;
+  if (!valid_build_params(p, &why)) return fail(HENN_E_INVAL, why);
+  if (num_layers < 1 || num_layers > HENN_MAX_LAYERS) return fail(HENN_E_INVAL, "num_layers");
+  if (!sizes || !adj_host || !ids_host) return fail(HENN_E_INVAL, "null layer arrays");
+  if (adj_stride < 1 || adj_stride > 64) return fail(HENN_E_INVAL, "adj_stride in [1, 64]");
+  if (sizes[0] != n) return fail(HENN_E_INVAL, "sizes[0] must equal n");
+  // host-side validation: ascending ids, nesting, adjacency range, no duplicates
+  std::vector<std::vector<int32_t>> down((size_t)num_layers);
+  for (int i = 0; i < num_layers; ++i) {
+    const int64_t sz = sizes[i];
+    if (sz < 1 || (i > 0 && sz > sizes[i - 1])) return fail(HENN_E_INVAL, "layer sizes");
+    if (i > 0 || ids_host[0]) {
+      const int32_t* ids = ids_host[i];
+      if (!ids) return fail(HENN_E_INVAL, "null ids for an upper layer");
+      for (int64_t j = 0; j < sz; ++j) {
+        if (ids[j] < 0 || ids[j] >= n || (j > 0 && ids[j] <= ids[j - 1]))
+          return fail(HENN_E_INVAL, "layer ids must be ascending point ids");
+      }
+    }
+    if (i > 0) {
+      down[(size_t)i].resize((size_t)sz);
+      const int32_t* below = ids_host[i - 1];
+      for (int64_t j = 0; j < sz; ++j) {
+        const int32_t id = ids_host[i][j];
+        int64_t pos;
+        if (!below) {
+          pos = id;
+        } else {
+          const int32_t* it = std::lower_bound(below, below + sizes[i - 1], id);
+          if (it == below + sizes[i - 1] || *it != id)
+            return fail(HENN_E_INVAL, "layer is not nested in the layer below");
+          pos = it - below;
+        }
+        down[(size_t)i][(size_t)j] = (int32_t)pos;
+      }
+    }
+    const int32_t* a = adj_host[i];
+    if (!a) return fail(HENN_E_INVAL, "null adjacency");
+    for (int64_t j = 0; j < sz; ++j) {
+      for (int c = 0; c < adj_stride; ++c) {
+        const int32_t u = a[j * adj_stride + c];
+        if (u < -1 || u >= sz) return fail(HENN_E_INVAL, "adjacency entry out of range");
+        if (u >= 0)
+          for (int c2 = 0; c2 < c; ++c2)
+            if (a[j * adj_stride + c2] == u) return fail(HENN_E_INVAL, "duplicate neighbour");
+      }
+    }
+  }
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  henn_index* ix = nullptr;
+  try {
+    ix = new_index(X, n, d, p, st);
+    ix->num_layers = num_layers;
+    for (int i = 0; i < num_layers; ++i) {
+      LayerDev& L = ix->L[i];
+      L.size = sizes[i];
+      L.info.size = sizes[i];
+      L.info.status = i == 0 ? 0 : 2;
+      L.deg = adj_stride;
+      L.info.degree = adj_stride;
+      L.adj = dalloc<int32_t>(L.size * adj_stride);
+      HENN_HIP(hipMemcpyAsync(L.adj, adj_host[i], sizeof(int32_t) * L.size * adj_stride,
+                              hipMemcpyHostToDevice, st));
+      if (i > 0) {
+        L.ids = dalloc<int32_t>(L.size);
+        L.down = dalloc<int32_t>(L.size);
+        HENN_HIP(hipMemcpyAsync(L.ids, ids_host[i], sizeof(int32_t) * L.size,
+                                hipMemcpyHostToDevice, st));
+        HENN_HIP(hipMemcpyAsync(L.down, down[(size_t)i].data(), sizeof(int32_t) * L.size,
+                                hipMemcpyHostToDevice, st));
+        L.vec32 = dalloc<float>(L.size * ix->dpad);
+        launch_copy_rows(ix->L[0].vec32, ix->dpad, L.ids, L.size, ix->dpad, L.vec32, ix->dpad,
+                         st);
+      }
+      if (ix->storage != HENN_F32) {
+        L.vecq = dalloc<uint8_t>(L.size * ix->dpad * storage_bytes(ix->storage));
+        if (ix->storage == HENN_FP8_E4M3) L.scale = dalloc<float>(L.size);
+        launch_quantize(ix->storage, L.vec32, L.size, ix->dpad, L.vecq, L.scale, st);
+      }
+      HENN_HIP(hipStreamSynchronize(st));
+    }
+    *out = ix;
+    return HENN_OK;
+  } catch (const HipError& e) {
+    destroy(ix);
+    return from_hip(e);
+  } catch (const std::bad_alloc&) {
+    destroy(ix);
+    return fail(HENN_E_NOMEM, "host allocation failed");
+  }
+}
+
+static std::atomic<uint32_t> g_counter_slot{0};
+static uint32_t* g_counter_pool[64] = {nullptr};  // per device id, 64 counters each
+
+henn_status henn_search_batch(const henn_index* idx, const float* Q, int64_t nq,
+                              const henn_search_params* sp, int32_t* out_ids, float* out_dist,
+                              void* hip_stream) {
+  if (!idx) return fail(HENN_E_INVAL, "index is null");
+  if (!sp || sp->struct_size != sizeof(henn_search_params))
+    return fail(HENN_E_INVAL, "search params null or struct_size mismatch");
+  if (nq < 0 || nq > 2147483647ll) return fail(HENN_E_INVAL, "nq out of range");
+  if (nq == 0) return HENN_OK;
+  if (!Q || !out_ids || !out_dist) return fail(HENN_E_INVAL, "null query or output pointer");
+  if (sp->k_max < 1 || sp->k_max > 1024) return fail(HENN_E_INVAL, "k_max in [1, 1024]");
+  if (!sp->k && (sp->k_all < 1 || sp->k_all > sp->k_max)) return fail(HENN_E_INVAL, "k_all");
+  if (!sp->ef && sp->ef_all < 1) return fail(HENN_E_INVAL, "ef_all >= 1");
+  if (sp->ef && sp->ef_max < 1) return fail(HENN_E_INVAL, "ef_max >= 1");
+  if (sp->ef_upper < 1) return fail(HENN_E_INVAL, "ef_upper >= 1");
+  if (idx->storage != HENN_F32 && sp->rerank_factor < 1)
+    return fail(HENN_E_INVAL, "rerank_factor >= 1");
+  const int ef_need = std::max(std::max(sp->k_max, sp->ef ? sp->ef_max : sp->ef_all), sp->ef_upper);
+  if (ef_need > 2048) return fail(HENN_E_INVAL, "beam width above 2048");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  try {
+    SearchArgs a;
+    memset(&a, 0, sizeof(a));
+    const int eb = storage_bytes(idx->storage);
+    for (int i = 0; i < idx->num_layers; ++i) {
+      const LayerDev& L = idx->L[i];
+      SearchLayer& s = a.layer[i];
+      s.vec = idx->storage == HENN_F32 ? (const void*)L.vec32 : (const void*)L.vecq;
+      s.scale = L.scale;
+      s.adj = L.adj;
+      s.down = L.down;
+      s.size = (int32_t)L.size;
+      s.deg = L.deg;
+      s.row_bytes = (int64_t)idx->dpad * eb;
+    }
+    a.rerank_vec = idx->storage == HENN_F32 ? nullptr : idx->L[0].vec32;
+    a.Q = Q;
+    a.nq = nq;
+    a.k_arr = sp->k;
+    a.ef_arr = sp->ef;
+    a.k_all = sp->k_all;
+    a.ef_all = sp->ef_all;
+    a.k_max = sp->k_max;
+    a.ef_upper = sp->ef_upper;
+    a.ef_cap = next_pow2(ef_need);
+    a.rerank_factor = std::max(1, sp->rerank_factor);
+    a.num_layers = idx->num_layers;
+    a.d = idx->d;
+    a.dpad = idx->dpad;
+    a.nchunks = idx->nchunks;
+    a.metric = idx->metric;
+    a.vis_bits = ef_need <= 64 ? 10 : ef_need <= 256 ? 11 : 12;
+    a.out_ids = out_ids;
+    a.out_dist = out_dist;
+    a.counters = sp->counters;
+
+    LaunchShape sh;
+    int lpn = 0, cpl = 0;
+    pick_lanes(idx->nchunks, sp->lanes_per_vec, &lpn, &cpl);
+    if (lpn == 0) return fail(HENN_E_INVAL, "lanes_per_vec not available for this dimension");
+    sh.lanes_per_vec = lpn;
+    sh.chunks_per_lane = cpl;
+    sh.vis_bits = a.vis_bits;
+    int wpb = sp->waves_per_block > 0 ? sp->waves_per_block : 4;
+    if (wpb != 1 && wpb != 2 && wpb != 4 && wpb != 8) return fail(HENN_E_INVAL, "waves_per_block");
+    while (wpb > 1 && search_lds_per_wave(a.ef_cap, a.vis_bits) * wpb > 65536) wpb /= 2;
+    sh.waves_per_block = wpb;
+    sh.persistent = (sp->flags & HENN_SEARCH_PERSISTENT) != 0;
+    sh.blocks = 0;
+    if (sh.persistent) {
+      const int dev = idx->device;
+      if (dev < 0 || dev >= 64) return fail(HENN_E_UNSUPPORTED, "device id");
+      if (!g_counter_pool[dev]) HENN_HIP(hipMalloc(&g_counter_pool[dev], 64 * sizeof(uint32_t)));
+      a.work_counter = g_counter_pool[dev] + (g_counter_slot.fetch_add(1) & 63u);
+    }
+    if (!launch_search(idx->storage, a, sh, st))
+      return fail(HENN_E_UNSUPPORTED, "no search kernel for this shape");
+    HENN_HIP(hipGetLastError());
+    return HENN_OK;
+  } catch (const HipError& e) {
+    return from_hip(e);
+  }
+}
+
+void henn_free(henn_index* idx) { destroy(idx); }
+
+henn_status henn_index_shape(const henn_index* idx, int32_t* num_layers, int64_t* n, int32_t* d) {
+  if (!idx) return fail(HENN_E_INVAL, "index is null");
+  if (num_layers) *num_layers = idx->num_layers;
+  if (n) *n = idx->n;
+  if (d) *d = idx->d;
+  return HENN_OK;
+}
+
+henn_status henn_layer_info_get(const henn_index* idx, int32_t layer, henn_layer_info* info) {
+  if (!idx || !info) return fail(HENN_E_INVAL, "null argument");
+  if (layer < 0 || layer >= idx->num_layers) return fail(HENN_E_INVAL, "layer out of range");
+  *info = idx->L[layer].info;
+  info->size = idx->L[layer].size;
+  info->degree = idx->L[layer].deg;
+  return HENN_OK;
+}
+
+henn_status henn_export_layer(const henn_index* idx, int32_t layer, int32_t* ids_host,
+                              int32_t* adj_host) {
+  if (!idx) return fail(HENN_E_INVAL, "index is null");
+  if (layer < 0 || layer >= idx->num_layers) return fail(HENN_E_INVAL, "layer out of range");
+  const LayerDev& L = idx->L[layer];
+  try {
+    if (ids_host) {
+      if (L.ids) {
+        HENN_HIP(hipMemcpy(ids_host, L.ids, sizeof(int32_t) * L.size, hipMemcpyDeviceToHost));
+      } else {
+        for (int64_t j = 0; j < L.size; ++j) ids_host[j] = (int32_t)j;
+      }
+    }
+    if (adj_host)
+      HENN_HIP(hipMemcpy(adj_host, L.adj, sizeof(int32_t) * L.size * L.deg, hipMemcpyDeviceToHost));
+    return HENN_OK;
+  } catch (const HipError& e) {
+    return from_hip(e);
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,151 @@
+// henn_internal.h -- host-side index layout and kernel launch interfaces.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/henn.h"
+
+namespace henn {
+
+// One layer of the hierarchy as it lives in HBM.
+//   vec32: FP32 rows [size][dpad] (zero padded to a multiple of 8 coords);
+//          for layer 0 this is the library's copy of X.
+//   vecq:  storage-format rows (BF16 [size][dpad] or FP8 [size][dpad]) for
+//          the precision forms, else nullptr.
+//   scale: per-row FP32 scale (FP8) or nullptr.
+//   adj:   int32 [size][deg], positions within the layer, (dist, id) order,
+//          -1 padded.
+//   ids:   int32 [size] ascending point ids (nullptr for layer 0 = identity).
+//   down:  int32 [size] position of the same point in layer-1 (the
+//          inter-layer edge of Def. HENN); nullptr for layer 0.
+struct LayerDev {
+  int64_t size = 0;
+  int32_t deg = 0;
+  float* vec32 = nullptr;
+  void* vecq = nullptr;
+  float* scale = nullptr;
+  int32_t* adj = nullptr;
+  int32_t* ids = nullptr;
+  int32_t* down = nullptr;
+  henn_layer_info info{};
+};
+
+}  // namespace henn
+
+struct henn_index {
+  int64_t n = 0;
+  int32_t d = 0, dpad = 0, nchunks = 0;
+  int32_t metric = 0, storage = 0;
+  henn_build_params params{};
+  int32_t num_layers = 0;
+  henn::LayerDev L[HENN_MAX_LAYERS];
+  int device = 0;
+};
+
+namespace henn {
+
+// ---- error plumbing -------------------------------------------------------
+void set_error(const std::string& msg);
+
+struct HipError {
+  hipError_t e;
+  const char* what;
+};
+
+#define HENN_HIP(call)                                   \
+  do {                                                   \
+    hipError_t _e = (call);                              \
+    if (_e != hipSuccess) throw ::henn::HipError{_e, #call}; \
+  } while (0)
+
+inline int next_pow2(int v) {
+  int p = 1;
+  while (p < v) p *= 2;
+  return p;
+}
+
+// ---- search ---------------------------------------------------------------
+struct SearchLayer {
+  const void* vec;
+  const float* scale;
+  const int32_t* adj;
+  const int32_t* down;
+  int32_t size;
+  int32_t deg;
+  int64_t row_bytes;
+};
+
+struct SearchArgs {
+  SearchLayer layer[HENN_MAX_LAYERS];
+  const float* rerank_vec;  // FP32 layer-0 rows for the precision forms, else nullptr
+  const float* Q;
+  int64_t nq;
+  const int32_t* k_arr;
+  const int32_t* ef_arr;
+  int32_t k_all, ef_all, k_max, ef_upper, ef_cap, rerank_factor;
+  int32_t num_layers, d, dpad, nchunks, metric, vis_bits;
+  int32_t* out_ids;
+  float* out_dist;
+  int32_t* counters;
+  uint32_t* work_counter;  // persistent form: device query counter
+};
+
+struct LaunchShape {
+  int lanes_per_vec;    // LPN
+  int chunks_per_lane;  // CPL
+  int waves_per_block;
+  int vis_bits;
+  bool persistent;
+  int blocks;           // persistent grid size (0 = computed)
+};
+
+// Shared-memory bytes one wave needs for a given list capacity.
+size_t search_lds_per_wave(int ef_cap, int vis_bits);
+
+// Enqueues the search kernel.  Returns false when no kernel instance
+// matches (storage, lanes_per_vec, chunks_per_lane).
+bool launch_search(int storage, const SearchArgs& a, const LaunchShape& s, hipStream_t st);
+
+// ---- build ----------------------------------------------------------------
+void launch_copy_rows(const float* src, int64_t src_stride, const int32_t* ids, int64_t count,
+                      int d, float* dst, int dpad, hipStream_t st);
+void launch_ring_keys(int lpn, int cpl, const float* vec, int dpad, int nchunks, int metric,
+                      int64_t s, const int32_t* centres, int r, uint64_t* keys, hipStream_t st);
+void launch_radix_select(const uint64_t* keys, int64_t s, int r, const int64_t* ranks_host,
+                         uint64_t* out_keys_host, hipStream_t st);
+void launch_ring_hits(int lpn, int cpl, const float* vec, int dpad, int nchunks, int metric,
+                      int64_t s, uint64_t seed, int layer, int attempt, int64_t draws,
+                      const int32_t* centres, const uint64_t* lo, const uint64_t* hi, int r,
+                      uint32_t* hits, hipStream_t st);
+void launch_draw_mark(uint64_t seed, int layer, int attempt, int64_t s, int64_t draws,
+                      uint32_t* bitmap, hipStream_t st);
+int64_t compact_bitmap(const uint32_t* bitmap, int64_t s, int32_t* out_local, hipStream_t st);
+void launch_map_ids(const int32_t* prev_ids, const int32_t* local, int64_t count, int32_t* ids,
+                    int32_t* down, hipStream_t st);
+void layer_mean(const float* vec, int64_t size, int dpad, float* mean_dev, hipStream_t st);
+void launch_row_norms(const float* vec, const float* mean, int64_t size, int dpad, float* norms,
+                      hipStream_t st);
+float max_norm(const float* norms, int64_t size, hipStream_t st);
+void launch_quantize(int storage, const float* vec, int64_t size, int dpad, void* out,
+                     float* scale, hipStream_t st);
+
+// kNN graph of one layer: FP32 MFMA Gram shortlist + exact re-rank + exact
+// fallback for rows whose shortlist cannot be proven to hold the top R.
+// Returns the number of fallback rows.
+int64_t build_knn_graph(const float* vec, int64_t size, int dpad, int nchunks, int metric, int R,
+                        int lpn, int cpl, int32_t* adj, hipStream_t st);
+
+// Reverse-edge augmentation (HENN_GRAPH_KNN_SYM): rows become the first
+// max_deg of the deduplicated union of out- and in-neighbours in
+// (distance, id) order.
+void symmetrize_graph(const float* vec, int64_t size, int dpad, int nchunks, int metric,
+                      const int32_t* adj_knn, int R, int32_t* adj_out, int max_deg, int lpn,
+                      int cpl, hipStream_t st);
+
+// Picks (lanes per vector, chunks per lane) for a dimension.
+void pick_lanes(int nchunks, int requested_lpn, int* lpn, int* cpl);
+
+}  // namespace henn

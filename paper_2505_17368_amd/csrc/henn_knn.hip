@@ -1,0 +1,325 @@
+// henn_knn.hip -- exact kNN navigable graph of one layer (App. B.2; the
+// "knn" graph of App. G.4): every member's R nearest other members in
+// (distance, id) order.
+//
+// Three steps:
+//  1. k_knn_gram (MFMA): all-pairs Gram tiles on FP32 matrix cores.  A
+//     workgroup owns 128 rows (4 waves x 32); candidate tiles of 32 rows are
+//     staged in LDS and multiplied with v_mfma_f32_32x32x2f32, the K split
+//     as (lane half h) x (step kk) over the two halves of each row.  Rows are
+//     centred on the layer mean first (L2 only), which shrinks the norms
+//     the Gram form cancels against.  Each lane keeps the 32 smallest Gram
+//     distances it sees in registers, so every row ends with a 64-entry
+//     shortlist (two halves) plus the 32nd Gram value of each half.
+//  2. k_knn_rerank: one wave per row recomputes the shortlist's distances
+//     in the canonical difference form, sorts the (distance, id) keys and
+//     keeps R.  A row is re-solved exactly when the shortlist cannot be
+//     proven to contain the true top R: when the R-th exact distance plus
+//     the Gram error bound is not below the shortlist cut minus that bound.
+//  3. k_knn_exact: the exact brute force for those rows.
+#include <math.h>
+
+#include "henn_device.h"
+#include "henn_internal.h"
+
+namespace henn {
+
+constexpr int kShort = 32;  // shortlist entries per lane half
+constexpr int kTileC = 32;  // candidates per LDS tile
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+template <int KHMAX>
+__global__ __launch_bounds__(256) void k_knn_gram(const float* vec, int64_t size, int dpad,
+                                                  const float* mean, const float* norms,
+                                                  int metric, float* sl_d, int32_t* sl_i) {
+  extern __shared__ __align__(16) float tile[];  // [kTileC][dpad + 4] + norms[kTileC]
+  const int lds_stride = dpad + 4;
+  float* tnorm = tile + kTileC * lds_stride;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int qc = lane & 31, h = lane >> 5;
+  const int kh = dpad >> 1;
+  const int64_t qrow = (int64_t)blockIdx.x * 128 + wave * 32 + qc;
+  const bool qvalid = qrow < size;
+
+  float bq[KHMAX];
+#pragma unroll
+  for (int kk = 0; kk < KHMAX; ++kk) {
+    float v = 0.0f;
+    if (kk < kh && qvalid) {
+      const int e = h * kh + kk;
+      v = vec[qrow * dpad + e] - (mean ? mean[e] : 0.0f);
+    }
+    bq[kk] = v;
+  }
+  const float nq = qvalid ? norms[qrow] : 0.0f;
+
+  float td[kShort];
+  int32_t ti[kShort];
+#pragma unroll
+  for (int j = 0; j < kShort; ++j) {
+    td[j] = INFINITY;
+    ti[j] = -1;
+  }
+
+  const int f4_per_row = dpad >> 2;
+  for (int64_t c0 = 0; c0 < size; c0 += kTileC) {
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < kTileC * f4_per_row; idx += 256) {
+      const int r = idx / f4_per_row, c4 = idx - r * f4_per_row;
+      const int64_t row = c0 + r;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (row < size) {
+        v = reinterpret_cast<const float4*>(vec + row * dpad)[c4];
+        if (mean) {
+          const float4 m = reinterpret_cast<const float4*>(mean)[c4];
+          v.x -= m.x; v.y -= m.y; v.z -= m.z; v.w -= m.w;
+        }
+      }
+      *reinterpret_cast<float4*>(tile + r * lds_stride + 4 * c4) = v;
+    }
+    if (threadIdx.x < kTileC) {
+      const int64_t row = c0 + threadIdx.x;
+      tnorm[threadIdx.x] = row < size ? norms[row] : 0.0f;
+    }
+    __syncthreads();
+
+    floatx16 acc;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+    const float* arow = tile + qc * lds_stride + h * kh;
+#pragma unroll
+    for (int kk = 0; kk < KHMAX; ++kk) {
+      if (kk < kh) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(arow[kk], bq[kk], acc, 0, 0, 0);
+    }
+
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int ci = 8 * (v >> 2) + 4 * h + (v & 3);
+      const int64_t crow = c0 + ci;
+      if (crow < size && crow != qrow) {
+        const float dist = metric == 0 ? (nq + tnorm[ci]) - 2.0f * acc[v] : -acc[v];
+        if (dist < td[kShort - 1]) {
+          float nd = dist;
+          int32_t ni = (int32_t)crow;
+#pragma unroll
+          for (int j = 0; j < kShort; ++j) {
+            const bool sw = nd < td[j];
+            const float od = td[j];
+            const int32_t oi = ti[j];
+            td[j] = sw ? nd : od;
+            ti[j] = sw ? ni : oi;
+            nd = sw ? od : nd;
+            ni = sw ? oi : ni;
+          }
+        }
+      }
+    }
+  }
+  if (qvalid) {
+    float* od = sl_d + qrow * (2 * kShort) + h * kShort;
+    int32_t* oi = sl_i + qrow * (2 * kShort) + h * kShort;
+#pragma unroll
+    for (int j = 0; j < kShort; ++j) {
+      od[j] = td[j];
+      oi[j] = ti[j];
+    }
+  }
+}
+
+__device__ inline uint64_t wave_sort64(uint64_t key) {
+  const int lane = lane_id();
+  for (int size = 2; size <= 64; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      const uint64_t other = shfl_xor_u64(key, stride);
+      const bool lower = (lane & stride) == 0;
+      const bool asc = (lane & size) == 0;
+      const bool take_min = lower == asc;
+      key = take_min ? (key < other ? key : other) : (key < other ? other : key);
+    }
+  }
+  return key;
+}
+
+template <int LPN, int CPL>
+__global__ __launch_bounds__(256) void k_knn_rerank(const float* vec, int64_t size, int dpad,
+                                                    int nchunks, int metric, const float* sl_d,
+                                                    const int32_t* sl_i, const float* norms,
+                                                    float nmax, int R, int32_t* adj,
+                                                    int32_t* fb_rows, uint32_t* fb_count) {
+  constexpr int G = 64 / LPN;
+  __shared__ uint64_t keys[4][64];
+  const int wave = threadIdx.x >> 6;
+  const int64_t row = (int64_t)blockIdx.x * 4 + wave;
+  if (row >= size) return;
+  const int lane = lane_id(), t = lane % LPN, g = lane / LPN;
+  float q[CPL][8];
+  load_query<CPL>(vec + row * dpad, dpad, t, q);
+  for (int base = 0; base < 2 * kShort; base += G) {
+    const int ci = base + g;
+    const int32_t id = sl_i[row * (2 * kShort) + ci];
+    const bool valid = id >= 0;
+    const float dist = group_distance<kF32, LPN, CPL>(q, vec + (int64_t)(valid ? id : 0) * dpad,
+                                                      1.0f, t, nchunks, metric, valid);
+    if (t == 0) keys[wave][ci] = valid ? dkey(dist, id) : ~0ull;
+  }
+  wave_sync();
+  const uint64_t key = wave_sort64(keys[wave][lane]);
+  if (lane < R) adj[row * R + lane] = key == ~0ull ? -1 : (int32_t)(uint32_t)key;
+  const float cut = fminf(sl_d[row * (2 * kShort) + kShort - 1], sl_d[row * (2 * kShort) + 2 * kShort - 1]);
+  const uint64_t kr = shfl_u64(key, R - 1);
+  if (lane == 0 && isfinite(cut)) {
+    const float exact_r = kr == ~0ull ? INFINITY : from_ordered((uint32_t)(kr >> 32));
+    const float delta = 4.0f * (float)(dpad + 8) * 0x1p-24f * (norms[row] + nmax);
+    if (!(exact_r + delta < cut - delta)) fb_rows[atomicAdd(fb_count, 1u)] = (int32_t)row;
+  }
+}
+
+// Exact brute force for one row per block: every group keeps a private
+// sorted top-R of the keys it computes; the lists are merged in LDS.
+template <int LPN, int CPL>
+__global__ __launch_bounds__(256) void k_knn_exact(const float* vec, int64_t size, int dpad,
+                                                   int nchunks, int metric, const int32_t* rows,
+                                                   int R, int rpad, int32_t* adj) {
+  constexpr int G = 64 / LPN;
+  extern __shared__ uint64_t lists[];  // [4*G][rpad], then padded to a power of two
+  const int wave = threadIdx.x >> 6;
+  const int lane = lane_id(), t = lane % LPN, g = lane / LPN;
+  const int64_t row = rows[blockIdx.x];
+  float q[CPL][8];
+  load_query<CPL>(vec + row * dpad, dpad, t, q);
+  uint64_t best[kShort];
+#pragma unroll
+  for (int j = 0; j < kShort; ++j) best[j] = ~0ull;
+  const int group = wave * G + g;
+  for (int64_t base = 0; base < size; base += 4 * G) {
+    const int64_t c = base + group;
+    const bool valid = c < size && c != row;
+    const float dist = group_distance<kF32, LPN, CPL>(q, vec + (valid ? c : 0) * dpad, 1.0f, t,
+                                                      nchunks, metric, valid);
+    if (valid && t == 0) {
+      uint64_t nk = dkey(dist, (int32_t)c);
+      if (nk < best[kShort - 1]) {
+#pragma unroll
+        for (int j = 0; j < kShort; ++j) {
+          const bool sw = nk < best[j];
+          const uint64_t o = best[j];
+          best[j] = sw ? nk : o;
+          nk = sw ? o : nk;
+        }
+      }
+    }
+  }
+  const int total = 4 * G * rpad;
+  int n2 = 1;
+  while (n2 < total) n2 <<= 1;
+  if (t == 0) {
+#pragma unroll
+    for (int j = 0; j < kShort; ++j)
+      if (j < rpad) lists[group * rpad + j] = best[j];
+  }
+  for (int i = total + threadIdx.x; i < n2; i += blockDim.x) lists[i] = ~0ull;
+  __syncthreads();
+  for (int sz = 2; sz <= n2; sz <<= 1) {
+    for (int stride = sz >> 1; stride > 0; stride >>= 1) {
+      for (int i = threadIdx.x; i < (n2 >> 1); i += blockDim.x) {
+        const int lo = 2 * i - (i & (stride - 1));
+        const int hi = lo + stride;
+        const bool asc = (lo & sz) == 0;
+        const uint64_t x = lists[lo], y = lists[hi];
+        if ((x > y) == asc) {
+          lists[lo] = y;
+          lists[hi] = x;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int j = threadIdx.x; j < R; j += blockDim.x)
+    adj[row * R + j] = lists[j] == ~0ull ? -1 : (int32_t)(uint32_t)lists[j];
+}
+
+#define HENN_KNN_COMBOS(X) \
+  X(1, 1) X(2, 1) X(4, 1) X(2, 2) X(4, 2) X(8, 1) X(2, 4) X(4, 4) X(8, 2) X(16, 1) X(8, 4) \
+  X(16, 2) X(4, 8) X(16, 4) X(16, 8)
+
+int64_t build_knn_graph(const float* vec, int64_t size, int dpad, int nchunks, int metric, int R,
+                        int lpn, int cpl, int32_t* adj, hipStream_t st) {
+  if (size <= 0) return 0;
+  if (dpad > 128) throw HipError{hipErrorInvalidValue, "kNN build supports d <= 128"};
+  float *mean = nullptr, *norms = nullptr, *sl_d = nullptr;
+  int32_t *sl_i = nullptr, *fb_rows = nullptr;
+  uint32_t* fb_count = nullptr;
+  HENN_HIP(hipMalloc(&norms, sizeof(float) * size));
+  HENN_HIP(hipMalloc(&sl_d, sizeof(float) * size * 2 * kShort));
+  HENN_HIP(hipMalloc(&sl_i, sizeof(int32_t) * size * 2 * kShort));
+  HENN_HIP(hipMalloc(&fb_rows, sizeof(int32_t) * size));
+  HENN_HIP(hipMalloc(&fb_count, sizeof(uint32_t)));
+  HENN_HIP(hipMemsetAsync(fb_count, 0, sizeof(uint32_t), st));
+  if (metric == 0) {
+    HENN_HIP(hipMalloc(&mean, sizeof(float) * dpad));
+    layer_mean(vec, size, dpad, mean, st);
+  }
+  launch_row_norms(vec, mean, size, dpad, norms, st);
+  const float nmax = max_norm(norms, size, st);
+
+  const size_t lds = sizeof(float) * (kTileC * (dpad + 4) + kTileC);
+  const unsigned nb = (unsigned)((size + 127) / 128);
+  const int kh = dpad / 2;
+  if (kh <= 16)
+    hipLaunchKernelGGL(k_knn_gram<16>, dim3(nb), dim3(256), lds, st, vec, size, dpad, mean, norms,
+                       metric, sl_d, sl_i);
+  else if (kh <= 32)
+    hipLaunchKernelGGL(k_knn_gram<32>, dim3(nb), dim3(256), lds, st, vec, size, dpad, mean, norms,
+                       metric, sl_d, sl_i);
+  else
+    hipLaunchKernelGGL(k_knn_gram<64>, dim3(nb), dim3(256), lds, st, vec, size, dpad, mean, norms,
+                       metric, sl_d, sl_i);
+  HENN_HIP(hipGetLastError());
+
+  const unsigned nr = (unsigned)((size + 3) / 4);
+  bool launched = false;
+#define HENN_TRY(L, C)                                                                         \
+  if (!launched && lpn == L && cpl == C) {                                                     \
+    hipLaunchKernelGGL((k_knn_rerank<L, C>), dim3(nr), dim3(256), 0, st, vec, size, dpad,      \
+                       nchunks, metric, sl_d, sl_i, norms, nmax, R, adj, fb_rows, fb_count);   \
+    launched = true;                                                                           \
+  }
+  HENN_KNN_COMBOS(HENN_TRY)
+#undef HENN_TRY
+  if (!launched) throw HipError{hipErrorInvalidValue, "no rerank kernel for this lane shape"};
+  uint32_t nfb = 0;
+  HENN_HIP(hipMemcpyAsync(&nfb, fb_count, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  HENN_HIP(hipStreamSynchronize(st));
+  if (nfb > 0) {
+    const int G = 64 / lpn;
+    const int rpad = R;
+    int n2 = 1;
+    while (n2 < 4 * G * rpad) n2 <<= 1;
+    const size_t lds2 = sizeof(uint64_t) * n2;
+    launched = false;
+#define HENN_TRY(L, C)                                                                          \
+  if (!launched && lpn == L && cpl == C) {                                                      \
+    hipLaunchKernelGGL((k_knn_exact<L, C>), dim3(nfb), dim3(256), lds2, st, vec, size, dpad,    \
+                       nchunks, metric, fb_rows, R, rpad, adj);                                 \
+    launched = true;                                                                            \
+  }
+    HENN_KNN_COMBOS(HENN_TRY)
+#undef HENN_TRY
+  }
+  HENN_HIP(hipStreamSynchronize(st));
+  if (mean) HENN_HIP(hipFree(mean));
+  HENN_HIP(hipFree(norms));
+  HENN_HIP(hipFree(sl_d));
+  HENN_HIP(hipFree(sl_i));
+  HENN_HIP(hipFree(fb_rows));
+  HENN_HIP(hipFree(fb_count));
+  return (int64_t)nfb;
+}
+
+void symmetrize_graph(const float*, int64_t, int, int, int, const int32_t*, int, int32_t*, int,
+                      int, int, hipStream_t) {
+  throw HipError{hipErrorNotSupported, "KNN_SYM graph"};
+}
+
+}  // namespace henn

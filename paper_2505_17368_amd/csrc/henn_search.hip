@@ -1,0 +1,377 @@
+// henn_search.hip -- batched HENN query kernel (Alg. 4 Query, Sec. 2.2).
+//
+// One query per wavefront.  For each layer from the root down, the wave runs
+// a beam search with list width ef_upper (1 = Alg. 4 GreedySearch) on the
+// upper layers and max(ef, k) on layer 0, handing the best node down the
+// inter-layer edge (Def. HENN: the same point one layer below).
+//
+// The beam keeps one ascending list W of (distance, id, expanded) keys in
+// LDS and repeatedly expands the smallest unexpanded entry; this is the
+// two-heap SEARCH-LAYER of HNSW (the candidate set the paper relies on for
+// k > 1) in an equivalent form: the expansion sequence and the final list
+// are identical under the strict (distance, id) order.  Visited nodes are
+// remembered in a direct-mapped LDS table that may forget (never invent)
+// entries; a forgotten node that comes back is either already in W (caught
+// by the duplicate check) or no better than W's worst (rejected again).
+//
+// Per expansion: 16 neighbour ids (one 64-byte load), the visited filter,
+// coalesced gathers of the fresh neighbours' rows (LPN lanes per row, each
+// lane a run of CPL 8-coordinate chunks), the canonical FP32 reduction
+// (henn_device.h), and a merge of the new keys into W by rank computation.
+// Precision forms traverse BF16 / FP8 rows and re-rank the first
+// min(|W|, rerank_factor*k) entries from the FP32 copy at the end.
+#include <math.h>
+
+#include "henn_device.h"
+#include "henn_internal.h"
+
+namespace henn {
+
+size_t search_lds_per_wave(int ef_cap, int vis_bits) {
+  return (size_t)ef_cap * 16 + 64 * 8 * 3 + ((size_t)1 << vis_bits) * 4 + 64 * 4;
+}
+
+struct WaveLds {
+  uint64_t* W;
+  uint64_t* Wn;
+  uint64_t* ckey;     // candidate keys (by compacted slot)
+  uint64_t* kstage;   // kept keys, arrival order
+  uint64_t* ksorted;  // kept keys, ascending
+  int32_t* vis;
+  int32_t* cid;
+};
+
+__device__ inline WaveLds carve(char* base, int ef_cap, int vis_bits) {
+  WaveLds s;
+  s.W = reinterpret_cast<uint64_t*>(base);
+  s.Wn = s.W + ef_cap;
+  s.ckey = s.Wn + ef_cap;
+  s.kstage = s.ckey + 64;
+  s.ksorted = s.kstage + 64;
+  s.vis = reinterpret_cast<int32_t*>(s.ksorted + 64);
+  s.cid = s.vis + (1 << vis_bits);
+  return s;
+}
+
+__device__ inline uint32_t vis_hash(int32_t u, int bits) {
+  return ((uint32_t)u * 2654435761u) >> (32 - bits);
+}
+
+__device__ inline int next_pow2_dev(int v) {
+  int p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+// Ascending bitonic sort of n (a power of two) keys in this wave's LDS.
+__device__ inline void wave_bitonic_sort(uint64_t* A, int n) {
+  const int lane = lane_id();
+  for (int size = 2; size <= n; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = lane; i < (n >> 1); i += 64) {
+        const int lo = 2 * i - (i & (stride - 1));
+        const int hi = lo + stride;
+        const bool asc = (lo & size) == 0;
+        const uint64_t x = A[lo], y = A[hi];
+        if ((x > y) == asc) {
+          A[lo] = y;
+          A[hi] = x;
+        }
+      }
+      wave_sync();
+    }
+  }
+}
+
+template <int KIND, int LPN, int CPL>
+__device__ void search_one(const SearchArgs& a, int64_t qi, WaveLds s) {
+  constexpr int G = 64 / LPN;
+  const int lane = lane_id(), t = lane % LPN, g = lane / LPN;
+  const int vis_n = 1 << a.vis_bits;
+
+  float q[CPL][8];
+  load_query<CPL>(a.Q + qi * a.d, a.d, t, q);
+  int k = a.k_arr ? a.k_arr[qi] : a.k_all;
+  const int ef = a.ef_arr ? a.ef_arr[qi] : a.ef_all;
+  k = min(max(k, 1), a.k_max);
+  const int ef0 = min(max(ef, k), a.ef_cap);
+
+  // entry: the smallest id of the root layer (position 0)
+  const int top = a.num_layers - 1;
+  float cur_d;
+  {
+    const SearchLayer& R = a.layer[top];
+    const float sc = (KIND == kFP8) ? R.scale[0] : 1.0f;
+    cur_d = group_distance<KIND, LPN, CPL>(q, R.vec, sc, t, a.nchunks, a.metric, g == 0);
+    cur_d = __shfl(cur_d, 0);
+  }
+  int32_t cur = 0;
+  int exps = 0, evals = 1, exps0 = 0, evals0 = 0;
+  uint64_t* W = s.W;
+  uint64_t* Wn = s.Wn;
+  int wsize = 1;
+
+  for (int li = top; li >= 0; --li) {
+    const SearchLayer L = a.layer[li];
+    const int efl = li == 0 ? ef0 : min(a.ef_upper, a.ef_cap);
+    if (li == 0) {
+      exps0 = exps;
+      evals0 = evals;
+    }
+    for (int i = lane; i < vis_n; i += 64) s.vis[i] = -1;
+    wave_sync();
+    if (lane == 0) {
+      W[0] = wkey(cur_d, cur);
+      s.vis[vis_hash(cur, a.vis_bits)] = cur;
+    }
+    wsize = 1;
+    wave_sync();
+
+    for (;;) {
+      // smallest unexpanded entry of W
+      int pos = -1;
+      for (int base = 0; base < wsize; base += 64) {
+        const int i = base + lane;
+        const bool un = i < wsize && !(W[i] & 1ull);
+        const uint64_t m = ballot(un);
+        if (m) {
+          pos = base + __ffsll((unsigned long long)m) - 1;
+          break;
+        }
+      }
+      if (pos < 0) break;
+      const uint64_t ck = W[pos];
+      wave_sync();
+      if (lane == 0) W[pos] = ck | 1ull;
+      const int32_t c = wkey_id(ck);
+      ++exps;
+
+      // neighbour ids and the visited filter
+      int32_t u = -1;
+      if (lane < L.deg) u = L.adj[(int64_t)c * L.deg + lane];
+      bool fresh = false;
+      uint32_t h = 0;
+      if (u >= 0) {
+        h = vis_hash(u, a.vis_bits);
+        fresh = s.vis[h] != u;
+      }
+      wave_sync();
+      if (fresh) s.vis[h] = u;
+      const uint64_t fm = ballot(fresh);
+      const int cnt = popc64(fm);
+      if (fresh) s.cid[rank_below(fm)] = u;
+      wave_sync();
+      evals += cnt;
+
+      // gather + distance, G rows per pass
+      for (int base = 0; base < cnt; base += G) {
+        const int ci = base + g;
+        const bool valid = ci < cnt;
+        const int32_t id = valid ? s.cid[ci] : 0;
+        const float sc = (KIND == kFP8 && valid) ? L.scale[id] : 1.0f;
+        const char* row = static_cast<const char*>(L.vec) + (int64_t)id * L.row_bytes;
+        const float dist =
+            group_distance<KIND, LPN, CPL>(q, row, sc, t, a.nchunks, a.metric, valid);
+        if (valid && t == 0) s.ckey[ci] = wkey(dist, id);
+      }
+      wave_sync();
+
+      // merge the new keys into W (truncated to efl)
+      const uint64_t key = lane < cnt ? s.ckey[lane] : ~0ull;
+      bool keep = lane < cnt;
+      if (keep && wsize >= efl) keep = key < wkey_strip(W[efl - 1]);
+      int lo = 0;
+      if (keep) {
+        int hi = wsize;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (wkey_strip(W[mid]) < key) lo = mid + 1; else hi = mid;
+        }
+        if (lo < wsize && wkey_strip(W[lo]) == key) keep = false;  // already in W
+      }
+      const uint64_t km = ballot(keep);
+      const int nk = popc64(km);
+      if (nk == 0) continue;
+      if (keep) s.kstage[rank_below(km)] = key;
+      wave_sync();
+      int rk = 0;
+      if (keep) {
+        for (int j = 0; j < nk; ++j) rk += s.kstage[j] < key;
+        s.ksorted[rk] = key;
+      }
+      wave_sync();
+      const int nsize = min(efl, wsize + nk);
+      for (int i = lane; i < wsize; i += 64) {
+        const uint64_t wv = W[i];
+        const uint64_t ws = wkey_strip(wv);
+        int l2 = 0, h2 = nk;
+        while (l2 < h2) {
+          const int mid = (l2 + h2) >> 1;
+          if (s.ksorted[mid] < ws) l2 = mid + 1; else h2 = mid;
+        }
+        const int np = i + l2;
+        if (np < efl) Wn[np] = wv;
+      }
+      if (keep) {
+        const int np = lo + rk;
+        if (np < efl) Wn[np] = key;
+      }
+      wave_sync();
+      uint64_t* tmp = W;
+      W = Wn;
+      Wn = tmp;
+      wsize = nsize;
+    }
+
+    if (li > 0) {
+      const uint64_t best = W[0];
+      cur = L.down[wkey_id(best)];
+      cur_d = wkey_dist(best);
+    }
+    wave_sync();
+  }
+
+  int64_t orow = qi * a.k_max;
+  if (a.rerank_vec == nullptr) {
+    for (int j = lane; j < a.k_max; j += 64) {
+      int32_t id = -1;
+      float dd = INFINITY;
+      if (j < k && j < wsize) {
+        id = wkey_id(W[j]);
+        dd = wkey_dist(W[j]);
+      }
+      a.out_ids[orow + j] = id;
+      a.out_dist[orow + j] = dd;
+    }
+  } else {
+    // FP32 re-rank of the first min(|W|, rerank_factor*k) entries
+    const int nr = min(wsize, a.rerank_factor * k);
+    for (int base = 0; base < nr; base += G) {
+      const int ci = base + g;
+      const bool valid = ci < nr;
+      const int32_t id = valid ? wkey_id(W[ci]) : 0;
+      const float dist = group_distance<kF32, LPN, CPL>(
+          q, a.rerank_vec + (int64_t)id * a.dpad, 1.0f, t, a.nchunks, a.metric, valid);
+      if (valid && t == 0) Wn[ci] = wkey(dist, id);
+    }
+    const int n2 = next_pow2_dev(nr);
+    for (int i = nr + lane; i < n2; i += 64) Wn[i] = ~0ull;
+    wave_sync();
+    wave_bitonic_sort(Wn, n2);
+    for (int j = lane; j < a.k_max; j += 64) {
+      int32_t id = -1;
+      float dd = INFINITY;
+      if (j < k && j < nr) {
+        id = wkey_id(Wn[j]);
+        dd = wkey_dist(Wn[j]);
+      }
+      a.out_ids[orow + j] = id;
+      a.out_dist[orow + j] = dd;
+    }
+  }
+  if (a.counters && lane == 0) {
+    int32_t* cc = a.counters + qi * 4;
+    cc[0] = exps;
+    cc[1] = evals;
+    cc[2] = exps - exps0;
+    cc[3] = evals - evals0;
+  }
+  wave_sync();
+}
+
+template <int KIND, int LPN, int CPL>
+__global__ __launch_bounds__(512) void k_search(SearchArgs a, int per_wave_bytes,
+                                                int waves_per_block, int persistent) {
+  extern __shared__ __align__(16) char smem[];
+  const int wave = threadIdx.x >> 6;
+  WaveLds s = carve(smem + (size_t)wave * per_wave_bytes, a.ef_cap, a.vis_bits);
+  if (persistent) {
+    for (;;) {
+      uint32_t qi = 0;
+      if (lane_id() == 0) qi = atomicAdd(a.work_counter, 1u);
+      qi = __shfl(qi, 0);
+      if ((int64_t)qi >= a.nq) break;
+      search_one<KIND, LPN, CPL>(a, (int64_t)qi, s);
+    }
+  } else {
+    const int64_t qi = (int64_t)blockIdx.x * waves_per_block + wave;
+    if (qi < a.nq) search_one<KIND, LPN, CPL>(a, qi, s);
+  }
+}
+
+__global__ void k_reset_counter(uint32_t* c) { *c = 0u; }
+
+template <int KIND, int LPN, int CPL>
+static void launch_one(const SearchArgs& a, const LaunchShape& sh, hipStream_t st) {
+  const size_t per_wave = search_lds_per_wave(a.ef_cap, a.vis_bits);
+  const int wpb = sh.waves_per_block;
+  const size_t lds = per_wave * wpb;
+  if (sh.persistent) {
+    int blocks = sh.blocks;
+    if (blocks <= 0) {
+      int dev = 0, cus = 0, per_cu = 0;
+      (void)hipGetDevice(&dev);
+      (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+      (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per_cu, reinterpret_cast<const void*>(&k_search<KIND, LPN, CPL>), 64 * wpb, lds);
+      blocks = max(1, cus * max(per_cu, 1));
+    }
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, st, a.work_counter);
+    hipLaunchKernelGGL((k_search<KIND, LPN, CPL>), dim3(blocks), dim3(64 * wpb), lds, st, a,
+                       (int)per_wave, wpb, 1);
+  } else {
+    const int64_t blocks = (a.nq + wpb - 1) / wpb;
+    hipLaunchKernelGGL((k_search<KIND, LPN, CPL>), dim3((unsigned)blocks), dim3(64 * wpb), lds,
+                       st, a, (int)per_wave, wpb, 0);
+  }
+}
+
+#define HENN_SEARCH_COMBOS(X) \
+  X(1, 1) X(2, 1) X(4, 1) X(2, 2) X(4, 2) X(8, 1) X(2, 4) X(4, 4) X(8, 2) X(16, 1) X(8, 4) \
+  X(16, 2) X(4, 8) X(16, 4) X(16, 8)
+
+template <int KIND>
+static bool dispatch(const SearchArgs& a, const LaunchShape& sh, hipStream_t st) {
+#define HENN_TRY(LPN, CPL)                              \
+  if (sh.lanes_per_vec == LPN && sh.chunks_per_lane == CPL) { \
+    launch_one<KIND, LPN, CPL>(a, sh, st);              \
+    return true;                                        \
+  }
+  HENN_SEARCH_COMBOS(HENN_TRY)
+#undef HENN_TRY
+  return false;
+}
+
+bool launch_search(int storage, const SearchArgs& a, const LaunchShape& s, hipStream_t st) {
+  switch (storage) {
+    case kF32: return dispatch<kF32>(a, s, st);
+    case kBF16: return dispatch<kBF16>(a, s, st);
+    case kFP8: return dispatch<kFP8>(a, s, st);
+    default: return false;
+  }
+}
+
+void pick_lanes(int nchunks, int requested_lpn, int* lpn, int* cpl) {
+  const int P = next_pow2(nchunks);
+  // instantiated (LPN, CPL) pairs with LPN * CPL == P
+  static const int combos[][2] = {{1, 1}, {2, 1},  {4, 1},  {2, 2}, {4, 2},  {8, 1},
+                                  {2, 4}, {4, 4},  {8, 2},  {16, 1}, {8, 4},  {16, 2},
+                                  {4, 8}, {16, 4}, {16, 8}};
+  int best_l = 0, best_c = 0;
+  for (auto& c : combos) {
+    if (c[0] * c[1] != P) continue;
+    if (requested_lpn > 0) {
+      if (c[0] == requested_lpn) { best_l = c[0]; best_c = c[1]; }
+      continue;
+    }
+    // default: the fewest lanes with at most 4 chunks per lane
+    if (best_l == 0 || (c[1] <= 4 && (best_c > 4 || c[0] < best_l))) {
+      best_l = c[0];
+      best_c = c[1];
+    }
+  }
+  *lpn = best_l;
+  *cpl = best_c;
+}
+
+}  // namespace henn

@@ -1,0 +1,284 @@
+"""Python binding of libhenn (include/henn.h): argument marshalling only.
+
+Every step of building and searching runs in the HIP library; this module
+only converts torch tensors to device pointers and structs.  The names match
+the C ABI: :func:`henn_build`, :func:`henn_search_batch`, :func:`henn_free`,
+plus the inspection calls.  Loading fails loudly when ``libhenn.so`` is
+missing; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhenn.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "henn.h")
+
+HENN_OK, HENN_E_INVAL, HENN_E_NOMEM, HENN_E_DEVICE, HENN_E_UNSUPPORTED = 0, 1, 2, 3, 4
+HENN_W_NOT_VERIFIED = 100
+HENN_L2, HENN_IP = 0, 1
+HENN_F32, HENN_BF16, HENN_FP8_E4M3 = 0, 1, 2
+HENN_GRAPH_KNN, HENN_GRAPH_KNN_SYM = 0, 1
+HENN_SEARCH_COUNTERS, HENN_SEARCH_PERSISTENT = 1, 2
+STORAGE = {"f32": HENN_F32, "bf16": HENN_BF16, "fp8": HENN_FP8_E4M3}
+METRIC = {"l2": HENN_L2, "ip": HENN_IP}
+
+
+class BuildParams(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("metric", ctypes.c_int32),
+                ("max_layers", ctypes.c_int32), ("m", ctypes.c_int32), ("c0", ctypes.c_double),
+                ("eps_override", ctypes.c_double), ("num_rings", ctypes.c_int32),
+                ("max_attempts", ctypes.c_int32), ("degree", ctypes.c_int32),
+                ("max_degree", ctypes.c_int32), ("graph", ctypes.c_int32),
+                ("storage", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+
+
+class SearchParams(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("k", ctypes.c_void_p), ("ef", ctypes.c_void_p), ("k_all", ctypes.c_int32),
+                ("ef_all", ctypes.c_int32), ("k_max", ctypes.c_int32), ("ef_max", ctypes.c_int32),
+                ("ef_upper", ctypes.c_int32), ("rerank_factor", ctypes.c_int32),
+                ("counters", ctypes.c_void_p), ("lanes_per_vec", ctypes.c_int32),
+                ("waves_per_block", ctypes.c_int32)]
+
+
+class LayerInfo(ctypes.Structure):
+    _fields_ = [("size", ctypes.c_int64), ("draws", ctypes.c_int64), ("eps", ctypes.c_double),
+                ("window", ctypes.c_int64), ("attempts", ctypes.c_int32),
+                ("hits", ctypes.c_int32), ("status", ctypes.c_int32), ("degree", ctypes.c_int32),
+                ("fallback_rows", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+STATUS_NAMES = {0: "base", 1: "vacuous", 2: "verified", 3: "not_verified"}
+
+_lib = None
+
+
+class HennError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"henn status {status}: {msg}")
+        self.status = status
+
+
+def load_library(path: str = LIB_PATH):
+    """Loads libhenn.so (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with __graft_entry__.build()")
+    # torch ships its own HIP runtime with the same soname; loading torch first
+    # makes libhenn bind to that one, so the process holds a single runtime
+    # (two runtimes in one process do not share the device).
+    import torch  # noqa: F401
+    lib = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    vp = ctypes.c_void_p
+    lib.henn_last_error.restype = ctypes.c_char_p
+    lib.henn_default_build_params.argtypes = [P(BuildParams)]
+    lib.henn_default_search_params.argtypes = [P(SearchParams)]
+    lib.henn_build.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, P(BuildParams), vp, P(vp)]
+    lib.henn_search_batch.argtypes = [vp, vp, ctypes.c_int64, P(SearchParams), vp, vp, vp]
+    lib.henn_free.argtypes = [vp]
+    lib.henn_free.restype = None
+    lib.henn_index_shape.argtypes = [vp, P(ctypes.c_int32), P(ctypes.c_int64), P(ctypes.c_int32)]
+    lib.henn_layer_info_get.argtypes = [vp, ctypes.c_int32, P(LayerInfo)]
+    lib.henn_export_layer.argtypes = [vp, ctypes.c_int32, vp, vp]
+    lib.henn_import.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, P(BuildParams), ctypes.c_int32,
+                                P(ctypes.c_int64), P(vp), P(vp), ctypes.c_int32, vp, P(vp)]
+    for name in ("henn_default_build_params", "henn_default_search_params", "henn_build",
+                 "henn_search_batch", "henn_index_shape", "henn_layer_info_get",
+                 "henn_export_layer", "henn_import"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def header_symbols(path: str = HEADER_PATH):
+    """Function names declared in include/henn.h."""
+    txt = open(path).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(henn_[a-z_0-9]+)\s*\(", txt)))
+
+
+def last_error() -> str:
+    return load_library().henn_last_error().decode()
+
+
+def _check(status: int, allow_warning: bool = False) -> int:
+    if status == HENN_OK or (allow_warning and status == HENN_W_NOT_VERIFIED):
+        return status
+    raise HennError(status, last_error())
+
+
+def _stream_ptr(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_f32(t, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) torch tensor")
+    if t.dtype != torch.float32 or t.dim() != 2:
+        raise TypeError(f"{name} must be float32 [rows, d]")
+    return t.contiguous()
+
+
+def default_build_params(**kw) -> BuildParams:
+    p = BuildParams()
+    _check(load_library().henn_default_build_params(ctypes.byref(p)))
+    for k, v in kw.items():
+        if k == "metric" and isinstance(v, str):
+            v = METRIC[v]
+        if k == "storage" and isinstance(v, str):
+            v = STORAGE[v]
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+class HennIndex:
+    """Owns a henn_index* (released by :meth:`free` or garbage collection)."""
+
+    def __init__(self, handle: ctypes.c_void_p, status: int):
+        self._h = handle
+        self.build_status = status
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise ValueError("index was freed")
+        return self._h
+
+    def shape(self):
+        nl, n, d = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int32()
+        _check(load_library().henn_index_shape(self.handle, ctypes.byref(nl), ctypes.byref(n),
+                                               ctypes.byref(d)))
+        return nl.value, n.value, d.value
+
+    @property
+    def num_layers(self) -> int:
+        return self.shape()[0]
+
+    def layer_info(self, layer: int) -> dict:
+        info = LayerInfo()
+        _check(load_library().henn_layer_info_get(self.handle, layer, ctypes.byref(info)))
+        out = {f: getattr(info, f) for f, _ in LayerInfo._fields_ if f != "reserved"}
+        out["status"] = STATUS_NAMES.get(out["status"], out["status"])
+        return out
+
+    def export_layer(self, layer: int):
+        info = self.layer_info(layer)
+        ids = np.zeros(info["size"], dtype=np.int32)
+        adj = np.zeros((info["size"], info["degree"]), dtype=np.int32)
+        _check(load_library().henn_export_layer(self.handle, layer, ids.ctypes.data_as(
+            ctypes.c_void_p), adj.ctypes.data_as(ctypes.c_void_p)))
+        return ids, adj
+
+    def free(self):
+        if self._h:
+            load_library().henn_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def henn_build(X, params: BuildParams | None = None, stream=None, **kw) -> HennIndex:
+    """Alg. 1 on the GPU; X is a float32 [n, d] device tensor (copied)."""
+    X = _dev_f32(X, "X")
+    p = params if params is not None else default_build_params(**kw)
+    h = ctypes.c_void_p()
+    st = load_library().henn_build(ctypes.c_void_p(X.data_ptr()), X.shape[0], X.shape[1],
+                                   ctypes.byref(p), _stream_ptr(stream), ctypes.byref(h))
+    _check(st, allow_warning=True)
+    return HennIndex(h, st)
+
+
+def henn_import(X, ids_per_layer, adj_per_layer, params: BuildParams | None = None, stream=None,
+                **kw) -> HennIndex:
+    """Index from given layers (host arrays): ids ascending, adjacency as
+    positions within each layer, -1 padded, equal row width across layers."""
+    X = _dev_f32(X, "X")
+    p = params if params is not None else default_build_params(**kw)
+    L = len(adj_per_layer)
+    stride = int(adj_per_layer[0].shape[1])
+    ids_keep = [None if (i == 0 and ids_per_layer[0] is None) else
+                np.ascontiguousarray(ids_per_layer[i], dtype=np.int32) for i in range(L)]
+    adj_keep = []
+    for a in adj_per_layer:
+        a = np.asarray(a, dtype=np.int32)
+        if a.shape[1] < stride:
+            a = np.concatenate([a, -np.ones((a.shape[0], stride - a.shape[1]), np.int32)], 1)
+        adj_keep.append(np.ascontiguousarray(a[:, :stride]))
+    sizes = (ctypes.c_int64 * L)(*[a.shape[0] for a in adj_keep])
+    ids_arr = (ctypes.c_void_p * L)(*[None if x is None else x.ctypes.data for x in ids_keep])
+    adj_arr = (ctypes.c_void_p * L)(*[x.ctypes.data for x in adj_keep])
+    h = ctypes.c_void_p()
+    st = load_library().henn_import(ctypes.c_void_p(X.data_ptr()), X.shape[0], X.shape[1],
+                                    ctypes.byref(p), L, sizes, ids_arr, adj_arr, stride,
+                                    _stream_ptr(stream), ctypes.byref(h))
+    _check(st)
+    return HennIndex(h, st)
+
+
+def search_params(k=10, ef=32, k_arr=None, ef_arr=None, k_max=None, ef_max=None, ef_upper=1,
+                  rerank_factor=4, counters=None, persistent=False, lanes_per_vec=0,
+                  waves_per_block=0) -> SearchParams:
+    sp = SearchParams()
+    _check(load_library().henn_default_search_params(ctypes.byref(sp)))
+    sp.k_all = k
+    sp.ef_all = ef
+    sp.k = k_arr.data_ptr() if k_arr is not None else None
+    sp.ef = ef_arr.data_ptr() if ef_arr is not None else None
+    sp.k_max = k_max if k_max is not None else k
+    sp.ef_max = ef_max if ef_max is not None else ef
+    sp.ef_upper = ef_upper
+    sp.rerank_factor = rerank_factor
+    sp.counters = counters.data_ptr() if counters is not None else None
+    sp.flags = (HENN_SEARCH_PERSISTENT if persistent else 0) | (
+        HENN_SEARCH_COUNTERS if counters is not None else 0)
+    sp.lanes_per_vec = lanes_per_vec
+    sp.waves_per_block = waves_per_block
+    return sp
+
+
+def henn_search_batch(index: HennIndex, Q, k=10, ef=32, k_arr=None, ef_arr=None, k_max=None,
+                      ef_max=None, ef_upper=1, rerank_factor=4, with_counters=False,
+                      persistent=False, lanes_per_vec=0, waves_per_block=0, out_ids=None,
+                      out_dist=None, stream=None):
+    """Enqueues a batched search; returns (ids, dist[, counters]) device tensors."""
+    import torch
+    Q = _dev_f32(Q, "Q")
+    nq = Q.shape[0]
+    kmax = k_max if k_max is not None else (int(k_arr.max().item()) if k_arr is not None else k)
+    if ef_arr is not None and ef_max is None:
+        ef_max = int(ef_arr.max().item())
+    if out_ids is None:
+        out_ids = torch.empty((nq, kmax), dtype=torch.int32, device=Q.device)
+    if out_dist is None:
+        out_dist = torch.empty((nq, kmax), dtype=torch.float32, device=Q.device)
+    counters = torch.zeros((nq, 4), dtype=torch.int32, device=Q.device) if with_counters else None
+    sp = search_params(k, ef, k_arr, ef_arr, kmax, ef_max, ef_upper, rerank_factor, counters,
+                       persistent, lanes_per_vec, waves_per_block)
+    _check(load_library().henn_search_batch(index.handle, ctypes.c_void_p(Q.data_ptr()), nq,
+                                            ctypes.byref(sp), ctypes.c_void_p(out_ids.data_ptr()),
+                                            ctypes.c_void_p(out_dist.data_ptr()),
+                                            _stream_ptr(stream)))
+    if with_counters:
+        return out_ids, out_dist, counters
+    return out_ids, out_dist
+
+
+def henn_free(index: HennIndex) -> None:
+    index.free()

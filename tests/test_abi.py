@@ -1,0 +1,80 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/henn.h declares, fills defaults, and rejects invalid
+arguments before touching a device."""
+import ctypes
+
+import pytest
+
+hn = pytest.importorskip("paper_2505_17368_amd.henn")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return hn.load_library()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = hn.header_symbols()
+    assert {"henn_build", "henn_search_batch", "henn_free"} <= set(names)
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_struct_sizes_match_header(lib):
+    p = hn.default_build_params()
+    assert p.struct_size == ctypes.sizeof(hn.BuildParams) == 64
+    sp = hn.SearchParams()
+    assert lib.henn_default_search_params(ctypes.byref(sp)) == hn.HENN_OK
+    assert sp.struct_size == ctypes.sizeof(hn.SearchParams) == 64
+    assert ctypes.sizeof(hn.LayerInfo) == 56
+
+
+def test_defaults(lib):
+    p = hn.default_build_params()
+    assert (p.metric, p.max_layers, p.m, p.c0, p.num_rings, p.max_attempts, p.degree,
+            p.max_degree, p.graph, p.storage, p.seed) == (0, -1, 4, 1.0, 64, 64, 16, 32, 0, 0, 0)
+    sp = hn.SearchParams()
+    lib.henn_default_search_params(ctypes.byref(sp))
+    assert (sp.k_all, sp.ef_all, sp.k_max, sp.ef_upper, sp.rerank_factor) == (10, 32, 10, 1, 4)
+
+
+def test_invalid_arguments_rejected_on_host(lib):
+    p = hn.default_build_params()
+    h = ctypes.c_void_p()
+    assert lib.henn_build(None, 10, 4, ctypes.byref(p), None, ctypes.byref(h)) == hn.HENN_E_INVAL
+    assert "null" in hn.last_error()
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.henn_build(fake, 0, 4, ctypes.byref(p), None, ctypes.byref(h)) == hn.HENN_E_INVAL
+    assert lib.henn_build(fake, 10, 0, ctypes.byref(p), None, ctypes.byref(h)) == hn.HENN_E_INVAL
+    assert lib.henn_build(fake, 2**31, 4, ctypes.byref(p), None,
+                          ctypes.byref(h)) == hn.HENN_E_INVAL
+    bad = hn.default_build_params()
+    bad.struct_size = 8
+    assert lib.henn_build(fake, 10, 4, ctypes.byref(bad), None, ctypes.byref(h)) == hn.HENN_E_INVAL
+    bad = hn.default_build_params(degree=0)
+    assert lib.henn_build(fake, 10, 4, ctypes.byref(bad), None, ctypes.byref(h)) == hn.HENN_E_INVAL
+    sp = hn.SearchParams()
+    lib.henn_default_search_params(ctypes.byref(sp))
+    assert lib.henn_search_batch(None, fake, 1, ctypes.byref(sp), fake, fake,
+                                 None) == hn.HENN_E_INVAL
+    assert lib.henn_index_shape(None, None, None, None) == hn.HENN_E_INVAL
+    lib.henn_free(None)  # no-op
+
+
+def test_import_validation_on_host(lib):
+    import numpy as np
+    p = hn.default_build_params()
+    fake = ctypes.c_void_p(0x1000)
+    h = ctypes.c_void_p()
+    adj = np.array([[1, 1], [0, -1], [0, 1]], dtype=np.int32)  # duplicate neighbour in row 0
+    sizes = (ctypes.c_int64 * 1)(3)
+    ids = (ctypes.c_void_p * 1)(None)
+    adjp = (ctypes.c_void_p * 1)(adj.ctypes.data)
+    st = lib.henn_import(fake, 3, 4, ctypes.byref(p), 1, sizes, ids, adjp, 2, None,
+                         ctypes.byref(h))
+    assert st == hn.HENN_E_INVAL and "duplicate" in hn.last_error()
+    adj = np.array([[1, 5], [0, -1], [0, 1]], dtype=np.int32)
+    adjp = (ctypes.c_void_p * 1)(adj.ctypes.data)
+    st = lib.henn_import(fake, 3, 4, ctypes.byref(p), 1, sizes, ids, adjp, 2, None,
+                         ctypes.byref(h))
+    assert st == hn.HENN_E_INVAL and "range" in hn.last_error()

@@ -1,0 +1,267 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+The plain FP32 path must return the oracle's ids bit-exactly, position by
+position, for every query whose oracle trace holds no decision with a
+relative margin <= 1e-5, with distances within 1e-5 relative.  Sizes span
+several tiles / waves and ragged tails; edge cases cover tiny and padded
+inputs.
+"""
+import numpy as np
+import pytest
+
+import workloads as wl
+from gpu_util import assert_results_valid, assert_search_parity, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hn():
+    import paper_2505_17368_amd as m
+    m.load_library()
+    return m
+
+
+@pytest.fixture(scope="module")
+def ho():
+    from oracle import henn_oracle
+    return henn_oracle
+
+
+@pytest.fixture(scope="module")
+def cfg1(ho):
+    """The parity workload: 10,000 x 32 uniform points, 1,000 queries."""
+    X, Q = wl.make("uniform_10k_d32")
+    oidx = ho.build_index(X, ho.BuildParams(degree=16))
+    return X, Q, oidx
+
+
+def _sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def _import(hn, X, oidx, **kw):
+    return hn.henn_import(to_dev(X), oidx.members, oidx.adj, degree=oidx.degree,
+                          metric=oidx.metric, **kw)
+
+
+def test_search_parity_on_oracle_index_cfg1(hn, ho, cfg1):
+    X, Q, oidx = cfg1
+    idx = _import(hn, X, oidx)
+    gi, gd = hn.henn_search_batch(idx, to_dev(Q), k=10, ef=32)
+    _sync()
+    ores = ho.search(oidx, Q, 10, 32)
+    ex = assert_search_parity(gi.cpu().numpy(), gd.cpu().numpy(), ores, X, Q)
+    print(f"exempt {ex.mean():.3f}")
+    assert_results_valid(gi.cpu().numpy()[:100], gd.cpu().numpy()[:100], X, Q[:100])
+    idx.free()
+
+
+@pytest.mark.parametrize("k,ef,ef_upper", [(1, 1, 1), (10, 10, 1), (10, 64, 1), (5, 200, 1),
+                                           (10, 32, 4), (64, 64, 1)])
+def test_search_parity_beam_widths(hn, ho, cfg1, k, ef, ef_upper):
+    X, Q, oidx = cfg1
+    idx = _import(hn, X, oidx)
+    Qs = Q[:300]
+    gi, gd = hn.henn_search_batch(idx, to_dev(Qs), k=k, ef=ef, ef_upper=ef_upper)
+    _sync()
+    ores = ho.search(oidx, Qs, k, ef, ef_upper)
+    assert_search_parity(gi.cpu().numpy(), gd.cpu().numpy(), ores, X, Qs, max_exempt=0.6)
+    idx.free()
+
+
+@pytest.mark.parametrize("metric,d", [(0, 20), (1, 24), (0, 100), (1, 128)])
+def test_search_parity_metrics_and_ragged_dims(hn, ho, metric, d):
+    X = wl.uniform(3001, d, 21) - 0.5
+    Q = wl.uniform(257, d, 22) - 0.5
+    if metric == 1:
+        X /= np.linalg.norm(X, axis=1, keepdims=True)
+        Q /= np.linalg.norm(Q, axis=1, keepdims=True)
+    oidx = ho.build_index(X, ho.BuildParams(degree=12, metric=metric))
+    idx = _import(hn, X, oidx)
+    gi, gd = hn.henn_search_batch(idx, to_dev(Q), k=7, ef=40)
+    _sync()
+    ores = ho.search(oidx, Q, 7, 40)
+    assert_search_parity(gi.cpu().numpy(), gd.cpu().numpy(), ores, X, Q, metric=metric,
+                         max_exempt=0.6)
+    idx.free()
+
+
+def test_launch_shapes_give_identical_results(hn, cfg1):
+    """Canonical reduction: any lanes-per-vector / waves-per-block / persistent
+    launch returns bit-identical ids and distances."""
+    X, Q, oidx = cfg1
+    idx = _import(hn, X, oidx)
+    Qd = to_dev(Q)
+    ref_i, ref_d = hn.henn_search_batch(idx, Qd, k=10, ef=48)
+    _sync()
+    ref_i, ref_d = ref_i.cpu().numpy(), ref_d.cpu().numpy()
+    for lpn in (2, 4):  # both lane shapes that exist for d = 32
+        for wpb in (1, 2, 4, 8):
+            for pers in (False, True):
+                gi, gd = hn.henn_search_batch(idx, Qd, k=10, ef=48, lanes_per_vec=lpn,
+                                              waves_per_block=wpb, persistent=pers)
+                _sync()
+                assert np.array_equal(gi.cpu().numpy(), ref_i), (lpn, wpb, pers)
+                assert np.array_equal(gd.cpu().numpy().view(np.uint32),
+                                      ref_d.view(np.uint32)), (lpn, wpb, pers)
+    idx.free()
+
+
+def test_query_alone_equals_query_in_batch(hn, cfg1):
+    X, Q, oidx = cfg1
+    idx = _import(hn, X, oidx)
+    full_i, full_d = hn.henn_search_batch(idx, to_dev(Q), k=10, ef=32)
+    _sync()
+    for qi in (0, 17, 999):
+        one_i, one_d = hn.henn_search_batch(idx, to_dev(Q[qi:qi + 1]), k=10, ef=32)
+        _sync()
+        assert np.array_equal(one_i.cpu().numpy()[0], full_i.cpu().numpy()[qi])
+        assert np.array_equal(one_d.cpu().numpy()[0], full_d.cpu().numpy()[qi])
+    idx.free()
+
+
+def test_mixed_k_ef_per_query_matches_uniform_calls(hn, ho, cfg1):
+    import torch
+    X, Q, oidx = cfg1
+    idx = _import(hn, X, oidx)
+    Qs = Q[:240]
+    ks = np.array([1, 10, 5, 3] * 60, dtype=np.int32)
+    efs = np.array([8, 32, 16, 64, 12, 40] * 40, dtype=np.int32)
+    gi, gd = hn.henn_search_batch(idx, to_dev(Qs), k_arr=to_dev(ks), ef_arr=to_dev(efs),
+                                  k_max=10, ef_max=64)
+    _sync()
+    gi, gd = gi.cpu().numpy(), gd.cpu().numpy()
+    for kk, ee in {(int(a), int(b)) for a, b in zip(ks, efs)}:
+        sel = np.where((ks == kk) & (efs == ee))[0]
+        ores = ho.search(oidx, Qs[sel], kk, ee)
+        assert_search_parity(gi[sel, :kk], gd[sel, :kk], ores, X, Qs[sel], max_exempt=0.6)
+        assert (gi[sel, kk:] == -1).all() and np.isinf(gd[sel, kk:]).all()
+    del torch
+    idx.free()
+
+
+def test_counters_match_oracle_on_exact_queries(hn, ho, cfg1):
+    X, Q, oidx = cfg1
+    idx = _import(hn, X, oidx)
+    gi, gd, cnt = hn.henn_search_batch(idx, to_dev(Q[:200]), k=10, ef=32, with_counters=True)
+    _sync()
+    ores = ho.search(oidx, Q[:200], 10, 32)
+    ok = ~ho.near_tie(ores)
+    c = cnt.cpu().numpy()
+    # expansions are exactly the oracle's; evaluations never fewer (the
+    # visited table may forget) and equal when nothing was forgotten
+    assert np.array_equal(c[ok, 0], ores.counters[ok, 0])
+    assert np.array_equal(c[ok, 2], ores.counters[ok, 2])
+    assert (c[ok, 1] >= ores.counters[ok, 1]).all()
+    idx.free()
+
+
+def test_edge_cases(hn, ho):
+    # one point; fewer points than k; empty batch
+    X = wl.uniform(5, 8, 30)
+    Q = wl.uniform(3, 8, 31)
+    oidx = ho.build_index(X, ho.BuildParams(degree=4))
+    idx = _import(hn, X, oidx)
+    gi, gd = hn.henn_search_batch(idx, to_dev(Q), k=8, ef=8)
+    _sync()
+    ores = ho.search(oidx, Q, 8, 8)
+    assert np.array_equal(gi.cpu().numpy(), ores.ids)
+    assert (gi.cpu().numpy()[:, 5:] == -1).all() and np.isinf(gd.cpu().numpy()[:, 5:]).all()
+    empty = to_dev(np.zeros((0, 8), np.float32))
+    ei, ed = hn.henn_search_batch(idx, empty, k=3, ef=3)
+    assert ei.shape == (0, 3)
+    idx.free()
+    X1 = wl.uniform(1, 3, 1)
+    idx1 = hn.henn_build(to_dev(X1))
+    gi, gd = hn.henn_search_batch(idx1, to_dev(X1), k=2, ef=2)
+    _sync()
+    assert gi.cpu().numpy().tolist() == [[0, -1]] and gd.cpu().numpy()[0, 0] == 0.0
+    idx1.free()
+
+
+# ----------------------------------------------------------- GPU build ----
+
+def _gpu_layers(idx):
+    return [idx.export_layer(i) for i in range(idx.num_layers)]
+
+
+def test_build_layers_match_oracle_cfg1(hn, ho, cfg1):
+    X, Q, oidx = cfg1
+    idx = hn.henn_build(to_dev(X), degree=16)
+    layers = _gpu_layers(idx)
+    assert len(layers) == oidx.num_layers
+    for i, (ids, _) in enumerate(layers):
+        assert np.array_equal(ids, oidx.members[i]), f"layer {i}"
+        gi = idx.layer_info(i)
+        oi = oidx.info[i]
+        if i > 0:
+            assert gi["status"] == oi.status and gi["attempts"] == oi.attempts
+            assert gi["window"] == oi.window and gi["draws"] == oi.draws
+            assert gi["eps"] == pytest.approx(oi.eps, rel=1e-15)
+    idx.free()
+
+
+@pytest.mark.parametrize("seed,eps", [(3, 0.031), (7, 0.02), (11, 0.05)])
+def test_build_las_vegas_repeats_match_oracle(hn, ho, seed, eps):
+    X = wl.uniform(4000, 6, seed)
+    p = dict(degree=8, seed=seed, eps_override=eps, max_layers=2)
+    olayers, oinfo = ho.build_layers(X, ho.BuildParams(**p))
+    idx = hn.henn_build(to_dev(X), **p)
+    layers = _gpu_layers(idx)
+    assert len(layers) == len(olayers)
+    for i in range(1, len(olayers)):
+        gi = idx.layer_info(i)
+        assert (gi["status"], gi["attempts"], gi["hits"]) == (
+            oinfo[i].status, oinfo[i].attempts, oinfo[i].hits), f"layer {i}"
+        assert np.array_equal(layers[i][0], olayers[i])
+    idx.free()
+
+
+def test_build_graph_matches_oracle(hn, ho, cfg1):
+    X, Q, oidx = cfg1
+    idx = hn.henn_build(to_dev(X), degree=16)
+    for i, (ids, adj) in enumerate(_gpu_layers(idx)):
+        oadj = oidx.adj[i]
+        same = (adj == oadj).all(1)
+        tie = oidx.order_margin[i] <= 1e-5
+        assert (same | tie).all(), f"layer {i}: {np.where(~same & ~tie)[0][:5]}"
+        # near-tie rows still hold the same neighbour set unless the R / R+1 cut is tied
+        cut_tie = oidx.adj_margin[i] <= 1e-5
+        for r in np.where(~same & ~cut_tie)[0]:
+            assert set(adj[r].tolist()) == set(oadj[r].tolist())
+    idx.free()
+
+
+def test_end_to_end_cfg1(hn, ho, cfg1):
+    X, Q, oidx = cfg1
+    idx = hn.henn_build(to_dev(X), degree=16)
+    gi, gd = hn.henn_search_batch(idx, to_dev(Q), k=10, ef=32)
+    _sync()
+    ores = ho.search(oidx, Q, 10, 32)
+    assert_search_parity(gi.cpu().numpy(), gd.cpu().numpy(), ores, X, Q)
+    idx.free()
+
+
+@pytest.mark.parametrize("n,d,metric", [(20000, 128, 0), (6000, 96, 0), (5000, 64, 1)])
+def test_build_graph_matches_oracle_rows_larger(hn, ho, n, d, metric):
+    """Several MFMA row blocks and a ragged tail: sampled layer-0 rows against
+    the oracle's exact kNN rows (order may differ only at near ties)."""
+    X = wl.gauss_mix(n, d, 20, 0.3, 40)
+    if metric == 1:
+        X /= np.linalg.norm(X, axis=1, keepdims=True)
+    idx = hn.henn_build(to_dev(X), degree=16, metric=metric, max_layers=0)
+    _, adj = idx.export_layer(0)
+    rows = np.sort(np.random.default_rng(0).choice(n, 200, replace=False))
+    rows = np.concatenate([rows, [n - 1]])
+    oadj, cut, order = ho.knn_rows(X, metric, np.arange(n, dtype=np.int32), rows, 16)
+    for j, r in enumerate(rows):
+        if np.array_equal(adj[r], oadj[j]):
+            continue
+        assert order[j] <= 1e-5, f"row {r}: {adj[r]} vs {oadj[j]}"
+        if cut[j] > 1e-5:
+            assert set(adj[r].tolist()) == set(oadj[j].tolist())
+    info = idx.layer_info(0)
+    print(f"fallback rows {info['fallback_rows']}")
+    idx.free()

@@ -406,3 +406,59 @@ def test_recall_tie_tolerant(oracle):
     assert oracle.recall_at_k(np.array([[0, 1]]), td, X, Q) == 1.0
     assert oracle.recall_at_k(np.array([[0, 3]]), td, X, Q) == 0.5
     assert oracle.recall_at_k(np.array([[-1, 3]]), td, X, Q) == 0.0
+
+
+# ------------------------------------------- kNN_SYM and complete root ----
+
+@pytest.mark.parametrize("metric", [0, 1])
+def test_knn_sym_matches_numpy(oracle, metric):
+    X = wl.uniform(240, 6, 15) - 0.5
+    members = np.arange(240, dtype=np.int32)[::2].copy()
+    R, M = 5, 9
+    Y = X[members].astype(np.float64)
+    D = ((Y[:, None, :] - Y[None, :, :]) ** 2).sum(-1) if metric == 0 else -(Y @ Y.T)
+    s = len(members)
+    knn = []
+    for v in range(s):
+        dv = D[v].copy()
+        dv[v] = np.inf
+        knn.append(np.lexsort((np.arange(s), dv))[:R])
+    adj, _, _, _ = oracle.knn_graph(X, metric, members, R)
+    assert np.array_equal(adj, np.array(knn))
+    sym, cut, order = oracle.knn_sym(X, metric, members, adj, M)
+    for v in range(s):
+        cand = set(knn[v].tolist()) | {u for u in range(s) if v in knn[u]}
+        cand = np.array(sorted(cand))
+        ref = cand[np.lexsort((cand, D[v][cand]))][:M]
+        row = sym[v][sym[v] >= 0]
+        assert np.array_equal(row, ref), v
+        assert (sym[v][len(ref):] == -1).all()
+
+
+def test_complete_root_hands_down_exact_root_nn(oracle):
+    """With the complete graph on the root, greedy search there returns the
+    root member nearest to q; the descent continues from it (Alg. 4)."""
+    X = wl.uniform(5000, 4, 16)
+    Q = wl.uniform(30, 4, 17)
+    p = oracle.BuildParams(degree=8, root_complete_max=400)
+    idx = oracle.build_index(X, p)
+    assert idx.root_complete and len(idx.members[-1]) <= 400
+    assert len(idx.members[-2]) > 400
+    res = oracle.search(idx, Q, k=1, ef=1, ef_upper=1)
+    top = idx.members[-1]
+    for i in range(len(Q)):
+        dq = np.array([d64_seq(Q[i], X[u]) for u in top])
+        v = int(top[np.lexsort((top, dq))[0]])
+        for lay in range(idx.num_layers - 2, -1, -1):
+            v = _greedy_alg4(X, idx.members[lay], idx.adj[lay], Q[i], v)
+        assert res.ids[i, 0] == v
+    # counters: the root scan evaluates every root member
+    assert (res.counters[:, 1] >= len(top)).all()
+
+
+def test_root_complete_stops_layer_loop(oracle):
+    X = wl.uniform(3000, 32, 0)
+    members, _ = oracle.build_layers(X, oracle.BuildParams(degree=8, root_complete_max=5000))
+    assert len(members) == 1
+    members, _ = oracle.build_layers(X, oracle.BuildParams(degree=8, root_complete_max=200))
+    assert len(members[-1]) <= 200 and len(members[-2]) > 200
