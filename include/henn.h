@@ -72,12 +72,20 @@ typedef struct {
   int32_t graph;          /* henn_graph */
   int32_t storage;        /* henn_storage */
   uint64_t seed;          /* key word 0 of the Philox4x64-10 stream (word 1 = 0) */
+  int32_t root_complete_max; /* > 0: stop adding layers once a layer holds at most this
+                                many points, and search that root with the complete graph
+                                (App. B.2: trivially navigable), i.e. an exhaustive scan
+                                for the root member nearest to q; 0: off */
+  int32_t reserved;
 } henn_build_params;
 
 /* Search flags */
 #define HENN_SEARCH_COUNTERS 1u   /* fill counters[] */
 #define HENN_SEARCH_PERSISTENT 2u /* one persistent launch pulling queries from a
                                      device work counter (batched form) */
+#define HENN_SEARCH_NO_ROOT_KERNEL 4u /* scan a complete-graph root inside the search
+                                         kernel instead of the separate tiled scan
+                                         (same results; for tests and tuning) */
 
 typedef struct {
   uint32_t struct_size;   /* = sizeof(henn_search_params) */
@@ -112,7 +120,8 @@ typedef struct {
 } henn_layer_info;
 
 /* Fills *p with the defaults: L2, max_layers -1, m 4, c0 1, no override,
- * 64 rings, 64 attempts, degree 16, max_degree 32, kNN graph, F32, seed 0. */
+ * 64 rings, 64 attempts, degree 16, max_degree 32, kNN graph, F32, seed 0,
+ * root_complete_max 0. */
 henn_status henn_default_build_params(henn_build_params *p);
 
 /* Defaults: no per-query arrays, k_all 10, ef_all 32, k_max 10, ef_max 32,

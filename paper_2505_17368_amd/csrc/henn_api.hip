@@ -76,6 +76,7 @@ static bool valid_build_params(const henn_build_params* p, std::string* why) {
     *why = "max_degree in [degree, 64]"; return false;
   }
   if (p->storage < HENN_F32 || p->storage > HENN_FP8_E4M3) { *why = "storage"; return false; }
+  if (p->root_complete_max < 0) { *why = "root_complete_max >= 0"; return false; }
   return true;
 }
 
@@ -329,6 +330,7 @@ henn_status henn_build(const float* X, int64_t n, int32_t d, const henn_build_pa
       const int64_t D = (s + (1ll << p->m) - 1) >> p->m;
       if (D < (int64_t)p->degree + 1) break;
       if (p->max_layers >= 0 && i > p->max_layers) break;
+      if (p->root_complete_max > 0 && s <= p->root_complete_max) break;
       local = dalloc<int32_t>(s);
       int64_t cnt = 0;
       sample_layer(ix, i, st, local, &cnt);
@@ -346,6 +348,7 @@ henn_status henn_build(const float* X, int64_t n, int32_t d, const henn_build_pa
       ix->num_layers = i + 1;
       if (L.info.status == 3) unverified = true;
     }
+    ix->root_complete = p->root_complete_max > 0 && ix->num_layers >= 2;
     for (int i = 0; i < ix->num_layers; ++i) finish_layer(ix, i, st);
     *out = ix;
     return unverified ? fail(HENN_W_NOT_VERIFIED, "a layer kept its best unverified attempt")
@@ -420,6 +423,7 @@ henn_status henn_import(const float* X, int64_t n, int32_t d, const henn_build_p
   try {
     ix = new_index(X, n, d, p, st);
     ix->num_layers = num_layers;
+    ix->root_complete = p->root_complete_max > 0 && num_layers >= 2;
     for (int i = 0; i < num_layers; ++i) {
       LayerDev& L = ix->L[i];
       L.size = sizes[i];
@@ -513,6 +517,7 @@ henn_status henn_search_batch(const henn_index* idx, const float* Q, int64_t nq,
     a.nchunks = idx->nchunks;
     a.metric = idx->metric;
     a.vis_bits = ef_need <= 64 ? 10 : ef_need <= 256 ? 11 : 12;
+    a.root_complete = idx->root_complete ? 1 : 0;
     a.out_ids = out_ids;
     a.out_dist = out_dist;
     a.counters = sp->counters;
@@ -536,8 +541,21 @@ henn_status henn_search_batch(const henn_index* idx, const float* Q, int64_t nq,
       if (!g_counter_pool[dev]) HENN_HIP(hipMalloc(&g_counter_pool[dev], 64 * sizeof(uint32_t)));
       a.work_counter = g_counter_pool[dev] + (g_counter_slot.fetch_add(1) & 63u);
     }
-    if (!launch_search(idx->storage, a, sh, st))
-      return fail(HENN_E_UNSUPPORTED, "no search kernel for this shape");
+    uint64_t* root_best = nullptr;
+    if (a.root_complete && idx->nchunks <= 16 && !(sp->flags & HENN_SEARCH_NO_ROOT_KERNEL)) {
+      int64_t per = 0;
+      const int splits = root_scan_splits(nq, idx->L[idx->num_layers - 1].size, &per);
+      HENN_HIP(hipMallocAsync((void**)&root_best, sizeof(uint64_t) * splits * nq, st));
+      if (!launch_root_scan(idx->storage, a, splits, per, root_best, st)) {
+        (void)hipFreeAsync(root_best, st);
+        return fail(HENN_E_UNSUPPORTED, "no root scan kernel for this shape");
+      }
+      a.root_best = root_best;
+      a.root_splits = splits;
+    }
+    const bool ok = launch_search(idx->storage, a, sh, st);
+    if (root_best) HENN_HIP(hipFreeAsync(root_best, st));
+    if (!ok) return fail(HENN_E_UNSUPPORTED, "no search kernel for this shape");
     HENN_HIP(hipGetLastError());
     return HENN_OK;
   } catch (const HipError& e) {

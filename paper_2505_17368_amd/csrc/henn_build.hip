@@ -151,6 +151,53 @@ int64_t compact_bitmap(const uint32_t* bitmap, int64_t s, int32_t* out_local, hi
   return (int64_t)h_total;
 }
 
+// generic exclusive scan of uint32 counts: out[0..n] (out[n] = total)
+__global__ void k_block_sum_u32(const uint32_t* in, int64_t n, uint32_t* bsum) {
+  __shared__ uint32_t part[kScanBlock / 64];
+  const int64_t i = (int64_t)blockIdx.x * kScanBlock + threadIdx.x;
+  uint32_t c = i < n ? in[i] : 0u;
+  for (int m = 32; m > 0; m >>= 1) c += __shfl_xor(c, m);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t s = 0;
+    for (int j = 0; j < kScanBlock / 64; ++j) s += part[j];
+    bsum[blockIdx.x] = s;
+  }
+}
+
+__global__ void k_block_scan_u32(const uint32_t* in, int64_t n, const uint32_t* boff,
+                                 const uint32_t* total, uint32_t* out) {
+  __shared__ uint32_t scan[kScanBlock];
+  const int64_t i = (int64_t)blockIdx.x * kScanBlock + threadIdx.x;
+  const uint32_t v = i < n ? in[i] : 0u;
+  scan[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = 1; off < kScanBlock; off <<= 1) {
+    const uint32_t a = threadIdx.x >= (unsigned)off ? scan[threadIdx.x - off] : 0u;
+    __syncthreads();
+    scan[threadIdx.x] += a;
+    __syncthreads();
+  }
+  if (i < n) out[i] = boff[blockIdx.x] + scan[threadIdx.x] - v;
+  if (i == 0) out[n] = *total;
+}
+
+int64_t exclusive_scan_u32(const uint32_t* in, int64_t n, uint32_t* out, hipStream_t st) {
+  const int64_t nb = std::max<int64_t>(1, (n + kScanBlock - 1) / kScanBlock);
+  uint32_t* bsum = nullptr;
+  HENN_HIP(hipMalloc(&bsum, sizeof(uint32_t) * (nb + 1)));
+  hipLaunchKernelGGL(k_block_sum_u32, dim3((unsigned)nb), dim3(kScanBlock), 0, st, in, n, bsum);
+  hipLaunchKernelGGL(k_scan_bsum, dim3(1), dim3(1024), 0, st, bsum, nb, bsum + nb);
+  hipLaunchKernelGGL(k_block_scan_u32, dim3((unsigned)nb), dim3(kScanBlock), 0, st, in, n, bsum,
+                     bsum + nb, out);
+  uint32_t total = 0;
+  HENN_HIP(hipMemcpyAsync(&total, bsum + nb, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  HENN_HIP(hipStreamSynchronize(st));
+  HENN_HIP(hipFree(bsum));
+  return (int64_t)total;
+}
+
 __global__ void k_map_ids(const int32_t* prev_ids, const int32_t* local, int64_t count,
                           int32_t* ids, int32_t* down) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -41,6 +41,7 @@ struct henn_index {
   int32_t metric = 0, storage = 0;
   henn_build_params params{};
   int32_t num_layers = 0;
+  bool root_complete = false;  // root searched by exhaustive scan (complete graph)
   henn::LayerDev L[HENN_MAX_LAYERS];
   int device = 0;
 };
@@ -86,11 +87,13 @@ struct SearchArgs {
   const int32_t* k_arr;
   const int32_t* ef_arr;
   int32_t k_all, ef_all, k_max, ef_upper, ef_cap, rerank_factor;
-  int32_t num_layers, d, dpad, nchunks, metric, vis_bits;
+  int32_t num_layers, d, dpad, nchunks, metric, vis_bits, root_complete;
   int32_t* out_ids;
   float* out_dist;
   int32_t* counters;
   uint32_t* work_counter;  // persistent form: device query counter
+  const uint64_t* root_best;  // [root_splits][nq] best root keys from k_root_scan, or nullptr
+  int32_t root_splits;
 };
 
 struct LaunchShape {
@@ -109,6 +112,12 @@ size_t search_lds_per_wave(int ef_cap, int vis_bits);
 // matches (storage, lanes_per_vec, chunks_per_lane).
 bool launch_search(int storage, const SearchArgs& a, const LaunchShape& s, hipStream_t st);
 
+// Exhaustive scan of a complete-graph root (dpad <= 128): writes
+// [splits][nq] best keys.  root_scan_splits() picks the split of the root.
+int root_scan_splits(int64_t nq, int64_t root_size, int64_t* rows_per_split);
+bool launch_root_scan(int storage, const SearchArgs& a, int splits, int64_t rows_per_split,
+                      uint64_t* out, hipStream_t st);
+
 // ---- build ----------------------------------------------------------------
 void launch_copy_rows(const float* src, int64_t src_stride, const int32_t* ids, int64_t count,
                       int d, float* dst, int dpad, hipStream_t st);
@@ -123,6 +132,7 @@ void launch_ring_hits(int lpn, int cpl, const float* vec, int dpad, int nchunks,
 void launch_draw_mark(uint64_t seed, int layer, int attempt, int64_t s, int64_t draws,
                       uint32_t* bitmap, hipStream_t st);
 int64_t compact_bitmap(const uint32_t* bitmap, int64_t s, int32_t* out_local, hipStream_t st);
+int64_t exclusive_scan_u32(const uint32_t* in, int64_t n, uint32_t* out, hipStream_t st);
 void launch_map_ids(const int32_t* prev_ids, const int32_t* local, int64_t count, int32_t* ids,
                     int32_t* down, hipStream_t st);
 void layer_mean(const float* vec, int64_t size, int dpad, float* mean_dev, hipStream_t st);

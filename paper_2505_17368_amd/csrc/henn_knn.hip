@@ -317,9 +317,113 @@ int64_t build_knn_graph(const float* vec, int64_t size, int dpad, int nchunks, i
   return (int64_t)nfb;
 }
 
-void symmetrize_graph(const float*, int64_t, int, int, int, const int32_t*, int, int32_t*, int,
-                      int, int, hipStream_t) {
-  throw HipError{hipErrorNotSupported, "KNN_SYM graph"};
+// ---------------------------------------------------------- kNN_SYM -----
+// Reverse edges: in-degree count, exclusive scan, scatter of the in-lists,
+// then one wave per node merges its out- and in-neighbours by (distance, id)
+// in chunks of 64 keys (sort the chunk, keep the lowest 64 of running list
+// and chunk with a bitonic half-cleaner) and writes the first max_deg.
+__global__ void k_indeg(const int32_t* adj, int64_t edges, uint32_t* cnt) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= edges) return;
+  const int32_t u = adj[e];
+  if (u >= 0) atomicAdd(cnt + u, 1u);
+}
+
+__global__ void k_scatter_in(const int32_t* adj, int64_t edges, int R, uint32_t* cursor,
+                             int32_t* inl) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= edges) return;
+  const int32_t u = adj[e];
+  if (u >= 0) inl[atomicAdd(cursor + u, 1u)] = (int32_t)(e / R);
+}
+
+template <int LPN, int CPL>
+__global__ __launch_bounds__(256) void k_sym_merge(const float* vec, int64_t size, int dpad,
+                                                   int nchunks, int metric,
+                                                   const int32_t* adj_knn, int R,
+                                                   const uint32_t* off, const int32_t* inl, int M,
+                                                   int32_t* out) {
+  constexpr int G = 64 / LPN;
+  __shared__ int32_t outids[4][32];
+  __shared__ int32_t cids[4][64];
+  __shared__ uint64_t keys[4][64];
+  const int w = threadIdx.x >> 6;
+  const int64_t v = (int64_t)blockIdx.x * 4 + w;
+  if (v >= size) return;
+  const int lane = lane_id(), t = lane % LPN, g = lane / LPN;
+  if (lane < 32) outids[w][lane] = lane < R ? adj_knn[v * R + lane] : -1;
+  wave_sync();
+  float q[CPL][8];
+  load_query<CPL>(vec + v * dpad, dpad, t, q);
+  const int64_t ib = off[v];
+  const int64_t total = R + (int64_t)(off[v + 1] - off[v]);
+  uint64_t best = ~0ull;
+  for (int64_t base = 0; base < total; base += 64) {
+    const int64_t j = base + lane;
+    int32_t cid = -1;
+    if (j < R) {
+      cid = outids[w][j];
+    } else if (j < total) {
+      const int32_t u = inl[ib + (j - R)];
+      bool dup = false;
+      for (int r = 0; r < R; ++r) dup |= outids[w][r] == u;
+      cid = dup ? -1 : u;
+    }
+    cids[w][lane] = cid;
+    wave_sync();
+    for (int pb = 0; pb < 64; pb += G) {
+      const int ci = pb + g;
+      const int32_t id = cids[w][ci];
+      const bool valid = id >= 0;
+      const float dist = group_distance<kF32, LPN, CPL>(
+          q, vec + (int64_t)(valid ? id : 0) * dpad, 1.0f, t, nchunks, metric, valid);
+      if (t == 0) keys[w][ci] = valid ? dkey(dist, id) : ~0ull;
+    }
+    wave_sync();
+    const uint64_t c = wave_sort64(keys[w][lane]);
+    const uint64_t rc = shfl_u64(c, 63 - lane);
+    uint64_t m = rc < best ? rc : best;
+    for (int stride = 32; stride > 0; stride >>= 1) {
+      const uint64_t o = shfl_xor_u64(m, stride);
+      const bool lower = (lane & stride) == 0;
+      m = lower ? (o < m ? o : m) : (o < m ? m : o);
+    }
+    best = m;
+    wave_sync();
+  }
+  if (lane < M) out[v * M + lane] = best == ~0ull ? -1 : (int32_t)(uint32_t)best;
+}
+
+void symmetrize_graph(const float* vec, int64_t size, int dpad, int nchunks, int metric,
+                      const int32_t* adj_knn, int R, int32_t* adj_out, int max_deg, int lpn,
+                      int cpl, hipStream_t st) {
+  const int64_t edges = size * R;
+  uint32_t *cnt = nullptr, *off = nullptr;
+  int32_t* inl = nullptr;
+  HENN_HIP(hipMalloc(&cnt, sizeof(uint32_t) * (size + 1)));
+  HENN_HIP(hipMalloc(&off, sizeof(uint32_t) * (size + 1)));
+  HENN_HIP(hipMalloc(&inl, sizeof(int32_t) * (edges > 0 ? edges : 1)));
+  HENN_HIP(hipMemsetAsync(cnt, 0, sizeof(uint32_t) * (size + 1), st));
+  const unsigned eb = (unsigned)((edges + 255) / 256);
+  hipLaunchKernelGGL(k_indeg, dim3(eb), dim3(256), 0, st, adj_knn, edges, cnt);
+  exclusive_scan_u32(cnt, size, off, st);
+  HENN_HIP(hipMemcpyAsync(cnt, off, sizeof(uint32_t) * size, hipMemcpyDeviceToDevice, st));
+  hipLaunchKernelGGL(k_scatter_in, dim3(eb), dim3(256), 0, st, adj_knn, edges, R, cnt, inl);
+  const unsigned nb = (unsigned)((size + 3) / 4);
+  bool launched = false;
+#define HENN_TRY(L, C)                                                                          \
+  if (!launched && lpn == L && cpl == C) {                                                      \
+    hipLaunchKernelGGL((k_sym_merge<L, C>), dim3(nb), dim3(256), 0, st, vec, size, dpad,        \
+                       nchunks, metric, adj_knn, R, off, inl, max_deg, adj_out);                \
+    launched = true;                                                                            \
+  }
+  HENN_KNN_COMBOS(HENN_TRY)
+#undef HENN_TRY
+  HENN_HIP(hipStreamSynchronize(st));
+  HENN_HIP(hipFree(cnt));
+  HENN_HIP(hipFree(off));
+  HENN_HIP(hipFree(inl));
+  if (!launched) throw HipError{hipErrorInvalidValue, "no merge kernel for this lane shape"};
 }
 
 }  // namespace henn

@@ -83,6 +83,126 @@ __device__ inline void wave_bitonic_sort(uint64_t* A, int n) {
   }
 }
 
+// One lane computes a whole distance with the same canonical order as
+// group_distance: chunk sums (eight sequential FMAs), then the pairwise tree
+// over P leaves, built left to right with a stack of partial sums (leaf c
+// merges with the pending left siblings named by the set low bits of c).
+template <int KIND, int P>
+__device__ inline float serial_distance(const float (&q)[P][8], const char* row, float scale,
+                                        int nchunks, int metric) {
+  float stack[8];
+  float v = 0.0f;
+#pragma unroll
+  for (int c = 0; c < P; ++c) {
+    v = 0.0f;
+    if (c < nchunks) {
+      float x[8];
+      Chunk<KIND>::load(row, c, x);
+      v = metric == 0 ? chunk_l2(q[c], x, scale, KIND == kFP8) : chunk_ip(q[c], x);
+    }
+#pragma unroll
+    for (int l = 0; (1 << l) < P; ++l) {
+      if (c & (1 << l)) {
+        v = stack[l] + v;
+      } else {
+        stack[l] = v;
+        break;
+      }
+    }
+  }
+  if (metric != 0) v = (KIND == kFP8) ? -(scale * v) : -v;
+  return v;
+}
+
+// Exhaustive scan of the complete-graph root for a batch of queries: one
+// thread per query (its vector in registers), root rows staged through LDS
+// tiles shared by the 256 queries of a block; the root is split over
+// blockIdx.y and each split writes its best (distance, position) key.
+constexpr int kRootTile = 32;
+
+template <int KIND, int P>
+__global__ __launch_bounds__(256) void k_root_scan(const float* Q, int64_t nq, int d, int nchunks,
+                                                   int metric, const void* rvec,
+                                                   const float* rscale, int64_t rsize,
+                                                   int64_t row_bytes, int64_t rows_per_split,
+                                                   uint64_t* best_out) {
+  extern __shared__ __align__(16) char tile[];
+  float* tscale = reinterpret_cast<float*>(tile + kRootTile * row_bytes);
+  const int64_t qi = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const bool qv = qi < nq;
+  float q[P][8];
+#pragma unroll
+  for (int c = 0; c < P; ++c) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int e = c * 8 + j;
+      q[c][j] = (qv && e < d) ? Q[qi * d + e] : 0.0f;
+    }
+  }
+  const int64_t r0 = (int64_t)blockIdx.y * rows_per_split;
+  const int64_t r1 = r0 + rows_per_split < rsize ? r0 + rows_per_split : rsize;
+  uint64_t best = ~0ull;
+  for (int64_t rt = r0; rt < r1; rt += kRootTile) {
+    const int nr = (int)(r1 - rt < kRootTile ? r1 - rt : kRootTile);
+    __syncthreads();
+    const uint2* src = reinterpret_cast<const uint2*>(static_cast<const char*>(rvec) + rt * row_bytes);
+    uint2* dst = reinterpret_cast<uint2*>(tile);
+    const int64_t nwords = (nr * row_bytes) >> 3;
+    for (int64_t i = threadIdx.x; i < nwords; i += 256) dst[i] = src[i];
+    if (KIND == kFP8 && (int)threadIdx.x < nr) tscale[threadIdx.x] = rscale[rt + threadIdx.x];
+    __syncthreads();
+    for (int r = 0; r < nr; ++r) {
+      const float sc = KIND == kFP8 ? tscale[r] : 1.0f;
+      const float dist = serial_distance<KIND, P>(q, tile + r * row_bytes, sc, nchunks, metric);
+      const uint64_t key = wkey(dist, (int32_t)(rt + r));
+      best = key < best ? key : best;
+    }
+  }
+  if (qv) best_out[(int64_t)blockIdx.y * nq + qi] = best;
+}
+
+template <int KIND>
+static bool launch_root_scan_kind(const SearchArgs& a, int P, int splits, int64_t rows_per_split,
+                                  uint64_t* out, hipStream_t st) {
+  const SearchLayer& R = a.layer[a.num_layers - 1];
+  const size_t lds = kRootTile * (size_t)R.row_bytes + kRootTile * sizeof(float);
+  const dim3 grid((unsigned)((a.nq + 255) / 256), (unsigned)splits);
+#define HENN_ROOT(PP)                                                                          \
+  if (P == PP) {                                                                               \
+    hipLaunchKernelGGL((k_root_scan<KIND, PP>), grid, dim3(256), lds, st, a.Q, a.nq, a.d,      \
+                       a.nchunks, a.metric, R.vec, R.scale, (int64_t)R.size, R.row_bytes,      \
+                       rows_per_split, out);                                                   \
+    return true;                                                                               \
+  }
+  HENN_ROOT(1) HENN_ROOT(2) HENN_ROOT(4) HENN_ROOT(8) HENN_ROOT(16)
+#undef HENN_ROOT
+  return false;
+}
+
+int root_scan_splits(int64_t nq, int64_t root_size, int64_t* rows_per_split) {
+  const int64_t qblocks = (nq + 255) / 256;
+  int64_t splits = (2048 + qblocks - 1) / qblocks;
+  const int64_t max_splits = (root_size + kRootTile - 1) / kRootTile;
+  splits = splits < 1 ? 1 : splits > max_splits ? max_splits : splits;
+  if (splits > 64) splits = 64;
+  int64_t per = (root_size + splits - 1) / splits;
+  per = (per + kRootTile - 1) / kRootTile * kRootTile;
+  *rows_per_split = per;
+  return (int)((root_size + per - 1) / per);
+}
+
+bool launch_root_scan(int storage, const SearchArgs& a, int splits, int64_t rows_per_split,
+                      uint64_t* out, hipStream_t st) {
+  const int P = next_pow2(a.nchunks);
+  if (P > 16) return false;
+  switch (storage) {
+    case kF32: return launch_root_scan_kind<kF32>(a, P, splits, rows_per_split, out, st);
+    case kBF16: return launch_root_scan_kind<kBF16>(a, P, splits, rows_per_split, out, st);
+    case kFP8: return launch_root_scan_kind<kFP8>(a, P, splits, rows_per_split, out, st);
+    default: return false;
+  }
+}
+
 template <int KIND, int LPN, int CPL>
 __device__ void search_one(const SearchArgs& a, int64_t qi, WaveLds s) {
   constexpr int G = 64 / LPN;
@@ -96,17 +216,61 @@ __device__ void search_one(const SearchArgs& a, int64_t qi, WaveLds s) {
   k = min(max(k, 1), a.k_max);
   const int ef0 = min(max(ef, k), a.ef_cap);
 
-  // entry: the smallest id of the root layer (position 0)
-  const int top = a.num_layers - 1;
+  int top = a.num_layers - 1;
   float cur_d;
-  {
+  int32_t cur = 0;
+  int exps = 0, evals = 0, exps0 = 0, evals0 = 0;
+  if (a.root_complete && top >= 1 && a.root_best) {
+    // complete graph on the root, scanned by k_root_scan: min over the splits
+    const SearchLayer& R = a.layer[top];
+    uint64_t best = ~0ull;
+    for (int sp = 0; sp < a.root_splits; ++sp) {
+      const uint64_t k = a.root_best[(int64_t)sp * a.nq + qi];
+      best = k < best ? k : best;
+    }
+    evals = R.size;
+    cur = R.down[wkey_id(best)];
+    cur_d = wkey_dist(best);
+    top -= 1;
+  } else if (a.root_complete && top >= 1) {
+    // complete graph on the root: exhaustive scan for its nearest member,
+    // two rows per group in flight
+    const SearchLayer& R = a.layer[top];
+    uint64_t best = ~0ull;
+    for (int base = 0; base < R.size; base += 2 * G) {
+      const int c0 = base + g, c1 = base + G + g;
+      const bool v0 = c0 < R.size, v1 = c1 < R.size;
+      const float s0 = (KIND == kFP8 && v0) ? R.scale[c0] : 1.0f;
+      const float s1 = (KIND == kFP8 && v1) ? R.scale[c1] : 1.0f;
+      const char* r0 = static_cast<const char*>(R.vec) + (int64_t)(v0 ? c0 : 0) * R.row_bytes;
+      const char* r1 = static_cast<const char*>(R.vec) + (int64_t)(v1 ? c1 : 0) * R.row_bytes;
+      const float d0 = group_distance<KIND, LPN, CPL>(q, r0, s0, t, a.nchunks, a.metric, v0);
+      const float d1 = group_distance<KIND, LPN, CPL>(q, r1, s1, t, a.nchunks, a.metric, v1);
+      if (v0) {
+        const uint64_t k0 = wkey(d0, c0);
+        best = k0 < best ? k0 : best;
+      }
+      if (v1) {
+        const uint64_t k1 = wkey(d1, c1);
+        best = k1 < best ? k1 : best;
+      }
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+      const uint64_t o = shfl_xor_u64(best, m);
+      best = o < best ? o : best;
+    }
+    evals = R.size;
+    cur = R.down[wkey_id(best)];
+    cur_d = wkey_dist(best);
+    top -= 1;
+  } else {
+    // entry: the smallest id of the root layer (position 0)
     const SearchLayer& R = a.layer[top];
     const float sc = (KIND == kFP8) ? R.scale[0] : 1.0f;
     cur_d = group_distance<KIND, LPN, CPL>(q, R.vec, sc, t, a.nchunks, a.metric, g == 0);
     cur_d = __shfl(cur_d, 0);
   }
-  int32_t cur = 0;
-  int exps = 0, evals = 1, exps0 = 0, evals0 = 0;
   uint64_t* W = s.W;
   uint64_t* Wn = s.Wn;
   int wsize = 1;
@@ -118,6 +282,7 @@ __device__ void search_one(const SearchArgs& a, int64_t qi, WaveLds s) {
       exps0 = exps;
       evals0 = evals;
     }
+    evals += 1;  // the entry (its distance is carried down, counted per layer)
     for (int i = lane; i < vis_n; i += 64) s.vis[i] = -1;
     wave_sync();
     if (lane == 0) {

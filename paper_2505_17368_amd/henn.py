@@ -23,7 +23,7 @@ HENN_W_NOT_VERIFIED = 100
 HENN_L2, HENN_IP = 0, 1
 HENN_F32, HENN_BF16, HENN_FP8_E4M3 = 0, 1, 2
 HENN_GRAPH_KNN, HENN_GRAPH_KNN_SYM = 0, 1
-HENN_SEARCH_COUNTERS, HENN_SEARCH_PERSISTENT = 1, 2
+HENN_SEARCH_COUNTERS, HENN_SEARCH_PERSISTENT, HENN_SEARCH_NO_ROOT_KERNEL = 1, 2, 4
 STORAGE = {"f32": HENN_F32, "bf16": HENN_BF16, "fp8": HENN_FP8_E4M3}
 METRIC = {"l2": HENN_L2, "ip": HENN_IP}
 
@@ -34,7 +34,8 @@ class BuildParams(ctypes.Structure):
                 ("eps_override", ctypes.c_double), ("num_rings", ctypes.c_int32),
                 ("max_attempts", ctypes.c_int32), ("degree", ctypes.c_int32),
                 ("max_degree", ctypes.c_int32), ("graph", ctypes.c_int32),
-                ("storage", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+                ("storage", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("root_complete_max", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class SearchParams(ctypes.Structure):
@@ -234,7 +235,7 @@ def henn_import(X, ids_per_layer, adj_per_layer, params: BuildParams | None = No
 
 def search_params(k=10, ef=32, k_arr=None, ef_arr=None, k_max=None, ef_max=None, ef_upper=1,
                   rerank_factor=4, counters=None, persistent=False, lanes_per_vec=0,
-                  waves_per_block=0) -> SearchParams:
+                  waves_per_block=0, root_kernel=True) -> SearchParams:
     sp = SearchParams()
     _check(load_library().henn_default_search_params(ctypes.byref(sp)))
     sp.k_all = k
@@ -247,7 +248,8 @@ def search_params(k=10, ef=32, k_arr=None, ef_arr=None, k_max=None, ef_max=None,
     sp.rerank_factor = rerank_factor
     sp.counters = counters.data_ptr() if counters is not None else None
     sp.flags = (HENN_SEARCH_PERSISTENT if persistent else 0) | (
-        HENN_SEARCH_COUNTERS if counters is not None else 0)
+        HENN_SEARCH_COUNTERS if counters is not None else 0) | (
+        0 if root_kernel else HENN_SEARCH_NO_ROOT_KERNEL)
     sp.lanes_per_vec = lanes_per_vec
     sp.waves_per_block = waves_per_block
     return sp
@@ -255,8 +257,8 @@ def search_params(k=10, ef=32, k_arr=None, ef_arr=None, k_max=None, ef_max=None,
 
 def henn_search_batch(index: HennIndex, Q, k=10, ef=32, k_arr=None, ef_arr=None, k_max=None,
                       ef_max=None, ef_upper=1, rerank_factor=4, with_counters=False,
-                      persistent=False, lanes_per_vec=0, waves_per_block=0, out_ids=None,
-                      out_dist=None, stream=None):
+                      persistent=False, lanes_per_vec=0, waves_per_block=0, root_kernel=True,
+                      out_ids=None, out_dist=None, stream=None):
     """Enqueues a batched search; returns (ids, dist[, counters]) device tensors."""
     import torch
     Q = _dev_f32(Q, "Q")
@@ -270,7 +272,7 @@ def henn_search_batch(index: HennIndex, Q, k=10, ef=32, k_arr=None, ef_arr=None,
         out_dist = torch.empty((nq, kmax), dtype=torch.float32, device=Q.device)
     counters = torch.zeros((nq, 4), dtype=torch.int32, device=Q.device) if with_counters else None
     sp = search_params(k, ef, k_arr, ef_arr, kmax, ef_max, ef_upper, rerank_factor, counters,
-                       persistent, lanes_per_vec, waves_per_block)
+                       persistent, lanes_per_vec, waves_per_block, root_kernel)
     _check(load_library().henn_search_batch(index.handle, ctypes.c_void_p(Q.data_ptr()), nq,
                                             ctypes.byref(sp), ctypes.c_void_p(out_ids.data_ptr()),
                                             ctypes.c_void_p(out_dist.data_ptr()),

@@ -22,7 +22,7 @@ def test_exports_every_declared_symbol(lib):
 
 def test_struct_sizes_match_header(lib):
     p = hn.default_build_params()
-    assert p.struct_size == ctypes.sizeof(hn.BuildParams) == 64
+    assert p.struct_size == ctypes.sizeof(hn.BuildParams) == 72
     sp = hn.SearchParams()
     assert lib.henn_default_search_params(ctypes.byref(sp)) == hn.HENN_OK
     assert sp.struct_size == ctypes.sizeof(hn.SearchParams) == 64
@@ -32,7 +32,8 @@ def test_struct_sizes_match_header(lib):
 def test_defaults(lib):
     p = hn.default_build_params()
     assert (p.metric, p.max_layers, p.m, p.c0, p.num_rings, p.max_attempts, p.degree,
-            p.max_degree, p.graph, p.storage, p.seed) == (0, -1, 4, 1.0, 64, 64, 16, 32, 0, 0, 0)
+            p.max_degree, p.graph, p.storage, p.seed, p.root_complete_max) == (
+                0, -1, 4, 1.0, 64, 64, 16, 32, 0, 0, 0, 0)
     sp = hn.SearchParams()
     lib.henn_default_search_params(ctypes.byref(sp))
     assert (sp.k_all, sp.ef_all, sp.k_max, sp.ef_upper, sp.rerank_factor) == (10, 32, 10, 1, 4)

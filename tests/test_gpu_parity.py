@@ -42,6 +42,8 @@ def _sync():
 
 
 def _import(hn, X, oidx, **kw):
+    if oidx.root_complete:
+        kw.setdefault("root_complete_max", len(oidx.members[-1]))
     return hn.henn_import(to_dev(X), oidx.members, oidx.adj, degree=oidx.degree,
                           metric=oidx.metric, **kw)
 
@@ -264,4 +266,83 @@ def test_build_graph_matches_oracle_rows_larger(hn, ho, n, d, metric):
             assert set(adj[r].tolist()) == set(oadj[j].tolist())
     info = idx.layer_info(0)
     print(f"fallback rows {info['fallback_rows']}")
+    idx.free()
+
+
+# ------------------------------------------- complete root, kNN_SYM ------
+
+@pytest.fixture(scope="module")
+def cfg1_sym_root(ho):
+    X, Q = wl.make("uniform_10k_d32")
+    p = ho.BuildParams(degree=16, graph=1, max_degree=32, root_complete_max=1000)
+    return X, Q, ho.build_index(X, p)
+
+
+def test_search_parity_complete_root_and_sym_graph(hn, ho, cfg1_sym_root):
+    X, Q, oidx = cfg1_sym_root
+    assert oidx.root_complete and oidx.num_layers == 2
+    idx = _import(hn, X, oidx)
+    gi, gd, cnt = hn.henn_search_batch(idx, to_dev(Q), k=10, ef=32, with_counters=True)
+    _sync()
+    ores = ho.search(oidx, Q, 10, 32)
+    ex = assert_search_parity(gi.cpu().numpy(), gd.cpu().numpy(), ores, X, Q)
+    c = cnt.cpu().numpy()
+    ok = ~ex
+    assert np.array_equal(c[ok, 0], ores.counters[ok, 0])
+    assert (c[ok, 1] >= ores.counters[ok, 1]).all()
+    idx.free()
+
+
+@pytest.mark.parametrize("storage", [1, 2])
+def test_complete_root_precision_forms_run(hn, ho, cfg1_sym_root, storage):
+    X, Q, oidx = cfg1_sym_root
+    idx = _import(hn, X, oidx, storage=storage)
+    gi, gd = hn.henn_search_batch(idx, to_dev(Q[:200]), k=10, ef=64)
+    _sync()
+    assert_results_valid(gi.cpu().numpy(), gd.cpu().numpy(), X, Q[:200])
+    idx.free()
+
+
+def test_build_sym_graph_matches_oracle(hn, ho, cfg1_sym_root):
+    X, Q, oidx = cfg1_sym_root
+    idx = hn.henn_build(to_dev(X), degree=16, graph=1, max_degree=32, root_complete_max=1000)
+    assert idx.num_layers == oidx.num_layers
+    for i in range(idx.num_layers):
+        ids, adj = idx.export_layer(i)
+        assert np.array_equal(ids, oidx.members[i])
+        same = (adj == oidx.adj[i]).all(1)
+        tie = oidx.order_margin[i] <= 3e-6
+        # a row may also move when a kNN row feeding it has a near tie at its cut
+        kadj, _, kcut, _ = ho.knn_graph(X, 0, oidx.members[i], 16)
+        knn_tie_rows = np.where(kcut <= 3e-6)[0]
+        touched = set(knn_tie_rows.tolist())
+        for r in knn_tie_rows:
+            touched |= set(kadj[r].tolist())
+        bad = [r for r in np.where(~same & ~tie)[0] if r not in touched]
+        assert not bad, f"layer {i}: rows {bad[:5]}"
+    gi, gd = hn.henn_search_batch(idx, to_dev(Q), k=10, ef=32)
+    _sync()
+    ores = ho.search(oidx, Q, 10, 32)
+    assert_search_parity(gi.cpu().numpy(), gd.cpu().numpy(), ores, X, Q)
+    idx.free()
+
+
+@pytest.mark.parametrize("storage,metric,d", [(0, 0, 32), (1, 0, 96), (2, 0, 128), (0, 1, 64),
+                                              (2, 1, 40)])
+def test_root_scan_kernel_matches_in_kernel_scan(hn, ho, storage, metric, d):
+    """The tiled root-scan kernel and the in-kernel scan compute the same
+    canonical distances, so the searches agree bit for bit."""
+    X = wl.uniform(6000, d, 50) - 0.5
+    Q = wl.uniform(700, d, 51) - 0.5
+    if metric == 1:
+        X /= np.linalg.norm(X, axis=1, keepdims=True)
+        Q /= np.linalg.norm(Q, axis=1, keepdims=True)
+    idx = hn.henn_build(to_dev(X), degree=12, metric=metric, storage=storage, graph=1,
+                        max_degree=24, root_complete_max=700)
+    assert idx.num_layers >= 2
+    a_i, a_d = hn.henn_search_batch(idx, to_dev(Q), k=10, ef=40)
+    b_i, b_d = hn.henn_search_batch(idx, to_dev(Q), k=10, ef=40, root_kernel=False)
+    _sync()
+    assert np.array_equal(a_i.cpu().numpy(), b_i.cpu().numpy())
+    assert np.array_equal(a_d.cpu().numpy().view(np.uint32), b_d.cpu().numpy().view(np.uint32))
     idx.free()
