@@ -103,6 +103,11 @@ typedef struct {
   int32_t lanes_per_vec;  /* 0 = autotuned; else 4, 8, 16, 32 or 64 lanes
                              cooperate on one neighbour vector */
   int32_t waves_per_block;/* 0 = autotuned; else 1, 2, 4 or 8 */
+  void *ev_begin;         /* hipEvent_t or NULL: recorded on hip_stream right before */
+  void *ev_end;           /* and right after the main search kernel (timing only) */
+  int32_t vis_bits;       /* 0 = autotuned; else log2 of the per-query visited-table
+                             entries in LDS, 8..13 (results do not depend on it) */
+  int32_t reserved;
 } henn_search_params;
 
 typedef struct {
@@ -150,6 +155,21 @@ henn_status henn_build(const float *X, int64_t n, int32_t d, const henn_build_pa
 henn_status henn_search_batch(const henn_index *idx, const float *Q, int64_t nq,
                               const henn_search_params *sp, int32_t *out_ids, float *out_dist,
                               void *hip_stream);
+
+/* Autotuner for the batched search.  Times candidate launch shapes (lanes
+ * cooperating on one neighbour vector, waves per workgroup, visited-table
+ * size in LDS, one-shot vs persistent launch) on the given queries with the
+ * given search parameters, writes *sp with the tuned fields set into
+ * *tuned (may be NULL), and caches the choice in the index for later calls
+ * whose tuned fields are 0 and whose storage, beam-width bucket and k_max
+ * bucket match.  Results never depend on the shape (every shape computes the
+ * same canonical distances), only the speed does.
+ *   Q: device FP32 [nq][d] calibration queries (nq >= 1); outputs are
+ *   scratch allocated inside.  Synchronous on hip_stream.
+ *   The cache write is guarded by a mutex; concurrent searches may run. */
+henn_status henn_autotune(henn_index *idx, const float *Q, int64_t nq,
+                          const henn_search_params *sp, void *hip_stream,
+                          henn_search_params *tuned);
 
 /* Releases the index.  No enqueued work may still use it.  NULL is a no-op. */
 void henn_free(henn_index *idx);

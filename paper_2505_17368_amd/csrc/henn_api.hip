@@ -516,24 +516,42 @@ henn_status henn_search_batch(const henn_index* idx, const float* Q, int64_t nq,
     a.dpad = idx->dpad;
     a.nchunks = idx->nchunks;
     a.metric = idx->metric;
-    a.vis_bits = ef_need <= 64 ? 10 : ef_need <= 256 ? 11 : 12;
+    if (sp->vis_bits != 0 && (sp->vis_bits < 8 || sp->vis_bits > 13))
+      return fail(HENN_E_INVAL, "vis_bits in [8, 13]");
+    a.vis_bits = sp->vis_bits ? sp->vis_bits : ef_need <= 64 ? 10 : ef_need <= 256 ? 11 : 12;
     a.root_complete = idx->root_complete ? 1 : 0;
     a.out_ids = out_ids;
     a.out_dist = out_dist;
     a.counters = sp->counters;
 
+    // autotuned shape for this (storage, beam bucket, k bucket), if cached
+    int want_lpn = sp->lanes_per_vec, want_wpb = sp->waves_per_block;
+    bool want_pers = (sp->flags & HENN_SEARCH_PERSISTENT) != 0;
+    {
+      std::lock_guard<std::mutex> lk(const_cast<henn_index*>(idx)->tune_mu);
+      for (const TuneEntry& te : idx->tune) {
+        if (te.storage == idx->storage && te.ef_bucket == a.ef_cap &&
+            te.k_bucket == next_pow2(sp->k_max)) {
+          if (!want_lpn) want_lpn = te.lanes_per_vec;
+          if (!want_wpb) want_wpb = te.waves_per_block;
+          if (!sp->vis_bits) a.vis_bits = te.vis_bits;
+          if (te.persistent && !(sp->flags & HENN_SEARCH_PERSISTENT)) want_pers = true;
+          break;
+        }
+      }
+    }
     LaunchShape sh;
     int lpn = 0, cpl = 0;
-    pick_lanes(idx->nchunks, sp->lanes_per_vec, &lpn, &cpl);
+    pick_lanes(idx->nchunks, want_lpn, &lpn, &cpl);
     if (lpn == 0) return fail(HENN_E_INVAL, "lanes_per_vec not available for this dimension");
     sh.lanes_per_vec = lpn;
     sh.chunks_per_lane = cpl;
     sh.vis_bits = a.vis_bits;
-    int wpb = sp->waves_per_block > 0 ? sp->waves_per_block : 4;
+    int wpb = want_wpb > 0 ? want_wpb : 4;
     if (wpb != 1 && wpb != 2 && wpb != 4 && wpb != 8) return fail(HENN_E_INVAL, "waves_per_block");
     while (wpb > 1 && search_lds_per_wave(a.ef_cap, a.vis_bits) * wpb > 65536) wpb /= 2;
     sh.waves_per_block = wpb;
-    sh.persistent = (sp->flags & HENN_SEARCH_PERSISTENT) != 0;
+    sh.persistent = want_pers;
     sh.blocks = 0;
     if (sh.persistent) {
       const int dev = idx->device;
@@ -553,12 +571,114 @@ henn_status henn_search_batch(const henn_index* idx, const float* Q, int64_t nq,
       a.root_best = root_best;
       a.root_splits = splits;
     }
+    if (sp->ev_begin) HENN_HIP(hipEventRecord(static_cast<hipEvent_t>(sp->ev_begin), st));
     const bool ok = launch_search(idx->storage, a, sh, st);
+    if (sp->ev_end) HENN_HIP(hipEventRecord(static_cast<hipEvent_t>(sp->ev_end), st));
     if (root_best) HENN_HIP(hipFreeAsync(root_best, st));
     if (!ok) return fail(HENN_E_UNSUPPORTED, "no search kernel for this shape");
     HENN_HIP(hipGetLastError());
     return HENN_OK;
   } catch (const HipError& e) {
+    return from_hip(e);
+  }
+}
+
+henn_status henn_autotune(henn_index* idx, const float* Q, int64_t nq,
+                          const henn_search_params* sp, void* hip_stream,
+                          henn_search_params* tuned) {
+  if (!idx || !Q || !sp) return fail(HENN_E_INVAL, "null argument");
+  if (sp->struct_size != sizeof(henn_search_params))
+    return fail(HENN_E_INVAL, "search params struct_size mismatch");
+  if (nq < 1) return fail(HENN_E_INVAL, "autotune needs at least one query");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  int32_t* ids = nullptr;
+  float* dist = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  try {
+    ids = dalloc<int32_t>(nq * sp->k_max);
+    dist = dalloc<float>(nq * sp->k_max);
+    HENN_HIP(hipEventCreate(&e0));
+    HENN_HIP(hipEventCreate(&e1));
+    const int P = next_pow2(idx->nchunks);
+    std::vector<int> lpns;
+    for (int l : {1, 2, 4, 8, 16}) {
+      int lp = 0, cp = 0;
+      pick_lanes(idx->nchunks, l, &lp, &cp);
+      if (lp == l && l <= P) lpns.push_back(l);
+    }
+    henn_search_params c = *sp;
+    c.counters = nullptr;
+    c.ev_begin = c.ev_end = nullptr;
+    auto time_of = [&](const henn_search_params& q) -> float {
+      float best = 1e30f;
+      for (int rep = 0; rep < 3; ++rep) {
+        HENN_HIP(hipEventRecord(e0, st));
+        henn_status s2 = henn_search_batch(idx, Q, nq, &q, ids, dist, st);
+        HENN_HIP(hipEventRecord(e1, st));
+        HENN_HIP(hipEventSynchronize(e1));
+        if (s2 != HENN_OK) return 1e30f;
+        float ms = 0.f;
+        HENN_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (rep > 0) best = std::min(best, ms);  // first run warms up
+      }
+      return best;
+    };
+    // 1) lanes per vector x visited-table size at 4 waves per block
+    henn_search_params bestp = c;
+    float bt = 1e30f;
+    for (int l : lpns) {
+      for (int vb = 8; vb <= 11; ++vb) {
+        henn_search_params q = c;
+        q.lanes_per_vec = l;
+        q.waves_per_block = 4;
+        q.vis_bits = vb;
+        q.flags &= ~HENN_SEARCH_PERSISTENT;
+        const float t = time_of(q);
+        if (t < bt) { bt = t; bestp = q; }
+      }
+    }
+    // 2) waves per block and persistent launch around the best
+    const henn_search_params base = bestp;
+    for (int w : {1, 2, 4, 8}) {
+      for (int pers = 0; pers < 2; ++pers) {
+        henn_search_params q = base;
+        q.waves_per_block = w;
+        q.flags = pers ? (q.flags | HENN_SEARCH_PERSISTENT) : (q.flags & ~HENN_SEARCH_PERSISTENT);
+        const float t = time_of(q);
+        if (t < bt) { bt = t; bestp = q; }
+      }
+    }
+    const int ef_need = std::max(std::max(sp->k_max, sp->ef ? sp->ef_max : sp->ef_all), sp->ef_upper);
+    TuneEntry te{idx->storage, next_pow2(ef_need), next_pow2(sp->k_max), bestp.lanes_per_vec,
+                 bestp.waves_per_block, bestp.vis_bits,
+                 (bestp.flags & HENN_SEARCH_PERSISTENT) ? 1 : 0};
+    {
+      std::lock_guard<std::mutex> lk(idx->tune_mu);
+      bool found = false;
+      for (TuneEntry& x : idx->tune)
+        if (x.storage == te.storage && x.ef_bucket == te.ef_bucket && x.k_bucket == te.k_bucket) {
+          x = te;
+          found = true;
+        }
+      if (!found) idx->tune.push_back(te);
+    }
+    if (tuned) {
+      *tuned = *sp;
+      tuned->lanes_per_vec = bestp.lanes_per_vec;
+      tuned->waves_per_block = bestp.waves_per_block;
+      tuned->vis_bits = bestp.vis_bits;
+      tuned->flags = bestp.flags | (sp->flags & HENN_SEARCH_COUNTERS);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(ids);
+    (void)hipFree(dist);
+    return HENN_OK;
+  } catch (const HipError& e) {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(ids);
+    (void)hipFree(dist);
     return from_hip(e);
   }
 }

@@ -4,7 +4,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "../../include/henn.h"
 
@@ -35,6 +37,14 @@ struct LayerDev {
 
 }  // namespace henn
 
+namespace henn {
+// One autotuned launch shape, valid for a (storage, beam bucket, k bucket).
+struct TuneEntry {
+  int storage, ef_bucket, k_bucket;
+  int lanes_per_vec, waves_per_block, vis_bits, persistent;
+};
+}  // namespace henn
+
 struct henn_index {
   int64_t n = 0;
   int32_t d = 0, dpad = 0, nchunks = 0;
@@ -44,6 +54,8 @@ struct henn_index {
   bool root_complete = false;  // root searched by exhaustive scan (complete graph)
   henn::LayerDev L[HENN_MAX_LAYERS];
   int device = 0;
+  std::mutex tune_mu;
+  std::vector<henn::TuneEntry> tune;  // autotuned launch shapes
 };
 
 namespace henn {

@@ -44,7 +44,9 @@ class SearchParams(ctypes.Structure):
                 ("ef_all", ctypes.c_int32), ("k_max", ctypes.c_int32), ("ef_max", ctypes.c_int32),
                 ("ef_upper", ctypes.c_int32), ("rerank_factor", ctypes.c_int32),
                 ("counters", ctypes.c_void_p), ("lanes_per_vec", ctypes.c_int32),
-                ("waves_per_block", ctypes.c_int32)]
+                ("waves_per_block", ctypes.c_int32), ("ev_begin", ctypes.c_void_p),
+                ("ev_end", ctypes.c_void_p), ("vis_bits", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class LayerInfo(ctypes.Structure):
@@ -89,11 +91,12 @@ def load_library(path: str = LIB_PATH):
     lib.henn_index_shape.argtypes = [vp, P(ctypes.c_int32), P(ctypes.c_int64), P(ctypes.c_int32)]
     lib.henn_layer_info_get.argtypes = [vp, ctypes.c_int32, P(LayerInfo)]
     lib.henn_export_layer.argtypes = [vp, ctypes.c_int32, vp, vp]
+    lib.henn_autotune.argtypes = [vp, vp, ctypes.c_int64, P(SearchParams), vp, P(SearchParams)]
     lib.henn_import.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, P(BuildParams), ctypes.c_int32,
                                 P(ctypes.c_int64), P(vp), P(vp), ctypes.c_int32, vp, P(vp)]
     for name in ("henn_default_build_params", "henn_default_search_params", "henn_build",
                  "henn_search_batch", "henn_index_shape", "henn_layer_info_get",
-                 "henn_export_layer", "henn_import"):
+                 "henn_export_layer", "henn_import", "henn_autotune"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -235,7 +238,8 @@ def henn_import(X, ids_per_layer, adj_per_layer, params: BuildParams | None = No
 
 def search_params(k=10, ef=32, k_arr=None, ef_arr=None, k_max=None, ef_max=None, ef_upper=1,
                   rerank_factor=4, counters=None, persistent=False, lanes_per_vec=0,
-                  waves_per_block=0, root_kernel=True) -> SearchParams:
+                  waves_per_block=0, root_kernel=True, events=None,
+                  vis_bits=0) -> SearchParams:
     sp = SearchParams()
     _check(load_library().henn_default_search_params(ctypes.byref(sp)))
     sp.k_all = k
@@ -252,14 +256,21 @@ def search_params(k=10, ef=32, k_arr=None, ef_arr=None, k_max=None, ef_max=None,
         0 if root_kernel else HENN_SEARCH_NO_ROOT_KERNEL)
     sp.lanes_per_vec = lanes_per_vec
     sp.waves_per_block = waves_per_block
+    sp.vis_bits = vis_bits
+    if events is not None:
+        sp.ev_begin = events[0].cuda_event
+        sp.ev_end = events[1].cuda_event
     return sp
 
 
 def henn_search_batch(index: HennIndex, Q, k=10, ef=32, k_arr=None, ef_arr=None, k_max=None,
                       ef_max=None, ef_upper=1, rerank_factor=4, with_counters=False,
                       persistent=False, lanes_per_vec=0, waves_per_block=0, root_kernel=True,
-                      out_ids=None, out_dist=None, stream=None):
-    """Enqueues a batched search; returns (ids, dist[, counters]) device tensors."""
+                      events=None, vis_bits=0, out_ids=None, out_dist=None, stream=None):
+    """Enqueues a batched search; returns (ids, dist[, counters]) device tensors.
+
+    ``events``: optional pair of recorded torch.cuda.Event (enable_timing) that
+    the library re-records around the main search kernel."""
     import torch
     Q = _dev_f32(Q, "Q")
     nq = Q.shape[0]
@@ -272,7 +283,8 @@ def henn_search_batch(index: HennIndex, Q, k=10, ef=32, k_arr=None, ef_arr=None,
         out_dist = torch.empty((nq, kmax), dtype=torch.float32, device=Q.device)
     counters = torch.zeros((nq, 4), dtype=torch.int32, device=Q.device) if with_counters else None
     sp = search_params(k, ef, k_arr, ef_arr, kmax, ef_max, ef_upper, rerank_factor, counters,
-                       persistent, lanes_per_vec, waves_per_block, root_kernel)
+                       persistent, lanes_per_vec, waves_per_block, root_kernel, events,
+                       vis_bits)
     _check(load_library().henn_search_batch(index.handle, ctypes.c_void_p(Q.data_ptr()), nq,
                                             ctypes.byref(sp), ctypes.c_void_p(out_ids.data_ptr()),
                                             ctypes.c_void_p(out_dist.data_ptr()),
@@ -280,6 +292,22 @@ def henn_search_batch(index: HennIndex, Q, k=10, ef=32, k_arr=None, ef_arr=None,
     if with_counters:
         return out_ids, out_dist, counters
     return out_ids, out_dist
+
+
+def henn_autotune(index: HennIndex, Q, k=10, ef=32, k_max=None, ef_max=None, ef_upper=1,
+                  rerank_factor=4, k_arr=None, ef_arr=None, stream=None) -> dict:
+    """Tunes and caches the launch shape for this (storage, beam, k) bucket
+    on the calibration queries Q; returns the chosen shape."""
+    Q = _dev_f32(Q, "Q")
+    kmax = k_max if k_max is not None else k
+    sp = search_params(k, ef, k_arr, ef_arr, kmax, ef_max if ef_max is not None else ef,
+                       ef_upper, rerank_factor)
+    out = SearchParams()
+    _check(load_library().henn_autotune(index.handle, ctypes.c_void_p(Q.data_ptr()), Q.shape[0],
+                                        ctypes.byref(sp), _stream_ptr(stream),
+                                        ctypes.byref(out)))
+    return {"lanes_per_vec": out.lanes_per_vec, "waves_per_block": out.waves_per_block,
+            "vis_bits": out.vis_bits, "persistent": bool(out.flags & HENN_SEARCH_PERSISTENT)}
 
 
 def henn_free(index: HennIndex) -> None:

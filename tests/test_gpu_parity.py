@@ -346,3 +346,19 @@ def test_root_scan_kernel_matches_in_kernel_scan(hn, ho, storage, metric, d):
     assert np.array_equal(a_i.cpu().numpy(), b_i.cpu().numpy())
     assert np.array_equal(a_d.cpu().numpy().view(np.uint32), b_d.cpu().numpy().view(np.uint32))
     idx.free()
+
+
+def test_autotune_caches_a_shape_and_keeps_results(hn, cfg1_sym_root):
+    X, Q, oidx = cfg1_sym_root
+    idx = _import(hn, X, oidx, storage=1)
+    Qd = to_dev(Q)
+    ref_i, ref_d = hn.henn_search_batch(idx, Qd, k=10, ef=64, lanes_per_vec=4, waves_per_block=4,
+                                        vis_bits=10)
+    _sync()
+    shape = hn.henn_autotune(idx, Qd, k=10, ef=64)
+    assert shape["lanes_per_vec"] in (1, 2, 4) and 8 <= shape["vis_bits"] <= 11
+    gi, gd = hn.henn_search_batch(idx, Qd, k=10, ef=64)  # uses the cached shape
+    _sync()
+    assert np.array_equal(gi.cpu().numpy(), ref_i.cpu().numpy())
+    assert np.array_equal(gd.cpu().numpy().view(np.uint32), ref_d.cpu().numpy().view(np.uint32))
+    idx.free()
