@@ -50,6 +50,9 @@ def parse():
     ap.add_argument("--max-degree", type=int, default=48)
     ap.add_argument("--root-max", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--shape", default=None,
+                    help="fixed launch shape 'lanes,waves,vis_bits,persistent' instead of the "
+                         "autotuner (profiling runs use the shape the default run chose)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
     return ap.parse_args()
@@ -154,7 +157,18 @@ def main():
         return out
 
     # ---- sweep: recall and single-launch time per (form, ef) ----
+    fixed = None
+    if args.shape:
+        lp, wp, vb, ps = (int(x) for x in args.shape.split(","))
+        fixed = {"lanes_per_vec": lp, "waves_per_block": wp, "vis_bits": vb, "persistent": bool(ps)}
+
     def run(idx, ef, persistent=False, events=None):
+        if fixed is not None:
+            return hn.henn_search_batch(idx, Qd, k=k, ef=ef, k_max=k, ef_max=ef, events=events,
+                                        lanes_per_vec=fixed["lanes_per_vec"],
+                                        waves_per_block=fixed["waves_per_block"],
+                                        vis_bits=fixed["vis_bits"],
+                                        persistent=fixed["persistent"])
         return hn.henn_search_batch(idx, Qd, k=k, ef=ef, k_max=k, ef_max=ef,
                                     persistent=persistent, events=events)
 
@@ -182,15 +196,20 @@ def main():
         sweep[f] = []
         for ef in efs:
             # the library's autotuner picks and caches the launch shape
-            tuned[(f, ef)] = hn.henn_autotune(indexes[f], calib, k=k, ef=ef)
+            tuned[(f, ef)] = fixed if fixed is not None else hn.henn_autotune(
+                indexes[f], calib, k=k, ef=ef)
             ids, dist = run(indexes[f], ef)
             torch.cuda.synchronize()
             ids_h = ids.cpu().numpy()
             rec = recall_of(ids_h, gt_dist, dist_rows, sample)
-            ts = time_launches(indexes[f], ef, 5)
-            tp = time_launches(indexes[f], ef, 5, persistent=True)
-            best = min(float(np.median(ts)), float(np.median(tp)))
-            pers = float(np.median(tp)) < float(np.median(ts))
+            if fixed is not None:
+                ts = time_launches(indexes[f], ef, 5)
+                best, pers = float(np.median(ts)), fixed["persistent"]
+            else:
+                ts = time_launches(indexes[f], ef, 5)
+                tp = time_launches(indexes[f], ef, 5, persistent=True)
+                best = min(float(np.median(ts)), float(np.median(tp)))
+                pers = float(np.median(tp)) < float(np.median(ts))
             qps = nq / (best / 1e3)
             sweep[f].append({"ef": ef, "recall": round(rec, 4), "ms": round(best, 3),
                              "qps": round(qps, 1), "persistent": pers,
@@ -211,7 +230,8 @@ def main():
 
     # ---- counters for the algorithmic byte model (FP32 form, same ef) ----
     _, _, cnt = hn.henn_search_batch(base, Qd, k=k, ef=ef, k_max=k, ef_max=ef,
-                                     with_counters=True)
+                                     with_counters=True, lanes_per_vec=4, waves_per_block=4,
+                                     vis_bits=10)
     torch.cuda.synchronize()
     cnt = cnt.cpu().numpy().astype(np.float64)
 
@@ -285,7 +305,17 @@ def main():
     bytes_q = evals * (d * b + bs) + exps * deg * 4 + n_rr * d * 4 + d * 4 + k * 8
     kernel_ms = float(np.mean(search_ms))
     achieved = bytes_q * nq / (kernel_ms / 1e3) / 1e9
+    # measured HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE,
+    # copy-calibrated), valid only while the kernel source is unchanged and
+    # for the same workload / form / beam width
     traffic = None
+    tpath = os.path.join(ROOT, "profiles", "k_search_traffic.json")
+    if os.path.exists(tpath):
+        from paper_2505_17368_amd.kernel_hash import search_kernel_hash
+        tr = json.load(open(tpath))
+        if (tr.get("source_hash") == search_kernel_hash() and tr.get("workload") == args.workload
+                and tr.get("form") == head_form and tr.get("ef") == ef):
+            traffic = round(tr["fetch_bytes"] + tr["write_bytes"])
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "bytes_per_query": round(bytes_q, 1), "evals_per_query": round(evals, 1),
