@@ -108,6 +108,10 @@ typedef struct {
   int32_t vis_bits;       /* 0 = autotuned; else log2 of the per-query visited-table
                              entries in LDS, 8..13 (results do not depend on it) */
   int32_t reserved;
+  void *workspace;        /* device scratch or NULL; when it holds at least
+                             henn_search_workspace_size() bytes the call allocates
+                             nothing (needed under hipGraph capture) */
+  int64_t workspace_bytes;
 } henn_search_params;
 
 typedef struct {
@@ -170,6 +174,26 @@ henn_status henn_search_batch(const henn_index *idx, const float *Q, int64_t nq,
 henn_status henn_autotune(henn_index *idx, const float *Q, int64_t nq,
                           const henn_search_params *sp, void *hip_stream,
                           henn_search_params *tuned);
+
+/* Scratch bytes henn_search_batch needs for nq queries with these params
+ * (root-scan partial results and the persistent work counter); 0 when it
+ * needs none.  Host-only. */
+henn_status henn_search_workspace_size(const henn_index *idx, int64_t nq,
+                                       const henn_search_params *sp, int64_t *bytes);
+
+/* Batched form captured once in a hipGraph: the launches of one
+ * henn_search_batch(idx, Q, nq, sp, out_ids, out_dist) call (root scan,
+ * counter reset, persistent search) are recorded on a private stream and
+ * instantiated; henn_search_graph_launch replays them on hip_stream.  Q and
+ * the outputs are bound at creation: refill Q in place between replays.
+ * The graph owns its workspace; it holds no memset nodes.  The index and the
+ * bound buffers must outlive the graph. */
+typedef struct henn_search_graph henn_search_graph;
+henn_status henn_search_graph_create(const henn_index *idx, const float *Q, int64_t nq,
+                                     const henn_search_params *sp, int32_t *out_ids,
+                                     float *out_dist, henn_search_graph **out);
+henn_status henn_search_graph_launch(henn_search_graph *g, void *hip_stream);
+void henn_search_graph_free(henn_search_graph *g);
 
 /* Releases the index.  No enqueued work may still use it.  NULL is a no-op. */
 void henn_free(henn_index *idx);

@@ -16,6 +16,7 @@
 #include <atomic>
 #include <cstdlib>
 #include <new>
+#include <stdexcept>
 #include <string>
 #include <vector>
 
@@ -463,6 +464,21 @@ henn_status henn_import(const float* X, int64_t n, int32_t d, const henn_build_p
   }
 }
 
+static bool root_kernel_used(const henn_index* idx, const henn_search_params* sp) {
+  return idx->root_complete && idx->nchunks <= 16 && !(sp->flags & HENN_SEARCH_NO_ROOT_KERNEL);
+}
+
+static int64_t search_workspace_bytes(const henn_index* idx, int64_t nq,
+                                      const henn_search_params* sp) {
+  int64_t b = 256;  // persistent work counter, padded
+  if (root_kernel_used(idx, sp)) {
+    int64_t per = 0;
+    const int splits = root_scan_splits(nq, idx->L[idx->num_layers - 1].size, &per);
+    b += (int64_t)sizeof(uint64_t) * splits * nq;
+  }
+  return b;
+}
+
 static std::atomic<uint32_t> g_counter_slot{0};
 static uint32_t* g_counter_pool[64] = {nullptr};  // per device id, 64 counters each
 
@@ -553,19 +569,30 @@ henn_status henn_search_batch(const henn_index* idx, const float* Q, int64_t nq,
     sh.waves_per_block = wpb;
     sh.persistent = want_pers;
     sh.blocks = 0;
-    if (sh.persistent) {
+    if (sh.persistent && !(sp->workspace && sp->workspace_bytes >= search_workspace_bytes(idx, nq, sp))) {
       const int dev = idx->device;
       if (dev < 0 || dev >= 64) return fail(HENN_E_UNSUPPORTED, "device id");
       if (!g_counter_pool[dev]) HENN_HIP(hipMalloc(&g_counter_pool[dev], 64 * sizeof(uint32_t)));
       a.work_counter = g_counter_pool[dev] + (g_counter_slot.fetch_add(1) & 63u);
     }
+    // scratch: the persistent work counter (256 B) then the root-scan keys
+    const int64_t need = search_workspace_bytes(idx, nq, sp);
+    const bool use_ws = sp->workspace && sp->workspace_bytes >= need;
+    char* ws = use_ws ? static_cast<char*>(sp->workspace) : nullptr;
+    if (sh.persistent && use_ws) a.work_counter = reinterpret_cast<uint32_t*>(ws);
     uint64_t* root_best = nullptr;
-    if (a.root_complete && idx->nchunks <= 16 && !(sp->flags & HENN_SEARCH_NO_ROOT_KERNEL)) {
+    bool root_owned = false;
+    if (root_kernel_used(idx, sp)) {
       int64_t per = 0;
       const int splits = root_scan_splits(nq, idx->L[idx->num_layers - 1].size, &per);
-      HENN_HIP(hipMallocAsync((void**)&root_best, sizeof(uint64_t) * splits * nq, st));
+      if (use_ws) {
+        root_best = reinterpret_cast<uint64_t*>(ws + 256);
+      } else {
+        HENN_HIP(hipMallocAsync((void**)&root_best, sizeof(uint64_t) * splits * nq, st));
+        root_owned = true;
+      }
       if (!launch_root_scan(idx->storage, a, splits, per, root_best, st)) {
-        (void)hipFreeAsync(root_best, st);
+        if (root_owned) (void)hipFreeAsync(root_best, st);
         return fail(HENN_E_UNSUPPORTED, "no root scan kernel for this shape");
       }
       a.root_best = root_best;
@@ -574,7 +601,7 @@ henn_status henn_search_batch(const henn_index* idx, const float* Q, int64_t nq,
     if (sp->ev_begin) HENN_HIP(hipEventRecord(static_cast<hipEvent_t>(sp->ev_begin), st));
     const bool ok = launch_search(idx->storage, a, sh, st);
     if (sp->ev_end) HENN_HIP(hipEventRecord(static_cast<hipEvent_t>(sp->ev_end), st));
-    if (root_best) HENN_HIP(hipFreeAsync(root_best, st));
+    if (root_owned) HENN_HIP(hipFreeAsync(root_best, st));
     if (!ok) return fail(HENN_E_UNSUPPORTED, "no search kernel for this shape");
     HENN_HIP(hipGetLastError());
     return HENN_OK;
@@ -681,6 +708,83 @@ henn_status henn_autotune(henn_index* idx, const float* Q, int64_t nq,
     (void)hipFree(dist);
     return from_hip(e);
   }
+}
+
+henn_status henn_search_workspace_size(const henn_index* idx, int64_t nq,
+                                       const henn_search_params* sp, int64_t* bytes) {
+  if (!idx || !sp || !bytes) return fail(HENN_E_INVAL, "null argument");
+  if (sp->struct_size != sizeof(henn_search_params))
+    return fail(HENN_E_INVAL, "search params struct_size mismatch");
+  if (nq < 0) return fail(HENN_E_INVAL, "nq < 0");
+  *bytes = search_workspace_bytes(idx, nq, sp);
+  return HENN_OK;
+}
+
+}  // extern "C"
+
+struct henn_search_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  void* workspace = nullptr;
+};
+
+extern "C" {
+
+henn_status henn_search_graph_create(const henn_index* idx, const float* Q, int64_t nq,
+                                     const henn_search_params* sp, int32_t* out_ids,
+                                     float* out_dist, henn_search_graph** out) {
+  if (!idx || !sp || !out) return fail(HENN_E_INVAL, "null argument");
+  if (sp->struct_size != sizeof(henn_search_params))
+    return fail(HENN_E_INVAL, "search params struct_size mismatch");
+  if (nq < 1) return fail(HENN_E_INVAL, "a graph needs nq >= 1");
+  if (sp->ev_begin || sp->ev_end) return fail(HENN_E_INVAL, "no timing events in a graph");
+  henn_search_graph* g = new henn_search_graph();
+  hipStream_t cs = nullptr;
+  try {
+    const int64_t need = search_workspace_bytes(idx, nq, sp);
+    HENN_HIP(hipMalloc(&g->workspace, need));
+    HENN_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    henn_search_params c = *sp;
+    c.workspace = g->workspace;
+    c.workspace_bytes = need;
+    HENN_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    const henn_status st = henn_search_batch(idx, Q, nq, &c, out_ids, out_dist, cs);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(cs, &graph);
+    if (st != HENN_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      throw std::runtime_error(henn_last_error());
+    }
+    HENN_HIP(ec);
+    g->graph = graph;
+    HENN_HIP(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+    HENN_HIP(hipStreamDestroy(cs));
+    *out = g;
+    return HENN_OK;
+  } catch (const HipError& e) {
+    if (cs) (void)hipStreamDestroy(cs);
+    henn_search_graph_free(g);
+    return from_hip(e);
+  } catch (const std::exception& e) {
+    if (cs) (void)hipStreamDestroy(cs);
+    henn_search_graph_free(g);
+    return fail(HENN_E_INVAL, std::string("capture failed: ") + e.what());
+  }
+}
+
+henn_status henn_search_graph_launch(henn_search_graph* g, void* hip_stream) {
+  if (!g || !g->exec) return fail(HENN_E_INVAL, "null graph");
+  const hipError_t e = hipGraphLaunch(g->exec, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return from_hip(HipError{e, "hipGraphLaunch"});
+  return HENN_OK;
+}
+
+void henn_search_graph_free(henn_search_graph* g) {
+  if (!g) return;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  if (g->workspace) (void)hipFree(g->workspace);
+  delete g;
 }
 
 void henn_free(henn_index* idx) { destroy(idx); }

@@ -46,7 +46,8 @@ class SearchParams(ctypes.Structure):
                 ("counters", ctypes.c_void_p), ("lanes_per_vec", ctypes.c_int32),
                 ("waves_per_block", ctypes.c_int32), ("ev_begin", ctypes.c_void_p),
                 ("ev_end", ctypes.c_void_p), ("vis_bits", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("reserved", ctypes.c_int32), ("workspace", ctypes.c_void_p),
+                ("workspace_bytes", ctypes.c_int64)]
 
 
 class LayerInfo(ctypes.Structure):
@@ -92,11 +93,20 @@ def load_library(path: str = LIB_PATH):
     lib.henn_layer_info_get.argtypes = [vp, ctypes.c_int32, P(LayerInfo)]
     lib.henn_export_layer.argtypes = [vp, ctypes.c_int32, vp, vp]
     lib.henn_autotune.argtypes = [vp, vp, ctypes.c_int64, P(SearchParams), vp, P(SearchParams)]
+    lib.henn_search_workspace_size.argtypes = [vp, ctypes.c_int64, P(SearchParams),
+                                               P(ctypes.c_int64)]
+    lib.henn_search_graph_create.argtypes = [vp, vp, ctypes.c_int64, P(SearchParams), vp, vp,
+                                             P(vp)]
+    lib.henn_search_graph_launch.argtypes = [vp, vp]
+    lib.henn_search_graph_free.argtypes = [vp]
+    lib.henn_search_graph_free.restype = None
     lib.henn_import.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, P(BuildParams), ctypes.c_int32,
                                 P(ctypes.c_int64), P(vp), P(vp), ctypes.c_int32, vp, P(vp)]
     for name in ("henn_default_build_params", "henn_default_search_params", "henn_build",
                  "henn_search_batch", "henn_index_shape", "henn_layer_info_get",
-                 "henn_export_layer", "henn_import", "henn_autotune"):
+                 "henn_export_layer", "henn_import", "henn_autotune",
+                 "henn_search_workspace_size", "henn_search_graph_create",
+                 "henn_search_graph_launch"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -308,6 +318,47 @@ def henn_autotune(index: HennIndex, Q, k=10, ef=32, k_max=None, ef_max=None, ef_
                                         ctypes.byref(out)))
     return {"lanes_per_vec": out.lanes_per_vec, "waves_per_block": out.waves_per_block,
             "vis_bits": out.vis_bits, "persistent": bool(out.flags & HENN_SEARCH_PERSISTENT)}
+
+
+class SearchGraph:
+    """A batched search captured once in a hipGraph (henn_search_graph_*).
+
+    Q and the outputs are bound at capture; refill ``self.Q`` in place and
+    call :meth:`launch` to replay."""
+
+    def __init__(self, index: HennIndex, Q, k=10, ef=32, k_arr=None, ef_arr=None, k_max=None,
+                 ef_max=None, ef_upper=1, rerank_factor=4, persistent=True):
+        import torch
+        self.index = index
+        self.Q = _dev_f32(Q, "Q")
+        nq = self.Q.shape[0]
+        kmax = k_max if k_max is not None else k
+        self.k_arr, self.ef_arr = k_arr, ef_arr
+        self.ids = torch.empty((nq, kmax), dtype=torch.int32, device=self.Q.device)
+        self.dist = torch.empty((nq, kmax), dtype=torch.float32, device=self.Q.device)
+        sp = search_params(k, ef, k_arr, ef_arr, kmax, ef_max if ef_max is not None else ef,
+                           ef_upper, rerank_factor, persistent=persistent)
+        self._g = ctypes.c_void_p()
+        torch.cuda.synchronize()
+        _check(load_library().henn_search_graph_create(
+            index.handle, ctypes.c_void_p(self.Q.data_ptr()), nq, ctypes.byref(sp),
+            ctypes.c_void_p(self.ids.data_ptr()), ctypes.c_void_p(self.dist.data_ptr()),
+            ctypes.byref(self._g)))
+
+    def launch(self, stream=None):
+        _check(load_library().henn_search_graph_launch(self._g, _stream_ptr(stream)))
+        return self.ids, self.dist
+
+    def free(self):
+        if self._g:
+            load_library().henn_search_graph_free(self._g)
+            self._g = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
 
 
 def henn_free(index: HennIndex) -> None:

@@ -362,3 +362,31 @@ def test_autotune_caches_a_shape_and_keeps_results(hn, cfg1_sym_root):
     assert np.array_equal(gi.cpu().numpy(), ref_i.cpu().numpy())
     assert np.array_equal(gd.cpu().numpy().view(np.uint32), ref_d.cpu().numpy().view(np.uint32))
     idx.free()
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_search_graph_replays_match_eager(hn, cfg1_sym_root, mixed):
+    """hipGraph form: every replay (new queries copied into the bound buffer,
+    eager work and synchronisation in between) equals the eager search."""
+    import torch
+    X, Q, oidx = cfg1_sym_root
+    idx = _import(hn, X, oidx, storage=2)
+    n = 400
+    kw = dict(k=10, ef=64)
+    if mixed:
+        ks = to_dev(np.array([1, 10, 5, 10] * (n // 4), dtype=np.int32))
+        efs = to_dev(np.array([32, 64, 16, 48, 64] * (n // 5), dtype=np.int32))
+        kw = dict(k=10, ef=64, k_arr=ks, ef_arr=efs, k_max=10, ef_max=64)
+    g = hn.SearchGraph(idx, to_dev(Q[:n]).clone(), persistent=True, **kw)
+    for rep in range(4):
+        qs = np.roll(Q, -137 * rep, axis=0)[:n].copy()
+        g.Q.copy_(to_dev(qs))
+        gi, gd = g.launch()
+        torch.cuda.synchronize()
+        gi, gd = gi.cpu().numpy().copy(), gd.cpu().numpy().copy()
+        ei, ed = hn.henn_search_batch(idx, to_dev(qs), **kw)
+        torch.cuda.synchronize()
+        assert np.array_equal(gi, ei.cpu().numpy()), rep
+        assert np.array_equal(gd.view(np.uint32), ed.cpu().numpy().view(np.uint32)), rep
+    g.free()
+    idx.free()
