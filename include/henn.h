@@ -195,6 +195,59 @@ henn_status henn_search_graph_create(const henn_index *idx, const float *Q, int6
 henn_status henn_search_graph_launch(henn_search_graph *g, void *hip_stream);
 void henn_search_graph_free(henn_search_graph *g);
 
+/* ---------------------------------------------------------------------
+ * Serving form: a continuous-batching request loop on one index.
+ * Requests wait in a host FIFO and are admitted at a tick when a slot is
+ * free and the device state pool has room for the request's traversal
+ * state (list of next_pow2(max(ef, k)) 8-byte keys + the visited table,
+ * rounded to 256 B): admission is by memory.  Each tick advances every
+ * admitted request by at most steps_per_tick expansions in one launch, so
+ * new requests join while others are in flight.  Results equal those of
+ * henn_search_batch with the same shape (the traversal code is shared and
+ * each request's state is private), whatever else is in flight.
+ * The server uses its own non-blocking stream; the index must outlive it.
+ * Not thread-safe: one host thread drives a server.
+ * --------------------------------------------------------------------- */
+typedef struct henn_server henn_server;
+
+typedef struct {
+  uint32_t struct_size;   /* = sizeof(henn_server_params) */
+  int32_t max_slots;      /* requests in flight at most */
+  int64_t pool_bytes;     /* device bytes for per-request traversal state */
+  int32_t steps_per_tick; /* expansions per request per tick */
+  int32_t k_max;          /* largest k; result row width */
+  int32_t ef_max;         /* largest beam width */
+  int32_t ef_upper;       /* beam width above layer 0 */
+  int32_t rerank_factor;  /* precision forms */
+  int32_t lanes_per_vec;  /* 0 = default shape */
+  int32_t waves_per_block;
+  int32_t vis_bits;       /* 0 = 10 */
+} henn_server_params;
+
+typedef struct {
+  int64_t pending, active, completed, admitted, ticks, pool_bytes_used, max_active,
+      done_queued;
+} henn_server_stats_t;
+
+/* Defaults: 4096 slots, 64 MiB pool, 16 steps per tick, k_max 10,
+ * ef_max 128, ef_upper 1, rerank_factor 4. */
+henn_status henn_default_server_params(henn_server_params *p);
+henn_status henn_server_create(const henn_index *idx, const henn_server_params *p,
+                               henn_server **out);
+/* q_host: host FP32 [d], copied.  1 <= k <= k_max, max(ef, k) <= ef_max. */
+henn_status henn_server_submit(henn_server *s, const float *q_host, int32_t k, int32_t ef,
+                               int64_t tag);
+/* Admits what fits, advances every active request one step, retires the
+ * finished ones to the completion queue.  Blocking (one short launch).
+ * *n_active (may be NULL): requests in flight during this tick. */
+henn_status henn_server_tick(henn_server *s, int32_t *n_active);
+/* Drains up to max_results completions: tags[n], ids[n][k_max],
+ * dist[n][k_max] (host; any may be NULL), *n_out. */
+henn_status henn_server_poll(henn_server *s, int32_t max_results, int64_t *tags, int32_t *ids,
+                             float *dist, int32_t *n_out);
+henn_status henn_server_stats(const henn_server *s, henn_server_stats_t *out);
+void henn_server_destroy(henn_server *s);
+
 /* Releases the index.  No enqueued work may still use it.  NULL is a no-op. */
 void henn_free(henn_index *idx);
 

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhenn.so")
-SOURCES = ["henn_api.hip", "henn_search.hip", "henn_build.hip", "henn_knn.hip"]
+SOURCES = ["henn_api.hip", "henn_search.hip", "henn_build.hip", "henn_knn.hip", "henn_serve.hip"]
 ARCH = os.environ.get("HENN_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}", "-Xclang", "-target-feature",
          "-Xclang", "-packed-fp32-ops", "-Wno-unused-command-line-argument",

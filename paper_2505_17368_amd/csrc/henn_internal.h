@@ -108,6 +108,36 @@ struct SearchArgs {
   int32_t root_splits;
 };
 
+// Traversal state of one query between expansions (wave-uniform).  The
+// serving form keeps it in HBM between ticks, with the list W and the
+// visited table.  li: current layer, or kSlotNew / kSlotDone.
+constexpr int32_t kSlotNew = -1;
+constexpr int32_t kSlotDone = -2;
+struct QState {
+  int32_t li;
+  int32_t need_init;
+  int32_t wsize;
+  int32_t cur;
+  float cur_d;
+  int32_t exps, evals, exps0, evals0;
+  int32_t k, ef0;
+  int32_t pad;
+};
+
+struct ServeArgs {
+  const int32_t* active;      // [n_active] slots to advance this tick
+  int32_t n_active;
+  int32_t budget;             // expansions per slot per tick
+  QState* states;             // [max_slots]
+  const int64_t* state_off;   // [max_slots] byte offset of the slot's W + visited table
+  const int32_t* cap;         // [max_slots] list capacity of the slot (power of two)
+  char* arena;
+  int32_t* done_count;        // completions of this tick
+  int32_t* done_slots;        // [max_slots] slot of completion i
+  int32_t* out_ids;           // [max_slots][k_max] result row of completion i
+  float* out_dist;
+};
+
 struct LaunchShape {
   int lanes_per_vec;    // LPN
   int chunks_per_lane;  // CPL
@@ -123,6 +153,12 @@ size_t search_lds_per_wave(int ef_cap, int vis_bits);
 // Enqueues the search kernel.  Returns false when no kernel instance
 // matches (storage, lanes_per_vec, chunks_per_lane).
 bool launch_search(int storage, const SearchArgs& a, const LaunchShape& s, hipStream_t st);
+
+bool launch_serve_step(int storage, const SearchArgs& a, const ServeArgs& sv,
+                       const LaunchShape& sh, hipStream_t st);
+void launch_serve_admit(const float* staged_q, const int32_t* meta, int n_new, int d,
+                        float* slot_q, int32_t* slot_k, int32_t* slot_ef, int64_t* state_off,
+                        int32_t* cap, QState* states, hipStream_t st);
 
 // Exhaustive scan of a complete-graph root (dpad <= 128): writes
 // [splits][nq] best keys.  root_scan_splits() picks the split of the root.

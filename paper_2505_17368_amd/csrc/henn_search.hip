@@ -203,35 +203,35 @@ bool launch_root_scan(int storage, const SearchArgs& a, int splits, int64_t rows
   }
 }
 
+// Loads this query's k and beam width and finds the entry of the first
+// searched layer: the root's smallest id, or the exact root nearest when the
+// root carries the complete graph (from k_root_scan's keys when given).
 template <int KIND, int LPN, int CPL>
-__device__ void search_one(const SearchArgs& a, int64_t qi, WaveLds s) {
+__device__ void start_query(const SearchArgs& a, int64_t qi, const float (&q)[CPL][8],
+                            QState& st) {
   constexpr int G = 64 / LPN;
   const int lane = lane_id(), t = lane % LPN, g = lane / LPN;
-  const int vis_n = 1 << a.vis_bits;
-
-  float q[CPL][8];
-  load_query<CPL>(a.Q + qi * a.d, a.d, t, q);
   int k = a.k_arr ? a.k_arr[qi] : a.k_all;
   const int ef = a.ef_arr ? a.ef_arr[qi] : a.ef_all;
   k = min(max(k, 1), a.k_max);
-  const int ef0 = min(max(ef, k), a.ef_cap);
-
+  st.k = k;
+  st.ef0 = min(max(ef, k), a.ef_cap);
+  st.exps = st.evals = st.exps0 = st.evals0 = 0;
+  st.need_init = 1;
+  st.wsize = 0;
   int top = a.num_layers - 1;
-  float cur_d;
-  int32_t cur = 0;
-  int exps = 0, evals = 0, exps0 = 0, evals0 = 0;
   if (a.root_complete && top >= 1 && a.root_best) {
     // complete graph on the root, scanned by k_root_scan: min over the splits
     const SearchLayer& R = a.layer[top];
     uint64_t best = ~0ull;
     for (int sp = 0; sp < a.root_splits; ++sp) {
-      const uint64_t k = a.root_best[(int64_t)sp * a.nq + qi];
-      best = k < best ? k : best;
+      const uint64_t kk = a.root_best[(int64_t)sp * a.nq + qi];
+      best = kk < best ? kk : best;
     }
-    evals = R.size;
-    cur = R.down[wkey_id(best)];
-    cur_d = wkey_dist(best);
-    top -= 1;
+    st.evals = R.size;
+    st.cur = R.down[wkey_id(best)];
+    st.cur_d = wkey_dist(best);
+    st.li = top - 1;
   } else if (a.root_complete && top >= 1) {
     // complete graph on the root: exhaustive scan for its nearest member,
     // two rows per group in flight
@@ -260,39 +260,53 @@ __device__ void search_one(const SearchArgs& a, int64_t qi, WaveLds s) {
       const uint64_t o = shfl_xor_u64(best, m);
       best = o < best ? o : best;
     }
-    evals = R.size;
-    cur = R.down[wkey_id(best)];
-    cur_d = wkey_dist(best);
-    top -= 1;
+    st.evals = R.size;
+    st.cur = R.down[wkey_id(best)];
+    st.cur_d = wkey_dist(best);
+    st.li = top - 1;
   } else {
     // entry: the smallest id of the root layer (position 0)
     const SearchLayer& R = a.layer[top];
     const float sc = (KIND == kFP8) ? R.scale[0] : 1.0f;
-    cur_d = group_distance<KIND, LPN, CPL>(q, R.vec, sc, t, a.nchunks, a.metric, g == 0);
-    cur_d = __shfl(cur_d, 0);
+    float dd = group_distance<KIND, LPN, CPL>(q, R.vec, sc, t, a.nchunks, a.metric, g == 0);
+    st.cur_d = __shfl(dd, 0);
+    st.cur = 0;
+    st.li = top;
   }
-  uint64_t* W = s.W;
-  uint64_t* Wn = s.Wn;
-  int wsize = 1;
+}
 
-  for (int li = top; li >= 0; --li) {
-    const SearchLayer L = a.layer[li];
-    const int efl = li == 0 ? ef0 : min(a.ef_upper, a.ef_cap);
-    if (li == 0) {
-      exps0 = exps;
-      evals0 = evals;
+// Runs up to `budget` expansions from the current state (layer changes are
+// free).  Returns true once the layer-0 beam has no unexpanded entry; then
+// W holds the final list (st.wsize entries).  W / Wn are this wave's two LDS
+// list buffers and are swapped as the list is rewritten.
+template <int KIND, int LPN, int CPL>
+__device__ bool advance(const SearchArgs& a, const float (&q)[CPL][8], WaveLds s, uint64_t*& W,
+                        uint64_t*& Wn, QState& st, int budget) {
+  constexpr int G = 64 / LPN;
+  const int lane = lane_id(), t = lane % LPN, g = lane / LPN;
+  const int vis_n = 1 << a.vis_bits;
+  for (;;) {
+    const SearchLayer L = a.layer[st.li];
+    const int efl = st.li == 0 ? st.ef0 : min(a.ef_upper, a.ef_cap);
+    if (st.need_init) {
+      if (st.li == 0) {
+        st.exps0 = st.exps;
+        st.evals0 = st.evals;
+      }
+      st.evals += 1;  // the entry (its distance is carried down, counted per layer)
+      for (int i = lane; i < vis_n; i += 64) s.vis[i] = -1;
+      wave_sync();
+      if (lane == 0) {
+        W[0] = wkey(st.cur_d, st.cur);
+        s.vis[vis_hash(st.cur, a.vis_bits)] = st.cur;
+      }
+      st.wsize = 1;
+      st.need_init = 0;
+      wave_sync();
     }
-    evals += 1;  // the entry (its distance is carried down, counted per layer)
-    for (int i = lane; i < vis_n; i += 64) s.vis[i] = -1;
-    wave_sync();
-    if (lane == 0) {
-      W[0] = wkey(cur_d, cur);
-      s.vis[vis_hash(cur, a.vis_bits)] = cur;
-    }
-    wsize = 1;
-    wave_sync();
-
-    for (;;) {
+    int wsize = st.wsize;
+    bool layer_done = false;
+    while (budget > 0) {
       // smallest unexpanded entry of W
       int pos = -1;
       for (int base = 0; base < wsize; base += 64) {
@@ -304,12 +318,16 @@ __device__ void search_one(const SearchArgs& a, int64_t qi, WaveLds s) {
           break;
         }
       }
-      if (pos < 0) break;
+      if (pos < 0) {
+        layer_done = true;
+        break;
+      }
+      --budget;
       const uint64_t ck = W[pos];
       wave_sync();
       if (lane == 0) W[pos] = ck | 1ull;
       const int32_t c = wkey_id(ck);
-      ++exps;
+      ++st.exps;
 
       // neighbour ids and the visited filter
       int32_t u = -1;
@@ -326,7 +344,7 @@ __device__ void search_one(const SearchArgs& a, int64_t qi, WaveLds s) {
       const int cnt = popc64(fm);
       if (fresh) s.cid[rank_below(fm)] = u;
       wave_sync();
-      evals += cnt;
+      st.evals += cnt;
 
       // gather + distance, G rows per pass
       for (int base = 0; base < cnt; base += G) {
@@ -387,16 +405,28 @@ __device__ void search_one(const SearchArgs& a, int64_t qi, WaveLds s) {
       Wn = tmp;
       wsize = nsize;
     }
-
-    if (li > 0) {
-      const uint64_t best = W[0];
-      cur = L.down[wkey_id(best)];
-      cur_d = wkey_dist(best);
-    }
+    st.wsize = wsize;
+    if (!layer_done) return false;
+    if (st.li == 0) return true;
+    // hand the best node down the inter-layer edge
+    const uint64_t best = W[0];
+    st.cur = L.down[wkey_id(best)];
+    st.cur_d = wkey_dist(best);
+    st.li -= 1;
+    st.need_init = 1;
     wave_sync();
   }
+}
 
-  int64_t orow = qi * a.k_max;
+// Writes the first k results (after the FP32 re-rank for the precision
+// forms) to out_ids / out_dist (k_max entries, padded) and the counters.
+template <int KIND, int LPN, int CPL>
+__device__ void finish_query(const SearchArgs& a, const float (&q)[CPL][8], uint64_t* W,
+                             uint64_t* Wn, const QState& st, int32_t* out_ids, float* out_dist,
+                             int32_t* counters) {
+  constexpr int G = 64 / LPN;
+  const int lane = lane_id(), t = lane % LPN, g = lane / LPN;
+  const int k = st.k, wsize = st.wsize;
   if (a.rerank_vec == nullptr) {
     for (int j = lane; j < a.k_max; j += 64) {
       int32_t id = -1;
@@ -405,8 +435,8 @@ __device__ void search_one(const SearchArgs& a, int64_t qi, WaveLds s) {
         id = wkey_id(W[j]);
         dd = wkey_dist(W[j]);
       }
-      a.out_ids[orow + j] = id;
-      a.out_dist[orow + j] = dd;
+      out_ids[j] = id;
+      out_dist[j] = dd;
     }
   } else {
     // FP32 re-rank of the first min(|W|, rerank_factor*k) entries
@@ -430,18 +460,113 @@ __device__ void search_one(const SearchArgs& a, int64_t qi, WaveLds s) {
         id = wkey_id(Wn[j]);
         dd = wkey_dist(Wn[j]);
       }
-      a.out_ids[orow + j] = id;
-      a.out_dist[orow + j] = dd;
+      out_ids[j] = id;
+      out_dist[j] = dd;
     }
   }
-  if (a.counters && lane == 0) {
-    int32_t* cc = a.counters + qi * 4;
-    cc[0] = exps;
-    cc[1] = evals;
-    cc[2] = exps - exps0;
-    cc[3] = evals - evals0;
+  if (counters && lane == 0) {
+    counters[0] = st.exps;
+    counters[1] = st.evals;
+    counters[2] = st.exps - st.exps0;
+    counters[3] = st.evals - st.evals0;
   }
   wave_sync();
+}
+
+template <int KIND, int LPN, int CPL>
+__device__ void search_one(const SearchArgs& a, int64_t qi, WaveLds s) {
+  const int t = lane_id() % LPN;
+  float q[CPL][8];
+  load_query<CPL>(a.Q + qi * a.d, a.d, t, q);
+  QState st;
+  start_query<KIND, LPN, CPL>(a, qi, q, st);
+  uint64_t* W = s.W;
+  uint64_t* Wn = s.Wn;
+  advance<KIND, LPN, CPL>(a, q, s, W, Wn, st, 0x7fffffff);
+  finish_query<KIND, LPN, CPL>(a, q, W, Wn, st, a.out_ids + qi * a.k_max,
+                               a.out_dist + qi * a.k_max,
+                               a.counters ? a.counters + qi * 4 : nullptr);
+}
+
+// ---------------------------------------------------------- serving ------
+// One tick of the serving form: every active slot advances by at most
+// `budget` expansions.  A slot's state (QState, its list W and visited
+// table) lives in HBM between ticks at arena + state_off[slot]; it is
+// loaded into this wave's LDS, advanced, and stored back.  A slot that
+// finishes appends its slot and result row to the tick's compact completion
+// list.  The traversal is the batch kernel's own code, so
+// a request's result does not depend on which others share its ticks.
+template <int KIND, int LPN, int CPL>
+__global__ __launch_bounds__(512) void k_serve_step(SearchArgs a, ServeArgs sv, int per_wave_bytes,
+                                                    int waves_per_block) {
+  extern __shared__ __align__(16) char smem[];
+  const int wave = threadIdx.x >> 6;
+  const int64_t idx = (int64_t)blockIdx.x * waves_per_block + wave;
+  if (idx >= sv.n_active) return;
+  const int lane = lane_id(), t = lane % LPN;
+  const int32_t slot = sv.active[idx];
+  WaveLds s = carve(smem + (size_t)wave * per_wave_bytes, a.ef_cap, a.vis_bits);
+  float q[CPL][8];
+  load_query<CPL>(a.Q + (int64_t)slot * a.d, a.d, t, q);
+  QState st = sv.states[slot];
+  char* base = sv.arena + sv.state_off[slot];
+  uint64_t* gW = reinterpret_cast<uint64_t*>(base);
+  int32_t* gvis = reinterpret_cast<int32_t*>(base + (size_t)sv.cap[slot] * 8);
+  const int vis_n = 1 << a.vis_bits;
+  if (st.li == kSlotNew) {
+    start_query<KIND, LPN, CPL>(a, slot, q, st);
+  } else if (!st.need_init) {
+    for (int i = lane; i < st.wsize; i += 64) s.W[i] = gW[i];
+    for (int i = lane; i < vis_n; i += 64) s.vis[i] = gvis[i];
+    wave_sync();
+  }
+  uint64_t* W = s.W;
+  uint64_t* Wn = s.Wn;
+  const bool done = advance<KIND, LPN, CPL>(a, q, s, W, Wn, st, sv.budget);
+  if (done) {
+    // finished: append (slot, row) to this tick's compact completion list
+    int pos = 0;
+    if (lane == 0) pos = atomicAdd(sv.done_count, 1);
+    pos = __shfl(pos, 0);
+    finish_query<KIND, LPN, CPL>(a, q, W, Wn, st, sv.out_ids + (int64_t)pos * a.k_max,
+                                 sv.out_dist + (int64_t)pos * a.k_max, nullptr);
+    st.li = kSlotDone;
+    if (lane == 0) sv.done_slots[pos] = slot;
+  } else if (!st.need_init) {
+    for (int i = lane; i < st.wsize; i += 64) gW[i] = W[i];
+    for (int i = lane; i < vis_n; i += 64) gvis[i] = s.vis[i];
+  }
+  if (lane == 0) sv.states[slot] = st;
+}
+
+__global__ void k_serve_admit(const float* staged_q, const int32_t* meta, int n_new, int d,
+                              float* slot_q, int32_t* slot_k, int32_t* slot_ef,
+                              int64_t* state_off, int32_t* cap, QState* states) {
+  // meta per new request: slot, k, ef, cap, offset (lo, hi)
+  const int r = blockIdx.x;
+  if (r >= n_new) return;
+  const int32_t* m = meta + r * 6;
+  const int32_t slot = m[0];
+  for (int j = threadIdx.x; j < d; j += blockDim.x)
+    slot_q[(int64_t)slot * d + j] = staged_q[(int64_t)r * d + j];
+  if (threadIdx.x == 0) {
+    slot_k[slot] = m[1];
+    slot_ef[slot] = m[2];
+    cap[slot] = m[3];
+    state_off[slot] = (int64_t)(((uint64_t)(uint32_t)m[5] << 32) | (uint32_t)m[4]);
+    QState st;
+    memset(&st, 0, sizeof(st));
+    st.li = kSlotNew;
+    states[slot] = st;
+  }
+}
+
+template <int KIND, int LPN, int CPL>
+static void launch_serve_one(const SearchArgs& a, const ServeArgs& sv, int wpb, hipStream_t st) {
+  const size_t per_wave = search_lds_per_wave(a.ef_cap, a.vis_bits);
+  const unsigned blocks = (unsigned)((sv.n_active + wpb - 1) / wpb);
+  hipLaunchKernelGGL((k_serve_step<KIND, LPN, CPL>), dim3(blocks), dim3(64 * wpb),
+                     per_wave * wpb, st, a, sv, (int)per_wave, wpb);
 }
 
 template <int KIND, int LPN, int CPL>
@@ -514,6 +639,38 @@ bool launch_search(int storage, const SearchArgs& a, const LaunchShape& s, hipSt
     case kFP8: return dispatch<kFP8>(a, s, st);
     default: return false;
   }
+}
+
+template <int KIND>
+static bool dispatch_serve(const SearchArgs& a, const ServeArgs& sv, const LaunchShape& sh,
+                           hipStream_t st) {
+#define HENN_TRY(LPN, CPL)                                        \
+  if (sh.lanes_per_vec == LPN && sh.chunks_per_lane == CPL) {     \
+    launch_serve_one<KIND, LPN, CPL>(a, sv, sh.waves_per_block, st); \
+    return true;                                                  \
+  }
+  HENN_SEARCH_COMBOS(HENN_TRY)
+#undef HENN_TRY
+  return false;
+}
+
+bool launch_serve_step(int storage, const SearchArgs& a, const ServeArgs& sv,
+                       const LaunchShape& sh, hipStream_t st) {
+  if (sv.n_active <= 0) return true;
+  switch (storage) {
+    case kF32: return dispatch_serve<kF32>(a, sv, sh, st);
+    case kBF16: return dispatch_serve<kBF16>(a, sv, sh, st);
+    case kFP8: return dispatch_serve<kFP8>(a, sv, sh, st);
+    default: return false;
+  }
+}
+
+void launch_serve_admit(const float* staged_q, const int32_t* meta, int n_new, int d,
+                        float* slot_q, int32_t* slot_k, int32_t* slot_ef, int64_t* state_off,
+                        int32_t* cap, QState* states, hipStream_t st) {
+  if (n_new <= 0) return;
+  hipLaunchKernelGGL(k_serve_admit, dim3(n_new), dim3(64), 0, st, staged_q, meta, n_new, d,
+                     slot_q, slot_k, slot_ef, state_off, cap, states);
 }
 
 void pick_lanes(int nchunks, int requested_lpn, int* lpn, int* cpl) {

@@ -1,0 +1,442 @@
+// henn_serve.hip -- the serving form: a continuous-batching request loop.
+//
+// Requests (query vector, k, beam width, tag) are submitted on the host and
+// wait in a FIFO until admission.  A request is admitted at the next tick
+// when a slot is free and the device arena has room for its traversal
+// state (its list of next_pow2(max(ef, k)) keys plus the visited table):
+// admission is by memory.  Every tick advances every active request by at
+// most steps_per_tick expansions in one launch (k_serve_step), so requests
+// that arrive while others are in flight join the running batch and their
+// work overlaps on the device; finished requests are retired to a host
+// completion queue with their results.  Index and per-request state stay
+// in HBM; only the admitted query vectors and the finished rows cross PCIe.
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <deque>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "henn_device.h"
+#include "henn_internal.h"
+
+namespace henn {
+
+// first-fit allocator over [0, size) of the device arena (host bookkeeping)
+class ArenaAlloc {
+ public:
+  explicit ArenaAlloc(int64_t size) { free_[0] = size; }
+  bool alloc(int64_t len, int64_t* off) {
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= len) {
+        *off = it->first;
+        const int64_t rest = it->second - len, start = it->first + len;
+        free_.erase(it);
+        if (rest > 0) free_[start] = rest;
+        used_ += len;
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(int64_t off, int64_t len) {
+    used_ -= len;
+    auto it = free_.emplace(off, len).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  int64_t used() const { return used_; }
+
+ private:
+  std::map<int64_t, int64_t> free_;
+  int64_t used_ = 0;
+};
+
+struct Pending {
+  std::vector<float> q;
+  int32_t k, ef;
+  int64_t tag;
+};
+
+struct Done {
+  int64_t tag;
+  std::vector<int32_t> ids;
+  std::vector<float> dist;
+};
+
+}  // namespace henn
+
+using namespace henn;
+
+struct henn_server {
+  const henn_index* idx = nullptr;
+  henn_server_params p{};
+  hipStream_t st = nullptr;
+  int d = 0, k_max = 0, ef_cap = 0, vis_bits = 0;
+  LaunchShape shape{};
+  // device
+  float* slot_q = nullptr;
+  int32_t *slot_k = nullptr, *slot_ef = nullptr, *slot_ids = nullptr, *cap = nullptr;
+  float* slot_dist = nullptr;
+  QState* states = nullptr;
+  int64_t* state_off = nullptr;
+  char* arena = nullptr;
+  int32_t *active_d = nullptr, *done_d = nullptr;  // done_d[0] count, then slots
+  float* stage_q_d = nullptr;
+  int32_t* stage_meta_d = nullptr;
+  int32_t* out_ids_d = nullptr;
+  float* out_dist_d = nullptr;
+  // pinned host
+  float* stage_q_h = nullptr;
+  int32_t* stage_meta_h = nullptr;
+  int32_t* active_h = nullptr;
+  int32_t* done_h = nullptr;
+  int32_t* out_ids_h = nullptr;
+  float* out_dist_h = nullptr;
+  // host state
+  ArenaAlloc* alloc = nullptr;
+  std::deque<Pending> pending;
+  std::vector<int32_t> free_slots;
+  std::vector<int32_t> active;
+  std::vector<int64_t> slot_tag, slot_off, slot_bytes;
+  std::vector<int32_t> slot_kk;
+  std::deque<Done> done;
+  int64_t ticks = 0, admitted = 0, completed = 0, max_active = 0;
+};
+
+namespace henn {
+void set_error(const std::string& msg);
+}
+
+static henn_status srv_fail(henn_status s, const std::string& m) {
+  henn::set_error(m);
+  return s;
+}
+
+static void srv_release(henn_server* s) {
+  (void)hipFree(s->slot_q);
+  (void)hipFree(s->slot_k);
+  (void)hipFree(s->slot_ef);
+  (void)hipFree(s->slot_ids);
+  (void)hipFree(s->slot_dist);
+  (void)hipFree(s->cap);
+  (void)hipFree(s->states);
+  (void)hipFree(s->state_off);
+  (void)hipFree(s->arena);
+  (void)hipFree(s->active_d);
+  (void)hipFree(s->done_d);
+  (void)hipFree(s->stage_q_d);
+  (void)hipFree(s->stage_meta_d);
+  (void)hipFree(s->out_ids_d);
+  (void)hipFree(s->out_dist_d);
+  (void)hipHostFree(s->stage_q_h);
+  (void)hipHostFree(s->stage_meta_h);
+  (void)hipHostFree(s->active_h);
+  (void)hipHostFree(s->done_h);
+  (void)hipHostFree(s->out_ids_h);
+  (void)hipHostFree(s->out_dist_h);
+  if (s->st) (void)hipStreamDestroy(s->st);
+  delete s->alloc;
+  delete s;
+}
+
+template <typename T>
+static void dmalloc(T** p, int64_t n) {
+  HENN_HIP(hipMalloc(reinterpret_cast<void**>(p), sizeof(T) * (size_t)std::max<int64_t>(n, 1)));
+}
+template <typename T>
+static void hmalloc(T** p, int64_t n) {
+  HENN_HIP(hipHostMalloc(reinterpret_cast<void**>(p), sizeof(T) * (size_t)std::max<int64_t>(n, 1),
+                         hipHostMallocDefault));
+}
+
+static int64_t state_bytes(const henn_server* s, int32_t k, int32_t ef) {
+  const int cap = next_pow2(std::max(std::max(ef, k), 1));
+  const int64_t b = (int64_t)cap * 8 + ((int64_t)1 << s->vis_bits) * 4;
+  return (b + 255) / 256 * 256;
+}
+
+extern "C" {
+
+henn_status henn_default_server_params(henn_server_params* p) {
+  if (!p) return srv_fail(HENN_E_INVAL, "null params");
+  memset(p, 0, sizeof(*p));
+  p->struct_size = sizeof(henn_server_params);
+  p->max_slots = 4096;
+  p->pool_bytes = 64ll << 20;
+  p->steps_per_tick = 16;
+  p->k_max = 10;
+  p->ef_max = 128;
+  p->ef_upper = 1;
+  p->rerank_factor = 4;
+  return HENN_OK;
+}
+
+henn_status henn_server_create(const henn_index* idx, const henn_server_params* p,
+                               henn_server** out) {
+  if (!idx || !p || !out) return srv_fail(HENN_E_INVAL, "null argument");
+  if (p->struct_size != sizeof(henn_server_params))
+    return srv_fail(HENN_E_INVAL, "server params struct_size mismatch");
+  if (p->max_slots < 1 || p->max_slots > (1 << 20)) return srv_fail(HENN_E_INVAL, "max_slots");
+  if (p->steps_per_tick < 1) return srv_fail(HENN_E_INVAL, "steps_per_tick >= 1");
+  if (p->k_max < 1 || p->k_max > 1024) return srv_fail(HENN_E_INVAL, "k_max in [1, 1024]");
+  if (p->ef_max < 1 || p->ef_upper < 1) return srv_fail(HENN_E_INVAL, "ef_max, ef_upper >= 1");
+  henn_server* s = new henn_server();
+  try {
+    s->idx = idx;
+    s->p = *p;
+    s->d = idx->d;
+    s->k_max = p->k_max;
+    s->ef_cap = next_pow2(std::max(std::max(p->ef_max, p->k_max), p->ef_upper));
+    if (s->ef_cap > 2048) throw HipError{hipErrorInvalidValue, "beam width above 2048"};
+    s->vis_bits = p->vis_bits ? p->vis_bits : 10;
+    if (s->vis_bits < 8 || s->vis_bits > 13) throw HipError{hipErrorInvalidValue, "vis_bits"};
+    int lpn = 0, cpl = 0;
+    pick_lanes(idx->nchunks, p->lanes_per_vec, &lpn, &cpl);
+    if (!lpn) throw HipError{hipErrorInvalidValue, "lanes_per_vec"};
+    s->shape.lanes_per_vec = lpn;
+    s->shape.chunks_per_lane = cpl;
+    s->shape.vis_bits = s->vis_bits;
+    int wpb = p->waves_per_block ? p->waves_per_block : 4;
+    while (wpb > 1 && search_lds_per_wave(s->ef_cap, s->vis_bits) * wpb > 65536) wpb /= 2;
+    s->shape.waves_per_block = wpb;
+    const int64_t M = p->max_slots;
+    if (p->pool_bytes < state_bytes(s, p->k_max, p->ef_max))
+      throw HipError{hipErrorInvalidValue, "pool_bytes below one request's state"};
+    HENN_HIP(hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking));
+    dmalloc(&s->slot_q, M * s->d);
+    dmalloc(&s->slot_k, M);
+    dmalloc(&s->slot_ef, M);
+    dmalloc(&s->cap, M);
+    dmalloc(&s->states, M);
+    dmalloc(&s->state_off, M);
+    dmalloc(&s->arena, p->pool_bytes);
+    dmalloc(&s->active_d, M);
+    dmalloc(&s->done_d, M + 1);
+    dmalloc(&s->stage_q_d, M * s->d);
+    dmalloc(&s->stage_meta_d, M * 6);
+    dmalloc(&s->out_ids_d, M * s->k_max);
+    dmalloc(&s->out_dist_d, M * s->k_max);
+    hmalloc(&s->stage_q_h, M * s->d);
+    hmalloc(&s->stage_meta_h, M * 6);
+    hmalloc(&s->active_h, M);
+    hmalloc(&s->done_h, M + 1);
+    hmalloc(&s->out_ids_h, M * s->k_max);
+    hmalloc(&s->out_dist_h, M * s->k_max);
+    s->alloc = new ArenaAlloc(p->pool_bytes);
+    s->slot_tag.assign(M, 0);
+    s->slot_off.assign(M, 0);
+    s->slot_bytes.assign(M, 0);
+    s->slot_kk.assign(M, 0);
+    for (int64_t i = M - 1; i >= 0; --i) s->free_slots.push_back((int32_t)i);
+    *out = s;
+    return HENN_OK;
+  } catch (const HipError& e) {
+    srv_release(s);
+    henn::set_error(std::string("server create: ") + e.what + " (" + hipGetErrorString(e.e) + ")");
+    return e.e == hipErrorOutOfMemory ? HENN_E_NOMEM : HENN_E_INVAL;
+  } catch (const std::bad_alloc&) {
+    srv_release(s);
+    return srv_fail(HENN_E_NOMEM, "host allocation failed");
+  }
+}
+
+henn_status henn_server_submit(henn_server* s, const float* q_host, int32_t k, int32_t ef,
+                               int64_t tag) {
+  if (!s || !q_host) return srv_fail(HENN_E_INVAL, "null argument");
+  if (k < 1 || k > s->k_max) return srv_fail(HENN_E_INVAL, "k outside [1, k_max]");
+  if (ef < 1 || std::max(ef, k) > s->ef_cap) return srv_fail(HENN_E_INVAL, "ef outside [1, ef_max]");
+  Pending r;
+  r.q.assign(q_host, q_host + s->d);
+  r.k = k;
+  r.ef = ef;
+  r.tag = tag;
+  s->pending.push_back(std::move(r));
+  return HENN_OK;
+}
+
+henn_status henn_server_tick(henn_server* s, int32_t* n_active_out) {
+  if (!s) return srv_fail(HENN_E_INVAL, "null server");
+  try {
+    // 1) admission: FIFO, while a slot and arena bytes are free
+    int n_new = 0;
+    while (!s->pending.empty() && !s->free_slots.empty()) {
+      const Pending& r = s->pending.front();
+      const int64_t need = state_bytes(s, r.k, r.ef);
+      int64_t off = 0;
+      if (!s->alloc->alloc(need, &off)) break;
+      const int32_t slot = s->free_slots.back();
+      s->free_slots.pop_back();
+      memcpy(s->stage_q_h + (int64_t)n_new * s->d, r.q.data(), sizeof(float) * s->d);
+      int32_t* m = s->stage_meta_h + n_new * 6;
+      m[0] = slot;
+      m[1] = r.k;
+      m[2] = r.ef;
+      m[3] = next_pow2(std::max(std::max(r.ef, r.k), 1));
+      m[4] = (int32_t)(uint32_t)((uint64_t)off & 0xffffffffu);
+      m[5] = (int32_t)(uint32_t)((uint64_t)off >> 32);
+      s->slot_tag[slot] = r.tag;
+      s->slot_off[slot] = off;
+      s->slot_bytes[slot] = need;
+      s->slot_kk[slot] = r.k;
+      s->active.push_back(slot);
+      s->pending.pop_front();
+      ++n_new;
+      ++s->admitted;
+    }
+    if (n_new > 0) {
+      HENN_HIP(hipMemcpyAsync(s->stage_q_d, s->stage_q_h, sizeof(float) * n_new * s->d,
+                              hipMemcpyHostToDevice, s->st));
+      HENN_HIP(hipMemcpyAsync(s->stage_meta_d, s->stage_meta_h, sizeof(int32_t) * n_new * 6,
+                              hipMemcpyHostToDevice, s->st));
+      launch_serve_admit(s->stage_q_d, s->stage_meta_d, n_new, s->d, s->slot_q, s->slot_k,
+                         s->slot_ef, s->state_off, s->cap, s->states, s->st);
+    }
+    const int n_active = (int)s->active.size();
+    s->max_active = std::max<int64_t>(s->max_active, n_active);
+    if (n_active_out) *n_active_out = n_active;
+    if (n_active == 0) return HENN_OK;
+    // 2) one step of every active request
+    memcpy(s->active_h, s->active.data(), sizeof(int32_t) * n_active);
+    HENN_HIP(hipMemcpyAsync(s->active_d, s->active_h, sizeof(int32_t) * n_active,
+                            hipMemcpyHostToDevice, s->st));
+    HENN_HIP(hipMemsetAsync(s->done_d, 0, sizeof(int32_t), s->st));
+    const henn_index* idx = s->idx;
+    SearchArgs a;
+    memset(&a, 0, sizeof(a));
+    const int eb = idx->storage == HENN_F32 ? 4 : idx->storage == HENN_BF16 ? 2 : 1;
+    for (int i = 0; i < idx->num_layers; ++i) {
+      const LayerDev& L = idx->L[i];
+      SearchLayer& sl = a.layer[i];
+      sl.vec = idx->storage == HENN_F32 ? (const void*)L.vec32 : (const void*)L.vecq;
+      sl.scale = L.scale;
+      sl.adj = L.adj;
+      sl.down = L.down;
+      sl.size = (int32_t)L.size;
+      sl.deg = L.deg;
+      sl.row_bytes = (int64_t)idx->dpad * eb;
+    }
+    a.rerank_vec = idx->storage == HENN_F32 ? nullptr : idx->L[0].vec32;
+    a.Q = s->slot_q;
+    a.nq = s->p.max_slots;
+    a.k_arr = s->slot_k;
+    a.ef_arr = s->slot_ef;
+    a.k_all = 1;
+    a.ef_all = 1;
+    a.k_max = s->k_max;
+    a.ef_upper = s->p.ef_upper;
+    a.ef_cap = s->ef_cap;
+    a.rerank_factor = std::max(1, s->p.rerank_factor);
+    a.num_layers = idx->num_layers;
+    a.d = idx->d;
+    a.dpad = idx->dpad;
+    a.nchunks = idx->nchunks;
+    a.metric = idx->metric;
+    a.vis_bits = s->vis_bits;
+    a.root_complete = idx->root_complete ? 1 : 0;
+    ServeArgs sv;
+    sv.active = s->active_d;
+    sv.n_active = n_active;
+    sv.budget = s->p.steps_per_tick;
+    sv.states = s->states;
+    sv.state_off = s->state_off;
+    sv.cap = s->cap;
+    sv.arena = s->arena;
+    sv.done_count = s->done_d;
+    sv.done_slots = s->done_d + 1;
+    sv.out_ids = s->out_ids_d;
+    sv.out_dist = s->out_dist_d;
+    if (!launch_serve_step(idx->storage, a, sv, s->shape, s->st))
+      return srv_fail(HENN_E_UNSUPPORTED, "no serving kernel for this shape");
+    HENN_HIP(hipGetLastError());
+    // 3) completions: count, then the finished slots and their rows
+    HENN_HIP(hipMemcpyAsync(s->done_h, s->done_d, sizeof(int32_t), hipMemcpyDeviceToHost, s->st));
+    HENN_HIP(hipStreamSynchronize(s->st));
+    const int nd = s->done_h[0];
+    ++s->ticks;
+    if (nd > 0) {
+      HENN_HIP(hipMemcpyAsync(s->done_h + 1, s->done_d + 1, sizeof(int32_t) * nd,
+                              hipMemcpyDeviceToHost, s->st));
+      HENN_HIP(hipMemcpyAsync(s->out_ids_h, s->out_ids_d, sizeof(int32_t) * nd * s->k_max,
+                              hipMemcpyDeviceToHost, s->st));
+      HENN_HIP(hipMemcpyAsync(s->out_dist_h, s->out_dist_d, sizeof(float) * nd * s->k_max,
+                              hipMemcpyDeviceToHost, s->st));
+      HENN_HIP(hipStreamSynchronize(s->st));
+      std::vector<char> finished(s->p.max_slots, 0);
+      for (int i = 0; i < nd; ++i) {
+        const int32_t slot = s->done_h[1 + i];
+        Done r;
+        r.tag = s->slot_tag[slot];
+        r.ids.assign(s->out_ids_h + (int64_t)i * s->k_max, s->out_ids_h + (int64_t)(i + 1) * s->k_max);
+        r.dist.assign(s->out_dist_h + (int64_t)i * s->k_max,
+                      s->out_dist_h + (int64_t)(i + 1) * s->k_max);
+        s->done.push_back(std::move(r));
+        s->alloc->release(s->slot_off[slot], s->slot_bytes[slot]);
+        s->free_slots.push_back(slot);
+        finished[slot] = 1;
+        ++s->completed;
+      }
+      std::vector<int32_t> keep;
+      keep.reserve(s->active.size());
+      for (int32_t sl : s->active)
+        if (!finished[sl]) keep.push_back(sl);
+      s->active.swap(keep);
+    }
+    return HENN_OK;
+  } catch (const HipError& e) {
+    henn::set_error(std::string("server tick: HIP error ") + hipGetErrorString(e.e) + " in " + e.what);
+    return HENN_E_DEVICE;
+  } catch (const std::bad_alloc&) {
+    return srv_fail(HENN_E_NOMEM, "host allocation failed");
+  }
+}
+
+henn_status henn_server_poll(henn_server* s, int32_t max_results, int64_t* tags, int32_t* ids,
+                             float* dist, int32_t* n_out) {
+  if (!s || !n_out) return srv_fail(HENN_E_INVAL, "null argument");
+  int n = 0;
+  while (n < max_results && !s->done.empty()) {
+    const Done& r = s->done.front();
+    if (tags) tags[n] = r.tag;
+    if (ids) memcpy(ids + (int64_t)n * s->k_max, r.ids.data(), sizeof(int32_t) * s->k_max);
+    if (dist) memcpy(dist + (int64_t)n * s->k_max, r.dist.data(), sizeof(float) * s->k_max);
+    s->done.pop_front();
+    ++n;
+  }
+  *n_out = n;
+  return HENN_OK;
+}
+
+henn_status henn_server_stats(const henn_server* s, henn_server_stats_t* out) {
+  if (!s || !out) return srv_fail(HENN_E_INVAL, "null argument");
+  out->pending = (int64_t)s->pending.size();
+  out->active = (int64_t)s->active.size();
+  out->completed = s->completed;
+  out->admitted = s->admitted;
+  out->ticks = s->ticks;
+  out->pool_bytes_used = s->alloc->used();
+  out->max_active = s->max_active;
+  out->done_queued = (int64_t)s->done.size();
+  return HENN_OK;
+}
+
+void henn_server_destroy(henn_server* s) {
+  if (!s) return;
+  (void)hipStreamSynchronize(s->st);
+  srv_release(s);
+}
+
+}  // extern "C"

@@ -57,6 +57,21 @@ class LayerInfo(ctypes.Structure):
                 ("fallback_rows", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class ServerParams(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("max_slots", ctypes.c_int32),
+                ("pool_bytes", ctypes.c_int64), ("steps_per_tick", ctypes.c_int32),
+                ("k_max", ctypes.c_int32), ("ef_max", ctypes.c_int32),
+                ("ef_upper", ctypes.c_int32), ("rerank_factor", ctypes.c_int32),
+                ("lanes_per_vec", ctypes.c_int32), ("waves_per_block", ctypes.c_int32),
+                ("vis_bits", ctypes.c_int32)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ("pending", "active", "completed", "admitted",
+                                              "ticks", "pool_bytes_used", "max_active",
+                                              "done_queued")]
+
+
 STATUS_NAMES = {0: "base", 1: "vacuous", 2: "verified", 3: "not_verified"}
 
 _lib = None
@@ -100,13 +115,23 @@ def load_library(path: str = LIB_PATH):
     lib.henn_search_graph_launch.argtypes = [vp, vp]
     lib.henn_search_graph_free.argtypes = [vp]
     lib.henn_search_graph_free.restype = None
+    lib.henn_default_server_params.argtypes = [P(ServerParams)]
+    lib.henn_server_create.argtypes = [vp, P(ServerParams), P(vp)]
+    lib.henn_server_submit.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64]
+    lib.henn_server_tick.argtypes = [vp, P(ctypes.c_int32)]
+    lib.henn_server_poll.argtypes = [vp, ctypes.c_int32, vp, vp, vp, P(ctypes.c_int32)]
+    lib.henn_server_stats.argtypes = [vp, P(ServerStats)]
+    lib.henn_server_destroy.argtypes = [vp]
+    lib.henn_server_destroy.restype = None
     lib.henn_import.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, P(BuildParams), ctypes.c_int32,
                                 P(ctypes.c_int64), P(vp), P(vp), ctypes.c_int32, vp, P(vp)]
     for name in ("henn_default_build_params", "henn_default_search_params", "henn_build",
                  "henn_search_batch", "henn_index_shape", "henn_layer_info_get",
                  "henn_export_layer", "henn_import", "henn_autotune",
                  "henn_search_workspace_size", "henn_search_graph_create",
-                 "henn_search_graph_launch"):
+                 "henn_search_graph_launch", "henn_default_server_params", "henn_server_create",
+                 "henn_server_submit", "henn_server_tick", "henn_server_poll",
+                 "henn_server_stats"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -357,6 +382,62 @@ class SearchGraph:
     def __del__(self):
         try:
             self.free()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching request loop on one index (henn_server_*)."""
+
+    def __init__(self, index: HennIndex, **kw):
+        lib = load_library()
+        p = ServerParams()
+        _check(lib.henn_default_server_params(ctypes.byref(p)))
+        for k, v in kw.items():
+            if not hasattr(p, k):
+                raise KeyError(k)
+            setattr(p, k, v)
+        self.k_max = p.k_max
+        self.index = index
+        self._s = ctypes.c_void_p()
+        _check(lib.henn_server_create(index.handle, ctypes.byref(p), ctypes.byref(self._s)))
+
+    def submit(self, q, k: int, ef: int, tag: int):
+        q = np.ascontiguousarray(q, dtype=np.float32)
+        _check(load_library().henn_server_submit(self._s, q.ctypes.data_as(ctypes.c_void_p), k,
+                                                 ef, tag))
+
+    def tick(self) -> int:
+        n = ctypes.c_int32()
+        _check(load_library().henn_server_tick(self._s, ctypes.byref(n)))
+        return n.value
+
+    def poll(self, max_results: int = 1 << 16):
+        tags = np.zeros(max_results, dtype=np.int64)
+        ids = np.zeros((max_results, self.k_max), dtype=np.int32)
+        dist = np.zeros((max_results, self.k_max), dtype=np.float32)
+        n = ctypes.c_int32()
+        _check(load_library().henn_server_poll(self._s, max_results,
+                                               tags.ctypes.data_as(ctypes.c_void_p),
+                                               ids.ctypes.data_as(ctypes.c_void_p),
+                                               dist.ctypes.data_as(ctypes.c_void_p),
+                                               ctypes.byref(n)))
+        m = n.value
+        return tags[:m], ids[:m], dist[:m]
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(load_library().henn_server_stats(self._s, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in ServerStats._fields_}
+
+    def close(self):
+        if self._s:
+            load_library().henn_server_destroy(self._s)
+            self._s = None
+
+    def __del__(self):
+        try:
+            self.close()
         except Exception:
             pass
 

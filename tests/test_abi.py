@@ -79,3 +79,14 @@ def test_import_validation_on_host(lib):
     st = lib.henn_import(fake, 3, 4, ctypes.byref(p), 1, sizes, ids, adjp, 2, None,
                          ctypes.byref(h))
     assert st == hn.HENN_E_INVAL and "range" in hn.last_error()
+
+
+def test_server_params_and_validation(lib):
+    p = hn.ServerParams()
+    assert lib.henn_default_server_params(ctypes.byref(p)) == hn.HENN_OK
+    assert p.struct_size == ctypes.sizeof(hn.ServerParams) == 48
+    assert (p.max_slots, p.steps_per_tick, p.k_max, p.ef_max) == (4096, 16, 10, 128)
+    out = ctypes.c_void_p()
+    assert lib.henn_server_create(None, ctypes.byref(p), ctypes.byref(out)) == hn.HENN_E_INVAL
+    assert lib.henn_server_tick(None, None) == hn.HENN_E_INVAL
+    lib.henn_server_destroy(None)

@@ -1,0 +1,95 @@
+"""Serving form: continuous batching with memory-based admission.  Each
+request's result is the same alone, in a mix of concurrent requests with
+other k / beam widths, and in a plain batched search with the same shape."""
+import numpy as np
+import pytest
+
+import workloads as wl
+from gpu_util import to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def setup():
+    import paper_2505_17368_amd as hn
+    X, Q = wl.make("uniform_10k_d32")
+    idx = hn.henn_build(to_dev(X), degree=16, graph=1, max_degree=32, root_complete_max=1000,
+                        storage=1)
+    yield hn, X, Q, idx
+    idx.free()
+
+
+def _batch(hn, idx, Q, k, ef):
+    import torch
+    gi, gd = hn.henn_search_batch(idx, to_dev(Q), k=k, ef=ef, k_max=10, ef_max=64, vis_bits=10)
+    torch.cuda.synchronize()
+    return gi.cpu().numpy(), gd.cpu().numpy()
+
+
+def _drain(srv, expected):
+    got = {}
+    for _ in range(100000):
+        srv.tick()
+        tags, ids, dist = srv.poll()
+        for t, i, d in zip(tags, ids, dist):
+            got[int(t)] = (i.copy(), d.copy())
+        if len(got) == expected:
+            return got
+    raise AssertionError("server did not finish")
+
+
+def test_alone_equals_batch(setup):
+    hn, X, Q, idx = setup
+    ref_i, ref_d = _batch(hn, idx, Q[:8], 10, 64)
+    for j in range(8):
+        srv = hn.Server(idx, max_slots=4, k_max=10, ef_max=64, steps_per_tick=5, vis_bits=10)
+        srv.submit(Q[j], 10, 64, j)
+        got = _drain(srv, 1)
+        assert np.array_equal(got[j][0], ref_i[j])
+        assert np.array_equal(got[j][1].view(np.uint32), ref_d[j].view(np.uint32))
+        srv.close()
+
+
+def test_mix_with_staggered_arrivals_and_memory_admission(setup):
+    hn, X, Q, idx = setup
+    n = 300
+    rng = np.random.default_rng(7)
+    ks = rng.choice([1, 5, 10], size=n)
+    efs = rng.choice([16, 32, 64], size=n)
+    refs = {}
+    for kk in (1, 5, 10):
+        for ee in (16, 32, 64):
+            sel = np.where((ks == kk) & (efs == ee))[0]
+            if len(sel):
+                bi, bd = _batch(hn, idx, Q[sel], kk, ee)
+                for r, qi in enumerate(sel):
+                    refs[int(qi)] = (bi[r], bd[r])
+    # a pool with room for ~20 requests of the largest state: admission waits on memory
+    srv = hn.Server(idx, max_slots=64, pool_bytes=20 * (512 + 4096), k_max=10, ef_max=64,
+                    steps_per_tick=7, vis_bits=10)
+    got = {}
+    submitted = 0
+    for tick in range(100000):
+        burst = int(rng.integers(0, 9))
+        for _ in range(burst):
+            if submitted < n:
+                srv.submit(Q[submitted], int(ks[submitted]), int(efs[submitted]), submitted)
+                submitted += 1
+        srv.tick()
+        st = srv.stats()
+        assert st["active"] <= 64 and st["pool_bytes_used"] <= 20 * (512 + 4096)
+        tags, ids, dist = srv.poll()
+        for t, i, d in zip(tags, ids, dist):
+            got[int(t)] = (i.copy(), d.copy())
+        if len(got) == n:
+            break
+    assert len(got) == n
+    st = srv.stats()
+    assert st["max_active"] > 1          # requests overlapped on the device
+    assert st["max_active"] <= 20 * 4608 // 4352  # memory bounded the batch
+    for qi, (ids, dist) in got.items():
+        ri, rd = refs[qi]
+        assert np.array_equal(ids, ri), qi
+        assert np.array_equal(dist.view(np.uint32), rd.view(np.uint32)), qi
+    srv.close()
