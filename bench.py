@@ -53,6 +53,11 @@ def parse():
     ap.add_argument("--shape", default=None,
                     help="fixed launch shape 'lanes,waves,vis_bits,persistent' instead of the "
                          "autotuner (profiling runs use the shape the default run chose)")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=10000)
+    ap.add_argument("--serve-slots", type=int, default=4096)
+    ap.add_argument("--serve-pool-mb", type=int, default=64)
+    ap.add_argument("--serve-steps", type=int, default=32)
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
     return ap.parse_args()
@@ -349,10 +354,76 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    if not args.no_serve:
+        out["serving"] = serving_experiment(hn, indexes[head_form], Q, gt_dist, dist_rows,
+                                            sample, args)
     for f in forms:
         indexes[f].free()
     base.free()
     print(json.dumps(out), flush=True)
+
+
+def serving_experiment(hn, idx, Q, gt_dist, dist_rows, sample, args):
+    """Continuous batching under Poisson arrivals: each request has its own
+    k in {10, 50} and beam width in {128, 192, 256}; first the saturated
+    throughput (all requests queued at once), then fixed fractions of it as
+    arrival rates.  Latency = completion observed by the host - arrival."""
+    import workloads as wl
+    nq = Q.shape[0]
+    n_req = min(args.serve_requests, nq)
+    rk = np.random.default_rng(6).choice([10, 50], size=n_req).astype(np.int32)
+    ref = np.random.default_rng(7).choice([128, 192, 256], size=n_req).astype(np.int32)
+    qs = Q[:n_req]
+    tags = np.arange(n_req, dtype=np.int64)
+
+    def run(arrivals):
+        srv = hn.Server(idx, max_slots=args.serve_slots, pool_bytes=args.serve_pool_mb << 20,
+                        k_max=50, ef_max=256, steps_per_tick=args.serve_steps)
+        t0 = time.perf_counter()
+        done_t = np.zeros(n_req)
+        got_ids = np.full((n_req, 50), -1, dtype=np.int32)
+        nxt, ndone, ticks = 0, 0, 0
+        while ndone < n_req:
+            now = time.perf_counter() - t0
+            j = int(np.searchsorted(arrivals, now, side="right"))
+            if j > nxt:
+                srv.submit_batch(qs[nxt:j], rk[nxt:j], ref[nxt:j], tags[nxt:j])
+                nxt = j
+            srv.tick()
+            ticks += 1
+            tg, ids, _ = srv.poll()
+            if len(tg):
+                tnow = time.perf_counter() - t0
+                done_t[tg] = tnow
+                got_ids[tg] = ids
+                ndone += len(tg)
+        st = srv.stats()
+        srv.close()
+        lat = (done_t - arrivals) * 1e3
+        span = done_t.max() - arrivals.min()
+        return {"qps": round(n_req / span, 1), "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                "max_ms": round(float(lat.max()), 3), "ticks": ticks,
+                "max_active": int(st["max_active"])}, got_ids
+
+    sat, ids = run(np.zeros(n_req))
+    in_sample = [j for j, qi in enumerate(sample) if qi < n_req]
+    rec = recall_of(ids[:, :10], gt_dist[in_sample], dist_rows,
+                    np.asarray(sample)[in_sample]) if in_sample else None
+    levels = []
+    for frac in (0.25, 0.5, 0.75):
+        rate = frac * sat["qps"]
+        arr = wl.poisson_arrivals(n_req, rate, seed=5)
+        arr -= arr[0]
+        r, _ = run(arr)
+        r["offered_qps"] = round(rate, 1)
+        levels.append(r)
+        log(f"serving at {rate:,.0f} QPS offered: {r}")
+    log(f"serving saturated: {sat}, recall@10 {rec}")
+    return {"requests": n_req, "k": [10, 50], "ef": [128, 192, 256],
+            "steps_per_tick": args.serve_steps, "slots": args.serve_slots,
+            "pool_mb": args.serve_pool_mb, "saturated": sat, "recall_at_10": rec,
+            "poisson": levels}
 
 
 if __name__ == "__main__":

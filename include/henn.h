@@ -237,6 +237,9 @@ henn_status henn_server_create(const henn_index *idx, const henn_server_params *
 /* q_host: host FP32 [d], copied.  1 <= k <= k_max, max(ef, k) <= ef_max. */
 henn_status henn_server_submit(henn_server *s, const float *q_host, int32_t k, int32_t ef,
                                int64_t tag);
+/* n requests at once: q_host FP32 [n][d], k[n], ef[n], tags[n] (host). */
+henn_status henn_server_submit_batch(henn_server *s, const float *q_host, const int32_t *k,
+                                     const int32_t *ef, const int64_t *tags, int64_t n);
 /* Admits what fits, advances every active request one step, retires the
  * finished ones to the completion queue.  Blocking (one short launch).
  * *n_active (may be NULL): requests in flight during this tick. */

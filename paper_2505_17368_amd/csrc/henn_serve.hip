@@ -268,6 +268,27 @@ henn_status henn_server_submit(henn_server* s, const float* q_host, int32_t k, i
   return HENN_OK;
 }
 
+henn_status henn_server_submit_batch(henn_server* s, const float* q_host, const int32_t* k,
+                                     const int32_t* ef, const int64_t* tags, int64_t n) {
+  if (!s || (n > 0 && (!q_host || !k || !ef || !tags))) return srv_fail(HENN_E_INVAL, "null argument");
+  for (int64_t i = 0; i < n; ++i)
+    if (k[i] < 1 || k[i] > s->k_max || ef[i] < 1 || std::max(ef[i], k[i]) > s->ef_cap)
+      return srv_fail(HENN_E_INVAL, "k or ef out of range");
+  try {
+    for (int64_t i = 0; i < n; ++i) {
+      Pending r;
+      r.q.assign(q_host + i * s->d, q_host + (i + 1) * s->d);
+      r.k = k[i];
+      r.ef = ef[i];
+      r.tag = tags[i];
+      s->pending.push_back(std::move(r));
+    }
+  } catch (const std::bad_alloc&) {
+    return srv_fail(HENN_E_NOMEM, "host allocation failed");
+  }
+  return HENN_OK;
+}
+
 henn_status henn_server_tick(henn_server* s, int32_t* n_active_out) {
   if (!s) return srv_fail(HENN_E_INVAL, "null server");
   try {

@@ -119,6 +119,7 @@ def load_library(path: str = LIB_PATH):
     lib.henn_server_create.argtypes = [vp, P(ServerParams), P(vp)]
     lib.henn_server_submit.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64]
     lib.henn_server_tick.argtypes = [vp, P(ctypes.c_int32)]
+    lib.henn_server_submit_batch.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int64]
     lib.henn_server_poll.argtypes = [vp, ctypes.c_int32, vp, vp, vp, P(ctypes.c_int32)]
     lib.henn_server_stats.argtypes = [vp, P(ServerStats)]
     lib.henn_server_destroy.argtypes = [vp]
@@ -130,7 +131,8 @@ def load_library(path: str = LIB_PATH):
                  "henn_export_layer", "henn_import", "henn_autotune",
                  "henn_search_workspace_size", "henn_search_graph_create",
                  "henn_search_graph_launch", "henn_default_server_params", "henn_server_create",
-                 "henn_server_submit", "henn_server_tick", "henn_server_poll",
+                 "henn_server_submit", "henn_server_submit_batch", "henn_server_tick",
+                 "henn_server_poll",
                  "henn_server_stats"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -406,6 +408,16 @@ class Server:
         q = np.ascontiguousarray(q, dtype=np.float32)
         _check(load_library().henn_server_submit(self._s, q.ctypes.data_as(ctypes.c_void_p), k,
                                                  ef, tag))
+
+    def submit_batch(self, Q, ks, efs, tags):
+        Q = np.ascontiguousarray(Q, dtype=np.float32)
+        ks = np.ascontiguousarray(ks, dtype=np.int32)
+        efs = np.ascontiguousarray(efs, dtype=np.int32)
+        tags = np.ascontiguousarray(tags, dtype=np.int64)
+        vp = ctypes.c_void_p
+        _check(load_library().henn_server_submit_batch(
+            self._s, Q.ctypes.data_as(vp), ks.ctypes.data_as(vp), efs.ctypes.data_as(vp),
+            tags.ctypes.data_as(vp), Q.shape[0]))
 
     def tick(self) -> int:
         n = ctypes.c_int32()
