@@ -53,6 +53,10 @@ def parse():
     ap.add_argument("--shape", default=None,
                     help="fixed launch shape 'lanes,waves,vis_bits,persistent' instead of the "
                          "autotuner (profiling runs use the shape the default run chose)")
+    ap.add_argument("--mode", default="search", choices=["search", "batched"],
+                    help="search: the metric's ef sweep and timed steps; batched: one hipGraph "
+                         "of a mixed-k / mixed-ef persistent batch (10M x 128, FP8 by default)")
+    ap.add_argument("--storage", default="fp8", help="batched mode storage form")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--serve-slots", type=int, default=4096)
@@ -73,6 +77,23 @@ def calib_copy():
         dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"calib_copy_bytes": n * 4, "dispatches": 3}), flush=True)
+
+
+def distance_error(ids, dist, gt_dist, Xd64_rows_fn, sample):
+    """Returned distances against FP64 recomputation of the returned ids
+    (max / mean relative error) and the mean ratio of the j-th returned
+    FP64 distance to the true j-th distance (L2 only; 1 = exact)."""
+    errs, ratios = [], []
+    for j, qi in enumerate(sample):
+        ok = ids[qi] >= 0
+        dd = Xd64_rows_fn(qi, ids[qi])
+        errs.extend((np.abs(dist[qi][ok].astype(np.float64) - dd[ok])
+                     / np.maximum(np.abs(dd[ok]), 1e-30)).tolist())
+        m = int(ok.sum())
+        ratios.extend((dd[:m] / np.maximum(gt_dist[j, :m], 1e-30)).tolist())
+    e = np.array(errs) if errs else np.zeros(1)
+    return {"max_rel_err": float(e.max()), "mean_rel_err": float(e.mean()),
+            "mean_dist_ratio": float(np.mean(ratios)) if ratios else None}
 
 
 def recall_of(ids, gt_dist, Xd64_rows_fn, sample):
@@ -99,6 +120,9 @@ def main():
               "workload fit one MI355X; multi-GPU sharding is not part of this build.",
               file=sys.stderr)
         sys.exit(2)
+    if args.mode == "batched":
+        batched(args)
+        return
     import torch
 
     import paper_2505_17368_amd as hn
@@ -207,6 +231,7 @@ def main():
             torch.cuda.synchronize()
             ids_h = ids.cpu().numpy()
             rec = recall_of(ids_h, gt_dist, dist_rows, sample)
+            derr = distance_error(ids_h, dist.cpu().numpy(), gt_dist, dist_rows, sample)
             if fixed is not None:
                 ts = time_launches(indexes[f], ef, 5)
                 best, pers = float(np.median(ts)), fixed["persistent"]
@@ -218,7 +243,10 @@ def main():
             qps = nq / (best / 1e3)
             sweep[f].append({"ef": ef, "recall": round(rec, 4), "ms": round(best, 3),
                              "qps": round(qps, 1), "persistent": pers,
-                             "shape": tuned[(f, ef)]})
+                             "shape": tuned[(f, ef)],
+                             "max_rel_dist_err": round(derr["max_rel_err"], 9),
+                             "mean_dist_ratio": round(derr["mean_dist_ratio"], 6)
+                             if derr["mean_dist_ratio"] is not None else None})
             log(f"{f} ef={ef}: recall {rec:.4f}  {best:.3f} ms  {qps:,.0f} QPS "
                 f"(persistent {pers})")
             if rec >= args.target_recall and f not in chosen:
@@ -424,6 +452,108 @@ def serving_experiment(hn, idx, Q, gt_dist, dist_rows, sample, args):
             "steps_per_tick": args.serve_steps, "slots": args.serve_slots,
             "pool_mb": args.serve_pool_mb, "saturated": sat, "recall_at_10": rec,
             "poisson": levels}
+
+
+
+def batched(args):
+    """Batched mixed-request form: every query carries its own k in
+    {1, 10, 100} and beam width in {32, 64, 128} (ef_eff = max(ef, k)); the
+    whole batch runs as one persistent launch captured in a hipGraph, with
+    the launch shape chosen by the library's autotuner."""
+    import torch
+
+    import paper_2505_17368_amd as hn
+    import workloads as wl
+    from oracle import henn_oracle as ho
+
+    wname = args.workload if args.workload != "gmm100_1M_d128" else "gmm1000_10M_d128"
+    w = wl.WORKLOADS[wname]
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    X, Q = wl.make(wname, n=args.n, nq=args.nq)
+    n, d = X.shape
+    nq = Q.shape[0]
+    metric = 0 if w["metric"] == "l2" else 1
+    ks, efs = wl.mixed_requests(nq)
+    log(f"data {n}x{d}, {nq} queries in {time.time() - t0:.1f}s")
+    Xd = torch.from_numpy(X).to(dev)
+    Qd = torch.from_numpy(Q).to(dev)
+    bp = dict(degree=args.degree, metric=metric, graph=1 if args.graph == "knn_sym" else 0,
+              max_degree=args.max_degree, root_complete_max=args.root_max)
+    torch.cuda.synchronize()
+    t = time.time()
+    base = hn.henn_build(Xd, storage=0, **bp)
+    torch.cuda.synchronize()
+    build_s = time.time() - t
+    sizes = [base.layer_info(i)["size"] for i in range(base.num_layers)]
+    log(f"build {build_s:.1f}s, layers {sizes}")
+    st_code = {"f32": 0, "bf16": 1, "fp8": 2}[args.storage]
+    if st_code:
+        ex = [base.export_layer(i) for i in range(base.num_layers)]
+        idx = hn.henn_import(Xd, [e[0] for e in ex], [e[1] for e in ex], storage=st_code, **bp)
+        base.free()
+        del ex
+    else:
+        idx = base
+    k_d = torch.from_numpy(ks).to(dev)
+    ef_d = torch.from_numpy(efs).to(dev)
+    calib = min(nq, 16384)
+    shape = hn.henn_autotune(idx, Qd[:calib], k=10, ef=128, k_arr=k_d[:calib],
+                             ef_arr=ef_d[:calib], k_max=100, ef_max=128)
+    log(f"autotuned shape {shape}")
+    g = hn.SearchGraph(idx, Qd.clone(), k=10, ef=128, k_arr=k_d, ef_arr=ef_d, k_max=100,
+                       ef_max=128, persistent=True)
+    for _ in range(args.warmup):
+        g.launch()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    t_start = time.perf_counter()
+    for e0, e1 in evs:
+        e0.record(stream)
+        g.launch()
+        e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    kms = np.array([a.elapsed_time(b) for a, b in evs])
+    ids = g.ids.cpu().numpy()
+    # recall per k class on a sample, against the oracle's FP64 brute force
+    rng = np.random.default_rng(123)
+    sample = np.sort(rng.choice(nq, min(args.gt_sample, nq), replace=False))
+    t = time.time()
+    gt_ids, gt_dist = ho.brute_force_knn(X, Q[sample], 100, metric)
+    log(f"oracle ground truth (k=100) for {len(sample)} queries in {time.time() - t:.1f}s")
+    per_k = {}
+    for kk in (1, 10, 100):
+        sel = [j for j, qi in enumerate(sample) if ks[qi] == kk]
+        hits = 0
+        for j in sel:
+            qi = sample[j]
+            row = ids[qi, :kk]
+            ok = row >= 0
+            xs = X[row[ok]].astype(np.float64)
+            qv = Q[qi].astype(np.float64)
+            dd = ((xs - qv) ** 2).sum(1) if metric == 0 else -(xs @ qv)
+            kth = gt_dist[j, kk - 1]
+            hits += int(np.sum(dd <= kth + 1e-9 * abs(kth)))
+        per_k[f"k={kk}"] = round(hits / max(1, len(sel) * kk), 4) if sel else None
+    g.free()
+    idx.free()
+    out = {
+        "metric": "batched mixed-request QPS (one persistent hipGraph launch)",
+        "value": round(nq * args.steps / wall, 1), "unit": "queries/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3 / args.steps, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": wname, "n": n, "d": d, "nq": nq, "storage": args.storage,
+                   "k": [1, 10, 100], "ef": [32, 64, 128], "graph": args.graph,
+                   "max_degree": args.max_degree, "root_complete_max": args.root_max},
+        "p50_ms": round(float(np.percentile(kms, 50)), 3),
+        "p99_ms": round(float(np.percentile(kms, 99)), 3),
+        "recall_by_k": per_k, "build_s": round(build_s, 1), "layers": sizes, "shape": shape,
+    }
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

@@ -18,6 +18,11 @@
 //     the Gram error bound is not below the shortlist cut minus that bound.
 //  3. k_knn_exact: the exact brute force for those rows.
 #include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+
+#include <algorithm>
+#include <chrono>
 
 #include "henn_device.h"
 #include "henn_internal.h"
@@ -32,14 +37,15 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 template <int KHMAX>
 __global__ __launch_bounds__(256) void k_knn_gram(const float* vec, int64_t size, int dpad,
                                                   const float* mean, const float* norms,
-                                                  int metric, float* sl_d, int32_t* sl_i) {
+                                                  int metric, float* sl_d, int32_t* sl_i,
+                                                  int64_t block0) {
   extern __shared__ __align__(16) float tile[];  // [kTileC][dpad + 4] + norms[kTileC]
   const int lds_stride = dpad + 4;
   float* tnorm = tile + kTileC * lds_stride;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int qc = lane & 31, h = lane >> 5;
   const int kh = dpad >> 1;
-  const int64_t qrow = (int64_t)blockIdx.x * 128 + wave * 32 + qc;
+  const int64_t qrow = (block0 + blockIdx.x) * 128 + wave * 32 + qc;
   const bool qvalid = qrow < size;
 
   float bq[KHMAX];
@@ -264,18 +270,35 @@ int64_t build_knn_graph(const float* vec, int64_t size, int dpad, int nchunks, i
   const float nmax = max_norm(norms, size, st);
 
   const size_t lds = sizeof(float) * (kTileC * (dpad + 4) + kTileC);
-  const unsigned nb = (unsigned)((size + 127) / 128);
+  const int64_t nb = (size + 127) / 128;
   const int kh = dpad / 2;
-  if (kh <= 16)
-    hipLaunchKernelGGL(k_knn_gram<16>, dim3(nb), dim3(256), lds, st, vec, size, dpad, mean, norms,
-                       metric, sl_d, sl_i);
-  else if (kh <= 32)
-    hipLaunchKernelGGL(k_knn_gram<32>, dim3(nb), dim3(256), lds, st, vec, size, dpad, mean, norms,
-                       metric, sl_d, sl_i);
-  else
-    hipLaunchKernelGGL(k_knn_gram<64>, dim3(nb), dim3(256), lds, st, vec, size, dpad, mean, norms,
-                       metric, sl_d, sl_i);
-  HENN_HIP(hipGetLastError());
+  // Launch in slices of row blocks so that very large layers report progress
+  // (HENN_PROGRESS=1) between slices; each slice is a full-width Gram sweep.
+  const bool progress = getenv("HENN_PROGRESS") != nullptr;
+  const int64_t slice = std::max<int64_t>(4096, (int64_t)(2e13 / ((double)size * dpad * 256.0)));
+  auto t_last = std::chrono::steady_clock::now();
+  for (int64_t b0 = 0; b0 < nb; b0 += slice) {
+    const unsigned nbs = (unsigned)std::min<int64_t>(slice, nb - b0);
+    if (kh <= 16)
+      hipLaunchKernelGGL(k_knn_gram<16>, dim3(nbs), dim3(256), lds, st, vec, size, dpad, mean,
+                         norms, metric, sl_d, sl_i, b0);
+    else if (kh <= 32)
+      hipLaunchKernelGGL(k_knn_gram<32>, dim3(nbs), dim3(256), lds, st, vec, size, dpad, mean,
+                         norms, metric, sl_d, sl_i, b0);
+    else
+      hipLaunchKernelGGL(k_knn_gram<64>, dim3(nbs), dim3(256), lds, st, vec, size, dpad, mean,
+                         norms, metric, sl_d, sl_i, b0);
+    HENN_HIP(hipGetLastError());
+    if (progress && b0 + (int64_t)nbs < nb) {
+      HENN_HIP(hipStreamSynchronize(st));
+      const auto now = std::chrono::steady_clock::now();
+      if (std::chrono::duration<double>(now - t_last).count() > 20.0) {
+        fprintf(stderr, "[henn] kNN graph of %lld rows: %lld row blocks of %lld done\n",
+                (long long)size, (long long)(b0 + nbs), (long long)nb);
+        t_last = now;
+      }
+    }
+  }
 
   const unsigned nr = (unsigned)((size + 3) / 4);
   bool launched = false;

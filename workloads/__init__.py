@@ -148,14 +148,15 @@ def make(name: str, n: int | None = None, nq: int | None = None):
     n = n or w["n"]
     nq = nq or w["nq"]
     d = w["d"]
-    if name.startswith("uniform"):
+    family = name.split("_")[0]
+    if family == "uniform":
         return uniform(n, d, 0), uniform(nq, d, 1)
-    if name.startswith("gmm100"):
+    if family == "gmm100":
         return gauss_mix(n, d, 100, 0.3, 0), gauss_mix(nq, d, 100, 0.3, 1)
-    if name.startswith("gmm1000"):
+    if family == "gmm1000":
         return gauss_mix(n, d, 1000, 0.25, 0), gauss_mix(nq, d, 1000, 0.25, 1)
-    if name.startswith("curve"):
+    if family == "curve":
         return curve(n, d, 0), curve_queries(nq, n, d, 1)
-    if name.startswith("spectral"):
+    if family == "spectral":
         return spectral(n, d, 0), spectral(nq, d, 1)
     raise KeyError(name)
