@@ -34,31 +34,47 @@ constexpr int kTileC = 32;  // candidates per LDS tile
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-template <int KHMAX>
-__global__ __launch_bounds__(256) void k_knn_gram(const float* vec, int64_t size, int dpad,
+// Shortlist pass of the layer's kNN graph (Alg. 1 builds one graph per
+// layer).  A block takes 128 rows (one 32-row MFMA column block per wave)
+// and streams every row of the layer through LDS in tiles of kTileC.
+// The distance is assembled inside the contraction: with y = centred
+// candidate and x = centred row,
+//   |y - x|^2 = sum_k y_k (-2 x_k) + (|y|^2 + pen) * 1 + 1 * |x|^2
+//   -<y, x>   = sum_k y_k (-x_k)  +  pen * 1         + 0 * 0
+// the last two products being one extra MFMA step over the two lane
+// halves; pen = +inf marks rows past the end of the layer.  Rows are taken
+// as zero-padded to 2 * KH coordinates (dpad <= 2 * KH); the K dimension
+// splits at KH between the lane halves, so each tile is a fixed,
+// branch-free chain of KH + 1 MFMAs and the epilogue is one compare per
+// value, with an insertion into the lane's sorted top-kShort only when the
+// value beats the current kShort-th.
+template <int KH>
+__global__ __launch_bounds__(256, 2) void k_knn_gram(const float* vec, int64_t size, int dpad,
                                                   const float* mean, const float* norms,
                                                   int metric, float* sl_d, int32_t* sl_i,
                                                   int64_t block0) {
-  extern __shared__ __align__(16) float tile[];  // [kTileC][dpad + 4] + norms[kTileC]
-  const int lds_stride = dpad + 4;
-  float* tnorm = tile + kTileC * lds_stride;
+  // two LDS buffers of [kTileC][2 * KH + 4] candidates + their norms; the
+  // next tile is fetched into registers while the current one is multiplied
+  extern __shared__ __align__(16) float tile[];
+  constexpr int kStride = 2 * KH + 4;
+  constexpr int kBuf = kTileC * kStride + kTileC;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int qc = lane & 31, h = lane >> 5;
-  const int kh = dpad >> 1;
   const int64_t qrow = (block0 + blockIdx.x) * 128 + wave * 32 + qc;
   const bool qvalid = qrow < size;
+  const bool l2 = metric == 0;
+  const float qscale = l2 ? -2.0f : -1.0f;
 
-  float bq[KHMAX];
+  float bq[KH];
 #pragma unroll
-  for (int kk = 0; kk < KHMAX; ++kk) {
-    float v = 0.0f;
-    if (kk < kh && qvalid) {
-      const int e = h * kh + kk;
-      v = vec[qrow * dpad + e] - (mean ? mean[e] : 0.0f);
-    }
-    bq[kk] = v;
+  for (int kk = 0; kk < KH; ++kk) {
+    const int e = h * KH + kk;
+    bq[kk] = (qvalid && e < dpad) ? qscale * (vec[qrow * dpad + e] - (mean ? mean[e] : 0.0f))
+                                  : 0.0f;
   }
-  const float nq = qvalid ? norms[qrow] : 0.0f;
+  // B operand of the extra step: row 0 is all ones, row 1 holds |x|^2 (L2)
+  const float b_extra = h == 0 ? 1.0f : (l2 && qvalid ? norms[qrow] : 0.0f);
+  const float a_one = l2 ? 1.0f : 0.0f;
 
   float td[kShort];
   int32_t ti[kShort];
@@ -68,45 +84,98 @@ __global__ __launch_bounds__(256) void k_knn_gram(const float* vec, int64_t size
     ti[j] = -1;
   }
 
+  // zero the padding columns [dpad, 2 KH) of both buffers once; tiles only
+  // ever write columns below dpad
+  for (int i = threadIdx.x; i < 2 * kTileC * (2 * KH - dpad); i += 256) {
+    const int per = 2 * KH - dpad;
+    const int b = i / (kTileC * per), rem = i - b * kTileC * per;
+    const int r = rem / per, c = dpad + (rem - r * per);
+    tile[b * kBuf + r * kStride + c] = 0.0f;
+  }
+
+  // a tile is kTileC * dpad / 4 <= 16 * KH float4, so each of the 256
+  // threads moves at most KH / 16 of them.  Loads are clamped to valid rows
+  // so that they issue without branches and complete while the previous
+  // tile is multiplied; the layer mean is subtracted when the tile is
+  // written to LDS.
+  constexpr int kMaxF4 = KH / 16;
   const int f4_per_row = dpad >> 2;
-  for (int64_t c0 = 0; c0 < size; c0 += kTileC) {
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < kTileC * f4_per_row; idx += 256) {
-      const int r = idx / f4_per_row, c4 = idx - r * f4_per_row;
-      const int64_t row = c0 + r;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (row < size) {
-        v = reinterpret_cast<const float4*>(vec + row * dpad)[c4];
+  const int tile_f4 = kTileC * f4_per_row;
+  float* mean_lds = tile + 2 * kBuf;
+  if (mean)
+    for (int e = threadIdx.x; e < dpad; e += 256) mean_lds[e] = mean[e];
+  int src_off[kMaxF4], dst_off[kMaxF4], src_row[kMaxF4];
+#pragma unroll
+  for (int u = 0; u < kMaxF4; ++u) {
+    const int idx = min((int)threadIdx.x + u * 256, tile_f4 - 1);
+    const int r = idx / f4_per_row, c4 = idx - r * f4_per_row;
+    src_row[u] = r;
+    src_off[u] = c4;
+    dst_off[u] = (int)threadIdx.x + u * 256 < tile_f4 ? r * kStride + 4 * c4 : -1;
+  }
+  float4 pre[kMaxF4];
+  float pnorm = 0.0f;
+  auto fetch = [&](int64_t c0) {
+#pragma unroll
+    for (int u = 0; u < kMaxF4; ++u) {
+      const int64_t row = min(c0 + src_row[u], size - 1);
+      pre[u] = reinterpret_cast<const float4*>(vec + row * dpad)[src_off[u]];
+    }
+    const int64_t nrow = c0 + (threadIdx.x & (kTileC - 1));
+    const float nv = norms[min(nrow, size - 1)];
+    pnorm = nrow < size ? (l2 ? nv : 0.0f) : INFINITY;
+  };
+  auto stash = [&](float* buf) {
+#pragma unroll
+    for (int u = 0; u < kMaxF4; ++u) {
+      if (dst_off[u] >= 0) {
+        float4 v = pre[u];
         if (mean) {
-          const float4 m = reinterpret_cast<const float4*>(mean)[c4];
+          const float4 m = reinterpret_cast<const float4*>(mean_lds)[src_off[u]];
           v.x -= m.x; v.y -= m.y; v.z -= m.z; v.w -= m.w;
         }
+        *reinterpret_cast<float4*>(buf + dst_off[u]) = v;
       }
-      *reinterpret_cast<float4*>(tile + r * lds_stride + 4 * c4) = v;
     }
-    if (threadIdx.x < kTileC) {
-      const int64_t row = c0 + threadIdx.x;
-      tnorm[threadIdx.x] = row < size ? norms[row] : 0.0f;
-    }
-    __syncthreads();
+    if (threadIdx.x < kTileC) buf[kTileC * kStride + threadIdx.x] = pnorm;
+  };
+
+  __syncthreads();
+  fetch(0);
+  stash(tile);
+  __syncthreads();
+  int cur = 0;
+  for (int64_t c0 = 0; c0 < size; c0 += kTileC) {
+    const bool more = c0 + kTileC < size;
+    if (more) fetch(c0 + kTileC);
+    const float* buf = tile + cur * kBuf;
 
     floatx16 acc;
 #pragma unroll
     for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
-    const float* arow = tile + qc * lds_stride + h * kh;
+    const float4* arow = reinterpret_cast<const float4*>(buf + qc * kStride + h * KH);
 #pragma unroll
-    for (int kk = 0; kk < KHMAX; ++kk) {
-      if (kk < kh) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(arow[kk], bq[kk], acc, 0, 0, 0);
+    for (int k4 = 0; k4 < KH / 4; ++k4) {
+      const float4 a = arow[k4];
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, bq[4 * k4 + 0], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.y, bq[4 * k4 + 1], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.z, bq[4 * k4 + 2], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a.w, bq[4 * k4 + 3], acc, 0, 0, 0);
     }
+    const float a_extra = h == 0 ? buf[kTileC * kStride + qc] : a_one;
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a_extra, b_extra, acc, 0, 0, 0);
 
+    bool any = false;
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int ci = 8 * (v >> 2) + 4 * h + (v & 3);
-      const int64_t crow = c0 + ci;
-      if (crow < size && crow != qrow) {
-        const float dist = metric == 0 ? (nq + tnorm[ci]) - 2.0f * acc[v] : -acc[v];
-        if (dist < td[kShort - 1]) {
-          float nd = dist;
+    for (int v = 0; v < 16; ++v) any |= acc[v] < td[kShort - 1];
+    if (__builtin_amdgcn_ballot_w64(any)) {
+      // lanes without a hit push +inf through the network, which leaves
+      // their list unchanged, so the network runs without divergence
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int64_t crow = c0 + 8 * (v >> 2) + 4 * h + (v & 3);
+        float nd = crow != qrow ? acc[v] : INFINITY;
+        if (__builtin_amdgcn_ballot_w64(nd < td[kShort - 1])) {
           int32_t ni = (int32_t)crow;
 #pragma unroll
           for (int j = 0; j < kShort; ++j) {
@@ -121,6 +190,9 @@ __global__ __launch_bounds__(256) void k_knn_gram(const float* vec, int64_t size
         }
       }
     }
+    if (more) stash(tile + (cur ^ 1) * kBuf);
+    __syncthreads();
+    cur ^= 1;
   }
   if (qvalid) {
     float* od = sl_d + qrow * (2 * kShort) + h * kShort;
@@ -269,9 +341,9 @@ int64_t build_knn_graph(const float* vec, int64_t size, int dpad, int nchunks, i
   launch_row_norms(vec, mean, size, dpad, norms, st);
   const float nmax = max_norm(norms, size, st);
 
-  const size_t lds = sizeof(float) * (kTileC * (dpad + 4) + kTileC);
+  const int kh = dpad <= 32 ? 16 : dpad <= 64 ? 32 : 64;
+  const size_t lds = sizeof(float) * (2 * (kTileC * (2 * kh + 4) + kTileC) + dpad);
   const int64_t nb = (size + 127) / 128;
-  const int kh = dpad / 2;
   // Launch in slices of row blocks so that very large layers report progress
   // (HENN_PROGRESS=1) between slices; each slice is a full-width Gram sweep.
   const bool progress = getenv("HENN_PROGRESS") != nullptr;
