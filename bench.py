@@ -53,7 +53,7 @@ def parse():
     ap.add_argument("--shape", default=None,
                     help="fixed launch shape 'lanes,waves,vis_bits,persistent' instead of the "
                          "autotuner (profiling runs use the shape the default run chose)")
-    ap.add_argument("--mode", default="search", choices=["search", "batched"],
+    ap.add_argument("--mode", default="search", choices=["search", "batched", "serving"],
                     help="search: the metric's ef sweep and timed steps; batched: one hipGraph "
                          "of a mixed-k / mixed-ef persistent batch (10M x 128, FP8 by default)")
     ap.add_argument("--storage", default="fp8", help="batched mode storage form")
@@ -62,6 +62,8 @@ def parse():
     ap.add_argument("--serve-slots", type=int, default=4096)
     ap.add_argument("--serve-pool-mb", type=int, default=64)
     ap.add_argument("--serve-steps", type=int, default=32)
+    ap.add_argument("--serve-root-max", type=int, default=0,
+                    help="serving mode: complete-root size limit (0 = greedy root)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
     return ap.parse_args()
@@ -116,12 +118,15 @@ def main():
         calib_copy()
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: the HENN index and every query of this "
-              "workload fit one MI355X; multi-GPU sharding is not part of this build.",
-              file=sys.stderr)
+        print("bench.py measures one GPU only (--gpus 1): the index and the queries of "
+              "every workload here fit one MI355X, and sharded multi-GPU search is not "
+              "implemented.", file=sys.stderr)
         sys.exit(2)
     if args.mode == "batched":
         batched(args)
+        return
+    if args.mode == "serving":
+        serving(args)
         return
     import torch
 
@@ -391,25 +396,28 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def serving_experiment(hn, idx, Q, gt_dist, dist_rows, sample, args):
+def serving_experiment(hn, idx, Q, gt_dist, dist_rows, sample, args, k_choices=(10, 50),
+                       ef_choices=(128, 192, 256), fracs=(0.25, 0.5, 0.75)):
     """Continuous batching under Poisson arrivals: each request has its own
-    k in {10, 50} and beam width in {128, 192, 256}; first the saturated
-    throughput (all requests queued at once), then fixed fractions of it as
-    arrival rates.  Latency = completion observed by the host - arrival."""
+    k (from k_choices, seed 6) and beam width (from ef_choices, seed 7);
+    first the saturated throughput (all requests queued at once), then the
+    given fractions of it as arrival rates.  Latency = completion observed
+    by the host - arrival."""
     import workloads as wl
     nq = Q.shape[0]
     n_req = min(args.serve_requests, nq)
-    rk = np.random.default_rng(6).choice([10, 50], size=n_req).astype(np.int32)
-    ref = np.random.default_rng(7).choice([128, 192, 256], size=n_req).astype(np.int32)
+    rk = np.random.default_rng(6).choice(list(k_choices), size=n_req).astype(np.int32)
+    ref = np.random.default_rng(7).choice(list(ef_choices), size=n_req).astype(np.int32)
+    k_max, ef_max = int(max(k_choices)), int(max(ef_choices))
     qs = Q[:n_req]
     tags = np.arange(n_req, dtype=np.int64)
 
     def run(arrivals):
         srv = hn.Server(idx, max_slots=args.serve_slots, pool_bytes=args.serve_pool_mb << 20,
-                        k_max=50, ef_max=256, steps_per_tick=args.serve_steps)
+                        k_max=k_max, ef_max=ef_max, steps_per_tick=args.serve_steps)
         t0 = time.perf_counter()
         done_t = np.zeros(n_req)
-        got_ids = np.full((n_req, 50), -1, dtype=np.int32)
+        got_ids = np.full((n_req, k_max), -1, dtype=np.int32)
         nxt, ndone, ticks = 0, 0, 0
         while ndone < n_req:
             now = time.perf_counter() - t0
@@ -439,7 +447,7 @@ def serving_experiment(hn, idx, Q, gt_dist, dist_rows, sample, args):
     rec = recall_of(ids[:, :10], gt_dist[in_sample], dist_rows,
                     np.asarray(sample)[in_sample]) if in_sample else None
     levels = []
-    for frac in (0.25, 0.5, 0.75):
+    for frac in fracs:
         rate = frac * sat["qps"]
         arr = wl.poisson_arrivals(n_req, rate, seed=5)
         arr -= arr[0]
@@ -448,7 +456,7 @@ def serving_experiment(hn, idx, Q, gt_dist, dist_rows, sample, args):
         levels.append(r)
         log(f"serving at {rate:,.0f} QPS offered: {r}")
     log(f"serving saturated: {sat}, recall@10 {rec}")
-    return {"requests": n_req, "k": [10, 50], "ef": [128, 192, 256],
+    return {"requests": n_req, "k": list(k_choices), "ef": list(ef_choices),
             "steps_per_tick": args.serve_steps, "slots": args.serve_slots,
             "pool_mb": args.serve_pool_mb, "saturated": sat, "recall_at_10": rec,
             "poisson": levels}
@@ -552,6 +560,109 @@ def batched(args):
         "p50_ms": round(float(np.percentile(kms, 50)), 3),
         "p99_ms": round(float(np.percentile(kms, 99)), 3),
         "recall_by_k": per_k, "build_s": round(build_s, 1), "layers": sizes, "shape": shape,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def serving(args):
+    """Serving form on the embedding-retrieval workload (5M x 768 unit
+    vectors, inner product, BF16 rows with an FP32 re-rank): build once,
+    take as per-request beam widths the three smallest sweep points at or
+    above the first one reaching the recall target at k = 10, then run
+    continuous batching saturated and at fractions of that rate under
+    Poisson arrivals, with k in {10, 50} per request."""
+    import torch
+
+    import paper_2505_17368_amd as hn
+    import workloads as wl
+    from oracle import henn_oracle as ho
+
+    wname = args.workload if args.workload != "gmm100_1M_d128" else "spectral_5M_d768"
+    w = wl.WORKLOADS[wname]
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    X, Q = wl.make(wname, n=args.n, nq=args.nq)
+    n, d = X.shape
+    nq = Q.shape[0]
+    metric = 0 if w["metric"] == "l2" else 1
+    log(f"data {n}x{d}, {nq} queries in {time.time() - t0:.1f}s")
+    Xd = torch.from_numpy(X).to(dev)
+    Qd = torch.from_numpy(Q).to(dev)
+    bp = dict(degree=args.degree, metric=metric, graph=1 if args.graph == "knn_sym" else 0,
+              max_degree=args.max_degree, root_complete_max=args.serve_root_max)
+    torch.cuda.synchronize()
+    t = time.time()
+    base = hn.henn_build(Xd, storage=0, **bp)
+    torch.cuda.synchronize()
+    build_s = time.time() - t
+    sizes = [base.layer_info(i)["size"] for i in range(base.num_layers)]
+    fallback = [base.layer_info(i)["fallback_rows"] for i in range(base.num_layers)]
+    log(f"build {build_s:.1f}s, layers {sizes}, exact-fallback rows {fallback}")
+    st_code = {"f32": 0, "bf16": 1, "fp8": 2}[args.storage]
+    if st_code:
+        ex = [base.export_layer(i) for i in range(base.num_layers)]
+        idx = hn.henn_import(Xd, [e[0] for e in ex], [e[1] for e in ex], storage=st_code, **bp)
+        base.free()
+        del ex
+    else:
+        idx = base
+
+    rng = np.random.default_rng(123)
+    sample = np.sort(rng.choice(nq, min(args.gt_sample, nq), replace=False))
+    t = time.time()
+    _, gt_dist = ho.brute_force_knn(X, Q[sample], 10, metric)
+    log(f"oracle ground truth for {len(sample)} queries in {time.time() - t:.1f}s")
+
+    def dist_rows(qi, ids):
+        ok = ids >= 0
+        out = np.full(ids.shape, np.inf)
+        if ok.any():
+            xs = X[ids[ok]].astype(np.float64)
+            qv = Q[qi].astype(np.float64)
+            out[ok] = ((xs - qv) ** 2).sum(1) if metric == 0 else -(xs @ qv)
+        return out
+
+    efs = [int(e) for e in args.efs.split(",")]
+    sweep = []
+    chosen = None
+    for ef in efs:
+        hn.henn_autotune(idx, Qd[: min(nq, 8192)], k=10, ef=ef)
+        ids, _ = hn.henn_search_batch(idx, Qd, k=10, ef=ef)
+        torch.cuda.synchronize()
+        rec = recall_of(ids.cpu().numpy(), gt_dist, dist_rows, sample)
+        ts = []
+        for _ in range(5):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            hn.henn_search_batch(idx, Qd, k=10, ef=ef)
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ms = float(np.median(ts))
+        sweep.append({"ef": ef, "recall": round(rec, 4), "batch_qps": round(nq / (ms / 1e3), 1)})
+        log(f"ef={ef}: recall@10 {rec:.4f}, batched {nq / (ms / 1e3):,.0f} QPS")
+        if chosen is None and rec >= args.target_recall:
+            chosen = ef
+    if chosen is None:
+        chosen = efs[-1]
+    pos = efs.index(chosen)
+    ef_choices = tuple(efs[pos:pos + 3]) if pos + 3 <= len(efs) else tuple(efs[-3:])
+    log(f"per-request beam widths {ef_choices}")
+    res = serving_experiment(hn, idx, Q, gt_dist, dist_rows, list(sample), args,
+                             k_choices=(10, 50), ef_choices=ef_choices,
+                             fracs=(0.1, 0.3, 0.5, 0.7, 0.9))
+    idx.free()
+    sat = res["saturated"]
+    out = {
+        "metric": "serving QPS (continuous batching, saturated) with Poisson-load p50/p99",
+        "value": sat["qps"], "unit": "queries/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": args.storage, "data": "synthetic",
+        "config": {"workload": wname, "n": n, "d": d, "nq": nq, "metric": w["metric"],
+                   "storage": args.storage, "graph": args.graph,
+                   "max_degree": args.max_degree, "root_complete_max": args.serve_root_max},
+        "build_s": round(build_s, 1), "layers": sizes, "fallback_rows": fallback,
+        "sweep": sweep, "serving": res,
     }
     print(json.dumps(out), flush=True)
 

@@ -38,7 +38,7 @@ typedef enum {
   HENN_E_INVAL = 1,       /* bad argument: sizes, null pointers, struct_size */
   HENN_E_NOMEM = 2,       /* device or host allocation failed */
   HENN_E_DEVICE = 3,      /* a HIP runtime call failed */
-  HENN_E_UNSUPPORTED = 4, /* valid but not supported by this build */
+  HENN_E_UNSUPPORTED = 4, /* valid but not supported by the library */
   HENN_W_NOT_VERIFIED = 100 /* warning: index usable, some layer kept its best
                                unverified sample (Alg. 2 attempt cap reached) */
 } henn_status;
@@ -140,7 +140,7 @@ henn_status henn_default_search_params(henn_search_params *p);
 /* Alg. 1 (BuildHENN) on the GPU.
  *   X: device, FP32 row-major [n][d]; copied into library memory, so the
  *      caller may free it on return.
- *   n in [1, 2^31 - 1]; d in [1, 4096].
+ *   n in [1, 2^31 - 1]; d in [1, 1024].
  *   *out: receives a new index owned by the library (free with henn_free).
  * Blocks: the Las-Vegas decisions of Alg. 2 are taken on the host, so the
  * call synchronises hip_stream.  Returns HENN_W_NOT_VERIFIED (index usable)

@@ -45,6 +45,7 @@ static void free_layer(LayerDev& L) {
   (void)hipFree(L.vec32);
   (void)hipFree(L.vecq);
   (void)hipFree(L.scale);
+  (void)hipFree(L.adj_scale);
   (void)hipFree(L.adj);
   (void)hipFree(L.ids);
   (void)hipFree(L.down);
@@ -119,6 +120,10 @@ static void finish_layer(henn_index* ix, int i, hipStream_t st) {
     L.vecq = dalloc<uint8_t>(L.size * ix->dpad * storage_bytes(ix->storage));
     if (ix->storage == HENN_FP8_E4M3) L.scale = dalloc<float>(L.size);
     launch_quantize(ix->storage, L.vec32, L.size, ix->dpad, L.vecq, L.scale, st);
+    if (ix->storage == HENN_FP8_E4M3) {
+      L.adj_scale = dalloc<float>(L.size * L.deg);
+      launch_adj_scale(L.adj, L.size * L.deg, L.scale, L.adj_scale, st);
+    }
   }
   HENN_HIP(hipStreamSynchronize(st));
 }
@@ -319,7 +324,6 @@ henn_status henn_build(const float* X, int64_t n, int32_t d, const henn_build_pa
   if (cs != HENN_OK) return cs;
   std::string why;
   if (!valid_build_params(p, &why)) return fail(HENN_E_INVAL, why);
-  if ((d + 7) / 8 * 8 > 128) return fail(HENN_E_UNSUPPORTED, "GPU graph build supports d <= 128");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   henn_index* ix = nullptr;
   int32_t* local = nullptr;
@@ -450,6 +454,10 @@ henn_status henn_import(const float* X, int64_t n, int32_t d, const henn_build_p
         L.vecq = dalloc<uint8_t>(L.size * ix->dpad * storage_bytes(ix->storage));
         if (ix->storage == HENN_FP8_E4M3) L.scale = dalloc<float>(L.size);
         launch_quantize(ix->storage, L.vec32, L.size, ix->dpad, L.vecq, L.scale, st);
+        if (ix->storage == HENN_FP8_E4M3) {
+          L.adj_scale = dalloc<float>(L.size * L.deg);
+          launch_adj_scale(L.adj, L.size * L.deg, L.scale, L.adj_scale, st);
+        }
       }
       HENN_HIP(hipStreamSynchronize(st));
     }
@@ -511,6 +519,7 @@ henn_status henn_search_batch(const henn_index* idx, const float* Q, int64_t nq,
       s.vec = idx->storage == HENN_F32 ? (const void*)L.vec32 : (const void*)L.vecq;
       s.scale = L.scale;
       s.adj = L.adj;
+      s.adj_scale = L.adj_scale;
       s.down = L.down;
       s.size = (int32_t)L.size;
       s.deg = L.deg;

@@ -509,6 +509,21 @@ __global__ void k_quantize_fp8(const float* vec, int64_t size, int dpad, uint8_t
   for (int j = lane; j < dpad; j += 64) out[row * dpad + j] = (uint8_t)f32_to_e4m3_rne(x[j] / sc);
 }
 
+__global__ void k_adj_scale(const int32_t* adj, int64_t n, const float* scale, float* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t u = adj[i];
+  out[i] = u >= 0 ? scale[u] : 0.0f;
+}
+
+void launch_adj_scale(const int32_t* adj, int64_t n, const float* scale, float* out,
+                      hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_adj_scale, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, adj, n,
+                     scale, out);
+  HENN_HIP(hipGetLastError());
+}
+
 void launch_quantize(int storage, const float* vec, int64_t size, int dpad, void* out,
                      float* scale, hipStream_t st) {
   if (storage == kBF16) {

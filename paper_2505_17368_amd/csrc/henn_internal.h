@@ -20,6 +20,9 @@ namespace henn {
 //   scale: per-row FP32 scale (FP8) or nullptr.
 //   adj:   int32 [size][deg], positions within the layer, (dist, id) order,
 //          -1 padded.
+//   adj_scale: FP8 only, float [size][deg]: the scale of each neighbour, so
+//          that an expansion reads its neighbours' scales with the adjacency
+//          row instead of one scattered 4-byte read per evaluated row.
 //   ids:   int32 [size] ascending point ids (nullptr for layer 0 = identity).
 //   down:  int32 [size] position of the same point in layer-1 (the
 //          inter-layer edge of Def. HENN); nullptr for layer 0.
@@ -30,6 +33,7 @@ struct LayerDev {
   void* vecq = nullptr;
   float* scale = nullptr;
   int32_t* adj = nullptr;
+  float* adj_scale = nullptr;
   int32_t* ids = nullptr;
   int32_t* down = nullptr;
   henn_layer_info info{};
@@ -85,6 +89,7 @@ struct SearchLayer {
   const void* vec;
   const float* scale;
   const int32_t* adj;
+  const float* adj_scale;  // FP8: neighbour scales beside adj, else nullptr
   const int32_t* down;
   int32_t size;
   int32_t deg;
@@ -189,6 +194,9 @@ void launch_row_norms(const float* vec, const float* mean, int64_t size, int dpa
 float max_norm(const float* norms, int64_t size, hipStream_t st);
 void launch_quantize(int storage, const float* vec, int64_t size, int dpad, void* out,
                      float* scale, hipStream_t st);
+// out[i] = scale[adj[i]] for the n entries of an adjacency array (0 for -1).
+void launch_adj_scale(const int32_t* adj, int64_t n, const float* scale, float* out,
+                      hipStream_t st);
 
 // kNN graph of one layer: FP32 MFMA Gram shortlist + exact re-rank + exact
 // fallback for rows whose shortlist cannot be proven to hold the top R.

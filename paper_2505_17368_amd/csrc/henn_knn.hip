@@ -3,7 +3,8 @@
 // (distance, id) order.
 //
 // Three steps:
-//  1. k_knn_gram (MFMA): all-pairs Gram tiles on FP32 matrix cores.  A
+//  1. k_knn_gram / k_knn_gram_wide (MFMA): all-pairs Gram tiles on FP32
+//     matrix cores (the wide form streams K in slices for d > 128).  A
 //     workgroup owns 128 rows (4 waves x 32); candidate tiles of 32 rows are
 //     staged in LDS and multiplied with v_mfma_f32_32x32x2f32, the K split
 //     as (lane half h) x (step kk) over the two halves of each row.  Rows are
@@ -205,6 +206,186 @@ __global__ __launch_bounds__(256, 2) void k_knn_gram(const float* vec, int64_t s
   }
 }
 
+// Shortlist pass for rows wider than 128 coordinates (up to 1024), where
+// a row block no longer fits in registers.  Same distances, same shortlist
+// and the same folded norm step as k_knn_gram, arranged as a GEMM: a block
+// owns 128 rows (32 per wave) and walks the layer in tiles of kWideC = 128
+// candidates; the K dimension streams through LDS in slices of kSlice = 32
+// coordinates (candidate slice and row slice, double buffered, fetched into
+// registers one slice ahead).  Each wave multiplies its 32 rows against the
+// tile's four 32-candidate blocks into four independent accumulators, the
+// two lane halves covering coordinates [0, 16) and [16, 32) of each slice.
+// Row values are pre-scaled by -2 (L2) or -1 (IP) when staged; coordinates
+// past dpad are staged as zeros.
+constexpr int kWideC = 128;
+constexpr int kSlice = 32;
+constexpr int kSStride = kSlice + 4;
+
+__global__ __launch_bounds__(256) void k_knn_gram_wide(const float* vec, int64_t size,
+                                                          int dpad, const float* mean,
+                                                          const float* norms, int metric,
+                                                          float* sl_d, int32_t* sl_i,
+                                                          int64_t block0) {
+  extern __shared__ __align__(16) float lds[];
+  constexpr int kHalf = kWideC * kSStride;  // one operand slice
+  constexpr int kBuf = 2 * kHalf;           // candidate slice + row slice
+  float* mean_lds = lds + 2 * kBuf;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int qc = lane & 31, h = lane >> 5;
+  const int64_t qbase = (block0 + blockIdx.x) * 128;
+  const int64_t qrow = qbase + wave * 32 + qc;
+  const bool qvalid = qrow < size;
+  const bool l2 = metric == 0;
+  const float qscale = l2 ? -2.0f : -1.0f;
+  const float b_extra = h == 0 ? 1.0f : (l2 && qvalid ? norms[qrow] : 0.0f);
+  const float a_one = l2 ? 1.0f : 0.0f;
+
+  float td[kShort];
+  int32_t ti[kShort];
+#pragma unroll
+  for (int j = 0; j < kShort; ++j) {
+    td[j] = INFINITY;
+    ti[j] = -1;
+  }
+  if (mean)
+    for (int e = threadIdx.x; e < dpad; e += 256) mean_lds[e] = mean[e];
+
+  // thread -> (row, float4 column) of a slice: 8 threads cover one row's 32
+  // coordinates; slot u < 4 stages candidate rows, u >= 4 the block's rows
+  const int lrow = threadIdx.x >> 3, lc4 = threadIdx.x & 7;
+  const int nsl = (dpad + kSlice - 1) / kSlice;
+  float4 pre[8];
+  auto fetch = [&](int64_t c0, int ks) {
+    const int col = ks * kSlice + 4 * lc4;
+    const int colc = col < dpad ? col : 0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t base = u < 4 ? c0 : qbase;
+      const int64_t row = min(base + lrow + 32 * (u & 3), size - 1);
+      pre[u] = *reinterpret_cast<const float4*>(vec + row * dpad + colc);
+    }
+  };
+  auto stash = [&](float* buf, int ks) {
+    const int col = ks * kSlice + 4 * lc4;
+    const bool cvalid = col < dpad;
+    float4 m = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (mean && cvalid) m = *reinterpret_cast<const float4*>(mean_lds + col);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      float4 v = pre[u];
+      v.x -= m.x; v.y -= m.y; v.z -= m.z; v.w -= m.w;
+      if (u >= 4) {
+        v.x *= qscale; v.y *= qscale; v.z *= qscale; v.w *= qscale;
+      }
+      if (!cvalid) v = make_float4(0.f, 0.f, 0.f, 0.f);
+      *reinterpret_cast<float4*>(buf + (u < 4 ? 0 : kHalf) + (lrow + 32 * (u & 3)) * kSStride +
+                                 4 * lc4) = v;
+    }
+  };
+  auto tile_norms = [&](int64_t c0, float* cn) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int64_t row = c0 + 32 * b + qc;
+      const float nv = norms[min(row, size - 1)];
+      cn[b] = row < size ? (l2 ? nv : 0.0f) : INFINITY;
+    }
+  };
+
+  __syncthreads();
+  fetch(0, 0);
+  stash(lds, 0);
+  __syncthreads();
+
+  int cur = 0;
+  for (int64_t c0 = 0; c0 < size; c0 += kWideC) {
+    float cn[4];
+    tile_norms(c0, cn);
+    floatx16 acc[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[b][v] = 0.0f;
+
+    for (int ks = 0; ks < nsl; ++ks) {
+      // the next slice, crossing into the next tile after the last one
+      const bool last = ks + 1 == nsl;
+      const int nks = last ? 0 : ks + 1;
+      const int64_t nc0 = last ? c0 + kWideC : c0;
+      const bool more = nc0 < size;
+      if (more) fetch(nc0, nks);
+
+      const float* buf = lds + cur * kBuf;
+      const float4* brow = reinterpret_cast<const float4*>(buf + kHalf +
+                                                           (wave * 32 + qc) * kSStride + 16 * h);
+#pragma unroll
+      for (int k4 = 0; k4 < 4; ++k4) {
+        const float4 bv = brow[k4];
+        float4 av[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          av[b] = reinterpret_cast<const float4*>(buf + (32 * b + qc) * kSStride + 16 * h)[k4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[b].x, bv.x, acc[b], 0, 0, 0);
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[b].y, bv.y, acc[b], 0, 0, 0);
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[b].z, bv.z, acc[b], 0, 0, 0);
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[b].w, bv.w, acc[b], 0, 0, 0);
+      }
+      if (more) stash(lds + (cur ^ 1) * kBuf, nks);
+      __syncthreads();
+      cur ^= 1;
+    }
+
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(h == 0 ? cn[b] : a_one, b_extra, acc[b], 0,
+                                                    0, 0);
+    float lo = INFINITY;
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) lo = fminf(lo, acc[b][v]);
+    if (__builtin_amdgcn_ballot_w64(lo < td[kShort - 1])) {
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int64_t crow = c0 + 32 * b + 8 * (v >> 2) + 4 * h + (v & 3);
+          float nd = crow != qrow ? acc[b][v] : INFINITY;
+          if (__builtin_amdgcn_ballot_w64(nd < td[kShort - 1])) {
+            int32_t ni = (int32_t)crow;
+#pragma unroll
+            for (int j = 0; j < kShort; ++j) {
+              const bool sw = nd < td[j];
+              const float od = td[j];
+              const int32_t oi = ti[j];
+              td[j] = sw ? nd : od;
+              ti[j] = sw ? ni : oi;
+              nd = sw ? od : nd;
+              ni = sw ? oi : ni;
+            }
+          }
+        }
+      }
+    }
+  }
+  if (qvalid) {
+    float* od = sl_d + qrow * (2 * kShort) + h * kShort;
+    int32_t* oi = sl_i + qrow * (2 * kShort) + h * kShort;
+#pragma unroll
+    for (int j = 0; j < kShort; ++j) {
+      od[j] = td[j];
+      oi[j] = ti[j];
+    }
+  }
+}
+
 __device__ inline uint64_t wave_sort64(uint64_t key) {
   const int lane = lane_id();
   for (int size = 2; size <= 64; size <<= 1) {
@@ -324,7 +505,7 @@ __global__ __launch_bounds__(256) void k_knn_exact(const float* vec, int64_t siz
 int64_t build_knn_graph(const float* vec, int64_t size, int dpad, int nchunks, int metric, int R,
                         int lpn, int cpl, int32_t* adj, hipStream_t st) {
   if (size <= 0) return 0;
-  if (dpad > 128) throw HipError{hipErrorInvalidValue, "kNN build supports d <= 128"};
+  if (dpad > 1024) throw HipError{hipErrorInvalidValue, "kNN build supports d <= 1024"};
   float *mean = nullptr, *norms = nullptr, *sl_d = nullptr;
   int32_t *sl_i = nullptr, *fb_rows = nullptr;
   uint32_t* fb_count = nullptr;
@@ -342,7 +523,9 @@ int64_t build_knn_graph(const float* vec, int64_t size, int dpad, int nchunks, i
   const float nmax = max_norm(norms, size, st);
 
   const int kh = dpad <= 32 ? 16 : dpad <= 64 ? 32 : 64;
-  const size_t lds = sizeof(float) * (2 * (kTileC * (2 * kh + 4) + kTileC) + dpad);
+  const bool wide = dpad > 128;
+  const size_t lds = wide ? sizeof(float) * (4 * kWideC * kSStride + dpad)
+                          : sizeof(float) * (2 * (kTileC * (2 * kh + 4) + kTileC) + dpad);
   const int64_t nb = (size + 127) / 128;
   // Launch in slices of row blocks so that very large layers report progress
   // (HENN_PROGRESS=1) between slices; each slice is a full-width Gram sweep.
@@ -351,7 +534,10 @@ int64_t build_knn_graph(const float* vec, int64_t size, int dpad, int nchunks, i
   auto t_last = std::chrono::steady_clock::now();
   for (int64_t b0 = 0; b0 < nb; b0 += slice) {
     const unsigned nbs = (unsigned)std::min<int64_t>(slice, nb - b0);
-    if (kh <= 16)
+    if (wide)
+      hipLaunchKernelGGL(k_knn_gram_wide, dim3(nbs), dim3(256), lds, st, vec, size, dpad, mean,
+                         norms, metric, sl_d, sl_i, b0);
+    else if (kh <= 16)
       hipLaunchKernelGGL(k_knn_gram<16>, dim3(nbs), dim3(256), lds, st, vec, size, dpad, mean,
                          norms, metric, sl_d, sl_i, b0);
     else if (kh <= 32)

@@ -329,9 +329,13 @@ __device__ bool advance(const SearchArgs& a, const float (&q)[CPL][8], WaveLds s
       const int32_t c = wkey_id(ck);
       ++st.exps;
 
-      // neighbour ids and the visited filter
+      // neighbour ids (and, for FP8 rows, their scales) and the visited filter
       int32_t u = -1;
-      if (lane < L.deg) u = L.adj[(int64_t)c * L.deg + lane];
+      float usc = 1.0f;
+      if (lane < L.deg) {
+        u = L.adj[(int64_t)c * L.deg + lane];
+        if (KIND == kFP8) usc = L.adj_scale[(int64_t)c * L.deg + lane];
+      }
       bool fresh = false;
       uint32_t h = 0;
       if (u >= 0) {
@@ -342,7 +346,12 @@ __device__ bool advance(const SearchArgs& a, const float (&q)[CPL][8], WaveLds s
       if (fresh) s.vis[h] = u;
       const uint64_t fm = ballot(fresh);
       const int cnt = popc64(fm);
-      if (fresh) s.cid[rank_below(fm)] = u;
+      // the scales ride in kstage, which is free until the merge below
+      float* csc = reinterpret_cast<float*>(s.kstage);
+      if (fresh) {
+        s.cid[rank_below(fm)] = u;
+        if (KIND == kFP8) csc[rank_below(fm)] = usc;
+      }
       wave_sync();
       st.evals += cnt;
 
@@ -351,7 +360,7 @@ __device__ bool advance(const SearchArgs& a, const float (&q)[CPL][8], WaveLds s
         const int ci = base + g;
         const bool valid = ci < cnt;
         const int32_t id = valid ? s.cid[ci] : 0;
-        const float sc = (KIND == kFP8 && valid) ? L.scale[id] : 1.0f;
+        const float sc = (KIND == kFP8 && valid) ? csc[ci] : 1.0f;
         const char* row = static_cast<const char*>(L.vec) + (int64_t)id * L.row_bytes;
         const float dist =
             group_distance<KIND, LPN, CPL>(q, row, sc, t, a.nchunks, a.metric, valid);

@@ -345,6 +345,7 @@ henn_status henn_server_tick(henn_server* s, int32_t* n_active_out) {
       sl.vec = idx->storage == HENN_F32 ? (const void*)L.vec32 : (const void*)L.vecq;
       sl.scale = L.scale;
       sl.adj = L.adj;
+      sl.adj_scale = L.adj_scale;
       sl.down = L.down;
       sl.size = (int32_t)L.size;
       sl.deg = L.deg;

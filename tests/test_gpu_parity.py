@@ -246,7 +246,8 @@ def test_end_to_end_cfg1(hn, ho, cfg1):
     idx.free()
 
 
-@pytest.mark.parametrize("n,d,metric", [(20000, 128, 0), (6000, 96, 0), (5000, 64, 1)])
+@pytest.mark.parametrize("n,d,metric", [(20000, 128, 0), (6000, 96, 0), (5000, 64, 1),
+                                         (5000, 200, 0), (4000, 768, 1), (3000, 136, 1)])
 def test_build_graph_matches_oracle_rows_larger(hn, ho, n, d, metric):
     """Several MFMA row blocks and a ragged tail: sampled layer-0 rows against
     the oracle's exact kNN rows (order may differ only at near ties)."""
@@ -266,6 +267,29 @@ def test_build_graph_matches_oracle_rows_larger(hn, ho, n, d, metric):
             assert set(adj[r].tolist()) == set(oadj[j].tolist())
     info = idx.layer_info(0)
     print(f"fallback rows {info['fallback_rows']}")
+    idx.free()
+
+
+@pytest.mark.parametrize("d,metric", [(200, 0), (768, 1)])
+def test_wide_rows_end_to_end(hn, ho, d, metric):
+    """Rows wider than 128 coordinates (K-sliced Gram build, 16-lane gathers):
+    the GPU hierarchy searched by the oracle and by the kernel agree."""
+    if metric == 0:
+        X = wl.gauss_mix(3000, d, 10, 0.3, 41)
+        Q = wl.gauss_mix(200, d, 10, 0.3, 42)
+    else:
+        # unit vectors with a power-law spectrum (the retrieval workload's
+        # distribution); normalised tight clusters would put most traces
+        # through a near tie of the inner products
+        X = wl.spectral(3000, d, 41)
+        Q = wl.spectral(200, d, 42)
+    idx = hn.henn_build(to_dev(X), degree=16, metric=metric)
+    layers = _gpu_layers(idx)
+    oidx = ho.index_from_arrays(X, metric, [l[0] for l in layers], [l[1] for l in layers])
+    gi, gd = hn.henn_search_batch(idx, to_dev(Q), k=10, ef=48)
+    _sync()
+    ores = ho.search(oidx, Q, 10, 48)
+    assert_search_parity(gi.cpu().numpy(), gd.cpu().numpy(), ores, X, Q, metric=metric)
     idx.free()
 
 
