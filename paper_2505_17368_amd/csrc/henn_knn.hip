@@ -210,16 +210,17 @@ __global__ __launch_bounds__(256, 2) void k_knn_gram(const float* vec, int64_t s
 // a row block no longer fits in registers.  Same distances, same shortlist
 // and the same folded norm step as k_knn_gram, arranged as a GEMM: a block
 // owns 128 rows (32 per wave) and walks the layer in tiles of kWideC = 128
-// candidates; the K dimension streams through LDS in slices of kSlice = 32
+// candidates; the K dimension streams through LDS in slices of kSlice = 64
 // coordinates (candidate slice and row slice, double buffered, fetched into
 // registers one slice ahead).  Each wave multiplies its 32 rows against the
 // tile's four 32-candidate blocks into four independent accumulators, the
-// two lane halves covering coordinates [0, 16) and [16, 32) of each slice.
+// two lane halves covering the first and second half of each slice.
 // Row values are pre-scaled by -2 (L2) or -1 (IP) when staged; coordinates
 // past dpad are staged as zeros.
 constexpr int kWideC = 128;
-constexpr int kSlice = 32;
+constexpr int kSlice = 64;
 constexpr int kSStride = kSlice + 4;
+constexpr int kF4Row = kSlice / 4;  // float4 per staged row slice = threads per row
 
 __global__ __launch_bounds__(256) void k_knn_gram_wide(const float* vec, int64_t size,
                                                           int dpad, const float* mean,
@@ -250,18 +251,21 @@ __global__ __launch_bounds__(256) void k_knn_gram_wide(const float* vec, int64_t
   if (mean)
     for (int e = threadIdx.x; e < dpad; e += 256) mean_lds[e] = mean[e];
 
-  // thread -> (row, float4 column) of a slice: 8 threads cover one row's 32
-  // coordinates; slot u < 4 stages candidate rows, u >= 4 the block's rows
-  const int lrow = threadIdx.x >> 3, lc4 = threadIdx.x & 7;
+  // thread -> (row, float4 column) of a slice: kF4Row threads cover one
+  // row's kSlice coordinates, 256 / kF4Row rows per pass; the first kPass
+  // slots stage candidate rows, the next kPass the block's rows
+  constexpr int kRowsPerPass = 256 / kF4Row;
+  constexpr int kPass = kWideC / kRowsPerPass;
+  const int lrow = threadIdx.x / kF4Row, lc4 = threadIdx.x % kF4Row;
   const int nsl = (dpad + kSlice - 1) / kSlice;
-  float4 pre[8];
+  float4 pre[2 * kPass];
   auto fetch = [&](int64_t c0, int ks) {
     const int col = ks * kSlice + 4 * lc4;
     const int colc = col < dpad ? col : 0;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int64_t base = u < 4 ? c0 : qbase;
-      const int64_t row = min(base + lrow + 32 * (u & 3), size - 1);
+    for (int u = 0; u < 2 * kPass; ++u) {
+      const int64_t base = u < kPass ? c0 : qbase;
+      const int64_t row = min(base + lrow + kRowsPerPass * (u % kPass), size - 1);
       pre[u] = *reinterpret_cast<const float4*>(vec + row * dpad + colc);
     }
   };
@@ -271,15 +275,15 @@ __global__ __launch_bounds__(256) void k_knn_gram_wide(const float* vec, int64_t
     float4 m = make_float4(0.f, 0.f, 0.f, 0.f);
     if (mean && cvalid) m = *reinterpret_cast<const float4*>(mean_lds + col);
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < 2 * kPass; ++u) {
       float4 v = pre[u];
       v.x -= m.x; v.y -= m.y; v.z -= m.z; v.w -= m.w;
-      if (u >= 4) {
+      if (u >= kPass) {
         v.x *= qscale; v.y *= qscale; v.z *= qscale; v.w *= qscale;
       }
       if (!cvalid) v = make_float4(0.f, 0.f, 0.f, 0.f);
-      *reinterpret_cast<float4*>(buf + (u < 4 ? 0 : kHalf) + (lrow + 32 * (u & 3)) * kSStride +
-                                 4 * lc4) = v;
+      *reinterpret_cast<float4*>(buf + (u < kPass ? 0 : kHalf) +
+                                 (lrow + kRowsPerPass * (u % kPass)) * kSStride + 4 * lc4) = v;
     }
   };
   auto tile_norms = [&](int64_t c0, float* cn) {
@@ -315,15 +319,16 @@ __global__ __launch_bounds__(256) void k_knn_gram_wide(const float* vec, int64_t
       if (more) fetch(nc0, nks);
 
       const float* buf = lds + cur * kBuf;
-      const float4* brow = reinterpret_cast<const float4*>(buf + kHalf +
-                                                           (wave * 32 + qc) * kSStride + 16 * h);
+      const float4* brow = reinterpret_cast<const float4*>(
+          buf + kHalf + (wave * 32 + qc) * kSStride + (kSlice / 2) * h);
 #pragma unroll
-      for (int k4 = 0; k4 < 4; ++k4) {
+      for (int k4 = 0; k4 < kSlice / 8; ++k4) {
         const float4 bv = brow[k4];
         float4 av[4];
 #pragma unroll
         for (int b = 0; b < 4; ++b)
-          av[b] = reinterpret_cast<const float4*>(buf + (32 * b + qc) * kSStride + 16 * h)[k4];
+          av[b] = reinterpret_cast<const float4*>(buf + (32 * b + qc) * kSStride +
+                                                  (kSlice / 2) * h)[k4];
 #pragma unroll
         for (int b = 0; b < 4; ++b)
           acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[b].x, bv.x, acc[b], 0, 0, 0);
