@@ -84,8 +84,11 @@ typedef struct {
 #define HENN_SEARCH_PERSISTENT 2u /* one persistent launch pulling queries from a
                                      device work counter (batched form) */
 #define HENN_SEARCH_NO_ROOT_KERNEL 4u /* scan a complete-graph root inside the search
-                                         kernel instead of the separate tiled scan
-                                         (same results; for tests and tuning) */
+                                         kernel instead of a separate scan (same
+                                         results; for tests and tuning) */
+#define HENN_SEARCH_ROOT_VALU 8u      /* scan a complete-graph root with the tiled
+                                         VALU kernel instead of the matrix-core
+                                         shortlist + exact check (same results) */
 
 typedef struct {
   uint32_t struct_size;   /* = sizeof(henn_search_params) */

@@ -239,7 +239,41 @@ static int sample_layer(henn_index* ix, int i, hipStream_t st, int32_t* local_ou
 static void destroy(henn_index* ix) {
   if (!ix) return;
   for (int i = 0; i < HENN_MAX_LAYERS; ++i) free_layer(ix->L[i]);
+  if (ix->root.dec_owned) (void)hipFree(ix->root.dec);
+  (void)hipFree(ix->root.mean);
+  (void)hipFree(ix->root.norm);
   delete ix;
+}
+
+// Prepares a complete-graph root for the MFMA scan (RootAux): FP32 rows of
+// the stored values, their mean (L2), norms and the bounds the exact check
+// needs.  Roots wider than 128 coordinates keep the canonical scans only.
+static void prepare_root(henn_index* ix, hipStream_t st) {
+  if (!ix->root_complete || ix->dpad > 128) return;
+  const LayerDev& R = ix->L[ix->num_layers - 1];
+  RootAux& r = ix->root;
+  r.size = R.size;
+  if (ix->storage == HENN_F32) {
+    r.dec = R.vec32;
+  } else {
+    r.dec = dalloc<float>(R.size * ix->dpad);
+    r.dec_owned = true;
+    launch_decode_rows(ix->storage, R.vecq, R.scale, R.size, ix->dpad, r.dec, st);
+  }
+  if (ix->metric == HENN_L2) {
+    r.mean = dalloc<float>(ix->dpad);
+    layer_mean(r.dec, R.size, ix->dpad, r.mean, st);
+    std::vector<float> m((size_t)ix->dpad);
+    HENN_HIP(hipMemcpyAsync(m.data(), r.mean, sizeof(float) * ix->dpad, hipMemcpyDeviceToHost,
+                            st));
+    HENN_HIP(hipStreamSynchronize(st));
+    double s2 = 0.0;
+    for (float v : m) s2 += (double)v * v;
+    r.mean_n2 = (float)s2;
+  }
+  r.norm = dalloc<float>(R.size);
+  launch_row_norms(r.dec, r.mean, R.size, ix->dpad, r.norm, st);
+  r.nmax = max_norm(r.norm, R.size, st);
 }
 
 static henn_index* new_index(const float* X, int64_t n, int32_t d, const henn_build_params* p,
@@ -355,6 +389,7 @@ henn_status henn_build(const float* X, int64_t n, int32_t d, const henn_build_pa
     }
     ix->root_complete = p->root_complete_max > 0 && ix->num_layers >= 2;
     for (int i = 0; i < ix->num_layers; ++i) finish_layer(ix, i, st);
+    prepare_root(ix, st);
     *out = ix;
     return unverified ? fail(HENN_W_NOT_VERIFIED, "a layer kept its best unverified attempt")
                       : HENN_OK;
@@ -461,6 +496,7 @@ henn_status henn_import(const float* X, int64_t n, int32_t d, const henn_build_p
       }
       HENN_HIP(hipStreamSynchronize(st));
     }
+    prepare_root(ix, st);
     *out = ix;
     return HENN_OK;
   } catch (const HipError& e) {
@@ -472,17 +508,33 @@ henn_status henn_import(const float* X, int64_t n, int32_t d, const henn_build_p
   }
 }
 
-static bool root_kernel_used(const henn_index* idx, const henn_search_params* sp) {
-  return idx->root_complete && idx->nchunks <= 16 && !(sp->flags & HENN_SEARCH_NO_ROOT_KERNEL);
+// How a complete-graph root is scanned: 0 inside the search kernel (or no
+// complete root), 1 the tiled VALU scan, 2 the MFMA shortlist + exact check.
+// All three give the same keys.
+static int root_mode(const henn_index* idx, const henn_search_params* sp) {
+  if (!idx->root_complete || (sp->flags & HENN_SEARCH_NO_ROOT_KERNEL)) return 0;
+  if (idx->root.size > 0 && !(sp->flags & HENN_SEARCH_ROOT_VALU)) return 2;
+  return idx->nchunks <= 16 ? 1 : 0;
 }
 
+// Scratch layout: 256 B (persistent work counter), then for mode 1 the
+// [splits][nq] root keys, for mode 2 the [nq] root keys and the Gram
+// shortlists (values, then positions).
 static int64_t search_workspace_bytes(const henn_index* idx, int64_t nq,
                                       const henn_search_params* sp) {
-  int64_t b = 256;  // persistent work counter, padded
-  if (root_kernel_used(idx, sp)) {
-    int64_t per = 0;
-    const int splits = root_scan_splits(nq, idx->L[idx->num_layers - 1].size, &per);
-    b += (int64_t)sizeof(uint64_t) * splits * nq;
+  int64_t b = 256;
+  const int64_t rs = idx->L[idx->num_layers - 1].size;
+  int64_t per = 0;
+  switch (root_mode(idx, sp)) {
+    case 1:
+      b += (int64_t)sizeof(uint64_t) * root_scan_splits(nq, rs, &per) * nq;
+      break;
+    case 2:
+      b += (int64_t)sizeof(uint64_t) * nq +
+           (int64_t)root_gram_splits(nq, rs, &per) * nq * 2 * kRootK * 8;
+      break;
+    default:
+      break;
   }
   return b;
 }
@@ -591,7 +643,28 @@ henn_status henn_search_batch(const henn_index* idx, const float* Q, int64_t nq,
     if (sh.persistent && use_ws) a.work_counter = reinterpret_cast<uint32_t*>(ws);
     uint64_t* root_best = nullptr;
     bool root_owned = false;
-    if (root_kernel_used(idx, sp)) {
+    const int rmode = root_mode(idx, sp);
+    if (rmode == 2) {
+      int64_t per = 0;
+      const int splits = root_gram_splits(nq, idx->root.size, &per);
+      const int64_t nsl = (int64_t)splits * nq * 2 * kRootK;
+      if (use_ws) {
+        root_best = reinterpret_cast<uint64_t*>(ws + 256);
+      } else {
+        HENN_HIP(hipMallocAsync((void**)&root_best, sizeof(uint64_t) * nq + 8 * nsl, st));
+        root_owned = true;
+      }
+      float* sl_d = reinterpret_cast<float*>(root_best + nq);
+      int32_t* sl_i = reinterpret_cast<int32_t*>(sl_d + nsl);
+      launch_root_gram(Q, nq, idx->d, idx->root, idx->dpad, idx->metric, splits, per, sl_d, sl_i,
+                       st);
+      if (!launch_root_check(idx->storage, a, idx->root, splits, sl_d, sl_i, root_best, st)) {
+        if (root_owned) (void)hipFreeAsync(root_best, st);
+        return fail(HENN_E_UNSUPPORTED, "no root check kernel for this shape");
+      }
+      a.root_best = root_best;
+      a.root_splits = 1;
+    } else if (rmode == 1) {
       int64_t per = 0;
       const int splits = root_scan_splits(nq, idx->L[idx->num_layers - 1].size, &per);
       if (use_ws) {

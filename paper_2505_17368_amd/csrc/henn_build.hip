@@ -509,6 +509,26 @@ __global__ void k_quantize_fp8(const float* vec, int64_t size, int dpad, uint8_t
   for (int j = lane; j < dpad; j += 64) out[row * dpad + j] = (uint8_t)f32_to_e4m3_rne(x[j] / sc);
 }
 
+__global__ void k_decode_rows(int storage, const void* vq, const float* scale, int64_t size,
+                              int dpad, float* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= size * dpad) return;
+  if (storage == kBF16) {
+    out[i] = bf16_to_f32(static_cast<const uint16_t*>(vq)[i]);
+  } else {
+    out[i] = scale[i / dpad] * fp8_to_f32(static_cast<const uint8_t*>(vq)[i]);
+  }
+}
+
+void launch_decode_rows(int storage, const void* vq, const float* scale, int64_t size, int dpad,
+                        float* out, hipStream_t st) {
+  const int64_t n = size * dpad;
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_decode_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, storage,
+                     vq, scale, size, dpad, out);
+  HENN_HIP(hipGetLastError());
+}
+
 __global__ void k_adj_scale(const int32_t* adj, int64_t n, const float* scale, float* out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;

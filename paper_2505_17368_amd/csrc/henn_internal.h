@@ -42,6 +42,22 @@ struct LayerDev {
 }  // namespace henn
 
 namespace henn {
+// A complete-graph root prepared for the MFMA scan (dpad <= 128):
+//   dec:  FP32 [size][dpad], the values the search form stores (the FP32
+//         rows themselves, decoded BF16, or scale * decoded FP8);
+//   mean: [dpad] mean of dec (L2 only, else nullptr);
+//   norm: [size] |dec - mean|^2 (L2) or |dec|^2 (IP);
+//   nmax: max of norm; mean_n2: |mean|^2.
+struct RootAux {
+  int64_t size = 0;
+  float* dec = nullptr;
+  bool dec_owned = false;
+  float* mean = nullptr;
+  float* norm = nullptr;
+  float nmax = 0.0f, mean_n2 = 0.0f;
+};
+constexpr int kRootK = 8;  // Gram shortlist per (root split, query, lane half)
+
 // One autotuned launch shape, valid for a (storage, beam bucket, k bucket).
 struct TuneEntry {
   int storage, ef_bucket, k_bucket;
@@ -57,6 +73,7 @@ struct henn_index {
   int32_t num_layers = 0;
   bool root_complete = false;  // root searched by exhaustive scan (complete graph)
   henn::LayerDev L[HENN_MAX_LAYERS];
+  henn::RootAux root;  // prepared when root_complete and dpad <= 128
   int device = 0;
   std::mutex tune_mu;
   std::vector<henn::TuneEntry> tune;  // autotuned launch shapes
@@ -171,6 +188,18 @@ int root_scan_splits(int64_t nq, int64_t root_size, int64_t* rows_per_split);
 bool launch_root_scan(int storage, const SearchArgs& a, int splits, int64_t rows_per_split,
                       uint64_t* out, hipStream_t st);
 
+// The same scan on matrix cores: a Gram shortlist of kRootK per (split,
+// query, lane half) over the prepared root (launch_root_gram), then per
+// query the exact canonical distances of the rows that can still be the
+// nearest given the Gram error bound, or a full canonical scan when the
+// shortlist cannot prove it (launch_root_check); writes [nq] best keys.
+int root_gram_splits(int64_t nq, int64_t root_size, int64_t* rows_per_split);
+void launch_root_gram(const float* Q, int64_t nq, int d, const RootAux& r, int dpad, int metric,
+                      int splits, int64_t rows_per_split, float* sl_d, int32_t* sl_i,
+                      hipStream_t st);
+bool launch_root_check(int storage, const SearchArgs& a, const RootAux& r, int splits,
+                       const float* sl_d, const int32_t* sl_i, uint64_t* out, hipStream_t st);
+
 // ---- build ----------------------------------------------------------------
 void launch_copy_rows(const float* src, int64_t src_stride, const int32_t* ids, int64_t count,
                       int d, float* dst, int dpad, hipStream_t st);
@@ -194,6 +223,9 @@ void launch_row_norms(const float* vec, const float* mean, int64_t size, int dpa
 float max_norm(const float* norms, int64_t size, hipStream_t st);
 void launch_quantize(int storage, const float* vec, int64_t size, int dpad, void* out,
                      float* scale, hipStream_t st);
+// FP32 rows of the stored values: decoded BF16, or scale * decoded FP8.
+void launch_decode_rows(int storage, const void* vq, const float* scale, int64_t size, int dpad,
+                        float* out, hipStream_t st);
 // out[i] = scale[adj[i]] for the n entries of an adjacency array (0 for -1).
 void launch_adj_scale(const int32_t* adj, int64_t n, const float* scale, float* out,
                       hipStream_t st);

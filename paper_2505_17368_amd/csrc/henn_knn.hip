@@ -3,7 +3,7 @@
 // (distance, id) order.
 //
 // Three steps:
-//  1. k_knn_gram / k_knn_gram_wide (MFMA): all-pairs Gram tiles on FP32
+//  1. k_gram_topk / k_knn_gram_wide (MFMA): all-pairs Gram tiles on FP32
 //     matrix cores (the wide form streams K in slices for d > 128).  A
 //     workgroup owns 128 rows (4 waves x 32); candidate tiles of 32 rows are
 //     staged in LDS and multiplied with v_mfma_f32_32x32x2f32, the K split
@@ -35,25 +35,32 @@ constexpr int kTileC = 32;  // candidates per LDS tile
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-// Shortlist pass of the layer's kNN graph (Alg. 1 builds one graph per
-// layer).  A block takes 128 rows (one 32-row MFMA column block per wave)
-// and streams every row of the layer through LDS in tiles of kTileC.
-// The distance is assembled inside the contraction: with y = centred
-// candidate and x = centred row,
+// Gram shortlist pass (d <= 128), used for two contractions:
+//  * the layer's kNN graph (Alg. 1 builds one graph per layer): queries and
+//    candidates are the layer's rows, a row never lists itself, KS = 32;
+//  * the exhaustive scan of a complete-graph root (Alg. 4 query on the root):
+//    queries are the search batch, candidates the root rows, KS = 8, the
+//    root split over blockIdx.y.
+// A block takes 128 queries (one 32-row MFMA column block per wave) and
+// streams its candidate range through LDS in tiles of kTileC.  The distance
+// is assembled inside the contraction: with y = centred candidate and
+// x = centred query,
 //   |y - x|^2 = sum_k y_k (-2 x_k) + (|y|^2 + pen) * 1 + 1 * |x|^2
 //   -<y, x>   = sum_k y_k (-x_k)  +  pen * 1         + 0 * 0
 // the last two products being one extra MFMA step over the two lane
-// halves; pen = +inf marks rows past the end of the layer.  Rows are taken
-// as zero-padded to 2 * KH coordinates (dpad <= 2 * KH); the K dimension
-// splits at KH between the lane halves, so each tile is a fixed,
-// branch-free chain of KH + 1 MFMAs and the epilogue is one compare per
-// value, with an insertion into the lane's sorted top-kShort only when the
-// value beats the current kShort-th.
-template <int KH>
-__global__ __launch_bounds__(256, 2) void k_knn_gram(const float* vec, int64_t size, int dpad,
-                                                  const float* mean, const float* norms,
-                                                  int metric, float* sl_d, int32_t* sl_i,
-                                                  int64_t block0) {
+// halves; pen = +inf marks rows past the end of the range (the |x|^2 term
+// is dropped when qnorms is null: it does not change a query's order).
+// Rows are taken as zero-padded to 2 * KH coordinates (dpad <= 2 * KH); the
+// K dimension splits at KH between the lane halves, so each tile is a
+// fixed, branch-free chain of KH + 1 MFMAs and the epilogue is one compare
+// per value, with an insertion into the lane's sorted top-KS only when the
+// value beats the current KS-th.  Output: per (split, query, lane half) the
+// KS smallest (value, candidate index) pairs, ascending.
+template <int KH, int KS, bool SELF>
+__global__ __launch_bounds__(256, 2) void k_gram_topk(
+    const float* qsrc, int64_t nq, int qstride, int qd, const float* qnorms, const float* cand,
+    int64_t csize, int64_t rows_per_split, int dpad, const float* cnorms, const float* mean,
+    int metric, float* sl_d, int32_t* sl_i, int64_t block0) {
   // two LDS buffers of [kTileC][2 * KH + 4] candidates + their norms; the
   // next tile is fetched into registers while the current one is multiplied
   extern __shared__ __align__(16) float tile[];
@@ -62,7 +69,11 @@ __global__ __launch_bounds__(256, 2) void k_knn_gram(const float* vec, int64_t s
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int qc = lane & 31, h = lane >> 5;
   const int64_t qrow = (block0 + blockIdx.x) * 128 + wave * 32 + qc;
-  const bool qvalid = qrow < size;
+  const bool qvalid = qrow < nq;
+  // candidate range: the whole matrix for the kNN graph, the blockIdx.y
+  // split for the root scan
+  const int64_t cb = SELF ? 0 : (int64_t)blockIdx.y * rows_per_split;
+  const int64_t ce = SELF ? csize : min(cb + rows_per_split, csize);
   const bool l2 = metric == 0;
   const float qscale = l2 ? -2.0f : -1.0f;
 
@@ -70,17 +81,18 @@ __global__ __launch_bounds__(256, 2) void k_knn_gram(const float* vec, int64_t s
 #pragma unroll
   for (int kk = 0; kk < KH; ++kk) {
     const int e = h * KH + kk;
-    bq[kk] = (qvalid && e < dpad) ? qscale * (vec[qrow * dpad + e] - (mean ? mean[e] : 0.0f))
-                                  : 0.0f;
+    bq[kk] = (qvalid && e < qd)
+                 ? qscale * (qsrc[qrow * qstride + e] - (mean ? mean[e] : 0.0f))
+                 : 0.0f;
   }
   // B operand of the extra step: row 0 is all ones, row 1 holds |x|^2 (L2)
-  const float b_extra = h == 0 ? 1.0f : (l2 && qvalid ? norms[qrow] : 0.0f);
+  const float b_extra = h == 0 ? 1.0f : (l2 && qnorms && qvalid ? qnorms[qrow] : 0.0f);
   const float a_one = l2 ? 1.0f : 0.0f;
 
-  float td[kShort];
-  int32_t ti[kShort];
+  float td[KS];
+  int32_t ti[KS];
 #pragma unroll
-  for (int j = 0; j < kShort; ++j) {
+  for (int j = 0; j < KS; ++j) {
     td[j] = INFINITY;
     ti[j] = -1;
   }
@@ -97,57 +109,65 @@ __global__ __launch_bounds__(256, 2) void k_knn_gram(const float* vec, int64_t s
   // a tile is kTileC * dpad / 4 <= 16 * KH float4, so each of the 256
   // threads moves at most KH / 16 of them.  Loads are clamped to valid rows
   // so that they issue without branches and complete while the previous
-  // tile is multiplied; the layer mean is subtracted when the tile is
-  // written to LDS.
+  // tile is multiplied; the mean is subtracted when the tile is written to
+  // LDS.
   constexpr int kMaxF4 = KH / 16;
   const int f4_per_row = dpad >> 2;
   const int tile_f4 = kTileC * f4_per_row;
   float* mean_lds = tile + 2 * kBuf;
   if (mean)
     for (int e = threadIdx.x; e < dpad; e += 256) mean_lds[e] = mean[e];
-  int src_off[kMaxF4], dst_off[kMaxF4], src_row[kMaxF4];
+  int src_row[kMaxF4], src_c4[kMaxF4];
 #pragma unroll
   for (int u = 0; u < kMaxF4; ++u) {
     const int idx = min((int)threadIdx.x + u * 256, tile_f4 - 1);
-    const int r = idx / f4_per_row, c4 = idx - r * f4_per_row;
-    src_row[u] = r;
-    src_off[u] = c4;
-    dst_off[u] = (int)threadIdx.x + u * 256 < tile_f4 ? r * kStride + 4 * c4 : -1;
+    src_row[u] = idx / f4_per_row;
+    src_c4[u] = idx - src_row[u] * f4_per_row;
   }
+  // fetch only issues loads (their values are first used by stash, after
+  // the tile in flight has been multiplied); stash applies the selects
   float4 pre[kMaxF4];
   float pnorm = 0.0f;
+  int plast = 0;
   auto fetch = [&](int64_t c0) {
+    const int64_t rem = ce - 1 - c0;
+    const int last = rem < kTileC - 1 ? (int)rem : kTileC - 1;  // last valid row of the tile
+    const float* base = cand + c0 * dpad;
 #pragma unroll
     for (int u = 0; u < kMaxF4; ++u) {
-      const int64_t row = min(c0 + src_row[u], size - 1);
-      pre[u] = reinterpret_cast<const float4*>(vec + row * dpad)[src_off[u]];
+      const int r = src_row[u] < last ? src_row[u] : last;
+      pre[u] = reinterpret_cast<const float4*>(base + r * dpad)[src_c4[u]];
     }
-    const int64_t nrow = c0 + (threadIdx.x & (kTileC - 1));
-    const float nv = norms[min(nrow, size - 1)];
-    pnorm = nrow < size ? (l2 ? nv : 0.0f) : INFINITY;
+    const int r = (int)(threadIdx.x & (kTileC - 1));
+    pnorm = cnorms[c0 + (r < last ? r : last)];
+    plast = last;
   };
   auto stash = [&](float* buf) {
 #pragma unroll
     for (int u = 0; u < kMaxF4; ++u) {
-      if (dst_off[u] >= 0) {
+      if ((int)threadIdx.x + u * 256 < tile_f4) {
         float4 v = pre[u];
         if (mean) {
-          const float4 m = reinterpret_cast<const float4*>(mean_lds)[src_off[u]];
+          const float4 m = reinterpret_cast<const float4*>(mean_lds)[src_c4[u]];
           v.x -= m.x; v.y -= m.y; v.z -= m.z; v.w -= m.w;
         }
-        *reinterpret_cast<float4*>(buf + dst_off[u]) = v;
+        *reinterpret_cast<float4*>(buf + src_row[u] * kStride + 4 * src_c4[u]) = v;
       }
     }
-    if (threadIdx.x < kTileC) buf[kTileC * kStride + threadIdx.x] = pnorm;
+    if (threadIdx.x < kTileC)
+      buf[kTileC * kStride + threadIdx.x] =
+          (int)threadIdx.x <= plast ? (l2 ? pnorm : 0.0f) : INFINITY;
   };
 
   __syncthreads();
-  fetch(0);
-  stash(tile);
+  if (cb < ce) {
+    fetch(cb);
+    stash(tile);
+  }
   __syncthreads();
   int cur = 0;
-  for (int64_t c0 = 0; c0 < size; c0 += kTileC) {
-    const bool more = c0 + kTileC < size;
+  for (int64_t c0 = cb; c0 < ce; c0 += kTileC) {
+    const bool more = c0 + kTileC < ce;
     if (more) fetch(c0 + kTileC);
     const float* buf = tile + cur * kBuf;
 
@@ -168,18 +188,18 @@ __global__ __launch_bounds__(256, 2) void k_knn_gram(const float* vec, int64_t s
 
     bool any = false;
 #pragma unroll
-    for (int v = 0; v < 16; ++v) any |= acc[v] < td[kShort - 1];
+    for (int v = 0; v < 16; ++v) any |= acc[v] < td[KS - 1];
     if (__builtin_amdgcn_ballot_w64(any)) {
       // lanes without a hit push +inf through the network, which leaves
       // their list unchanged, so the network runs without divergence
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const int64_t crow = c0 + 8 * (v >> 2) + 4 * h + (v & 3);
-        float nd = crow != qrow ? acc[v] : INFINITY;
-        if (__builtin_amdgcn_ballot_w64(nd < td[kShort - 1])) {
+        float nd = (SELF && crow == qrow) ? INFINITY : acc[v];
+        if (__builtin_amdgcn_ballot_w64(nd < td[KS - 1])) {
           int32_t ni = (int32_t)crow;
 #pragma unroll
-          for (int j = 0; j < kShort; ++j) {
+          for (int j = 0; j < KS; ++j) {
             const bool sw = nd < td[j];
             const float od = td[j];
             const int32_t oi = ti[j];
@@ -196,19 +216,18 @@ __global__ __launch_bounds__(256, 2) void k_knn_gram(const float* vec, int64_t s
     cur ^= 1;
   }
   if (qvalid) {
-    float* od = sl_d + qrow * (2 * kShort) + h * kShort;
-    int32_t* oi = sl_i + qrow * (2 * kShort) + h * kShort;
+    const int64_t o = ((int64_t)blockIdx.y * nq + qrow) * (2 * KS) + h * KS;
 #pragma unroll
-    for (int j = 0; j < kShort; ++j) {
-      od[j] = td[j];
-      oi[j] = ti[j];
+    for (int j = 0; j < KS; ++j) {
+      sl_d[o + j] = td[j];
+      sl_i[o + j] = ti[j];
     }
   }
 }
 
 // Shortlist pass for rows wider than 128 coordinates (up to 1024), where
 // a row block no longer fits in registers.  Same distances, same shortlist
-// and the same folded norm step as k_knn_gram, arranged as a GEMM: a block
+// and the same folded norm step as k_gram_topk, arranged as a GEMM: a block
 // owns 128 rows (32 per wave) and walks the layer in tiles of kWideC = 128
 // candidates; the K dimension streams through LDS in slices of kSlice = 64
 // coordinates (candidate slice and row slice, double buffered, fetched into
@@ -507,6 +526,38 @@ __global__ __launch_bounds__(256) void k_knn_exact(const float* vec, int64_t siz
   X(1, 1) X(2, 1) X(4, 1) X(2, 2) X(4, 2) X(8, 1) X(2, 4) X(4, 4) X(8, 2) X(16, 1) X(8, 4) \
   X(16, 2) X(4, 8) X(16, 4) X(16, 8)
 
+int root_gram_splits(int64_t nq, int64_t root_size, int64_t* rows_per_split) {
+  // about 1,024 workgroups (two waves of 512 resident), at least 8 tiles each
+  const int64_t qblocks = (nq + 127) / 128;
+  int64_t splits = (1024 + qblocks - 1) / qblocks;
+  const int64_t max_splits = std::max<int64_t>(1, root_size / (8 * kTileC));
+  splits = std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(splits, max_splits), 64));
+  int64_t per = (root_size + splits - 1) / splits;
+  per = (per + kTileC - 1) / kTileC * kTileC;
+  *rows_per_split = per;
+  return (int)((root_size + per - 1) / per);
+}
+
+void launch_root_gram(const float* Q, int64_t nq, int d, const RootAux& r, int dpad, int metric,
+                      int splits, int64_t rows_per_split, float* sl_d, int32_t* sl_i,
+                      hipStream_t st) {
+  const int kh = dpad <= 32 ? 16 : dpad <= 64 ? 32 : 64;
+  const size_t lds = sizeof(float) * (2 * (kTileC * (2 * kh + 4) + kTileC) + dpad);
+  const dim3 grid((unsigned)((nq + 127) / 128), (unsigned)splits);
+#define HENN_RG(KH)                                                                            \
+  hipLaunchKernelGGL((k_gram_topk<KH, kRootK, false>), grid, dim3(256), lds, st, Q, nq, d, d,  \
+                     (const float*)nullptr, r.dec, r.size, rows_per_split, dpad, r.norm, r.mean, \
+                     metric, sl_d, sl_i, (int64_t)0)
+  if (kh == 16)
+    HENN_RG(16);
+  else if (kh == 32)
+    HENN_RG(32);
+  else
+    HENN_RG(64);
+#undef HENN_RG
+  HENN_HIP(hipGetLastError());
+}
+
 int64_t build_knn_graph(const float* vec, int64_t size, int dpad, int nchunks, int metric, int R,
                         int lpn, int cpl, int32_t* adj, hipStream_t st) {
   if (size <= 0) return 0;
@@ -543,14 +594,17 @@ int64_t build_knn_graph(const float* vec, int64_t size, int dpad, int nchunks, i
       hipLaunchKernelGGL(k_knn_gram_wide, dim3(nbs), dim3(256), lds, st, vec, size, dpad, mean,
                          norms, metric, sl_d, sl_i, b0);
     else if (kh <= 16)
-      hipLaunchKernelGGL(k_knn_gram<16>, dim3(nbs), dim3(256), lds, st, vec, size, dpad, mean,
-                         norms, metric, sl_d, sl_i, b0);
+      hipLaunchKernelGGL((k_gram_topk<16, kShort, true>), dim3(nbs), dim3(256), lds, st, vec,
+                         size, dpad, dpad, norms, vec, size, size, dpad, norms, mean, metric, sl_d,
+                         sl_i, b0);
     else if (kh <= 32)
-      hipLaunchKernelGGL(k_knn_gram<32>, dim3(nbs), dim3(256), lds, st, vec, size, dpad, mean,
-                         norms, metric, sl_d, sl_i, b0);
+      hipLaunchKernelGGL((k_gram_topk<32, kShort, true>), dim3(nbs), dim3(256), lds, st, vec,
+                         size, dpad, dpad, norms, vec, size, size, dpad, norms, mean, metric, sl_d,
+                         sl_i, b0);
     else
-      hipLaunchKernelGGL(k_knn_gram<64>, dim3(nbs), dim3(256), lds, st, vec, size, dpad, mean,
-                         norms, metric, sl_d, sl_i, b0);
+      hipLaunchKernelGGL((k_gram_topk<64, kShort, true>), dim3(nbs), dim3(256), lds, st, vec,
+                         size, dpad, dpad, norms, vec, size, size, dpad, norms, mean, metric, sl_d,
+                         sl_i, b0);
     HENN_HIP(hipGetLastError());
     if (progress && b0 + (int64_t)nbs < nb) {
       HENN_HIP(hipStreamSynchronize(st));

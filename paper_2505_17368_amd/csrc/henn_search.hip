@@ -203,6 +203,134 @@ bool launch_root_scan(int storage, const SearchArgs& a, int splits, int64_t rows
   }
 }
 
+// Exhaustive canonical scan of a complete-graph root by one wave (two rows
+// per lane group in flight); every lane returns the best (distance,
+// position) key.
+template <int KIND, int LPN, int CPL>
+__device__ uint64_t root_scan_wave(const SearchArgs& a, const SearchLayer& R,
+                                   const float (&q)[CPL][8]) {
+  constexpr int G = 64 / LPN;
+  const int lane = lane_id(), t = lane % LPN, g = lane / LPN;
+  uint64_t best = ~0ull;
+  for (int base = 0; base < R.size; base += 2 * G) {
+    const int c0 = base + g, c1 = base + G + g;
+    const bool v0 = c0 < R.size, v1 = c1 < R.size;
+    const float s0 = (KIND == kFP8 && v0) ? R.scale[c0] : 1.0f;
+    const float s1 = (KIND == kFP8 && v1) ? R.scale[c1] : 1.0f;
+    const char* r0 = static_cast<const char*>(R.vec) + (int64_t)(v0 ? c0 : 0) * R.row_bytes;
+    const char* r1 = static_cast<const char*>(R.vec) + (int64_t)(v1 ? c1 : 0) * R.row_bytes;
+    const float d0 = group_distance<KIND, LPN, CPL>(q, r0, s0, t, a.nchunks, a.metric, v0);
+    const float d1 = group_distance<KIND, LPN, CPL>(q, r1, s1, t, a.nchunks, a.metric, v1);
+    if (v0) {
+      const uint64_t k0 = wkey(d0, c0);
+      best = k0 < best ? k0 : best;
+    }
+    if (v1) {
+      const uint64_t k1 = wkey(d1, c1);
+      best = k1 < best ? k1 : best;
+    }
+  }
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    const uint64_t o = shfl_xor_u64(best, m);
+    best = o < best ? o : best;
+  }
+  return best;
+}
+
+// Exact check after the MFMA root shortlist (one wave per query).  With
+// a(y) the Gram value of root row y (computed on the stored values, the
+// query-norm term dropped) and c(y) the canonical distance, both are within
+// an absolute bound of the exact distance that scales with
+// N = |q - mean|^2 + max_y |y - mean|^2 + |mean|^2 (L2; uncentred for IP):
+// |a - e| <= 4 (dpad + 8) 2^-24 N and |c - e| <= (10 + log2 chunks) 2^-23 N.
+// A row whose Gram value exceeds a_min + M, M = 32 (dpad + 16) 2^-24 N
+// (above twice the sum of both bounds), has c(y) > c(argmin_a), so the
+// nearest root member under (distance, position) is among the shortlisted
+// rows with a <= a_min + M -- provided every row left out of the
+// shortlists has a > a_min + M, i.e. the smallest cut-off (the kRootK-th
+// value of each list) exceeds it.  Otherwise the wave scans the root.
+template <int KIND, int LPN, int CPL>
+__global__ __launch_bounds__(256) void k_root_check(SearchArgs a, RootAux r, int splits,
+                                                    const float* sl_d, const int32_t* sl_i,
+                                                    uint64_t* out) {
+  constexpr int G = 64 / LPN;
+  const int lane = lane_id(), t = lane % LPN, g = lane / LPN;
+  const int64_t qi = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (qi >= a.nq) return;  // whole wave
+  const SearchLayer& R = a.layer[a.num_layers - 1];
+  float q[CPL][8];
+  load_query<CPL>(a.Q + qi * a.d, a.d, t, q);
+  // |q - mean|^2 (L2) or |q|^2 (IP): this lane's chunks, summed over the group
+  float qn = 0.0f;
+#pragma unroll
+  for (int i = 0; i < CPL; ++i)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int e = (t * CPL + i) * 8 + j;
+      const float v = q[i][j] - ((r.mean && e < a.dpad) ? r.mean[e] : 0.0f);
+      qn += v * v;
+    }
+  qn = group_sum<LPN>(qn);
+  const float N = qn + r.nmax + r.mean_n2;
+  const float M = 32.0f * (float)(a.dpad + 16) * 0x1p-24f * N;
+
+  const int nl = 2 * splits;  // lists of kRootK ascending values
+  float amin = INFINITY, cut = INFINITY;
+  for (int l = lane; l < nl; l += 64) {
+    const int64_t o = (((int64_t)(l >> 1) * a.nq + qi) * 2 + (l & 1)) * kRootK;
+    amin = fminf(amin, sl_d[o]);
+    cut = fminf(cut, sl_d[o + kRootK - 1]);
+  }
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    amin = fminf(amin, __shfl_xor(amin, m));
+    cut = fminf(cut, __shfl_xor(cut, m));
+  }
+  const float T = amin + M;
+  __shared__ int32_t rows_all[4][64];
+  int32_t* rows = rows_all[threadIdx.x >> 6];
+  uint64_t best = ~0ull;
+  if (!(cut > T)) {
+    best = root_scan_wave<KIND, LPN, CPL>(a, R, q);
+  } else {
+    const int n = nl * kRootK;
+    for (int base = 0; base < n; base += 64) {
+      // compact this chunk's entries with a <= T, then G rows per pass
+      const int e = base + lane;
+      int32_t pos = -1;
+      if (e < n) {
+        const int l = e / kRootK, j = e % kRootK;
+        const int64_t o = (((int64_t)(l >> 1) * a.nq + qi) * 2 + (l & 1)) * kRootK + j;
+        if (sl_d[o] <= T) pos = sl_i[o];
+      }
+      const uint64_t m = ballot(pos >= 0);
+      const int cnt = popc64(m);
+      if (cnt == 0) continue;
+      wave_sync();
+      if (pos >= 0) rows[rank_below(m)] = pos;
+      wave_sync();
+      for (int b = 0; b < cnt; b += G) {
+        const int32_t row = b + g < cnt ? rows[b + g] : -1;
+        const bool valid = row >= 0;
+        const float sc = (KIND == kFP8 && valid) ? R.scale[row] : 1.0f;
+        const char* rp = static_cast<const char*>(R.vec) + (int64_t)(valid ? row : 0) * R.row_bytes;
+        const float dist = group_distance<KIND, LPN, CPL>(q, rp, sc, t, a.nchunks, a.metric, valid);
+        if (valid) {
+          const uint64_t k = wkey(dist, row);
+          best = k < best ? k : best;
+        }
+      }
+    }
+#pragma unroll
+    for (int m2 = 32; m2 >= 1; m2 >>= 1) {
+      const uint64_t o = shfl_xor_u64(best, m2);
+      best = o < best ? o : best;
+    }
+  }
+  if (lane == 0) out[qi] = best;
+}
+
 // Loads this query's k and beam width and finds the entry of the first
 // searched layer: the root's smallest id, or the exact root nearest when the
 // root carries the complete graph (from k_root_scan's keys when given).
@@ -233,33 +361,9 @@ __device__ void start_query(const SearchArgs& a, int64_t qi, const float (&q)[CP
     st.cur_d = wkey_dist(best);
     st.li = top - 1;
   } else if (a.root_complete && top >= 1) {
-    // complete graph on the root: exhaustive scan for its nearest member,
-    // two rows per group in flight
+    // complete graph on the root: exhaustive scan for its nearest member
     const SearchLayer& R = a.layer[top];
-    uint64_t best = ~0ull;
-    for (int base = 0; base < R.size; base += 2 * G) {
-      const int c0 = base + g, c1 = base + G + g;
-      const bool v0 = c0 < R.size, v1 = c1 < R.size;
-      const float s0 = (KIND == kFP8 && v0) ? R.scale[c0] : 1.0f;
-      const float s1 = (KIND == kFP8 && v1) ? R.scale[c1] : 1.0f;
-      const char* r0 = static_cast<const char*>(R.vec) + (int64_t)(v0 ? c0 : 0) * R.row_bytes;
-      const char* r1 = static_cast<const char*>(R.vec) + (int64_t)(v1 ? c1 : 0) * R.row_bytes;
-      const float d0 = group_distance<KIND, LPN, CPL>(q, r0, s0, t, a.nchunks, a.metric, v0);
-      const float d1 = group_distance<KIND, LPN, CPL>(q, r1, s1, t, a.nchunks, a.metric, v1);
-      if (v0) {
-        const uint64_t k0 = wkey(d0, c0);
-        best = k0 < best ? k0 : best;
-      }
-      if (v1) {
-        const uint64_t k1 = wkey(d1, c1);
-        best = k1 < best ? k1 : best;
-      }
-    }
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) {
-      const uint64_t o = shfl_xor_u64(best, m);
-      best = o < best ? o : best;
-    }
+    const uint64_t best = root_scan_wave<KIND, LPN, CPL>(a, R, q);
     st.evals = R.size;
     st.cur = R.down[wkey_id(best)];
     st.cur_d = wkey_dist(best);
@@ -680,6 +784,36 @@ void launch_serve_admit(const float* staged_q, const int32_t* meta, int n_new, i
   if (n_new <= 0) return;
   hipLaunchKernelGGL(k_serve_admit, dim3(n_new), dim3(64), 0, st, staged_q, meta, n_new, d,
                      slot_q, slot_k, slot_ef, state_off, cap, states);
+}
+
+template <int KIND>
+static bool launch_root_check_kind(const SearchArgs& a, const RootAux& r, int splits,
+                                   const float* sl_d, const int32_t* sl_i, uint64_t* out,
+                                   hipStream_t st) {
+  int lpn = 0, cpl = 0;
+  pick_lanes(a.nchunks, 0, &lpn, &cpl);
+  const dim3 grid((unsigned)((a.nq + 3) / 4));
+#define HENN_TRY(L, C)                                                                       \
+  if (lpn == L && cpl == C) {                                                                \
+    hipLaunchKernelGGL((k_root_check<KIND, L, C>), grid, dim3(256), 0, st, a, r, splits, sl_d, \
+                       sl_i, out);                                                           \
+    return true;                                                                             \
+  }
+  HENN_TRY(1, 1) HENN_TRY(2, 1) HENN_TRY(4, 1) HENN_TRY(2, 2) HENN_TRY(4, 2) HENN_TRY(8, 1)
+  HENN_TRY(2, 4) HENN_TRY(4, 4) HENN_TRY(8, 2) HENN_TRY(16, 1)
+#undef HENN_TRY
+  return false;
+}
+
+bool launch_root_check(int storage, const SearchArgs& a, const RootAux& r, int splits,
+                       const float* sl_d, const int32_t* sl_i, uint64_t* out, hipStream_t st) {
+  if (a.nq <= 0) return true;
+  switch (storage) {
+    case kF32: return launch_root_check_kind<kF32>(a, r, splits, sl_d, sl_i, out, st);
+    case kBF16: return launch_root_check_kind<kBF16>(a, r, splits, sl_d, sl_i, out, st);
+    case kFP8: return launch_root_check_kind<kFP8>(a, r, splits, sl_d, sl_i, out, st);
+    default: return false;
+  }
 }
 
 void pick_lanes(int nchunks, int requested_lpn, int* lpn, int* cpl) {

@@ -24,6 +24,7 @@ HENN_L2, HENN_IP = 0, 1
 HENN_F32, HENN_BF16, HENN_FP8_E4M3 = 0, 1, 2
 HENN_GRAPH_KNN, HENN_GRAPH_KNN_SYM = 0, 1
 HENN_SEARCH_COUNTERS, HENN_SEARCH_PERSISTENT, HENN_SEARCH_NO_ROOT_KERNEL = 1, 2, 4
+HENN_SEARCH_ROOT_VALU = 8
 STORAGE = {"f32": HENN_F32, "bf16": HENN_BF16, "fp8": HENN_FP8_E4M3}
 METRIC = {"l2": HENN_L2, "ip": HENN_IP}
 
@@ -288,9 +289,14 @@ def search_params(k=10, ef=32, k_arr=None, ef_arr=None, k_max=None, ef_max=None,
     sp.ef_upper = ef_upper
     sp.rerank_factor = rerank_factor
     sp.counters = counters.data_ptr() if counters is not None else None
+    # root_kernel: True (matrix-core scan where available), "valu" (tiled
+    # VALU scan) or False (scan inside the search kernel); same results
+    if root_kernel not in (True, False, "valu"):
+        raise ValueError("root_kernel must be True, False or 'valu'")
     sp.flags = (HENN_SEARCH_PERSISTENT if persistent else 0) | (
         HENN_SEARCH_COUNTERS if counters is not None else 0) | (
-        0 if root_kernel else HENN_SEARCH_NO_ROOT_KERNEL)
+        HENN_SEARCH_NO_ROOT_KERNEL if root_kernel is False else 0) | (
+        HENN_SEARCH_ROOT_VALU if root_kernel == "valu" else 0)
     sp.lanes_per_vec = lanes_per_vec
     sp.waves_per_block = waves_per_block
     sp.vis_bits = vis_bits

@@ -354,8 +354,9 @@ def test_build_sym_graph_matches_oracle(hn, ho, cfg1_sym_root):
 @pytest.mark.parametrize("storage,metric,d", [(0, 0, 32), (1, 0, 96), (2, 0, 128), (0, 1, 64),
                                               (2, 1, 40)])
 def test_root_scan_kernel_matches_in_kernel_scan(hn, ho, storage, metric, d):
-    """The tiled root-scan kernel and the in-kernel scan compute the same
-    canonical distances, so the searches agree bit for bit."""
+    """The matrix-core root scan (Gram shortlist + exact check), the tiled
+    VALU scan and the in-kernel scan find the same root member, so the
+    searches agree bit for bit."""
     X = wl.uniform(6000, d, 50) - 0.5
     Q = wl.uniform(700, d, 51) - 0.5
     if metric == 1:
@@ -365,10 +366,12 @@ def test_root_scan_kernel_matches_in_kernel_scan(hn, ho, storage, metric, d):
                         max_degree=24, root_complete_max=700)
     assert idx.num_layers >= 2
     a_i, a_d = hn.henn_search_batch(idx, to_dev(Q), k=10, ef=40)
-    b_i, b_d = hn.henn_search_batch(idx, to_dev(Q), k=10, ef=40, root_kernel=False)
-    _sync()
-    assert np.array_equal(a_i.cpu().numpy(), b_i.cpu().numpy())
-    assert np.array_equal(a_d.cpu().numpy().view(np.uint32), b_d.cpu().numpy().view(np.uint32))
+    for mode in (False, "valu"):
+        b_i, b_d = hn.henn_search_batch(idx, to_dev(Q), k=10, ef=40, root_kernel=mode)
+        _sync()
+        assert np.array_equal(a_i.cpu().numpy(), b_i.cpu().numpy()), mode
+        assert np.array_equal(a_d.cpu().numpy().view(np.uint32),
+                              b_d.cpu().numpy().view(np.uint32)), mode
     idx.free()
 
 
