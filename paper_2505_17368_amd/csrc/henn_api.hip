@@ -702,6 +702,7 @@ henn_status henn_autotune(henn_index* idx, const float* Q, int64_t nq,
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   int32_t* ids = nullptr;
   float* dist = nullptr;
+  void* ws = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   try {
     ids = dalloc<int32_t>(nq * sp->k_max);
@@ -718,9 +719,20 @@ henn_status henn_autotune(henn_index* idx, const float* Q, int64_t nq,
     henn_search_params c = *sp;
     c.counters = nullptr;
     c.ev_begin = c.ev_end = nullptr;
+    // one workspace for every trial, so that no trial times an allocation
+    // (its size depends on the flags and nq, not on the launch shape)
+    {
+      henn_search_params cp = c;
+      cp.flags |= HENN_SEARCH_PERSISTENT;
+      const int64_t wb = search_workspace_bytes(idx, nq, &cp);
+      HENN_HIP(hipMalloc(&ws, wb));
+      c.workspace = ws;
+      c.workspace_bytes = wb;
+    }
+    // one warm-up launch, then the median of five
     auto time_of = [&](const henn_search_params& q) -> float {
-      float best = 1e30f;
-      for (int rep = 0; rep < 3; ++rep) {
+      float t[5];
+      for (int rep = 0; rep < 6; ++rep) {
         HENN_HIP(hipEventRecord(e0, st));
         henn_status s2 = henn_search_batch(idx, Q, nq, &q, ids, dist, st);
         HENN_HIP(hipEventRecord(e1, st));
@@ -728,9 +740,10 @@ henn_status henn_autotune(henn_index* idx, const float* Q, int64_t nq,
         if (s2 != HENN_OK) return 1e30f;
         float ms = 0.f;
         HENN_HIP(hipEventElapsedTime(&ms, e0, e1));
-        if (rep > 0) best = std::min(best, ms);  // first run warms up
+        if (rep > 0) t[rep - 1] = ms;
       }
-      return best;
+      std::sort(t, t + 5);
+      return t[2];
     };
     // 1) lanes per vector x visited-table size at 4 waves per block
     henn_search_params bestp = c;
@@ -746,8 +759,10 @@ henn_status henn_autotune(henn_index* idx, const float* Q, int64_t nq,
         if (t < bt) { bt = t; bestp = q; }
       }
     }
-    // 2) waves per block and persistent launch around the best
+    // 2) waves per block and persistent launch around the best (the phase-1
+    //    winner is timed again among them)
     const henn_search_params base = bestp;
+    bt = 1e30f;
     for (int w : {1, 2, 4, 8}) {
       for (int pers = 0; pers < 2; ++pers) {
         henn_search_params q = base;
@@ -782,12 +797,14 @@ henn_status henn_autotune(henn_index* idx, const float* Q, int64_t nq,
     (void)hipEventDestroy(e1);
     (void)hipFree(ids);
     (void)hipFree(dist);
+    (void)hipFree(ws);
     return HENN_OK;
   } catch (const HipError& e) {
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     (void)hipFree(ids);
     (void)hipFree(dist);
+    (void)hipFree(ws);
     return from_hip(e);
   }
 }
