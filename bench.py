@@ -225,7 +225,9 @@ def main():
     sweep = {}
     chosen = {}
     tuned = {}
-    calib = Qd[: min(nq, 4096)]
+    # the tuner sees the timed batch itself: the best shape depends on how
+    # many query waves the batch puts in flight
+    calib = Qd
     for f in forms:
         sweep[f] = []
         for ef in efs:
@@ -626,7 +628,7 @@ def serving(args):
     sweep = []
     chosen = None
     for ef in efs:
-        hn.henn_autotune(idx, Qd[: min(nq, 8192)], k=10, ef=ef)
+        hn.henn_autotune(idx, Qd, k=10, ef=ef)
         ids, _ = hn.henn_search_batch(idx, Qd, k=10, ef=ef)
         torch.cuda.synchronize()
         rec = recall_of(ids.cpu().numpy(), gt_dist, dist_rows, sample)

@@ -171,16 +171,20 @@ struct Chunk<kBF16> {
   }
 };
 
+// FP8 rows decode with gfx950's packed converter (OCP E4M3, exact; two
+// codes per instruction, the low byte first); fp8_to_f32 above is the same
+// map written out, used where rows are decoded once.
 template <>
 struct Chunk<kFP8> {
   static constexpr int kBytes = 8;
   __device__ static inline void load(const void* row, int c, float (&v)[8]) {
     const uint2 a = *reinterpret_cast<const uint2*>(static_cast<const uint8_t*>(row) + c * 8);
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      v[j] = fp8_to_f32((a.x >> (8 * j)) & 0xffu);
-      v[4 + j] = fp8_to_f32((a.y >> (8 * j)) & 0xffu);
-    }
+    const auto p0 = __builtin_amdgcn_cvt_pk_f32_fp8((int)a.x, false);
+    const auto p1 = __builtin_amdgcn_cvt_pk_f32_fp8((int)a.x, true);
+    const auto p2 = __builtin_amdgcn_cvt_pk_f32_fp8((int)a.y, false);
+    const auto p3 = __builtin_amdgcn_cvt_pk_f32_fp8((int)a.y, true);
+    v[0] = p0[0]; v[1] = p0[1]; v[2] = p1[0]; v[3] = p1[1];
+    v[4] = p2[0]; v[5] = p2[1]; v[6] = p3[0]; v[7] = p3[1];
   }
 };
 
