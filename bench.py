@@ -352,10 +352,11 @@ def main():
     tpath = os.path.join(ROOT, "profiles", "k_search_traffic.json")
     if os.path.exists(tpath):
         from paper_2505_17368_amd.kernel_hash import search_kernel_hash
-        tr = json.load(open(tpath))
-        if (tr.get("source_hash") == search_kernel_hash() and tr.get("workload") == args.workload
-                and tr.get("form") == head_form and tr.get("ef") == ef):
-            traffic = round(tr["fetch_bytes"] + tr["write_bytes"])
+        h = search_kernel_hash()
+        for tr in json.load(open(tpath)).get("entries", []):
+            if (tr.get("source_hash") == h and tr.get("workload") == args.workload
+                    and tr.get("form") == head_form and tr.get("ef") == ef):
+                traffic = round(tr["fetch_bytes"] + tr["write_bytes"])
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "bytes_per_query": round(bytes_q, 1), "evals_per_query": round(evals, 1),
