@@ -241,23 +241,93 @@ __device__ inline float group_sum(float v) {
 // group return the same value.
 // `valid` false skips the loads (the lane still joins the butterfly, so a
 // group whose candidate slot is empty keeps the wave's shuffles uniform).
+// Distances of NR rows per lane group.  Every chunk the lane needs is
+// loaded first, without branches (chunks past the row are clamped to chunk
+// 0 and dropped), so that all NR * CPL loads are in flight together; then
+// the chunks are decoded and reduced exactly as group_distance does.  rows[r]
+// must point at readable row memory even when !valid[r].
+template <int KIND>
+struct ChunkRaw;
+template <>
+struct ChunkRaw<kF32> {
+  float4 a, b;
+  __device__ inline void fetch(const void* row, int c) {
+    const float4* p = reinterpret_cast<const float4*>(static_cast<const float*>(row) + c * 8);
+    a = p[0];
+    b = p[1];
+  }
+  __device__ inline void decode(float (&v)[8]) const {
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+  }
+};
+template <>
+struct ChunkRaw<kBF16> {
+  uint4 a;
+  __device__ inline void fetch(const void* row, int c) {
+    a = *reinterpret_cast<const uint4*>(static_cast<const uint16_t*>(row) + c * 8);
+  }
+  __device__ inline void decode(float (&v)[8]) const {
+    v[0] = bf16_to_f32(a.x & 0xffffu); v[1] = bf16_to_f32(a.x >> 16);
+    v[2] = bf16_to_f32(a.y & 0xffffu); v[3] = bf16_to_f32(a.y >> 16);
+    v[4] = bf16_to_f32(a.z & 0xffffu); v[5] = bf16_to_f32(a.z >> 16);
+    v[6] = bf16_to_f32(a.w & 0xffffu); v[7] = bf16_to_f32(a.w >> 16);
+  }
+};
+template <>
+struct ChunkRaw<kFP8> {
+  uint2 a;
+  __device__ inline void fetch(const void* row, int c) {
+    a = *reinterpret_cast<const uint2*>(static_cast<const uint8_t*>(row) + c * 8);
+  }
+  __device__ inline void decode(float (&v)[8]) const {
+    const auto p0 = __builtin_amdgcn_cvt_pk_f32_fp8((int)a.x, false);
+    const auto p1 = __builtin_amdgcn_cvt_pk_f32_fp8((int)a.x, true);
+    const auto p2 = __builtin_amdgcn_cvt_pk_f32_fp8((int)a.y, false);
+    const auto p3 = __builtin_amdgcn_cvt_pk_f32_fp8((int)a.y, true);
+    v[0] = p0[0]; v[1] = p0[1]; v[2] = p1[0]; v[3] = p1[1];
+    v[4] = p2[0]; v[5] = p2[1]; v[6] = p3[0]; v[7] = p3[1];
+  }
+};
+
+template <int KIND, int LPN, int CPL, int NR>
+__device__ inline void group_distances(const float (&q)[CPL][8], const void* const (&rows)[NR],
+                                       const float (&scale)[NR], int t, int nchunks, int metric,
+                                       const bool (&valid)[NR], float (&out)[NR]) {
+  ChunkRaw<KIND> raw[NR][CPL];
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+#pragma unroll
+    for (int i = 0; i < CPL; ++i) {
+      const int c = t * CPL + i;
+      raw[r][i].fetch(rows[r], c < nchunks ? c : 0);
+    }
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    float part[CPL];
+#pragma unroll
+    for (int i = 0; i < CPL; ++i) {
+      const int c = t * CPL + i;
+      float x[8];
+      raw[r][i].decode(x);
+      const float v = metric == 0 ? chunk_l2(q[i], x, scale[r], KIND == kFP8) : chunk_ip(q[i], x);
+      part[i] = (valid[r] && c < nchunks) ? v : 0.0f;
+    }
+    float s2 = group_sum<LPN>(tree_sum<CPL>(part));
+    if (metric != 0) s2 = (KIND == kFP8) ? -(scale[r] * s2) : -s2;
+    out[r] = s2;
+  }
+}
+
 template <int KIND, int LPN, int CPL>
 __device__ inline float group_distance(const float (&q)[CPL][8], const void* row, float scale,
                                        int t, int nchunks, int metric, bool valid = true) {
-  float part[CPL];
-#pragma unroll
-  for (int i = 0; i < CPL; ++i) {
-    const int c = t * CPL + i;
-    part[i] = 0.0f;
-    if (valid && c < nchunks) {
-      float x[8];
-      Chunk<KIND>::load(row, c, x);
-      part[i] = metric == 0 ? chunk_l2(q[i], x, scale, KIND == kFP8) : chunk_ip(q[i], x);
-    }
-  }
-  float s = group_sum<LPN>(tree_sum<CPL>(part));
-  if (metric != 0) s = (KIND == kFP8) ? -(scale * s) : -s;
-  return s;
+  const void* const rows[1] = {row};
+  const float sc[1] = {scale};
+  const bool vd[1] = {valid};
+  float out[1];
+  group_distances<KIND, LPN, CPL, 1>(q, rows, sc, t, nchunks, metric, vd, out);
+  return out[0];
 }
 
 // Loads this lane's query slice (FP32 source, chunked; zero beyond d).

@@ -217,10 +217,14 @@ __device__ uint64_t root_scan_wave(const SearchArgs& a, const SearchLayer& R,
     const bool v0 = c0 < R.size, v1 = c1 < R.size;
     const float s0 = (KIND == kFP8 && v0) ? R.scale[c0] : 1.0f;
     const float s1 = (KIND == kFP8 && v1) ? R.scale[c1] : 1.0f;
-    const char* r0 = static_cast<const char*>(R.vec) + (int64_t)(v0 ? c0 : 0) * R.row_bytes;
-    const char* r1 = static_cast<const char*>(R.vec) + (int64_t)(v1 ? c1 : 0) * R.row_bytes;
-    const float d0 = group_distance<KIND, LPN, CPL>(q, r0, s0, t, a.nchunks, a.metric, v0);
-    const float d1 = group_distance<KIND, LPN, CPL>(q, r1, s1, t, a.nchunks, a.metric, v1);
+    const void* const rows[2] = {
+        static_cast<const char*>(R.vec) + (int64_t)(v0 ? c0 : 0) * R.row_bytes,
+        static_cast<const char*>(R.vec) + (int64_t)(v1 ? c1 : 0) * R.row_bytes};
+    const float sc[2] = {s0, s1};
+    const bool vd[2] = {v0, v1};
+    float dd[2];
+    group_distances<KIND, LPN, CPL, 2>(q, rows, sc, t, a.nchunks, a.metric, vd, dd);
+    const float d0 = dd[0], d1 = dd[1];
     if (v0) {
       const uint64_t k0 = wkey(d0, c0);
       best = k0 < best ? k0 : best;
@@ -459,16 +463,25 @@ __device__ bool advance(const SearchArgs& a, const float (&q)[CPL][8], WaveLds s
       wave_sync();
       st.evals += cnt;
 
-      // gather + distance, G rows per pass
-      for (int base = 0; base < cnt; base += G) {
-        const int ci = base + g;
-        const bool valid = ci < cnt;
-        const int32_t id = valid ? s.cid[ci] : 0;
-        const float sc = (KIND == kFP8 && valid) ? csc[ci] : 1.0f;
-        const char* row = static_cast<const char*>(L.vec) + (int64_t)id * L.row_bytes;
-        const float dist =
-            group_distance<KIND, LPN, CPL>(q, row, sc, t, a.nchunks, a.metric, valid);
-        if (valid && t == 0) s.ckey[ci] = wkey(dist, id);
+      // gather + distance, 2G rows per pass with all their loads in flight
+      // together (an empty slot re-reads the pass's first row)
+      for (int base = 0; base < cnt; base += 2 * G) {
+        const int ci0 = base + g, ci1 = base + G + g;
+        const bool v0 = ci0 < cnt, v1 = ci1 < cnt;
+        const int32_t id0 = s.cid[v0 ? ci0 : base];
+        const int32_t id1 = v1 ? s.cid[ci1] : id0;
+        const float sc[2] = {(KIND == kFP8) ? csc[v0 ? ci0 : base] : 1.0f,
+                             (KIND == kFP8 && v1) ? csc[ci1] : 1.0f};
+        const void* const rows[2] = {
+            static_cast<const char*>(L.vec) + (int64_t)id0 * L.row_bytes,
+            static_cast<const char*>(L.vec) + (int64_t)id1 * L.row_bytes};
+        const bool vd[2] = {v0, v1};
+        float dist[2];
+        group_distances<KIND, LPN, CPL, 2>(q, rows, sc, t, a.nchunks, a.metric, vd, dist);
+        if (t == 0) {
+          if (v0) s.ckey[ci0] = wkey(dist[0], id0);
+          if (v1) s.ckey[ci1] = wkey(dist[1], id1);
+        }
       }
       wave_sync();
 
