@@ -207,6 +207,43 @@ int ho_knn_graph(const float *X, int d, int metric, const int32_t *members, int6
 }
 
 /* ------------------------------------------------------------------ */
+/* Diversity pruning (App. B.2 navigable graphs: the neighbour selection  */
+/* of NSW/HNSW-style graphs).  Row v of adj_in holds C candidates in      */
+/* ascending (dist(v,.), id) order, -1 padded.  They are taken in that    */
+/* order; a candidate c is dropped when some already kept r is closer to  */
+/* c than v is, d(c, r) < d(c, v); otherwise it is kept, until R_keep are */
+/* kept.  Rows are -1 padded.  prune_margin[v] = the smallest relative    */
+/* margin |d(c,r) - d(c,v)| / max(|.|) over every comparison made.        */
+/* ------------------------------------------------------------------ */
+int ho_prune(const float *X, int d, int metric, const int32_t *members, int64_t s,
+             const int32_t *adj_in, int C, int R_keep, int32_t *adj_out, double *prune_margin) {
+  int32_t *kept = (int32_t *)malloc(sizeof(int32_t) * (size_t)(R_keep > 0 ? R_keep : 1));
+  if (!kept) return -2;
+  for (int64_t v = 0; v < s; ++v) {
+    const float *xv = X + (size_t)members[v] * (size_t)d;
+    int nk = 0;
+    double mg = INFINITY;
+    for (int j = 0; j < C && nk < R_keep; ++j) {
+      const int32_t c = adj_in[(size_t)v * C + j];
+      if (c < 0) break;
+      const float *xc = X + (size_t)members[c] * (size_t)d;
+      const double dcv = dist64(xc, xv, d, metric);
+      int drop = 0;
+      for (int r = 0; r < nk; ++r) {
+        const double dcr = dist64(xc, X + (size_t)members[kept[r]] * (size_t)d, d, metric);
+        mg = fmin(mg, margin_l2(dcr, dcv));
+        if (dcr < dcv) drop = 1;
+      }
+      if (!drop) kept[nk++] = c;
+    }
+    for (int r = 0; r < R_keep; ++r) adj_out[(size_t)v * R_keep + r] = r < nk ? kept[r] : -1;
+    if (prune_margin) prune_margin[v] = mg;
+  }
+  free(kept);
+  return 0;
+}
+
+/* ------------------------------------------------------------------ */
 /* kNN graph plus reverse edges (the kNN_SYM navigable graph): row v is   */
 /* the first max_deg of the deduplicated union of v's out-neighbours and  */
 /* the nodes that list v, in ascending (dist(v,u), u) order.  adj_knn is  */

@@ -96,6 +96,9 @@ def _load():
         lib.ho_knn_sym.restype = ctypes.c_int
         lib.ho_knn_sym.argtypes = [c_f32p, ctypes.c_int, ctypes.c_int, c_i32p, ctypes.c_int64,
                                    c_i32p, ctypes.c_int, ctypes.c_int, c_i32p, c_f64p, c_f64p]
+        lib.ho_prune.restype = ctypes.c_int
+        lib.ho_prune.argtypes = [c_f32p, ctypes.c_int, ctypes.c_int, c_i32p, ctypes.c_int64,
+                                 c_i32p, ctypes.c_int, ctypes.c_int, c_i32p, c_f64p]
         lib.ho_brute_knn.restype = ctypes.c_int
         lib.ho_brute_knn.argtypes = [c_f32p, ctypes.c_int64, ctypes.c_int, ctypes.c_int, c_f32p,
                                      ctypes.c_int64, ctypes.c_int64, ctypes.c_int, c_i32p, c_f64p]
@@ -183,8 +186,10 @@ class BuildParams:
     max_attempts: int = 64
     degree: int = 16
     seed: int = 0
-    graph: int = 0               # 0: exact kNN; 1: kNN plus reverse edges (kNN_SYM)
-    max_degree: int = 32         # row cap of kNN_SYM
+    graph: int = 0               # 0: exact kNN; 1: kNN plus reverse edges (kNN_SYM);
+                                 # 2: diversity-pruned kNN (PRUNED); 3: PRUNED plus
+                                 # reverse edges (PRUNED_SYM)
+    max_degree: int = 32         # row cap of the graphs with reverse edges
     root_complete_max: int = 0   # > 0: stop adding layers once a layer holds at most
                                  # this many points and give that root the complete graph
 
@@ -343,7 +348,19 @@ def build_index(X: np.ndarray, p: BuildParams | None = None, threads=None) -> Or
     idx = OracleIndex(X=X, metric=p.metric, degree=p.degree, members=members, info=infos,
                       root_complete=root_complete)
     for mb in members:
-        a, ad, cut, order = knn_graph(X, p.metric, mb, p.degree, threads)
+        if p.graph in (2, 3):
+            cands = prune_candidates(p.degree)
+            a, ad, cut, order = knn_graph(X, p.metric, mb, cands, threads)
+            a, pm = prune(X, p.metric, mb, a, p.degree)
+            # a row's list now also rests on its pruning comparisons
+            order = np.minimum(np.minimum(order, cut), pm)
+            cut = order.copy()
+            ad = None
+            if p.graph == 3:
+                a, cut2, order2 = knn_sym(X, p.metric, mb, a, p.max_degree)
+                cut, order = np.minimum(cut, cut2), np.minimum(order, order2)
+        else:
+            a, ad, cut, order = knn_graph(X, p.metric, mb, p.degree, threads)
         if p.graph == 1:
             a, cut, order = knn_sym(X, p.metric, mb, a, p.max_degree)
             ad = None
@@ -355,6 +372,27 @@ def build_index(X: np.ndarray, p: BuildParams | None = None, threads=None) -> Or
         # the root's decisions are the exhaustive scan's, not its list's
         idx.adj_margin[-1] = np.full(len(members[-1]), np.inf)
     return idx
+
+
+def prune_candidates(degree: int) -> int:
+    """Candidates scanned by the pruned graphs: the exact top min(2R, 32)."""
+    return min(2 * degree, 32)
+
+
+def prune(X, metric, members, adj_in, keep):
+    """Diversity pruning of candidate lists (ho_prune): returns (adjacency
+    [s, keep], smallest relative margin of each row's comparisons)."""
+    lib = _load()
+    s = len(members)
+    adj_in = np.ascontiguousarray(adj_in, dtype=np.int32)
+    out = np.full((s, keep), -1, dtype=np.int32)
+    pm = np.full(s, np.inf)
+    rc = lib.ho_prune(_ptr(X, ctypes.c_float), X.shape[1], metric,
+                      _ptr(members, ctypes.c_int32), s, _ptr(adj_in, ctypes.c_int32),
+                      adj_in.shape[1], keep, _ptr(out, ctypes.c_int32), _ptr(pm, ctypes.c_double))
+    if rc != 0:
+        raise RuntimeError("prune failed")
+    return out, pm
 
 
 def knn_sym(X, metric, members, adj_knn, max_deg):

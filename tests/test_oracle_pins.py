@@ -462,3 +462,117 @@ def test_root_complete_stops_layer_loop(oracle):
     assert len(members) == 1
     members, _ = oracle.build_layers(X, oracle.BuildParams(degree=8, root_complete_max=200))
     assert len(members[-1]) <= 200 and len(members[-2]) > 200
+
+
+# ---------------------------------------------------------------- pruning ---
+
+def _line_points(n, d, seed):
+    """n distinct points on a line in R^d with irregular gaps."""
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.uniform(0.5, 2.0, size=n))
+    u = rng.standard_normal(d)
+    u /= np.linalg.norm(u)
+    return (t[:, None] * u[None, :]).astype(np.float32), t
+
+
+def test_prune_on_a_line_keeps_the_nearest_on_each_side(oracle):
+    """On a line a farther candidate on the same side as a kept one is closer
+    to that kept point than to v, so exactly the two nearest neighbours (one
+    per side; one at the ends) survive."""
+    X, t = _line_points(60, 8, 3)
+    members = np.arange(60, dtype=np.int32)
+    cand, _, _, _ = oracle.knn_graph(X, oracle.L2, members, 16)
+    out, pm = oracle.prune(X, oracle.L2, members, cand, 16)
+    order = np.argsort(t)
+    rank = np.empty(60, dtype=int)
+    rank[order] = np.arange(60)
+    for v in range(60):
+        r = rank[v]
+        expect = set()
+        if r > 0:
+            expect.add(int(order[r - 1]))
+        if r < 59:
+            expect.add(int(order[r + 1]))
+        got = [int(x) for x in out[v] if x >= 0]
+        assert set(got) == expect, (v, got, expect)
+        assert got[0] == cand[v][0]  # the nearest candidate is always kept
+    assert np.all(pm > 1e-6)
+
+
+def test_prune_keeps_orthogonal_candidates(oracle):
+    """Candidates on distinct orthogonal axes around v are farther from each
+    other than from v (r_i^2 + r_j^2 > r_i^2), so none is dropped."""
+    d = 12
+    radii = np.linspace(1.0, 2.1, d)
+    pts = [np.zeros(d)]
+    for i in range(d):
+        e = np.zeros(d)
+        e[i] = radii[i]
+        pts.append(e)
+    X = np.array(pts, dtype=np.float32)
+    members = np.arange(d + 1, dtype=np.int32)
+    cand, _, _, _ = oracle.knn_graph(X, oracle.L2, members, d)
+    out, _ = oracle.prune(X, oracle.L2, members, cand, d)
+    assert np.array_equal(out[0], cand[0])
+    out4, _ = oracle.prune(X, oracle.L2, members, cand, 4)
+    assert np.array_equal(out4[0], cand[0][:4])  # the cap keeps the first four
+
+
+@pytest.mark.parametrize("metric", [0, 1])
+def test_pruned_graph_invariants(oracle, metric):
+    """Pruned rows are ordered subsequences of the candidate lists, start with
+    the nearest candidate, never repeat or list the row itself, and every
+    dropped candidate has a kept one strictly closer to it than the row is
+    (checked in FP64 with NumPy)."""
+    X = wl.uniform(400, 6, 11) - 0.5
+    if metric == 1:
+        X /= np.linalg.norm(X, axis=1, keepdims=True)
+    members = np.arange(400, dtype=np.int32)
+    C = oracle.prune_candidates(8)
+    cand, _, _, _ = oracle.knn_graph(X, metric, members, C)
+    out, pm = oracle.prune(X, metric, members, cand, 8)
+    X64 = X.astype(np.float64)
+
+    def dist(a, b):
+        return float(((X64[a] - X64[b]) ** 2).sum()) if metric == 0 else -float(X64[a] @ X64[b])
+
+    for v in range(400):
+        kept = [int(x) for x in out[v] if x >= 0]
+        cl = [int(x) for x in cand[v] if x >= 0]
+        assert kept[0] == cl[0] and v not in kept and len(set(kept)) == len(kept)
+        pos = [cl.index(k) for k in kept]
+        assert pos == sorted(pos)
+        last = pos[-1] if len(kept) == 8 else len(cl) - 1
+        for j in range(last + 1):
+            c = cl[j]
+            if c in kept:
+                continue
+            earlier = [k for k in kept if cl.index(k) < j]
+            assert any(dist(c, k) < dist(c, v) for k in earlier), (v, c)
+
+
+def test_pruned_sym_rows_are_out_plus_in_neighbours(oracle):
+    """PRUNED_SYM rows: the pruned out-list plus only nodes whose pruned list
+    holds the row, deduplicated, sorted by (distance, id), at most max_degree."""
+    X = wl.uniform(500, 5, 12)
+    members = np.arange(500, dtype=np.int32)
+    cand, _, _, _ = oracle.knn_graph(X, oracle.L2, members, oracle.prune_candidates(6))
+    pr, _ = oracle.prune(X, oracle.L2, members, cand, 6)
+    sym, _, _ = oracle.knn_sym(X, oracle.L2, members, pr, 20)
+    X64 = X.astype(np.float64)
+    ins = {v: set() for v in range(500)}
+    for u in range(500):
+        for x in pr[u]:
+            if x >= 0:
+                ins[int(x)].add(u)
+    for v in range(500):
+        row = [int(x) for x in sym[v] if x >= 0]
+        out = {int(x) for x in pr[v] if x >= 0}
+        assert len(row) == len(set(row)) <= 20
+        assert set(row) <= out | ins[v]
+        if len(out | ins[v]) <= 20:
+            assert set(row) == out | ins[v]
+        dd = [float(((X64[v] - X64[u]) ** 2).sum()) for u in row]
+        assert all(dd[i] <= dd[i + 1] for i in range(len(dd) - 1))
+    idx = oracle.build_index(X, oracle.BuildParams(degree=6, graph=3, max_degree=20))
+    assert np.array_equal(idx.adj[0], sym)
