@@ -147,7 +147,7 @@ def main():
     efs = [int(e) for e in args.efs.split(",")]
     k = args.k
     storage_of = {"f32": 0, "bf16": 1, "fp8": 2}
-    graph = 1 if args.graph == "knn_sym" else 0
+    graph = hn.GRAPH[args.graph]
 
     # ---- build once (FP32), then the same hierarchy with BF16 / FP8 rows ----
     indexes = {}
@@ -489,7 +489,7 @@ def batched(args):
     log(f"data {n}x{d}, {nq} queries in {time.time() - t0:.1f}s")
     Xd = torch.from_numpy(X).to(dev)
     Qd = torch.from_numpy(Q).to(dev)
-    bp = dict(degree=args.degree, metric=metric, graph=1 if args.graph == "knn_sym" else 0,
+    bp = dict(degree=args.degree, metric=metric, graph=hn.GRAPH[args.graph],
               max_degree=args.max_degree, root_complete_max=args.root_max)
     torch.cuda.synchronize()
     t = time.time()
@@ -591,7 +591,7 @@ def serving(args):
     log(f"data {n}x{d}, {nq} queries in {time.time() - t0:.1f}s")
     Xd = torch.from_numpy(X).to(dev)
     Qd = torch.from_numpy(Q).to(dev)
-    bp = dict(degree=args.degree, metric=metric, graph=1 if args.graph == "knn_sym" else 0,
+    bp = dict(degree=args.degree, metric=metric, graph=hn.GRAPH[args.graph],
               max_degree=args.max_degree, root_complete_max=args.serve_root_max)
     torch.cuda.synchronize()
     t = time.time()

@@ -52,7 +52,20 @@ typedef enum { HENN_F32 = 0, HENN_BF16 = 1, HENN_FP8_E4M3 = 2 } henn_storage;
 
 /* Navigable graph per layer (App. B.2): exact kNN, or kNN plus reverse
  * edges (deduplicated, kept in (distance, id) order, capped at max_degree). */
-typedef enum { HENN_GRAPH_KNN = 0, HENN_GRAPH_KNN_SYM = 1 } henn_graph;
+/* Navigable graph of each layer (App. B.2):
+ *   KNN:        the exact R nearest other members, (distance, id) order;
+ *   KNN_SYM:    KNN plus reverse edges: the first max_degree of the
+ *               deduplicated union of out- and in-neighbours in that order;
+ *   PRUNED:     diversity pruning of the exact top min(2R, 32) (the NSW/HNSW
+ *               neighbour selection): candidates in order, each dropped when an
+ *               already kept one is closer to it than the row is; <= R kept;
+ *   PRUNED_SYM: PRUNED plus reverse edges, as KNN_SYM. */
+typedef enum {
+  HENN_GRAPH_KNN = 0,
+  HENN_GRAPH_KNN_SYM = 1,
+  HENN_GRAPH_PRUNED = 2,
+  HENN_GRAPH_PRUNED_SYM = 3
+} henn_graph;
 
 #define HENN_MAX_LAYERS 16
 
@@ -67,8 +80,8 @@ typedef struct {
   double eps_override;    /* > 0: use this eps on every layer instead of Eq. (1) */
   int32_t num_rings;      /* r: ring ranges checked per layer (App. G.2) */
   int32_t max_attempts;   /* Las-Vegas cap of Alg. 2's repeat loop */
-  int32_t degree;         /* R: kNN graph degree */
-  int32_t max_degree;     /* row capacity for HENN_GRAPH_KNN_SYM (>= degree) */
+  int32_t degree;         /* R: kNN graph degree (kept neighbours for PRUNED) */
+  int32_t max_degree;     /* row capacity of the graphs with reverse edges (>= degree) */
   int32_t graph;          /* henn_graph */
   int32_t storage;        /* henn_storage */
   uint64_t seed;          /* key word 0 of the Philox4x64-10 stream (word 1 = 0) */

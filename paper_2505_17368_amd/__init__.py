@@ -1,4 +1,4 @@
 """HENN (arXiv 2505.17368) on MI355X: C-ABI HIP library + thin Python binding."""
-from .henn import (HennError, HennIndex, default_build_params, henn_autotune,  # noqa: F401
+from .henn import (GRAPH, HennError, HennIndex, default_build_params, henn_autotune,  # noqa: F401
                    henn_build, henn_free, henn_import, henn_search_batch, load_library,
                    search_params, SearchGraph, Server)

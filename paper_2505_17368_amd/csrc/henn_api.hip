@@ -73,8 +73,9 @@ static bool valid_build_params(const henn_build_params* p, std::string* why) {
   if (p->num_rings < 1 || p->num_rings > 4096) { *why = "num_rings in [1, 4096]"; return false; }
   if (p->max_attempts < 1) { *why = "max_attempts >= 1"; return false; }
   if (p->degree < 1 || p->degree > 32) { *why = "degree in [1, 32]"; return false; }
-  if (p->graph != HENN_GRAPH_KNN && p->graph != HENN_GRAPH_KNN_SYM) { *why = "graph"; return false; }
-  if (p->graph == HENN_GRAPH_KNN_SYM && (p->max_degree < p->degree || p->max_degree > 64)) {
+  if (p->graph < HENN_GRAPH_KNN || p->graph > HENN_GRAPH_PRUNED_SYM) { *why = "graph"; return false; }
+  const bool sym = p->graph == HENN_GRAPH_KNN_SYM || p->graph == HENN_GRAPH_PRUNED_SYM;
+  if (sym && (p->max_degree < p->degree || p->max_degree > 64)) {
     *why = "max_degree in [degree, 64]"; return false;
   }
   if (p->storage < HENN_F32 || p->storage > HENN_FP8_E4M3) { *why = "storage"; return false; }
@@ -88,17 +89,29 @@ static void finish_layer(henn_index* ix, int i, hipStream_t st) {
   const henn_build_params& p = ix->params;
   int lpn, cpl;
   pick_lanes(ix->nchunks, 0, &lpn, &cpl);
+  const bool pruned = p.graph == HENN_GRAPH_PRUNED || p.graph == HENN_GRAPH_PRUNED_SYM;
   const int R = p.degree;
+  // the pruned graphs scan the exact top min(2R, 32) candidates
+  const int C = pruned ? std::min(2 * R, 32) : R;
   int32_t* adj = dalloc<int32_t>(L.size * R);
+  int32_t* cand = pruned ? dalloc<int32_t>(L.size * C) : adj;
   try {
     L.info.fallback_rows =
-        (int32_t)build_knn_graph(L.vec32, L.size, ix->dpad, ix->nchunks, ix->metric, R, lpn, cpl,
-                                 adj, st);
+        (int32_t)build_knn_graph(L.vec32, L.size, ix->dpad, ix->nchunks, ix->metric, C, lpn, cpl,
+                                 cand, st);
+    if (pruned) {
+      prune_graph(L.vec32, L.size, ix->dpad, ix->nchunks, ix->metric, cand, C, R, adj, lpn, cpl,
+                  st);
+      HENN_HIP(hipStreamSynchronize(st));
+      (void)hipFree(cand);
+      cand = adj;
+    }
   } catch (...) {
+    if (cand != adj) (void)hipFree(cand);
     (void)hipFree(adj);
     throw;
   }
-  if (p.graph == HENN_GRAPH_KNN_SYM) {
+  if (p.graph == HENN_GRAPH_KNN_SYM || p.graph == HENN_GRAPH_PRUNED_SYM) {
     int32_t* adj2 = dalloc<int32_t>(L.size * p.max_degree);
     try {
       symmetrize_graph(L.vec32, L.size, ix->dpad, ix->nchunks, ix->metric, adj, R, adj2,

@@ -243,6 +243,13 @@ void symmetrize_graph(const float* vec, int64_t size, int dpad, int nchunks, int
                       const int32_t* adj_knn, int R, int32_t* adj_out, int max_deg, int lpn,
                       int cpl, hipStream_t st);
 
+// Diversity pruning of C <= 32 candidates per row (ascending, -1 padded)
+// to at most R kept neighbours (-1 padded), as the NSW/HNSW neighbour
+// selection does.
+void prune_graph(const float* vec, int64_t size, int dpad, int nchunks, int metric,
+                 const int32_t* adj_in, int C, int R, int32_t* adj_out, int lpn, int cpl,
+                 hipStream_t st);
+
 // Picks (lanes per vector, chunks per lane) for a dimension.
 void pick_lanes(int nchunks, int requested_lpn, int* lpn, int* cpl);
 

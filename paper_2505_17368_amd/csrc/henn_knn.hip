@@ -77,13 +77,22 @@ __global__ __launch_bounds__(256, 2) void k_gram_topk(
   const bool l2 = metric == 0;
   const float qscale = l2 ? -2.0f : -1.0f;
 
+  // the query's coordinates: loads clamped into the row (no branches, all in
+  // flight together), out-of-range values dropped afterwards
   float bq[KH];
+  {
+    const float* qr = qsrc + (qvalid ? qrow : 0) * qstride;
 #pragma unroll
-  for (int kk = 0; kk < KH; ++kk) {
-    const int e = h * KH + kk;
-    bq[kk] = (qvalid && e < qd)
-                 ? qscale * (qsrc[qrow * qstride + e] - (mean ? mean[e] : 0.0f))
-                 : 0.0f;
+    for (int kk = 0; kk < KH; ++kk) {
+      const int e = h * KH + kk;
+      bq[kk] = qr[e < qd ? e : 0];
+    }
+#pragma unroll
+    for (int kk = 0; kk < KH; ++kk) {
+      const int e = h * KH + kk;
+      const float m = (mean && e < qd) ? mean[e] : 0.0f;
+      bq[kk] = (qvalid && e < qd) ? qscale * (bq[kk] - m) : 0.0f;
+    }
   }
   // B operand of the extra step: row 0 is all ones, row 1 holds |x|^2 (L2)
   const float b_extra = h == 0 ? 1.0f : (l2 && qnorms && qvalid ? qnorms[qrow] : 0.0f);
@@ -662,6 +671,97 @@ int64_t build_knn_graph(const float* vec, int64_t size, int dpad, int nchunks, i
 // then one wave per node merges its out- and in-neighbours by (distance, id)
 // in chunks of 64 keys (sort the chunk, keep the lowest 64 of running list
 // and chunk with a bitonic half-cleaner) and writes the first max_deg.
+// Diversity pruning of a layer's candidate lists (App. B.2 navigable graphs:
+// the neighbour selection of NSW/HNSW-style graphs).  One wave per row v;
+// the C <= 32 candidates of adj_in (ascending (distance, id), -1 padded)
+// are taken in order and a candidate c is dropped when an already kept r
+// has d(c, r) < d(c, v), until R are kept.  All distances are the
+// canonical FP32 ones: d(v, c_j) first, then the candidate pairs
+// d(c_i, c_j), i < j (the difference form is symmetric in its arguments),
+// into a per-wave LDS matrix; the scan is then a ballot per candidate.
+template <int LPN, int CPL>
+__global__ __launch_bounds__(256) void k_prune(const float* vec, int64_t size, int dpad,
+                                               int nchunks, int metric, const int32_t* adj_in,
+                                               int C, int R, int32_t* adj_out) {
+  constexpr int G = 64 / LPN;
+  __shared__ float D[4][32][33];
+  __shared__ float dv[4][32];
+  __shared__ int32_t cid[4][32];
+  const int w = threadIdx.x >> 6;
+  const int64_t v = (int64_t)blockIdx.x * 4 + w;
+  if (v >= size) return;  // whole wave
+  const int lane = lane_id(), t = lane % LPN, g = lane / LPN;
+  const int32_t my = lane < C ? adj_in[v * C + lane] : -1;
+  const int nc = popc64(ballot(my >= 0));  // candidates form a prefix
+  if (lane < 32) cid[w][lane] = my;
+  wave_sync();
+
+  float q[CPL][8];
+  load_query<CPL>(vec + v * dpad, dpad, t, q);
+  for (int base = 0; base < nc; base += 2 * G) {
+    const int j0 = base + g, j1 = base + G + g;
+    const bool v0 = j0 < nc, v1 = j1 < nc;
+    const void* const rows[2] = {vec + (int64_t)cid[w][v0 ? j0 : base] * dpad,
+                                 vec + (int64_t)cid[w][v1 ? j1 : base] * dpad};
+    const float sc[2] = {1.0f, 1.0f};
+    const bool vd[2] = {v0, v1};
+    float dd[2];
+    group_distances<kF32, LPN, CPL, 2>(q, rows, sc, t, nchunks, metric, vd, dd);
+    if (t == 0) {
+      if (v0) dv[w][j0] = dd[0];
+      if (v1) dv[w][j1] = dd[1];
+    }
+  }
+  for (int i = 0; i + 1 < nc; ++i) {
+    load_query<CPL>(vec + (int64_t)cid[w][i] * dpad, dpad, t, q);
+    for (int base = i + 1; base < nc; base += 2 * G) {
+      const int j0 = base + g, j1 = base + G + g;
+      const bool v0 = j0 < nc, v1 = j1 < nc;
+      const void* const rows[2] = {vec + (int64_t)cid[w][v0 ? j0 : base] * dpad,
+                                   vec + (int64_t)cid[w][v1 ? j1 : base] * dpad};
+      const float sc[2] = {1.0f, 1.0f};
+      const bool vd[2] = {v0, v1};
+      float dd[2];
+      group_distances<kF32, LPN, CPL, 2>(q, rows, sc, t, nchunks, metric, vd, dd);
+      if (t == 0) {
+        if (v0) { D[w][i][j0] = dd[0]; D[w][j0][i] = dd[0]; }
+        if (v1) { D[w][i][j1] = dd[1]; D[w][j1][i] = dd[1]; }
+      }
+    }
+  }
+  wave_sync();
+  uint32_t kept = 0;
+  int nk = 0;
+  for (int j = 0; j < nc && nk < R; ++j) {
+    const bool closer = lane < j && ((kept >> lane) & 1u) && D[w][j][lane] < dv[w][j];
+    if (!ballot(closer)) {
+      kept |= 1u << j;
+      if (lane == 0) adj_out[v * R + nk] = cid[w][j];
+      ++nk;
+    }
+  }
+  for (int r = nk + lane; r < R; r += 64) adj_out[v * R + r] = -1;
+}
+
+void prune_graph(const float* vec, int64_t size, int dpad, int nchunks, int metric,
+                 const int32_t* adj_in, int C, int R, int32_t* adj_out, int lpn, int cpl,
+                 hipStream_t st) {
+  if (size <= 0) return;
+  if (C > 32 || R > C) throw HipError{hipErrorInvalidValue, "prune: C <= 32 and R <= C"};
+  const unsigned nb = (unsigned)((size + 3) / 4);
+  bool launched = false;
+#define HENN_TRY(L, CP)                                                                         \
+  if (!launched && lpn == L && cpl == CP) {                                                     \
+    hipLaunchKernelGGL((k_prune<L, CP>), dim3(nb), dim3(256), 0, st, vec, size, dpad, nchunks, \
+                       metric, adj_in, C, R, adj_out);                                          \
+    launched = true;                                                                            \
+  }
+  HENN_KNN_COMBOS(HENN_TRY)
+#undef HENN_TRY
+  if (!launched) throw HipError{hipErrorInvalidValue, "no prune kernel for this lane shape"};
+  HENN_HIP(hipGetLastError());
+}
+
 __global__ void k_indeg(const int32_t* adj, int64_t edges, uint32_t* cnt) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= edges) return;

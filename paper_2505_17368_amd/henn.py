@@ -22,7 +22,8 @@ HENN_OK, HENN_E_INVAL, HENN_E_NOMEM, HENN_E_DEVICE, HENN_E_UNSUPPORTED = 0, 1, 2
 HENN_W_NOT_VERIFIED = 100
 HENN_L2, HENN_IP = 0, 1
 HENN_F32, HENN_BF16, HENN_FP8_E4M3 = 0, 1, 2
-HENN_GRAPH_KNN, HENN_GRAPH_KNN_SYM = 0, 1
+HENN_GRAPH_KNN, HENN_GRAPH_KNN_SYM, HENN_GRAPH_PRUNED, HENN_GRAPH_PRUNED_SYM = 0, 1, 2, 3
+GRAPH = {"knn": 0, "knn_sym": 1, "pruned": 2, "pruned_sym": 3}
 HENN_SEARCH_COUNTERS, HENN_SEARCH_PERSISTENT, HENN_SEARCH_NO_ROOT_KERNEL = 1, 2, 4
 HENN_SEARCH_ROOT_VALU = 8
 STORAGE = {"f32": HENN_F32, "bf16": HENN_BF16, "fp8": HENN_FP8_E4M3}
@@ -180,6 +181,8 @@ def default_build_params(**kw) -> BuildParams:
             v = METRIC[v]
         if k == "storage" and isinstance(v, str):
             v = STORAGE[v]
+        if k == "graph" and isinstance(v, str):
+            v = GRAPH[v]
         if not hasattr(p, k):
             raise KeyError(k)
         setattr(p, k, v)

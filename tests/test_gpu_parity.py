@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import workloads as wl
-from gpu_util import assert_results_valid, assert_search_parity, to_dev
+from gpu_util import STRICT, assert_results_valid, assert_search_parity, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -464,4 +464,55 @@ def test_search_graph_replays_match_eager(hn, cfg1_sym_root, mixed):
         assert np.array_equal(gi, ei.cpu().numpy()), rep
         assert np.array_equal(gd.view(np.uint32), ed.cpu().numpy().view(np.uint32)), rep
     g.free()
+    idx.free()
+
+
+# ------------------------------------------------- pruned navigable graphs ---
+
+@pytest.mark.parametrize("graph,metric", [(2, 0), (3, 0), (3, 1)])
+def test_pruned_graphs_match_oracle(hn, ho, graph, metric):
+    """Diversity-pruned graphs (with and without reverse edges) against the
+    oracle's, layer by layer.  Rows whose candidate order, candidate cut or
+    pruning comparisons hold a near tie are exempt; with reverse edges, so
+    are the rows such a node may point to."""
+    X = wl.uniform(6000, 24, 60) - 0.5
+    if metric == 1:
+        X /= np.linalg.norm(X, axis=1, keepdims=True)
+    p = ho.BuildParams(degree=12, graph=graph, max_degree=28, metric=metric)
+    oidx = ho.build_index(X, p)
+    idx = hn.henn_build(to_dev(X), degree=12, graph=graph, max_degree=28, metric=metric)
+    layers = _gpu_layers(idx)
+    assert len(layers) == oidx.num_layers
+    C = ho.prune_candidates(12)
+    checked = 0
+    for i, (ids, adj) in enumerate(layers):
+        assert np.array_equal(ids, oidx.members[i])
+        mb = oidx.members[i]
+        cand, _, cut, order = ho.knn_graph(X, metric, mb, C)
+        _, pm = ho.prune(X, metric, mb, cand, 12)
+        tie = np.minimum(np.minimum(cut, order), pm) <= STRICT
+        if graph == 3:
+            spread = tie.copy()
+            for u in np.where(tie)[0]:
+                spread[cand[u][cand[u] >= 0]] = True
+            tie = spread
+        same = (adj == oidx.adj[i]).all(1)
+        assert (same | tie).all(), f"layer {i}: rows {np.where(~same & ~tie)[0][:5]}"
+        checked += int((~tie).sum())
+    assert checked > 0.75 * sum(len(m) for m in oidx.members)
+    idx.free()
+
+
+def test_pruned_sym_search_parity(hn, ho):
+    """Search on a GPU-built PRUNED_SYM hierarchy against the oracle searching
+    the same exported hierarchy."""
+    X, Q = wl.make("uniform_10k_d32")
+    idx = hn.henn_build(to_dev(X), degree=16, graph=3, max_degree=32, root_complete_max=1000)
+    layers = _gpu_layers(idx)
+    oidx = ho.index_from_arrays(X, 0, [l[0] for l in layers], [l[1] for l in layers],
+                                root_complete=True)
+    gi, gd = hn.henn_search_batch(idx, to_dev(Q), k=10, ef=48)
+    _sync()
+    ores = ho.search(oidx, Q, 10, 48)
+    assert_search_parity(gi.cpu().numpy(), gd.cpu().numpy(), ores, X, Q)
     idx.free()
