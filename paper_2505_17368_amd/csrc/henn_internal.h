@@ -178,9 +178,12 @@ bool launch_search(int storage, const SearchArgs& a, const LaunchShape& s, hipSt
 
 bool launch_serve_step(int storage, const SearchArgs& a, const ServeArgs& sv,
                        const LaunchShape& sh, hipStream_t st);
+// root_keys (nullable): the new requests' complete-root keys, copied to
+// slot_root[slot].
 void launch_serve_admit(const float* staged_q, const int32_t* meta, int n_new, int d,
                         float* slot_q, int32_t* slot_k, int32_t* slot_ef, int64_t* state_off,
-                        int32_t* cap, QState* states, hipStream_t st);
+                        int32_t* cap, QState* states, const uint64_t* root_keys,
+                        uint64_t* slot_root, hipStream_t st);
 
 // Exhaustive scan of a complete-graph root (dpad <= 128): writes
 // [splits][nq] best keys.  root_scan_splits() picks the split of the root.

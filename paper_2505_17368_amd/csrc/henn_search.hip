@@ -414,17 +414,24 @@ __device__ bool advance(const SearchArgs& a, const float (&q)[CPL][8], WaveLds s
     }
     int wsize = st.wsize;
     bool layer_done = false;
+    // adjacency row fetched one expansion ahead for the entry expected to be
+    // expanded next (the second smallest unexpanded one); used only when it
+    // is indeed the next, so the expansion order is unchanged
+    int32_t pf_node = -1;
+    int32_t pf_u = -1;
+    float pf_sc = 1.0f;
     while (budget > 0) {
-      // smallest unexpanded entry of W
-      int pos = -1;
-      for (int base = 0; base < wsize; base += 64) {
+      // smallest and second smallest unexpanded entries of W
+      int pos = -1, pos2 = -1;
+      for (int base = 0; base < wsize && pos2 < 0; base += 64) {
         const int i = base + lane;
         const bool un = i < wsize && !(W[i] & 1ull);
-        const uint64_t m = ballot(un);
-        if (m) {
+        uint64_t m = ballot(un);
+        if (m && pos < 0) {
           pos = base + __ffsll((unsigned long long)m) - 1;
-          break;
+          m &= m - 1;
         }
+        if (m) pos2 = base + __ffsll((unsigned long long)m) - 1;
       }
       if (pos < 0) {
         layer_done = true;
@@ -432,6 +439,7 @@ __device__ bool advance(const SearchArgs& a, const float (&q)[CPL][8], WaveLds s
       }
       --budget;
       const uint64_t ck = W[pos];
+      const int32_t c2 = pos2 >= 0 ? wkey_id(W[pos2]) : -1;
       wave_sync();
       if (lane == 0) W[pos] = ck | 1ull;
       const int32_t c = wkey_id(ck);
@@ -440,9 +448,17 @@ __device__ bool advance(const SearchArgs& a, const float (&q)[CPL][8], WaveLds s
       // neighbour ids (and, for FP8 rows, their scales) and the visited filter
       int32_t u = -1;
       float usc = 1.0f;
-      if (lane < L.deg) {
+      if (c == pf_node) {
+        u = pf_u;
+        usc = pf_sc;
+      } else if (lane < L.deg) {
         u = L.adj[(int64_t)c * L.deg + lane];
         if (KIND == kFP8) usc = L.adj_scale[(int64_t)c * L.deg + lane];
+      }
+      pf_node = c2;
+      if (c2 >= 0 && lane < L.deg) {
+        pf_u = L.adj[(int64_t)c2 * L.deg + lane];
+        if (KIND == kFP8) pf_sc = L.adj_scale[(int64_t)c2 * L.deg + lane];
       }
       bool fresh = false;
       uint32_t h = 0;
@@ -667,7 +683,8 @@ __global__ __launch_bounds__(512) void k_serve_step(SearchArgs a, ServeArgs sv, 
 
 __global__ void k_serve_admit(const float* staged_q, const int32_t* meta, int n_new, int d,
                               float* slot_q, int32_t* slot_k, int32_t* slot_ef,
-                              int64_t* state_off, int32_t* cap, QState* states) {
+                              int64_t* state_off, int32_t* cap, QState* states,
+                              const uint64_t* root_keys, uint64_t* slot_root) {
   // meta per new request: slot, k, ef, cap, offset (lo, hi)
   const int r = blockIdx.x;
   if (r >= n_new) return;
@@ -684,6 +701,7 @@ __global__ void k_serve_admit(const float* staged_q, const int32_t* meta, int n_
     memset(&st, 0, sizeof(st));
     st.li = kSlotNew;
     states[slot] = st;
+    if (root_keys) slot_root[slot] = root_keys[r];
   }
 }
 
@@ -793,10 +811,11 @@ bool launch_serve_step(int storage, const SearchArgs& a, const ServeArgs& sv,
 
 void launch_serve_admit(const float* staged_q, const int32_t* meta, int n_new, int d,
                         float* slot_q, int32_t* slot_k, int32_t* slot_ef, int64_t* state_off,
-                        int32_t* cap, QState* states, hipStream_t st) {
+                        int32_t* cap, QState* states, const uint64_t* root_keys,
+                        uint64_t* slot_root, hipStream_t st) {
   if (n_new <= 0) return;
   hipLaunchKernelGGL(k_serve_admit, dim3(n_new), dim3(64), 0, st, staged_q, meta, n_new, d,
-                     slot_q, slot_k, slot_ef, state_off, cap, states);
+                     slot_q, slot_k, slot_ef, state_off, cap, states, root_keys, slot_root);
 }
 
 template <int KIND>

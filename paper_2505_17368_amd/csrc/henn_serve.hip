@@ -99,6 +99,12 @@ struct henn_server {
   int32_t* stage_meta_d = nullptr;
   int32_t* out_ids_d = nullptr;
   float* out_dist_d = nullptr;
+  // complete-graph root on matrix cores (prepared roots only): each admitted
+  // request's root key, its shortlist scratch and the per-slot keys
+  uint64_t* root_keys = nullptr;
+  float* root_sl = nullptr;
+  int64_t root_sl_entries = 0;
+  uint64_t* slot_root = nullptr;
   // pinned host
   float* stage_q_h = nullptr;
   int32_t* stage_meta_h = nullptr;
@@ -142,6 +148,9 @@ static void srv_release(henn_server* s) {
   (void)hipFree(s->stage_meta_d);
   (void)hipFree(s->out_ids_d);
   (void)hipFree(s->out_dist_d);
+  (void)hipFree(s->root_keys);
+  (void)hipFree(s->root_sl);
+  (void)hipFree(s->slot_root);
   (void)hipHostFree(s->stage_q_h);
   (void)hipHostFree(s->stage_meta_h);
   (void)hipHostFree(s->active_h);
@@ -230,6 +239,18 @@ henn_status henn_server_create(const henn_index* idx, const henn_server_params* 
     dmalloc(&s->stage_meta_d, M * 6);
     dmalloc(&s->out_ids_d, M * s->k_max);
     dmalloc(&s->out_dist_d, M * s->k_max);
+    if (idx->root.size > 0) {
+      // shortlist entries for the largest admission batch's split
+      int64_t most = 0;
+      for (int64_t nn = 1; nn <= M; ++nn) {
+        int64_t per = 0;
+        most = std::max<int64_t>(most, (int64_t)root_gram_splits(nn, idx->root.size, &per) * nn);
+      }
+      s->root_sl_entries = most * 2 * kRootK;
+      dmalloc(&s->root_keys, M);
+      dmalloc(&s->slot_root, M);
+      dmalloc(&s->root_sl, 2 * s->root_sl_entries);  // values, then positions
+    }
     hmalloc(&s->stage_q_h, M * s->d);
     hmalloc(&s->stage_meta_h, M * 6);
     hmalloc(&s->active_h, M);
@@ -318,23 +339,6 @@ henn_status henn_server_tick(henn_server* s, int32_t* n_active_out) {
       ++n_new;
       ++s->admitted;
     }
-    if (n_new > 0) {
-      HENN_HIP(hipMemcpyAsync(s->stage_q_d, s->stage_q_h, sizeof(float) * n_new * s->d,
-                              hipMemcpyHostToDevice, s->st));
-      HENN_HIP(hipMemcpyAsync(s->stage_meta_d, s->stage_meta_h, sizeof(int32_t) * n_new * 6,
-                              hipMemcpyHostToDevice, s->st));
-      launch_serve_admit(s->stage_q_d, s->stage_meta_d, n_new, s->d, s->slot_q, s->slot_k,
-                         s->slot_ef, s->state_off, s->cap, s->states, s->st);
-    }
-    const int n_active = (int)s->active.size();
-    s->max_active = std::max<int64_t>(s->max_active, n_active);
-    if (n_active_out) *n_active_out = n_active;
-    if (n_active == 0) return HENN_OK;
-    // 2) one step of every active request
-    memcpy(s->active_h, s->active.data(), sizeof(int32_t) * n_active);
-    HENN_HIP(hipMemcpyAsync(s->active_d, s->active_h, sizeof(int32_t) * n_active,
-                            hipMemcpyHostToDevice, s->st));
-    HENN_HIP(hipMemsetAsync(s->done_d, 0, sizeof(int32_t), s->st));
     const henn_index* idx = s->idx;
     SearchArgs a;
     memset(&a, 0, sizeof(a));
@@ -352,10 +356,6 @@ henn_status henn_server_tick(henn_server* s, int32_t* n_active_out) {
       sl.row_bytes = (int64_t)idx->dpad * eb;
     }
     a.rerank_vec = idx->storage == HENN_F32 ? nullptr : idx->L[0].vec32;
-    a.Q = s->slot_q;
-    a.nq = s->p.max_slots;
-    a.k_arr = s->slot_k;
-    a.ef_arr = s->slot_ef;
     a.k_all = 1;
     a.ef_all = 1;
     a.k_max = s->k_max;
@@ -369,6 +369,47 @@ henn_status henn_server_tick(henn_server* s, int32_t* n_active_out) {
     a.metric = idx->metric;
     a.vis_bits = s->vis_bits;
     a.root_complete = idx->root_complete ? 1 : 0;
+    if (n_new > 0) {
+      HENN_HIP(hipMemcpyAsync(s->stage_q_d, s->stage_q_h, sizeof(float) * n_new * s->d,
+                              hipMemcpyHostToDevice, s->st));
+      HENN_HIP(hipMemcpyAsync(s->stage_meta_d, s->stage_meta_h, sizeof(int32_t) * n_new * 6,
+                              hipMemcpyHostToDevice, s->st));
+      if (s->slot_root) {
+        // the new requests' complete-root scans, on matrix cores
+        int64_t per = 0;
+        const int splits = root_gram_splits(n_new, idx->root.size, &per);
+        float* sl_d = s->root_sl;
+        int32_t* sl_i = reinterpret_cast<int32_t*>(s->root_sl + s->root_sl_entries);
+        launch_root_gram(s->stage_q_d, n_new, s->d, idx->root, idx->dpad, idx->metric, splits,
+                         per, sl_d, sl_i, s->st);
+        SearchArgs ra = a;
+        ra.Q = s->stage_q_d;
+        ra.nq = n_new;
+        if (!launch_root_check(idx->storage, ra, idx->root, splits, sl_d, sl_i, s->root_keys,
+                               s->st))
+          return srv_fail(HENN_E_UNSUPPORTED, "no root check kernel for this shape");
+      }
+      launch_serve_admit(s->stage_q_d, s->stage_meta_d, n_new, s->d, s->slot_q, s->slot_k,
+                         s->slot_ef, s->state_off, s->cap, s->states, s->root_keys,
+                         s->slot_root, s->st);
+    }
+    const int n_active = (int)s->active.size();
+    s->max_active = std::max<int64_t>(s->max_active, n_active);
+    if (n_active_out) *n_active_out = n_active;
+    if (n_active == 0) return HENN_OK;
+    // 2) one step of every active request
+    memcpy(s->active_h, s->active.data(), sizeof(int32_t) * n_active);
+    HENN_HIP(hipMemcpyAsync(s->active_d, s->active_h, sizeof(int32_t) * n_active,
+                            hipMemcpyHostToDevice, s->st));
+    HENN_HIP(hipMemsetAsync(s->done_d, 0, sizeof(int32_t), s->st));
+    a.Q = s->slot_q;
+    a.nq = s->p.max_slots;
+    a.k_arr = s->slot_k;
+    a.ef_arr = s->slot_ef;
+    if (s->slot_root) {
+      a.root_best = s->slot_root;
+      a.root_splits = 1;
+    }
     ServeArgs sv;
     sv.active = s->active_d;
     sv.n_active = n_active;

@@ -54,6 +54,14 @@ def test_invalid_arguments_rejected_on_host(lib):
     assert lib.henn_build(fake, 10, 4, ctypes.byref(bad), None, ctypes.byref(h)) == hn.HENN_E_INVAL
     bad = hn.default_build_params(degree=0)
     assert lib.henn_build(fake, 10, 4, ctypes.byref(bad), None, ctypes.byref(h)) == hn.HENN_E_INVAL
+    # graph kinds: 0..3; the ones with reverse edges need degree <= max_degree <= 64
+    for graph, maxdeg in ((4, 32), (-1, 32), (3, 8), (3, 65), (1, 65)):
+        bad = hn.default_build_params(degree=16, graph=graph, max_degree=maxdeg)
+        assert lib.henn_build(fake, 10, 4, ctypes.byref(bad), None,
+                              ctypes.byref(h)) == hn.HENN_E_INVAL, (graph, maxdeg)
+        assert "graph" in hn.last_error() or "max_degree" in hn.last_error()
+    assert hn.GRAPH == {"knn": 0, "knn_sym": 1, "pruned": 2, "pruned_sym": 3}
+    assert hn.default_build_params(graph="pruned_sym").graph == 3
     sp = hn.SearchParams()
     lib.henn_default_search_params(ctypes.byref(sp))
     assert lib.henn_search_batch(None, fake, 1, ctypes.byref(sp), fake, fake,
