@@ -57,6 +57,9 @@ __device__ inline uint32_t vis_hash(int32_t u, int bits) {
   return ((uint32_t)u * 2654435761u) >> (32 - bits);
 }
 
+// Largest power of two <= v (0 for v <= 0).
+__device__ inline int pow2_floor(int v) { return v <= 0 ? 0 : 1 << (31 - __clz(v)); }
+
 __device__ inline int next_pow2_dev(int v) {
   int p = 1;
   while (p < v) p <<= 1;
@@ -343,8 +346,8 @@ __device__ void start_query(const SearchArgs& a, int64_t qi, const float (&q)[CP
                             QState& st) {
   constexpr int G = 64 / LPN;
   const int lane = lane_id(), t = lane % LPN, g = lane / LPN;
-  int k = a.k_arr ? a.k_arr[qi] : a.k_all;
-  const int ef = a.ef_arr ? a.ef_arr[qi] : a.ef_all;
+  int k = uni(a.k_arr ? a.k_arr[qi] : a.k_all);
+  const int ef = uni(a.ef_arr ? a.ef_arr[qi] : a.ef_all);
   k = min(max(k, 1), a.k_max);
   st.k = k;
   st.ef0 = min(max(ef, k), a.ef_cap);
@@ -360,16 +363,17 @@ __device__ void start_query(const SearchArgs& a, int64_t qi, const float (&q)[CP
       const uint64_t kk = a.root_best[(int64_t)sp * a.nq + qi];
       best = kk < best ? kk : best;
     }
+    best = uni_u64(best);
     st.evals = R.size;
-    st.cur = R.down[wkey_id(best)];
+    st.cur = uni(R.down[wkey_id(best)]);
     st.cur_d = wkey_dist(best);
     st.li = top - 1;
   } else if (a.root_complete && top >= 1) {
     // complete graph on the root: exhaustive scan for its nearest member
     const SearchLayer& R = a.layer[top];
-    const uint64_t best = root_scan_wave<KIND, LPN, CPL>(a, R, q);
+    const uint64_t best = uni_u64(root_scan_wave<KIND, LPN, CPL>(a, R, q));
     st.evals = R.size;
-    st.cur = R.down[wkey_id(best)];
+    st.cur = uni(R.down[wkey_id(best)]);
     st.cur_d = wkey_dist(best);
     st.li = top - 1;
   } else {
@@ -377,7 +381,7 @@ __device__ void start_query(const SearchArgs& a, int64_t qi, const float (&q)[CP
     const SearchLayer& R = a.layer[top];
     const float sc = (KIND == kFP8) ? R.scale[0] : 1.0f;
     float dd = group_distance<KIND, LPN, CPL>(q, R.vec, sc, t, a.nchunks, a.metric, g == 0);
-    st.cur_d = __shfl(dd, 0);
+    st.cur_d = uni_f(dd);  // lane 0 holds group 0's distance
     st.cur = 0;
     st.li = top;
   }
@@ -414,32 +418,24 @@ __device__ bool advance(const SearchArgs& a, const float (&q)[CPL][8], WaveLds s
     }
     int wsize = st.wsize;
     bool layer_done = false;
-    // adjacency row fetched one expansion ahead for the entry expected to be
-    // expanded next (the second smallest unexpanded one); used only when it
-    // is indeed the next, so the expansion order is unchanged
-    int32_t pf_node = -1;
-    int32_t pf_u = -1;
-    float pf_sc = 1.0f;
     while (budget > 0) {
-      // smallest and second smallest unexpanded entries of W
-      int pos = -1, pos2 = -1;
-      for (int base = 0; base < wsize && pos2 < 0; base += 64) {
+      // smallest unexpanded entry of W
+      int pos = -1;
+      for (int base = 0; base < wsize; base += 64) {
         const int i = base + lane;
         const bool un = i < wsize && !(W[i] & 1ull);
-        uint64_t m = ballot(un);
-        if (m && pos < 0) {
+        const uint64_t m = ballot(un);
+        if (m) {
           pos = base + __ffsll((unsigned long long)m) - 1;
-          m &= m - 1;
+          break;
         }
-        if (m) pos2 = base + __ffsll((unsigned long long)m) - 1;
       }
       if (pos < 0) {
         layer_done = true;
         break;
       }
       --budget;
-      const uint64_t ck = W[pos];
-      const int32_t c2 = pos2 >= 0 ? wkey_id(W[pos2]) : -1;
+      const uint64_t ck = uni_u64(W[pos]);
       wave_sync();
       if (lane == 0) W[pos] = ck | 1ull;
       const int32_t c = wkey_id(ck);
@@ -448,17 +444,9 @@ __device__ bool advance(const SearchArgs& a, const float (&q)[CPL][8], WaveLds s
       // neighbour ids (and, for FP8 rows, their scales) and the visited filter
       int32_t u = -1;
       float usc = 1.0f;
-      if (c == pf_node) {
-        u = pf_u;
-        usc = pf_sc;
-      } else if (lane < L.deg) {
+      if (lane < L.deg) {
         u = L.adj[(int64_t)c * L.deg + lane];
         if (KIND == kFP8) usc = L.adj_scale[(int64_t)c * L.deg + lane];
-      }
-      pf_node = c2;
-      if (c2 >= 0 && lane < L.deg) {
-        pf_u = L.adj[(int64_t)c2 * L.deg + lane];
-        if (KIND == kFP8) pf_sc = L.adj_scale[(int64_t)c2 * L.deg + lane];
       }
       bool fresh = false;
       uint32_t h = 0;
@@ -505,15 +493,12 @@ __device__ bool advance(const SearchArgs& a, const float (&q)[CPL][8], WaveLds s
       const uint64_t key = lane < cnt ? s.ckey[lane] : ~0ull;
       bool keep = lane < cnt;
       if (keep && wsize >= efl) keep = key < wkey_strip(W[efl - 1]);
+      // lo = number of W entries below key (fixed-step lower bound: the trip
+      // count depends only on the wave-uniform list size)
       int lo = 0;
-      if (keep) {
-        int hi = wsize;
-        while (lo < hi) {
-          const int mid = (lo + hi) >> 1;
-          if (wkey_strip(W[mid]) < key) lo = mid + 1; else hi = mid;
-        }
-        if (lo < wsize && wkey_strip(W[lo]) == key) keep = false;  // already in W
-      }
+      for (int step = pow2_floor(wsize); step > 0; step >>= 1)
+        if (lo + step <= wsize && wkey_strip(W[lo + step - 1]) < key) lo += step;
+      if (keep && lo < wsize && wkey_strip(W[lo]) == key) keep = false;  // already in W
       const uint64_t km = ballot(keep);
       const int nk = popc64(km);
       if (nk == 0) continue;
@@ -526,14 +511,13 @@ __device__ bool advance(const SearchArgs& a, const float (&q)[CPL][8], WaveLds s
       }
       wave_sync();
       const int nsize = min(efl, wsize + nk);
+      const int nk_step = pow2_floor(nk);
       for (int i = lane; i < wsize; i += 64) {
         const uint64_t wv = W[i];
         const uint64_t ws = wkey_strip(wv);
-        int l2 = 0, h2 = nk;
-        while (l2 < h2) {
-          const int mid = (l2 + h2) >> 1;
-          if (s.ksorted[mid] < ws) l2 = mid + 1; else h2 = mid;
-        }
+        int l2 = 0;  // kept keys below W[i]
+        for (int step = nk_step; step > 0; step >>= 1)
+          if (l2 + step <= nk && s.ksorted[l2 + step - 1] < ws) l2 += step;
         const int np = i + l2;
         if (np < efl) Wn[np] = wv;
       }
@@ -551,8 +535,8 @@ __device__ bool advance(const SearchArgs& a, const float (&q)[CPL][8], WaveLds s
     if (!layer_done) return false;
     if (st.li == 0) return true;
     // hand the best node down the inter-layer edge
-    const uint64_t best = W[0];
-    st.cur = L.down[wkey_id(best)];
+    const uint64_t best = uni_u64(W[0]);
+    st.cur = uni(L.down[wkey_id(best)]);
     st.cur_d = wkey_dist(best);
     st.li -= 1;
     st.need_init = 1;
@@ -646,11 +630,18 @@ __global__ __launch_bounds__(512) void k_serve_step(SearchArgs a, ServeArgs sv, 
   const int64_t idx = (int64_t)blockIdx.x * waves_per_block + wave;
   if (idx >= sv.n_active) return;
   const int lane = lane_id(), t = lane % LPN;
-  const int32_t slot = sv.active[idx];
+  const int32_t slot = uni(sv.active[idx]);
   WaveLds s = carve(smem + (size_t)wave * per_wave_bytes, a.ef_cap, a.vis_bits);
   float q[CPL][8];
   load_query<CPL>(a.Q + (int64_t)slot * a.d, a.d, t, q);
   QState st = sv.states[slot];
+  st.li = uni(st.li);
+  st.need_init = uni(st.need_init);
+  st.wsize = uni(st.wsize);
+  st.cur = uni(st.cur);
+  st.cur_d = uni_f(st.cur_d);
+  st.k = uni(st.k);
+  st.ef0 = uni(st.ef0);
   char* base = sv.arena + sv.state_off[slot];
   uint64_t* gW = reinterpret_cast<uint64_t*>(base);
   int32_t* gvis = reinterpret_cast<int32_t*>(base + (size_t)sv.cap[slot] * 8);
@@ -723,7 +714,7 @@ __global__ __launch_bounds__(512) void k_search(SearchArgs a, int per_wave_bytes
     for (;;) {
       uint32_t qi = 0;
       if (lane_id() == 0) qi = atomicAdd(a.work_counter, 1u);
-      qi = __shfl(qi, 0);
+      qi = (uint32_t)uni((int32_t)qi);
       if ((int64_t)qi >= a.nq) break;
       search_one<KIND, LPN, CPL>(a, (int64_t)qi, s);
     }
