@@ -241,19 +241,36 @@ __device__ inline float tree_sum(float (&c)[CPL]) {
 
 // Butterfly over LPN consecutive lanes: after it every lane of the group
 // holds the same, tree-ordered total.
+// Lane exchange inside a row of 16 lanes through DPP (a VALU operand
+// modifier, no LDS round trip).  ctrl: 0xB1 quad_perm [1,0,3,2] (lane ^ 1),
+// 0x4E quad_perm [2,3,0,1] (lane ^ 2), 0x104 row_shl:4, 0x114 row_shr:4,
+// 0x128 row_ror:8 (lane ^ 8).
+template <int CTRL>
+__device__ inline float dpp_mov(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+// Butterfly sum over the LPN lanes of a group: step m adds the value of lane
+// ^ m, for m = 1, 2, 4, ...; every lane of the group ends with the same sum.
+// Must be reached by the whole wave.
 template <int LPN>
 __device__ inline float group_sum(float v) {
+  if (LPN >= 2) v = v + dpp_mov<0xB1>(v);
+  if (LPN >= 4) v = v + dpp_mov<0x4E>(v);
+  if (LPN >= 8) {
+    // lane ^ 4: lanes with bit 2 clear read lane + 4, the others lane - 4
+    const float up = dpp_mov<0x104>(v), down = dpp_mov<0x114>(v);
+    v = v + ((lane_id() & 4) ? down : up);
+  }
+  if (LPN >= 16) v = v + dpp_mov<0x128>(v);
 #pragma unroll
-  for (int m = 1; m < LPN; m *= 2) v = v + __shfl_xor(v, m, 64);
+  for (int m = 32; m < LPN; m *= 2) v = v + __shfl_xor(v, m, 64);
   return v;
 }
 
-// Distance between a query slice held in registers (this lane's chunks
-// [t*CPL, (t+1)*CPL)) and row `row` of a stored layer.  All LPN lanes of the
-// group return the same value.
-// `valid` false skips the loads (the lane still joins the butterfly, so a
-// group whose candidate slot is empty keeps the wave's shuffles uniform).
-// Distances of NR rows per lane group.  Every chunk the lane needs is
+// Distances between a query slice held in registers (this lane's chunks
+// [t*CPL, (t+1)*CPL)) and NR rows per lane group; all LPN lanes of a group
+// return the same values, and every lane joins the butterfly.  Every chunk the lane needs is
 // loaded first, without branches (chunks past the row are clamped to chunk
 // 0 and dropped), so that all NR * CPL loads are in flight together; then
 // the chunks are decoded and reduced exactly as group_distance does.  rows[r]
