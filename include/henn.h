@@ -102,6 +102,9 @@ typedef struct {
 #define HENN_SEARCH_ROOT_VALU 8u      /* scan a complete-graph root with the tiled
                                          VALU kernel instead of the matrix-core
                                          shortlist + exact check (same results) */
+#define HENN_SEARCH_VIS32 16u         /* keep full 32-bit ids in the visited table
+                                         even where 16-bit tags are exact (same
+                                         results; for tests) */
 
 typedef struct {
   uint32_t struct_size;   /* = sizeof(henn_search_params) */

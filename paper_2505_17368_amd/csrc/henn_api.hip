@@ -637,9 +637,10 @@ henn_status henn_search_batch(const henn_index* idx, const float* Q, int64_t nq,
     sh.lanes_per_vec = lpn;
     sh.chunks_per_lane = cpl;
     sh.vis_bits = a.vis_bits;
+    a.vis16 = (vis_tags16(idx->n, a.vis_bits) && !(sp->flags & HENN_SEARCH_VIS32)) ? 1 : 0;
     int wpb = want_wpb > 0 ? want_wpb : 4;
     if (wpb != 1 && wpb != 2 && wpb != 4 && wpb != 8) return fail(HENN_E_INVAL, "waves_per_block");
-    while (wpb > 1 && search_lds_per_wave(a.ef_cap, a.vis_bits) * wpb > 65536) wpb /= 2;
+    while (wpb > 1 && search_lds_per_wave(a.ef_cap, a.vis_bits, a.vis16 != 0) * wpb > 65536) wpb /= 2;
     sh.waves_per_block = wpb;
     sh.persistent = want_pers;
     sh.blocks = 0;

@@ -27,8 +27,8 @@
 
 namespace henn {
 
-size_t search_lds_per_wave(int ef_cap, int vis_bits) {
-  return (size_t)ef_cap * 16 + 64 * 8 * 3 + ((size_t)1 << vis_bits) * 4 + 64 * 4;
+size_t search_lds_per_wave(int ef_cap, int vis_bits, bool vis16) {
+  return (size_t)ef_cap * 16 + 64 * 8 * 3 + ((size_t)1 << vis_bits) * (vis16 ? 2 : 4) + 64 * 4;
 }
 
 struct WaveLds {
@@ -37,25 +37,43 @@ struct WaveLds {
   uint64_t* ckey;     // candidate keys (by compacted slot)
   uint64_t* kstage;   // kept keys, arrival order
   uint64_t* ksorted;  // kept keys, ascending
-  int32_t* vis;
+  void* vis;  // 2^vis_bits entries: uint16 tags or int32 ids
   int32_t* cid;
 };
 
-__device__ inline WaveLds carve(char* base, int ef_cap, int vis_bits) {
+__device__ inline WaveLds carve(char* base, int ef_cap, int vis_bits, int vis16) {
   WaveLds s;
   s.W = reinterpret_cast<uint64_t*>(base);
   s.Wn = s.W + ef_cap;
   s.ckey = s.Wn + ef_cap;
   s.kstage = s.ckey + 64;
   s.ksorted = s.kstage + 64;
-  s.vis = reinterpret_cast<int32_t*>(s.ksorted + 64);
-  s.cid = s.vis + (1 << vis_bits);
+  s.vis = s.ksorted + 64;
+  s.cid = reinterpret_cast<int32_t*>(static_cast<char*>(s.vis) +
+                                     ((size_t)1 << vis_bits) * (vis16 ? 2 : 4));
   return s;
 }
 
-__device__ inline uint32_t vis_hash(int32_t u, int bits) {
-  return ((uint32_t)u * 2654435761u) >> (32 - bits);
+// Visited table slot and stored value of id u (see vis_tags16).
+__device__ inline void vis_slot(int32_t u, int bits, int vis16, uint32_t& h, uint32_t& tag) {
+  if (vis16) {
+    h = (uint32_t)u & ((1u << bits) - 1u);
+    tag = ((uint32_t)u >> bits) + 1u;
+  } else {
+    h = ((uint32_t)u * 2654435761u) >> (32 - bits);
+    tag = (uint32_t)u;
+  }
 }
+__device__ inline uint32_t vis_get(const void* vis, int vis16, uint32_t h) {
+  return vis16 ? (uint32_t) static_cast<const uint16_t*>(vis)[h] : static_cast<const uint32_t*>(vis)[h];
+}
+__device__ inline void vis_put(void* vis, int vis16, uint32_t h, uint32_t tag) {
+  if (vis16)
+    static_cast<uint16_t*>(vis)[h] = (uint16_t)tag;
+  else
+    static_cast<uint32_t*>(vis)[h] = tag;
+}
+
 
 // Largest power of two <= v (0 for v <= 0).
 __device__ inline int pow2_floor(int v) { return v <= 0 ? 0 : 1 << (31 - __clz(v)); }
@@ -391,6 +409,9 @@ __device__ void start_query(const SearchArgs& a, int64_t qi, const float (&q)[CP
 // free).  Returns true once the layer-0 beam has no unexpanded entry; then
 // W holds the final list (st.wsize entries).  W / Wn are this wave's two LDS
 // list buffers and are swapped as the list is rewritten.
+// Rows each lane group gathers per pass of an expansion.
+constexpr int kGatherRows = 2;
+
 template <int KIND, int LPN, int CPL>
 __device__ bool advance(const SearchArgs& a, const float (&q)[CPL][8], WaveLds s, uint64_t*& W,
                         uint64_t*& Wn, QState& st, int budget) {
@@ -406,11 +427,16 @@ __device__ bool advance(const SearchArgs& a, const float (&q)[CPL][8], WaveLds s
         st.evals0 = st.evals;
       }
       st.evals += 1;  // the entry (its distance is carried down, counted per layer)
-      for (int i = lane; i < vis_n; i += 64) s.vis[i] = -1;
+      // empty: tag 0 (16-bit) or id -1 (32-bit); cleared as 32-bit words
+      const int vis_words = a.vis16 ? vis_n / 2 : vis_n;
+      const uint32_t empty = a.vis16 ? 0u : 0xffffffffu;
+      for (int i = lane; i < vis_words; i += 64) static_cast<uint32_t*>(s.vis)[i] = empty;
       wave_sync();
       if (lane == 0) {
         W[0] = wkey(st.cur_d, st.cur);
-        s.vis[vis_hash(st.cur, a.vis_bits)] = st.cur;
+        uint32_t h0, t0;
+        vis_slot(st.cur, a.vis_bits, a.vis16, h0, t0);
+        vis_put(s.vis, a.vis16, h0, t0);
       }
       st.wsize = 1;
       st.need_init = 0;
@@ -449,13 +475,13 @@ __device__ bool advance(const SearchArgs& a, const float (&q)[CPL][8], WaveLds s
         if (KIND == kFP8) usc = L.adj_scale[(int64_t)c * L.deg + lane];
       }
       bool fresh = false;
-      uint32_t h = 0;
+      uint32_t h = 0, tag = 0;
       if (u >= 0) {
-        h = vis_hash(u, a.vis_bits);
-        fresh = s.vis[h] != u;
+        vis_slot(u, a.vis_bits, a.vis16, h, tag);
+        fresh = vis_get(s.vis, a.vis16, h) != tag;
       }
       wave_sync();
-      if (fresh) s.vis[h] = u;
+      if (fresh) vis_put(s.vis, a.vis16, h, tag);
       const uint64_t fm = ballot(fresh);
       const int cnt = popc64(fm);
       // the scales ride in kstage, which is free until the merge below
@@ -467,24 +493,28 @@ __device__ bool advance(const SearchArgs& a, const float (&q)[CPL][8], WaveLds s
       wave_sync();
       st.evals += cnt;
 
-      // gather + distance, 2G rows per pass with all their loads in flight
-      // together (an empty slot re-reads the pass's first row)
-      for (int base = 0; base < cnt; base += 2 * G) {
-        const int ci0 = base + g, ci1 = base + G + g;
-        const bool v0 = ci0 < cnt, v1 = ci1 < cnt;
-        const int32_t id0 = s.cid[v0 ? ci0 : base];
-        const int32_t id1 = v1 ? s.cid[ci1] : id0;
-        const float sc[2] = {(KIND == kFP8) ? csc[v0 ? ci0 : base] : 1.0f,
-                             (KIND == kFP8 && v1) ? csc[ci1] : 1.0f};
-        const void* const rows[2] = {
-            static_cast<const char*>(L.vec) + (int64_t)id0 * L.row_bytes,
-            static_cast<const char*>(L.vec) + (int64_t)id1 * L.row_bytes};
-        const bool vd[2] = {v0, v1};
-        float dist[2];
-        group_distances<KIND, LPN, CPL, 2>(q, rows, sc, t, a.nchunks, a.metric, vd, dist);
+      // gather + distance, kGatherRows * G rows per pass with all their loads
+      // in flight together (an empty slot re-reads the pass's first row)
+      for (int base = 0; base < cnt; base += kGatherRows * G) {
+        const void* rows[kGatherRows];
+        float sc[kGatherRows];
+        bool vd[kGatherRows];
+        int32_t ids[kGatherRows];
+#pragma unroll
+        for (int r = 0; r < kGatherRows; ++r) {
+          const int ci = base + r * G + g;
+          vd[r] = ci < cnt;
+          ids[r] = s.cid[vd[r] ? ci : base];
+          sc[r] = (KIND == kFP8) ? csc[vd[r] ? ci : base] : 1.0f;
+          rows[r] = static_cast<const char*>(L.vec) + (int64_t)ids[r] * L.row_bytes;
+        }
+        float dist[kGatherRows];
+        group_distances<KIND, LPN, CPL, kGatherRows>(q, rows, sc, t, a.nchunks, a.metric, vd,
+                                                     dist);
         if (t == 0) {
-          if (v0) s.ckey[ci0] = wkey(dist[0], id0);
-          if (v1) s.ckey[ci1] = wkey(dist[1], id1);
+#pragma unroll
+          for (int r = 0; r < kGatherRows; ++r)
+            if (vd[r]) s.ckey[base + r * G + g] = wkey(dist[r], ids[r]);
         }
       }
       wave_sync();
@@ -631,7 +661,7 @@ __global__ __launch_bounds__(512) void k_serve_step(SearchArgs a, ServeArgs sv, 
   if (idx >= sv.n_active) return;
   const int lane = lane_id(), t = lane % LPN;
   const int32_t slot = uni(sv.active[idx]);
-  WaveLds s = carve(smem + (size_t)wave * per_wave_bytes, a.ef_cap, a.vis_bits);
+  WaveLds s = carve(smem + (size_t)wave * per_wave_bytes, a.ef_cap, a.vis_bits, a.vis16);
   float q[CPL][8];
   load_query<CPL>(a.Q + (int64_t)slot * a.d, a.d, t, q);
   QState st = sv.states[slot];
@@ -644,13 +674,13 @@ __global__ __launch_bounds__(512) void k_serve_step(SearchArgs a, ServeArgs sv, 
   st.ef0 = uni(st.ef0);
   char* base = sv.arena + sv.state_off[slot];
   uint64_t* gW = reinterpret_cast<uint64_t*>(base);
-  int32_t* gvis = reinterpret_cast<int32_t*>(base + (size_t)sv.cap[slot] * 8);
-  const int vis_n = 1 << a.vis_bits;
+  uint32_t* gvis = reinterpret_cast<uint32_t*>(base + (size_t)sv.cap[slot] * 8);
+  const int vis_n = (1 << a.vis_bits) / (a.vis16 ? 2 : 1);  // 32-bit words of the table
   if (st.li == kSlotNew) {
     start_query<KIND, LPN, CPL>(a, slot, q, st);
   } else if (!st.need_init) {
     for (int i = lane; i < st.wsize; i += 64) s.W[i] = gW[i];
-    for (int i = lane; i < vis_n; i += 64) s.vis[i] = gvis[i];
+    for (int i = lane; i < vis_n; i += 64) static_cast<uint32_t*>(s.vis)[i] = gvis[i];
     wave_sync();
   }
   uint64_t* W = s.W;
@@ -667,7 +697,7 @@ __global__ __launch_bounds__(512) void k_serve_step(SearchArgs a, ServeArgs sv, 
     if (lane == 0) sv.done_slots[pos] = slot;
   } else if (!st.need_init) {
     for (int i = lane; i < st.wsize; i += 64) gW[i] = W[i];
-    for (int i = lane; i < vis_n; i += 64) gvis[i] = s.vis[i];
+    for (int i = lane; i < vis_n; i += 64) gvis[i] = static_cast<uint32_t*>(s.vis)[i];
   }
   if (lane == 0) sv.states[slot] = st;
 }
@@ -698,7 +728,7 @@ __global__ void k_serve_admit(const float* staged_q, const int32_t* meta, int n_
 
 template <int KIND, int LPN, int CPL>
 static void launch_serve_one(const SearchArgs& a, const ServeArgs& sv, int wpb, hipStream_t st) {
-  const size_t per_wave = search_lds_per_wave(a.ef_cap, a.vis_bits);
+  const size_t per_wave = search_lds_per_wave(a.ef_cap, a.vis_bits, a.vis16 != 0);
   const unsigned blocks = (unsigned)((sv.n_active + wpb - 1) / wpb);
   hipLaunchKernelGGL((k_serve_step<KIND, LPN, CPL>), dim3(blocks), dim3(64 * wpb),
                      per_wave * wpb, st, a, sv, (int)per_wave, wpb);
@@ -709,7 +739,7 @@ __global__ __launch_bounds__(512) void k_search(SearchArgs a, int per_wave_bytes
                                                 int waves_per_block, int persistent) {
   extern __shared__ __align__(16) char smem[];
   const int wave = threadIdx.x >> 6;
-  WaveLds s = carve(smem + (size_t)wave * per_wave_bytes, a.ef_cap, a.vis_bits);
+  WaveLds s = carve(smem + (size_t)wave * per_wave_bytes, a.ef_cap, a.vis_bits, a.vis16);
   if (persistent) {
     for (;;) {
       uint32_t qi = 0;
@@ -728,7 +758,7 @@ __global__ void k_reset_counter(uint32_t* c) { *c = 0u; }
 
 template <int KIND, int LPN, int CPL>
 static void launch_one(const SearchArgs& a, const LaunchShape& sh, hipStream_t st) {
-  const size_t per_wave = search_lds_per_wave(a.ef_cap, a.vis_bits);
+  const size_t per_wave = search_lds_per_wave(a.ef_cap, a.vis_bits, a.vis16 != 0);
   const int wpb = sh.waves_per_block;
   const size_t lds = per_wave * wpb;
   if (sh.persistent) {
