@@ -523,6 +523,8 @@ __device__ bool advance(const SearchArgs& a, const float (&q)[CPL][8], WaveLds s
       const uint64_t key = lane < cnt ? s.ckey[lane] : ~0ull;
       bool keep = lane < cnt;
       if (keep && wsize >= efl) keep = key < wkey_strip(W[efl - 1]);
+      // nothing can enter a full list: skip the merge (common late in a search)
+      if (!ballot(keep)) continue;
       // lo = number of W entries below key (fixed-step lower bound: the trip
       // count depends only on the wave-uniform list size)
       int lo = 0;
