@@ -82,10 +82,27 @@ __global__ __launch_bounds__(256, 2) void k_gram_topk(
   float bq[KH];
   {
     const float* qr = qsrc + (qvalid ? qrow : 0) * qstride;
+    // float4 loads when rows and widths are 16-byte granular (then a float4
+    // starting below qd lies wholly below it).  The kNN graph's blocks scan a
+    // whole layer, so their prologue stays scalar (fewer live registers).
+    const bool vec4 = !SELF && (qstride & 3) == 0 && (qd & 3) == 0 &&
+                      (reinterpret_cast<uintptr_t>(qsrc) & 15) == 0;
+    if (vec4) {
 #pragma unroll
-    for (int kk = 0; kk < KH; ++kk) {
-      const int e = h * KH + kk;
-      bq[kk] = qr[e < qd ? e : 0];
+      for (int k4 = 0; k4 < KH / 4; ++k4) {
+        const int e = h * KH + 4 * k4;
+        const float4 v = *reinterpret_cast<const float4*>(qr + (e < qd ? e : 0));
+        bq[4 * k4 + 0] = v.x;
+        bq[4 * k4 + 1] = v.y;
+        bq[4 * k4 + 2] = v.z;
+        bq[4 * k4 + 3] = v.w;
+      }
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < KH; ++kk) {
+        const int e = h * KH + kk;
+        bq[kk] = qr[e < qd ? e : 0];
+      }
     }
 #pragma unroll
     for (int kk = 0; kk < KH; ++kk) {
@@ -536,10 +553,11 @@ __global__ __launch_bounds__(256) void k_knn_exact(const float* vec, int64_t siz
   X(16, 2) X(4, 8) X(16, 4) X(16, 8)
 
 int root_gram_splits(int64_t nq, int64_t root_size, int64_t* rows_per_split) {
-  // about 1,024 workgroups (two waves of 512 resident), at least 8 tiles each
+  // about 512 workgroups (one resident wave of them), at least 16 tiles each
+  // so that a block's query prologue is amortised
   const int64_t qblocks = (nq + 127) / 128;
-  int64_t splits = (1024 + qblocks - 1) / qblocks;
-  const int64_t max_splits = std::max<int64_t>(1, root_size / (8 * kTileC));
+  int64_t splits = (512 + qblocks - 1) / qblocks;
+  const int64_t max_splits = std::max<int64_t>(1, root_size / (16 * kTileC));
   splits = std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(splits, max_splits), 64));
   int64_t per = (root_size + splits - 1) / splits;
   per = (per + kTileC - 1) / kTileC * kTileC;
