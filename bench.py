@@ -295,13 +295,14 @@ def main():
             el += time.time() - t
             counts.append(r.counters)
             done += len(sub)
-            if el >= args.cpu_seconds or done >= 4 * nq:
+            if el >= args.cpu_seconds or done >= 64 * nq:
                 break
             m = min(nq, m * 2)
         oracle_counts = np.concatenate(counts).astype(np.float64)
         cpu = {"value": round(done / el, 2), "unit": "queries/s", "cores": threads,
                "kind": "oracle",
-               "sample": f"{done} queries of the {nq}-query workload (same index, ef={ef}, "
+               "sample": f"{done} oracle searches over the {nq} workload queries taken in "
+                         f"order and repeated (same index, ef={ef}, "
                          f"k={k}), FP64 C oracle, {threads} threads, {el:.1f}s"}
         log(f"cpu baseline {cpu['value']} QPS on {threads} threads")
 
