@@ -156,9 +156,10 @@ struct ServeArgs {
   const int32_t* cap;         // [max_slots] list capacity of the slot (power of two)
   char* arena;
   int32_t* done_count;        // completions of this tick
-  int32_t* done_slots;        // [max_slots] slot of completion i
-  int32_t* out_ids;           // [max_slots][k_max] result row of completion i
-  float* out_dist;
+  int32_t* done_clear;        // the next tick's counter, cleared by this kernel
+  // completion i of the tick: row i of [max_slots][1 + 2 k_max] words =
+  // its slot, k_max ids, k_max distances (FP32 bits), copied back in one piece
+  int32_t* done_rows;
 };
 
 struct LaunchShape {

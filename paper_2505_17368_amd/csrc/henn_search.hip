@@ -660,6 +660,7 @@ __global__ __launch_bounds__(512) void k_serve_step(SearchArgs a, ServeArgs sv, 
   extern __shared__ __align__(16) char smem[];
   const int wave = threadIdx.x >> 6;
   const int64_t idx = (int64_t)blockIdx.x * waves_per_block + wave;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *sv.done_clear = 0;
   if (idx >= sv.n_active) return;
   const int lane = lane_id(), t = lane % LPN;
   const int32_t slot = uni(sv.active[idx]);
@@ -693,10 +694,11 @@ __global__ __launch_bounds__(512) void k_serve_step(SearchArgs a, ServeArgs sv, 
     int pos = 0;
     if (lane == 0) pos = atomicAdd(sv.done_count, 1);
     pos = __shfl(pos, 0);
-    finish_query<KIND, LPN, CPL>(a, q, W, Wn, st, sv.out_ids + (int64_t)pos * a.k_max,
-                                 sv.out_dist + (int64_t)pos * a.k_max, nullptr);
+    int32_t* row = sv.done_rows + (int64_t)pos * (1 + 2 * a.k_max);
+    finish_query<KIND, LPN, CPL>(a, q, W, Wn, st, row + 1,
+                                 reinterpret_cast<float*>(row + 1 + a.k_max), nullptr);
     st.li = kSlotDone;
-    if (lane == 0) sv.done_slots[pos] = slot;
+    if (lane == 0) row[0] = slot;
   } else if (!st.need_init) {
     for (int i = lane; i < st.wsize; i += 64) gW[i] = W[i];
     for (int i = lane; i < vis_n; i += 64) gvis[i] = static_cast<uint32_t*>(s.vis)[i];

@@ -71,11 +71,6 @@ struct Pending {
   int64_t tag;
 };
 
-struct Done {
-  int64_t tag;
-  std::vector<int32_t> ids;
-  std::vector<float> dist;
-};
 
 }  // namespace henn
 
@@ -94,11 +89,11 @@ struct henn_server {
   QState* states = nullptr;
   int64_t* state_off = nullptr;
   char* arena = nullptr;
-  int32_t *active_d = nullptr, *done_d = nullptr;  // done_d[0] count, then slots
+  // done_d: two completion counters, used by alternate ticks
+  int32_t* done_d = nullptr;
   float* stage_q_d = nullptr;
   int32_t* stage_meta_d = nullptr;
-  int32_t* out_ids_d = nullptr;
-  float* out_dist_d = nullptr;
+  int32_t* rows_d = nullptr;  // completion rows of a tick (ServeArgs::done_rows)
   // complete-graph root on matrix cores (prepared roots only): each admitted
   // request's root key, its shortlist scratch and the per-slot keys
   uint64_t* root_keys = nullptr;
@@ -108,10 +103,8 @@ struct henn_server {
   // pinned host
   float* stage_q_h = nullptr;
   int32_t* stage_meta_h = nullptr;
-  int32_t* active_h = nullptr;
   int32_t* done_h = nullptr;
-  int32_t* out_ids_h = nullptr;
-  float* out_dist_h = nullptr;
+  int32_t* rows_h = nullptr;
   // host state
   ArenaAlloc* alloc = nullptr;
   std::deque<Pending> pending;
@@ -119,7 +112,10 @@ struct henn_server {
   std::vector<int32_t> active;
   std::vector<int64_t> slot_tag, slot_off, slot_bytes;
   std::vector<int32_t> slot_kk;
-  std::deque<Done> done;
+  // completed, not yet polled: tags, and per completion k_max ids then
+  // k_max distance bits
+  std::deque<int64_t> done_tags;
+  std::deque<int32_t> done_vals;
   int64_t ticks = 0, admitted = 0, completed = 0, max_active = 0;
 };
 
@@ -142,21 +138,17 @@ static void srv_release(henn_server* s) {
   (void)hipFree(s->states);
   (void)hipFree(s->state_off);
   (void)hipFree(s->arena);
-  (void)hipFree(s->active_d);
   (void)hipFree(s->done_d);
   (void)hipFree(s->stage_q_d);
   (void)hipFree(s->stage_meta_d);
-  (void)hipFree(s->out_ids_d);
-  (void)hipFree(s->out_dist_d);
+  (void)hipFree(s->rows_d);
   (void)hipFree(s->root_keys);
   (void)hipFree(s->root_sl);
   (void)hipFree(s->slot_root);
   (void)hipHostFree(s->stage_q_h);
   (void)hipHostFree(s->stage_meta_h);
-  (void)hipHostFree(s->active_h);
   (void)hipHostFree(s->done_h);
-  (void)hipHostFree(s->out_ids_h);
-  (void)hipHostFree(s->out_dist_h);
+  (void)hipHostFree(s->rows_h);
   if (s->st) (void)hipStreamDestroy(s->st);
   delete s->alloc;
   delete s;
@@ -234,12 +226,11 @@ henn_status henn_server_create(const henn_index* idx, const henn_server_params* 
     dmalloc(&s->states, M);
     dmalloc(&s->state_off, M);
     dmalloc(&s->arena, p->pool_bytes);
-    dmalloc(&s->active_d, M);
-    dmalloc(&s->done_d, M + 1);
+    dmalloc(&s->done_d, 2);
+    HENN_HIP(hipMemset(s->done_d, 0, sizeof(int32_t) * 2));
     dmalloc(&s->stage_q_d, M * s->d);
-    dmalloc(&s->stage_meta_d, M * 6);
-    dmalloc(&s->out_ids_d, M * s->k_max);
-    dmalloc(&s->out_dist_d, M * s->k_max);
+    dmalloc(&s->stage_meta_d, M * 7);  // admission metadata [n_new][6], then the active list
+    dmalloc(&s->rows_d, M * (1 + 2 * s->k_max));
     if (idx->root.size > 0) {
       // shortlist entries for the largest admission batch's split
       int64_t most = 0;
@@ -253,11 +244,9 @@ henn_status henn_server_create(const henn_index* idx, const henn_server_params* 
       dmalloc(&s->root_sl, 2 * s->root_sl_entries);  // values, then positions
     }
     hmalloc(&s->stage_q_h, M * s->d);
-    hmalloc(&s->stage_meta_h, M * 6);
-    hmalloc(&s->active_h, M);
-    hmalloc(&s->done_h, M + 1);
-    hmalloc(&s->out_ids_h, M * s->k_max);
-    hmalloc(&s->out_dist_h, M * s->k_max);
+    hmalloc(&s->stage_meta_h, M * 7);
+    hmalloc(&s->done_h, 2);
+    hmalloc(&s->rows_h, M * (1 + 2 * s->k_max));
     s->alloc = new ArenaAlloc(p->pool_bytes);
     s->slot_tag.assign(M, 0);
     s->slot_off.assign(M, 0);
@@ -374,8 +363,15 @@ henn_status henn_server_tick(henn_server* s, int32_t* n_active_out) {
     if (n_new > 0) {
       HENN_HIP(hipMemcpyAsync(s->stage_q_d, s->stage_q_h, sizeof(float) * n_new * s->d,
                               hipMemcpyHostToDevice, s->st));
-      HENN_HIP(hipMemcpyAsync(s->stage_meta_d, s->stage_meta_h, sizeof(int32_t) * n_new * 6,
-                              hipMemcpyHostToDevice, s->st));
+    }
+    // one H2D copy: the admission metadata, then the active list
+    const int n_active = (int)s->active.size();
+    memcpy(s->stage_meta_h + n_new * 6, s->active.data(), sizeof(int32_t) * n_active);
+    if (n_new + n_active > 0)
+      HENN_HIP(hipMemcpyAsync(s->stage_meta_d, s->stage_meta_h,
+                              sizeof(int32_t) * (n_new * 6 + n_active), hipMemcpyHostToDevice,
+                              s->st));
+    if (n_new > 0) {
       if (s->slot_root) {
         // the new requests' complete-root scans, on matrix cores
         int64_t per = 0;
@@ -395,15 +391,13 @@ henn_status henn_server_tick(henn_server* s, int32_t* n_active_out) {
                          s->slot_ef, s->state_off, s->cap, s->states, s->root_keys,
                          s->slot_root, s->st);
     }
-    const int n_active = (int)s->active.size();
     s->max_active = std::max<int64_t>(s->max_active, n_active);
     if (n_active_out) *n_active_out = n_active;
     if (n_active == 0) return HENN_OK;
-    // 2) one step of every active request
-    memcpy(s->active_h, s->active.data(), sizeof(int32_t) * n_active);
-    HENN_HIP(hipMemcpyAsync(s->active_d, s->active_h, sizeof(int32_t) * n_active,
-                            hipMemcpyHostToDevice, s->st));
-    HENN_HIP(hipMemsetAsync(s->done_d, 0, sizeof(int32_t), s->st));
+    // 2) one step of every active request; completions are counted in
+    //    done_d[c] (c = tick parity) while the kernel clears done_d[c ^ 1] for
+    //    the next tick
+    const int c = (int)(s->ticks & 1);
     a.Q = s->slot_q;
     a.nq = s->p.max_slots;
     a.k_arr = s->slot_k;
@@ -413,42 +407,36 @@ henn_status henn_server_tick(henn_server* s, int32_t* n_active_out) {
       a.root_splits = 1;
     }
     ServeArgs sv;
-    sv.active = s->active_d;
+    sv.active = s->stage_meta_d + n_new * 6;
     sv.n_active = n_active;
     sv.budget = s->p.steps_per_tick;
     sv.states = s->states;
     sv.state_off = s->state_off;
     sv.cap = s->cap;
     sv.arena = s->arena;
-    sv.done_count = s->done_d;
-    sv.done_slots = s->done_d + 1;
-    sv.out_ids = s->out_ids_d;
-    sv.out_dist = s->out_dist_d;
+    sv.done_count = s->done_d + c;
+    sv.done_clear = s->done_d + (c ^ 1);
+    sv.done_rows = s->rows_d;
     if (!launch_serve_step(idx->storage, a, sv, s->shape, s->st))
       return srv_fail(HENN_E_UNSUPPORTED, "no serving kernel for this shape");
     HENN_HIP(hipGetLastError());
     // 3) completions: count, then the finished slots and their rows
-    HENN_HIP(hipMemcpyAsync(s->done_h, s->done_d, sizeof(int32_t), hipMemcpyDeviceToHost, s->st));
+    HENN_HIP(hipMemcpyAsync(s->done_h, s->done_d + c, sizeof(int32_t), hipMemcpyDeviceToHost,
+                            s->st));
     HENN_HIP(hipStreamSynchronize(s->st));
     const int nd = s->done_h[0];
     ++s->ticks;
     if (nd > 0) {
-      HENN_HIP(hipMemcpyAsync(s->done_h + 1, s->done_d + 1, sizeof(int32_t) * nd,
-                              hipMemcpyDeviceToHost, s->st));
-      HENN_HIP(hipMemcpyAsync(s->out_ids_h, s->out_ids_d, sizeof(int32_t) * nd * s->k_max,
-                              hipMemcpyDeviceToHost, s->st));
-      HENN_HIP(hipMemcpyAsync(s->out_dist_h, s->out_dist_d, sizeof(float) * nd * s->k_max,
+      const int words = 1 + 2 * s->k_max;
+      HENN_HIP(hipMemcpyAsync(s->rows_h, s->rows_d, sizeof(int32_t) * nd * words,
                               hipMemcpyDeviceToHost, s->st));
       HENN_HIP(hipStreamSynchronize(s->st));
       std::vector<char> finished(s->p.max_slots, 0);
       for (int i = 0; i < nd; ++i) {
-        const int32_t slot = s->done_h[1 + i];
-        Done r;
-        r.tag = s->slot_tag[slot];
-        r.ids.assign(s->out_ids_h + (int64_t)i * s->k_max, s->out_ids_h + (int64_t)(i + 1) * s->k_max);
-        r.dist.assign(s->out_dist_h + (int64_t)i * s->k_max,
-                      s->out_dist_h + (int64_t)(i + 1) * s->k_max);
-        s->done.push_back(std::move(r));
+        const int32_t* row = s->rows_h + (int64_t)i * words;
+        const int32_t slot = row[0];
+        s->done_tags.push_back(s->slot_tag[slot]);
+        s->done_vals.insert(s->done_vals.end(), row + 1, row + words);
         s->alloc->release(s->slot_off[slot], s->slot_bytes[slot]);
         s->free_slots.push_back(slot);
         finished[slot] = 1;
@@ -473,12 +461,14 @@ henn_status henn_server_poll(henn_server* s, int32_t max_results, int64_t* tags,
                              float* dist, int32_t* n_out) {
   if (!s || !n_out) return srv_fail(HENN_E_INVAL, "null argument");
   int n = 0;
-  while (n < max_results && !s->done.empty()) {
-    const Done& r = s->done.front();
-    if (tags) tags[n] = r.tag;
-    if (ids) memcpy(ids + (int64_t)n * s->k_max, r.ids.data(), sizeof(int32_t) * s->k_max);
-    if (dist) memcpy(dist + (int64_t)n * s->k_max, r.dist.data(), sizeof(float) * s->k_max);
-    s->done.pop_front();
+  const int K = s->k_max;
+  while (n < max_results && !s->done_tags.empty()) {
+    if (tags) tags[n] = s->done_tags.front();
+    auto it = s->done_vals.begin();
+    if (ids) std::copy(it, it + K, ids + (int64_t)n * K);
+    if (dist) std::copy(it + K, it + 2 * K, reinterpret_cast<int32_t*>(dist) + (int64_t)n * K);
+    s->done_vals.erase(it, it + 2 * K);
+    s->done_tags.pop_front();
     ++n;
   }
   *n_out = n;
@@ -494,7 +484,7 @@ henn_status henn_server_stats(const henn_server* s, henn_server_stats_t* out) {
   out->ticks = s->ticks;
   out->pool_bytes_used = s->alloc->used();
   out->max_active = s->max_active;
-  out->done_queued = (int64_t)s->done.size();
+  out->done_queued = (int64_t)s->done_tags.size();
   return HENN_OK;
 }
 

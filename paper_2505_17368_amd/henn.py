@@ -436,10 +436,17 @@ class Server:
         _check(load_library().henn_server_tick(self._s, ctypes.byref(n)))
         return n.value
 
-    def poll(self, max_results: int = 1 << 16):
-        tags = np.zeros(max_results, dtype=np.int64)
-        ids = np.zeros((max_results, self.k_max), dtype=np.int32)
-        dist = np.zeros((max_results, self.k_max), dtype=np.float32)
+    def poll(self, max_results: int | None = None):
+        if max_results is None:
+            st = ServerStats()
+            _check(load_library().henn_server_stats(self._s, ctypes.byref(st)))
+            max_results = int(st.done_queued)
+        if max_results <= 0:
+            return (np.zeros(0, dtype=np.int64), np.zeros((0, self.k_max), dtype=np.int32),
+                    np.zeros((0, self.k_max), dtype=np.float32))
+        tags = np.empty(max_results, dtype=np.int64)
+        ids = np.empty((max_results, self.k_max), dtype=np.int32)
+        dist = np.empty((max_results, self.k_max), dtype=np.float32)
         n = ctypes.c_int32()
         _check(load_library().henn_server_poll(self._s, max_results,
                                                tags.ctypes.data_as(ctypes.c_void_p),
