@@ -156,47 +156,62 @@ __device__ inline float fp8_to_f32(uint32_t b) {
   return (b & 0x80u) ? -mag : mag;
 }
 
+// One chunk of 8 coordinates of a stored row: fetch() issues the load,
+// decode() turns it into FP32 values (exactly).  FP8 rows decode with
+// gfx950's packed converter (OCP E4M3; two codes per instruction, the low
+// byte first); fp8_to_f32 above is the same map written out, used where
+// rows are decoded once.
 template <int KIND>
-struct Chunk;
-
+struct ChunkRaw;
 template <>
-struct Chunk<kF32> {
-  static constexpr int kBytes = 32;
-  __device__ static inline void load(const void* row, int c, float (&v)[8]) {
+struct ChunkRaw<kF32> {
+  float4 a, b;
+  __device__ inline void fetch(const void* row, int c) {
     const float4* p = reinterpret_cast<const float4*>(static_cast<const float*>(row) + c * 8);
-    const float4 a = p[0];
-    const float4 b = p[1];
+    a = p[0];
+    b = p[1];
+  }
+  __device__ inline void decode(float (&v)[8]) const {
     v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
     v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
   }
 };
-
 template <>
-struct Chunk<kBF16> {
-  static constexpr int kBytes = 16;
-  __device__ static inline void load(const void* row, int c, float (&v)[8]) {
-    const uint4 a = *reinterpret_cast<const uint4*>(static_cast<const uint16_t*>(row) + c * 8);
+struct ChunkRaw<kBF16> {
+  uint4 a;
+  __device__ inline void fetch(const void* row, int c) {
+    a = *reinterpret_cast<const uint4*>(static_cast<const uint16_t*>(row) + c * 8);
+  }
+  __device__ inline void decode(float (&v)[8]) const {
     v[0] = bf16_to_f32(a.x & 0xffffu); v[1] = bf16_to_f32(a.x >> 16);
     v[2] = bf16_to_f32(a.y & 0xffffu); v[3] = bf16_to_f32(a.y >> 16);
     v[4] = bf16_to_f32(a.z & 0xffffu); v[5] = bf16_to_f32(a.z >> 16);
     v[6] = bf16_to_f32(a.w & 0xffffu); v[7] = bf16_to_f32(a.w >> 16);
   }
 };
-
-// FP8 rows decode with gfx950's packed converter (OCP E4M3, exact; two
-// codes per instruction, the low byte first); fp8_to_f32 above is the same
-// map written out, used where rows are decoded once.
 template <>
-struct Chunk<kFP8> {
-  static constexpr int kBytes = 8;
-  __device__ static inline void load(const void* row, int c, float (&v)[8]) {
-    const uint2 a = *reinterpret_cast<const uint2*>(static_cast<const uint8_t*>(row) + c * 8);
+struct ChunkRaw<kFP8> {
+  uint2 a;
+  __device__ inline void fetch(const void* row, int c) {
+    a = *reinterpret_cast<const uint2*>(static_cast<const uint8_t*>(row) + c * 8);
+  }
+  __device__ inline void decode(float (&v)[8]) const {
     const auto p0 = __builtin_amdgcn_cvt_pk_f32_fp8((int)a.x, false);
     const auto p1 = __builtin_amdgcn_cvt_pk_f32_fp8((int)a.x, true);
     const auto p2 = __builtin_amdgcn_cvt_pk_f32_fp8((int)a.y, false);
     const auto p3 = __builtin_amdgcn_cvt_pk_f32_fp8((int)a.y, true);
     v[0] = p0[0]; v[1] = p0[1]; v[2] = p1[0]; v[3] = p1[1];
     v[4] = p2[0]; v[5] = p2[1]; v[6] = p3[0]; v[7] = p3[1];
+  }
+};
+
+// fetch + decode in one step
+template <int KIND>
+struct Chunk {
+  __device__ static inline void load(const void* row, int c, float (&v)[8]) {
+    ChunkRaw<KIND> r;
+    r.fetch(row, c);
+    r.decode(v);
   }
 };
 
@@ -275,50 +290,6 @@ __device__ inline float group_sum(float v) {
 // 0 and dropped), so that all NR * CPL loads are in flight together; then
 // the chunks are decoded and reduced exactly as group_distance does.  rows[r]
 // must point at readable row memory even when !valid[r].
-template <int KIND>
-struct ChunkRaw;
-template <>
-struct ChunkRaw<kF32> {
-  float4 a, b;
-  __device__ inline void fetch(const void* row, int c) {
-    const float4* p = reinterpret_cast<const float4*>(static_cast<const float*>(row) + c * 8);
-    a = p[0];
-    b = p[1];
-  }
-  __device__ inline void decode(float (&v)[8]) const {
-    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
-    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
-  }
-};
-template <>
-struct ChunkRaw<kBF16> {
-  uint4 a;
-  __device__ inline void fetch(const void* row, int c) {
-    a = *reinterpret_cast<const uint4*>(static_cast<const uint16_t*>(row) + c * 8);
-  }
-  __device__ inline void decode(float (&v)[8]) const {
-    v[0] = bf16_to_f32(a.x & 0xffffu); v[1] = bf16_to_f32(a.x >> 16);
-    v[2] = bf16_to_f32(a.y & 0xffffu); v[3] = bf16_to_f32(a.y >> 16);
-    v[4] = bf16_to_f32(a.z & 0xffffu); v[5] = bf16_to_f32(a.z >> 16);
-    v[6] = bf16_to_f32(a.w & 0xffffu); v[7] = bf16_to_f32(a.w >> 16);
-  }
-};
-template <>
-struct ChunkRaw<kFP8> {
-  uint2 a;
-  __device__ inline void fetch(const void* row, int c) {
-    a = *reinterpret_cast<const uint2*>(static_cast<const uint8_t*>(row) + c * 8);
-  }
-  __device__ inline void decode(float (&v)[8]) const {
-    const auto p0 = __builtin_amdgcn_cvt_pk_f32_fp8((int)a.x, false);
-    const auto p1 = __builtin_amdgcn_cvt_pk_f32_fp8((int)a.x, true);
-    const auto p2 = __builtin_amdgcn_cvt_pk_f32_fp8((int)a.y, false);
-    const auto p3 = __builtin_amdgcn_cvt_pk_f32_fp8((int)a.y, true);
-    v[0] = p0[0]; v[1] = p0[1]; v[2] = p1[0]; v[3] = p1[1];
-    v[4] = p2[0]; v[5] = p2[1]; v[6] = p3[0]; v[7] = p3[1];
-  }
-};
-
 template <int KIND, int LPN, int CPL, int NR>
 __device__ inline void group_distances(const float (&q)[CPL][8], const void* const (&rows)[NR],
                                        const float (&scale)[NR], int t, int nchunks, int metric,

@@ -412,6 +412,34 @@ __device__ void start_query(const SearchArgs& a, int64_t qi, const float (&q)[CP
 // Rows each lane group gathers per pass of an expansion.
 constexpr int kGatherRows = 2;
 
+// One gather pass: rows [base, base + NR * G) of this expansion's fresh
+// candidates (cid / csc), their distances, and their keys into ckey.
+template <int KIND, int LPN, int CPL, int NR>
+__device__ inline void gather_pass(const SearchArgs& a, const SearchLayer& L,
+                                   const float (&q)[CPL][8], const WaveLds& s, const float* csc,
+                                   int base, int cnt, int t, int g) {
+  constexpr int G = 64 / LPN;
+  const void* rows[NR];
+  float sc[NR];
+  bool vd[NR];
+  int32_t ids[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int ci = base + r * G + g;
+    vd[r] = ci < cnt;
+    ids[r] = s.cid[vd[r] ? ci : base];
+    sc[r] = (KIND == kFP8) ? csc[vd[r] ? ci : base] : 1.0f;
+    rows[r] = static_cast<const char*>(L.vec) + (int64_t)ids[r] * L.row_bytes;
+  }
+  float dist[NR];
+  group_distances<KIND, LPN, CPL, NR>(q, rows, sc, t, a.nchunks, a.metric, vd, dist);
+  if (t == 0) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+      if (vd[r]) s.ckey[base + r * G + g] = wkey(dist[r], ids[r]);
+  }
+}
+
 template <int KIND, int LPN, int CPL>
 __device__ bool advance(const SearchArgs& a, const float (&q)[CPL][8], WaveLds s, uint64_t*& W,
                         uint64_t*& Wn, QState& st, int budget) {
@@ -494,27 +522,15 @@ __device__ bool advance(const SearchArgs& a, const float (&q)[CPL][8], WaveLds s
       st.evals += cnt;
 
       // gather + distance, kGatherRows * G rows per pass with all their loads
-      // in flight together (an empty slot re-reads the pass's first row)
-      for (int base = 0; base < cnt; base += kGatherRows * G) {
-        const void* rows[kGatherRows];
-        float sc[kGatherRows];
-        bool vd[kGatherRows];
-        int32_t ids[kGatherRows];
-#pragma unroll
-        for (int r = 0; r < kGatherRows; ++r) {
-          const int ci = base + r * G + g;
-          vd[r] = ci < cnt;
-          ids[r] = s.cid[vd[r] ? ci : base];
-          sc[r] = (KIND == kFP8) ? csc[vd[r] ? ci : base] : 1.0f;
-          rows[r] = static_cast<const char*>(L.vec) + (int64_t)ids[r] * L.row_bytes;
-        }
-        float dist[kGatherRows];
-        group_distances<KIND, LPN, CPL, kGatherRows>(q, rows, sc, t, a.nchunks, a.metric, vd,
-                                                     dist);
-        if (t == 0) {
-#pragma unroll
-          for (int r = 0; r < kGatherRows; ++r)
-            if (vd[r]) s.ckey[base + r * G + g] = wkey(dist[r], ids[r]);
+      // in flight together (an empty slot re-reads the pass's first row); a
+      // last pass of at most G rows takes one row per group
+      for (int base = 0; base < cnt;) {
+        if (cnt - base > G) {
+          gather_pass<KIND, LPN, CPL, kGatherRows>(a, L, q, s, csc, base, cnt, t, g);
+          base += kGatherRows * G;
+        } else {
+          gather_pass<KIND, LPN, CPL, 1>(a, L, q, s, csc, base, cnt, t, g);
+          base += G;
         }
       }
       wave_sync();
