@@ -67,6 +67,20 @@ typedef enum {
   HENN_GRAPH_PRUNED_SYM = 3
 } henn_graph;
 
+/* How layer i is drawn from layer i-1 (App. B.1):
+ *   DRAWS:   Alg. 2 (BuildEpsNetSampling): ceil(|L_{i-1}| / 2^m) draws with
+ *            replacement, duplicates merged;
+ *   HALVING: Alg. 3 (BuildEpsNetDiscV2): m halving steps.  Each step pairs
+ *            the current members in ascending id order (the matching the paper
+ *            leaves arbitrary), keeps one member of every pair by a coin, and
+ *            keeps an odd last member; the layer then holds exactly
+ *            ceil(|L_{i-1}| / 2^m) distinct points.  The coin of pair p in
+ *            step j (0-based) of attempt t is u(word p of stream
+ *            (tag 4 + j, layer i, attempt t), 2): 0 keeps the lower id.
+ * Either sample goes through the same ring check and Las-Vegas repeat
+ * (max_attempts 1 gives the plain one-shot construction). */
+typedef enum { HENN_SAMPLER_DRAWS = 0, HENN_SAMPLER_HALVING = 1 } henn_sampler;
+
 #define HENN_MAX_LAYERS 16
 
 typedef struct {
@@ -89,7 +103,7 @@ typedef struct {
                                 many points, and search that root with the complete graph
                                 (App. B.2: trivially navigable), i.e. an exhaustive scan
                                 for the root member nearest to q; 0: off */
-  int32_t reserved;
+  int32_t sampler;        /* henn_sampler */
 } henn_build_params;
 
 /* Search flags */
@@ -135,7 +149,8 @@ typedef struct {
 
 typedef struct {
   int64_t size;           /* |L_i| */
-  int64_t draws;          /* samples drawn (with replacement) */
+  int64_t draws;          /* samples drawn (with replacement), or the halved
+                             size ceil(|L_{i-1}| / 2^m) */
   double eps;             /* eps_i used (Eq. (1) or override) */
   int64_t window;         /* minimal heavy ring size floor(eps*s)+1 */
   int32_t attempts;       /* Las-Vegas attempts made */
@@ -149,7 +164,7 @@ typedef struct {
 
 /* Fills *p with the defaults: L2, max_layers -1, m 4, c0 1, no override,
  * 64 rings, 64 attempts, degree 16, max_degree 32, kNN graph, F32, seed 0,
- * root_complete_max 0. */
+ * root_complete_max 0, DRAWS sampler. */
 henn_status henn_default_build_params(henn_build_params *p);
 
 /* Defaults: no per-query arrays, k_all 10, ef_all 32, k_max 10, ef_max 32,

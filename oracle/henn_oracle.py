@@ -10,7 +10,9 @@ of the paper's algorithms:
 * :func:`build_index` -- Alg. 1 (BuildHENN): layer i is an eps-net of layer
   i-1 drawn by Alg. 2 (BuildEpsNetSampling, samples with replacement) and
   verified against ``r`` sampled ring ranges (App. B.1 "Practical
-  Implementation", App. G.2); each layer then gets an exact kNN navigable
+  Implementation", App. G.2) -- or, with ``sampler=1``, drawn by Alg. 3's
+  halving (:func:`halve`, BuildEpsNetDiscV2) and checked the same way; each
+  layer then gets an exact kNN navigable
   graph (App. B.2, App. G.4).  Layer sizes follow Cor. "layer-size":
   ceil(|L_{i-1}| / 2^m) draws per layer.
 * :func:`search` -- Alg. 4 (Query) from the root down, ef=1 greedy on the
@@ -45,7 +47,7 @@ _LIB = os.path.join(_HERE, "libhenn_oracle.so")
 _lib = None
 _lock = threading.Lock()
 
-TAG_SAMPLE, TAG_RING_CENTRE, TAG_RING_START = 1, 2, 3
+TAG_SAMPLE, TAG_RING_CENTRE, TAG_RING_START, TAG_HALVE = 1, 2, 3, 4
 L2, IP = 0, 1
 
 
@@ -192,6 +194,7 @@ class BuildParams:
     max_degree: int = 32         # row cap of the graphs with reverse edges
     root_complete_max: int = 0   # > 0: stop adding layers once a layer holds at most
                                  # this many points and give that root the complete graph
+    sampler: int = 0             # 0: Alg. 2 draws with replacement; 1: Alg. 3 halving
 
 
 @dataclass
@@ -237,8 +240,37 @@ def ring_members(X, metric, members, centre_local, a, w):
     return out, float(mg[0])
 
 
+def halve(seed, layer, attempt, s, m) -> np.ndarray:
+    """Alg. 3, BuildEpsNetDiscV2: m halving steps of the positions [0, s).
+
+    Each step matches the current members in pairs -- the paper leaves the
+    matching arbitrary; here consecutive members in ascending order -- and
+    keeps one member of every pair by a coin; an odd last member has no pair
+    and stays.  Pair p of step j (0-based) takes its coin from word p of the
+    stream (tag 4 + j, layer, attempt): u(w, 2) = 0 keeps the lower member.
+    Returns the ascending survivors."""
+    A = np.arange(s, dtype=np.int64)
+    for j in range(m):
+        a = len(A)
+        pairs = a // 2
+        coins = draw_indices(seed, TAG_HALVE + j, layer, attempt, 2, pairs)
+        kept = A[2 * np.arange(pairs) + coins]       # member 2q or 2q+1 of pair q
+        if a % 2 == 1:
+            kept = np.append(kept, A[a - 1])
+        A = kept
+    return A
+
+
+def _candidate(p: BuildParams, layer, attempt, s, D):
+    """One attempt's sample: Alg. 2's D draws (with repeats) or Alg. 3's halving."""
+    if p.sampler == 1:
+        return halve(p.seed, layer, attempt, s, p.m)
+    return draw_indices(p.seed, TAG_SAMPLE, layer, attempt, s, D)
+
+
 def sample_layer(X, prev, layer, d, p: BuildParams, threads=None):
-    """Alg. 2 with the practical IsEpsNet of App. B.1 for one layer.
+    """Alg. 2 (or Alg. 3's halving, ``p.sampler == 1``) with the practical
+    IsEpsNet of App. B.1 for one layer.
 
     Returns (local indices of the accepted sample, ascending, distinct), LayerInfo.
     """
@@ -247,7 +279,7 @@ def sample_layer(X, prev, layer, d, p: BuildParams, threads=None):
     eps = p.eps_override if p.eps_override > 0 else eps_of(s, d, p.m, p.c0)
     w = window_of(eps, s)
     if w > s:
-        draws = draw_indices(p.seed, TAG_SAMPLE, layer, 0, s, D)
+        draws = _candidate(p, layer, 0, s, D)
         return np.unique(draws), LayerInfo(0, D, eps, w, 1, 0, "vacuous")
     r = p.num_rings
     centres = draw_indices(p.seed, TAG_RING_CENTRE, layer, 0, s, r)
@@ -262,7 +294,7 @@ def sample_layer(X, prev, layer, d, p: BuildParams, threads=None):
     _parallel(r, one, threads)
     best_t, best_hits, best = -1, -1, None
     for t in range(p.max_attempts):
-        draws = draw_indices(p.seed, TAG_SAMPLE, layer, t, s, D)
+        draws = _candidate(p, layer, t, s, D)
         sel = np.zeros(s, dtype=bool)
         sel[draws] = True
         hits = int(sum(bool(sel[ring].any()) for ring in rings))

@@ -80,6 +80,9 @@ static bool valid_build_params(const henn_build_params* p, std::string* why) {
   }
   if (p->storage < HENN_F32 || p->storage > HENN_FP8_E4M3) { *why = "storage"; return false; }
   if (p->root_complete_max < 0) { *why = "root_complete_max >= 0"; return false; }
+  if (p->sampler != HENN_SAMPLER_DRAWS && p->sampler != HENN_SAMPLER_HALVING) {
+    *why = "sampler"; return false;
+  }
   return true;
 }
 
@@ -141,8 +144,8 @@ static void finish_layer(henn_index* ix, int i, hipStream_t st) {
   HENN_HIP(hipStreamSynchronize(st));
 }
 
-// One eps-net layer (Alg. 2 with the ring check).  Returns the accepted
-// attempt and fills info.
+// One eps-net layer (Alg. 2's draws or Alg. 3's halving, then the ring
+// check).  Returns the accepted attempt and fills info.
 static int sample_layer(henn_index* ix, int i, hipStream_t st, int32_t* local_out,
                         int64_t* count_out) {
   const henn_build_params& p = ix->params;
@@ -157,9 +160,14 @@ static int sample_layer(henn_index* ix, int i, hipStream_t st, int32_t* local_ou
   info.draws = D;
   info.eps = eps;
   info.window = w;
+  const bool halving = p.sampler == HENN_SAMPLER_HALVING;
   int lpn, cpl;
   pick_lanes(ix->nchunks, 0, &lpn, &cpl);
   int accepted = 0;
+  if (halving) {
+    // the halved sample is distinct and ascending already: written in place
+    *count_out = launch_halve(p.seed, i, 0, s, p.m, local_out, st);
+  }
   if (w > s) {
     info.status = 1;  // vacuous: no ring can be heavy
     info.attempts = 1;
@@ -202,8 +210,10 @@ static int sample_layer(henn_index* ix, int i, hipStream_t st, int32_t* local_ou
       int t = 0;
       for (; t < p.max_attempts; ++t) {
         HENN_HIP(hipMemsetAsync(d_hits, 0, sizeof(uint32_t) * r, st));
+        if (halving && t > 0) launch_halve(p.seed, i, t, s, p.m, local_out, st);
         launch_ring_hits(lpn, cpl, prev.vec32, ix->dpad, ix->nchunks, ix->metric, s, p.seed, i,
-                         t, D, d_centres, d_lohi, d_lohi + r, r, d_hits, st);
+                         t, D, halving ? local_out : nullptr, d_centres, d_lohi, d_lohi + r, r,
+                         d_hits, st);
         HENN_HIP(hipMemcpyAsync(hits.data(), d_hits, sizeof(uint32_t) * r, hipMemcpyDeviceToHost,
                                 st));
         HENN_HIP(hipStreamSynchronize(st));
@@ -234,6 +244,11 @@ static int sample_layer(henn_index* ix, int i, hipStream_t st, int32_t* local_ou
     (void)hipFree(d_centres);
     (void)hipFree(d_lohi);
     (void)hipFree(d_hits);
+  }
+  if (halving) {
+    // local_out holds the last attempt made; redo the kept one if it differs
+    if (accepted != info.attempts - 1) launch_halve(p.seed, i, accepted, s, p.m, local_out, st);
+    return accepted;
   }
   const int64_t nwords = (s + 31) / 32;
   uint32_t* bitmap = dalloc<uint32_t>(nwords);
@@ -349,6 +364,7 @@ henn_status henn_default_build_params(henn_build_params* p) {
   p->graph = HENN_GRAPH_KNN;
   p->storage = HENN_F32;
   p->seed = 0;
+  p->sampler = HENN_SAMPLER_DRAWS;
   return HENN_OK;
 }
 

@@ -5,6 +5,10 @@
 //    draws are independent, so they parallelise trivially) and sets their
 //    bits in a membership bitmap over L_{i-1}.
 //  * compaction: popcount + two-level exclusive scan -> ascending positions.
+//  * k_halve: Alg. 3's m halving steps (BuildEpsNetDiscV2).  With pairs of
+//    consecutive members, the survivor of pair p of a step lands at position
+//    p of the next step, so one thread per final position walks the m steps
+//    backwards (one coin per step) to its position in L_{i-1}; no scan.
 //  * ring verification (App. B.1 "Practical Implementation", App. G.2):
 //    r sampled rings, each the rank window [a, a+w-1] of L_{i-1} ordered by
 //    (distance to a sampled centre, id).  k_ring_keys writes the 64-bit
@@ -63,6 +67,41 @@ void launch_draw_mark(uint64_t seed, int layer, int attempt, int64_t s, int64_t 
   const int64_t blocks4 = (draws + 3) / 4;
   hipLaunchKernelGGL(k_draw_mark, dim3((unsigned)((blocks4 + 255) / 256)), dim3(256), 0, st,
                      seed, layer, attempt, s, draws, bitmap);
+}
+
+// ------------------------------------------------------------- halving ----
+struct HalveSizes {
+  int64_t a[32];  // a[j]: member count before step j; a[m] = final count
+};
+
+__global__ void k_halve(uint64_t seed, int layer, int attempt, int m, HalveSizes sz,
+                        int32_t* out) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= sz.a[m]) return;
+  int64_t pos = p;
+  for (int j = m - 1; j >= 0; --j) {
+    const int64_t a = sz.a[j];
+    if (pos == a / 2) {
+      pos = a - 1;  // odd count: the unpaired last member is kept
+    } else {
+      const uint64_t w = stream_word(seed, kTagHalve + (uint32_t)j, (uint32_t)layer,
+                                     (uint32_t)attempt, (uint64_t)pos);
+      pos = 2 * pos + (int64_t)uniform_index(w, 2);
+    }
+  }
+  out[p] = (int32_t)pos;
+}
+
+int64_t launch_halve(uint64_t seed, int layer, int attempt, int64_t s, int m, int32_t* out,
+                     hipStream_t st) {
+  HalveSizes sz;
+  sz.a[0] = s;
+  for (int j = 0; j < m; ++j) sz.a[j + 1] = (sz.a[j] + 1) / 2;
+  const int64_t count = sz.a[m];
+  if (count > 0)
+    hipLaunchKernelGGL(k_halve, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, seed,
+                       layer, attempt, m, sz, out);
+  return count;
 }
 
 // ---------------------------------------------------------- compaction ----
@@ -241,6 +280,7 @@ template <int LPN, int CPL>
 __global__ __launch_bounds__(256) void k_ring_hits(const float* vec, int dpad, int nchunks,
                                                    int metric, int64_t s, uint64_t seed,
                                                    int layer, int attempt, int64_t draws,
+                                                   const int32_t* cand,
                                                    const int32_t* centres, const uint64_t* lo,
                                                    const uint64_t* hi, uint32_t* hits) {
   constexpr int G = 64 / LPN;
@@ -255,7 +295,9 @@ __global__ __launch_bounds__(256) void k_ring_hits(const float* vec, int dpad, i
     const int64_t qd = base + (threadIdx.x >> 6) * G + g;
     const bool valid = qd < draws;
     int64_t row = 0;
-    if (valid) {
+    if (valid && cand) {
+      row = cand[qd];
+    } else if (valid) {
       const uint64_t w = stream_word(seed, kTagSample, (uint32_t)layer, (uint32_t)attempt,
                                      (uint64_t)qd);
       row = (int64_t)uniform_index(w, (uint64_t)s);
@@ -289,14 +331,14 @@ void launch_ring_keys(int lpn, int cpl, const float* vec, int dpad, int nchunks,
 
 void launch_ring_hits(int lpn, int cpl, const float* vec, int dpad, int nchunks, int metric,
                       int64_t s, uint64_t seed, int layer, int attempt, int64_t draws,
-                      const int32_t* centres, const uint64_t* lo, const uint64_t* hi, int r,
-                      uint32_t* hits, hipStream_t st) {
+                      const int32_t* cand, const int32_t* centres, const uint64_t* lo,
+                      const uint64_t* hi, int r, uint32_t* hits, hipStream_t st) {
   const int64_t per_block = 4 * (64 / lpn);
   const unsigned gx = (unsigned)std::min<int64_t>((draws + per_block - 1) / per_block, 65535);
 #define HENN_TRY(L, C)                                                                          \
   if (lpn == L && cpl == C) {                                                                   \
     hipLaunchKernelGGL((k_ring_hits<L, C>), dim3(gx, r), dim3(256), 0, st, vec, dpad, nchunks,  \
-                       metric, s, seed, layer, attempt, draws, centres, lo, hi, hits);          \
+                       metric, s, seed, layer, attempt, draws, cand, centres, lo, hi, hits);    \
     return;                                                                                     \
   }
   HENN_RING_COMBOS(HENN_TRY)

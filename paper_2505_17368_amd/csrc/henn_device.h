@@ -53,7 +53,8 @@ __host__ __device__ inline Philox4x64 philox4x64_10(uint64_t c0, uint64_t c1, ui
   return r;
 }
 
-enum : uint32_t { kTagSample = 1, kTagRingCentre = 2, kTagRingStart = 3 };
+// stream tags; halving step j (0-based) draws from tag kTagHalve + j
+enum : uint32_t { kTagSample = 1, kTagRingCentre = 2, kTagRingStart = 3, kTagHalve = 4 };
 
 __host__ __device__ inline uint64_t stream_word(uint64_t seed, uint32_t tag, uint32_t layer,
                                                 uint32_t attempt, uint64_t q) {

@@ -217,10 +217,16 @@ void launch_ring_keys(int lpn, int cpl, const float* vec, int dpad, int nchunks,
                       int64_t s, const int32_t* centres, int r, uint64_t* keys, hipStream_t st);
 void launch_radix_select(const uint64_t* keys, int64_t s, int r, const int64_t* ranks_host,
                          uint64_t* out_keys_host, hipStream_t st);
+// cand == nullptr: the sample is Alg. 2's draws of (seed, layer, attempt);
+// else the `draws` positions in cand.
 void launch_ring_hits(int lpn, int cpl, const float* vec, int dpad, int nchunks, int metric,
                       int64_t s, uint64_t seed, int layer, int attempt, int64_t draws,
-                      const int32_t* centres, const uint64_t* lo, const uint64_t* hi, int r,
-                      uint32_t* hits, hipStream_t st);
+                      const int32_t* cand, const int32_t* centres, const uint64_t* lo,
+                      const uint64_t* hi, int r, uint32_t* hits, hipStream_t st);
+// Alg. 3 (BuildEpsNetDiscV2): m halving steps of positions [0, s); writes the
+// ceil(s / 2^m) ascending survivors to out and returns their count.
+int64_t launch_halve(uint64_t seed, int layer, int attempt, int64_t s, int m, int32_t* out,
+                     hipStream_t st);
 void launch_draw_mark(uint64_t seed, int layer, int attempt, int64_t s, int64_t draws,
                       uint32_t* bitmap, hipStream_t st);
 int64_t compact_bitmap(const uint32_t* bitmap, int64_t s, int32_t* out_local, hipStream_t st);

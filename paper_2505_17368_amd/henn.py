@@ -24,6 +24,7 @@ HENN_L2, HENN_IP = 0, 1
 HENN_F32, HENN_BF16, HENN_FP8_E4M3 = 0, 1, 2
 HENN_GRAPH_KNN, HENN_GRAPH_KNN_SYM, HENN_GRAPH_PRUNED, HENN_GRAPH_PRUNED_SYM = 0, 1, 2, 3
 GRAPH = {"knn": 0, "knn_sym": 1, "pruned": 2, "pruned_sym": 3}
+SAMPLER = {"draws": 0, "halving": 1}
 HENN_SEARCH_COUNTERS, HENN_SEARCH_PERSISTENT, HENN_SEARCH_NO_ROOT_KERNEL = 1, 2, 4
 HENN_SEARCH_ROOT_VALU = 8
 HENN_SEARCH_VIS32 = 16
@@ -38,7 +39,7 @@ class BuildParams(ctypes.Structure):
                 ("max_attempts", ctypes.c_int32), ("degree", ctypes.c_int32),
                 ("max_degree", ctypes.c_int32), ("graph", ctypes.c_int32),
                 ("storage", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("root_complete_max", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("root_complete_max", ctypes.c_int32), ("sampler", ctypes.c_int32)]
 
 
 class SearchParams(ctypes.Structure):
@@ -184,6 +185,8 @@ def default_build_params(**kw) -> BuildParams:
             v = STORAGE[v]
         if k == "graph" and isinstance(v, str):
             v = GRAPH[v]
+        if k == "sampler" and isinstance(v, str):
+            v = SAMPLER[v]
         if not hasattr(p, k):
             raise KeyError(k)
         setattr(p, k, v)

@@ -32,8 +32,8 @@ def test_struct_sizes_match_header(lib):
 def test_defaults(lib):
     p = hn.default_build_params()
     assert (p.metric, p.max_layers, p.m, p.c0, p.num_rings, p.max_attempts, p.degree,
-            p.max_degree, p.graph, p.storage, p.seed, p.root_complete_max) == (
-                0, -1, 4, 1.0, 64, 64, 16, 32, 0, 0, 0, 0)
+            p.max_degree, p.graph, p.storage, p.seed, p.root_complete_max, p.sampler) == (
+                0, -1, 4, 1.0, 64, 64, 16, 32, 0, 0, 0, 0, 0)
     sp = hn.SearchParams()
     lib.henn_default_search_params(ctypes.byref(sp))
     assert (sp.k_all, sp.ef_all, sp.k_max, sp.ef_upper, sp.rerank_factor) == (10, 32, 10, 1, 4)
@@ -62,6 +62,13 @@ def test_invalid_arguments_rejected_on_host(lib):
         assert "graph" in hn.last_error() or "max_degree" in hn.last_error()
     assert hn.GRAPH == {"knn": 0, "knn_sym": 1, "pruned": 2, "pruned_sym": 3}
     assert hn.default_build_params(graph="pruned_sym").graph == 3
+    # samplers: 0 draws (Alg. 2), 1 halving (Alg. 3)
+    for sampler in (2, -1):
+        bad = hn.default_build_params(sampler=sampler)
+        assert lib.henn_build(fake, 10, 4, ctypes.byref(bad), None,
+                              ctypes.byref(h)) == hn.HENN_E_INVAL
+        assert "sampler" in hn.last_error()
+    assert hn.default_build_params(sampler="halving").sampler == 1
     sp = hn.SearchParams()
     lib.henn_default_search_params(ctypes.byref(sp))
     assert lib.henn_search_batch(None, fake, 1, ctypes.byref(sp), fake, fake,

@@ -221,6 +221,30 @@ def test_build_las_vegas_repeats_match_oracle(hn, ho, seed, eps):
     idx.free()
 
 
+@pytest.mark.parametrize("n,d,seed,eps,attempts", [
+    (4000, 6, 3, 0.015, 64),       # Las-Vegas repeats (layer 1 kept at attempt 6)
+    (4000, 6, 7, 0.006, 4),        # attempt cap: best attempt kept
+    (10_000, 32, 5, 0.0, 64),      # Eq. (1) schedule (vacuous layers)
+    (1_000_003, 4, 9, 2.0, 1),     # one large odd layer, no ring check
+])
+def test_halving_layers_match_oracle(hn, ho, n, d, seed, eps, attempts):
+    """Alg. 3's halving sampler: member lists bit-exact, same Las-Vegas outcome."""
+    X = wl.uniform(n, d, seed)
+    p = dict(degree=8, seed=seed, eps_override=eps, max_attempts=attempts, sampler=1,
+             max_layers=1 if n > 100_000 else -1)
+    olayers, oinfo = ho.build_layers(X, ho.BuildParams(**p))
+    idx = hn.henn_build(to_dev(X), **p)
+    layers = _gpu_layers(idx)
+    assert len(layers) == len(olayers)
+    for i in range(1, len(olayers)):
+        gi = idx.layer_info(i)
+        assert (gi["status"], gi["attempts"], gi["hits"]) == (
+            oinfo[i].status, oinfo[i].attempts, oinfo[i].hits), f"layer {i}"
+        assert len(layers[i][0]) == -(-len(olayers[i - 1]) // 16)
+        assert np.array_equal(layers[i][0], olayers[i]), f"layer {i}"
+    idx.free()
+
+
 def test_build_graph_matches_oracle(hn, ho, cfg1):
     X, Q, oidx = cfg1
     idx = hn.henn_build(to_dev(X), degree=16)

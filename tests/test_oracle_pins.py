@@ -8,6 +8,8 @@ an independent library routine or a brute-force recomputation:
   the first block, so block B(x) is NumPy's first output for counter x-1).
 * Eq. (1) against hand-computed values.
 * Alg. 2 layer samples against ``np.unique`` of NumPy-Philox draws.
+* Alg. 3 halving: sizes ceil(s / 2^m), one survivor per dyadic block, fair
+  and independent coins, and a backward walk with NumPy-Philox coins.
 * Ring ranges (Def. Ring Ranges) and the hit test against a NumPy lexsort.
 * The exact kNN graph (App. B.2) against NumPy all-pairs + lexsort.
 * Search: complete graph => exact k-NN (App. B.2: the complete graph is
@@ -180,6 +182,90 @@ def test_layer_sample_not_verified_keeps_best(oracle):
     assert infos[1].status == "not_verified" and infos[1].hits == hits[best]
     draws = numpy_uindex(numpy_stream(5, 1, 1, best, D), s)
     assert np.array_equal(members[1], np.unique(draws).astype(np.int32))
+
+
+# ------------------------------------------------------- Alg. 3 halving --
+
+def _numpy_halving_walk(seed, layer, attempt, s, m):
+    """Alg. 3's halving written backwards, with NumPy's Philox: with pairs of
+    consecutive members the survivor of pair p lands at position p of the next
+    step, so a final position is traced back through the m steps."""
+    sizes = [s]
+    for _ in range(m):
+        sizes.append((sizes[-1] + 1) // 2)
+    coins = [numpy_uindex(numpy_stream(seed, 4 + j, layer, attempt, sizes[j] // 2), 2)
+             for j in range(m)]
+    out = []
+    for p in range(sizes[m]):
+        pos = p
+        for j in range(m - 1, -1, -1):
+            pos = sizes[j] - 1 if pos == sizes[j] // 2 else 2 * pos + int(coins[j][pos])
+        out.append(pos)
+    return np.array(out, dtype=np.int64)
+
+
+@pytest.mark.parametrize("s", [0, 1, 2, 3, 5, 16, 17, 31, 32, 33, 100, 1023, 4096])
+@pytest.mark.parametrize("m", [1, 2, 4])
+def test_halving_size_order_and_dyadic_blocks(oracle, s, m):
+    got = oracle.halve(9, 2, 1, s, m)
+    assert len(got) == -(-s // 2 ** m)                  # Cor. layer-size: ceil(s / 2^m)
+    assert np.all(np.diff(got) > 0) and (len(got) == 0 or (got[0] >= 0 and got[-1] < s))
+    if s % 2 ** m == 0:
+        # consecutive pairs compose into dyadic blocks: one survivor per block
+        assert np.array_equal(got // 2 ** m, np.arange(s // 2 ** m))
+    if s % 2 == 1 and m == 1:
+        assert got[-1] == s - 1                          # the unpaired last member stays
+
+
+def test_halving_tiny_case_by_hand(oracle):
+    # s = 5, m = 2: step 0 keeps one of {0,1}, one of {2,3} and 4; step 1
+    # keeps one of the first two survivors and 4 again
+    for t in range(50):
+        got = oracle.halve(1, 1, t, 5, 2)
+        assert len(got) == 2 and got[1] == 4 and 0 <= got[0] <= 3
+
+
+@pytest.mark.parametrize("s,m", [(37, 1), (64, 3), (1000, 4), (77, 5)])
+def test_halving_matches_backward_walk_with_numpy_philox(oracle, s, m):
+    for seed, layer, attempt in [(0, 1, 0), (5, 3, 7)]:
+        assert np.array_equal(oracle.halve(seed, layer, attempt, s, m),
+                              _numpy_halving_walk(seed, layer, attempt, s, m))
+
+
+def test_halving_coins_are_fair_and_independent(oracle):
+    """Each halving keeps either member of a pair with probability 1/2, so
+    with s = 16 and m = 2 every point survives with probability 1/4, and the
+    choices in the four blocks are independent."""
+    T = 4000
+    picks = np.array([oracle.halve(13, 1, t, 16, 2) for t in range(T)])   # [T, 4]
+    freq = np.bincount(picks.ravel(), minlength=16) / T
+    assert np.all(np.abs(freq - 0.25) < 0.035), freq
+    joint = np.bincount((picks[:, 0] % 4) * 4 + picks[:, 1] % 4, minlength=16) / T
+    assert np.all(np.abs(joint - 1 / 16) < 0.025), joint
+
+
+def test_halving_layer_las_vegas(oracle):
+    """Alg. 3's sample goes through the same ring check: the kept attempt is
+    the first halving that hits every sampled ring (brute force)."""
+    X = wl.uniform(2000, 3, 0)
+    s, r = 2000, 64
+    p = oracle.BuildParams(degree=8, seed=3, eps_override=0.025, num_rings=r, max_layers=1,
+                           sampler=1)
+    members, infos = oracle.build_layers(X, p)
+    w = oracle.window_of(0.025, s)
+    centres = numpy_uindex(numpy_stream(3, 2, 1, 0, r), s)
+    starts = numpy_uindex(numpy_stream(3, 3, 1, 0, r), s - w + 1)
+    rings = _brute_rings(X, members[0], centres, starts, w)
+    accepted = None
+    for t in range(p.max_attempts):
+        kept = set(_numpy_halving_walk(3, 1, t, s, 4).tolist())
+        if all(ring & kept for ring in rings):
+            accepted = t
+            break
+    assert accepted is not None and accepted >= 1, "fixture must exercise a repeat"
+    assert infos[1].status == "verified" and infos[1].attempts == accepted + 1
+    assert len(members[1]) == 125
+    assert np.array_equal(members[1], _numpy_halving_walk(3, 1, accepted, s, 4))
 
 
 def test_ring_members_brute_force(oracle):
