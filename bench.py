@@ -46,6 +46,10 @@ def parse():
     ap.add_argument("--target-recall", type=float, default=0.95)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--graph", default="knn_sym")
+    ap.add_argument("--sampler", default="draws", choices=["draws", "halving"],
+                    help="layer sampler: Alg. 2 draws or Alg. 3 halving")
+    ap.add_argument("--ef-construction", type=int, default=256, help="NSW insertion beam")
+    ap.add_argument("--insert-shift", type=int, default=3, help="NSW batch = inserted >> shift")
     ap.add_argument("--degree", type=int, default=16)
     ap.add_argument("--max-degree", type=int, default=48)
     ap.add_argument("--root-max", type=int, default=4096)
@@ -155,7 +159,8 @@ def main():
     torch.cuda.synchronize()
     t = time.time()
     bparams = dict(degree=args.degree, metric=metric, graph=graph, max_degree=args.max_degree,
-                   root_complete_max=args.root_max)
+                   root_complete_max=args.root_max, sampler=hn.SAMPLER[args.sampler],
+                   ef_construction=args.ef_construction, insert_shift=args.insert_shift)
     base = hn.henn_build(Xd, storage=0, **bparams)
     torch.cuda.synchronize()
     build_s["f32"] = time.time() - t
@@ -380,7 +385,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "d": d, "nq": nq, "k": k, "ef": ef,
                    "form": head_form, "storage": head_form, "persistent": pers,
-                   "graph": args.graph, "degree": args.degree, "max_degree": args.max_degree,
+                   "graph": args.graph, "sampler": args.sampler, "degree": args.degree,
+                   "max_degree": args.max_degree,
+                   **({"ef_construction": args.ef_construction,
+                       "insert_shift": args.insert_shift} if args.graph == "nsw" else {}),
                    "root_complete_max": args.root_max, "metric": w["metric"]},
         "recall_at_10": head["recall"],
         "p50_ms": round(float(np.percentile(kms, 50)), 4),
@@ -491,6 +499,8 @@ def batched(args):
     Xd = torch.from_numpy(X).to(dev)
     Qd = torch.from_numpy(Q).to(dev)
     bp = dict(degree=args.degree, metric=metric, graph=hn.GRAPH[args.graph],
+              sampler=hn.SAMPLER[args.sampler], ef_construction=args.ef_construction,
+              insert_shift=args.insert_shift,
               max_degree=args.max_degree, root_complete_max=args.root_max)
     torch.cuda.synchronize()
     t = time.time()
@@ -560,6 +570,7 @@ def batched(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": wname, "n": n, "d": d, "nq": nq, "storage": args.storage,
                    "k": [1, 10, 100], "ef": [32, 64, 128], "graph": args.graph,
+                   "sampler": args.sampler,
                    "max_degree": args.max_degree, "root_complete_max": args.root_max},
         "p50_ms": round(float(np.percentile(kms, 50)), 3),
         "p99_ms": round(float(np.percentile(kms, 99)), 3),
@@ -593,6 +604,8 @@ def serving(args):
     Xd = torch.from_numpy(X).to(dev)
     Qd = torch.from_numpy(Q).to(dev)
     bp = dict(degree=args.degree, metric=metric, graph=hn.GRAPH[args.graph],
+              sampler=hn.SAMPLER[args.sampler], ef_construction=args.ef_construction,
+              insert_shift=args.insert_shift,
               max_degree=args.max_degree, root_complete_max=args.serve_root_max)
     torch.cuda.synchronize()
     t = time.time()
@@ -663,7 +676,7 @@ def serving(args):
         "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": args.storage, "data": "synthetic",
         "config": {"workload": wname, "n": n, "d": d, "nq": nq, "metric": w["metric"],
-                   "storage": args.storage, "graph": args.graph,
+                   "storage": args.storage, "graph": args.graph, "sampler": args.sampler,
                    "max_degree": args.max_degree, "root_complete_max": args.serve_root_max},
         "build_s": round(build_s, 1), "layers": sizes, "fallback_rows": fallback,
         "sweep": sweep, "serving": res,

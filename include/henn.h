@@ -59,12 +59,21 @@ typedef enum { HENN_F32 = 0, HENN_BF16 = 1, HENN_FP8_E4M3 = 2 } henn_storage;
  *   PRUNED:     diversity pruning of the exact top min(2R, 32) (the NSW/HNSW
  *               neighbour selection): candidates in order, each dropped when an
  *               already kept one is closer to it than the row is; <= R kept;
- *   PRUNED_SYM: PRUNED plus reverse edges, as KNN_SYM. */
+ *   PRUNED_SYM: PRUNED plus reverse edges, as KNN_SYM;
+ *   NSW:        the incremental-insertion graph of App. B.2: members join in
+ *               ascending id order, each linked to the R best results of a
+ *               beam search (width max(ef_construction, R), from the first
+ *               member) over the graph built so far, and every point it
+ *               links to keeps the first max_degree of its row plus the new
+ *               point, in (distance, id) order.  Insertion runs in batches
+ *               [lo, lo + max(1, lo >> insert_shift)) whose points search
+ *               the graph on [0, lo) together (henn_nsw_insert). */
 typedef enum {
   HENN_GRAPH_KNN = 0,
   HENN_GRAPH_KNN_SYM = 1,
   HENN_GRAPH_PRUNED = 2,
-  HENN_GRAPH_PRUNED_SYM = 3
+  HENN_GRAPH_PRUNED_SYM = 3,
+  HENN_GRAPH_NSW = 4
 } henn_graph;
 
 /* How layer i is drawn from layer i-1 (App. B.1):
@@ -95,7 +104,8 @@ typedef struct {
   int32_t num_rings;      /* r: ring ranges checked per layer (App. G.2) */
   int32_t max_attempts;   /* Las-Vegas cap of Alg. 2's repeat loop */
   int32_t degree;         /* R: kNN graph degree (kept neighbours for PRUNED) */
-  int32_t max_degree;     /* row capacity of the graphs with reverse edges (>= degree) */
+  int32_t max_degree;     /* row capacity of the graphs with reverse edges and NSW
+                             (>= degree, <= 64) */
   int32_t graph;          /* henn_graph */
   int32_t storage;        /* henn_storage */
   uint64_t seed;          /* key word 0 of the Philox4x64-10 stream (word 1 = 0) */
@@ -104,6 +114,9 @@ typedef struct {
                                 (App. B.2: trivially navigable), i.e. an exhaustive scan
                                 for the root member nearest to q; 0: off */
   int32_t sampler;        /* henn_sampler */
+  int32_t ef_construction;/* NSW: beam width of the insertion searches, [1, 2048] */
+  int32_t insert_shift;   /* NSW: batch after lo inserted members = max(1, lo >> shift);
+                             large values give the one-by-one insertion */
 } henn_build_params;
 
 /* Search flags */
@@ -164,7 +177,7 @@ typedef struct {
 
 /* Fills *p with the defaults: L2, max_layers -1, m 4, c0 1, no override,
  * 64 rings, 64 attempts, degree 16, max_degree 32, kNN graph, F32, seed 0,
- * root_complete_max 0, DRAWS sampler. */
+ * root_complete_max 0, DRAWS sampler, ef_construction 256, insert_shift 3. */
 henn_status henn_default_build_params(henn_build_params *p);
 
 /* Defaults: no per-query arrays, k_all 10, ef_all 32, k_max 10, ef_max 32,
@@ -317,6 +330,23 @@ henn_status henn_import(const float *X, int64_t n, int32_t d, const henn_build_p
                         int32_t num_layers, const int64_t *sizes,
                         const int32_t *const *ids_host, const int32_t *const *adj_host,
                         int32_t adj_stride, void *hip_stream, henn_index **out);
+
+/* One batch of the NSW insertion (App. B.2; the HENN_GRAPH_NSW rule) on a
+ * graph the caller holds, e.g. to grow a layer graph or to check a batch.
+ *   V:   device FP32 [s][d] row-major, the layer's points in insertion order
+ *        (only rows < hi are read); d in [1, 1024]; metric a henn_metric.
+ *   adj: device int32 [s][max_degree] positions, -1 padded at the end of a
+ *        row; rows < lo hold the graph on [0, lo), rows [lo, hi) are
+ *        overwritten with the new points' rows, rows < lo that some new
+ *        point links to are replaced by their merged rows, rows >= hi are
+ *        not touched.
+ *   0 <= lo <= hi <= s < 2^31; degree (R) in [1, 32]; max_degree in
+ *   [degree, 64]; ef_construction in [1, 2048].
+ * Blocking: returns after the batch is complete on hip_stream.  On error
+ * adj may be partly updated only when the error is HENN_E_DEVICE. */
+henn_status henn_nsw_insert(const float *V, int64_t s, int32_t d, int32_t metric, int32_t *adj,
+                            int32_t max_degree, int64_t lo, int64_t hi, int32_t degree,
+                            int32_t ef_construction, void *hip_stream);
 
 #ifdef __cplusplus
 }

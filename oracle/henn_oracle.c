@@ -548,6 +548,115 @@ int ho_search(const float *X, int d, int metric, int num_layers, const int64_t *
 }
 
 /* ------------------------------------------------------------------ */
+/* NSW graph of one layer (App. B.2: points are inserted one after the   */
+/* other and joined to their nearest neighbours found in the graph built */
+/* so far), one batch of the insertion.  The layer's members are given   */
+/* by ascending global id; positions [0, lo) already form the graph in   */
+/* adj (local positions, M per row, -1 padded) and the positions         */
+/* [lo, hi) join it together:                                            */
+/*  1. each new point p runs SEARCH-LAYER with a beam of max(ef, R) over  */
+/*     the graph on [0, lo) from position 0, and its row becomes the R    */
+/*     best results (none when lo = 0);                                  */
+/*  2. every old point v chosen by some new points gets, as its row, the */
+/*     first M of (its row plus those new points) in (distance, id)      */
+/*     order.                                                            */
+/* Points of one batch do not see each other (batched insertion); a      */
+/* batch of one point is the plain sequential insertion.  margin[] is    */
+/* min-folded with each row's decision margins: the search trace of a    */
+/* new row, the adjacent keys and the M / M+1 cut of a merged row.       */
+/* ------------------------------------------------------------------ */
+static int64_t local_of(const int32_t *members, int64_t size, int64_t id) {
+  int64_t lo = 0, hi = size - 1;
+  while (lo < hi) {
+    int64_t mid = (lo + hi) / 2;
+    if (members[mid] < id) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+int ho_nsw_insert(const float *X, int d, int metric, const int32_t *members, int64_t s,
+                  int32_t *adj, int M, int64_t lo, int64_t hi, int R, int ef, double *margin) {
+  if (lo < 0 || hi > s || lo > hi || R < 1 || M < R || ef < 1) return -1;
+  if (hi == lo) return 0;
+  const int64_t nb = hi - lo;
+  const int efl = ef > R ? ef : R;
+  int32_t *rows = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nb * R));
+  int32_t *stamp = (int32_t *)calloc((size_t)(lo > 0 ? lo : 1), sizeof(int32_t));
+  dkey *res = (dkey *)malloc(sizeof(dkey) * (size_t)efl);
+  if (!rows || !stamp || !res) { free(rows); free(stamp); free(res); return -2; }
+  /* 1. searches over the graph on [0, lo) */
+  int32_t gen = 0;
+  for (int64_t p = lo; p < hi; ++p) {
+    int32_t *row = rows + (size_t)(p - lo) * (size_t)R;
+    for (int j = 0; j < R; ++j) row[j] = -1;
+    if (lo == 0) continue;
+    trace t;
+    t.X = X; t.d = d; t.metric = metric;
+    t.q = X + (size_t)members[p] * (size_t)d;
+    t.qnorm = norm64(t.q, d);
+    t.min_margin = INFINITY; t.min_adj_margin = INFINITY;
+    t.expansions = 0; t.evals = 0;
+    ++gen;
+    int64_t m = search_layer(&t, members, lo, adj, M, 0, 0, efl, stamp, gen, res);
+    int64_t kk = m < R ? m : R;
+    for (int64_t j = 1; j < kk + (m > R ? 1 : 0); ++j) note(&t, res[j - 1], res[j]);
+    for (int64_t j = 0; j < kk; ++j) row[j] = (int32_t)local_of(members, lo, res[j].id);
+    if (t.min_margin < margin[p]) margin[p] = t.min_margin;
+  }
+  for (int64_t p = lo; p < hi; ++p)
+    for (int j = 0; j < M; ++j)
+      adj[(size_t)p * M + j] = j < R ? rows[(size_t)(p - lo) * R + j] : -1;
+  /* 2. reverse edges: the new points that chose v, grouped per v */
+  int64_t *start = (int64_t *)calloc((size_t)lo + 1, sizeof(int64_t));
+  int32_t *chosen = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nb * R + 1));
+  int64_t *cur = (int64_t *)malloc(sizeof(int64_t) * (size_t)(lo + 1));
+  dkey *keys = (dkey *)malloc(sizeof(dkey) * (size_t)(M + nb + 1));
+  if (!start || !chosen || !cur || !keys) {
+    free(rows); free(stamp); free(res); free(start); free(chosen); free(cur); free(keys);
+    return -2;
+  }
+  for (int64_t i = 0; i < nb * R; ++i)
+    if (rows[i] >= 0) start[rows[i] + 1]++;
+  for (int64_t v = 0; v < lo; ++v) start[v + 1] += start[v];
+  for (int64_t v = 0; v < lo; ++v) cur[v] = start[v];
+  for (int64_t p = lo; p < hi; ++p)
+    for (int j = 0; j < R; ++j) {
+      int32_t v = rows[(size_t)(p - lo) * R + j];
+      if (v >= 0) chosen[cur[v]++] = (int32_t)p;
+    }
+  for (int64_t v = 0; v < lo; ++v) {
+    if (start[v + 1] == start[v]) continue;
+    trace t;
+    t.X = X; t.d = d; t.metric = metric;
+    t.q = X + (size_t)members[v] * (size_t)d;
+    t.qnorm = norm64(t.q, d);
+    t.min_margin = INFINITY;
+    int64_t cnt = 0;
+    for (int j = 0; j < M; ++j) {
+      int32_t u = adj[(size_t)v * M + j];
+      if (u < 0) continue;
+      keys[cnt].d = dist64(t.q, X + (size_t)members[u] * (size_t)d, d, metric);
+      keys[cnt].id = members[u];
+      ++cnt;
+    }
+    for (int64_t i = start[v]; i < start[v + 1]; ++i) {
+      int32_t u = chosen[i];
+      keys[cnt].d = dist64(t.q, X + (size_t)members[u] * (size_t)d, d, metric);
+      keys[cnt].id = members[u];
+      ++cnt;
+    }
+    qsort(keys, (size_t)cnt, sizeof(dkey), key_cmp);
+    int64_t lim = cnt < (int64_t)M + 1 ? cnt : (int64_t)M + 1;
+    for (int64_t r = 1; r < lim; ++r) note(&t, keys[r - 1], keys[r]);
+    for (int j = 0; j < M; ++j)
+      adj[(size_t)v * M + j] = j < cnt ? (int32_t)local_of(members, s, keys[j].id) : -1;
+    if (t.min_margin < margin[v]) margin[v] = t.min_margin;
+  }
+  free(rows); free(stamp); free(res); free(start); free(chosen); free(cur); free(keys);
+  return 0;
+}
+
+/* ------------------------------------------------------------------ */
 /* Brute-force exact k-NN (Sec. 2 problem setting): quality reference.  */
 /* ------------------------------------------------------------------ */
 int ho_brute_knn(const float *X, int64_t n, int d, int metric, const float *Q, int64_t q_begin,

@@ -13,7 +13,8 @@ of the paper's algorithms:
   Implementation", App. G.2) -- or, with ``sampler=1``, drawn by Alg. 3's
   halving (:func:`halve`, BuildEpsNetDiscV2) and checked the same way; each
   layer then gets an exact kNN navigable
-  graph (App. B.2, App. G.4).  Layer sizes follow Cor. "layer-size":
+  graph (App. B.2, App. G.4), or (``graph=4``) the NSW graph of App. B.2
+  built by batched incremental insertion (:func:`nsw_graph`).  Layer sizes follow Cor. "layer-size":
   ceil(|L_{i-1}| / 2^m) draws per layer.
 * :func:`search` -- Alg. 4 (Query) from the root down, ef=1 greedy on the
   upper layers and a beam of max(ef, k) candidates on layer 0 (Sec. 2.2).
@@ -95,6 +96,10 @@ def _load():
                                   ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
                                   ctypes.c_int, ctypes.c_int, c_i32p, c_f64p, c_f64p, c_f64p,
                                   c_i64p]
+        lib.ho_nsw_insert.restype = ctypes.c_int
+        lib.ho_nsw_insert.argtypes = [c_f32p, ctypes.c_int, ctypes.c_int, c_i32p, ctypes.c_int64,
+                                      c_i32p, ctypes.c_int, ctypes.c_int64, ctypes.c_int64,
+                                      ctypes.c_int, ctypes.c_int, c_f64p]
         lib.ho_knn_sym.restype = ctypes.c_int
         lib.ho_knn_sym.argtypes = [c_f32p, ctypes.c_int, ctypes.c_int, c_i32p, ctypes.c_int64,
                                    c_i32p, ctypes.c_int, ctypes.c_int, c_i32p, c_f64p, c_f64p]
@@ -190,7 +195,9 @@ class BuildParams:
     seed: int = 0
     graph: int = 0               # 0: exact kNN; 1: kNN plus reverse edges (kNN_SYM);
                                  # 2: diversity-pruned kNN (PRUNED); 3: PRUNED plus
-                                 # reverse edges (PRUNED_SYM)
+                                 # reverse edges (PRUNED_SYM); 4: NSW by batched insertion
+    ef_construction: int = 256   # NSW: beam width of the insertion searches
+    insert_shift: int = 3        # NSW: a batch after lo inserted points holds max(1, lo >> shift)
     max_degree: int = 32         # row cap of the graphs with reverse edges
     root_complete_max: int = 0   # > 0: stop adding layers once a layer holds at most
                                  # this many points and give that root the complete graph
@@ -391,6 +398,10 @@ def build_index(X: np.ndarray, p: BuildParams | None = None, threads=None) -> Or
             if p.graph == 3:
                 a, cut2, order2 = knn_sym(X, p.metric, mb, a, p.max_degree)
                 cut, order = np.minimum(cut, cut2), np.minimum(order, order2)
+        elif p.graph == 4:
+            a, order = nsw_graph(X, p.metric, mb, p.degree, p.max_degree, p.ef_construction,
+                                 p.insert_shift)
+            ad, cut = None, order.copy()
         else:
             a, ad, cut, order = knn_graph(X, p.metric, mb, p.degree, threads)
         if p.graph == 1:
@@ -425,6 +436,41 @@ def prune(X, metric, members, adj_in, keep):
     if rc != 0:
         raise RuntimeError("prune failed")
     return out, pm
+
+
+def nsw_batches(s: int, shift: int):
+    """Insertion batches of the NSW graph: [lo, lo + max(1, lo >> shift)), from lo = 0."""
+    lo = 0
+    while lo < s:
+        hi = min(s, lo + max(1, lo >> shift))
+        yield lo, hi
+        lo = hi
+
+
+def nsw_insert(X, metric, members, adj, margin, lo, hi, R, ef):
+    """One NSW insertion batch (ho_nsw_insert), in place on adj [s, M] and margin [s]."""
+    lib = _load()
+    assert adj.dtype == np.int32 and adj.flags.c_contiguous and margin.dtype == np.float64
+    rc = lib.ho_nsw_insert(_ptr(X, ctypes.c_float), X.shape[1], metric,
+                           _ptr(members, ctypes.c_int32), len(members),
+                           _ptr(adj, ctypes.c_int32), adj.shape[1], lo, hi, R, ef,
+                           _ptr(margin, ctypes.c_double))
+    if rc != 0:
+        raise RuntimeError(f"nsw_insert failed ({rc})")
+
+
+def nsw_graph(X, metric, members, R, M, ef, shift):
+    """App. B.2's NSW graph of one layer: the members join in ascending id
+    order, in the batches of :func:`nsw_batches`.  Returns (adjacency [s, M]
+    local positions in (distance, id) order, -1 padded; min decision margin per row)."""
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    members = np.ascontiguousarray(members, dtype=np.int32)
+    s = len(members)
+    adj = np.full((s, M), -1, dtype=np.int32)
+    margin = np.full(s, np.inf)
+    for lo, hi in nsw_batches(s, shift):
+        nsw_insert(X, metric, members, adj, margin, lo, hi, R, ef)
+    return adj, margin
 
 
 def knn_sym(X, metric, members, adj_knn, max_deg):

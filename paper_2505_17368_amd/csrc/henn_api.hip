@@ -73,8 +73,9 @@ static bool valid_build_params(const henn_build_params* p, std::string* why) {
   if (p->num_rings < 1 || p->num_rings > 4096) { *why = "num_rings in [1, 4096]"; return false; }
   if (p->max_attempts < 1) { *why = "max_attempts >= 1"; return false; }
   if (p->degree < 1 || p->degree > 32) { *why = "degree in [1, 32]"; return false; }
-  if (p->graph < HENN_GRAPH_KNN || p->graph > HENN_GRAPH_PRUNED_SYM) { *why = "graph"; return false; }
-  const bool sym = p->graph == HENN_GRAPH_KNN_SYM || p->graph == HENN_GRAPH_PRUNED_SYM;
+  if (p->graph < HENN_GRAPH_KNN || p->graph > HENN_GRAPH_NSW) { *why = "graph"; return false; }
+  const bool sym = p->graph == HENN_GRAPH_KNN_SYM || p->graph == HENN_GRAPH_PRUNED_SYM ||
+                   p->graph == HENN_GRAPH_NSW;
   if (sym && (p->max_degree < p->degree || p->max_degree > 64)) {
     *why = "max_degree in [degree, 64]"; return false;
   }
@@ -83,7 +84,112 @@ static bool valid_build_params(const henn_build_params* p, std::string* why) {
   if (p->sampler != HENN_SAMPLER_DRAWS && p->sampler != HENN_SAMPLER_HALVING) {
     *why = "sampler"; return false;
   }
+  if (p->graph == HENN_GRAPH_NSW) {
+    if (p->ef_construction < 1 || p->ef_construction > 2048) {
+      *why = "ef_construction in [1, 2048]"; return false;
+    }
+    if (p->insert_shift < 0 || p->insert_shift > 62) { *why = "insert_shift in [0, 62]"; return false; }
+  }
   return true;
+}
+
+// ---- NSW graphs (App. B.2) ---------------------------------------------------
+// Batched incremental insertion: the layer's members join in ascending id
+// order, in batches [lo, lo + max(1, lo >> insert_shift)).  The searches of
+// a batch are the library's own beam search (one FP32 layer: the graph on
+// [0, lo), entry position 0, beam max(ef_construction, R), top R), then
+// nsw_merge_batch writes the new rows and merges the reverse edges.
+struct NswWork {
+  int32_t* res = nullptr;
+  float* dist = nullptr;
+  uint32_t* cnt = nullptr;
+  uint32_t* off = nullptr;
+  int32_t* inl = nullptr;
+  NswWork(int64_t s, int64_t nb_max, int R) {
+    try {
+      res = dalloc<int32_t>(nb_max * R);
+      dist = dalloc<float>(nb_max * R);
+      cnt = dalloc<uint32_t>(s + 1);
+      off = dalloc<uint32_t>(s + 1);
+      inl = dalloc<int32_t>(nb_max * R);
+    } catch (...) {
+      release();
+      throw;
+    }
+  }
+  ~NswWork() { release(); }
+  void release() {
+    (void)hipFree(res);
+    (void)hipFree(dist);
+    (void)hipFree(cnt);
+    (void)hipFree(off);
+    (void)hipFree(inl);
+    res = nullptr;
+    dist = nullptr;
+    cnt = off = nullptr;
+    inl = nullptr;
+  }
+};
+
+static int64_t nsw_batch_end(int64_t lo, int64_t s, int shift) {
+  return std::min(s, lo + std::max<int64_t>(1, lo >> shift));
+}
+
+// vec: FP32 rows [>= hi][dpad]; adj: [>= hi][M], rows < lo hold the graph.
+static void nsw_insert_batch(int device, const float* vec, int dpad, int nchunks, int metric,
+                             int32_t* adj, int M, int64_t lo, int64_t hi, int R, int ef,
+                             const NswWork& w, hipStream_t st) {
+  const int64_t nb = hi - lo;
+  if (nb <= 0) return;
+  if (lo == 0) {
+    HENN_HIP(hipMemsetAsync(w.res, 0xFF, sizeof(int32_t) * nb * R, st));  // no graph yet
+  } else {
+    henn_index g;  // a one-layer view of the graph on [0, lo); owns nothing
+    g.n = lo;
+    g.d = dpad;
+    g.dpad = dpad;
+    g.nchunks = nchunks;
+    g.metric = metric;
+    g.storage = HENN_F32;
+    g.num_layers = 1;
+    g.device = device;
+    g.L[0].size = lo;
+    g.L[0].deg = M;
+    g.L[0].vec32 = const_cast<float*>(vec);
+    g.L[0].adj = adj;
+    henn_search_params sp;
+    henn_default_search_params(&sp);
+    sp.k_all = R;
+    sp.k_max = R;
+    sp.ef_all = std::max(ef, R);
+    if (henn_search_batch(&g, vec + lo * dpad, nb, &sp, w.res, w.dist, st) != HENN_OK)
+      throw HipError{hipErrorInvalidValue, "NSW insertion search"};
+  }
+  int lpn, cpl;
+  pick_lanes(nchunks, 0, &lpn, &cpl);
+  nsw_merge_batch(vec, dpad, nchunks, metric, w.res, lo, nb, R, adj, M, w.cnt, w.off, w.inl, lpn,
+                  cpl, st);
+}
+
+static int32_t* nsw_graph(henn_index* ix, const float* vec, int64_t s, hipStream_t st) {
+  const henn_build_params& p = ix->params;
+  const int M = p.max_degree, R = p.degree;
+  int32_t* adj = dalloc<int32_t>(s * M);
+  try {
+    HENN_HIP(hipMemsetAsync(adj, 0xFF, sizeof(int32_t) * s * M, st));
+    const NswWork w(s, std::max<int64_t>(1, s >> p.insert_shift), R);
+    for (int64_t lo = 0; lo < s;) {
+      const int64_t hi = nsw_batch_end(lo, s, p.insert_shift);
+      nsw_insert_batch(ix->device, vec, ix->dpad, ix->nchunks, ix->metric, adj, M, lo, hi, R,
+                       p.ef_construction, w, st);
+      lo = hi;
+    }
+    HENN_HIP(hipStreamSynchronize(st));
+  } catch (...) {
+    (void)hipFree(adj);
+    throw;
+  }
+  return adj;
 }
 
 // Finishes a layer: graph (+ optional symmetrisation) and traversal copy.
@@ -92,44 +198,49 @@ static void finish_layer(henn_index* ix, int i, hipStream_t st) {
   const henn_build_params& p = ix->params;
   int lpn, cpl;
   pick_lanes(ix->nchunks, 0, &lpn, &cpl);
-  const bool pruned = p.graph == HENN_GRAPH_PRUNED || p.graph == HENN_GRAPH_PRUNED_SYM;
-  const int R = p.degree;
-  // the pruned graphs scan the exact top min(2R, 32) candidates
-  const int C = pruned ? std::min(2 * R, 32) : R;
-  int32_t* adj = dalloc<int32_t>(L.size * R);
-  int32_t* cand = pruned ? dalloc<int32_t>(L.size * C) : adj;
-  try {
-    L.info.fallback_rows =
-        (int32_t)build_knn_graph(L.vec32, L.size, ix->dpad, ix->nchunks, ix->metric, C, lpn, cpl,
-                                 cand, st);
-    if (pruned) {
-      prune_graph(L.vec32, L.size, ix->dpad, ix->nchunks, ix->metric, cand, C, R, adj, lpn, cpl,
-                  st);
-      HENN_HIP(hipStreamSynchronize(st));
-      (void)hipFree(cand);
-      cand = adj;
-    }
-  } catch (...) {
-    if (cand != adj) (void)hipFree(cand);
-    (void)hipFree(adj);
-    throw;
-  }
-  if (p.graph == HENN_GRAPH_KNN_SYM || p.graph == HENN_GRAPH_PRUNED_SYM) {
-    int32_t* adj2 = dalloc<int32_t>(L.size * p.max_degree);
-    try {
-      symmetrize_graph(L.vec32, L.size, ix->dpad, ix->nchunks, ix->metric, adj, R, adj2,
-                       p.max_degree, lpn, cpl, st);
-    } catch (...) {
-      (void)hipFree(adj);
-      (void)hipFree(adj2);
-      throw;
-    }
-    (void)hipFree(adj);
-    L.adj = adj2;
+  if (p.graph == HENN_GRAPH_NSW) {
+    L.adj = nsw_graph(ix, L.vec32, L.size, st);
     L.deg = p.max_degree;
   } else {
-    L.adj = adj;
-    L.deg = R;
+    const bool pruned = p.graph == HENN_GRAPH_PRUNED || p.graph == HENN_GRAPH_PRUNED_SYM;
+    const int R = p.degree;
+    // the pruned graphs scan the exact top min(2R, 32) candidates
+    const int C = pruned ? std::min(2 * R, 32) : R;
+    int32_t* adj = dalloc<int32_t>(L.size * R);
+    int32_t* cand = pruned ? dalloc<int32_t>(L.size * C) : adj;
+    try {
+      L.info.fallback_rows =
+          (int32_t)build_knn_graph(L.vec32, L.size, ix->dpad, ix->nchunks, ix->metric, C, lpn, cpl,
+                                   cand, st);
+      if (pruned) {
+        prune_graph(L.vec32, L.size, ix->dpad, ix->nchunks, ix->metric, cand, C, R, adj, lpn, cpl,
+                    st);
+        HENN_HIP(hipStreamSynchronize(st));
+        (void)hipFree(cand);
+        cand = adj;
+      }
+    } catch (...) {
+      if (cand != adj) (void)hipFree(cand);
+      (void)hipFree(adj);
+      throw;
+    }
+    if (p.graph == HENN_GRAPH_KNN_SYM || p.graph == HENN_GRAPH_PRUNED_SYM) {
+      int32_t* adj2 = dalloc<int32_t>(L.size * p.max_degree);
+      try {
+        symmetrize_graph(L.vec32, L.size, ix->dpad, ix->nchunks, ix->metric, adj, R, adj2,
+                         p.max_degree, lpn, cpl, st);
+      } catch (...) {
+        (void)hipFree(adj);
+        (void)hipFree(adj2);
+        throw;
+      }
+      (void)hipFree(adj);
+      L.adj = adj2;
+      L.deg = p.max_degree;
+    } else {
+      L.adj = adj;
+      L.deg = R;
+    }
   }
   L.info.degree = L.deg;
   if (ix->storage != HENN_F32) {
@@ -365,6 +476,8 @@ henn_status henn_default_build_params(henn_build_params* p) {
   p->storage = HENN_F32;
   p->seed = 0;
   p->sampler = HENN_SAMPLER_DRAWS;
+  p->ef_construction = 256;
+  p->insert_shift = 3;
   return HENN_OK;
 }
 
@@ -535,6 +648,43 @@ henn_status henn_import(const float* X, int64_t n, int32_t d, const henn_build_p
     destroy(ix);
     return fail(HENN_E_NOMEM, "host allocation failed");
   }
+}
+
+henn_status henn_nsw_insert(const float* V, int64_t s, int32_t d, int32_t metric, int32_t* adj,
+                            int32_t max_degree, int64_t lo, int64_t hi, int32_t degree,
+                            int32_t ef_construction, void* hip_stream) {
+  if (!V || !adj) return fail(HENN_E_INVAL, "null V or adj");
+  if (s < 1 || s > 2147483647ll) return fail(HENN_E_INVAL, "s must be in [1, 2^31-1]");
+  if (d < 1 || d > 1024) return fail(HENN_E_INVAL, "d must be in [1, 1024]");
+  if (metric != HENN_L2 && metric != HENN_IP) return fail(HENN_E_INVAL, "metric");
+  if (lo < 0 || hi < lo || hi > s) return fail(HENN_E_INVAL, "need 0 <= lo <= hi <= s");
+  if (degree < 1 || degree > 32) return fail(HENN_E_INVAL, "degree in [1, 32]");
+  if (max_degree < degree || max_degree > 64)
+    return fail(HENN_E_INVAL, "max_degree in [degree, 64]");
+  if (ef_construction < 1 || ef_construction > 2048)
+    return fail(HENN_E_INVAL, "ef_construction in [1, 2048]");
+  if (hi == lo) return HENN_OK;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const int dpad = (d + 7) / 8 * 8;
+  float* vec = nullptr;
+  try {
+    int device = 0;
+    HENN_HIP(hipGetDevice(&device));
+    vec = dalloc<float>(hi * dpad);  // the rows in the library's padded layout
+    launch_copy_rows(V, d, nullptr, hi, d, vec, dpad, st);
+    const NswWork w(hi, hi - lo, degree);
+    nsw_insert_batch(device, vec, dpad, dpad / 8, metric, adj, max_degree, lo, hi, degree,
+                     ef_construction, w, st);
+    HENN_HIP(hipStreamSynchronize(st));
+  } catch (const HipError& e) {
+    (void)hipFree(vec);
+    return from_hip(e);
+  } catch (const std::bad_alloc&) {
+    (void)hipFree(vec);
+    return fail(HENN_E_NOMEM, "host allocation failed");
+  }
+  (void)hipFree(vec);
+  return HENN_OK;
 }
 
 // How a complete-graph root is scanned: 0 inside the search kernel (or no

@@ -262,6 +262,13 @@ void symmetrize_graph(const float* vec, int64_t size, int dpad, int nchunks, int
 // Diversity pruning of C <= 32 candidates per row (ascending, -1 padded)
 // to at most R kept neighbours (-1 padded), as the NSW/HNSW neighbour
 // selection does.
+// One NSW insertion batch after its searches (res: [nb][R] positions of the
+// new points [lo, lo + nb), -1 padded): writes their rows and merges the
+// reverse edges into the rows of [0, lo).  Scratch: cnt and off hold lo + 1
+// entries, inl nb * R.
+void nsw_merge_batch(const float* vec, int dpad, int nchunks, int metric, const int32_t* res,
+                     int64_t lo, int64_t nb, int R, int32_t* adj, int M, uint32_t* cnt,
+                     uint32_t* off, int32_t* inl, int lpn, int cpl, hipStream_t st);
 void prune_graph(const float* vec, int64_t size, int dpad, int nchunks, int metric,
                  const int32_t* adj_in, int C, int R, int32_t* adj_out, int lpn, int cpl,
                  hipStream_t st);

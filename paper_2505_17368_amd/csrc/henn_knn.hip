@@ -787,12 +787,13 @@ __global__ void k_indeg(const int32_t* adj, int64_t edges, uint32_t* cnt) {
   if (u >= 0) atomicAdd(cnt + u, 1u);
 }
 
-__global__ void k_scatter_in(const int32_t* adj, int64_t edges, int R, uint32_t* cursor,
-                             int32_t* inl) {
+// in-lists: row r of adj (R entries) is the source src_base + r
+__global__ void k_scatter_in(const int32_t* adj, int64_t edges, int R, int64_t src_base,
+                             uint32_t* cursor, int32_t* inl) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= edges) return;
   const int32_t u = adj[e];
-  if (u >= 0) inl[atomicAdd(cursor + u, 1u)] = (int32_t)(e / R);
+  if (u >= 0) inl[atomicAdd(cursor + u, 1u)] = (int32_t)(src_base + e / R);
 }
 
 template <int LPN, int CPL>
@@ -866,7 +867,8 @@ void symmetrize_graph(const float* vec, int64_t size, int dpad, int nchunks, int
   hipLaunchKernelGGL(k_indeg, dim3(eb), dim3(256), 0, st, adj_knn, edges, cnt);
   exclusive_scan_u32(cnt, size, off, st);
   HENN_HIP(hipMemcpyAsync(cnt, off, sizeof(uint32_t) * size, hipMemcpyDeviceToDevice, st));
-  hipLaunchKernelGGL(k_scatter_in, dim3(eb), dim3(256), 0, st, adj_knn, edges, R, cnt, inl);
+  hipLaunchKernelGGL(k_scatter_in, dim3(eb), dim3(256), 0, st, adj_knn, edges, R, (int64_t)0,
+                     cnt, inl);
   const unsigned nb = (unsigned)((size + 3) / 4);
   bool launched = false;
 #define HENN_TRY(L, C)                                                                          \
@@ -882,6 +884,97 @@ void symmetrize_graph(const float* vec, int64_t size, int dpad, int nchunks, int
   HENN_HIP(hipFree(off));
   HENN_HIP(hipFree(inl));
   if (!launched) throw HipError{hipErrorInvalidValue, "no merge kernel for this lane shape"};
+}
+
+// ---------------------------------------------------------------- NSW -----
+// One batch of the NSW insertion (App. B.2), after the batch's searches:
+// the new rows [lo, lo + nb) take their R results, -1 padded to M; the old
+// points they chose collect them as in-lists (count, scan, scatter as for
+// kNN_SYM); then one wave per chosen old point v merges its row with its
+// in-list by (distance, id) in chunks of 64 keys and keeps the first M, in
+// place (a wave reads its whole row before it writes it, and no other wave
+// touches that row).
+__global__ void k_nsw_rows(const int32_t* res, int64_t nb, int R, int M, int64_t lo,
+                           int32_t* adj) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nb * M) return;
+  const int64_t r = e / M;
+  const int j = (int)(e % M);
+  adj[(lo + r) * M + j] = j < R ? res[r * R + j] : -1;
+}
+
+template <int LPN, int CPL>
+__global__ __launch_bounds__(256) void k_nsw_merge(const float* vec, int64_t lo, int dpad,
+                                                   int nchunks, int metric, const uint32_t* off,
+                                                   const int32_t* inl, int M, int32_t* adj) {
+  constexpr int G = 64 / LPN;
+  __shared__ int32_t cids[4][64];
+  __shared__ uint64_t keys[4][64];
+  const int w = threadIdx.x >> 6;
+  const int64_t v = (int64_t)blockIdx.x * 4 + w;
+  if (v >= lo) return;
+  const int64_t ib = off[v];
+  const int64_t nin = (int64_t)(off[v + 1] - off[v]);
+  if (nin == 0) return;  // whole wave: v was chosen by no new point
+  const int lane = lane_id(), t = lane % LPN, g = lane / LPN;
+  const int32_t mine = lane < M ? adj[v * M + lane] : -1;  // the row, read before any write
+  float q[CPL][8];
+  load_query<CPL>(vec + v * dpad, dpad, t, q);
+  const int64_t total = 64 + nin;
+  uint64_t best = ~0ull;
+  for (int64_t base = 0; base < total; base += 64) {
+    const int64_t j = base + lane;
+    cids[w][lane] = base == 0 ? mine : j < total ? inl[ib + (j - 64)] : -1;
+    wave_sync();
+    for (int pb = 0; pb < 64; pb += G) {
+      const int ci = pb + g;
+      const int32_t id = cids[w][ci];
+      const bool valid = id >= 0;
+      const float dist = group_distance<kF32, LPN, CPL>(
+          q, vec + (int64_t)(valid ? id : 0) * dpad, 1.0f, t, nchunks, metric, valid);
+      if (t == 0) keys[w][ci] = valid ? dkey(dist, id) : ~0ull;
+    }
+    wave_sync();
+    const uint64_t c = wave_sort64(keys[w][lane]);
+    const uint64_t rc = shfl_u64(c, 63 - lane);
+    uint64_t m = rc < best ? rc : best;
+    for (int stride = 32; stride > 0; stride >>= 1) {
+      const uint64_t o = shfl_xor_u64(m, stride);
+      const bool lower = (lane & stride) == 0;
+      m = lower ? (o < m ? o : m) : (o < m ? m : o);
+    }
+    best = m;
+    wave_sync();
+  }
+  if (lane < M) adj[v * M + lane] = best == ~0ull ? -1 : (int32_t)(uint32_t)best;
+}
+
+void nsw_merge_batch(const float* vec, int dpad, int nchunks, int metric, const int32_t* res,
+                     int64_t lo, int64_t nb, int R, int32_t* adj, int M, uint32_t* cnt,
+                     uint32_t* off, int32_t* inl, int lpn, int cpl, hipStream_t st) {
+  const int64_t rows = nb * M;
+  hipLaunchKernelGGL(k_nsw_rows, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, st, res,
+                     nb, R, M, lo, adj);
+  if (lo == 0) return;
+  const int64_t edges = nb * R;
+  const unsigned eb = (unsigned)((edges + 255) / 256);
+  HENN_HIP(hipMemsetAsync(cnt, 0, sizeof(uint32_t) * (lo + 1), st));
+  hipLaunchKernelGGL(k_indeg, dim3(eb), dim3(256), 0, st, res, edges, cnt);
+  exclusive_scan_u32(cnt, lo, off, st);
+  HENN_HIP(hipMemcpyAsync(cnt, off, sizeof(uint32_t) * lo, hipMemcpyDeviceToDevice, st));
+  hipLaunchKernelGGL(k_scatter_in, dim3(eb), dim3(256), 0, st, res, edges, R, lo, cnt, inl);
+  const unsigned mb = (unsigned)((lo + 3) / 4);
+  bool launched = false;
+#define HENN_TRY(L, C)                                                                          \
+  if (!launched && lpn == L && cpl == C) {                                                      \
+    hipLaunchKernelGGL((k_nsw_merge<L, C>), dim3(mb), dim3(256), 0, st, vec, lo, dpad, nchunks, \
+                       metric, off, inl, M, adj);                                               \
+    launched = true;                                                                            \
+  }
+  HENN_KNN_COMBOS(HENN_TRY)
+#undef HENN_TRY
+  if (!launched) throw HipError{hipErrorInvalidValue, "no merge kernel for this lane shape"};
+  HENN_HIP(hipGetLastError());
 }
 
 }  // namespace henn

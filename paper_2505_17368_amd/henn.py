@@ -23,7 +23,7 @@ HENN_W_NOT_VERIFIED = 100
 HENN_L2, HENN_IP = 0, 1
 HENN_F32, HENN_BF16, HENN_FP8_E4M3 = 0, 1, 2
 HENN_GRAPH_KNN, HENN_GRAPH_KNN_SYM, HENN_GRAPH_PRUNED, HENN_GRAPH_PRUNED_SYM = 0, 1, 2, 3
-GRAPH = {"knn": 0, "knn_sym": 1, "pruned": 2, "pruned_sym": 3}
+GRAPH = {"knn": 0, "knn_sym": 1, "pruned": 2, "pruned_sym": 3, "nsw": 4}
 SAMPLER = {"draws": 0, "halving": 1}
 HENN_SEARCH_COUNTERS, HENN_SEARCH_PERSISTENT, HENN_SEARCH_NO_ROOT_KERNEL = 1, 2, 4
 HENN_SEARCH_ROOT_VALU = 8
@@ -39,7 +39,8 @@ class BuildParams(ctypes.Structure):
                 ("max_attempts", ctypes.c_int32), ("degree", ctypes.c_int32),
                 ("max_degree", ctypes.c_int32), ("graph", ctypes.c_int32),
                 ("storage", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("root_complete_max", ctypes.c_int32), ("sampler", ctypes.c_int32)]
+                ("root_complete_max", ctypes.c_int32), ("sampler", ctypes.c_int32),
+                ("ef_construction", ctypes.c_int32), ("insert_shift", ctypes.c_int32)]
 
 
 class SearchParams(ctypes.Structure):
@@ -130,6 +131,9 @@ def load_library(path: str = LIB_PATH):
     lib.henn_server_destroy.restype = None
     lib.henn_import.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, P(BuildParams), ctypes.c_int32,
                                 P(ctypes.c_int64), P(vp), P(vp), ctypes.c_int32, vp, P(vp)]
+    lib.henn_nsw_insert.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, vp,
+                                    ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
+                                    ctypes.c_int32, vp]
     for name in ("henn_default_build_params", "henn_default_search_params", "henn_build",
                  "henn_search_batch", "henn_index_shape", "henn_layer_info_get",
                  "henn_export_layer", "henn_import", "henn_autotune",
@@ -137,7 +141,7 @@ def load_library(path: str = LIB_PATH):
                  "henn_search_graph_launch", "henn_default_server_params", "henn_server_create",
                  "henn_server_submit", "henn_server_submit_batch", "henn_server_tick",
                  "henn_server_poll",
-                 "henn_server_stats"):
+                 "henn_server_stats", "henn_nsw_insert"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -279,6 +283,23 @@ def henn_import(X, ids_per_layer, adj_per_layer, params: BuildParams | None = No
                                     _stream_ptr(stream), ctypes.byref(h))
     _check(st)
     return HennIndex(h, st)
+
+
+def henn_nsw_insert(V, adj, lo: int, hi: int, degree: int, ef_construction: int,
+                    metric=HENN_L2, stream=None) -> None:
+    """One NSW insertion batch on a caller-held graph: V device FP32 [s, d],
+    adj device int32 [s, max_degree] (updated in place)."""
+    import torch
+    V = _dev_f32(V, "V")
+    if not (adj.is_cuda and adj.dtype == torch.int32 and adj.is_contiguous()
+            and adj.dim() == 2 and adj.shape[0] == V.shape[0]):
+        raise ValueError("adj must be a contiguous int32 device tensor [s, max_degree]")
+    if isinstance(metric, str):
+        metric = METRIC[metric]
+    _check(load_library().henn_nsw_insert(
+        ctypes.c_void_p(V.data_ptr()), V.shape[0], V.shape[1], metric,
+        ctypes.c_void_p(adj.data_ptr()), adj.shape[1], lo, hi, degree, ef_construction,
+        _stream_ptr(stream)))
 
 
 def search_params(k=10, ef=32, k_arr=None, ef_arr=None, k_max=None, ef_max=None, ef_upper=1,

@@ -22,7 +22,7 @@ def test_exports_every_declared_symbol(lib):
 
 def test_struct_sizes_match_header(lib):
     p = hn.default_build_params()
-    assert p.struct_size == ctypes.sizeof(hn.BuildParams) == 72
+    assert p.struct_size == ctypes.sizeof(hn.BuildParams) == 80
     sp = hn.SearchParams()
     assert lib.henn_default_search_params(ctypes.byref(sp)) == hn.HENN_OK
     assert sp.struct_size == ctypes.sizeof(hn.SearchParams) == 104
@@ -32,8 +32,9 @@ def test_struct_sizes_match_header(lib):
 def test_defaults(lib):
     p = hn.default_build_params()
     assert (p.metric, p.max_layers, p.m, p.c0, p.num_rings, p.max_attempts, p.degree,
-            p.max_degree, p.graph, p.storage, p.seed, p.root_complete_max, p.sampler) == (
-                0, -1, 4, 1.0, 64, 64, 16, 32, 0, 0, 0, 0, 0)
+            p.max_degree, p.graph, p.storage, p.seed, p.root_complete_max, p.sampler,
+            p.ef_construction, p.insert_shift) == (
+                0, -1, 4, 1.0, 64, 64, 16, 32, 0, 0, 0, 0, 0, 256, 3)
     sp = hn.SearchParams()
     lib.henn_default_search_params(ctypes.byref(sp))
     assert (sp.k_all, sp.ef_all, sp.k_max, sp.ef_upper, sp.rerank_factor) == (10, 32, 10, 1, 4)
@@ -54,13 +55,28 @@ def test_invalid_arguments_rejected_on_host(lib):
     assert lib.henn_build(fake, 10, 4, ctypes.byref(bad), None, ctypes.byref(h)) == hn.HENN_E_INVAL
     bad = hn.default_build_params(degree=0)
     assert lib.henn_build(fake, 10, 4, ctypes.byref(bad), None, ctypes.byref(h)) == hn.HENN_E_INVAL
-    # graph kinds: 0..3; the ones with reverse edges need degree <= max_degree <= 64
-    for graph, maxdeg in ((4, 32), (-1, 32), (3, 8), (3, 65), (1, 65)):
+    # graph kinds: 0..4; the ones with reverse edges and NSW need degree <= max_degree <= 64
+    for graph, maxdeg in ((5, 32), (-1, 32), (3, 8), (3, 65), (1, 65), (4, 8), (4, 65)):
         bad = hn.default_build_params(degree=16, graph=graph, max_degree=maxdeg)
         assert lib.henn_build(fake, 10, 4, ctypes.byref(bad), None,
                               ctypes.byref(h)) == hn.HENN_E_INVAL, (graph, maxdeg)
         assert "graph" in hn.last_error() or "max_degree" in hn.last_error()
-    assert hn.GRAPH == {"knn": 0, "knn_sym": 1, "pruned": 2, "pruned_sym": 3}
+    assert hn.GRAPH == {"knn": 0, "knn_sym": 1, "pruned": 2, "pruned_sym": 3, "nsw": 4}
+    for kw in (dict(ef_construction=0), dict(ef_construction=2049), dict(insert_shift=-1),
+               dict(insert_shift=63)):
+        bad = hn.default_build_params(graph="nsw", **kw)
+        assert lib.henn_build(fake, 10, 4, ctypes.byref(bad), None,
+                              ctypes.byref(h)) == hn.HENN_E_INVAL, kw
+    # NSW insertion batch: argument checks happen on the host
+    ok = dict(s=100, d=8, metric=0, M=16, lo=10, hi=20, R=8, ef=32)
+    for kw in (dict(lo=30), dict(hi=101), dict(lo=-1), dict(R=0), dict(R=33), dict(M=4),
+               dict(M=65), dict(ef=0), dict(ef=4096), dict(d=0), dict(d=1025), dict(metric=2),
+               dict(s=0)):
+        a = {**ok, **kw}
+        assert lib.henn_nsw_insert(fake, a["s"], a["d"], a["metric"], fake, a["M"], a["lo"],
+                                   a["hi"], a["R"], a["ef"], None) == hn.HENN_E_INVAL, kw
+    assert lib.henn_nsw_insert(None, 100, 8, 0, fake, 16, 0, 1, 8, 32, None) == hn.HENN_E_INVAL
+    assert lib.henn_nsw_insert(fake, 100, 8, 0, fake, 16, 5, 5, 8, 32, None) == hn.HENN_OK
     assert hn.default_build_params(graph="pruned_sym").graph == 3
     # samplers: 0 draws (Alg. 2), 1 halving (Alg. 3)
     for sampler in (2, -1):

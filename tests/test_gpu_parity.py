@@ -557,3 +557,61 @@ def test_visited_tags_and_ids_give_the_same_results(hn, cfg1_sym_root, storage):
         assert np.array_equal(a_i.cpu().numpy(), b_i.cpu().numpy())
         assert np.array_equal(a_d.cpu().numpy().view(np.uint32), b_d.cpu().numpy().view(np.uint32))
     idx.free()
+
+
+# ---------------------------------------------------------------- NSW graphs
+
+@pytest.mark.parametrize("metric,d", [(0, 16), (1, 20)])
+def test_nsw_insert_batch_matches_oracle(hn, ho, metric, d):
+    """One NSW insertion batch on the GPU against the oracle's batch from the
+    same graph state: every row either matches or was decided by a near tie."""
+    import torch
+    s, R, M, ef = 3000, 8, 16, 32
+    X = np.ascontiguousarray(wl.uniform(s, d, 31) - (0.5 if metric else 0.0), dtype=np.float32)
+    mb = np.arange(s, dtype=np.int32)
+    adj = np.full((s, M), -1, np.int32)
+    batches = list(ho.nsw_batches(s, 3))
+    check = {0, 1, 5, 12, len(batches) // 2, len(batches) - 1}
+    Vd = to_dev(X)
+    tied = 0
+    for bi, (lo, hi) in enumerate(batches):
+        if bi in check:
+            g = torch.from_numpy(adj.copy()).to("cuda:0")
+            hn.henn_nsw_insert(Vd, g, lo, hi, R, ef, metric=metric)
+            got = g.cpu().numpy()
+        bm = np.full(s, np.inf)
+        ho.nsw_insert(X, metric, mb, adj, bm, lo, hi, R, ef)
+        if bi in check:
+            diff = np.any(got != adj, axis=1)
+            tie = bm < 1e-5
+            assert not np.any(diff & ~tie), (bi, lo, hi, np.where(diff & ~tie)[0][:5])
+            assert np.all(got[hi:] == -1)
+            tied += int(tie.sum())
+    assert tied < 0.05 * s
+
+
+@pytest.mark.parametrize("metric", [0, 1])
+def test_nsw_build_matches_oracle(hn, ho, metric):
+    """Whole NSW builds: same layers, nearly all rows identical (a near tie in
+    one batch can move later rows), and the same search quality."""
+    X = np.ascontiguousarray(wl.uniform(6000, 24, 41) - (0.5 if metric else 0.0),
+                             dtype=np.float32)
+    Q = np.ascontiguousarray(wl.uniform(300, 24, 42) - (0.5 if metric else 0.0),
+                             dtype=np.float32)
+    p = dict(degree=8, max_degree=16, graph=4, ef_construction=48, seed=5, metric=metric)
+    oidx = ho.build_index(X, ho.BuildParams(**p))
+    idx = hn.henn_build(to_dev(X), **p)
+    layers = _gpu_layers(idx)
+    assert len(layers) == oidx.num_layers
+    for i, (ids, adj) in enumerate(layers):
+        assert np.array_equal(ids, oidx.members[i])
+        same = (adj == oidx.adj[i]).all(1).mean()
+        print(f"layer {i}: {same:.4f} of {len(ids)} rows identical")
+        assert same >= 0.98, (i, same)
+    gi, gd = hn.henn_search_batch(idx, to_dev(Q), k=10, ef=48)
+    ores = ho.search(oidx, Q, k=10, ef=48)
+    _, gt_d = ho.brute_force_knn(X, Q, 10, metric)
+    rg = ho.recall_at_k(gi.cpu().numpy(), gt_d, X, Q, metric)
+    ro = ho.recall_at_k(ores.ids, gt_d, X, Q, metric)
+    assert rg > 0.8 and abs(rg - ro) < 0.02, (rg, ro)      # 24-d uniform data, ef 48
+    idx.free()

@@ -10,6 +10,8 @@ an independent library routine or a brute-force recomputation:
 * Alg. 2 layer samples against ``np.unique`` of NumPy-Philox draws.
 * Alg. 3 halving: sizes ceil(s / 2^m), one survivor per dyadic block, fair
   and independent coins, and a backward walk with NumPy-Philox coins.
+* NSW graphs (App. B.2): with a beam as wide as the layer the insertion
+  equals exact k-NN over the inserted prefix (brute force); row invariants.
 * Ring ranges (Def. Ring Ranges) and the hit test against a NumPy lexsort.
 * The exact kNN graph (App. B.2) against NumPy all-pairs + lexsort.
 * Search: complete graph => exact k-NN (App. B.2: the complete graph is
@@ -266,6 +268,98 @@ def test_halving_layer_las_vegas(oracle):
     assert infos[1].status == "verified" and infos[1].attempts == accepted + 1
     assert len(members[1]) == 125
     assert np.array_equal(members[1], _numpy_halving_walk(3, 1, accepted, s, 4))
+
+
+# ---------------------------------------------------- NSW (App. B.2) -------
+
+def test_nsw_batch_schedule(oracle):
+    for s, shift in [(1, 3), (17, 3), (1000, 3), (1000, 0), (300, 62)]:
+        b = list(oracle.nsw_batches(s, shift))
+        assert b[0] == (0, 1) and b[-1][1] == s
+        assert all(b[i][1] == b[i + 1][0] for i in range(len(b) - 1))
+        assert all(hi - lo == min(s - lo, max(1, lo >> shift)) for lo, hi in b)
+        if shift == 62:
+            assert len(b) == s            # one point at a time: plain sequential insertion
+
+
+def _nsw_by_exact_prefix_knn(X, metric, R, M, shift):
+    """The NSW rule with every insertion search replaced by an exact k-NN
+    over the points inserted before the batch (what a beam as wide as the
+    layer finds on a connected graph).  Also reports whether a row ever
+    overflowed M (a dropped reverse edge could disconnect the graph)."""
+    s = len(X)
+    D = np.array([[d64_seq(X[i], X[j], metric) for j in range(s)] for i in range(s)])
+    rows = [[] for _ in range(s)]
+    overflow = False
+    lo = 0
+    while lo < s:
+        hi = min(s, lo + max(1, lo >> shift))
+        new = {}
+        for p in range(lo, hi):
+            order = np.lexsort((np.arange(lo), D[p, :lo]))
+            new[p] = order[:R].tolist()
+        chosen = {}
+        for p in range(lo, hi):
+            rows[p] = list(new[p])
+            for v in new[p]:
+                chosen.setdefault(v, []).append(p)
+        for v, ps in chosen.items():
+            cand = rows[v] + ps
+            overflow |= len(cand) > M
+            cand.sort(key=lambda u: (D[v, u], u))
+            rows[v] = cand[:M]
+        lo = hi
+    adj = np.full((s, M), -1, dtype=np.int32)
+    for v in range(s):
+        adj[v, :len(rows[v])] = rows[v]
+    return adj, overflow
+
+
+@pytest.mark.parametrize("metric,shift", [(0, 62), (0, 2), (1, 3)])
+def test_nsw_with_exhaustive_beam_is_prefix_knn(oracle, metric, shift):
+    X = wl.uniform(150, 4, 21) - (0.5 if metric == 1 else 0.0)
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    mb = np.arange(150, dtype=np.int32)
+    ref, overflow = _nsw_by_exact_prefix_knn(X, metric, 4, 64, shift)
+    assert not overflow, "fixture must keep every reverse edge"
+    got, _ = oracle.nsw_graph(X, metric, mb, 4, 64, 150, shift)
+    assert np.array_equal(got, ref)
+
+
+def test_nsw_graph_invariants(oracle):
+    X = wl.uniform(2000, 8, 4)
+    mb = np.arange(2000, dtype=np.int32)
+    R, M = 8, 16
+    adj, _ = oracle.nsw_graph(X, 0, mb, R, M, 32, 3)
+    X64 = X.astype(np.float64)
+    for v in range(2000):
+        row = adj[v][adj[v] >= 0]
+        assert np.all(adj[v][len(row):] == -1)            # padding only at the end
+        assert len(set(row.tolist())) == len(row) and v not in row
+        if v > 0:
+            assert len(row) >= 1
+        d = ((X64[row] - X64[v]) ** 2).sum(1)
+        assert np.all(np.diff(d) >= -1e-12)              # (distance, id) order
+    # the graph is navigable from the entry in practice: BFS from position 0
+    seen = np.zeros(2000, bool)
+    seen[0] = True
+    frontier = [0]
+    while frontier:
+        nxt = [u for v in frontier for u in adj[v] if u >= 0 and not seen[u]]
+        for u in nxt:
+            seen[u] = True
+        frontier = list(set(nxt))
+    assert seen.mean() > 0.99
+
+
+def test_nsw_index_search_quality(oracle):
+    X = wl.uniform(4000, 8, 6)
+    Q = wl.uniform(200, 8, 7)
+    idx = oracle.build_index(X, oracle.BuildParams(degree=8, max_degree=16, graph=4,
+                                                   ef_construction=32, seed=2))
+    res = oracle.search(idx, Q, k=10, ef=48)
+    _, gt_d = oracle.brute_force_knn(X, Q, 10, 0)
+    assert oracle.recall_at_k(res.ids, gt_d, X, Q) > 0.95
 
 
 def test_ring_members_brute_force(oracle):
