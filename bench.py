@@ -57,9 +57,16 @@ def parse():
     ap.add_argument("--shape", default=None,
                     help="fixed launch shape 'lanes,waves,vis_bits,persistent' instead of the "
                          "autotuner (profiling runs use the shape the default run chose)")
-    ap.add_argument("--mode", default="search", choices=["search", "batched", "serving"],
+    ap.add_argument("--mode", default="search",
+                    choices=["search", "batched", "serving", "worstcase"],
                     help="search: the metric's ef sweep and timed steps; batched: one hipGraph "
-                         "of a mixed-k / mixed-ef persistent batch (10M x 128, FP8 by default)")
+                         "of a mixed-k / mixed-ef persistent batch (10M x 128, FP8 by default); "
+                         "worstcase: eps-net against random layers on skewed data")
+    ap.add_argument("--wc-runs", type=int, default=3, help="worstcase: builds per configuration")
+    ap.add_argument("--wc-nq", type=int, default=1000, help="worstcase: queries per configuration")
+    ap.add_argument("--wc-c0d", type=float, default=0.32,
+                    help="worstcase: c0 * d of Eq. (1) for the eps-net layers")
+    ap.add_argument("--wc-lam", type=float, default=32.0, help="worstcase: skew of the n / d sweeps")
     ap.add_argument("--storage", default="fp8", help="batched mode storage form")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=10000)
@@ -131,6 +138,9 @@ def main():
         return
     if args.mode == "serving":
         serving(args)
+        return
+    if args.mode == "worstcase":
+        worstcase(args)
         return
     import torch
 
@@ -680,6 +690,118 @@ def serving(args):
                    "max_degree": args.max_degree, "root_complete_max": args.serve_root_max},
         "build_s": round(build_s, 1), "layers": sizes, "fallback_rows": fallback,
         "sweep": sweep, "serving": res,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def worstcase(args):
+    """The paper's synthetic worst-case study (Sec. 4.2 "Synthetic Dataset",
+    App. G.5 recall bounds) on the GPU path: HENN with verified eps-net layers
+    (Eq. (1) with a small c0, so that the ring check of App. B.1 rejects
+    samples) against the same construction with every ring vacuous (random
+    layers, the HNSW-style hierarchy), on skewed exponential data (``expskew``).
+    Both use NSW graphs (App. B.2) and the same build seeds.  Per build:
+    Alg. 4 greedy queries (k = 1, ef = 1) give the hops (expansions over all
+    layers), the batch time, and the rank of the returned point among the exact
+    neighbours (rho_0.9 = its 90th percentile, App. G.5); the n = 50,000, d = 32
+    configurations also sweep ef at k = 10 for Recall@10.  "Worst case" is the
+    maximum over the runs, as in the paper."""
+    import torch
+    import paper_2505_17368_amd as hn
+    import workloads as wl
+    from oracle import henn_oracle as ho
+    hn.load_library()
+    dev = torch.device("cuda:0")
+    nq, runs, lam0 = args.wc_nq, args.wc_runs, args.wc_lam
+    configs = [(n, d, lam0) for d in (16, 32) for n in (1 << 14, 1 << 16, 1 << 18, 1 << 20)]
+    configs += [(1 << 16, d, lam0) for d in (8, 64, 128)]
+    recall_configs = [(50_000, 32, lam) for lam in (4.0, 32.0, 256.0)]
+    efs = (8, 16, 32, 64, 128)
+    study = []
+    st = torch.cuda.current_stream()
+
+    def timed(idx, Qd, **kw):
+        hn.henn_search_batch(idx, Qd, **kw)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(5):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            hn.henn_search_batch(idx, Qd, **kw)
+            e1.record(st)
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
+
+    for n, d, lam in configs + recall_configs:
+        t0 = time.time()
+        X = wl.expskew(n, d, lam, seed=0)
+        Q = wl.expskew(nq, d, lam, seed=1)
+        gt_ids, gt_dist = ho.brute_force_knn(X, Q, 100, 0)
+        Xd, Qd = torch.from_numpy(X).to(dev), torch.from_numpy(Q).to(dev)
+        entry = {"n": n, "d": d, "lam": lam}
+        for variant in ("eps_net", "random"):
+            per_run = []
+            for run in range(runs):
+                bp = dict(degree=16, max_degree=32, graph=hn.GRAPH["nsw"], ef_construction=256,
+                          seed=1000 + run)
+                if variant == "eps_net":
+                    bp["c0"] = args.wc_c0d / d
+                else:
+                    bp["eps_override"] = 2.0          # every ring vacuous: random layers
+                idx = hn.henn_build(Xd, **bp)
+                info = [idx.layer_info(i) for i in range(1, idx.num_layers)]
+                ids, _, cnt = hn.henn_search_batch(idx, Qd, k=1, ef=1, with_counters=True)
+                torch.cuda.synchronize()
+                hops = cnt[:, 0].cpu().numpy()
+                got = ids[:, 0].cpu().numpy()
+                rank = np.full(nq, 101)
+                hit = gt_ids == got[:, None]
+                rank[hit.any(1)] = hit.argmax(1)[hit.any(1)] + 1
+                r = {"mean_hops": float(hops.mean()), "max_hops": int(hops.max()),
+                     "greedy_ms": timed(idx, Qd, k=1, ef=1),
+                     "rho_0.9": int(np.sort(rank)[int(np.ceil(0.9 * nq)) - 1]),
+                     "exact_nn": float((rank == 1).mean()),
+                     "layers": [x["size"] for x in info],
+                     "attempts": [x["attempts"] for x in info],
+                     "status": [x["status"] for x in info]}
+                if (n, d, lam) in recall_configs:
+                    r["sweep"] = []
+                    for ef in efs:
+                        ids10, _ = hn.henn_search_batch(idx, Qd, k=10, ef=ef)
+                        torch.cuda.synchronize()
+                        rec = ho.recall_at_k(ids10.cpu().numpy(), gt_dist[:, :10], X, Q)
+                        ms = timed(idx, Qd, k=10, ef=ef)
+                        r["sweep"].append({"ef": ef, "recall": round(rec, 4),
+                                           "qps": round(nq / (ms / 1e3), 1)})
+                per_run.append(r)
+                idx.free()
+            entry[variant] = {
+                "worst_mean_hops": max(r["mean_hops"] for r in per_run),
+                "worst_max_hops": max(r["max_hops"] for r in per_run),
+                "worst_greedy_ms": max(r["greedy_ms"] for r in per_run),
+                "mean_rho_0.9": float(np.mean([r["rho_0.9"] for r in per_run])),
+                "runs": per_run}
+        e, r = entry["eps_net"], entry["random"]
+        log(f"n={n} d={d} lam={lam:g}: worst mean hops {e['worst_mean_hops']:.1f} (eps-net) vs "
+            f"{r['worst_mean_hops']:.1f} (random); worst max hops {e['worst_max_hops']} vs "
+            f"{r['worst_max_hops']}; rho_0.9 {e['mean_rho_0.9']:.1f} vs {r['mean_rho_0.9']:.1f}; "
+            f"{time.time() - t0:.1f}s")
+        study.append(entry)
+    ratios = [x["random"]["worst_mean_hops"] / x["eps_net"]["worst_mean_hops"]
+              for x in study if (x["n"], x["d"], x["lam"]) in configs]
+    out = {
+        "metric": "worst-case Alg. 4 hops, random layers / eps-net layers (geometric mean over "
+                  "the n and d sweeps)",
+        "value": round(float(np.exp(np.mean(np.log(ratios)))), 4), "unit": "ratio",
+        "n_gpus": 1, "steps": runs, "warmup": 0, "ms_per_step": None,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "expskew", "nq": nq, "runs": runs, "lam": lam0,
+                   "c0_times_d": args.wc_c0d, "graph": "nsw", "degree": 16, "max_degree": 32,
+                   "ef_construction": 256},
+        "study": study,
     }
     print(json.dumps(out), flush=True)
 

@@ -19,6 +19,12 @@ of 2**20 rows, labels first and then noise within each chunk):
 * ``spectral``   -- anisotropic Gaussian with power-law spectrum
   lambda_i = i^-0.8 in a random orthonormal basis, unit-normalised
   (embedding-like vectors for inner-product search).
+* ``expskew``    -- exponential coordinates with a per-point scale: point i
+  draws v_i ~ U(0,1) and coordinates Exp(1) / lam^v_i.  lam = 1 is i.i.d.
+  Exp(1) data; a larger lam spreads the point scales over a factor lam, so
+  the density varies by up to lam^d between the dense core and the sparse
+  outskirts (the skewed synthetic data of Sec. 4.2 with an explicit skew
+  parameter: i.i.d. Exp(lam) coordinates would only rescale the data).
 """
 from __future__ import annotations
 
@@ -114,6 +120,17 @@ def spectral(n: int, d: int, seed: int, alpha: float = 0.8, basis_seed: int = 2)
         x = z @ M.T
         x /= np.linalg.norm(x, axis=1, keepdims=True)
         out[b:e] = x.astype(np.float32)
+    return out
+
+
+def expskew(n: int, d: int, lam: float, seed: int) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    out = np.empty((n, d), dtype=np.float32)
+    for b in range(0, n, CHUNK):
+        e = min(n, b + CHUNK)
+        v = rng.random(e - b)
+        coords = rng.standard_exponential((e - b, d))
+        out[b:e] = (coords / np.power(float(lam), v)[:, None]).astype(np.float32)
     return out
 
 
