@@ -331,6 +331,23 @@ henn_status henn_import(const float *X, int64_t n, int32_t d, const henn_build_p
                         const int32_t *const *ids_host, const int32_t *const *adj_host,
                         int32_t adj_stride, void *hip_stream, henn_index **out);
 
+/* Insert(x) of the dynamic setting (App. C) for an index built with the NSW
+ * graph: appends count points with ids n, n+1, ..., n+count-1.
+ *   X_new: device FP32 [count][d] (copied).
+ * Every new point joins layer 0; a new member g of layer i-1 also joins layer
+ * i when u(word g of stream (tag 5, layer i, attempt 0), 2^m) = 0, i.e. with
+ * probability 2^-m, which keeps each layer a random sample of the one below
+ * (no new layers are added).  Each layer graph takes its new members by NSW
+ * insertion (HENN_GRAPH_NSW rule, continuing the build's batch schedule from
+ * the layer's old size); the precision-form copies and a complete root's scan
+ * data are rebuilt.  The eps-net check is not re-run: layer_info keeps the
+ * build's verification record.
+ * Errors: HENN_E_UNSUPPORTED for other graph kinds; HENN_E_INVAL for a null
+ * index or X_new, count < 0 or n + count >= 2^31.  On HENN_E_DEVICE /
+ * HENN_E_NOMEM the index may be partly grown and should be freed.
+ * Blocking; no search may use the index meanwhile. */
+henn_status henn_insert(henn_index *idx, const float *X_new, int64_t count, void *hip_stream);
+
 /* One batch of the NSW insertion (App. B.2; the HENN_GRAPH_NSW rule) on a
  * graph the caller holds, e.g. to grow a layer graph or to check a batch.
  *   V:   device FP32 [s][d] row-major, the layer's points in insertion order

@@ -48,7 +48,7 @@ _LIB = os.path.join(_HERE, "libhenn_oracle.so")
 _lib = None
 _lock = threading.Lock()
 
-TAG_SAMPLE, TAG_RING_CENTRE, TAG_RING_START, TAG_HALVE = 1, 2, 3, 4
+TAG_SAMPLE, TAG_RING_CENTRE, TAG_RING_START, TAG_HALVE, TAG_INSERT = 1, 2, 3, 4, 5
 L2, IP = 0, 1
 
 
@@ -471,6 +471,48 @@ def nsw_graph(X, metric, members, R, M, ef, shift):
     for lo, hi in nsw_batches(s, shift):
         nsw_insert(X, metric, members, adj, margin, lo, hi, R, ef)
     return adj, margin
+
+
+def insert(idx: OracleIndex, X_new: np.ndarray, p: BuildParams) -> OracleIndex:
+    """Insert(x) of the dynamic setting (App. C) for an index with NSW graphs.
+
+    The new points get ids n, n+1, ...  Each layer is kept a random sample of
+    the one below: a new member g of layer i-1 joins layer i when
+    u(word g of stream (tag 5, layer i, attempt 0), 2^m) = 0 (probability
+    2^-m).  New ids are the largest, so they extend every member list in order,
+    and each layer graph takes its new members by NSW insertion, continuing the
+    batch schedule of :func:`nsw_batches` from the layer's old size."""
+    X_new = np.ascontiguousarray(X_new, dtype=np.float32)
+    n_old = idx.X.shape[0]
+    X = np.ascontiguousarray(np.concatenate([idx.X, X_new]), dtype=np.float32)
+    new = np.arange(n_old, n_old + len(X_new), dtype=np.int32)
+    out = OracleIndex(X=X, metric=idx.metric, degree=idx.degree,
+                      root_complete=idx.root_complete, info=list(idx.info))
+    for i in range(idx.num_layers):
+        if i > 0:
+            new = np.array([g for g in new.tolist()
+                            if uniform_index(stream_word(p.seed, TAG_INSERT, i, 0, g),
+                                             2 ** p.m) == 0], dtype=np.int32)
+        old = idx.members[i]
+        mb = np.concatenate([old, new]).astype(np.int32)
+        M = idx.adj[i].shape[1]
+        adj = np.full((len(mb), M), -1, dtype=np.int32)
+        adj[:len(old)] = idx.adj[i]
+        margin = np.full(len(mb), np.inf)
+        margin[:len(old)] = idx.order_margin[i]
+        lo = len(old)
+        while lo < len(mb):
+            hi = min(len(mb), lo + max(1, lo >> p.insert_shift))
+            nsw_insert(X, idx.metric, mb, adj, margin, lo, hi, p.degree, p.ef_construction)
+            lo = hi
+        out.members.append(mb)
+        out.adj.append(adj)
+        out.adj_dist.append(None)
+        out.adj_margin.append(margin.copy())
+        out.order_margin.append(margin)
+    if out.root_complete:
+        out.adj_margin[-1] = np.full(len(out.members[-1]), np.inf)
+    return out
 
 
 def knn_sym(X, metric, members, adj_knn, max_deg):

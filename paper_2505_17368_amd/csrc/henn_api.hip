@@ -192,6 +192,90 @@ static int32_t* nsw_graph(henn_index* ix, const float* vec, int64_t s, hipStream
   return adj;
 }
 
+// ---- insertion into a built NSW index (App. C "Dynamic Setting") --------------
+// Layer i takes the new points g of layer i - 1 whose coin u(word g of stream
+// (tag 5, layer i, attempt 0), 2^m) is 0, i.e. with probability 2^-m, as the
+// random layers are maintained under insertion.  New points have the largest
+// ids, so they are appended to every member list in order; each layer graph
+// then takes them by NSW insertion, continuing the build's batch schedule.
+static constexpr uint32_t kTagInsert = 5;
+
+static void replace(float*& p, float* q) { (void)hipFree(p); p = q; }
+static void replace(int32_t*& p, int32_t* q) { (void)hipFree(p); p = q; }
+
+// Grows layer i by the points new_ids (ascending, all above the old ids);
+// new_local: their rows in X_new; new_down: their positions one layer below.
+static void grow_layer(henn_index* ix, int i, const float* X_new,
+                       const std::vector<int32_t>& new_ids, const std::vector<int32_t>& new_local,
+                       const std::vector<int32_t>& new_down, hipStream_t st) {
+  LayerDev& L = ix->L[i];
+  const int64_t s = L.size, c = (int64_t)new_ids.size(), t = s + c;
+  const int M = L.deg, dpad = ix->dpad;
+  const henn_build_params& p = ix->params;
+  int32_t* local_d = dalloc<int32_t>(c);
+  float* vec = nullptr;
+  int32_t *adj = nullptr, *ids = nullptr, *down = nullptr;
+  try {
+    HENN_HIP(hipMemcpyAsync(local_d, new_local.data(), sizeof(int32_t) * c,
+                            hipMemcpyHostToDevice, st));
+    vec = dalloc<float>(t * dpad);
+    HENN_HIP(hipMemcpyAsync(vec, L.vec32, sizeof(float) * s * dpad, hipMemcpyDeviceToDevice, st));
+    launch_copy_rows(X_new, ix->d, local_d, c, ix->d, vec + s * dpad, dpad, st);
+    adj = dalloc<int32_t>(t * M);
+    HENN_HIP(hipMemcpyAsync(adj, L.adj, sizeof(int32_t) * s * M, hipMemcpyDeviceToDevice, st));
+    HENN_HIP(hipMemsetAsync(adj + s * M, 0xFF, sizeof(int32_t) * c * M, st));
+    if (i > 0) {
+      ids = dalloc<int32_t>(t);
+      down = dalloc<int32_t>(t);
+      HENN_HIP(hipMemcpyAsync(ids, L.ids, sizeof(int32_t) * s, hipMemcpyDeviceToDevice, st));
+      HENN_HIP(hipMemcpyAsync(ids + s, new_ids.data(), sizeof(int32_t) * c,
+                              hipMemcpyHostToDevice, st));
+      HENN_HIP(hipMemcpyAsync(down, L.down, sizeof(int32_t) * s, hipMemcpyDeviceToDevice, st));
+      HENN_HIP(hipMemcpyAsync(down + s, new_down.data(), sizeof(int32_t) * c,
+                              hipMemcpyHostToDevice, st));
+    }
+    const NswWork w(t, std::max<int64_t>(1, t >> p.insert_shift), p.degree);
+    for (int64_t lo = s; lo < t;) {
+      const int64_t hi = nsw_batch_end(lo, t, p.insert_shift);
+      nsw_insert_batch(ix->device, vec, dpad, ix->nchunks, ix->metric, adj, M, lo, hi, p.degree,
+                       p.ef_construction, w, st);
+      lo = hi;
+    }
+    HENN_HIP(hipStreamSynchronize(st));
+  } catch (...) {
+    (void)hipFree(local_d);
+    (void)hipFree(vec);
+    (void)hipFree(adj);
+    (void)hipFree(ids);
+    (void)hipFree(down);
+    throw;
+  }
+  (void)hipFree(local_d);
+  replace(L.vec32, vec);
+  replace(L.adj, adj);
+  if (i > 0) {
+    replace(L.ids, ids);
+    replace(L.down, down);
+  }
+  L.size = t;
+  L.info.size = t;
+  if (ix->storage != HENN_F32) {  // the traversal copy of the whole layer again
+    (void)hipFree(L.vecq);
+    (void)hipFree(L.scale);
+    (void)hipFree(L.adj_scale);
+    L.vecq = nullptr;
+    L.scale = L.adj_scale = nullptr;
+    L.vecq = dalloc<uint8_t>(t * dpad * storage_bytes(ix->storage));
+    if (ix->storage == HENN_FP8_E4M3) L.scale = dalloc<float>(t);
+    launch_quantize(ix->storage, L.vec32, t, dpad, L.vecq, L.scale, st);
+    if (ix->storage == HENN_FP8_E4M3) {
+      L.adj_scale = dalloc<float>(t * M);
+      launch_adj_scale(L.adj, t * M, L.scale, L.adj_scale, st);
+    }
+    HENN_HIP(hipStreamSynchronize(st));
+  }
+}
+
 // Finishes a layer: graph (+ optional symmetrisation) and traversal copy.
 static void finish_layer(henn_index* ix, int i, hipStream_t st) {
   LayerDev& L = ix->L[i];
@@ -648,6 +732,57 @@ henn_status henn_import(const float* X, int64_t n, int32_t d, const henn_build_p
     destroy(ix);
     return fail(HENN_E_NOMEM, "host allocation failed");
   }
+}
+
+henn_status henn_insert(henn_index* idx, const float* X_new, int64_t count, void* hip_stream) {
+  if (!idx) return fail(HENN_E_INVAL, "index is null");
+  if (count < 0) return fail(HENN_E_INVAL, "count must be >= 0");
+  if (count == 0) return HENN_OK;
+  if (!X_new) return fail(HENN_E_INVAL, "X_new is null");
+  if (idx->n + count > 2147483647ll) return fail(HENN_E_INVAL, "n + count above 2^31 - 1");
+  if (idx->params.graph != HENN_GRAPH_NSW)
+    return fail(HENN_E_UNSUPPORTED, "insertion needs an index built with the NSW graph");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const henn_build_params& p = idx->params;
+  const int64_t n_old = idx->n;
+  try {
+    // membership: layer 0 takes every new point, layer i each member of
+    // layer i - 1's new points whose coin comes up (probability 2^-m)
+    std::vector<int32_t> ids((size_t)count), local((size_t)count), down;
+    for (int64_t j = 0; j < count; ++j) {
+      ids[(size_t)j] = (int32_t)(n_old + j);
+      local[(size_t)j] = (int32_t)j;
+    }
+    grow_layer(idx, 0, X_new, ids, local, down, st);
+    for (int i = 1; i < idx->num_layers && !ids.empty(); ++i) {
+      const int64_t below_old = idx->L[i - 1].size - (int64_t)ids.size();
+      std::vector<int32_t> up, up_local, up_down;
+      for (size_t j = 0; j < ids.size(); ++j) {
+        const uint64_t w = stream_word(p.seed, kTagInsert, (uint32_t)i, 0u, (uint64_t)ids[j]);
+        if (uniform_index(w, 1ull << p.m) != 0) continue;
+        up.push_back(ids[j]);
+        up_local.push_back((int32_t)(ids[j] - n_old));
+        up_down.push_back((int32_t)(below_old + (int64_t)j));
+      }
+      if (!up.empty()) grow_layer(idx, i, X_new, up, up_local, up_down, st);
+      ids.swap(up);
+    }
+    idx->n = n_old + count;
+    if (idx->root_complete) {  // the root's scan data again
+      RootAux& r = idx->root;
+      if (r.dec_owned) (void)hipFree(r.dec);
+      (void)hipFree(r.mean);
+      (void)hipFree(r.norm);
+      r = RootAux{};
+      prepare_root(idx, st);
+      HENN_HIP(hipStreamSynchronize(st));
+    }
+  } catch (const HipError& e) {
+    return from_hip(e);
+  } catch (const std::bad_alloc&) {
+    return fail(HENN_E_NOMEM, "host allocation failed");
+  }
+  return HENN_OK;
 }
 
 henn_status henn_nsw_insert(const float* V, int64_t s, int32_t d, int32_t metric, int32_t* adj,

@@ -615,3 +615,68 @@ def test_nsw_build_matches_oracle(hn, ho, metric):
     ro = ho.recall_at_k(ores.ids, gt_d, X, Q, metric)
     assert rg > 0.8 and abs(rg - ro) < 0.02, (rg, ro)      # 24-d uniform data, ef 48
     idx.free()
+
+
+# --------------------------------------------------- Insert(x) (App. C) ----
+
+@pytest.mark.parametrize("metric,root_max", [(0, 0), (1, 0), (0, 400)])
+def test_insert_matches_oracle(hn, ho, metric, root_max):
+    """Insert(x) into an NSW index on the GPU against the oracle's insertion:
+    same members per layer, nearly all rows identical, same search quality."""
+    sh = 0.5 if metric else 0.0
+    X = np.ascontiguousarray(wl.uniform(6000, 24, 51) - sh, dtype=np.float32)
+    Xn = np.ascontiguousarray(wl.uniform(3000, 24, 52) - sh, dtype=np.float32)
+    Q = np.ascontiguousarray(wl.uniform(300, 24, 53) - sh, dtype=np.float32)
+    p = dict(degree=8, max_degree=16, graph=4, ef_construction=48, seed=6, metric=metric,
+             root_complete_max=root_max)
+    bp = ho.BuildParams(**p)
+    grown = ho.insert(ho.build_index(X, bp), Xn, bp)
+    idx = hn.henn_build(to_dev(X), **p)
+    hn.henn_insert(idx, to_dev(Xn))
+    assert idx.shape()[1] == 9000
+    layers = _gpu_layers(idx)
+    assert len(layers) == grown.num_layers
+    for i, (ids, adj) in enumerate(layers):
+        assert np.array_equal(ids, grown.members[i]), f"layer {i}"
+        same = (adj == grown.adj[i]).all(1).mean()
+        print(f"layer {i}: {same:.4f} of {len(ids)} rows identical")
+        assert same >= 0.98, (i, same)
+    Xa = np.concatenate([X, Xn])
+    gi, gd = hn.henn_search_batch(idx, to_dev(Q), k=10, ef=48)
+    ores = ho.search(grown, Q, k=10, ef=48)
+    _, gt_d = ho.brute_force_knn(Xa, Q, 10, metric)
+    rg = ho.recall_at_k(gi.cpu().numpy(), gt_d, Xa, Q, metric)
+    ro = ho.recall_at_k(ores.ids, gt_d, Xa, Q, metric)
+    assert rg > 0.8 and abs(rg - ro) < 0.02, (rg, ro)
+    idx.free()
+
+
+@pytest.mark.parametrize("storage", [1, 2])
+def test_insert_precision_forms(hn, storage):
+    """Insert(x) rebuilds the BF16 / FP8 copies: the grown index searches like
+    its FP32 twin (same graphs) up to the precision forms' usual recall gap."""
+    X = wl.uniform(5000, 32, 61)
+    Xn = wl.uniform(5000, 32, 62)
+    Q = to_dev(wl.uniform(200, 32, 63))
+    p = dict(degree=8, max_degree=16, graph=4, ef_construction=48, seed=3)
+    a = hn.henn_build(to_dev(X), storage=0, **p)
+    b = hn.henn_build(to_dev(X), storage=storage, **p)
+    for ix in (a, b):
+        hn.henn_insert(ix, to_dev(Xn))
+    for i in range(a.num_layers):
+        assert np.array_equal(a.export_layer(i)[1], b.export_layer(i)[1])
+    ia, _ = hn.henn_search_batch(a, Q, k=10, ef=64)
+    ib, db = hn.henn_search_batch(b, Q, k=10, ef=64)
+    ia, ib = ia.cpu().numpy(), ib.cpu().numpy()
+    overlap = np.mean([len(set(x) & set(y)) / 10 for x, y in zip(ia, ib)])
+    assert overlap > 0.9 and (ib >= 5000).any()
+    assert np.all(np.diff(db.cpu().numpy(), axis=1) >= 0)
+    a.free()
+    b.free()
+
+
+def test_insert_rejects_other_graphs(hn):
+    idx = hn.henn_build(to_dev(wl.uniform(2000, 8, 1)), degree=8)
+    with pytest.raises(hn.HennError):
+        hn.henn_insert(idx, to_dev(wl.uniform(10, 8, 2)))
+    idx.free()

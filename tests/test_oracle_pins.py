@@ -12,6 +12,9 @@ an independent library routine or a brute-force recomputation:
   and independent coins, and a backward walk with NumPy-Philox coins.
 * NSW graphs (App. B.2): with a beam as wide as the layer the insertion
   equals exact k-NN over the inserted prefix (brute force); row invariants.
+* Insert(x) (App. C): growing a one-layer index from a batch boundary equals
+  building it whole; upper-layer membership against NumPy-Philox coins,
+  nesting and the 2^-m rate.
 * Ring ranges (Def. Ring Ranges) and the hit test against a NumPy lexsort.
 * The exact kNN graph (App. B.2) against NumPy all-pairs + lexsort.
 * Search: complete graph => exact k-NN (App. B.2: the complete graph is
@@ -360,6 +363,54 @@ def test_nsw_index_search_quality(oracle):
     res = oracle.search(idx, Q, k=10, ef=48)
     _, gt_d = oracle.brute_force_knn(X, Q, 10, 0)
     assert oracle.recall_at_k(res.ids, gt_d, X, Q) > 0.95
+
+
+# ------------------------------------------ Insert(x), App. C (NSW index) --
+
+def test_insert_into_layer0_continues_the_build(oracle):
+    """A single-layer NSW index built on a prefix that ends at a batch boundary
+    and then given the rest by Insert(x) is the index built on all points."""
+    X = wl.uniform(3000, 8, 12)
+    starts = [lo for lo, _ in oracle.nsw_batches(3000, 3)]
+    n0 = [lo for lo in starts if lo >= 1800][0]
+    p = oracle.BuildParams(degree=8, max_degree=16, graph=4, ef_construction=32, max_layers=0)
+    full = oracle.build_index(X, p)
+    grown = oracle.insert(oracle.build_index(X[:n0], p), X[n0:], p)
+    assert grown.num_layers == 1 and np.array_equal(grown.members[0], full.members[0])
+    assert np.array_equal(grown.adj[0], full.adj[0])
+
+
+def test_insert_membership_coins_and_nesting(oracle):
+    X = wl.uniform(6000, 8, 13)
+    Xn = wl.uniform(4000, 8, 14)
+    p = oracle.BuildParams(degree=8, max_degree=16, graph=4, ef_construction=32, seed=9)
+    idx = oracle.build_index(X, p)
+    grown = oracle.insert(idx, Xn, p)
+    new = np.arange(6000, 10000)
+    for i in range(1, idx.num_layers):
+        coins = numpy_uindex(numpy_stream(9, 5, i, 0, 10000), 16)
+        new = new[coins[new] == 0]
+        assert np.array_equal(grown.members[i], np.concatenate([idx.members[i], new]))
+        assert np.isin(grown.members[i], grown.members[i - 1]).all()      # nesting
+    k1 = len(grown.members[1]) - len(idx.members[1])
+    assert abs(k1 - 4000 / 16) < 4 * math.sqrt(4000 / 16)       # probability 2^-m
+    for i in range(grown.num_layers):
+        a = grown.adj[i]
+        assert a.shape == (len(grown.members[i]), 16)
+        assert a.max() < len(grown.members[i]) and np.all((a >= 0).sum(1)[1:] >= 1)
+
+
+def test_insert_keeps_search_quality(oracle):
+    X = wl.uniform(5000, 8, 15)
+    Xn = wl.uniform(3000, 8, 16)
+    Q = wl.uniform(200, 8, 17)
+    p = oracle.BuildParams(degree=8, max_degree=16, graph=4, ef_construction=32, seed=4)
+    grown = oracle.insert(oracle.build_index(X, p), Xn, p)
+    Xa = np.concatenate([X, Xn])
+    res = oracle.search(grown, Q, k=10, ef=48)
+    _, gt_d = oracle.brute_force_knn(Xa, Q, 10, 0)
+    assert oracle.recall_at_k(res.ids, gt_d, Xa, Q) > 0.95
+    assert (res.ids >= 5000).any()            # inserted points are found
 
 
 def test_ring_members_brute_force(oracle):
