@@ -332,7 +332,8 @@ henn_status henn_import(const float *X, int64_t n, int32_t d, const henn_build_p
                         int32_t adj_stride, void *hip_stream, henn_index **out);
 
 /* Insert(x) of the dynamic setting (App. C) for an index built with the NSW
- * graph: appends count points with ids n, n+1, ..., n+count-1.
+ * graph: appends count points with ids N, N+1, ..., N+count-1, where N is one
+ * past the largest id the index ever held (n for a fresh index).
  *   X_new: device FP32 [count][d] (copied).
  * Every new point joins layer 0; a new member g of layer i-1 also joins layer
  * i when u(word g of stream (tag 5, layer i, attempt 0), 2^m) = 0, i.e. with
@@ -343,10 +344,34 @@ henn_status henn_import(const float *X, int64_t n, int32_t d, const henn_build_p
  * data are rebuilt.  The eps-net check is not re-run: layer_info keeps the
  * build's verification record.
  * Errors: HENN_E_UNSUPPORTED for other graph kinds; HENN_E_INVAL for a null
- * index or X_new, count < 0 or n + count >= 2^31.  On HENN_E_DEVICE /
+ * index or X_new, count < 0 or N + count >= 2^31.  On HENN_E_DEVICE /
  * HENN_E_NOMEM the index may be partly grown and should be freed.
- * Blocking; no search may use the index meanwhile. */
+ * Blocking; no search may use the index meanwhile, and captured search graphs
+ * of the index must be created again afterwards (servers need not be). */
 henn_status henn_insert(henn_index *idx, const float *X_new, int64_t count, void *hip_stream);
+
+/* Delete(x) of the dynamic setting (App. C) for an index built with the NSW
+ * graph.
+ *   ids_host: host int32 [count] point ids to delete (repeats are ignored);
+ *   each must be in the index, and at least one point must remain.
+ * Every deleted point leaves every layer.  In each layer, every remaining
+ * row that linked to a deleted member is replaced by the first max_degree of
+ * the remaining points among its row and the rows of its deleted neighbours
+ * (itself and repeats left out), in (distance, id) order; then the layer is
+ * compacted (positions stay in id order).  A layer i >= 1 left with fewer
+ * than half of ceil(|L_{i-1}| / 2^m) members is drawn again from L_{i-1}
+ * with the build's sampler, ring check and streams, together with every
+ * layer above it, and those layers get new NSW graphs.  Ids of the remaining
+ * points do not change, and ids are never reused by henn_insert (which
+ * continues after the largest id ever given).
+ * Errors: HENN_E_UNSUPPORTED for other graph kinds; HENN_E_INVAL for a null
+ * index or ids_host, count < 0, an id not in the index, or deleting every
+ * point (nothing is changed then).  On HENN_E_DEVICE / HENN_E_NOMEM the index
+ * may be partly changed and should be freed.
+ * Blocking; no search may use the index meanwhile, and captured search graphs
+ * of the index must be created again afterwards (servers need not be). */
+henn_status henn_delete(henn_index *idx, const int32_t *ids_host, int64_t count,
+                        void *hip_stream);
 
 /* One batch of the NSW insertion (App. B.2; the HENN_GRAPH_NSW rule) on a
  * graph the caller holds, e.g. to grow a layer graph or to check a batch.

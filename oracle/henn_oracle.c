@@ -657,6 +657,63 @@ int ho_nsw_insert(const float *X, int d, int metric, const int32_t *members, int
 }
 
 /* ------------------------------------------------------------------ */
+/* Delete(x) (App. C): repair of one layer graph before its deleted      */
+/* members are dropped.  Every live row v that links to a deleted member */
+/* becomes the first M of the live points among its own row and the rows */
+/* of its deleted neighbours (v itself and repeats left out), in         */
+/* (distance, id) order.  Deleted rows are left as they are.  margin[] is */
+/* min-folded with the repaired rows' adjacent-key and cut margins.      */
+/* ------------------------------------------------------------------ */
+int ho_nsw_repair(const float *X, int d, int metric, const int32_t *members, int64_t s,
+                  int32_t *adj, int M, const uint8_t *del, double *margin) {
+  int32_t *cand = (int32_t *)malloc(sizeof(int32_t) * (size_t)(M + M * M + 1));
+  dkey *keys = (dkey *)malloc(sizeof(dkey) * (size_t)(M + M * M + 1));
+  int32_t *row = (int32_t *)malloc(sizeof(int32_t) * (size_t)M);
+  if (!cand || !keys || !row) { free(cand); free(keys); free(row); return -2; }
+  for (int64_t v = 0; v < s; ++v) {
+    if (del[v]) continue;
+    int touched = 0;
+    for (int j = 0; j < M; ++j) {
+      row[j] = adj[(size_t)v * M + j];
+      if (row[j] >= 0 && del[row[j]]) touched = 1;
+    }
+    if (!touched) continue;
+    int64_t nc = 0;
+    for (int j = 0; j < M; ++j) {
+      int32_t u = row[j];
+      if (u < 0) continue;
+      if (!del[u]) { cand[nc++] = u; continue; }
+      for (int r = 0; r < M; ++r) {
+        int32_t w = adj[(size_t)u * M + r];
+        if (w >= 0 && !del[w] && w != v) cand[nc++] = w;
+      }
+    }
+    trace t;
+    t.X = X; t.d = d; t.metric = metric;
+    t.q = X + (size_t)members[v] * (size_t)d;
+    t.qnorm = norm64(t.q, d);
+    t.min_margin = INFINITY;
+    int64_t nk = 0;
+    for (int64_t i = 0; i < nc; ++i) {
+      int dup = 0;
+      for (int64_t j = 0; j < nk && !dup; ++j) dup = keys[j].id == members[cand[i]];
+      if (dup) continue;
+      keys[nk].d = dist64(t.q, X + (size_t)members[cand[i]] * (size_t)d, d, metric);
+      keys[nk].id = members[cand[i]];
+      ++nk;
+    }
+    qsort(keys, (size_t)nk, sizeof(dkey), key_cmp);
+    int64_t lim = nk < (int64_t)M + 1 ? nk : (int64_t)M + 1;
+    for (int64_t r = 1; r < lim; ++r) note(&t, keys[r - 1], keys[r]);
+    for (int j = 0; j < M; ++j)
+      adj[(size_t)v * M + j] = j < nk ? (int32_t)local_of(members, s, keys[j].id) : -1;
+    if (t.min_margin < margin[v]) margin[v] = t.min_margin;
+  }
+  free(cand); free(keys); free(row);
+  return 0;
+}
+
+/* ------------------------------------------------------------------ */
 /* Brute-force exact k-NN (Sec. 2 problem setting): quality reference.  */
 /* ------------------------------------------------------------------ */
 int ho_brute_knn(const float *X, int64_t n, int d, int metric, const float *Q, int64_t q_begin,

@@ -32,6 +32,7 @@ before a layer whose draw count would fall below degree+1.
 """
 from __future__ import annotations
 
+import copy
 import ctypes
 import math
 import os
@@ -96,6 +97,9 @@ def _load():
                                   ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
                                   ctypes.c_int, ctypes.c_int, c_i32p, c_f64p, c_f64p, c_f64p,
                                   c_i64p]
+        lib.ho_nsw_repair.restype = ctypes.c_int
+        lib.ho_nsw_repair.argtypes = [c_f32p, ctypes.c_int, ctypes.c_int, c_i32p, ctypes.c_int64,
+                                      c_i32p, ctypes.c_int, P(ctypes.c_uint8), c_f64p]
         lib.ho_nsw_insert.restype = ctypes.c_int
         lib.ho_nsw_insert.argtypes = [c_f32p, ctypes.c_int, ctypes.c_int, c_i32p, ctypes.c_int64,
                                       c_i32p, ctypes.c_int, ctypes.c_int64, ctypes.c_int64,
@@ -359,10 +363,17 @@ def knn_rows(X, metric, members, rows, R):
 def build_layers(X: np.ndarray, p: BuildParams, threads=None):
     """Alg. 1 layer loop: returns ascending member lists and per-layer info."""
     X = np.ascontiguousarray(X, dtype=np.float32)
-    n, d = X.shape
+    n = X.shape[0]
     members = [np.arange(n, dtype=np.int32)]
     infos = [LayerInfo(n, n, 0.0, 0, 0, 0, "base")]
-    i = 1
+    _extend_layers(X, members, infos, p, threads)
+    return members, infos
+
+
+def _extend_layers(X, members, infos, p: BuildParams, threads=None):
+    """Alg. 1's layer loop on top of the given layers, in place."""
+    d = X.shape[1]
+    i = len(members)
     while True:
         s = len(members[-1])
         D = -(-s // (2 ** p.m))
@@ -375,7 +386,6 @@ def build_layers(X: np.ndarray, p: BuildParams, threads=None):
         info.size = len(local)
         infos.append(info)
         i += 1
-    return members, infos
 
 
 def build_index(X: np.ndarray, p: BuildParams | None = None, threads=None) -> OracleIndex:
@@ -512,6 +522,65 @@ def insert(idx: OracleIndex, X_new: np.ndarray, p: BuildParams) -> OracleIndex:
         out.order_margin.append(margin)
     if out.root_complete:
         out.adj_margin[-1] = np.full(len(out.members[-1]), np.inf)
+    return out
+
+
+def delete(idx: OracleIndex, ids, p: BuildParams) -> OracleIndex:
+    """Delete(x) of the dynamic setting (App. C) for an index with NSW graphs.
+
+    Every deleted point leaves every layer.  In each layer, the live rows that
+    linked to deleted members are repaired (``ho_nsw_repair``), then the
+    deleted members are dropped and positions renumbered in id order.  When a
+    layer i >= 1 falls below half of ceil(|L_{i-1}| / 2^m), layers i and up are
+    drawn again from L_{i-1} (Alg. 1's loop, same streams) and given new NSW
+    graphs.  The rows of deleted points stay in X, unreachable."""
+    lib = _load()
+    X = idx.X
+    D = np.unique(np.asarray(ids, dtype=np.int64))
+    members, adjs, margins = [], [], []
+    for i in range(idx.num_layers):
+        mb = idx.members[i]
+        pos = np.searchsorted(mb, D)
+        pos = pos[(pos < len(mb)) & (mb[np.minimum(pos, len(mb) - 1)] == D)]
+        adj = np.ascontiguousarray(idx.adj[i], dtype=np.int32).copy()
+        margin = np.ascontiguousarray(idx.order_margin[i], dtype=np.float64).copy()
+        if len(pos):
+            dflag = np.zeros(len(mb), dtype=np.uint8)
+            dflag[pos] = 1
+            rc = lib.ho_nsw_repair(_ptr(X, ctypes.c_float), X.shape[1], idx.metric,
+                                   _ptr(mb, ctypes.c_int32), len(mb), _ptr(adj, ctypes.c_int32),
+                                   adj.shape[1], _ptr(dflag, ctypes.c_uint8),
+                                   _ptr(margin, ctypes.c_double))
+            if rc != 0:
+                raise RuntimeError("nsw_repair failed")
+            keep = dflag == 0
+            newpos = np.cumsum(keep) - 1
+            newpos[~keep] = -1
+            adj = adj[keep]
+            adj = np.where(adj >= 0, newpos[np.maximum(adj, 0)], -1).astype(np.int32)
+            mb, margin = mb[keep], margin[keep]
+        members.append(mb.astype(np.int32))
+        adjs.append(adj)
+        margins.append(margin)
+    infos = [copy.copy(x) for x in idx.info]
+    for i in range(1, len(members)):
+        if 2 * len(members[i]) < -(-len(members[i - 1]) // 2 ** p.m):
+            del members[i:], adjs[i:], margins[i:], infos[i:]
+            _extend_layers(X, members, infos, p)
+            for mb in members[i:]:
+                a, mg = nsw_graph(X, idx.metric, mb, p.degree, p.max_degree, p.ef_construction,
+                                  p.insert_shift)
+                adjs.append(a)
+                margins.append(mg)
+            break
+    for i, mb in enumerate(members):
+        infos[i].size = len(mb)
+    root_complete = p.root_complete_max > 0 and len(members) >= 2
+    out = OracleIndex(X=X, metric=idx.metric, degree=idx.degree, root_complete=root_complete,
+                      members=members, adj=adjs, adj_dist=[None] * len(members),
+                      adj_margin=[m.copy() for m in margins], order_margin=margins, info=infos)
+    if root_complete:
+        out.adj_margin[-1] = np.full(len(members[-1]), np.inf)
     return out
 
 

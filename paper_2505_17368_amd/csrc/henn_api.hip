@@ -192,6 +192,47 @@ static int32_t* nsw_graph(henn_index* ix, const float* vec, int64_t s, hipStream
   return adj;
 }
 
+static int sample_layer(henn_index* ix, int i, hipStream_t st, int32_t* local_out,
+                        int64_t* count_out);
+
+// Alg. 1's layer loop from layer `first` on (layers below it exist): samples
+// each layer from the one below until the stopping rule; graphs are built by
+// the caller.  Returns true when some layer kept an unverified attempt.
+static bool sample_layers_from(henn_index* ix, int first, hipStream_t st) {
+  const henn_build_params& p = ix->params;
+  bool unverified = false;
+  ix->num_layers = first;
+  for (int i = first; i < HENN_MAX_LAYERS; ++i) {
+    const int64_t s = ix->L[i - 1].size;
+    const int64_t D = (s + (1ll << p.m) - 1) >> p.m;
+    if (D < (int64_t)p.degree + 1) break;
+    if (p.max_layers >= 0 && i > p.max_layers) break;
+    if (p.root_complete_max > 0 && s <= p.root_complete_max) break;
+    int32_t* local = dalloc<int32_t>(s);
+    try {
+      int64_t cnt = 0;
+      sample_layer(ix, i, st, local, &cnt);
+      LayerDev& L = ix->L[i];
+      L.size = cnt;
+      L.info.size = cnt;
+      L.ids = dalloc<int32_t>(cnt);
+      L.down = dalloc<int32_t>(cnt);
+      launch_map_ids(ix->L[i - 1].ids, local, cnt, L.ids, L.down, st);
+      L.vec32 = dalloc<float>(cnt * ix->dpad);
+      launch_copy_rows(ix->L[i - 1].vec32, ix->dpad, local, cnt, ix->dpad, L.vec32, ix->dpad,
+                       st);
+      HENN_HIP(hipStreamSynchronize(st));
+    } catch (...) {
+      (void)hipFree(local);
+      throw;
+    }
+    (void)hipFree(local);
+    ix->num_layers = i + 1;
+    if (ix->L[i].info.status == 3) unverified = true;
+  }
+  return unverified;
+}
+
 // ---- insertion into a built NSW index (App. C "Dynamic Setting") --------------
 // Layer i takes the new points g of layer i - 1 whose coin u(word g of stream
 // (tag 5, layer i, attempt 0), 2^m) is 0, i.e. with probability 2^-m, as the
@@ -202,6 +243,37 @@ static constexpr uint32_t kTagInsert = 5;
 
 static void replace(float*& p, float* q) { (void)hipFree(p); p = q; }
 static void replace(int32_t*& p, int32_t* q) { (void)hipFree(p); p = q; }
+
+// The precision-form copy of a whole layer again (after its rows changed).
+static void refresh_forms(henn_index* ix, LayerDev& L, hipStream_t st) {
+  if (ix->storage == HENN_F32) return;
+  (void)hipFree(L.vecq);
+  (void)hipFree(L.scale);
+  (void)hipFree(L.adj_scale);
+  L.vecq = nullptr;
+  L.scale = L.adj_scale = nullptr;
+  L.vecq = dalloc<uint8_t>(L.size * ix->dpad * storage_bytes(ix->storage));
+  if (ix->storage == HENN_FP8_E4M3) L.scale = dalloc<float>(L.size);
+  launch_quantize(ix->storage, L.vec32, L.size, ix->dpad, L.vecq, L.scale, st);
+  if (ix->storage == HENN_FP8_E4M3) {
+    L.adj_scale = dalloc<float>(L.size * L.deg);
+    launch_adj_scale(L.adj, L.size * L.deg, L.scale, L.adj_scale, st);
+  }
+  HENN_HIP(hipStreamSynchronize(st));
+}
+
+static void prepare_root(henn_index* ix, hipStream_t st);
+
+// The complete root's scan data again (after the root layer changed).
+static void refresh_root(henn_index* ix, hipStream_t st) {
+  RootAux& r = ix->root;
+  if (r.dec_owned) (void)hipFree(r.dec);
+  (void)hipFree(r.mean);
+  (void)hipFree(r.norm);
+  r = RootAux{};
+  prepare_root(ix, st);
+  HENN_HIP(hipStreamSynchronize(st));
+}
 
 // Grows layer i by the points new_ids (ascending, all above the old ids);
 // new_local: their rows in X_new; new_down: their positions one layer below.
@@ -224,12 +296,14 @@ static void grow_layer(henn_index* ix, int i, const float* X_new,
     adj = dalloc<int32_t>(t * M);
     HENN_HIP(hipMemcpyAsync(adj, L.adj, sizeof(int32_t) * s * M, hipMemcpyDeviceToDevice, st));
     HENN_HIP(hipMemsetAsync(adj + s * M, 0xFF, sizeof(int32_t) * c * M, st));
-    if (i > 0) {
+    if (L.ids) {  // upper layers, and layer 0 once deletions gave it an id list
       ids = dalloc<int32_t>(t);
-      down = dalloc<int32_t>(t);
       HENN_HIP(hipMemcpyAsync(ids, L.ids, sizeof(int32_t) * s, hipMemcpyDeviceToDevice, st));
       HENN_HIP(hipMemcpyAsync(ids + s, new_ids.data(), sizeof(int32_t) * c,
                               hipMemcpyHostToDevice, st));
+    }
+    if (i > 0) {
+      down = dalloc<int32_t>(t);
       HENN_HIP(hipMemcpyAsync(down, L.down, sizeof(int32_t) * s, hipMemcpyDeviceToDevice, st));
       HENN_HIP(hipMemcpyAsync(down + s, new_down.data(), sizeof(int32_t) * c,
                               hipMemcpyHostToDevice, st));
@@ -253,27 +327,11 @@ static void grow_layer(henn_index* ix, int i, const float* X_new,
   (void)hipFree(local_d);
   replace(L.vec32, vec);
   replace(L.adj, adj);
-  if (i > 0) {
-    replace(L.ids, ids);
-    replace(L.down, down);
-  }
+  if (ids) replace(L.ids, ids);
+  if (down) replace(L.down, down);
   L.size = t;
   L.info.size = t;
-  if (ix->storage != HENN_F32) {  // the traversal copy of the whole layer again
-    (void)hipFree(L.vecq);
-    (void)hipFree(L.scale);
-    (void)hipFree(L.adj_scale);
-    L.vecq = nullptr;
-    L.scale = L.adj_scale = nullptr;
-    L.vecq = dalloc<uint8_t>(t * dpad * storage_bytes(ix->storage));
-    if (ix->storage == HENN_FP8_E4M3) L.scale = dalloc<float>(t);
-    launch_quantize(ix->storage, L.vec32, t, dpad, L.vecq, L.scale, st);
-    if (ix->storage == HENN_FP8_E4M3) {
-      L.adj_scale = dalloc<float>(t * M);
-      launch_adj_scale(L.adj, t * M, L.scale, L.adj_scale, st);
-    }
-    HENN_HIP(hipStreamSynchronize(st));
-  }
+  refresh_forms(ix, L, st);
 }
 
 // Finishes a layer: graph (+ optional symmetrisation) and traversal copy.
@@ -503,6 +561,7 @@ static henn_index* new_index(const float* X, int64_t n, int32_t d, const henn_bu
                              hipStream_t st) {
   henn_index* ix = new henn_index();
   ix->n = n;
+  ix->next_id = n;
   ix->d = d;
   ix->dpad = (d + 7) / 8 * 8;
   ix->nchunks = ix->dpad / 8;
@@ -586,33 +645,9 @@ henn_status henn_build(const float* X, int64_t n, int32_t d, const henn_build_pa
   if (!valid_build_params(p, &why)) return fail(HENN_E_INVAL, why);
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   henn_index* ix = nullptr;
-  int32_t* local = nullptr;
   try {
     ix = new_index(X, n, d, p, st);
-    bool unverified = false;
-    for (int i = 1; i < HENN_MAX_LAYERS; ++i) {
-      const int64_t s = ix->L[i - 1].size;
-      const int64_t D = (s + (1ll << p->m) - 1) >> p->m;
-      if (D < (int64_t)p->degree + 1) break;
-      if (p->max_layers >= 0 && i > p->max_layers) break;
-      if (p->root_complete_max > 0 && s <= p->root_complete_max) break;
-      local = dalloc<int32_t>(s);
-      int64_t cnt = 0;
-      sample_layer(ix, i, st, local, &cnt);
-      LayerDev& L = ix->L[i];
-      L.size = cnt;
-      L.info.size = cnt;
-      L.ids = dalloc<int32_t>(cnt);
-      L.down = dalloc<int32_t>(cnt);
-      launch_map_ids(ix->L[i - 1].ids, local, cnt, L.ids, L.down, st);
-      L.vec32 = dalloc<float>(cnt * ix->dpad);
-      launch_copy_rows(ix->L[i - 1].vec32, ix->dpad, local, cnt, ix->dpad, L.vec32, ix->dpad, st);
-      HENN_HIP(hipStreamSynchronize(st));
-      (void)hipFree(local);
-      local = nullptr;
-      ix->num_layers = i + 1;
-      if (L.info.status == 3) unverified = true;
-    }
+    const bool unverified = sample_layers_from(ix, 1, st);
     ix->root_complete = p->root_complete_max > 0 && ix->num_layers >= 2;
     for (int i = 0; i < ix->num_layers; ++i) finish_layer(ix, i, st);
     prepare_root(ix, st);
@@ -620,11 +655,9 @@ henn_status henn_build(const float* X, int64_t n, int32_t d, const henn_build_pa
     return unverified ? fail(HENN_W_NOT_VERIFIED, "a layer kept its best unverified attempt")
                       : HENN_OK;
   } catch (const HipError& e) {
-    (void)hipFree(local);
     destroy(ix);
     return from_hip(e);
   } catch (const std::bad_alloc&) {
-    (void)hipFree(local);
     destroy(ix);
     return fail(HENN_E_NOMEM, "host allocation failed");
   }
@@ -739,18 +772,19 @@ henn_status henn_insert(henn_index* idx, const float* X_new, int64_t count, void
   if (count < 0) return fail(HENN_E_INVAL, "count must be >= 0");
   if (count == 0) return HENN_OK;
   if (!X_new) return fail(HENN_E_INVAL, "X_new is null");
-  if (idx->n + count > 2147483647ll) return fail(HENN_E_INVAL, "n + count above 2^31 - 1");
+  if (idx->next_id + count > 2147483647ll)
+    return fail(HENN_E_INVAL, "ids would pass 2^31 - 1");
   if (idx->params.graph != HENN_GRAPH_NSW)
     return fail(HENN_E_UNSUPPORTED, "insertion needs an index built with the NSW graph");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   const henn_build_params& p = idx->params;
-  const int64_t n_old = idx->n;
+  const int64_t base = idx->next_id;
   try {
     // membership: layer 0 takes every new point, layer i each member of
     // layer i - 1's new points whose coin comes up (probability 2^-m)
     std::vector<int32_t> ids((size_t)count), local((size_t)count), down;
     for (int64_t j = 0; j < count; ++j) {
-      ids[(size_t)j] = (int32_t)(n_old + j);
+      ids[(size_t)j] = (int32_t)(base + j);
       local[(size_t)j] = (int32_t)j;
     }
     grow_layer(idx, 0, X_new, ids, local, down, st);
@@ -761,25 +795,135 @@ henn_status henn_insert(henn_index* idx, const float* X_new, int64_t count, void
         const uint64_t w = stream_word(p.seed, kTagInsert, (uint32_t)i, 0u, (uint64_t)ids[j]);
         if (uniform_index(w, 1ull << p.m) != 0) continue;
         up.push_back(ids[j]);
-        up_local.push_back((int32_t)(ids[j] - n_old));
+        up_local.push_back((int32_t)(ids[j] - base));
         up_down.push_back((int32_t)(below_old + (int64_t)j));
       }
       if (!up.empty()) grow_layer(idx, i, X_new, up, up_local, up_down, st);
       ids.swap(up);
     }
-    idx->n = n_old + count;
-    if (idx->root_complete) {  // the root's scan data again
-      RootAux& r = idx->root;
-      if (r.dec_owned) (void)hipFree(r.dec);
-      (void)hipFree(r.mean);
-      (void)hipFree(r.norm);
-      r = RootAux{};
-      prepare_root(idx, st);
-      HENN_HIP(hipStreamSynchronize(st));
-    }
+    idx->n += count;
+    idx->next_id = base + count;
+    if (idx->root_complete) refresh_root(idx, st);
   } catch (const HipError& e) {
     return from_hip(e);
   } catch (const std::bad_alloc&) {
+    return fail(HENN_E_NOMEM, "host allocation failed");
+  }
+  return HENN_OK;
+}
+
+henn_status henn_delete(henn_index* idx, const int32_t* ids_host, int64_t count,
+                        void* hip_stream) {
+  if (!idx) return fail(HENN_E_INVAL, "index is null");
+  if (count < 0) return fail(HENN_E_INVAL, "count must be >= 0");
+  if (count == 0) return HENN_OK;
+  if (!ids_host) return fail(HENN_E_INVAL, "ids_host is null");
+  if (idx->params.graph != HENN_GRAPH_NSW)
+    return fail(HENN_E_UNSUPPORTED, "deletion needs an index built with the NSW graph");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const henn_build_params& p = idx->params;
+  std::vector<int32_t> gone(ids_host, ids_host + count);
+  std::sort(gone.begin(), gone.end());
+  gone.erase(std::unique(gone.begin(), gone.end()), gone.end());
+  int32_t* below_np = nullptr;  // the layer below's old -> new positions (device)
+  uint8_t* del_d = nullptr;
+  int32_t* np_d = nullptr;
+  try {
+    // validate against layer 0's ids before touching anything
+    LayerDev& L0 = idx->L[0];
+    std::vector<int32_t> id0((size_t)L0.size);
+    if (L0.ids) {
+      HENN_HIP(hipMemcpy(id0.data(), L0.ids, sizeof(int32_t) * L0.size, hipMemcpyDeviceToHost));
+    } else {
+      for (int64_t j = 0; j < L0.size; ++j) id0[(size_t)j] = (int32_t)j;
+    }
+    for (int32_t g : gone)
+      if (!std::binary_search(id0.begin(), id0.end(), g))
+        return fail(HENN_E_INVAL, "an id to delete is not in the index");
+    if ((int64_t)gone.size() >= L0.size)
+      return fail(HENN_E_INVAL, "deletion would leave the index empty");
+    int lpn, cpl;
+    pick_lanes(idx->nchunks, 0, &lpn, &cpl);
+    for (int i = 0; i < idx->num_layers; ++i) {
+      LayerDev& L = idx->L[i];
+      const int64_t s = L.size;
+      std::vector<int32_t> ids_i;
+      if (i == 0) {
+        ids_i.swap(id0);
+      } else {
+        ids_i.resize((size_t)s);
+        HENN_HIP(hipMemcpy(ids_i.data(), L.ids, sizeof(int32_t) * s, hipMemcpyDeviceToHost));
+      }
+      std::vector<uint8_t> del((size_t)s, 0);
+      int64_t ndel = 0;
+      for (int32_t g : gone) {
+        const auto it = std::lower_bound(ids_i.begin(), ids_i.end(), g);
+        if (it != ids_i.end() && *it == g) {
+          del[(size_t)(it - ids_i.begin())] = 1;
+          ++ndel;
+        }
+      }
+      if (ndel == 0) {
+        if (below_np) launch_remap_down(L.down, s, below_np, st);
+        HENN_HIP(hipStreamSynchronize(st));
+        (void)hipFree(below_np);
+        below_np = nullptr;
+        continue;
+      }
+      // repair the rows around the deleted members, then drop them
+      del_d = dalloc<uint8_t>(s);
+      HENN_HIP(hipMemcpyAsync(del_d, del.data(), s, hipMemcpyHostToDevice, st));
+      repair_graph(L.vec32, s, idx->dpad, idx->nchunks, idx->metric, del_d, L.deg, L.adj, lpn,
+                   cpl, st);
+      std::vector<int32_t> np((size_t)s);
+      int64_t t = 0;
+      for (int64_t r = 0; r < s; ++r) np[(size_t)r] = del[(size_t)r] ? -1 : (int32_t)t++;
+      np_d = dalloc<int32_t>(s);
+      HENN_HIP(hipMemcpyAsync(np_d, np.data(), sizeof(int32_t) * s, hipMemcpyHostToDevice, st));
+      float* vec = dalloc<float>(t * idx->dpad);
+      int32_t* adj = dalloc<int32_t>(t * L.deg);
+      int32_t* ids = dalloc<int32_t>(t);
+      int32_t* down = i > 0 ? dalloc<int32_t>(t) : nullptr;
+      launch_compact_layer(L.vec32, L.adj, L.ids, L.down, np_d, below_np, s, idx->dpad, L.deg, vec,
+                           adj, ids, down, st);
+      HENN_HIP(hipStreamSynchronize(st));
+      replace(L.vec32, vec);
+      replace(L.adj, adj);
+      replace(L.ids, ids);
+      if (i > 0) replace(L.down, down);
+      L.size = t;
+      L.info.size = t;
+      refresh_forms(idx, L, st);
+      (void)hipFree(del_d);
+      del_d = nullptr;
+      (void)hipFree(below_np);
+      below_np = np_d;
+      np_d = nullptr;
+    }
+    (void)hipFree(below_np);
+    below_np = nullptr;
+    idx->n = idx->L[0].size;
+    // a layer that fell below half its expected size is drawn again, with
+    // every layer above it (App. C)
+    for (int i = 1; i < idx->num_layers; ++i) {
+      const int64_t expect = (idx->L[i - 1].size + (1ll << p.m) - 1) >> p.m;
+      if (2 * idx->L[i].size >= expect) continue;
+      for (int j = i; j < idx->num_layers; ++j) free_layer(idx->L[j]);
+      sample_layers_from(idx, i, st);
+      for (int j = i; j < idx->num_layers; ++j) finish_layer(idx, j, st);
+      break;
+    }
+    idx->root_complete = p.root_complete_max > 0 && idx->num_layers >= 2;
+    refresh_root(idx, st);
+  } catch (const HipError& e) {
+    (void)hipFree(below_np);
+    (void)hipFree(del_d);
+    (void)hipFree(np_d);
+    return from_hip(e);
+  } catch (const std::bad_alloc&) {
+    (void)hipFree(below_np);
+    (void)hipFree(del_d);
+    (void)hipFree(np_d);
     return fail(HENN_E_NOMEM, "host allocation failed");
   }
   return HENN_OK;
@@ -892,6 +1036,7 @@ henn_status henn_search_batch(const henn_index* idx, const float* Q, int64_t nq,
       s.row_bytes = (int64_t)idx->dpad * eb;
     }
     a.rerank_vec = idx->storage == HENN_F32 ? nullptr : idx->L[0].vec32;
+    a.ids0 = idx->L[0].ids;
     a.Q = Q;
     a.nq = nq;
     a.k_arr = sp->k;

@@ -104,6 +104,58 @@ int64_t launch_halve(uint64_t seed, int layer, int attempt, int64_t s, int m, in
   return count;
 }
 
+// ------------------------------------------------ Delete(x) compaction ----
+// Old position r of a layer moves to newpos[r] (-1: deleted).  One wave per
+// old row: the row's vector, its adjacency renumbered through newpos (the
+// repaired rows link only to live members), its id (positions are the ids of
+// a layer without an id list), and its down position renumbered through the
+// layer below's map (below_newpos nullptr: unchanged).
+__global__ void k_compact_layer(const float* vec, const int32_t* adj, const int32_t* ids,
+                                const int32_t* down, const int32_t* newpos,
+                                const int32_t* below_newpos, int64_t size, int dpad, int M,
+                                float* vec_out, int32_t* adj_out, int32_t* ids_out,
+                                int32_t* down_out) {
+  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= size) return;
+  const int32_t np = newpos[r];
+  if (np < 0) return;
+  const int lane = threadIdx.x & 63;
+  for (int j = lane; j < dpad; j += 64) vec_out[(int64_t)np * dpad + j] = vec[r * dpad + j];
+  for (int j = lane; j < M; j += 64) {
+    const int32_t e = adj[r * M + j];
+    adj_out[(int64_t)np * M + j] = e >= 0 ? newpos[e] : -1;
+  }
+  if (lane == 0) {
+    ids_out[np] = ids ? ids[r] : (int32_t)r;
+    if (down_out) down_out[np] = below_newpos ? below_newpos[down[r]] : down[r];
+  }
+}
+
+void launch_compact_layer(const float* vec, const int32_t* adj, const int32_t* ids,
+                          const int32_t* down, const int32_t* newpos,
+                          const int32_t* below_newpos, int64_t size, int dpad, int M,
+                          float* vec_out, int32_t* adj_out, int32_t* ids_out, int32_t* down_out,
+                          hipStream_t st) {
+  if (size <= 0) return;
+  hipLaunchKernelGGL(k_compact_layer, dim3((unsigned)((size + 3) / 4)), dim3(256), 0, st, vec,
+                     adj, ids, down, newpos, below_newpos, size, dpad, M, vec_out, adj_out,
+                     ids_out, down_out);
+}
+
+// down positions of a layer whose own members all stay, after the layer
+// below was compacted
+__global__ void k_remap_down(int32_t* down, int64_t size, const int32_t* below_newpos) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < size) down[r] = below_newpos[down[r]];
+}
+
+void launch_remap_down(int32_t* down, int64_t size, const int32_t* below_newpos,
+                       hipStream_t st) {
+  if (size <= 0) return;
+  hipLaunchKernelGGL(k_remap_down, dim3((unsigned)((size + 255) / 256)), dim3(256), 0, st, down,
+                     size, below_newpos);
+}
+
 // ---------------------------------------------------------- compaction ----
 constexpr int kScanBlock = 256;
 

@@ -71,6 +71,7 @@ struct henn_index {
   int32_t metric = 0, storage = 0;
   henn_build_params params{};
   int32_t num_layers = 0;
+  int64_t next_id = 0;         // id of the next inserted point (ids are never reused)
   bool root_complete = false;  // root searched by exhaustive scan (complete graph)
   henn::LayerDev L[HENN_MAX_LAYERS];
   henn::RootAux root;  // prepared when root_complete and dpad <= 128
@@ -116,6 +117,8 @@ struct SearchLayer {
 struct SearchArgs {
   SearchLayer layer[HENN_MAX_LAYERS];
   const float* rerank_vec;  // FP32 layer-0 rows for the precision forms, else nullptr
+  const int32_t* ids0;      // point id of each layer-0 position (after deletions), or
+                            // nullptr when positions are the ids
   const float* Q;
   int64_t nq;
   const int32_t* k_arr;
@@ -262,6 +265,17 @@ void symmetrize_graph(const float* vec, int64_t size, int dpad, int nchunks, int
 // Diversity pruning of C <= 32 candidates per row (ascending, -1 padded)
 // to at most R kept neighbours (-1 padded), as the NSW/HNSW neighbour
 // selection does.
+// Delete(x): repair of a layer graph around the deleted members (del[pos] = 1),
+// in place on the live rows; then the compaction of the layer.
+void repair_graph(const float* vec, int64_t size, int dpad, int nchunks, int metric,
+                  const uint8_t* del, int M, int32_t* adj, int lpn, int cpl, hipStream_t st);
+void launch_compact_layer(const float* vec, const int32_t* adj, const int32_t* ids,
+                          const int32_t* down, const int32_t* newpos,
+                          const int32_t* below_newpos, int64_t size, int dpad, int M,
+                          float* vec_out, int32_t* adj_out, int32_t* ids_out, int32_t* down_out,
+                          hipStream_t st);
+void launch_remap_down(int32_t* down, int64_t size, const int32_t* below_newpos, hipStream_t st);
+
 // One NSW insertion batch after its searches (res: [nb][R] positions of the
 // new points [lo, lo + nb), -1 padded): writes their rows and merges the
 // reverse edges into the rows of [0, lo).  Scratch: cnt and off hold lo + 1

@@ -977,4 +977,93 @@ void nsw_merge_batch(const float* vec, int dpad, int nchunks, int metric, const 
   HENN_HIP(hipGetLastError());
 }
 
+// Delete(x) repair of a layer graph: every live row v that links to deleted
+// members gets the first M of the live candidates {row(v)} + {row(u) : u a
+// deleted member of row(v)}, without v and without repeats, in (distance, id)
+// order.  One wave per row; candidates go through one source row at a time
+// (a key already in the running list is dropped, then sort and merge).
+// Deleted rows are read, never written, and a
+// live row is read and written only by its own wave, so the repair runs in
+// place.
+template <int LPN, int CPL>
+__global__ __launch_bounds__(256) void k_nsw_repair(const float* vec, int64_t size, int dpad,
+                                                    int nchunks, int metric,
+                                                    const uint8_t* del, int M, int32_t* adj) {
+  constexpr int G = 64 / LPN;
+  __shared__ int32_t rows[4][64];
+  __shared__ int32_t cids[4][64];
+  __shared__ uint64_t keys[4][64];
+  const int w = threadIdx.x >> 6;
+  const int64_t v = (int64_t)blockIdx.x * 4 + w;
+  if (v >= size || del[v]) return;  // whole wave
+  const int lane = lane_id(), t = lane % LPN, g = lane / LPN;
+  const int32_t mine = lane < M ? adj[v * M + lane] : -1;
+  const bool hit = mine >= 0 && del[mine] != 0;
+  const uint64_t hits = ballot(hit);
+  if (hits == 0) return;  // nothing of this row was deleted
+  rows[w][lane] = mine;
+  wave_sync();
+  float q[CPL][8];
+  load_query<CPL>(vec + v * dpad, dpad, t, q);
+  uint64_t best = ~0ull;
+  // candidate sources: the row itself, then each deleted neighbour's row
+  uint64_t todo = hits;
+  for (int src = -1; src < 64; ) {
+    int32_t cid = -1;
+    if (src < 0) {
+      cid = mine;
+    } else {
+      const int32_t u = rows[w][src];
+      cid = lane < M ? adj[(int64_t)u * M + lane] : -1;
+    }
+    if (cid >= 0 && (del[cid] || cid == v)) cid = -1;
+    cids[w][lane] = cid;
+    wave_sync();
+    for (int pb = 0; pb < 64; pb += G) {
+      const int ci = pb + g;
+      const int32_t id = cids[w][ci];
+      const bool valid = id >= 0;
+      const float dist = group_distance<kF32, LPN, CPL>(
+          q, vec + (int64_t)(valid ? id : 0) * dpad, 1.0f, t, nchunks, metric, valid);
+      if (t == 0) keys[w][ci] = valid ? dkey(dist, id) : ~0ull;
+    }
+    wave_sync();
+    uint64_t key = keys[w][lane];
+    for (int j = 0; j < 64; ++j) {  // a candidate already kept (same id, same key)
+      const uint64_t b = shfl_u64(best, j);
+      if (key != ~0ull && key == b) key = ~0ull;
+    }
+    const uint64_t c = wave_sort64(key);
+    const uint64_t rc = shfl_u64(c, 63 - lane);
+    uint64_t m = rc < best ? rc : best;
+    for (int stride = 32; stride > 0; stride >>= 1) {
+      const uint64_t o = shfl_xor_u64(m, stride);
+      const bool lower = (lane & stride) == 0;
+      m = lower ? (o < m ? o : m) : (o < m ? m : o);
+    }
+    best = m;
+    wave_sync();
+    if (todo == 0) break;
+    src = __builtin_ctzll(todo);
+    todo &= todo - 1;
+  }
+  if (lane < M) adj[v * M + lane] = best == ~0ull ? -1 : (int32_t)(uint32_t)best;
+}
+
+void repair_graph(const float* vec, int64_t size, int dpad, int nchunks, int metric,
+                  const uint8_t* del, int M, int32_t* adj, int lpn, int cpl, hipStream_t st) {
+  const unsigned nb = (unsigned)((size + 3) / 4);
+  bool launched = false;
+#define HENN_TRY(L, C)                                                                          \
+  if (!launched && lpn == L && cpl == C) {                                                      \
+    hipLaunchKernelGGL((k_nsw_repair<L, C>), dim3(nb), dim3(256), 0, st, vec, size, dpad,       \
+                       nchunks, metric, del, M, adj);                                           \
+    launched = true;                                                                            \
+  }
+  HENN_KNN_COMBOS(HENN_TRY)
+#undef HENN_TRY
+  if (!launched) throw HipError{hipErrorInvalidValue, "no repair kernel for this lane shape"};
+  HENN_HIP(hipGetLastError());
+}
+
 }  // namespace henn

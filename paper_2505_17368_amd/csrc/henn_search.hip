@@ -608,6 +608,7 @@ __device__ void finish_query(const SearchArgs& a, const float (&q)[CPL][8], uint
       if (j < k && j < wsize) {
         id = wkey_id(W[j]);
         dd = wkey_dist(W[j]);
+        if (a.ids0) id = a.ids0[id];
       }
       out_ids[j] = id;
       out_dist[j] = dd;
@@ -633,6 +634,7 @@ __device__ void finish_query(const SearchArgs& a, const float (&q)[CPL][8], uint
       if (j < k && j < nr) {
         id = wkey_id(Wn[j]);
         dd = wkey_dist(Wn[j]);
+        if (a.ids0) id = a.ids0[id];
       }
       out_ids[j] = id;
       out_dist[j] = dd;

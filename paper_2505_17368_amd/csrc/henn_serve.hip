@@ -346,6 +346,7 @@ henn_status henn_server_tick(henn_server* s, int32_t* n_active_out) {
       sl.row_bytes = (int64_t)idx->dpad * eb;
     }
     a.rerank_vec = idx->storage == HENN_F32 ? nullptr : idx->L[0].vec32;
+    a.ids0 = idx->L[0].ids;
     a.k_all = 1;
     a.ef_all = 1;
     a.k_max = s->k_max;

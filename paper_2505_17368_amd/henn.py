@@ -132,6 +132,7 @@ def load_library(path: str = LIB_PATH):
     lib.henn_import.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, P(BuildParams), ctypes.c_int32,
                                 P(ctypes.c_int64), P(vp), P(vp), ctypes.c_int32, vp, P(vp)]
     lib.henn_insert.argtypes = [vp, vp, ctypes.c_int64, vp]
+    lib.henn_delete.argtypes = [vp, vp, ctypes.c_int64, vp]
     lib.henn_nsw_insert.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, vp,
                                     ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
                                     ctypes.c_int32, vp]
@@ -142,7 +143,7 @@ def load_library(path: str = LIB_PATH):
                  "henn_search_graph_launch", "henn_default_server_params", "henn_server_create",
                  "henn_server_submit", "henn_server_submit_batch", "henn_server_tick",
                  "henn_server_poll",
-                 "henn_server_stats", "henn_nsw_insert", "henn_insert"):
+                 "henn_server_stats", "henn_nsw_insert", "henn_insert", "henn_delete"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -292,6 +293,13 @@ def henn_insert(index: HennIndex, X_new, stream=None) -> None:
     X_new = _dev_f32(X_new, "X_new")
     _check(load_library().henn_insert(index.handle, ctypes.c_void_p(X_new.data_ptr()),
                                       X_new.shape[0], _stream_ptr(stream)))
+
+
+def henn_delete(index: HennIndex, ids, stream=None) -> None:
+    """Delete(x) of the dynamic setting for an NSW-graph index; ids: host ints."""
+    arr = np.ascontiguousarray(np.asarray(ids, dtype=np.int32).ravel())
+    _check(load_library().henn_delete(index.handle, arr.ctypes.data_as(ctypes.c_void_p),
+                                      arr.size, _stream_ptr(stream)))
 
 
 def henn_nsw_insert(V, adj, lo: int, hi: int, degree: int, ef_construction: int,

@@ -77,6 +77,7 @@ def test_invalid_arguments_rejected_on_host(lib):
                                    a["hi"], a["R"], a["ef"], None) == hn.HENN_E_INVAL, kw
     assert lib.henn_nsw_insert(None, 100, 8, 0, fake, 16, 0, 1, 8, 32, None) == hn.HENN_E_INVAL
     assert lib.henn_insert(None, fake, 10, None) == hn.HENN_E_INVAL
+    assert lib.henn_delete(None, fake, 10, None) == hn.HENN_E_INVAL
     assert lib.henn_nsw_insert(fake, 100, 8, 0, fake, 16, 5, 5, 8, 32, None) == hn.HENN_OK
     assert hn.default_build_params(graph="pruned_sym").graph == 3
     # samplers: 0 draws (Alg. 2), 1 halving (Alg. 3)

@@ -680,3 +680,101 @@ def test_insert_rejects_other_graphs(hn):
     with pytest.raises(hn.HennError):
         hn.henn_insert(idx, to_dev(wl.uniform(10, 8, 2)))
     idx.free()
+
+
+# --------------------------------------------------- Delete(x) (App. C) ----
+
+def _delete_case(hn, ho, X, Q, p, gone, then_insert=None):
+    bp = ho.BuildParams(**p)
+    oidx = ho.delete(ho.build_index(X, bp), gone, bp)
+    idx = hn.henn_build(to_dev(X), **p)
+    hn.henn_delete(idx, gone)
+    Xa = X
+    if then_insert is not None:
+        oidx = ho.insert(oidx, then_insert, bp)
+        hn.henn_insert(idx, to_dev(then_insert))
+        Xa = np.concatenate([X, then_insert])
+    layers = _gpu_layers(idx)
+    assert len(layers) == oidx.num_layers
+    for i, (ids, adj) in enumerate(layers):
+        assert np.array_equal(ids, oidx.members[i]), f"layer {i}"
+        same = (adj == oidx.adj[i]).all(1).mean()
+        print(f"layer {i}: {same:.4f} of {len(ids)} rows identical")
+        assert same >= 0.98, (i, same)
+    gi, _ = hn.henn_search_batch(idx, to_dev(Q), k=10, ef=48)
+    gi = gi.cpu().numpy()
+    assert not np.isin(gi, gone).any()
+    ores = ho.search(oidx, Q, k=10, ef=48)
+    live = oidx.members[0]
+    _, gt_d = ho.brute_force_knn(Xa[live], Q, 10, p.get("metric", 0))
+    rg = ho.recall_at_k(gi, gt_d, Xa, Q, p.get("metric", 0))
+    ro = ho.recall_at_k(ores.ids, gt_d, Xa, Q, p.get("metric", 0))
+    assert rg > 0.8 and abs(rg - ro) < 0.02, (rg, ro)
+    return idx
+
+
+@pytest.mark.parametrize("metric,root_max", [(0, 0), (1, 0), (0, 400)])
+def test_delete_matches_oracle(hn, ho, metric, root_max):
+    """Delete(x) on the GPU against the oracle's: same layers, repaired rows
+    identical (near ties aside), no deleted id returned, same recall."""
+    sh = 0.5 if metric else 0.0
+    X = np.ascontiguousarray(wl.uniform(6000, 24, 71) - sh, dtype=np.float32)
+    Q = np.ascontiguousarray(wl.uniform(300, 24, 72) - sh, dtype=np.float32)
+    p = dict(degree=8, max_degree=16, graph=4, ef_construction=48, seed=2, metric=metric,
+             root_complete_max=root_max)
+    gone = np.random.default_rng(9).choice(6000, 1500, replace=False).astype(np.int32)
+    idx = _delete_case(hn, ho, X, Q, p, gone)
+    assert idx.shape()[1] == 4500
+    idx.free()
+
+
+def test_delete_redraws_thinned_layers_and_insert_continues(hn, ho):
+    """Deleting most of layer 1 redraws it and the layers above (bit-exact
+    samples); a later Insert(x) continues after the largest id."""
+    X = wl.uniform(6000, 16, 73)
+    Q = wl.uniform(300, 16, 74)
+    p = dict(degree=8, max_degree=16, graph=4, ef_construction=48, seed=3)
+    ref = ho.build_index(X, ho.BuildParams(**p))
+    gone = ref.members[1][: int(0.7 * len(ref.members[1]))].astype(np.int32)
+    idx = _delete_case(hn, ho, X, Q, p, gone, then_insert=wl.uniform(2000, 16, 75))
+    ids0 = idx.export_layer(0)[0]
+    assert ids0[-1] == 7999 and len(ids0) == 8000 - len(gone)
+    idx.free()
+
+
+@pytest.mark.parametrize("storage", [1, 2])
+def test_delete_precision_forms(hn, storage):
+    X = wl.uniform(5000, 32, 76)
+    Q = to_dev(wl.uniform(200, 32, 77))
+    p = dict(degree=8, max_degree=16, graph=4, ef_construction=48, seed=4)
+    gone = np.arange(0, 5000, 3, dtype=np.int32)
+    a = hn.henn_build(to_dev(X), storage=0, **p)
+    b = hn.henn_build(to_dev(X), storage=storage, **p)
+    for ix in (a, b):
+        hn.henn_delete(ix, gone)
+    ia, _ = hn.henn_search_batch(a, Q, k=10, ef=64)
+    ib, db = hn.henn_search_batch(b, Q, k=10, ef=64)
+    ia, ib = ia.cpu().numpy(), ib.cpu().numpy()
+    assert not np.isin(ib, gone).any() and not np.isin(ia, gone).any()
+    overlap = np.mean([len(set(x) & set(y)) / 10 for x, y in zip(ia, ib)])
+    assert overlap > 0.9
+    assert np.all(np.diff(db.cpu().numpy(), axis=1) >= 0)
+    a.free()
+    b.free()
+
+
+def test_delete_argument_errors(hn):
+    idx = hn.henn_build(to_dev(wl.uniform(2000, 8, 78)), degree=8, max_degree=16, graph=4)
+    with pytest.raises(hn.HennError):
+        hn.henn_delete(idx, [2000])                 # not in the index
+    with pytest.raises(hn.HennError):
+        hn.henn_delete(idx, np.arange(2000))        # would empty the index
+    hn.henn_delete(idx, [5, 5, 7])                  # repeats are fine
+    assert idx.shape()[1] == 1998
+    with pytest.raises(hn.HennError):
+        hn.henn_delete(idx, [5])                    # already gone
+    idx.free()
+    knn = hn.henn_build(to_dev(wl.uniform(2000, 8, 79)), degree=8)
+    with pytest.raises(hn.HennError):
+        hn.henn_delete(knn, [1])
+    knn.free()

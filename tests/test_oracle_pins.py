@@ -15,6 +15,8 @@ an independent library routine or a brute-force recomputation:
 * Insert(x) (App. C): growing a one-layer index from a batch boundary equals
   building it whole; upper-layer membership against NumPy-Philox coins,
   nesting and the 2^-m rate.
+* Delete(x) (App. C): the repair rule written out with NumPy keys; no
+  deleted point left in layers or results; a thinned layer is drawn again.
 * Ring ranges (Def. Ring Ranges) and the hit test against a NumPy lexsort.
 * The exact kNN graph (App. B.2) against NumPy all-pairs + lexsort.
 * Search: complete graph => exact k-NN (App. B.2: the complete graph is
@@ -411,6 +413,84 @@ def test_insert_keeps_search_quality(oracle):
     _, gt_d = oracle.brute_force_knn(Xa, Q, 10, 0)
     assert oracle.recall_at_k(res.ids, gt_d, Xa, Q) > 0.95
     assert (res.ids >= 5000).any()            # inserted points are found
+
+
+# ------------------------------------------ Delete(x), App. C (NSW index) --
+
+def _repair_by_definition(X, metric, members, adj, dflag):
+    """The repair rule written out with NumPy keys: each live row that links to
+    a deleted member takes the first M live points among its row and its
+    deleted neighbours' rows (itself and repeats out), in (distance, id) order."""
+    M = adj.shape[1]
+    out = adj.copy()
+    for v in range(len(members)):
+        row = [u for u in adj[v] if u >= 0]
+        if dflag[v] or not any(dflag[u] for u in row):
+            continue
+        cand = {u for u in row if not dflag[u]}
+        for u in row:
+            if dflag[u]:
+                cand |= {w for w in adj[u] if w >= 0 and not dflag[w] and w != v}
+        cand = sorted(cand, key=lambda u: (d64_seq(X[members[v]], X[members[u]], metric),
+                                           members[u]))[:M]
+        out[v] = cand + [-1] * (M - len(cand))
+    return out
+
+
+@pytest.mark.parametrize("metric", [0, 1])
+def test_delete_repairs_rows_by_definition(oracle, metric):
+    X = np.ascontiguousarray(wl.uniform(600, 4, 22) - (0.5 if metric else 0.0), dtype=np.float32)
+    p = oracle.BuildParams(degree=6, max_degree=12, graph=4, ef_construction=24, max_layers=0,
+                           metric=metric)
+    idx = oracle.build_index(X, p)
+    gone = np.random.default_rng(3).choice(600, 150, replace=False)
+    dflag = np.zeros(600, bool)
+    dflag[gone] = True
+    ref = _repair_by_definition(X, metric, idx.members[0], idx.adj[0], dflag)
+    keep = ~dflag
+    newpos = np.cumsum(keep) - 1
+    ref = np.where(ref[keep] >= 0, newpos[np.maximum(ref[keep], 0)], -1)
+    out = oracle.delete(idx, gone, p)
+    assert np.array_equal(out.members[0], np.flatnonzero(keep))
+    assert np.array_equal(out.adj[0], ref)
+
+
+def test_delete_search_returns_only_live_points(oracle):
+    X = wl.uniform(4000, 8, 23)
+    Q = wl.uniform(200, 8, 24)
+    p = oracle.BuildParams(degree=8, max_degree=16, graph=4, ef_construction=32, seed=7)
+    idx = oracle.build_index(X, p)
+    gone = np.random.default_rng(5).choice(4000, 1000, replace=False)
+    out = oracle.delete(idx, gone, p)
+    for i in range(out.num_layers):
+        assert not np.isin(out.members[i], gone).any()
+        if i:
+            assert np.isin(out.members[i], out.members[i - 1]).all()
+    res = oracle.search(out, Q, k=10, ef=48)
+    assert not np.isin(res.ids, gone).any()
+    live = np.setdiff1d(np.arange(4000), gone)
+    gt_ids, gt_d = oracle.brute_force_knn(X[live], Q, 10, 0)
+    assert oracle.recall_at_k(res.ids, gt_d, X, Q) > 0.95
+
+
+def test_delete_redraws_a_thinned_layer(oracle):
+    """Deleting most of layer 1 leaves it below half its expected size, so it
+    and the layers above are drawn again from the remaining layer 0."""
+    X = wl.uniform(6000, 8, 25)
+    p = oracle.BuildParams(degree=8, max_degree=16, graph=4, ef_construction=32, seed=8)
+    idx = oracle.build_index(X, p)
+    gone = idx.members[1][: int(0.7 * len(idx.members[1]))]
+    out = oracle.delete(idx, gone, p)
+    s0 = len(out.members[0])
+    assert s0 == 6000 - len(gone)
+    ref = oracle.build_layers(X, p)      # the layer loop on the remaining points
+    members = [out.members[0]]
+    infos = [ref[1][0]]
+    oracle._extend_layers(X, members, infos, p)
+    assert len(members) == out.num_layers
+    for a, b in zip(members[1:], out.members[1:]):
+        assert np.array_equal(a, b)
+    assert 2 * len(out.members[1]) >= -(-s0 // 16)
 
 
 def test_ring_members_brute_force(oracle):
