@@ -347,7 +347,7 @@ henn_status henn_import(const float *X, int64_t n, int32_t d, const henn_build_p
  * index or X_new, count < 0 or N + count >= 2^31.  On HENN_E_DEVICE /
  * HENN_E_NOMEM the index may be partly grown and should be freed.
  * Blocking; no search may use the index meanwhile, and captured search graphs
- * of the index must be created again afterwards (servers need not be). */
+ * and servers of the index must be created again afterwards. */
 henn_status henn_insert(henn_index *idx, const float *X_new, int64_t count, void *hip_stream);
 
 /* Delete(x) of the dynamic setting (App. C) for an index built with the NSW
@@ -369,7 +369,7 @@ henn_status henn_insert(henn_index *idx, const float *X_new, int64_t count, void
  * point (nothing is changed then).  On HENN_E_DEVICE / HENN_E_NOMEM the index
  * may be partly changed and should be freed.
  * Blocking; no search may use the index meanwhile, and captured search graphs
- * of the index must be created again afterwards (servers need not be). */
+ * and servers of the index must be created again afterwards. */
 henn_status henn_delete(henn_index *idx, const int32_t *ids_host, int64_t count,
                         void *hip_stream);
 
