@@ -58,10 +58,11 @@ def parse():
                     help="fixed launch shape 'lanes,waves,vis_bits,persistent' instead of the "
                          "autotuner (profiling runs use the shape the default run chose)")
     ap.add_argument("--mode", default="search",
-                    choices=["search", "batched", "serving", "worstcase"],
+                    choices=["search", "batched", "serving", "worstcase", "dynamic"],
                     help="search: the metric's ef sweep and timed steps; batched: one hipGraph "
                          "of a mixed-k / mixed-ef persistent batch (10M x 128, FP8 by default); "
-                         "worstcase: eps-net against random layers on skewed data")
+                         "worstcase: eps-net against random layers on skewed data; dynamic: "
+                         "Insert / Delete on an NSW index")
     ap.add_argument("--wc-runs", type=int, default=3, help="worstcase: builds per configuration")
     ap.add_argument("--wc-nq", type=int, default=1000, help="worstcase: queries per configuration")
     ap.add_argument("--wc-c0d", type=float, default=0.32,
@@ -141,6 +142,9 @@ def main():
         return
     if args.mode == "worstcase":
         worstcase(args)
+        return
+    if args.mode == "dynamic":
+        dynamic(args)
         return
     import torch
 
@@ -802,6 +806,92 @@ def worstcase(args):
                    "c0_times_d": args.wc_c0d, "graph": "nsw", "degree": 16, "max_degree": 32,
                    "ef_construction": 256},
         "study": study,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def dynamic(args):
+    """Insert(x) / Delete(x) of the dynamic setting (App. C) on the GPU path.
+
+    An NSW index of the 1M x 128 mixture is built on its first 900,000
+    points, takes the last 100,000 by Insert(x) in batches of 10,000, then
+    loses 100,000 random points by Delete(x) in batches of 10,000.  Recall@10
+    (FP32 rows, sampled queries) is measured after each phase and compared
+    with a fresh build on the final point set."""
+    import torch
+    import paper_2505_17368_amd as hn
+    import workloads as wl
+    from oracle import henn_oracle as ho
+    hn.load_library()
+    dev = torch.device("cuda:0")
+    X, Q = wl.make("gmm100_1M_d128")
+    n, nq = X.shape[0], Q.shape[0]
+    n0, batch, n_del = 900_000, 10_000, 100_000
+    Xd, Qd = torch.from_numpy(X).to(dev), torch.from_numpy(Q).to(dev)
+    rng = np.random.default_rng(123)
+    sample = np.sort(rng.choice(nq, min(args.gt_sample, nq), replace=False))
+    bp = dict(degree=args.degree, max_degree=args.max_degree, graph=hn.GRAPH["nsw"],
+              ef_construction=args.ef_construction, insert_shift=args.insert_shift,
+              root_complete_max=args.root_max)
+    efs = (64, 128, 192)
+
+    def recall(idx, live, id_map=None):
+        _, gt = ho.brute_force_knn(X[live], Q[sample], 10, 0)
+        out = {}
+        for ef in efs:
+            ids, _ = hn.henn_search_batch(idx, Qd, k=10, ef=ef)
+            torch.cuda.synchronize()
+            ids = ids.cpu().numpy()[sample]
+            if id_map is not None:
+                ids = np.where(ids >= 0, id_map[np.maximum(ids, 0)], -1)
+            out[ef] = round(ho.recall_at_k(ids, gt, X, Q[sample]), 4)
+        return out
+
+    torch.cuda.synchronize()
+    t = time.time()
+    idx = hn.henn_build(Xd[:n0].contiguous(), **bp)
+    torch.cuda.synchronize()
+    build_s = time.time() - t
+    log(f"build on {n0} points: {build_s:.2f}s")
+    t = time.time()
+    for b in range(n0, n, batch):
+        hn.henn_insert(idx, Xd[b:b + batch].contiguous())
+    torch.cuda.synchronize()
+    ins_s = time.time() - t
+    rec_ins = recall(idx, np.arange(n))
+    log(f"insert {n - n0} points in {ins_s:.2f}s ({(n - n0) / ins_s:,.0f}/s); recall {rec_ins}")
+    gone = np.sort(rng.choice(n, n_del, replace=False)).astype(np.int32)
+    t = time.time()
+    for b in range(0, n_del, batch):
+        hn.henn_delete(idx, gone[b:b + batch])
+    torch.cuda.synchronize()
+    del_s = time.time() - t
+    live = np.setdiff1d(np.arange(n), gone)
+    rec_del = recall(idx, live)
+    layers = [idx.layer_info(i)["size"] for i in range(idx.num_layers)]
+    log(f"delete {n_del} points in {del_s:.2f}s ({n_del / del_s:,.0f}/s); recall {rec_del}; "
+        f"layers {layers}")
+    idx.free()
+    torch.cuda.synchronize()
+    t = time.time()
+    fresh = hn.henn_build(Xd[torch.from_numpy(live).to(dev)].contiguous(), **bp)
+    torch.cuda.synchronize()
+    fresh_s = time.time() - t
+    rec_fresh = recall(fresh, live, id_map=live)
+    log(f"fresh build on the final {len(live)} points: {fresh_s:.2f}s; recall {rec_fresh}")
+    fresh.free()
+    out = {
+        "metric": "Insert(x) throughput into a 1M x 128 NSW index (batches of 10,000)",
+        "value": round((n - n0) / ins_s, 1), "unit": "points/s", "n_gpus": 1, "steps": 1,
+        "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "gmm100_1M_d128", "n0": n0, "inserted": n - n0,
+                   "deleted": n_del, "batch": batch, "graph": "nsw", "degree": args.degree,
+                   "max_degree": args.max_degree, "ef_construction": args.ef_construction},
+        "build_s": round(build_s, 2), "insert_s": round(ins_s, 2),
+        "delete_points_per_s": round(n_del / del_s, 1), "delete_s": round(del_s, 2),
+        "recall_after_insert": rec_ins, "recall_after_delete": rec_del,
+        "fresh_build_s": round(fresh_s, 2), "recall_fresh_build": rec_fresh,
     }
     print(json.dumps(out), flush=True)
 
