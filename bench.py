@@ -1,8 +1,8 @@
 """Benchmark of the HENN search hot path on one MI355X.
 
 Workload (default): 1,000,000 x 128 Gaussian mixture (100 clusters, sigma
-0.3), 10,000 queries from the same mixture, L2, k = 10, degree-16 kNN graph
-per layer.  Build once (timed and reported separately), then sweep the beam
+0.3), 10,000 queries from the same mixture, L2, k = 10, kNN graph of degree
+32 plus reverse edges (60 slots) per layer.  Build once (timed and reported separately), then sweep the beam
 width for the FP32 form and the BF16 / FP8 forms (FP32 re-rank of 4k
 candidates), pick for every form the smallest beam width whose Recall@10
 reaches 0.95, and time exactly --steps batched searches of the best form.
@@ -40,7 +40,7 @@ def parse():
     ap.add_argument("--n", type=int, default=None, help="fewer points (smoke runs)")
     ap.add_argument("--nq", type=int, default=None)
     ap.add_argument("--k", type=int, default=10)
-    ap.add_argument("--efs", default="48,64,80,96,112,128,160,192,256")
+    ap.add_argument("--efs", default="64,72,80,84,88,92,96,104,112,128,160,192")
     ap.add_argument("--forms", default="f32,bf16,fp8")
     ap.add_argument("--gt-sample", type=int, default=1000)
     ap.add_argument("--target-recall", type=float, default=0.95)
@@ -50,8 +50,8 @@ def parse():
                     help="layer sampler: Alg. 2 draws or Alg. 3 halving")
     ap.add_argument("--ef-construction", type=int, default=256, help="NSW insertion beam")
     ap.add_argument("--insert-shift", type=int, default=3, help="NSW batch = inserted >> shift")
-    ap.add_argument("--degree", type=int, default=16)
-    ap.add_argument("--max-degree", type=int, default=48)
+    ap.add_argument("--degree", type=int, default=32)
+    ap.add_argument("--max-degree", type=int, default=60)
     ap.add_argument("--root-max", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--shape", default=None,
@@ -375,7 +375,9 @@ def main():
         h = search_kernel_hash()
         for tr in json.load(open(tpath)).get("entries", []):
             if (tr.get("source_hash") == h and tr.get("workload") == args.workload
-                    and tr.get("form") == head_form and tr.get("ef") == ef):
+                    and tr.get("form") == head_form and tr.get("ef") == ef
+                    and tr.get("graph") == args.graph and tr.get("degree") == args.degree
+                    and tr.get("max_degree") == args.max_degree):
                 traffic = round(tr["fetch_bytes"] + tr["write_bytes"])
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,

@@ -1,6 +1,6 @@
 """The search at the benchmark's full size and launch configuration: the
-1M x 128 Gaussian-mixture workload, 10,000 queries, k = 10, ef = 128,
-kNN + reverse-edge graph (degree 16, 48 slots), complete root of 3,665
+1M x 128 Gaussian-mixture workload, 10,000 queries, k = 10, ef = 88,
+kNN + reverse-edge graph (degree 32, 60 slots), complete root of 3,665
 points, autotuned launch as the bench runs it.  Outputs are checked on
 sampled queries the oracle computes one by one."""
 import numpy as np
@@ -11,7 +11,8 @@ from gpu_util import assert_results_valid, assert_search_parity, to_dev
 
 pytestmark = pytest.mark.gpu
 
-BUILD = dict(degree=16, graph=1, max_degree=48, root_complete_max=4096)
+BUILD = dict(degree=32, graph=1, max_degree=60, root_complete_max=4096)
+EF = 88
 
 
 @pytest.fixture(scope="module")
@@ -39,8 +40,8 @@ def full():
 
 def _bench_search(hn, idx, Qd):
     import torch
-    hn.henn_autotune(idx, Qd, k=10, ef=128)
-    gi, gd = hn.henn_search_batch(idx, Qd, k=10, ef=128, persistent=True)
+    hn.henn_autotune(idx, Qd, k=10, ef=EF)
+    gi, gd = hn.henn_search_batch(idx, Qd, k=10, ef=EF, persistent=True)
     torch.cuda.synchronize()
     return gi.cpu().numpy(), gd.cpu().numpy()
 
@@ -56,7 +57,7 @@ def test_fp32_form_matches_oracle_on_sampled_queries(full):
     top 10 almost entirely."""
     hn, ho, X, Q, Qd, forms, oidx, sample = full
     gi, gd = _bench_search(hn, forms[0], Qd)
-    ores = ho.search(oidx, Q[sample], 10, 128)
+    ores = ho.search(oidx, Q[sample], 10, EF)
     exempt = assert_search_parity(gi[sample], gd[sample], ores, X, Q[sample], max_exempt=0.9)
     assert (~exempt).sum() >= 40, f"only {(~exempt).sum()} queries compared exactly"
     ex = np.where(exempt)[0]
