@@ -416,8 +416,11 @@ def main():
         "cpu_baseline": cpu,
     }
     if not args.no_serve:
+        # per-request beam widths: the pick and the next two grid points
+        pos = efs.index(ef)
+        ef_choices = tuple(efs[pos:pos + 3]) if pos + 3 <= len(efs) else tuple(efs[-3:])
         out["serving"] = serving_experiment(hn, indexes[head_form], Q, gt_dist, dist_rows,
-                                            sample, args)
+                                            sample, args, ef_choices=ef_choices)
     for f in forms:
         indexes[f].free()
     base.free()
