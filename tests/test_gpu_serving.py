@@ -96,3 +96,38 @@ def test_mix_with_staggered_arrivals_and_memory_admission(setup):
         assert np.array_equal(ids, ri), qi
         assert np.array_equal(dist.view(np.uint32), rd.view(np.uint32)), qi
     srv.close()
+
+
+@pytest.mark.parametrize("storage", [0, 2])
+def test_serving_and_captured_graph_after_updates(storage):
+    """After Delete(x) and Insert(x) on an NSW index, the serving form and a
+    captured search graph (both created afterwards) return the batched
+    search's ids, which are point ids, not layer positions."""
+    import torch
+
+    import paper_2505_17368_amd as hn
+    X = wl.uniform(6000, 16, 81)
+    Xn = wl.uniform(1000, 16, 82)
+    Q = wl.uniform(64, 16, 83)
+    idx = hn.henn_build(to_dev(X), degree=8, max_degree=16, graph=4, storage=storage,
+                        root_complete_max=400)
+    gone = np.arange(0, 6000, 4, dtype=np.int32)
+    hn.henn_delete(idx, gone)
+    hn.henn_insert(idx, to_dev(Xn))
+    ref_i, ref_d = _batch(hn, idx, Q, 10, 64)
+    assert not np.isin(ref_i, gone).any() and (ref_i >= 6000).any()
+    srv = hn.Server(idx, max_slots=16, k_max=10, ef_max=64, steps_per_tick=8, vis_bits=10)
+    for j in range(len(Q)):
+        srv.submit(Q[j], 10, 64, j)
+    got = _drain(srv, len(Q))
+    srv.close()
+    for j in range(len(Q)):
+        assert np.array_equal(got[j][0], ref_i[j]), j
+        assert np.array_equal(got[j][1].view(np.uint32), ref_d[j].view(np.uint32)), j
+    g = hn.SearchGraph(idx, to_dev(Q), k=10, ef=64, k_max=10, ef_max=64)
+    for _ in range(3):
+        g.launch()
+        torch.cuda.synchronize()
+        assert np.array_equal(g.ids.cpu().numpy(), ref_i)
+    g.free()
+    idx.free()
