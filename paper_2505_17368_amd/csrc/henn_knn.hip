@@ -553,12 +553,23 @@ __global__ __launch_bounds__(256) void k_knn_exact(const float* vec, int64_t siz
   X(16, 2) X(4, 8) X(16, 4) X(16, 8)
 
 int root_gram_splits(int64_t nq, int64_t root_size, int64_t* rows_per_split) {
-  // about 512 workgroups (one resident wave of them), at least 16 tiles each
-  // so that a block's query prologue is amortised
+  // Two 256-thread workgroups fit a CU, so 512 run at once.  Pick the split
+  // count with the shortest makespan, (rounds of 512 workgroups) x (tiles per
+  // split), the fewest splits among equals; at least 16 tiles per split so
+  // that a block's query prologue is amortised.
   const int64_t qblocks = (nq + 127) / 128;
-  int64_t splits = (512 + qblocks - 1) / qblocks;
-  const int64_t max_splits = std::max<int64_t>(1, root_size / (16 * kTileC));
-  splits = std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(splits, max_splits), 64));
+  const int64_t tiles = (root_size + kTileC - 1) / kTileC;
+  const int64_t max_splits =
+      std::min<int64_t>(64, std::max<int64_t>(1, root_size / (16 * kTileC)));
+  int64_t splits = 1, best = -1;
+  for (int64_t sp = 1; sp <= max_splits; ++sp) {
+    const int64_t rounds = (qblocks * sp + 511) / 512;
+    const int64_t span = rounds * ((tiles + sp - 1) / sp);
+    if (best < 0 || span < best) {
+      best = span;
+      splits = sp;
+    }
+  }
   int64_t per = (root_size + splits - 1) / splits;
   per = (per + kTileC - 1) / kTileC * kTileC;
   *rows_per_split = per;
