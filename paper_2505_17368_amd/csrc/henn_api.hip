@@ -880,13 +880,23 @@ henn_status henn_delete(henn_index* idx, const int32_t* ids_host, int64_t count,
       for (int64_t r = 0; r < s; ++r) np[(size_t)r] = del[(size_t)r] ? -1 : (int32_t)t++;
       np_d = dalloc<int32_t>(s);
       HENN_HIP(hipMemcpyAsync(np_d, np.data(), sizeof(int32_t) * s, hipMemcpyHostToDevice, st));
-      float* vec = dalloc<float>(t * idx->dpad);
-      int32_t* adj = dalloc<int32_t>(t * L.deg);
-      int32_t* ids = dalloc<int32_t>(t);
-      int32_t* down = i > 0 ? dalloc<int32_t>(t) : nullptr;
-      launch_compact_layer(L.vec32, L.adj, L.ids, L.down, np_d, below_np, s, idx->dpad, L.deg, vec,
-                           adj, ids, down, st);
-      HENN_HIP(hipStreamSynchronize(st));
+      float* vec = nullptr;
+      int32_t *adj = nullptr, *ids = nullptr, *down = nullptr;
+      try {
+        vec = dalloc<float>(t * idx->dpad);
+        adj = dalloc<int32_t>(t * L.deg);
+        ids = dalloc<int32_t>(t);
+        if (i > 0) down = dalloc<int32_t>(t);
+        launch_compact_layer(L.vec32, L.adj, L.ids, L.down, np_d, below_np, s, idx->dpad, L.deg,
+                             vec, adj, ids, down, st);
+        HENN_HIP(hipStreamSynchronize(st));
+      } catch (...) {
+        (void)hipFree(vec);
+        (void)hipFree(adj);
+        (void)hipFree(ids);
+        (void)hipFree(down);
+        throw;
+      }
       replace(L.vec32, vec);
       replace(L.adj, adj);
       replace(L.ids, ids);
