@@ -410,7 +410,7 @@ __device__ void start_query(const SearchArgs& a, int64_t qi, const float (&q)[CP
 // W holds the final list (st.wsize entries).  W / Wn are this wave's two LDS
 // list buffers and are swapped as the list is rewritten.
 // Rows each lane group gathers per pass of an expansion.
-constexpr int kGatherRows = 2;
+constexpr int kGatherRows = 3;
 
 // One gather pass: rows [base, base + NR * G) of this expansion's fresh
 // candidates (cid / csc), their distances, and their keys into ckey.
