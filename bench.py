@@ -81,6 +81,17 @@ def parse():
     return ap.parse_args()
 
 
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def calib_copy():
     """A plain copy of known size: 1 GiB read + 1 GiB written per dispatch."""
     import torch
@@ -318,12 +329,21 @@ def main():
                 break
             m = min(nq, m * 2)
         oracle_counts = np.concatenate(counts).astype(np.float64)
+        # one thread, on the first 1,000 queries
+        n1 = min(nq, 1000)
+        t = time.time()
+        ho.search(oidx, Q[:n1], k, ef, 1, threads=1)
+        el1 = time.time() - t
         cpu = {"value": round(done / el, 2), "unit": "queries/s", "cores": threads,
                "kind": "oracle",
                "sample": f"{done} oracle searches over the {nq} workload queries taken in "
                          f"order and repeated (same index, ef={ef}, "
-                         f"k={k}), FP64 C oracle, {threads} threads, {el:.1f}s"}
-        log(f"cpu baseline {cpu['value']} QPS on {threads} threads")
+                         f"k={k}), FP64 C oracle, {threads} threads, {el:.1f}s",
+               "value_1_thread": round(n1 / el1, 2),
+               "sample_1_thread": f"the first {n1} queries on one thread, {el1:.1f}s",
+               "cpu_model": _cpu_model()}
+        log(f"cpu baseline {cpu['value']} QPS on {threads} threads, "
+            f"{cpu['value_1_thread']} QPS on one")
 
     # ---- timed region: exactly --steps batched searches ----
     for _ in range(args.warmup):
