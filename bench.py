@@ -34,8 +34,8 @@ def log(msg):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="gmm100_1M_d128")
     ap.add_argument("--n", type=int, default=None, help="fewer points (smoke runs)")
     ap.add_argument("--nq", type=int, default=None)
