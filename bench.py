@@ -770,15 +770,17 @@ def worstcase(args):
         gt_ids, gt_dist = ho.brute_force_knn(X, Q, 100, 0)
         Xd, Qd = torch.from_numpy(X).to(dev), torch.from_numpy(Q).to(dev)
         entry = {"n": n, "d": d, "lam": lam}
-        for variant in ("eps_net", "random"):
+        for variant in ("eps_net", "halving", "random"):
             per_run = []
             for run in range(runs):
                 bp = dict(degree=16, max_degree=32, graph=hn.GRAPH["nsw"], ef_construction=256,
                           seed=1000 + run)
-                if variant == "eps_net":
-                    bp["c0"] = args.wc_c0d / d
-                else:
+                if variant == "random":
                     bp["eps_override"] = 2.0          # every ring vacuous: random layers
+                else:
+                    bp["c0"] = args.wc_c0d / d
+                    if variant == "halving":
+                        bp["sampler"] = hn.SAMPLER["halving"]
                 idx = hn.henn_build(Xd, **bp)
                 info = [idx.layer_info(i) for i in range(1, idx.num_layers)]
                 ids, _, cnt = hn.henn_search_batch(idx, Qd, k=1, ef=1, with_counters=True)
@@ -812,18 +814,22 @@ def worstcase(args):
                 "worst_greedy_ms": max(r["greedy_ms"] for r in per_run),
                 "mean_rho_0.9": float(np.mean([r["rho_0.9"] for r in per_run])),
                 "runs": per_run}
-        e, r = entry["eps_net"], entry["random"]
-        log(f"n={n} d={d} lam={lam:g}: worst mean hops {e['worst_mean_hops']:.1f} (eps-net) vs "
-            f"{r['worst_mean_hops']:.1f} (random); worst max hops {e['worst_max_hops']} vs "
-            f"{r['worst_max_hops']}; rho_0.9 {e['mean_rho_0.9']:.1f} vs {r['mean_rho_0.9']:.1f}; "
-            f"{time.time() - t0:.1f}s")
+        e, hv, r = entry["eps_net"], entry["halving"], entry["random"]
+        log(f"n={n} d={d} lam={lam:g}: worst mean hops {e['worst_mean_hops']:.1f} (eps-net) / "
+            f"{hv['worst_mean_hops']:.1f} (halving) / {r['worst_mean_hops']:.1f} (random); "
+            f"worst max hops {e['worst_max_hops']} / {hv['worst_max_hops']} / "
+            f"{r['worst_max_hops']}; rho_0.9 {e['mean_rho_0.9']:.1f} / "
+            f"{hv['mean_rho_0.9']:.1f} / {r['mean_rho_0.9']:.1f}; {time.time() - t0:.1f}s")
         study.append(entry)
     ratios = [x["random"]["worst_mean_hops"] / x["eps_net"]["worst_mean_hops"]
               for x in study if (x["n"], x["d"], x["lam"]) in configs]
+    ratios_h = [x["random"]["worst_mean_hops"] / x["halving"]["worst_mean_hops"]
+                for x in study if (x["n"], x["d"], x["lam"]) in configs]
     out = {
         "metric": "worst-case Alg. 4 hops, random layers / eps-net layers (geometric mean over "
                   "the n and d sweeps)",
         "value": round(float(np.exp(np.mean(np.log(ratios)))), 4), "unit": "ratio",
+        "halving_ratio": round(float(np.exp(np.mean(np.log(ratios_h)))), 4),
         "n_gpus": 1, "steps": runs, "warmup": 0, "ms_per_step": None,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
