@@ -28,15 +28,17 @@
 namespace henn {
 
 size_t search_lds_per_wave(int ef_cap, int vis_bits, bool vis16) {
-  return (size_t)ef_cap * 16 + 64 * 8 * 3 + ((size_t)1 << vis_bits) * (vis16 ? 2 : 4) + 64 * 4;
+  return (size_t)ef_cap * 8 + 64 * 8 * 2 + ((size_t)1 << vis_bits) * (vis16 ? 2 : 4) + 64 * 4;
 }
 
+// One list W, merged in place.  The kept keys' sorted copy shares storage
+// with the candidate keys: a merge reads every candidate key into a register
+// before it writes any sorted one.
 struct WaveLds {
   uint64_t* W;
-  uint64_t* Wn;
   uint64_t* ckey;     // candidate keys (by compacted slot)
-  uint64_t* kstage;   // kept keys, arrival order
-  uint64_t* ksorted;  // kept keys, ascending
+  uint64_t* kstage;   // kept keys, arrival order (FP8 scales during the gather)
+  uint64_t* ksorted;  // kept keys, ascending (= ckey)
   void* vis;  // 2^vis_bits entries: uint16 tags or int32 ids
   int32_t* cid;
 };
@@ -44,11 +46,10 @@ struct WaveLds {
 __device__ inline WaveLds carve(char* base, int ef_cap, int vis_bits, int vis16) {
   WaveLds s;
   s.W = reinterpret_cast<uint64_t*>(base);
-  s.Wn = s.W + ef_cap;
-  s.ckey = s.Wn + ef_cap;
+  s.ckey = s.W + ef_cap;
   s.kstage = s.ckey + 64;
-  s.ksorted = s.kstage + 64;
-  s.vis = s.ksorted + 64;
+  s.ksorted = s.ckey;
+  s.vis = s.kstage + 64;
   s.cid = reinterpret_cast<int32_t*>(static_cast<char*>(s.vis) +
                                      ((size_t)1 << vis_bits) * (vis16 ? 2 : 4));
   return s;
@@ -407,8 +408,7 @@ __device__ void start_query(const SearchArgs& a, int64_t qi, const float (&q)[CP
 
 // Runs up to `budget` expansions from the current state (layer changes are
 // free).  Returns true once the layer-0 beam has no unexpanded entry; then
-// W holds the final list (st.wsize entries).  W / Wn are this wave's two LDS
-// list buffers and are swapped as the list is rewritten.
+// W (this wave's LDS list) holds the final list (st.wsize entries).
 // Rows each lane group gathers per pass of an expansion.
 constexpr int kGatherRows = 3;
 
@@ -441,8 +441,8 @@ __device__ inline void gather_pass(const SearchArgs& a, const SearchLayer& L,
 }
 
 template <int KIND, int LPN, int CPL>
-__device__ bool advance(const SearchArgs& a, const float (&q)[CPL][8], WaveLds s, uint64_t*& W,
-                        uint64_t*& Wn, QState& st, int budget) {
+__device__ bool advance(const SearchArgs& a, const float (&q)[CPL][8], WaveLds s, uint64_t* W,
+                        QState& st, int budget) {
   constexpr int G = 64 / LPN;
   const int lane = lane_id(), t = lane % LPN, g = lane / LPN;
   const int vis_n = 1 << a.vis_bits;
@@ -557,26 +557,36 @@ __device__ bool advance(const SearchArgs& a, const float (&q)[CPL][8], WaveLds s
         for (int j = 0; j < nk; ++j) rk += s.kstage[j] < key;
         s.ksorted[rk] = key;
       }
+      // entries below the smallest kept key stay where they are
+      const uint64_t m0 = ballot(keep && rk == 0);
+      const int lo_min = uni(__shfl(lo, __ffsll((unsigned long long)m0) - 1));
       wave_sync();
       const int nsize = min(efl, wsize + nk);
       const int nk_step = pow2_floor(nk);
-      for (int i = lane; i < wsize; i += 64) {
-        const uint64_t wv = W[i];
-        const uint64_t ws = wkey_strip(wv);
-        int l2 = 0;  // kept keys below W[i]
-        for (int step = nk_step; step > 0; step >>= 1)
-          if (l2 + step <= nk && s.ksorted[l2 + step - 1] < ws) l2 += step;
-        const int np = i + l2;
-        if (np < efl) Wn[np] = wv;
+      // in place: an entry moves up by the kept keys below it.  Blocks of 64
+      // go from the top down, and a block is read whole before it is written,
+      // so no entry is overwritten before it is read.
+      for (int b = (wsize - 1) & ~63; b >= 0 && b + 64 > lo_min; b -= 64) {
+        const int i = b + lane;
+        uint64_t wv = 0;
+        int np = i;
+        if (i < wsize && i >= lo_min) {
+          wv = W[i];
+          const uint64_t ws = wkey_strip(wv);
+          int l2 = 0;  // kept keys below W[i]
+          for (int step = nk_step; step > 0; step >>= 1)
+            if (l2 + step <= nk && s.ksorted[l2 + step - 1] < ws) l2 += step;
+          np = i + l2;
+        }
+        wave_sync();
+        if (np != i && np < efl) W[np] = wv;
+        wave_sync();
       }
       if (keep) {
         const int np = lo + rk;
-        if (np < efl) Wn[np] = key;
+        if (np < efl) W[np] = key;
       }
       wave_sync();
-      uint64_t* tmp = W;
-      W = Wn;
-      Wn = tmp;
       wsize = nsize;
     }
     st.wsize = wsize;
@@ -596,7 +606,7 @@ __device__ bool advance(const SearchArgs& a, const float (&q)[CPL][8], WaveLds s
 // forms) to out_ids / out_dist (k_max entries, padded) and the counters.
 template <int KIND, int LPN, int CPL>
 __device__ void finish_query(const SearchArgs& a, const float (&q)[CPL][8], uint64_t* W,
-                             uint64_t* Wn, const QState& st, int32_t* out_ids, float* out_dist,
+                             const QState& st, int32_t* out_ids, float* out_dist,
                              int32_t* counters) {
   constexpr int G = 64 / LPN;
   const int lane = lane_id(), t = lane % LPN, g = lane / LPN;
@@ -622,18 +632,19 @@ __device__ void finish_query(const SearchArgs& a, const float (&q)[CPL][8], uint
       const int32_t id = valid ? wkey_id(W[ci]) : 0;
       const float dist = group_distance<kF32, LPN, CPL>(
           q, a.rerank_vec + (int64_t)id * a.dpad, 1.0f, t, a.nchunks, a.metric, valid);
-      if (valid && t == 0) Wn[ci] = wkey(dist, id);
+      // in place: a group reads its entry before the distance and writes it after
+      if (valid && t == 0) W[ci] = wkey(dist, id);
     }
     const int n2 = next_pow2_dev(nr);
-    for (int i = nr + lane; i < n2; i += 64) Wn[i] = ~0ull;
+    for (int i = nr + lane; i < n2; i += 64) W[i] = ~0ull;
     wave_sync();
-    wave_bitonic_sort(Wn, n2);
+    wave_bitonic_sort(W, n2);
     for (int j = lane; j < a.k_max; j += 64) {
       int32_t id = -1;
       float dd = INFINITY;
       if (j < k && j < nr) {
-        id = wkey_id(Wn[j]);
-        dd = wkey_dist(Wn[j]);
+        id = wkey_id(W[j]);
+        dd = wkey_dist(W[j]);
         if (a.ids0) id = a.ids0[id];
       }
       out_ids[j] = id;
@@ -657,9 +668,8 @@ __device__ void search_one(const SearchArgs& a, int64_t qi, WaveLds s) {
   QState st;
   start_query<KIND, LPN, CPL>(a, qi, q, st);
   uint64_t* W = s.W;
-  uint64_t* Wn = s.Wn;
-  advance<KIND, LPN, CPL>(a, q, s, W, Wn, st, 0x7fffffff);
-  finish_query<KIND, LPN, CPL>(a, q, W, Wn, st, a.out_ids + qi * a.k_max,
+  advance<KIND, LPN, CPL>(a, q, s, W, st, 0x7fffffff);
+  finish_query<KIND, LPN, CPL>(a, q, W, st, a.out_ids + qi * a.k_max,
                                a.out_dist + qi * a.k_max,
                                a.counters ? a.counters + qi * 4 : nullptr);
 }
@@ -705,15 +715,14 @@ __global__ __launch_bounds__(512) void k_serve_step(SearchArgs a, ServeArgs sv, 
     wave_sync();
   }
   uint64_t* W = s.W;
-  uint64_t* Wn = s.Wn;
-  const bool done = advance<KIND, LPN, CPL>(a, q, s, W, Wn, st, sv.budget);
+  const bool done = advance<KIND, LPN, CPL>(a, q, s, W, st, sv.budget);
   if (done) {
     // finished: append (slot, row) to this tick's compact completion list
     int pos = 0;
     if (lane == 0) pos = atomicAdd(sv.done_count, 1);
     pos = __shfl(pos, 0);
     int32_t* row = sv.done_rows + (int64_t)pos * (1 + 2 * a.k_max);
-    finish_query<KIND, LPN, CPL>(a, q, W, Wn, st, row + 1,
+    finish_query<KIND, LPN, CPL>(a, q, W, st, row + 1,
                                  reinterpret_cast<float*>(row + 1 + a.k_max), nullptr);
     st.li = kSlotDone;
     if (lane == 0) row[0] = slot;
