@@ -23,7 +23,9 @@ namespace henn {
 //   adj_scale: FP8 only, float [size][deg]: the scale of each neighbour, so
 //          that an expansion reads its neighbours' scales with the adjacency
 //          row instead of one scattered 4-byte read per evaluated row.
-//   ids:   int32 [size] ascending point ids (nullptr for layer 0 = identity).
+//   ids:   int32 [size] ascending point ids. For layer 0 it is nullptr (the
+//          position is the id) until the first deletion leaves gaps in the
+//          ids; from then on it is kept like the upper layers' lists.
 //   down:  int32 [size] position of the same point in layer-1 (the
 //          inter-layer edge of Def. HENN); nullptr for layer 0.
 struct LayerDev {
