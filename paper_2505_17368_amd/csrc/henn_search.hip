@@ -31,14 +31,13 @@ size_t search_lds_per_wave(int ef_cap, int vis_bits, bool vis16) {
   return (size_t)ef_cap * 8 + 64 * 8 * 2 + ((size_t)1 << vis_bits) * (vis16 ? 2 : 4) + 64 * 4;
 }
 
-// One list W, merged in place.  The kept keys' sorted copy shares storage
-// with the candidate keys: a merge reads every candidate key into a register
-// before it writes any sorted one.
+// One list W, merged in place.  A merge ranks the kept keys in kstage, then
+// reuses it as the map of the list positions that take a kept key.
 struct WaveLds {
   uint64_t* W;
   uint64_t* ckey;     // candidate keys (by compacted slot)
-  uint64_t* kstage;   // kept keys, arrival order (FP8 scales during the gather)
-  uint64_t* ksorted;  // kept keys, ascending (= ckey)
+  uint64_t* kstage;   // kept keys in arrival order; FP8 scales during the
+                      // gather and the merge's slot map after the ranks
   void* vis;  // 2^vis_bits entries: uint16 tags or int32 ids
   int32_t* cid;
 };
@@ -48,7 +47,6 @@ __device__ inline WaveLds carve(char* base, int ef_cap, int vis_bits, int vis16)
   s.W = reinterpret_cast<uint64_t*>(base);
   s.ckey = s.W + ef_cap;
   s.kstage = s.ckey + 64;
-  s.ksorted = s.ckey;
   s.vis = s.kstage + 64;
   s.cid = reinterpret_cast<int32_t*>(static_cast<char*>(s.vis) +
                                      ((size_t)1 << vis_bits) * (vis16 ? 2 : 4));
@@ -522,12 +520,17 @@ __device__ bool advance(const SearchArgs& a, const float (&q)[CPL][8], WaveLds s
       st.evals += cnt;
 
       // gather + distance, kGatherRows * G rows per pass with all their loads
-      // in flight together (an empty slot re-reads the pass's first row); a
-      // last pass of at most G rows takes one row per group
+      // in flight together (an empty slot re-reads the pass's first row); the
+      // last pass takes only as many rows per group as the rest needs
+      static_assert(kGatherRows == 3, "the pass sizes below assume three rows");
       for (int base = 0; base < cnt;) {
-        if (cnt - base > G) {
-          gather_pass<KIND, LPN, CPL, kGatherRows>(a, L, q, s, csc, base, cnt, t, g);
-          base += kGatherRows * G;
+        const int rest = cnt - base;
+        if (rest > 2 * G) {
+          gather_pass<KIND, LPN, CPL, 3>(a, L, q, s, csc, base, cnt, t, g);
+          base += 3 * G;
+        } else if (rest > G) {
+          gather_pass<KIND, LPN, CPL, 2>(a, L, q, s, csc, base, cnt, t, g);
+          base += 2 * G;
         } else {
           gather_pass<KIND, LPN, CPL, 1>(a, L, q, s, csc, base, cnt, t, g);
           base += G;
@@ -551,41 +554,57 @@ __device__ bool advance(const SearchArgs& a, const float (&q)[CPL][8], WaveLds s
       const int nk = popc64(km);
       if (nk == 0) continue;
       if (keep) s.kstage[rank_below(km)] = key;
+      // pad to a multiple of 4 (at most 64 slots) with keys below which
+      // nothing ranks, so the count below reads four keys per step
+      const int nk4 = (nk + 3) & ~3;
+      if (lane >= nk && lane < nk4) s.kstage[lane] = ~0ull;
       wave_sync();
-      int rk = 0;
-      if (keep) {
-        for (int j = 0; j < nk; ++j) rk += s.kstage[j] < key;
-        s.ksorted[rk] = key;
-      }
-      // entries below the smallest kept key stay where they are
+      int rk = 0;  // kept keys below this one
+      if (keep)
+        for (int j = 0; j < nk4; j += 4)
+          rk += (s.kstage[j] < key) + (s.kstage[j + 1] < key) + (s.kstage[j + 2] < key) +
+                (s.kstage[j + 3] < key);
+      // a kept key lands at p = lo + rk: the p are distinct and ascend with
+      // the key; the entries below the smallest stay where they are
+      const int p = lo + rk;
       const uint64_t m0 = ballot(keep && rk == 0);
       const int lo_min = uni(__shfl(lo, __ffsll((unsigned long long)m0) - 1));
-      wave_sync();
       const int nsize = min(efl, wsize + nk);
-      const int nk_step = pow2_floor(nk);
-      // in place: an entry moves up by the kept keys below it.  Blocks of 64
-      // go from the top down, and a block is read whole before it is written,
-      // so no entry is overwritten before it is read.
-      for (int b = (wsize - 1) & ~63; b >= 0 && b + 64 > lo_min; b -= 64) {
-        const int i = b + lane;
+      wave_sync();
+      // slot map (in kstage, free again): bit x of word x >> 6 marks the
+      // positions that take a kept key; nsize <= 2048 needs at most 32 words
+      uint64_t* slot = s.kstage;
+      const int w0 = lo_min >> 6;
+      if (lane <= ((nsize - 1) >> 6) - w0) {
+        uint32_t* sw = reinterpret_cast<uint32_t*>(slot + w0 + lane);
+        sw[0] = 0u;
+        sw[1] = 0u;
+      }
+      wave_sync();
+      if (keep && p < nsize) atomicOr(reinterpret_cast<unsigned long long*>(&slot[p >> 6]),
+                                      1ull << (p & 63));
+      wave_sync();
+      // in place, by output position: a position x in [lo_min, nsize) that
+      // takes no key takes W[x - K(x)], K(x) the key positions below x.  The
+      // source never lies above x, so blocks of 64 go from the top down and
+      // each reads its sources whole before it writes.
+      int kb = popc64(ballot(keep && p < nsize));  // key positions below block b + 64
+      for (int b = (nsize - 1) & ~63; b >= 0 && b + 64 > lo_min; b -= 64) {
+        const int x = b + lane;
+        const uint64_t mask = uni_u64(slot[b >> 6]);
+        kb -= popc64(mask);
+        const int below = rank_below(mask);
+        const int kx = kb + below;
+        // x takes a key when the count through this lane exceeds the one below
+        const bool is_key = rank_below(mask >> 1) + (int)(mask & 1ull) != below;
+        const bool mv = x >= lo_min && x < nsize && !is_key && kx > 0;
         uint64_t wv = 0;
-        int np = i;
-        if (i < wsize && i >= lo_min) {
-          wv = W[i];
-          const uint64_t ws = wkey_strip(wv);
-          int l2 = 0;  // kept keys below W[i]
-          for (int step = nk_step; step > 0; step >>= 1)
-            if (l2 + step <= nk && s.ksorted[l2 + step - 1] < ws) l2 += step;
-          np = i + l2;
-        }
+        if (mv) wv = W[x - kx];
         wave_sync();
-        if (np != i && np < efl) W[np] = wv;
+        if (mv) W[x] = wv;
         wave_sync();
       }
-      if (keep) {
-        const int np = lo + rk;
-        if (np < efl) W[np] = key;
-      }
+      if (keep && p < nsize) W[p] = key;
       wave_sync();
       wsize = nsize;
     }
