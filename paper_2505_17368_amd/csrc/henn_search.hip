@@ -572,7 +572,9 @@ __device__ bool advance(const SearchArgs& a, const float (&q)[CPL][8], WaveLds s
       const int nsize = min(efl, wsize + nk);
       wave_sync();
       // slot map (in kstage, free again): bit x of word x >> 6 marks the
-      // positions that take a kept key; nsize <= 2048 needs at most 32 words
+      // positions that take a kept key; nsize <= 2048 needs at most 32 words.
+      // The words are cleared as 32-bit halves: a 64-bit zero is otherwise
+      // kept live in two registers through the whole expansion loop.
       uint64_t* slot = s.kstage;
       const int w0 = lo_min >> 6;
       if (lane <= ((nsize - 1) >> 6) - w0) {
@@ -588,14 +590,16 @@ __device__ bool advance(const SearchArgs& a, const float (&q)[CPL][8], WaveLds s
       // takes no key takes W[x - K(x)], K(x) the key positions below x.  The
       // source never lies above x, so blocks of 64 go from the top down and
       // each reads its sources whole before it writes.
-      int kb = popc64(ballot(keep && p < nsize));  // key positions below block b + 64
+      int kb = popc64(ballot(keep && p < nsize));  // then: key positions below block b
       for (int b = (nsize - 1) & ~63; b >= 0 && b + 64 > lo_min; b -= 64) {
         const int x = b + lane;
         const uint64_t mask = uni_u64(slot[b >> 6]);
         kb -= popc64(mask);
         const int below = rank_below(mask);
         const int kx = kb + below;
-        // x takes a key when the count through this lane exceeds the one below
+        // x takes a key when the count through this lane exceeds the one
+        // below (counted, not tested as mask & (1 << lane): that lane mask
+        // would stay live in two registers)
         const bool is_key = rank_below(mask >> 1) + (int)(mask & 1ull) != below;
         const bool mv = x >= lo_min && x < nsize && !is_key && kx > 0;
         uint64_t wv = 0;
