@@ -130,8 +130,10 @@ typedef struct {
                                          VALU kernel instead of the matrix-core
                                          shortlist + exact check (same results) */
 #define HENN_SEARCH_VIS32 16u         /* keep full 32-bit ids in the visited table
-                                         even where 16-bit tags are exact (same
-                                         results; for tests) */
+                                         even where 8- or 16-bit tags are exact
+                                         (same results; for tests) */
+#define HENN_SEARCH_VIS16 32u         /* keep 16-bit tags where 8-bit tags would be
+                                         exact (same results; for tests) */
 
 typedef struct {
   uint32_t struct_size;   /* = sizeof(henn_search_params) */
@@ -152,7 +154,9 @@ typedef struct {
   void *ev_begin;         /* hipEvent_t or NULL: recorded on hip_stream right before */
   void *ev_end;           /* and right after the main search kernel (timing only) */
   int32_t vis_bits;       /* 0 = autotuned; else log2 of the per-query visited-table
-                             entries in LDS, 8..13 (results do not depend on it) */
+                             entries in LDS, 8..13 (results do not depend on it).
+                             An entry takes 1 byte while n < 2^vis_bits * 255, 2
+                             while n < 2^vis_bits * 65535, else 4 */
   int32_t reserved;
   void *workspace;        /* device scratch or NULL; when it holds at least
                              henn_search_workspace_size() bytes the call allocates

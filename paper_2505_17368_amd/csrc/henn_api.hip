@@ -1064,7 +1064,16 @@ henn_status henn_search_batch(const henn_index* idx, const float* Q, int64_t nq,
     a.metric = idx->metric;
     if (sp->vis_bits != 0 && (sp->vis_bits < 8 || sp->vis_bits > 13))
       return fail(HENN_E_INVAL, "vis_bits in [8, 13]");
-    a.vis_bits = sp->vis_bits ? sp->vis_bits : ef_need <= 64 ? 10 : ef_need <= 256 ? 11 : 12;
+    if (sp->vis_bits) {
+      a.vis_bits = sp->vis_bits;
+    } else {
+      // by beam width; one more slot bit where 8-bit tags are exact there
+      // (the table's bytes stay those of 16-bit tags)
+      a.vis_bits = ef_need <= 64 ? 10 : ef_need <= 256 ? 11 : 12;
+      if (!(sp->flags & (HENN_SEARCH_VIS16 | HENN_SEARCH_VIS32)) &&
+          vis_tag_bytes(idx->n, a.vis_bits + 1) == 1)
+        a.vis_bits += 1;
+    }
     a.root_complete = idx->root_complete ? 1 : 0;
     a.out_ids = out_ids;
     a.out_dist = out_dist;
@@ -1093,10 +1102,11 @@ henn_status henn_search_batch(const henn_index* idx, const float* Q, int64_t nq,
     sh.lanes_per_vec = lpn;
     sh.chunks_per_lane = cpl;
     sh.vis_bits = a.vis_bits;
-    a.vis16 = (vis_tags16(idx->n, a.vis_bits) && !(sp->flags & HENN_SEARCH_VIS32)) ? 1 : 0;
+    a.vis_bytes = (sp->flags & HENN_SEARCH_VIS32) ? 4 : vis_tag_bytes(idx->n, a.vis_bits);
+    if (a.vis_bytes == 1 && (sp->flags & HENN_SEARCH_VIS16)) a.vis_bytes = 2;
     int wpb = want_wpb > 0 ? want_wpb : 4;
     if (wpb != 1 && wpb != 2 && wpb != 4 && wpb != 8) return fail(HENN_E_INVAL, "waves_per_block");
-    while (wpb > 1 && search_lds_per_wave(a.ef_cap, a.vis_bits, a.vis16 != 0) * wpb > 65536) wpb /= 2;
+    while (wpb > 1 && search_lds_per_wave(a.ef_cap, a.vis_bits, a.vis_bytes) * wpb > 65536) wpb /= 2;
     sh.waves_per_block = wpb;
     sh.persistent = want_pers;
     sh.blocks = 0;
@@ -1219,7 +1229,7 @@ henn_status henn_autotune(henn_index* idx, const float* Q, int64_t nq,
     henn_search_params bestp = c;
     float bt = 1e30f;
     for (int l : lpns) {
-      for (int vb = 8; vb <= 11; ++vb) {
+      for (int vb = 8; vb <= 12; ++vb) {
         henn_search_params q = c;
         q.lanes_per_vec = l;
         q.waves_per_block = 4;

@@ -127,7 +127,7 @@ struct SearchArgs {
   const int32_t* ef_arr;
   int32_t k_all, ef_all, k_max, ef_upper, ef_cap, rerank_factor;
   int32_t num_layers, d, dpad, nchunks, metric, vis_bits, root_complete;
-  int32_t vis16;  // visited table of 16-bit tags (see vis_tags16)
+  int32_t vis_bytes;  // bytes per visited-table entry: 1, 2 or 4 (see vis_tag_bytes)
   int32_t* out_ids;
   float* out_dist;
   int32_t* counters;
@@ -176,13 +176,17 @@ struct LaunchShape {
   int blocks;           // persistent grid size (0 = computed)
 };
 
-// The visited table can hold 16-bit tags, slot = id mod 2^vis_bits and
-// tag = (id >> vis_bits) + 1 (0 = empty), which identify an id exactly when
-// every id of the index is below 2^vis_bits * 65535; else it holds ids.
-inline bool vis_tags16(int64_t n, int vis_bits) { return ((n - 1) >> vis_bits) < 65535; }
+// The visited table's entry for id is at slot id mod 2^vis_bits and holds
+// the tag (id >> vis_bits) + 1 (0 = empty), which identifies the id exactly:
+// in one byte when every id of the index is below 2^vis_bits * 255, in two
+// below 2^vis_bits * 65535; larger indexes keep full ids (4 bytes, hashed slot).
+inline int vis_tag_bytes(int64_t n, int vis_bits) {
+  const int64_t hi = (n - 1) >> vis_bits;
+  return hi < 255 ? 1 : hi < 65535 ? 2 : 4;
+}
 
 // Shared-memory bytes one wave needs for a given list capacity.
-size_t search_lds_per_wave(int ef_cap, int vis_bits, bool vis16);
+size_t search_lds_per_wave(int ef_cap, int vis_bits, int vis_bytes);
 
 // Enqueues the search kernel.  Returns false when no kernel instance
 // matches (storage, lanes_per_vec, chunks_per_lane).

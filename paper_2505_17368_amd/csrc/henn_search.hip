@@ -27,8 +27,8 @@
 
 namespace henn {
 
-size_t search_lds_per_wave(int ef_cap, int vis_bits, bool vis16) {
-  return (size_t)ef_cap * 8 + 64 * 8 * 2 + ((size_t)1 << vis_bits) * (vis16 ? 2 : 4) + 64 * 4;
+size_t search_lds_per_wave(int ef_cap, int vis_bits, int vis_bytes) {
+  return (size_t)ef_cap * 8 + 64 * 8 * 2 + ((size_t)1 << vis_bits) * vis_bytes + 64 * 4;
 }
 
 // One list W, merged in place.  A merge ranks the kept keys in kstage, then
@@ -38,24 +38,24 @@ struct WaveLds {
   uint64_t* ckey;     // candidate keys (by compacted slot)
   uint64_t* kstage;   // kept keys in arrival order; FP8 scales during the
                       // gather and the merge's slot map after the ranks
-  void* vis;  // 2^vis_bits entries: uint16 tags or int32 ids
+  void* vis;  // 2^vis_bits entries: uint8 or uint16 tags, or int32 ids
   int32_t* cid;
 };
 
-__device__ inline WaveLds carve(char* base, int ef_cap, int vis_bits, int vis16) {
+__device__ inline WaveLds carve(char* base, int ef_cap, int vis_bits, int vis_bytes) {
   WaveLds s;
   s.W = reinterpret_cast<uint64_t*>(base);
   s.ckey = s.W + ef_cap;
   s.kstage = s.ckey + 64;
   s.vis = s.kstage + 64;
   s.cid = reinterpret_cast<int32_t*>(static_cast<char*>(s.vis) +
-                                     ((size_t)1 << vis_bits) * (vis16 ? 2 : 4));
+                                     ((size_t)1 << vis_bits) * vis_bytes);
   return s;
 }
 
-// Visited table slot and stored value of id u (see vis_tags16).
-__device__ inline void vis_slot(int32_t u, int bits, int vis16, uint32_t& h, uint32_t& tag) {
-  if (vis16) {
+// Visited table slot and stored value of id u (see vis_tag_bytes).
+__device__ inline void vis_slot(int32_t u, int bits, int vis_bytes, uint32_t& h, uint32_t& tag) {
+  if (vis_bytes < 4) {
     h = (uint32_t)u & ((1u << bits) - 1u);
     tag = ((uint32_t)u >> bits) + 1u;
   } else {
@@ -63,11 +63,15 @@ __device__ inline void vis_slot(int32_t u, int bits, int vis16, uint32_t& h, uin
     tag = (uint32_t)u;
   }
 }
-__device__ inline uint32_t vis_get(const void* vis, int vis16, uint32_t h) {
-  return vis16 ? (uint32_t) static_cast<const uint16_t*>(vis)[h] : static_cast<const uint32_t*>(vis)[h];
+__device__ inline uint32_t vis_get(const void* vis, int vis_bytes, uint32_t h) {
+  if (vis_bytes == 1) return static_cast<const uint8_t*>(vis)[h];
+  if (vis_bytes == 2) return static_cast<const uint16_t*>(vis)[h];
+  return static_cast<const uint32_t*>(vis)[h];
 }
-__device__ inline void vis_put(void* vis, int vis16, uint32_t h, uint32_t tag) {
-  if (vis16)
+__device__ inline void vis_put(void* vis, int vis_bytes, uint32_t h, uint32_t tag) {
+  if (vis_bytes == 1)
+    static_cast<uint8_t*>(vis)[h] = (uint8_t)tag;
+  else if (vis_bytes == 2)
     static_cast<uint16_t*>(vis)[h] = (uint16_t)tag;
   else
     static_cast<uint32_t*>(vis)[h] = tag;
@@ -453,16 +457,16 @@ __device__ bool advance(const SearchArgs& a, const float (&q)[CPL][8], WaveLds s
         st.evals0 = st.evals;
       }
       st.evals += 1;  // the entry (its distance is carried down, counted per layer)
-      // empty: tag 0 (16-bit) or id -1 (32-bit); cleared as 32-bit words
-      const int vis_words = a.vis16 ? vis_n / 2 : vis_n;
-      const uint32_t empty = a.vis16 ? 0u : 0xffffffffu;
+      // empty: tag 0 (8 / 16-bit) or id -1 (32-bit); cleared as 32-bit words
+      const int vis_words = vis_n * a.vis_bytes / 4;
+      const uint32_t empty = a.vis_bytes < 4 ? 0u : 0xffffffffu;
       for (int i = lane; i < vis_words; i += 64) static_cast<uint32_t*>(s.vis)[i] = empty;
       wave_sync();
       if (lane == 0) {
         W[0] = wkey(st.cur_d, st.cur);
         uint32_t h0, t0;
-        vis_slot(st.cur, a.vis_bits, a.vis16, h0, t0);
-        vis_put(s.vis, a.vis16, h0, t0);
+        vis_slot(st.cur, a.vis_bits, a.vis_bytes, h0, t0);
+        vis_put(s.vis, a.vis_bytes, h0, t0);
       }
       st.wsize = 1;
       st.need_init = 0;
@@ -503,11 +507,11 @@ __device__ bool advance(const SearchArgs& a, const float (&q)[CPL][8], WaveLds s
       bool fresh = false;
       uint32_t h = 0, tag = 0;
       if (u >= 0) {
-        vis_slot(u, a.vis_bits, a.vis16, h, tag);
-        fresh = vis_get(s.vis, a.vis16, h) != tag;
+        vis_slot(u, a.vis_bits, a.vis_bytes, h, tag);
+        fresh = vis_get(s.vis, a.vis_bytes, h) != tag;
       }
       wave_sync();
-      if (fresh) vis_put(s.vis, a.vis16, h, tag);
+      if (fresh) vis_put(s.vis, a.vis_bytes, h, tag);
       const uint64_t fm = ballot(fresh);
       const int cnt = popc64(fm);
       // the scales ride in kstage, which is free until the merge below
@@ -715,7 +719,7 @@ __global__ __launch_bounds__(512) void k_serve_step(SearchArgs a, ServeArgs sv, 
   if (idx >= sv.n_active) return;
   const int lane = lane_id(), t = lane % LPN;
   const int32_t slot = uni(sv.active[idx]);
-  WaveLds s = carve(smem + (size_t)wave * per_wave_bytes, a.ef_cap, a.vis_bits, a.vis16);
+  WaveLds s = carve(smem + (size_t)wave * per_wave_bytes, a.ef_cap, a.vis_bits, a.vis_bytes);
   float q[CPL][8];
   load_query<CPL>(a.Q + (int64_t)slot * a.d, a.d, t, q);
   QState st = sv.states[slot];
@@ -729,7 +733,7 @@ __global__ __launch_bounds__(512) void k_serve_step(SearchArgs a, ServeArgs sv, 
   char* base = sv.arena + sv.state_off[slot];
   uint64_t* gW = reinterpret_cast<uint64_t*>(base);
   uint32_t* gvis = reinterpret_cast<uint32_t*>(base + (size_t)sv.cap[slot] * 8);
-  const int vis_n = (1 << a.vis_bits) / (a.vis16 ? 2 : 1);  // 32-bit words of the table
+  const int vis_n = (1 << a.vis_bits) * a.vis_bytes / 4;  // 32-bit words of the table
   if (st.li == kSlotNew) {
     start_query<KIND, LPN, CPL>(a, slot, q, st);
   } else if (!st.need_init) {
@@ -782,7 +786,7 @@ __global__ void k_serve_admit(const float* staged_q, const int32_t* meta, int n_
 
 template <int KIND, int LPN, int CPL>
 static void launch_serve_one(const SearchArgs& a, const ServeArgs& sv, int wpb, hipStream_t st) {
-  const size_t per_wave = search_lds_per_wave(a.ef_cap, a.vis_bits, a.vis16 != 0);
+  const size_t per_wave = search_lds_per_wave(a.ef_cap, a.vis_bits, a.vis_bytes);
   const unsigned blocks = (unsigned)((sv.n_active + wpb - 1) / wpb);
   hipLaunchKernelGGL((k_serve_step<KIND, LPN, CPL>), dim3(blocks), dim3(64 * wpb),
                      per_wave * wpb, st, a, sv, (int)per_wave, wpb);
@@ -793,7 +797,7 @@ __global__ __launch_bounds__(512) void k_search(SearchArgs a, int per_wave_bytes
                                                 int waves_per_block, int persistent) {
   extern __shared__ __align__(16) char smem[];
   const int wave = threadIdx.x >> 6;
-  WaveLds s = carve(smem + (size_t)wave * per_wave_bytes, a.ef_cap, a.vis_bits, a.vis16);
+  WaveLds s = carve(smem + (size_t)wave * per_wave_bytes, a.ef_cap, a.vis_bits, a.vis_bytes);
   if (persistent) {
     for (;;) {
       uint32_t qi = 0;
@@ -812,7 +816,7 @@ __global__ void k_reset_counter(uint32_t* c) { *c = 0u; }
 
 template <int KIND, int LPN, int CPL>
 static void launch_one(const SearchArgs& a, const LaunchShape& sh, hipStream_t st) {
-  const size_t per_wave = search_lds_per_wave(a.ef_cap, a.vis_bits, a.vis16 != 0);
+  const size_t per_wave = search_lds_per_wave(a.ef_cap, a.vis_bits, a.vis_bytes);
   const int wpb = sh.waves_per_block;
   const size_t lds = per_wave * wpb;
   if (sh.persistent) {

@@ -167,7 +167,7 @@ static void hmalloc(T** p, int64_t n) {
 static int64_t state_bytes(const henn_server* s, int32_t k, int32_t ef) {
   const int cap = next_pow2(std::max(std::max(ef, k), 1));
   const int64_t b = (int64_t)cap * 8 +
-                    ((int64_t)1 << s->vis_bits) * (vis_tags16(s->idx->n, s->vis_bits) ? 2 : 4);
+                    ((int64_t)1 << s->vis_bits) * vis_tag_bytes(s->idx->n, s->vis_bits);
   return (b + 255) / 256 * 256;
 }
 
@@ -213,7 +213,7 @@ henn_status henn_server_create(const henn_index* idx, const henn_server_params* 
     s->shape.chunks_per_lane = cpl;
     s->shape.vis_bits = s->vis_bits;
     int wpb = p->waves_per_block ? p->waves_per_block : 4;
-    while (wpb > 1 && search_lds_per_wave(s->ef_cap, s->vis_bits, vis_tags16(idx->n, s->vis_bits)) * wpb > 65536) wpb /= 2;
+    while (wpb > 1 && search_lds_per_wave(s->ef_cap, s->vis_bits, vis_tag_bytes(idx->n, s->vis_bits)) * wpb > 65536) wpb /= 2;
     s->shape.waves_per_block = wpb;
     const int64_t M = p->max_slots;
     if (p->pool_bytes < state_bytes(s, p->k_max, p->ef_max))
@@ -359,7 +359,7 @@ henn_status henn_server_tick(henn_server* s, int32_t* n_active_out) {
     a.nchunks = idx->nchunks;
     a.metric = idx->metric;
     a.vis_bits = s->vis_bits;
-    a.vis16 = vis_tags16(idx->n, s->vis_bits) ? 1 : 0;
+    a.vis_bytes = vis_tag_bytes(idx->n, s->vis_bits);
     a.root_complete = idx->root_complete ? 1 : 0;
     if (n_new > 0) {
       HENN_HIP(hipMemcpyAsync(s->stage_q_d, s->stage_q_h, sizeof(float) * n_new * s->d,

@@ -28,6 +28,7 @@ SAMPLER = {"draws": 0, "halving": 1}
 HENN_SEARCH_COUNTERS, HENN_SEARCH_PERSISTENT, HENN_SEARCH_NO_ROOT_KERNEL = 1, 2, 4
 HENN_SEARCH_ROOT_VALU = 8
 HENN_SEARCH_VIS32 = 16
+HENN_SEARCH_VIS16 = 32
 STORAGE = {"f32": HENN_F32, "bf16": HENN_BF16, "fp8": HENN_FP8_E4M3}
 METRIC = {"l2": HENN_L2, "ip": HENN_IP}
 
@@ -322,7 +323,7 @@ def henn_nsw_insert(V, adj, lo: int, hi: int, degree: int, ef_construction: int,
 def search_params(k=10, ef=32, k_arr=None, ef_arr=None, k_max=None, ef_max=None, ef_upper=1,
                   rerank_factor=4, counters=None, persistent=False, lanes_per_vec=0,
                   waves_per_block=0, root_kernel=True, events=None,
-                  vis_bits=0, vis32=False) -> SearchParams:
+                  vis_bits=0, vis32=False, vis16=False) -> SearchParams:
     sp = SearchParams()
     _check(load_library().henn_default_search_params(ctypes.byref(sp)))
     sp.k_all = k
@@ -342,7 +343,7 @@ def search_params(k=10, ef=32, k_arr=None, ef_arr=None, k_max=None, ef_max=None,
         HENN_SEARCH_COUNTERS if counters is not None else 0) | (
         HENN_SEARCH_NO_ROOT_KERNEL if root_kernel is False else 0) | (
         HENN_SEARCH_ROOT_VALU if root_kernel == "valu" else 0) | (
-        HENN_SEARCH_VIS32 if vis32 else 0)
+        HENN_SEARCH_VIS32 if vis32 else 0) | (HENN_SEARCH_VIS16 if vis16 else 0)
     sp.lanes_per_vec = lanes_per_vec
     sp.waves_per_block = waves_per_block
     sp.vis_bits = vis_bits
@@ -356,7 +357,7 @@ def henn_search_batch(index: HennIndex, Q, k=10, ef=32, k_arr=None, ef_arr=None,
                       ef_max=None, ef_upper=1, rerank_factor=4, with_counters=False,
                       persistent=False, lanes_per_vec=0, waves_per_block=0, root_kernel=True,
                       events=None, vis_bits=0, out_ids=None, out_dist=None, stream=None,
-                      vis32=False):
+                      vis32=False, vis16=False):
     """Enqueues a batched search; returns (ids, dist[, counters]) device tensors.
 
     ``events``: optional pair of recorded torch.cuda.Event (enable_timing) that
@@ -374,7 +375,7 @@ def henn_search_batch(index: HennIndex, Q, k=10, ef=32, k_arr=None, ef_arr=None,
     counters = torch.zeros((nq, 4), dtype=torch.int32, device=Q.device) if with_counters else None
     sp = search_params(k, ef, k_arr, ef_arr, kmax, ef_max, ef_upper, rerank_factor, counters,
                        persistent, lanes_per_vec, waves_per_block, root_kernel, events,
-                       vis_bits, vis32)
+                       vis_bits, vis32, vis16)
     _check(load_library().henn_search_batch(index.handle, ctypes.c_void_p(Q.data_ptr()), nq,
                                             ctypes.byref(sp), ctypes.c_void_p(out_ids.data_ptr()),
                                             ctypes.c_void_p(out_dist.data_ptr()),

@@ -544,18 +544,21 @@ def test_pruned_sym_search_parity(hn, ho):
 
 @pytest.mark.parametrize("storage", [0, 2])
 def test_visited_tags_and_ids_give_the_same_results(hn, cfg1_sym_root, storage):
-    """The visited table may hold 16-bit tags (slot = low id bits) or full
-    ids (multiplicative hash); it only decides what is re-evaluated, so the
-    results are identical, also for a table small enough to evict often."""
+    """The visited table may hold 8- or 16-bit tags (slot = low id bits) or
+    full ids (multiplicative hash); it only decides what is re-evaluated, so
+    the results are identical, also for a table small enough to evict often
+    (10,000 points: 8-bit tags are exact for every table size here)."""
     X, Q, oidx = cfg1_sym_root
     idx = _import(hn, X, oidx, storage=storage)
     Qd = to_dev(Q)
-    for vb in (8, 10):
+    for vb in (8, 10, 12):
         a_i, a_d = hn.henn_search_batch(idx, Qd, k=10, ef=64, vis_bits=vb)
-        b_i, b_d = hn.henn_search_batch(idx, Qd, k=10, ef=64, vis_bits=vb, vis32=True)
-        _sync()
-        assert np.array_equal(a_i.cpu().numpy(), b_i.cpu().numpy())
-        assert np.array_equal(a_d.cpu().numpy().view(np.uint32), b_d.cpu().numpy().view(np.uint32))
+        for kw in (dict(vis16=True), dict(vis32=True)):
+            b_i, b_d = hn.henn_search_batch(idx, Qd, k=10, ef=64, vis_bits=vb, **kw)
+            _sync()
+            assert np.array_equal(a_i.cpu().numpy(), b_i.cpu().numpy()), (vb, kw)
+            assert np.array_equal(a_d.cpu().numpy().view(np.uint32),
+                                  b_d.cpu().numpy().view(np.uint32)), (vb, kw)
     idx.free()
 
 
