@@ -270,8 +270,17 @@ __device__ inline float dpp_mov(float v) {
 // ^ m, for m = 1, 2, 4, ...; every lane of the group ends with the same sum.
 // Must be reached by the whole wave.
 template <int LPN>
+__device__ inline float group_sum_from2(float v);
+
+template <int LPN>
 __device__ inline float group_sum(float v) {
   if (LPN >= 2) v = v + dpp_mov<0xB1>(v);
+  return group_sum_from2<LPN>(v);
+}
+
+// The butterfly's steps from m = 2 on.
+template <int LPN>
+__device__ inline float group_sum_from2(float v) {
   if (LPN >= 4) v = v + dpp_mov<0x4E>(v);
   if (LPN >= 8) {
     // lane ^ 4: lanes with bit 2 clear read lane + 4, the others lane - 4
@@ -317,6 +326,54 @@ __device__ inline void group_distances(const float (&q)[CPL][8], const void* con
     float s2 = group_sum<LPN>(tree_sum<CPL>(part));
     if (metric != 0) s2 = (KIND == kFP8) ? -(scale[r] * s2) : -s2;
     out[r] = s2;
+  }
+}
+
+// As group_distances for NR = 2 or 3 rows, with rows 0 and 1 reduced in one
+// butterfly: the first step sends row 1's partial sum from the even lanes
+// and row 0's from the odd ones, so from then on the even lanes of a group
+// carry row 0 and the odd lanes row 1.  Every sum adds the same two operands
+// as group_sum's (addition commutes), so the distances are bit-identical to
+// group_distance's.  d01: row 0's distance on even lanes, row 1's on odd
+// lanes; d2: row 2's (NR = 3) on every lane.  Needs LPN >= 2.
+template <int KIND, int LPN, int CPL, int NR>
+__device__ inline void group_distances_paired(const float (&q)[CPL][8],
+                                              const void* const (&rows)[NR],
+                                              const float (&scale)[NR], int t, int nchunks,
+                                              int metric, const bool (&valid)[NR], float& d01,
+                                              float& d2) {
+  static_assert(LPN >= 2 && (NR == 2 || NR == 3), "pairs rows 0 and 1 of a lane group");
+  ChunkRaw<KIND> raw[NR][CPL];
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+#pragma unroll
+    for (int i = 0; i < CPL; ++i) {
+      const int c = t * CPL + i;
+      raw[r][i].fetch(rows[r], c < nchunks ? c : 0);
+    }
+  float ts[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    float part[CPL];
+#pragma unroll
+    for (int i = 0; i < CPL; ++i) {
+      const int c = t * CPL + i;
+      float x[8];
+      raw[r][i].decode(x);
+      const float v = metric == 0 ? chunk_l2(q[i], x, scale[r], KIND == kFP8) : chunk_ip(q[i], x);
+      part[i] = (valid[r] && c < nchunks) ? v : 0.0f;
+    }
+    ts[r] = tree_sum<CPL>(part);
+  }
+  const bool odd = (lane_id() & 1) != 0;
+  float v = (odd ? ts[1] : ts[0]) + dpp_mov<0xB1>(odd ? ts[0] : ts[1]);
+  v = group_sum_from2<LPN>(v);
+  if (metric != 0) v = (KIND == kFP8) ? -((odd ? scale[1] : scale[0]) * v) : -v;
+  d01 = v;
+  if (NR == 3) {
+    float s2 = group_sum<LPN>(ts[NR - 1]);
+    if (metric != 0) s2 = (KIND == kFP8) ? -(scale[NR - 1] * s2) : -s2;
+    d2 = s2;
   }
 }
 

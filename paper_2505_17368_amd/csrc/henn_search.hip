@@ -433,12 +433,20 @@ __device__ inline void gather_pass(const SearchArgs& a, const SearchLayer& L,
     sc[r] = (KIND == kFP8) ? csc[vd[r] ? ci : base] : 1.0f;
     rows[r] = static_cast<const char*>(L.vec) + (int64_t)ids[r] * L.row_bytes;
   }
-  float dist[NR];
-  group_distances<KIND, LPN, CPL, NR>(q, rows, sc, t, a.nchunks, a.metric, vd, dist);
-  if (t == 0) {
+  if constexpr (LPN >= 2 && NR >= 2) {
+    // rows 0 and 1 in one butterfly: lane t = 0 writes row 0, t = 1 row 1
+    float d01, d2 = 0.0f;
+    group_distances_paired<KIND, LPN, CPL, NR>(q, rows, sc, t, a.nchunks, a.metric, vd, d01, d2);
+    if (t < 2 && (t ? vd[1] : vd[0])) s.ckey[base + t * G + g] = wkey(d01, t ? ids[1] : ids[0]);
+    if (NR == 3 && t == 0 && vd[NR - 1]) s.ckey[base + (NR - 1) * G + g] = wkey(d2, ids[NR - 1]);
+  } else {
+    float dist[NR];
+    group_distances<KIND, LPN, CPL, NR>(q, rows, sc, t, a.nchunks, a.metric, vd, dist);
+    if (t == 0) {
 #pragma unroll
-    for (int r = 0; r < NR; ++r)
-      if (vd[r]) s.ckey[base + r * G + g] = wkey(dist[r], ids[r]);
+      for (int r = 0; r < NR; ++r)
+        if (vd[r]) s.ckey[base + r * G + g] = wkey(dist[r], ids[r]);
+    }
   }
 }
 
