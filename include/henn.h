@@ -272,7 +272,7 @@ typedef struct {
   int32_t rerank_factor;  /* precision forms */
   int32_t lanes_per_vec;  /* 0 = default shape */
   int32_t waves_per_block;
-  int32_t vis_bits;       /* 0 = 10 */
+  int32_t vis_bits;       /* 0 = by beam width, as henn_search_batch chooses */
 } henn_server_params;
 
 typedef struct {
@@ -351,7 +351,9 @@ henn_status henn_import(const float *X, int64_t n, int32_t d, const henn_build_p
  * index or X_new, count < 0 or N + count >= 2^31.  On HENN_E_DEVICE /
  * HENN_E_NOMEM the index may be partly grown and should be freed.
  * Blocking; no search may use the index meanwhile, and captured search graphs
- * and servers of the index must be created again afterwards. */
+ * and servers of the index must be created again afterwards
+ * (henn_search_graph_launch and henn_server_tick return HENN_E_INVAL for
+ * ones made before). */
 henn_status henn_insert(henn_index *idx, const float *X_new, int64_t count, void *hip_stream);
 
 /* Delete(x) of the dynamic setting (App. C) for an index built with the NSW
@@ -373,7 +375,9 @@ henn_status henn_insert(henn_index *idx, const float *X_new, int64_t count, void
  * point (nothing is changed then).  On HENN_E_DEVICE / HENN_E_NOMEM the index
  * may be partly changed and should be freed.
  * Blocking; no search may use the index meanwhile, and captured search graphs
- * and servers of the index must be created again afterwards. */
+ * and servers of the index must be created again afterwards
+ * (henn_search_graph_launch and henn_server_tick return HENN_E_INVAL for
+ * ones made before). */
 henn_status henn_delete(henn_index *idx, const int32_t *ids_host, int64_t count,
                         void *hip_stream);
 

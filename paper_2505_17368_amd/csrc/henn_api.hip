@@ -779,6 +779,7 @@ henn_status henn_insert(henn_index* idx, const float* X_new, int64_t count, void
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   const henn_build_params& p = idx->params;
   const int64_t base = idx->next_id;
+  ++idx->updates;
   try {
     // membership: layer 0 takes every new point, layer i each member of
     // layer i - 1's new points whose coin comes up (probability 2^-m)
@@ -842,6 +843,7 @@ henn_status henn_delete(henn_index* idx, const int32_t* ids_host, int64_t count,
         return fail(HENN_E_INVAL, "an id to delete is not in the index");
     if ((int64_t)gone.size() >= L0.size)
       return fail(HENN_E_INVAL, "deletion would leave the index empty");
+    ++idx->updates;
     int lpn, cpl;
     pick_lanes(idx->nchunks, 0, &lpn, &cpl);
     for (int i = 0; i < idx->num_layers; ++i) {
@@ -1064,16 +1066,9 @@ henn_status henn_search_batch(const henn_index* idx, const float* Q, int64_t nq,
     a.metric = idx->metric;
     if (sp->vis_bits != 0 && (sp->vis_bits < 8 || sp->vis_bits > 13))
       return fail(HENN_E_INVAL, "vis_bits in [8, 13]");
-    if (sp->vis_bits) {
-      a.vis_bits = sp->vis_bits;
-    } else {
-      // by beam width; one more slot bit where 8-bit tags are exact there
-      // (the table's bytes stay those of 16-bit tags)
-      a.vis_bits = ef_need <= 64 ? 10 : ef_need <= 256 ? 11 : 12;
-      if (!(sp->flags & (HENN_SEARCH_VIS16 | HENN_SEARCH_VIS32)) &&
-          vis_tag_bytes(idx->n, a.vis_bits + 1) == 1)
-        a.vis_bits += 1;
-    }
+    a.vis_bits = sp->vis_bits ? sp->vis_bits
+                              : default_vis_bits(ef_need, idx->n,
+                                                 !(sp->flags & (HENN_SEARCH_VIS16 | HENN_SEARCH_VIS32)));
     a.root_complete = idx->root_complete ? 1 : 0;
     a.out_ids = out_ids;
     a.out_dist = out_dist;
@@ -1305,6 +1300,8 @@ struct henn_search_graph {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   void* workspace = nullptr;
+  const henn_index* idx = nullptr;
+  int64_t idx_updates = 0;  // the index's update count when captured
 };
 
 extern "C" {
@@ -1318,6 +1315,8 @@ henn_status henn_search_graph_create(const henn_index* idx, const float* Q, int6
   if (nq < 1) return fail(HENN_E_INVAL, "a graph needs nq >= 1");
   if (sp->ev_begin || sp->ev_end) return fail(HENN_E_INVAL, "no timing events in a graph");
   henn_search_graph* g = new henn_search_graph();
+  g->idx = idx;
+  g->idx_updates = idx->updates;
   hipStream_t cs = nullptr;
   try {
     const int64_t need = search_workspace_bytes(idx, nq, sp);
@@ -1353,6 +1352,9 @@ henn_status henn_search_graph_create(const henn_index* idx, const float* Q, int6
 
 henn_status henn_search_graph_launch(henn_search_graph* g, void* hip_stream) {
   if (!g || !g->exec) return fail(HENN_E_INVAL, "null graph");
+  // the graph holds the layer arrays of capture time, which Insert / Delete replace
+  if (g->idx->updates != g->idx_updates)
+    return fail(HENN_E_INVAL, "the index was updated after this graph was captured");
   const hipError_t e = hipGraphLaunch(g->exec, static_cast<hipStream_t>(hip_stream));
   if (e != hipSuccess) return from_hip(HipError{e, "hipGraphLaunch"});
   return HENN_OK;

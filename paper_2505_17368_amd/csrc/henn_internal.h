@@ -74,6 +74,8 @@ struct henn_index {
   henn_build_params params{};
   int32_t num_layers = 0;
   int64_t next_id = 0;         // id of the next inserted point (ids are never reused)
+  int64_t updates = 0;         // Insert / Delete calls that changed the index; servers
+                               // and captured graphs made before one refuse to run
   bool root_complete = false;  // root searched by exhaustive scan (complete graph)
   henn::LayerDev L[HENN_MAX_LAYERS];
   henn::RootAux root;  // prepared when root_complete and dpad <= 128
@@ -183,6 +185,15 @@ struct LaunchShape {
 inline int vis_tag_bytes(int64_t n, int vis_bits) {
   const int64_t hi = (n - 1) >> vis_bits;
   return hi < 255 ? 1 : hi < 65535 ? 2 : 4;
+}
+
+// Default table size for a beam width: 2^10 / 2^11 / 2^12 slots, one more
+// bit where one-byte tags are exact there (the bytes of two-byte tags at the
+// base size) unless the caller keeps wider tags.
+inline int default_vis_bits(int ef_need, int64_t n, bool narrow_ok) {
+  int b = ef_need <= 64 ? 10 : ef_need <= 256 ? 11 : 12;
+  if (narrow_ok && vis_tag_bytes(n, b + 1) == 1) b += 1;
+  return b;
 }
 
 // Shared-memory bytes one wave needs for a given list capacity.

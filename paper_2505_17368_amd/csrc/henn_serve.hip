@@ -78,6 +78,7 @@ using namespace henn;
 
 struct henn_server {
   const henn_index* idx = nullptr;
+  int64_t idx_updates = 0;  // the index's update count at creation
   henn_server_params p{};
   hipStream_t st = nullptr;
   int d = 0, k_max = 0, ef_cap = 0, vis_bits = 0;
@@ -199,12 +200,15 @@ henn_status henn_server_create(const henn_index* idx, const henn_server_params* 
   henn_server* s = new henn_server();
   try {
     s->idx = idx;
+    s->idx_updates = idx->updates;
     s->p = *p;
     s->d = idx->d;
     s->k_max = p->k_max;
     s->ef_cap = next_pow2(std::max(std::max(p->ef_max, p->k_max), p->ef_upper));
     if (s->ef_cap > 2048) throw HipError{hipErrorInvalidValue, "beam width above 2048"};
-    s->vis_bits = p->vis_bits ? p->vis_bits : 10;
+    s->vis_bits = p->vis_bits ? p->vis_bits
+                              : default_vis_bits(std::max(std::max(p->ef_max, p->k_max), p->ef_upper),
+                                                 idx->n, true);
     if (s->vis_bits < 8 || s->vis_bits > 13) throw HipError{hipErrorInvalidValue, "vis_bits"};
     int lpn = 0, cpl = 0;
     pick_lanes(idx->nchunks, p->lanes_per_vec, &lpn, &cpl);
@@ -302,6 +306,10 @@ henn_status henn_server_submit_batch(henn_server* s, const float* q_host, const 
 
 henn_status henn_server_tick(henn_server* s, int32_t* n_active_out) {
   if (!s) return srv_fail(HENN_E_INVAL, "null server");
+  // sizes fixed at creation (visited-table tags, root scan) follow the index
+  // as it was then
+  if (s->idx->updates != s->idx_updates)
+    return srv_fail(HENN_E_INVAL, "the index was updated after this server was created");
   try {
     // 1) admission: FIFO, while a slot and arena bytes are free
     int n_new = 0;

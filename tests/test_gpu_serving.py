@@ -112,8 +112,18 @@ def test_serving_and_captured_graph_after_updates(storage):
     idx = hn.henn_build(to_dev(X), degree=8, max_degree=16, graph=4, storage=storage,
                         root_complete_max=400)
     gone = np.arange(0, 6000, 4, dtype=np.int32)
+    # a server and a graph made before the updates refuse to run after them
+    # (the check is on the host: nothing is launched)
+    old_srv = hn.Server(idx, max_slots=16, k_max=10, ef_max=64, steps_per_tick=8)
+    old_g = hn.SearchGraph(idx, to_dev(Q), k=10, ef=64, k_max=10, ef_max=64)
     hn.henn_delete(idx, gone)
     hn.henn_insert(idx, to_dev(Xn))
+    with pytest.raises(hn.HennError):
+        old_srv.tick()
+    with pytest.raises(hn.HennError):
+        old_g.launch()
+    old_srv.close()
+    old_g.free()
     ref_i, ref_d = _batch(hn, idx, Q, 10, 64)
     assert not np.isin(ref_i, gone).any() and (ref_i >= 6000).any()
     srv = hn.Server(idx, max_slots=16, k_max=10, ef_max=64, steps_per_tick=8, vis_bits=10)
