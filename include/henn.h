@@ -243,6 +243,9 @@ typedef struct henn_search_graph henn_search_graph;
 henn_status henn_search_graph_create(const henn_index *idx, const float *Q, int64_t nq,
                                      const henn_search_params *sp, int32_t *out_ids,
                                      float *out_dist, henn_search_graph **out);
+/* Replays the graph on hip_stream.  HENN_E_INVAL for a null graph, or once the
+ * index has been changed by henn_insert / henn_delete since the capture (the
+ * graph holds the old layer arrays). */
 henn_status henn_search_graph_launch(henn_search_graph *g, void *hip_stream);
 void henn_search_graph_free(henn_search_graph *g);
 
@@ -293,7 +296,9 @@ henn_status henn_server_submit_batch(henn_server *s, const float *q_host, const 
                                      const int32_t *ef, const int64_t *tags, int64_t n);
 /* Admits what fits, advances every active request one step, retires the
  * finished ones to the completion queue.  Blocking (one short launch).
- * *n_active (may be NULL): requests in flight during this tick. */
+ * *n_active (may be NULL): requests in flight during this tick.
+ * HENN_E_INVAL once the index has been changed by henn_insert / henn_delete
+ * since the server was created. */
 henn_status henn_server_tick(henn_server *s, int32_t *n_active);
 /* Drains up to max_results completions: tags[n], ids[n][k_max],
  * dist[n][k_max] (host; any may be NULL), *n_out. */
