@@ -123,3 +123,24 @@ def test_server_params_and_validation(lib):
     assert lib.henn_server_create(None, ctypes.byref(p), ctypes.byref(out)) == hn.HENN_E_INVAL
     assert lib.henn_server_tick(None, None) == hn.HENN_E_INVAL
     lib.henn_server_destroy(None)
+
+
+def test_binding_constants_match_header():
+    """Every enumerator and flag the binding mirrors has the header's value."""
+    import os
+    import re
+    text = open(os.path.join(os.path.dirname(__file__), "..", "include", "henn.h")).read()
+    values = {m.group(1): int(m.group(2))
+              for m in re.finditer(r"\b(HENN_[A-Z0-9_]+)\s*=\s*(\d+)", text)}
+    values.update({m.group(1): int(m.group(2))
+                   for m in re.finditer(r"#define\s+(HENN_[A-Z0-9_]+)\s+(\d+)u", text)})
+    mirrored = [n for n in dir(hn) if n.startswith("HENN_") and isinstance(getattr(hn, n), int)]
+    assert len(mirrored) >= 20
+    for name in mirrored:
+        assert name in values, name
+        assert getattr(hn, name) == values[name], name
+    for table, prefix in ((hn.GRAPH, "HENN_GRAPH_"), (hn.SAMPLER, "HENN_SAMPLER_")):
+        for key, v in table.items():
+            assert values[prefix + key.upper()] == v, (prefix, key)
+    assert hn.STORAGE == {"f32": values["HENN_F32"], "bf16": values["HENN_BF16"],
+                          "fp8": values["HENN_FP8_E4M3"]}
