@@ -148,8 +148,11 @@ typedef struct {
   int32_t rerank_factor;  /* precision forms: re-rank min(|W|, factor*k) in FP32 */
   int32_t *counters;      /* device [nq][4] or NULL: expansions, distance
                              evaluations, layer-0 expansions, layer-0 evaluations */
-  int32_t lanes_per_vec;  /* 0 = autotuned; else 4, 8, 16, 32 or 64 lanes
-                             cooperate on one neighbour vector */
+  int32_t lanes_per_vec;  /* 0 = autotuned; else 1, 2, 4, 8 or 16 lanes
+                             cooperate on one neighbour vector (those whose
+                             chunks per lane, 1 to 8, times lanes equal the
+                             row's 8-coordinate chunks rounded up to a power
+                             of two; HENN_E_INVAL otherwise) */
   int32_t waves_per_block;/* 0 = autotuned; else 1, 2, 4 or 8 */
   void *ev_begin;         /* hipEvent_t or NULL: recorded on hip_stream right before */
   void *ev_end;           /* and right after the main search kernel (timing only) */

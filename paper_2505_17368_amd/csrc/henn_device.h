@@ -289,7 +289,7 @@ __device__ inline float group_sum_from2(float v) {
   }
   if (LPN >= 16) v = v + dpp_mov<0x128>(v);
 #pragma unroll
-  for (int m = 32; m < LPN; m *= 2) v = v + __shfl_xor(v, m, 64);
+  for (int m = 16; m < LPN; m *= 2) v = v + __shfl_xor(v, m, 64);  // groups wider than a row
   return v;
 }
 
