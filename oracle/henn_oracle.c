@@ -356,15 +356,6 @@ static dkey heap_pop(heap *h) {
   return top;
 }
 
-/* second element in heap order: the better of the two children of the root */
-static int heap_second(const heap *h, dkey *out) {
-  if (h->n < 2) return 0;
-  dkey s = h->a[1];
-  if (h->n > 2 && heap_above(h, h->a[2], s)) s = h->a[2];
-  *out = s;
-  return 1;
-}
-
 /* ------------------------------------------------------------------ */
 /* One layer of the search: HNSW's SEARCH-LAYER under the total order.   */
 /* Sec. 2.2 (k>1 through a candidate set), Alg. 4 GreedySearch when      */
@@ -412,8 +403,9 @@ static int64_t search_layer(trace *t, const int32_t *members, int64_t size, cons
   heap_push(&W, e);
   while (C.n > 0) {
     dkey c = heap_pop(&C);
-    dkey cs;
-    if (heap_second(&C, &cs)) note(t, c, cs); /* which candidate is expanded next */
+    /* which candidate is expanded next: c against the one that follows it,
+     * now the top of C */
+    if (C.n > 0) note(t, c, C.a[0]);
     dkey wmax = W.a[0];
     note(t, c, wmax); /* the stop test */
     if (key_less(wmax, c)) break;

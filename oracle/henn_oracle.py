@@ -679,6 +679,84 @@ def brute_force_knn(X: np.ndarray, Q: np.ndarray, k: int, metric: int = L2, thre
     return ids, dist
 
 
+def _seq_dist(Xc: np.ndarray, q: np.ndarray, metric: int) -> np.ndarray:
+    """FP64 distances of rows Xc [m, d] to q, each summed in coordinate order
+    (the same sums as the C oracle's, vectorised over the rows)."""
+    Xc = Xc.astype(np.float64)
+    q = q.astype(np.float64)
+    acc = np.zeros(Xc.shape[0])
+    for j in range(Xc.shape[1]):
+        if metric == L2:
+            t = Xc[:, j] - q[j]
+            acc += t * t
+        else:
+            acc += Xc[:, j] * q[j]
+    return acc if metric == L2 else -acc
+
+
+def brute_force_knn_gram(X: np.ndarray, Q: np.ndarray, k: int, metric: int = L2,
+                         threads=None, chunk: int = 256):
+    """Exact k-NN (Sec. 2 problem setting) for large inputs, through an FP64
+    matrix product as a step (the same result as :func:`brute_force_knn`):
+
+    1. g(x) = |x|^2 - 2 <q, x> (L2; the squared distance minus |q|^2) or
+       -<q, x> (IP) for every point, by one FP64 matrix product per block of
+       queries (torch on the CPU);
+    2. the m = 2k + 8 points of smallest g per query (torch.topk);
+    3. their exact FP64 distances (:func:`_seq_dist`, coordinate order), sorted
+       by (distance, id); the first k are the answer
+    4. provided the shortlist provably holds them: every point left out has
+       g >= the m-th g, and |g + |q|^2 - dist| <= delta with
+       delta = 2 (d + 2) 2^-53 (|q| + max|x|)^2 (the rounding of the dot
+       product and of the norms), so when the exact k-th distance is below
+       (m-th g) + |q|^2 - 2 delta no left-out point can enter the top k.
+       Queries that fail the test are answered by :func:`brute_force_knn`.
+    Returns (ids int32 [nq, k], FP64 distances [nq, k])."""
+    import torch
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    Q = np.ascontiguousarray(Q, dtype=np.float32)
+    n, d = X.shape
+    nq = Q.shape[0]
+    m = min(n, 2 * k + 8)
+    old = torch.get_num_threads()
+    torch.set_num_threads(threads or default_threads())
+    try:
+        Xt = torch.from_numpy(X).to(torch.float64)
+        xn = (Xt * Xt).sum(1)
+        xmax = float(xn.max().sqrt())
+        ids = np.full((nq, k), -1, dtype=np.int32)
+        dist = np.full((nq, k), np.inf)
+        redo = []
+        for b in range(0, nq, chunk):
+            Qc = torch.from_numpy(Q[b:b + chunk]).to(torch.float64)
+            if metric == L2:
+                g = torch.addmm(xn.unsqueeze(0).expand(Qc.shape[0], -1), Qc, Xt.T, alpha=-2.0)
+            else:
+                g = -(Qc @ Xt.T)
+            gv, gi = torch.topk(g, m, dim=1, largest=False, sorted=True)
+            gv, gi = gv.numpy(), gi.numpy()
+            del g
+            for r in range(Qc.shape[0]):
+                qi = b + r
+                cand = gi[r]
+                dd = _seq_dist(X[cand], Q[qi], metric)
+                order = np.lexsort((cand, dd))[:k]
+                ids[qi, :len(order)] = cand[order]
+                dist[qi, :len(order)] = dd[order]
+                if m < n:
+                    qn = float(np.linalg.norm(Q[qi].astype(np.float64)))
+                    delta = 2.0 * (d + 2) * 2.0 ** -53 * (qn + xmax) ** 2
+                    bound = gv[r, m - 1] + (qn * qn if metric == L2 else 0.0) - 2 * delta
+                    if not dist[qi, k - 1] < bound:
+                        redo.append(qi)
+        if redo:
+            ri, rd = brute_force_knn(X, Q[redo], k, metric, threads)
+            ids[redo], dist[redo] = ri, rd
+    finally:
+        torch.set_num_threads(old)
+    return ids, dist
+
+
 def distance(a: np.ndarray, b: np.ndarray, metric: int = L2) -> float:
     a = np.ascontiguousarray(a, dtype=np.float32)
     b = np.ascontiguousarray(b, dtype=np.float32)

@@ -15,8 +15,10 @@ an independent library routine or a brute-force recomputation:
 * Insert(x) (App. C): growing a one-layer index from a batch boundary equals
   building it whole; upper-layer membership against NumPy-Philox coins,
   nesting and the 2^-m rate.
-* Delete(x) (App. C): the repair rule written out with NumPy keys; no
-  deleted point left in layers or results; a thinned layer is drawn again.
+* Delete(x) (App. C): the repair rule written out with NumPy keys; the
+  closed form on the complete graph (the complete graph on the survivors);
+  rows without deleted neighbours unchanged; no deleted point left in layers
+  or results; a thinned layer is drawn again.
 * Ring ranges (Def. Ring Ranges) and the hit test against a NumPy lexsort.
 * The exact kNN graph (App. B.2) against NumPy all-pairs + lexsort.
 * Search: complete graph => exact k-NN (App. B.2: the complete graph is
@@ -455,6 +457,54 @@ def test_delete_repairs_rows_by_definition(oracle, metric):
     assert np.array_equal(out.adj[0], ref)
 
 
+@pytest.mark.parametrize("metric", [0, 1])
+def test_delete_repair_of_the_complete_graph_is_complete_on_survivors(oracle, metric):
+    """Closed form: when every row lists all other points in (distance, id)
+    order (the complete graph, row capacity s - 1), every live row links to a
+    deleted point, and its repaired row must be the complete graph on the live
+    points: all other survivors, (distance, id) order, -1 padded."""
+    s = 40
+    X = np.ascontiguousarray(wl.uniform(s, 5, 26) - (0.5 if metric else 0.0), dtype=np.float32)
+    Xd = X.astype(np.float64)
+    D = ((Xd[:, None, :] - Xd[None, :, :]) ** 2).sum(-1) if metric == 0 else -(Xd @ Xd.T)
+    ids = np.arange(s)
+    adj = np.full((s, s - 1), -1, np.int32)
+    for v in range(s):
+        order = [u for u in np.lexsort((ids, D[v])) if u != v]
+        adj[v] = order
+    idx = oracle.index_from_arrays(X, metric, [ids.astype(np.int32)], [adj])
+    idx.order_margin = [np.full(s, np.inf)]
+    idx.info = [oracle.LayerInfo(s, s, 0.0, 0, 0, 0, "base")]
+    p = oracle.BuildParams(degree=4, max_degree=s - 1, graph=4, max_layers=0, metric=metric)
+    gone = np.array([0, 3, 4, 17, 18, 30, 39])
+    out = oracle.delete(idx, gone, p)
+    live = np.setdiff1d(ids, gone)
+    assert np.array_equal(out.members[0], live)
+    for j, v in enumerate(live):
+        others = [u for u in live[np.lexsort((live, D[v, live]))] if u != v]
+        want = np.searchsorted(live, others).tolist() + [-1] * (s - 1 - len(others))
+        assert out.adj[0][j].tolist() == want, v
+
+
+def test_delete_leaves_rows_without_deleted_neighbours_alone(oracle):
+    """Rows that link to no deleted member keep their neighbours (renumbered)."""
+    X = wl.uniform(800, 4, 27)
+    p = oracle.BuildParams(degree=6, max_degree=12, graph=4, ef_construction=24, max_layers=0)
+    idx = oracle.build_index(X, p)
+    gone = np.random.default_rng(4).choice(800, 40, replace=False)
+    out = oracle.delete(idx, gone, p)
+    live = np.setdiff1d(np.arange(800), gone)
+    untouched = 0
+    for j, v in enumerate(live):
+        row = [u for u in idx.adj[0][v] if u >= 0]
+        if np.isin(row, gone).any():
+            continue
+        untouched += 1
+        got = [int(live[u]) for u in out.adj[0][j] if u >= 0]
+        assert got == row
+    assert untouched > 400
+
+
 def test_delete_search_returns_only_live_points(oracle):
     X = wl.uniform(4000, 8, 23)
     Q = wl.uniform(200, 8, 24)
@@ -887,3 +937,19 @@ def test_pruned_sym_rows_are_out_plus_in_neighbours(oracle):
         assert all(dd[i] <= dd[i + 1] for i in range(len(dd) - 1))
     idx = oracle.build_index(X, oracle.BuildParams(degree=6, graph=3, max_degree=20))
     assert np.array_equal(idx.adj[0], sym)
+
+
+@pytest.mark.parametrize("metric,n,d,k", [(0, 3000, 16, 10), (1, 2500, 24, 7), (0, 40, 8, 30)])
+def test_gram_brute_force_equals_plain_brute_force(oracle, metric, n, d, k):
+    """The matrix-product route to exact k-NN returns the plain brute force's
+    ids and distances (bit for bit: both sum each distance in coordinate
+    order), also when k exceeds half the points (no shortlist)."""
+    X = wl.gauss_mix(n, d, 8, 0.3, 28)
+    Q = wl.gauss_mix(60, d, 8, 0.3, 29)
+    if metric == 1:
+        X /= np.linalg.norm(X, axis=1, keepdims=True)
+        Q /= np.linalg.norm(Q, axis=1, keepdims=True)
+    a_i, a_d = oracle.brute_force_knn(X, Q, k, metric)
+    b_i, b_d = oracle.brute_force_knn_gram(X, Q, k, metric, chunk=16)
+    assert np.array_equal(a_i, b_i)
+    assert np.array_equal(a_d, b_d)
