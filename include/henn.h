@@ -256,8 +256,8 @@ void henn_search_graph_free(henn_search_graph *g);
  * Serving form: a continuous-batching request loop on one index.
  * Requests wait in a host FIFO and are admitted at a tick when a slot is
  * free and the device state pool has room for the request's traversal
- * state (list of next_pow2(max(ef, k)) 8-byte keys + the visited table,
- * rounded to 256 B): admission is by memory.  Each tick advances every
+ * state (list of next_pow2(max(ef, k, ef_upper)) 8-byte keys + the visited
+ * table, rounded to 256 B): admission is by memory.  Each tick advances every
  * admitted request by at most steps_per_tick expansions in one launch, so
  * new requests join while others are in flight.  Results equal those of
  * henn_search_batch with the same shape (the traversal code is shared and

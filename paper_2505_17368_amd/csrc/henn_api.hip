@@ -1009,12 +1009,15 @@ static int64_t search_workspace_bytes(const henn_index* idx, int64_t nq,
   return b;
 }
 
-static std::atomic<uint32_t> g_counter_slot{0};
-static uint32_t* g_counter_pool[64] = {nullptr};  // per device id, 64 counters each
-
-henn_status henn_search_batch(const henn_index* idx, const float* Q, int64_t nq,
-                              const henn_search_params* sp, int32_t* out_ids, float* out_dist,
-                              void* hip_stream) {
+// The search behind henn_search_batch and henn_search_batch_noalloc.
+// Scratch (the persistent work counter, then the root-scan keys) comes from
+// `fixed` when given (fixed_bytes must hold search_workspace_bytes), else from
+// the caller's workspace when large enough, else from one stream-ordered
+// block of this call's own, so that concurrent searches never share a work
+// counter or root keys.
+static henn_status search_impl(const henn_index* idx, const float* Q, int64_t nq,
+                               const henn_search_params* sp, int32_t* out_ids, float* out_dist,
+                               hipStream_t st, char* fixed, int64_t fixed_bytes) {
   if (!idx) return fail(HENN_E_INVAL, "index is null");
   if (!sp || sp->struct_size != sizeof(henn_search_params))
     return fail(HENN_E_INVAL, "search params null or struct_size mismatch");
@@ -1030,7 +1033,8 @@ henn_status henn_search_batch(const henn_index* idx, const float* Q, int64_t nq,
     return fail(HENN_E_INVAL, "rerank_factor >= 1");
   const int ef_need = std::max(std::max(sp->k_max, sp->ef ? sp->ef_max : sp->ef_all), sp->ef_upper);
   if (ef_need > 2048) return fail(HENN_E_INVAL, "beam width above 2048");
-  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  char* ws = nullptr;
+  bool ws_owned = false;
   try {
     SearchArgs a;
     memset(&a, 0, sizeof(a));
@@ -1105,36 +1109,36 @@ henn_status henn_search_batch(const henn_index* idx, const float* Q, int64_t nq,
     sh.waves_per_block = wpb;
     sh.persistent = want_pers;
     sh.blocks = 0;
-    if (sh.persistent && !(sp->workspace && sp->workspace_bytes >= search_workspace_bytes(idx, nq, sp))) {
-      const int dev = idx->device;
-      if (dev < 0 || dev >= 64) return fail(HENN_E_UNSUPPORTED, "device id");
-      if (!g_counter_pool[dev]) HENN_HIP(hipMalloc(&g_counter_pool[dev], 64 * sizeof(uint32_t)));
-      a.work_counter = g_counter_pool[dev] + (g_counter_slot.fetch_add(1) & 63u);
-    }
+
     // scratch: the persistent work counter (256 B) then the root-scan keys
-    const int64_t need = search_workspace_bytes(idx, nq, sp);
-    const bool use_ws = sp->workspace && sp->workspace_bytes >= need;
-    char* ws = use_ws ? static_cast<char*>(sp->workspace) : nullptr;
-    if (sh.persistent && use_ws) a.work_counter = reinterpret_cast<uint32_t*>(ws);
-    uint64_t* root_best = nullptr;
-    bool root_owned = false;
     const int rmode = root_mode(idx, sp);
+    if (sh.persistent || rmode != 0) {
+      const int64_t need = search_workspace_bytes(idx, nq, sp);
+      if (fixed) {
+        if (fixed_bytes < need)
+          return fail(HENN_E_INVAL, "search needs " + std::to_string(need) +
+                                        " scratch bytes, above the fixed maximum of " +
+                                        std::to_string(fixed_bytes));
+        ws = fixed;
+      } else if (sp->workspace && sp->workspace_bytes >= need) {
+        ws = static_cast<char*>(sp->workspace);
+      } else {
+        HENN_HIP(hipMallocAsync((void**)&ws, need, st));
+        ws_owned = true;
+      }
+    }
+    if (sh.persistent) a.work_counter = reinterpret_cast<uint32_t*>(ws);
     if (rmode == 2) {
       int64_t per = 0;
       const int splits = root_gram_splits(nq, idx->root.size, &per);
       const int64_t nsl = (int64_t)splits * nq * 2 * kRootK;
-      if (use_ws) {
-        root_best = reinterpret_cast<uint64_t*>(ws + 256);
-      } else {
-        HENN_HIP(hipMallocAsync((void**)&root_best, sizeof(uint64_t) * nq + 8 * nsl, st));
-        root_owned = true;
-      }
+      uint64_t* root_best = reinterpret_cast<uint64_t*>(ws + 256);
       float* sl_d = reinterpret_cast<float*>(root_best + nq);
       int32_t* sl_i = reinterpret_cast<int32_t*>(sl_d + nsl);
       launch_root_gram(Q, nq, idx->d, idx->root, idx->dpad, idx->metric, splits, per, sl_d, sl_i,
                        st);
       if (!launch_root_check(idx->storage, a, idx->root, splits, sl_d, sl_i, root_best, st)) {
-        if (root_owned) (void)hipFreeAsync(root_best, st);
+        if (ws_owned) (void)hipFreeAsync(ws, st);
         return fail(HENN_E_UNSUPPORTED, "no root check kernel for this shape");
       }
       a.root_best = root_best;
@@ -1142,14 +1146,9 @@ henn_status henn_search_batch(const henn_index* idx, const float* Q, int64_t nq,
     } else if (rmode == 1) {
       int64_t per = 0;
       const int splits = root_scan_splits(nq, idx->L[idx->num_layers - 1].size, &per);
-      if (use_ws) {
-        root_best = reinterpret_cast<uint64_t*>(ws + 256);
-      } else {
-        HENN_HIP(hipMallocAsync((void**)&root_best, sizeof(uint64_t) * splits * nq, st));
-        root_owned = true;
-      }
+      uint64_t* root_best = reinterpret_cast<uint64_t*>(ws + 256);
       if (!launch_root_scan(idx->storage, a, splits, per, root_best, st)) {
-        if (root_owned) (void)hipFreeAsync(root_best, st);
+        if (ws_owned) (void)hipFreeAsync(ws, st);
         return fail(HENN_E_UNSUPPORTED, "no root scan kernel for this shape");
       }
       a.root_best = root_best;
@@ -1158,13 +1157,24 @@ henn_status henn_search_batch(const henn_index* idx, const float* Q, int64_t nq,
     if (sp->ev_begin) HENN_HIP(hipEventRecord(static_cast<hipEvent_t>(sp->ev_begin), st));
     const bool ok = launch_search(idx->storage, a, sh, st);
     if (sp->ev_end) HENN_HIP(hipEventRecord(static_cast<hipEvent_t>(sp->ev_end), st));
-    if (root_owned) HENN_HIP(hipFreeAsync(root_best, st));
+    if (ws_owned) {
+      ws_owned = false;
+      HENN_HIP(hipFreeAsync(ws, st));
+    }
     if (!ok) return fail(HENN_E_UNSUPPORTED, "no search kernel for this shape");
     HENN_HIP(hipGetLastError());
     return HENN_OK;
   } catch (const HipError& e) {
+    if (ws_owned) (void)hipFreeAsync(ws, st);
     return from_hip(e);
   }
+}
+
+henn_status henn_search_batch(const henn_index* idx, const float* Q, int64_t nq,
+                              const henn_search_params* sp, int32_t* out_ids, float* out_dist,
+                              void* hip_stream) {
+  return search_impl(idx, Q, nq, sp, out_ids, out_dist, static_cast<hipStream_t>(hip_stream),
+                     nullptr, 0);
 }
 
 henn_status henn_autotune(henn_index* idx, const float* Q, int64_t nq,

@@ -3,7 +3,8 @@
 // Requests (query vector, k, beam width, tag) are submitted on the host and
 // wait in a FIFO until admission.  A request is admitted at the next tick
 // when a slot is free and the device arena has room for its traversal
-// state (its list of next_pow2(max(ef, k)) keys plus the visited table):
+// state (its list of next_pow2(max(ef, k, ef_upper)) keys plus the visited
+// table):
 // admission is by memory.  Every tick advances every active request by at
 // most steps_per_tick expansions in one launch (k_serve_step), so requests
 // that arrive while others are in flight join the running batch and their
@@ -165,8 +166,14 @@ static void hmalloc(T** p, int64_t n) {
                          hipHostMallocDefault));
 }
 
+// List capacity of a request: its layer-0 beam max(ef, k), and the beam of
+// ef_upper entries the layers above layer 0 keep in the same list.
+static int request_cap(const henn_server* s, int32_t k, int32_t ef) {
+  return next_pow2(std::max(std::max(std::max(ef, k), s->p.ef_upper), 1));
+}
+
 static int64_t state_bytes(const henn_server* s, int32_t k, int32_t ef) {
-  const int cap = next_pow2(std::max(std::max(ef, k), 1));
+  const int cap = request_cap(s, k, ef);
   const int64_t b = (int64_t)cap * 8 +
                     ((int64_t)1 << s->vis_bits) * vis_tag_bytes(s->idx->n, s->vis_bits);
   return (b + 255) / 256 * 256;
@@ -325,7 +332,7 @@ henn_status henn_server_tick(henn_server* s, int32_t* n_active_out) {
       m[0] = slot;
       m[1] = r.k;
       m[2] = r.ef;
-      m[3] = next_pow2(std::max(std::max(r.ef, r.k), 1));
+      m[3] = request_cap(s, r.k, r.ef);
       m[4] = (int32_t)(uint32_t)((uint64_t)off & 0xffffffffu);
       m[5] = (int32_t)(uint32_t)((uint64_t)off >> 32);
       s->slot_tag[slot] = r.tag;

@@ -1,14 +1,33 @@
 """Shared helpers of the GPU parity tests (comparison against the oracle)."""
+import math
+
 import numpy as np
 
-TOL = 1e-5  # relative tolerance on distances and the spec's near-tie exemption
-# FP32 difference-form distances carry at most (2 + 8 + log2(chunks)) * 2^-24
-# relative error (one rounding of q - x, eight sequential FMAs per chunk, a
-# pairwise tree over chunks): about 1e-6 for d <= 1024.  Two distances can
-# therefore only compare differently from FP64 when their relative gap is
-# below ~2e-6, so the exemption is applied at 3e-6, which is stricter than the
-# 1e-5 the specification allows (it checks more queries, never fewer).
-STRICT = 3e-6
+TOL = 1e-5  # relative tolerance on returned distances
+
+
+def exempt_tol(d):
+    """Relative decision margin below which FP32 can order two distances
+    differently from FP64, for d-dimensional rows.
+
+    The library's FP32 distance rounds q - x once (two units on the square),
+    sums each chunk of 8 coordinates with 8 sequential FMAs and adds the chunk
+    sums by a pairwise tree over P = next_pow2(ceil(d / 8)) leaves: a relative
+    error of at most E = (2 + 8 + log2 P) 2^-24 for squared L2 (all terms are
+    positive), and at most (8 + log2 P) 2^-24 |q||x| for inner products.  Two
+    distances can only compare differently from FP64 when their relative gap is
+    at most 2E, so the exemption threshold is 2E with a 10% allowance: 1.57e-6
+    at d = 32, 1.84e-6 at d = 128, 2.23e-6 at d = 768 -- all tighter than the
+    specification's 1e-5 (it checks more queries, never fewer)."""
+    chunks = -(-int(d) // 8)
+    P = 1
+    while P < chunks:
+        P *= 2
+    return 2.2 * (10 + math.log2(P)) * 2.0 ** -24
+
+
+# kept for the graph-build tests that compare rows at the d = 32 workload
+STRICT = exempt_tol(32)
 
 
 def device():
@@ -31,16 +50,30 @@ def dist_tol(ores_dist, X, Q, ids, metric):
     return TOL * qn * xn + 1e-30
 
 
-def assert_search_parity(gids, gdist, ores, X, Q, metric=0, max_exempt=0.35, k=None,
-                         exempt_tol=STRICT):
+def exempt_mask(ores, d, graph_margins=False):
+    """Queries exempt from the id check: the oracle trace holds a decision
+    within exempt_tol(d); with graph_margins, also an expanded node whose
+    graph row was decided that close (only where the GPU searched a graph it
+    built itself, not the oracle's)."""
+    tol = exempt_tol(d)
+    ex = ores.margin <= tol
+    if graph_margins:
+        ex = ex | (ores.adj_margin <= tol)
+    return ex
+
+
+def assert_search_parity(gids, gdist, ores, X, Q, metric=0, max_exempt=None, k=None,
+                         graph_margins=False):
     """Ids bit-exact and distances within 1e-5 relative for every query whose
-    oracle trace holds no decision with a relative margin <= exempt_tol;
-    exempt queries are counted and returned."""
-    from oracle import henn_oracle as ho
+    oracle trace holds no decision within the FP32 error bound exempt_tol(d);
+    exempt queries are counted, printed with the cap, and returned.
+    max_exempt is the largest exempt fraction the test allows: about 1.5x the
+    oracle's own rate on that test's inputs, so that a near-tie recorder that
+    exempts too much fails."""
     k = k or ores.ids.shape[1]
     gids = np.asarray(gids)[:, :k]
     gdist = np.asarray(gdist)[:, :k]
-    exempt = ho.near_tie(ores, exempt_tol)
+    exempt = exempt_mask(ores, X.shape[1], graph_margins)
     ok = ~exempt
     bad = np.where(ok & ~(gids == ores.ids).all(1))[0]
     assert bad.size == 0, (f"{bad.size} non-exempt queries differ, first {bad[:5]}: "
@@ -50,7 +83,10 @@ def assert_search_parity(gids, gdist, ores, X, Q, metric=0, max_exempt=0.35, k=N
     err = np.where(valid, np.abs(gdist.astype(np.float64) - np.where(valid, ores.dist, 0)), 0)
     assert (err[ok] <= tol[ok]).all(), f"distance error {np.max(err[ok] / tol[ok])} x tol"
     assert np.isinf(gdist[~valid & ok[:, None]]).all()
-    assert exempt.mean() <= max_exempt, f"exempt fraction {exempt.mean():.3f}"
+    if max_exempt is not None:
+        print(f"exempt {exempt.mean():.4f} of {exempt.size} (cap {max_exempt}, "
+              f"tol {exempt_tol(X.shape[1]):.3g})")
+        assert exempt.mean() <= max_exempt, f"exempt fraction {exempt.mean():.4f}"
     return exempt
 
 

@@ -31,7 +31,7 @@ def full():
     for st in (1, 2):
         forms[st] = hn.henn_import(Xd, [l[0] for l in layers], [l[1] for l in layers],
                                    storage=st, **BUILD)
-    sample = np.sort(np.random.default_rng(5).choice(Q.shape[0], 256, replace=False))
+    sample = np.sort(np.random.default_rng(5).choice(Q.shape[0], 1500, replace=False))
     yield hn, ho, X, Q, Qd, forms, oidx, sample
     for idx in forms.values():
         idx.free()
@@ -47,20 +47,22 @@ def _bench_search(hn, idx, Qd):
 
 
 def test_fp32_form_matches_oracle_on_sampled_queries(full):
-    """The whole 10,000-query batch runs as the bench runs it; 256 sampled
+    """The whole 10,000-query batch runs as the bench runs it; 1,500 sampled
     queries are searched by the oracle on the exported hierarchy.  Queries
-    whose trace holds no decision within the FP32 error bound (3e-6
-    relative) must agree id for id, distances within 1e-5.  At this scale a
-    trace makes ~3,000 evaluations, so most traces hold such a near tie
-    somewhere; those are exempt from the id check but must still return
-    valid results (exact FP32 distances, sorted) that overlap the oracle's
-    top 10 almost entirely."""
+    whose trace holds no decision within the FP32 error bound (1.84e-6
+    relative at d = 128) must agree id for id, distances within 1e-5.  At
+    this scale a trace makes ~3,000 evaluations, so many traces hold such a
+    near tie somewhere; those are exempt from the id check but must still
+    return valid results (exact FP32 distances, sorted) that overlap the
+    oracle's top 10 almost entirely.  At least 200 queries are compared
+    exactly."""
     hn, ho, X, Q, Qd, forms, oidx, sample = full
     gi, gd = _bench_search(hn, forms[0], Qd)
     ores = ho.search(oidx, Q[sample], 10, EF)
-    exempt = assert_search_parity(gi[sample], gd[sample], ores, X, Q[sample], max_exempt=0.9)
-    assert (~exempt).sum() >= 40, f"only {(~exempt).sum()} queries compared exactly"
-    ex = np.where(exempt)[0]
+    # the oracle exempts 42.2% of these 1,500 queries
+    exempt = assert_search_parity(gi[sample], gd[sample], ores, X, Q[sample], max_exempt=0.64)
+    assert (~exempt).sum() >= 200, f"only {(~exempt).sum()} queries compared exactly"
+    ex = np.where(exempt)[0][:300]
     assert_results_valid(gi[sample[ex]], gd[sample[ex]], X, Q[sample[ex]])
     overlap = [len(set(gi[sample[j]]) & set(ores.ids[j])) / 10 for j in ex]
     assert np.mean(overlap) >= 0.9, np.mean(overlap)
@@ -73,6 +75,7 @@ def test_precision_forms_at_full_size(full, storage):
     sampled Recall@10 against the FP64 brute force stays at the level the
     bench reports (0.95 at this beam width)."""
     hn, ho, X, Q, Qd, forms, oidx, sample = full
+    sample = sample[:256]
     gi, gd = _bench_search(hn, forms[storage], Qd)
     assert_results_valid(gi[sample], gd[sample], X, Q[sample])
     _, gt = ho.brute_force_knn(X, Q[sample], 10, 0)

@@ -1,8 +1,10 @@
 """Parity of the HIP path (through the C ABI) with the FP64 oracle.
 
 The plain FP32 path must return the oracle's ids bit-exactly, position by
-position, for every query whose oracle trace holds no decision with a
-relative margin <= 1e-5, with distances within 1e-5 relative.  Sizes span
+position, for every query whose oracle trace holds no decision within the
+FP32 error bound (exempt_tol(d), below the specification's 1e-5), with
+distances within 1e-5 relative.  Each test caps the exempt fraction near 1.5x
+the oracle's own rate on its inputs (printed).  Sizes span
 several tiles / waves and ragged tails; edge cases cover tiny and padded
 inputs.
 """
@@ -10,7 +12,8 @@ import numpy as np
 import pytest
 
 import workloads as wl
-from gpu_util import STRICT, assert_results_valid, assert_search_parity, to_dev
+from gpu_util import (assert_results_valid, assert_search_parity, exempt_mask, exempt_tol,
+                      to_dev)
 
 pytestmark = pytest.mark.gpu
 
@@ -54,27 +57,31 @@ def test_search_parity_on_oracle_index_cfg1(hn, ho, cfg1):
     gi, gd = hn.henn_search_batch(idx, to_dev(Q), k=10, ef=32)
     _sync()
     ores = ho.search(oidx, Q, 10, 32)
-    ex = assert_search_parity(gi.cpu().numpy(), gd.cpu().numpy(), ores, X, Q)
-    print(f"exempt {ex.mean():.3f}")
+    assert_search_parity(gi.cpu().numpy(), gd.cpu().numpy(), ores, X, Q, max_exempt=0.041)
     assert_results_valid(gi.cpu().numpy()[:100], gd.cpu().numpy()[:100], X, Q[:100])
     idx.free()
 
 
-@pytest.mark.parametrize("k,ef,ef_upper", [(1, 1, 1), (10, 10, 1), (10, 64, 1), (5, 200, 1),
-                                           (10, 32, 4), (64, 64, 1)])
-def test_search_parity_beam_widths(hn, ho, cfg1, k, ef, ef_upper):
+# caps: 1.5x the oracle's exempt rate on these 300 queries (0, 0, 10.7%, 43.3%,
+# 2.0%, 11.7%), at least 1%
+@pytest.mark.parametrize("k,ef,ef_upper,cap", [(1, 1, 1, 0.01), (10, 10, 1, 0.01),
+                                               (10, 64, 1, 0.161), (5, 200, 1, 0.65),
+                                               (10, 32, 4, 0.03), (64, 64, 1, 0.176)])
+def test_search_parity_beam_widths(hn, ho, cfg1, k, ef, ef_upper, cap):
     X, Q, oidx = cfg1
     idx = _import(hn, X, oidx)
     Qs = Q[:300]
     gi, gd = hn.henn_search_batch(idx, to_dev(Qs), k=k, ef=ef, ef_upper=ef_upper)
     _sync()
     ores = ho.search(oidx, Qs, k, ef, ef_upper)
-    assert_search_parity(gi.cpu().numpy(), gd.cpu().numpy(), ores, X, Qs, max_exempt=0.6)
+    assert_search_parity(gi.cpu().numpy(), gd.cpu().numpy(), ores, X, Qs, max_exempt=cap)
     idx.free()
 
 
-@pytest.mark.parametrize("metric,d", [(0, 20), (1, 24), (0, 100), (1, 128)])
-def test_search_parity_metrics_and_ragged_dims(hn, ho, metric, d):
+# caps: 1.5x the oracle's exempt rate (1.6%, 3.9%, 6.2%, 8.6% of 257 queries)
+@pytest.mark.parametrize("metric,d,cap", [(0, 20, 0.024), (1, 24, 0.059), (0, 100, 0.094),
+                                          (1, 128, 0.129)])
+def test_search_parity_metrics_and_ragged_dims(hn, ho, metric, d, cap):
     X = wl.uniform(3001, d, 21) - 0.5
     Q = wl.uniform(257, d, 22) - 0.5
     if metric == 1:
@@ -86,7 +93,7 @@ def test_search_parity_metrics_and_ragged_dims(hn, ho, metric, d):
     _sync()
     ores = ho.search(oidx, Q, 7, 40)
     assert_search_parity(gi.cpu().numpy(), gd.cpu().numpy(), ores, X, Q, metric=metric,
-                         max_exempt=0.6)
+                         max_exempt=cap)
     idx.free()
 
 
@@ -108,6 +115,33 @@ def test_launch_shapes_give_identical_results(hn, cfg1):
                 assert np.array_equal(gi.cpu().numpy(), ref_i), (lpn, wpb, pers)
                 assert np.array_equal(gd.cpu().numpy().view(np.uint32),
                                       ref_d.view(np.uint32)), (lpn, wpb, pers)
+    idx.free()
+
+
+def test_concurrent_persistent_searches_on_two_streams(hn, cfg1):
+    """Persistent searches each take their own work counter: one large search
+    on one stream while 80 small ones run on another (more than any shared
+    pool of counters would hold) all equal the same searches run alone."""
+    import torch
+    X, Q, oidx = cfg1
+    idx = _import(hn, X, oidx)
+    Qd = to_dev(Q)
+    big_ref = hn.henn_search_batch(idx, Qd, k=10, ef=64, persistent=True)
+    small_ref = [hn.henn_search_batch(idx, Qd[j * 8:(j + 1) * 8], k=10, ef=32, persistent=True)
+                 for j in range(80)]
+    _sync()
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(sa):
+        big = hn.henn_search_batch(idx, Qd, k=10, ef=64, persistent=True, stream=sa)
+    with torch.cuda.stream(sb):
+        small = [hn.henn_search_batch(idx, Qd[j * 8:(j + 1) * 8], k=10, ef=32, persistent=True,
+                                      stream=sb) for j in range(80)]
+    torch.cuda.synchronize()
+    assert torch.equal(big[0], big_ref[0]) and torch.equal(big[1], big_ref[1])
+    for j in range(80):
+        assert torch.equal(small[j][0], small_ref[j][0]), j
+        assert torch.equal(small[j][1], small_ref[j][1]), j
     idx.free()
 
 
@@ -135,11 +169,15 @@ def test_mixed_k_ef_per_query_matches_uniform_calls(hn, ho, cfg1):
                                   k_max=10, ef_max=64)
     _sync()
     gi, gd = gi.cpu().numpy(), gd.cpu().numpy()
+    exempt = 0
     for kk, ee in {(int(a), int(b)) for a, b in zip(ks, efs)}:
         sel = np.where((ks == kk) & (efs == ee))[0]
         ores = ho.search(oidx, Qs[sel], kk, ee)
-        assert_search_parity(gi[sel, :kk], gd[sel, :kk], ores, X, Qs[sel], max_exempt=0.6)
+        exempt += int(assert_search_parity(gi[sel, :kk], gd[sel, :kk], ores, X, Qs[sel]).sum())
         assert (gi[sel, kk:] == -1).all() and np.isinf(gd[sel, kk:]).all()
+    # the oracle exempts 2 of these 240 queries
+    print(f"exempt {exempt} of 240")
+    assert exempt <= 3
     del torch
     idx.free()
 
@@ -150,7 +188,7 @@ def test_counters_match_oracle_on_exact_queries(hn, ho, cfg1):
     gi, gd, cnt = hn.henn_search_batch(idx, to_dev(Q[:200]), k=10, ef=32, with_counters=True)
     _sync()
     ores = ho.search(oidx, Q[:200], 10, 32)
-    ok = ~ho.near_tie(ores)
+    ok = ~exempt_mask(ores, X.shape[1])
     c = cnt.cpu().numpy()
     # expansions are exactly the oracle's; evaluations never fewer (the
     # visited table may forget) and equal when nothing was forgotten
@@ -245,16 +283,73 @@ def test_halving_layers_match_oracle(hn, ho, n, d, seed, eps, attempts):
     idx.free()
 
 
+def _ring_outcomes(ho, X, prev, layer, p, window, attempts, d):
+    """Per attempt and ring: 1 when the sample certainly hits the ring under
+    any FP32 ordering of the distances, 0 when it certainly misses, -1 when a
+    sample point near a window end leaves it open.  A point's rank among the
+    ring centre's distances is bounded by the points certainly below it (FP64
+    distance below its own by more than both FP32 errors) and those possibly
+    below it."""
+    s = len(prev)
+    Xl = X[prev].astype(np.float64)
+    E = exempt_tol(d) / 2.0                       # one distance's relative error, with allowance
+    lo_f, hi_f = (1 - E) / (1 + E), (1 + E) / (1 - E)
+    D = -(-s // 2 ** p.m)
+    cen = ho.draw_indices(p.seed, ho.TAG_RING_CENTRE, layer, 0, s, p.num_rings)
+    st = ho.draw_indices(p.seed, ho.TAG_RING_START, layer, 0, s - window + 1, p.num_rings)
+    samples = [np.unique(ho.draw_indices(p.seed, ho.TAG_SAMPLE, layer, t, s, D))
+               for t in range(attempts)]
+    out = np.zeros((attempts, p.num_rings), np.int8)
+    for j in range(p.num_rings):
+        dd = ((Xl - Xl[cen[j]]) ** 2).sum(1)
+        srt = np.sort(dd)
+        a = int(st[j])
+        for t, S in enumerate(samples):
+            certainly_below = np.searchsorted(srt, dd[S] * lo_f, side="left")
+            possibly_below = np.searchsorted(srt, dd[S] * hi_f, side="right") - 1
+            inside = (certainly_below >= a) & (possibly_below <= a + window - 1)
+            outside = (possibly_below < a) | (certainly_below > a + window - 1)
+            out[t, j] = 1 if inside.any() else (0 if outside.all() else -1)
+    return out
+
+
+@pytest.mark.parametrize("seed,status,attempts", [(4, "verified", 3), (6, "not_verified", 3)])
+def test_ring_check_at_400k_points_matches_oracle(hn, ho, seed, status, attempts):
+    """Layer 1 of 400,000 points: the ring check ranks 400,000 keys per ring
+    (the radix histogram's grid-stride loop runs more than once) with windows
+    of 49 points, so samples are redrawn (Alg. 2's repeat) or the attempt cap
+    keeps the best one.  Every attempt's outcome on every ring is first shown
+    to be independent of FP32 rounding at the window ends; then the GPU's
+    status, attempts, hits and member list equal the oracle's."""
+    n, d = 400_000, 8
+    X = wl.uniform(n, d, 90)
+    kw = dict(degree=8, seed=seed, eps_override=1.2e-4, max_layers=1, max_attempts=3)
+    p = ho.BuildParams(**kw)
+    olayers, oinfo = ho.build_layers(X, p)
+    info = oinfo[1]
+    assert (info.status, info.attempts) == (status, attempts)
+    rings = _ring_outcomes(ho, X, olayers[0], 1, p, info.window, info.attempts, d)
+    print(f"ring outcomes open to rounding: {int((rings < 0).sum())}; window margin "
+          f"{info.ring_margin:.3g}; hits per attempt {(rings == 1).sum(1).tolist()}")
+    assert (rings >= 0).all()
+    idx = hn.henn_build(to_dev(X), **kw)
+    gi = idx.layer_info(1)
+    assert (gi["status"], gi["attempts"], gi["hits"], gi["window"]) == (
+        info.status, info.attempts, info.hits, info.window)
+    assert np.array_equal(idx.export_layer(1)[0], olayers[1])
+    idx.free()
+
+
 def test_build_graph_matches_oracle(hn, ho, cfg1):
     X, Q, oidx = cfg1
     idx = hn.henn_build(to_dev(X), degree=16)
     for i, (ids, adj) in enumerate(_gpu_layers(idx)):
         oadj = oidx.adj[i]
         same = (adj == oadj).all(1)
-        tie = oidx.order_margin[i] <= 1e-5
+        tie = oidx.order_margin[i] <= exempt_tol(X.shape[1])
         assert (same | tie).all(), f"layer {i}: {np.where(~same & ~tie)[0][:5]}"
         # near-tie rows still hold the same neighbour set unless the R / R+1 cut is tied
-        cut_tie = oidx.adj_margin[i] <= 1e-5
+        cut_tie = oidx.adj_margin[i] <= exempt_tol(X.shape[1])
         for r in np.where(~same & ~cut_tie)[0]:
             assert set(adj[r].tolist()) == set(oadj[r].tolist())
     idx.free()
@@ -266,7 +361,8 @@ def test_end_to_end_cfg1(hn, ho, cfg1):
     gi, gd = hn.henn_search_batch(idx, to_dev(Q), k=10, ef=32)
     _sync()
     ores = ho.search(oidx, Q, 10, 32)
-    assert_search_parity(gi.cpu().numpy(), gd.cpu().numpy(), ores, X, Q)
+    assert_search_parity(gi.cpu().numpy(), gd.cpu().numpy(), ores, X, Q, max_exempt=0.041,
+                         graph_margins=True)
     idx.free()
 
 
@@ -286,8 +382,8 @@ def test_build_graph_matches_oracle_rows_larger(hn, ho, n, d, metric):
     for j, r in enumerate(rows):
         if np.array_equal(adj[r], oadj[j]):
             continue
-        assert order[j] <= 1e-5, f"row {r}: {adj[r]} vs {oadj[j]}"
-        if cut[j] > 1e-5:
+        assert order[j] <= exempt_tol(d), f"row {r}: {adj[r]} vs {oadj[j]}"
+        if cut[j] > exempt_tol(d):
             assert set(adj[r].tolist()) == set(oadj[j].tolist())
     info = idx.layer_info(0)
     print(f"fallback rows {info['fallback_rows']}")
@@ -313,7 +409,9 @@ def test_wide_rows_end_to_end(hn, ho, d, metric):
     gi, gd = hn.henn_search_batch(idx, to_dev(Q), k=10, ef=48)
     _sync()
     ores = ho.search(oidx, Q, 10, 48)
-    assert_search_parity(gi.cpu().numpy(), gd.cpu().numpy(), ores, X, Q, metric=metric)
+    # the oracle exempts 14.5% (d = 200) / 13.5% (d = 768) of these 200 queries
+    assert_search_parity(gi.cpu().numpy(), gd.cpu().numpy(), ores, X, Q, metric=metric,
+                         max_exempt=0.22 if d == 200 else 0.21)
     idx.free()
 
 
@@ -333,7 +431,7 @@ def test_search_parity_complete_root_and_sym_graph(hn, ho, cfg1_sym_root):
     gi, gd, cnt = hn.henn_search_batch(idx, to_dev(Q), k=10, ef=32, with_counters=True)
     _sync()
     ores = ho.search(oidx, Q, 10, 32)
-    ex = assert_search_parity(gi.cpu().numpy(), gd.cpu().numpy(), ores, X, Q)
+    ex = assert_search_parity(gi.cpu().numpy(), gd.cpu().numpy(), ores, X, Q, max_exempt=0.051)
     c = cnt.cpu().numpy()
     ok = ~ex
     assert np.array_equal(c[ok, 0], ores.counters[ok, 0])
@@ -359,10 +457,10 @@ def test_build_sym_graph_matches_oracle(hn, ho, cfg1_sym_root):
         ids, adj = idx.export_layer(i)
         assert np.array_equal(ids, oidx.members[i])
         same = (adj == oidx.adj[i]).all(1)
-        tie = oidx.order_margin[i] <= 3e-6
+        tie = oidx.order_margin[i] <= exempt_tol(X.shape[1])
         # a row may also move when a kNN row feeding it has a near tie at its cut
         kadj, _, kcut, _ = ho.knn_graph(X, 0, oidx.members[i], 16)
-        knn_tie_rows = np.where(kcut <= 3e-6)[0]
+        knn_tie_rows = np.where(kcut <= exempt_tol(X.shape[1]))[0]
         touched = set(knn_tie_rows.tolist())
         for r in knn_tie_rows:
             touched |= set(kadj[r].tolist())
@@ -371,7 +469,8 @@ def test_build_sym_graph_matches_oracle(hn, ho, cfg1_sym_root):
     gi, gd = hn.henn_search_batch(idx, to_dev(Q), k=10, ef=32)
     _sync()
     ores = ho.search(oidx, Q, 10, 32)
-    assert_search_parity(gi.cpu().numpy(), gd.cpu().numpy(), ores, X, Q)
+    assert_search_parity(gi.cpu().numpy(), gd.cpu().numpy(), ores, X, Q, max_exempt=0.051,
+                         graph_margins=True)
     idx.free()
 
 
@@ -514,7 +613,7 @@ def test_pruned_graphs_match_oracle(hn, ho, graph, metric):
         mb = oidx.members[i]
         cand, _, cut, order = ho.knn_graph(X, metric, mb, C)
         _, pm = ho.prune(X, metric, mb, cand, 12)
-        tie = np.minimum(np.minimum(cut, order), pm) <= STRICT
+        tie = np.minimum(np.minimum(cut, order), pm) <= exempt_tol(X.shape[1])
         if graph == 3:
             spread = tie.copy()
             for u in np.where(tie)[0]:
@@ -538,7 +637,7 @@ def test_pruned_sym_search_parity(hn, ho):
     gi, gd = hn.henn_search_batch(idx, to_dev(Q), k=10, ef=48)
     _sync()
     ores = ho.search(oidx, Q, 10, 48)
-    assert_search_parity(gi.cpu().numpy(), gd.cpu().numpy(), ores, X, Q)
+    assert_search_parity(gi.cpu().numpy(), gd.cpu().numpy(), ores, X, Q, max_exempt=0.087)
     idx.free()
 
 
@@ -564,32 +663,46 @@ def test_visited_tags_and_ids_give_the_same_results(hn, cfg1_sym_root, storage):
 
 # ---------------------------------------------------------------- NSW graphs
 
+def _explained_rows(got, ref, margin, lo, hi, tol):
+    """Rows of one NSW insertion batch that may differ between the GPU (got)
+    and the oracle (ref): a row decided by a near tie (its own search or merge,
+    margin <= tol), and a row that a near-tie new point links to in either
+    graph (its merge then takes or misses that point)."""
+    tie = margin <= tol
+    linked = np.zeros(len(margin), bool)
+    for p in np.where(tie[lo:hi])[0] + lo:
+        for row in (got[p], ref[p]):
+            linked[row[row >= 0]] = True
+    return tie | linked
+
+
 @pytest.mark.parametrize("metric,d", [(0, 16), (1, 20)])
 def test_nsw_insert_batch_matches_oracle(hn, ho, metric, d):
-    """One NSW insertion batch on the GPU against the oracle's batch from the
-    same graph state: every row either matches or was decided by a near tie."""
+    """Every NSW insertion batch of a layer, run on the GPU from the oracle's
+    graph state before it, against the oracle's batch: each differing row is
+    one the oracle recorded a near tie for, or linked to such a new point."""
     import torch
     s, R, M, ef = 3000, 8, 16, 32
     X = np.ascontiguousarray(wl.uniform(s, d, 31) - (0.5 if metric else 0.0), dtype=np.float32)
     mb = np.arange(s, dtype=np.int32)
     adj = np.full((s, M), -1, np.int32)
-    batches = list(ho.nsw_batches(s, 3))
-    check = {0, 1, 5, 12, len(batches) // 2, len(batches) - 1}
     Vd = to_dev(X)
-    tied = 0
-    for bi, (lo, hi) in enumerate(batches):
-        if bi in check:
-            g = torch.from_numpy(adj.copy()).to("cuda:0")
-            hn.henn_nsw_insert(Vd, g, lo, hi, R, ef, metric=metric)
-            got = g.cpu().numpy()
+    tol = exempt_tol(d)
+    tied = differ = 0
+    batches = list(ho.nsw_batches(s, 3))
+    for lo, hi in batches:
+        g = torch.from_numpy(adj.copy()).to("cuda:0")
+        hn.henn_nsw_insert(Vd, g, lo, hi, R, ef, metric=metric)
+        got = g.cpu().numpy()
         bm = np.full(s, np.inf)
         ho.nsw_insert(X, metric, mb, adj, bm, lo, hi, R, ef)
-        if bi in check:
-            diff = np.any(got != adj, axis=1)
-            tie = bm < 1e-5
-            assert not np.any(diff & ~tie), (bi, lo, hi, np.where(diff & ~tie)[0][:5])
-            assert np.all(got[hi:] == -1)
-            tied += int(tie.sum())
+        diff = np.any(got != adj, axis=1)
+        ok = _explained_rows(got, adj, bm, lo, hi, tol)
+        assert not np.any(diff & ~ok), (lo, hi, np.where(diff & ~ok)[0][:5])
+        assert np.all(got[hi:] == -1)
+        tied += int((bm <= tol).sum())
+        differ += int(diff.sum())
+    print(f"{len(batches)} batches: {tied} near-tie rows, {differ} rows differ")
     assert tied < 0.05 * s
 
 
@@ -651,6 +764,38 @@ def test_insert_matches_oracle(hn, ho, metric, root_max):
     rg = ho.recall_at_k(gi.cpu().numpy(), gt_d, Xa, Q, metric)
     ro = ho.recall_at_k(ores.ids, gt_d, Xa, Q, metric)
     assert rg > 0.8 and abs(rg - ro) < 0.02, (rg, ro)
+    idx.free()
+
+
+@pytest.mark.parametrize("metric", [0, 1])
+def test_insert_rows_attributed_on_imported_index(hn, ho, metric):
+    """Insert(x) into the oracle's own NSW hierarchy, imported into the library:
+    with insert_shift 0 each layer takes its new points in one insertion
+    batch, so every row that differs from the oracle's insertion is decided by
+    a near tie of that batch or linked to such a new point."""
+    sh = 0.5 if metric else 0.0
+    X = np.ascontiguousarray(wl.uniform(5000, 24, 54) - sh, dtype=np.float32)
+    Xn = np.ascontiguousarray(wl.uniform(800, 24, 55) - sh, dtype=np.float32)
+    p = dict(degree=8, max_degree=16, graph=4, ef_construction=48, seed=6, metric=metric,
+             insert_shift=0)
+    bp = ho.BuildParams(**p)
+    built = ho.build_index(X, bp)
+    base = ho.index_from_arrays(X, metric, built.members, built.adj)
+    base.order_margin = [np.full(len(m), np.inf) for m in built.members]
+    base.info = built.info
+    grown = ho.insert(base, Xn, bp)
+    idx = hn.henn_import(to_dev(X), built.members, built.adj, **p)
+    hn.henn_insert(idx, to_dev(Xn))
+    tol = exempt_tol(24)
+    for i, (ids, adj) in enumerate(_gpu_layers(idx)):
+        assert np.array_equal(ids, grown.members[i]), f"layer {i}"
+        lo, hi = len(built.members[i]), len(ids)
+        assert hi - lo <= max(1, lo), "one batch per layer"
+        diff = np.any(adj != grown.adj[i], axis=1)
+        ok = _explained_rows(adj, grown.adj[i], grown.order_margin[i], lo, hi, tol)
+        assert not np.any(diff & ~ok), (i, np.where(diff & ~ok)[0][:5])
+        print(f"layer {i}: {hi - lo} new, {int(diff.sum())} rows differ, "
+              f"{int((grown.order_margin[i] <= tol).sum())} near-tie rows")
     idx.free()
 
 
@@ -742,6 +887,35 @@ def test_delete_redraws_thinned_layers_and_insert_continues(hn, ho):
     idx = _delete_case(hn, ho, X, Q, p, gone, then_insert=wl.uniform(2000, 16, 75))
     ids0 = idx.export_layer(0)[0]
     assert ids0[-1] == 7999 and len(ids0) == 8000 - len(gone)
+    idx.free()
+
+
+@pytest.mark.parametrize("metric", [0, 1])
+def test_delete_rows_attributed_on_imported_index(hn, ho, metric):
+    """Delete(x) on the oracle's own NSW hierarchy, imported into the library:
+    the repair reads the same graph on both sides, so every repaired row equals
+    the oracle's unless the oracle recorded a near tie in its sorted list."""
+    sh = 0.5 if metric else 0.0
+    X = np.ascontiguousarray(wl.uniform(6000, 24, 81) - sh, dtype=np.float32)
+    p = dict(degree=8, max_degree=16, graph=4, ef_construction=48, seed=2, metric=metric)
+    bp = ho.BuildParams(**p)
+    built = ho.build_index(X, bp)
+    base = ho.index_from_arrays(X, metric, built.members, built.adj)
+    base.order_margin = [np.full(len(m), np.inf) for m in built.members]
+    base.info = built.info
+    gone = np.random.default_rng(10).choice(6000, 1500, replace=False).astype(np.int32)
+    out = ho.delete(base, gone, bp)
+    idx = hn.henn_import(to_dev(X), built.members, built.adj, **p)
+    hn.henn_delete(idx, gone)
+    layers = _gpu_layers(idx)
+    assert len(layers) == out.num_layers == built.num_layers   # no layer is redrawn here
+    tol = exempt_tol(24)
+    for i, (ids, adj) in enumerate(layers):
+        assert np.array_equal(ids, out.members[i]), f"layer {i}"
+        diff = np.any(adj != out.adj[i], axis=1)
+        tie = out.order_margin[i] <= tol
+        assert not np.any(diff & ~tie), (i, np.where(diff & ~tie)[0][:5])
+        print(f"layer {i}: {int(diff.sum())} rows differ, {int(tie.sum())} near-tie rows")
     idx.free()
 
 

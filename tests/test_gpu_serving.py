@@ -141,3 +141,41 @@ def test_serving_and_captured_graph_after_updates(storage):
         assert np.array_equal(g.ids.cpu().numpy(), ref_i)
     g.free()
     idx.free()
+
+
+def test_upper_layer_beam_wider_than_the_request_list():
+    """A server whose beam above layer 0 (ef_upper = 16) is wider than a
+    request's own list (k = 1, ef = 8): each request's state holds the wider
+    list, and the result alone, in a mix and in the batched search agree."""
+    import torch
+
+    import paper_2505_17368_amd as hn
+    X, Q = wl.make("uniform_10k_d32")
+    idx = hn.henn_build(to_dev(X), degree=16, graph=1, max_degree=32)
+    assert idx.num_layers >= 3             # greedy layers above layer 0
+    Qs = Q[:48]
+    ref_i, ref_d = hn.henn_search_batch(idx, to_dev(Qs), k=1, ef=8, k_max=10, ef_max=64,
+                                        ef_upper=16, vis_bits=10)
+    torch.cuda.synchronize()
+    ref_i, ref_d = ref_i.cpu().numpy(), ref_d.cpu().numpy()
+    kw = dict(k_max=10, ef_max=64, ef_upper=16, steps_per_tick=3, vis_bits=10)
+    for j in (0, 5):
+        srv = hn.Server(idx, max_slots=4, **kw)
+        srv.submit(Qs[j], 1, 8, j)
+        got = _drain(srv, 1)
+        srv.close()
+        assert np.array_equal(got[j][0], ref_i[j]), j
+        assert np.array_equal(got[j][1].view(np.uint32), ref_d[j].view(np.uint32)), j
+    srv = hn.Server(idx, max_slots=32, **kw)
+    efs = [8, 64, 8, 32]
+    ks = [1, 10, 1, 5]
+    for j in range(len(Qs)):
+        srv.submit(Qs[j], ks[j % 4], efs[j % 4], j)
+    got = _drain(srv, len(Qs))
+    srv.close()
+    for j in range(len(Qs)):
+        if ks[j % 4] != 1 or efs[j % 4] != 8:
+            continue
+        assert np.array_equal(got[j][0], ref_i[j]), j
+        assert np.array_equal(got[j][1].view(np.uint32), ref_d[j].view(np.uint32)), j
+    idx.free()
