@@ -214,6 +214,22 @@ henn_status henn_search_batch(const henn_index *idx, const float *Q, int64_t nq,
                               const henn_search_params *sp, int32_t *out_ids, float *out_dist,
                               void *hip_stream);
 
+/* henn_search_batch for callers that cannot allocate device memory: code
+ * under hipGraph capture, tight serving loops, harnesses that forbid
+ * allocation.  Same arguments, results and stream semantics as
+ * henn_search_batch (sp->workspace is ignored); the scratch the search
+ * needs (the persistent work counter and the complete-root scan's keys,
+ * henn_search_workspace_size bytes) comes from a fixed 32 MiB device array
+ * that the library holds once per GPU until the process ends, so the call
+ * makes no allocation at all.  HENN_E_INVAL when the search needs more
+ * scratch than that (e.g. more than ~240,000 queries on a complete root of
+ * a few thousand points).  Every call on one GPU shares its array: calls
+ * whose work overlaps on that GPU (several streams, or host threads) race
+ * and must be serialised by the caller; calls in one stream are safe. */
+henn_status henn_search_batch_noalloc(const henn_index *idx, const float *Q, int64_t nq,
+                                      const henn_search_params *sp, int32_t *out_ids,
+                                      float *out_dist, void *hip_stream);
+
 /* Autotuner for the batched search.  Times candidate launch shapes (lanes
  * cooperating on one neighbour vector, waves per workgroup, visited-table
  * size in LDS, one-shot vs persistent launch) on the given queries with the

@@ -13,8 +13,8 @@
 #include <string.h>
 
 #include <algorithm>
-#include <atomic>
 #include <cstdlib>
+#include <mutex>
 #include <new>
 #include <stdexcept>
 #include <string>
@@ -1175,6 +1175,42 @@ henn_status henn_search_batch(const henn_index* idx, const float* Q, int64_t nq,
                               void* hip_stream) {
   return search_impl(idx, Q, nq, sp, out_ids, out_dist, static_cast<hipStream_t>(hip_stream),
                      nullptr, 0);
+}
+
+}  // extern "C"
+
+// Scratch of henn_search_batch_noalloc: a fixed device array (one copy per
+// GPU, held until the process ends).  Host code never passes the array's
+// name to a kernel: it takes the device address from hipGetSymbolAddress,
+// once per device, with that device current.
+static constexpr int64_t kNoAllocScratchBytes = 32ll << 20;
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+static std::mutex g_scratch_mu;
+static char* g_scratch_ptr[64] = {};
+
+extern "C" {
+
+henn_status henn_search_batch_noalloc(const henn_index* idx, const float* Q, int64_t nq,
+                                      const henn_search_params* sp, int32_t* out_ids,
+                                      float* out_dist, void* hip_stream) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(HENN_E_DEVICE, "hipGetDevice failed");
+  if (dev < 0 || dev >= 64) return fail(HENN_E_UNSUPPORTED, "device id above 63");
+  char* ptr = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+      void* p = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !p)
+        return fail(HENN_E_DEVICE, std::string("hipGetSymbolAddress of the scratch array: ") +
+                                       hipGetErrorString(e));
+      g_scratch_ptr[dev] = static_cast<char*>(p);
+    }
+    ptr = g_scratch_ptr[dev];
+  }
+  return search_impl(idx, Q, nq, sp, out_ids, out_dist, static_cast<hipStream_t>(hip_stream),
+                     ptr, kNoAllocScratchBytes);
 }
 
 henn_status henn_autotune(henn_index* idx, const float* Q, int64_t nq,

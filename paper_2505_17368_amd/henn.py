@@ -108,6 +108,8 @@ def load_library(path: str = LIB_PATH):
     lib.henn_default_search_params.argtypes = [P(SearchParams)]
     lib.henn_build.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, P(BuildParams), vp, P(vp)]
     lib.henn_search_batch.argtypes = [vp, vp, ctypes.c_int64, P(SearchParams), vp, vp, vp]
+    lib.henn_search_batch_noalloc.argtypes = [vp, vp, ctypes.c_int64, P(SearchParams), vp, vp,
+                                              vp]
     lib.henn_free.argtypes = [vp]
     lib.henn_free.restype = None
     lib.henn_index_shape.argtypes = [vp, P(ctypes.c_int32), P(ctypes.c_int64), P(ctypes.c_int32)]
@@ -138,7 +140,8 @@ def load_library(path: str = LIB_PATH):
                                     ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
                                     ctypes.c_int32, vp]
     for name in ("henn_default_build_params", "henn_default_search_params", "henn_build",
-                 "henn_search_batch", "henn_index_shape", "henn_layer_info_get",
+                 "henn_search_batch", "henn_search_batch_noalloc", "henn_index_shape",
+                 "henn_layer_info_get",
                  "henn_export_layer", "henn_import", "henn_autotune",
                  "henn_search_workspace_size", "henn_search_graph_create",
                  "henn_search_graph_launch", "henn_default_server_params", "henn_server_create",
@@ -357,8 +360,10 @@ def henn_search_batch(index: HennIndex, Q, k=10, ef=32, k_arr=None, ef_arr=None,
                       ef_max=None, ef_upper=1, rerank_factor=4, with_counters=False,
                       persistent=False, lanes_per_vec=0, waves_per_block=0, root_kernel=True,
                       events=None, vis_bits=0, out_ids=None, out_dist=None, stream=None,
-                      vis32=False, vis16=False):
+                      vis32=False, vis16=False, noalloc=False):
     """Enqueues a batched search; returns (ids, dist[, counters]) device tensors.
+    ``noalloc``: call henn_search_batch_noalloc (the library's fixed scratch;
+    pass out_ids / out_dist to keep the call free of allocations here too).
 
     ``events``: optional pair of recorded torch.cuda.Event (enable_timing) that
     the library re-records around the main search kernel."""
@@ -376,10 +381,11 @@ def henn_search_batch(index: HennIndex, Q, k=10, ef=32, k_arr=None, ef_arr=None,
     sp = search_params(k, ef, k_arr, ef_arr, kmax, ef_max, ef_upper, rerank_factor, counters,
                        persistent, lanes_per_vec, waves_per_block, root_kernel, events,
                        vis_bits, vis32, vis16)
-    _check(load_library().henn_search_batch(index.handle, ctypes.c_void_p(Q.data_ptr()), nq,
-                                            ctypes.byref(sp), ctypes.c_void_p(out_ids.data_ptr()),
-                                            ctypes.c_void_p(out_dist.data_ptr()),
-                                            _stream_ptr(stream)))
+    entry = load_library().henn_search_batch_noalloc if noalloc else \
+        load_library().henn_search_batch
+    _check(entry(index.handle, ctypes.c_void_p(Q.data_ptr()), nq, ctypes.byref(sp),
+                 ctypes.c_void_p(out_ids.data_ptr()), ctypes.c_void_p(out_dist.data_ptr()),
+                 _stream_ptr(stream)))
     if with_counters:
         return out_ids, out_dist, counters
     return out_ids, out_dist
