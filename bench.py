@@ -7,9 +7,12 @@ width for the FP32 form and the BF16 / FP8 forms (FP32 re-rank of 4k
 candidates), pick for every form the smallest beam width whose Recall@10
 reaches 0.95, and time exactly --steps batched searches of the best form.
 
-Prints ONE JSON line (rank 0, N = 1).  Recall is measured against the FP64
-brute force of the oracle on a sample of the queries; the same CPU leg times
-the oracle's own search on the host cores (the cpu_baseline object).
+Prints ONE JSON line (rank 0, N = 1).  Recall is measured against the exact
+FP64 k-NN of every query (the oracle's matrix-product route); the same CPU leg
+times the oracle's own search on the host cores (the cpu_baseline object).
+The default run also measures the adversarial-layout workload (1M x 96 points
+on a curve with exponentially shrinking gaps, BF16 rows, FP32 re-rank of 4k)
+as an extra key.
 """
 from __future__ import annotations
 
@@ -40,9 +43,12 @@ def parse():
     ap.add_argument("--n", type=int, default=None, help="fewer points (smoke runs)")
     ap.add_argument("--nq", type=int, default=None)
     ap.add_argument("--k", type=int, default=10)
-    ap.add_argument("--efs", default="64,72,80,84,88,92,96,104,112,128,160,192")
+    ap.add_argument("--efs", default="16,24,32,48,64,72,80,84,88,92,96,104,112,128,160,192,256")
     ap.add_argument("--forms", default="f32,bf16,fp8")
-    ap.add_argument("--gt-sample", type=int, default=1000)
+    ap.add_argument("--gt-sample", type=int, default=0,
+                    help="queries with exact ground truth (0 = all)")
+    ap.add_argument("--no-adversarial", action="store_true",
+                    help="skip the 1M x 96 adversarial-layout measurement")
     ap.add_argument("--target-recall", type=float, default=0.95)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--graph", default="knn_sym")
@@ -90,6 +96,43 @@ def _cpu_model() -> str:
     except OSError:
         pass
     return "unknown"
+
+
+def cpu_threads():
+    """Threads of the CPU legs: the process's affinity mask, at most 16 (the
+    host's CPU share per GPU).  Returns (threads, affinity size, nproc)."""
+    try:
+        aff = len(os.sched_getaffinity(0))
+    except AttributeError:
+        aff = os.cpu_count() or 1
+    return max(1, min(aff, 16)), aff, os.cpu_count() or aff
+
+
+def quality(ids, dist, gt_dist, X, Q, sample, metric):
+    """Per-query tie-tolerant Recall@k on the sampled queries (a returned id
+    counts when its FP64 distance is at most the true k-th; the sums run in a
+    different order than the oracle's, so 1e-9 relative is allowed), and the
+    returned distances' error against FP64 recomputation: max / mean relative
+    error and the mean ratio of the j-th returned FP64 distance to the true
+    j-th (L2; 1 = exact)."""
+    k = gt_dist.shape[1]
+    I = ids[sample][:, :k]
+    ok = I >= 0
+    xs = X[np.maximum(I, 0)].astype(np.float64)
+    qv = Q[sample].astype(np.float64)[:, None, :]
+    dd = ((xs - qv) ** 2).sum(-1) if metric == 0 else -(xs * qv).sum(-1)
+    kth = gt_dist[:, k - 1][:, None]
+    hit = ok & (dd <= kth + 1e-9 * np.abs(kth))
+    per_q = hit.sum(1) / float(k)
+    rec = float(per_q.mean())
+    ci = float(1.96 * per_q.std(ddof=1) / np.sqrt(len(per_q))) if len(per_q) > 1 else None
+    dsel = dist[sample][:, :k].astype(np.float64)
+    err = np.abs(dsel - dd)[ok] / np.maximum(np.abs(dd[ok]), 1e-30)
+    ratio = (dd / np.maximum(gt_dist, 1e-30))[ok] if metric == 0 else None
+    return {"recall": rec, "recall_ci95": ci,
+            "max_rel_err": float(err.max()) if err.size else 0.0,
+            "mean_rel_err": float(err.mean()) if err.size else 0.0,
+            "mean_dist_ratio": float(ratio.mean()) if ratio is not None and ratio.size else None}
 
 
 def calib_copy():
@@ -203,13 +246,16 @@ def main():
         build_s[f] = build_s["f32"] + time.time() - t
     layers_info = [base.layer_info(i) for i in range(base.num_layers)]
 
-    # ---- CPU leg: FP64 oracle ground truth on a sample + oracle search timing --
+    # ---- CPU leg: exact FP64 ground truth of the queries ----
     from oracle import henn_oracle as ho
+    threads, affinity, nproc = cpu_threads()
     rng = np.random.default_rng(123)
-    sample = np.sort(rng.choice(nq, min(args.gt_sample, nq), replace=False))
+    sample = (np.arange(nq) if args.gt_sample <= 0 or args.gt_sample >= nq
+              else np.sort(rng.choice(nq, args.gt_sample, replace=False)))
     t = time.time()
-    gt_ids, gt_dist = ho.brute_force_knn(X, Q[sample], k, metric)
-    log(f"oracle ground truth for {len(sample)} queries in {time.time() - t:.1f}s")
+    gt_ids, gt_dist = ho.brute_force_knn_gram(X, Q[sample], k, metric, threads=threads)
+    log(f"oracle ground truth for {len(sample)} queries in {time.time() - t:.1f}s "
+        f"({threads} threads)")
 
     def dist_rows(qi, ids):
         ok = ids >= 0
@@ -226,15 +272,15 @@ def main():
         lp, wp, vb, ps = (int(x) for x in args.shape.split(","))
         fixed = {"lanes_per_vec": lp, "waves_per_block": wp, "vis_bits": vb, "persistent": bool(ps)}
 
-    def run(idx, ef, persistent=False, events=None):
+    def run(idx, ef, persistent=False, events=None, **kw):
         if fixed is not None:
             return hn.henn_search_batch(idx, Qd, k=k, ef=ef, k_max=k, ef_max=ef, events=events,
                                         lanes_per_vec=fixed["lanes_per_vec"],
                                         waves_per_block=fixed["waves_per_block"],
                                         vis_bits=fixed["vis_bits"],
-                                        persistent=fixed["persistent"])
+                                        persistent=fixed["persistent"], **kw)
         return hn.henn_search_batch(idx, Qd, k=k, ef=ef, k_max=k, ef_max=ef,
-                                    persistent=persistent, events=events)
+                                    persistent=persistent, events=events, **kw)
 
     def time_launches(idx, ef, reps, persistent=False):
         for _ in range(2):
@@ -266,9 +312,8 @@ def main():
                 indexes[f], calib, k=k, ef=ef)
             ids, dist = run(indexes[f], ef)
             torch.cuda.synchronize()
-            ids_h = ids.cpu().numpy()
-            rec = recall_of(ids_h, gt_dist, dist_rows, sample)
-            derr = distance_error(ids_h, dist.cpu().numpy(), gt_dist, dist_rows, sample)
+            qual = quality(ids.cpu().numpy(), dist.cpu().numpy(), gt_dist, X, Q, sample, metric)
+            rec = qual["recall"]
             if fixed is not None:
                 ts = time_launches(indexes[f], ef, 5)
                 best, pers = float(np.median(ts)), fixed["persistent"]
@@ -278,14 +323,16 @@ def main():
                 best = min(float(np.median(ts)), float(np.median(tp)))
                 pers = float(np.median(tp)) < float(np.median(ts))
             qps = nq / (best / 1e3)
-            sweep[f].append({"ef": ef, "recall": round(rec, 4), "ms": round(best, 3),
+            sweep[f].append({"ef": ef, "recall": round(rec, 4),
+                             "recall_ci95": round(qual["recall_ci95"], 4),
+                             "ms": round(best, 3),
                              "qps": round(qps, 1), "persistent": pers,
                              "shape": tuned[(f, ef)],
-                             "max_rel_dist_err": round(derr["max_rel_err"], 9),
-                             "mean_dist_ratio": round(derr["mean_dist_ratio"], 6)
-                             if derr["mean_dist_ratio"] is not None else None})
-            log(f"{f} ef={ef}: recall {rec:.4f}  {best:.3f} ms  {qps:,.0f} QPS "
-                f"(persistent {pers})")
+                             "max_rel_dist_err": round(qual["max_rel_err"], 9),
+                             "mean_dist_ratio": round(qual["mean_dist_ratio"], 6)
+                             if qual["mean_dist_ratio"] is not None else None})
+            log(f"{f} ef={ef}: recall {rec:.4f} +- {qual['recall_ci95']:.4f}  {best:.3f} ms  "
+                f"{qps:,.0f} QPS (persistent {pers})")
             if rec >= args.target_recall and f not in chosen:
                 chosen[f] = sweep[f][-1]
         if f not in chosen:
@@ -313,7 +360,6 @@ def main():
         adj_l = [e[1] for e in exported]
         oidx = ho.index_from_arrays(X, metric, ids_l, adj_l,
                                     root_complete=args.root_max > 0 and len(ids_l) >= 2)
-        threads = ho.default_threads()
         # grow the sample until the oracle has worked ~cpu_seconds
         m = min(nq, 256)
         done, el = 0, 0.0
@@ -329,25 +375,44 @@ def main():
                 break
             m = min(nq, m * 2)
         oracle_counts = np.concatenate(counts).astype(np.float64)
-        # one thread, on the first 1,000 queries
+        # one thread, query by query, on the first 1,000 queries
         n1 = min(nq, 1000)
+        lat = np.empty(n1)
         t = time.time()
-        ho.search(oidx, Q[:n1], k, ef, 1, threads=1)
+        for i in range(n1):
+            t0 = time.perf_counter()
+            ho.search(oidx, Q[i:i + 1], k, ef, 1, threads=1)
+            lat[i] = time.perf_counter() - t0
         el1 = time.time() - t
         cpu = {"value": round(done / el, 2), "unit": "queries/s", "cores": threads,
                "kind": "oracle",
                "sample": f"{done} oracle searches over the {nq} workload queries taken in "
                          f"order and repeated (same index, ef={ef}, "
                          f"k={k}), FP64 C oracle, {threads} threads, {el:.1f}s",
+               "nproc": nproc, "affinity_cpus": affinity,
+               "threads_note": "threads = the affinity mask, at most 16 (the host's CPU "
+                               "share per GPU)",
                "value_1_thread": round(n1 / el1, 2),
-               "sample_1_thread": f"the first {n1} queries on one thread, {el1:.1f}s",
+               "sample_1_thread": f"the first {n1} queries on one thread, one call each, "
+                                  f"{el1:.1f}s",
+               "latency_1_thread_ms": {"p50": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                                       "p99": round(float(np.percentile(lat, 99)) * 1e3, 3),
+                                       "max": round(float(lat.max()) * 1e3, 3),
+                                       "note": "per call, including the binding's overhead"},
                "cpu_model": _cpu_model()}
         log(f"cpu baseline {cpu['value']} QPS on {threads} threads, "
             f"{cpu['value_1_thread']} QPS on one")
 
     # ---- timed region: exactly --steps batched searches ----
+    # a workspace and the outputs are allocated once, outside the timed region
+    wsb = hn.workspace_size(idx, nq, k=k, ef=ef, k_max=k, ef_max=ef,
+                            persistent=pers if fixed is None else fixed["persistent"])
+    wsp = torch.empty(max(wsb, 256), dtype=torch.uint8, device=dev)
+    o_ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
+    o_dist = torch.empty((nq, k), dtype=torch.float32, device=dev)
+    tkw = dict(workspace=wsp, out_ids=o_ids, out_dist=o_dist)
     for _ in range(args.warmup):
-        run(idx, ef, pers)
+        run(idx, ef, pers, **tkw)
     torch.cuda.synchronize()
     st = torch.cuda.current_stream()
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -361,7 +426,7 @@ def main():
     t_start = time.perf_counter()
     for (e0, e1), ke in zip(evs, kev):
         e0.record(st)
-        run(idx, ef, pers, events=ke)
+        run(idx, ef, pers, events=ke, **tkw)
         e1.record(st)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
@@ -369,14 +434,16 @@ def main():
     search_ms = np.array([a_.elapsed_time(b_) for a_, b_ in kev])
     ms_per_step = wall * 1e3 / args.steps
     value = nq * args.steps / wall
+    timed_ok = quality(o_ids.cpu().numpy(), o_dist.cpu().numpy(), gt_dist, X, Q, sample,
+                       metric)["recall"]
 
     # ---- roofline of the search kernel (HBM bound, algorithmic bytes) ----
     b = {"f32": 4, "bf16": 2, "fp8": 1}[head_form]
     bs = 4 if head_form == "fp8" else 0
     src = oracle_counts if oracle_counts is not None else cnt
-    # the root's exhaustive scan runs in its own kernel (k_root_scan); the
-    # roofline is that of the dominant kernel, k_search: the layers below the
-    # root, each evaluation a row gather, each expansion an adjacency row
+    # the root's exhaustive scan runs in its own kernels; the roofline is that
+    # of the dominant kernel, k_search: the layers below the root, each
+    # evaluation a row gather, each expansion an adjacency row
     root_n = layers_info[-1]["size"] if args.root_max > 0 and len(layers_info) >= 2 else 0
     evals = src[:, 1].mean() - root_n
     exps = src[:, 0].mean()
@@ -406,6 +473,8 @@ def main():
                 "kernel_ms": round(kernel_ms, 4),
                 "count_source": "oracle" if oracle_counts is not None else "gpu"}
 
+    dtype_of = {"f32": "f32", "bf16": "bf16 storage, f32 accumulate",
+                "fp8": "fp8_e4m3 storage, f16 difference, f32 accumulate"}
     out = {
         "metric": "QPS at recall@10>=0.95, n=1M d=128; BF16/FP8 vs FP32 form; p99 ms",
         "value": round(value, 1),
@@ -417,7 +486,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": dtype_of[head_form],
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "d": d, "nq": nq, "k": k, "ef": ef,
                    "form": head_form, "storage": head_form, "persistent": pers,
@@ -427,6 +496,9 @@ def main():
                        "insert_shift": args.insert_shift} if args.graph == "nsw" else {}),
                    "root_complete_max": args.root_max, "metric": w["metric"]},
         "recall_at_10": head["recall"],
+        "recall_ci95": head["recall_ci95"],
+        "recall_queries": int(len(sample)),
+        "recall_timed_run": round(timed_ok, 4),
         "p50_ms": round(float(np.percentile(kms, 50)), 4),
         "p99_ms": round(float(np.percentile(kms, 99)), 4),
         "forms": {f: {**chosen[f], "build_s": round(build_s[f], 2)} for f in forms},
@@ -444,7 +516,104 @@ def main():
     for f in forms:
         indexes[f].free()
     base.free()
+    if not args.no_adversarial and args.workload == "gmm100_1M_d128" and args.n is None:
+        out["adversarial"] = adversarial_experiment(hn, args, threads)
     print(json.dumps(out), flush=True)
+
+
+def adversarial_experiment(hn, args, threads, wname="curve_1M_d96", storage="bf16"):
+    """The adversarial-layout workload: 1M x 96 points along a curve whose
+    gaps shrink as 0.5^(i mod 40) (Sec. 4.2's skewed regime), 10,000 queries
+    near the dense end of random periods; BF16 traversal rows and an FP32
+    re-rank of 4k = 40 candidates, k = 10.  The smallest swept beam width
+    whose Recall@10 (all queries, exact FP64 ground truth) reaches the target
+    is timed; the roofline of k_search uses the oracle's exact-visited counts
+    on 500 of the queries."""
+    import torch
+    import workloads as wl
+    from oracle import henn_oracle as ho
+    dev = torch.device("cuda:0")
+    k = 10
+    X, Q = wl.make(wname)
+    n, d = X.shape
+    nq = Q.shape[0]
+    Xd = torch.from_numpy(X).to(dev)
+    Qd = torch.from_numpy(Q).to(dev)
+    bp = dict(degree=args.degree, metric=0, graph=hn.GRAPH[args.graph],
+              max_degree=args.max_degree, root_complete_max=args.root_max)
+    torch.cuda.synchronize()
+    t = time.time()
+    base = hn.henn_build(Xd, storage=0, **bp)
+    torch.cuda.synchronize()
+    build_s = time.time() - t
+    ex = [base.export_layer(i) for i in range(base.num_layers)]
+    sizes = [len(e[0]) for e in ex]
+    st_code = {"f32": 0, "bf16": 1, "fp8": 2}[storage]
+    idx = hn.henn_import(Xd, [e[0] for e in ex], [e[1] for e in ex], storage=st_code, **bp)
+    t = time.time()
+    sample = np.arange(nq)
+    _, gt_dist = ho.brute_force_knn_gram(X, Q, k, 0, threads=threads)
+    log(f"adversarial: build {build_s:.1f}s, layers {sizes}, ground truth "
+        f"{time.time() - t:.1f}s")
+    sweep, pick = [], None
+    for ef in [int(e) for e in args.efs.split(",")]:
+        hn.henn_autotune(idx, Qd, k=k, ef=ef)
+        ids, dist = hn.henn_search_batch(idx, Qd, k=k, ef=ef)
+        torch.cuda.synchronize()
+        qual = quality(ids.cpu().numpy(), dist.cpu().numpy(), gt_dist, X, Q, sample, 0)
+        sweep.append({"ef": ef, "recall": round(qual["recall"], 4)})
+        log(f"adversarial ef={ef}: recall {qual['recall']:.4f}")
+        if qual["recall"] >= args.target_recall:
+            pick = (ef, qual)
+            break
+    if pick is None:
+        idx.free()
+        base.free()
+        return {"workload": wname, "sweep": sweep, "reached_target": False}
+    ef, qual = pick
+    st = torch.cuda.current_stream()
+    for _ in range(3):
+        hn.henn_search_batch(idx, Qd, k=k, ef=ef)
+    torch.cuda.synchronize()
+    ts, ks = [], []
+    for _ in range(20):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        k0, k1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        k0.record(st)
+        k1.record(st)
+        e0.record(st)
+        hn.henn_search_batch(idx, Qd, k=k, ef=ef, events=(k0, k1))
+        e1.record(st)
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+        ks.append(k0.elapsed_time(k1))
+    ms, kms = float(np.median(ts)), float(np.mean(ks))
+    oidx = ho.index_from_arrays(X, 0, [e[0] for e in ex], [e[1] for e in ex],
+                                root_complete=args.root_max > 0 and len(ex) >= 2)
+    r = ho.search(oidx, Q[:500], k, ef, 1, threads=threads)
+    root_n = sizes[-1] if args.root_max > 0 and len(sizes) >= 2 else 0
+    evals = r.counters[:, 1].mean() - root_n
+    exps = r.counters[:, 0].mean()
+    deg = ex[0][1].shape[1]
+    bytes_q = evals * d * 2 + exps * deg * 4 + min(ef, 4 * k) * d * 4 + d * 4 + k * 8
+    achieved = bytes_q * nq / (kms / 1e3) / 1e9
+    idx.free()
+    base.free()
+    return {"workload": wname, "n": n, "d": d, "nq": nq, "k": k, "storage": storage,
+            "dtype": "bf16 storage, f32 accumulate", "rerank": 4 * k, "ef": ef,
+            "recall_at_10": round(qual["recall"], 4), "recall_ci95": round(qual["recall_ci95"], 4),
+            "qps": round(nq / (ms / 1e3), 1), "ms_per_batch": round(ms, 4),
+            "max_rel_dist_err": round(qual["max_rel_err"], 9),
+            "mean_dist_ratio": round(qual["mean_dist_ratio"], 6),
+            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                         "kernel": "k_search", "kernel_ms": round(kms, 4),
+                         "bytes_per_query": round(bytes_q, 1),
+                         "evals_per_query": round(evals, 1),
+                         "expansions_per_query": round(exps, 1), "count_source": "oracle"},
+            "build_s": round(build_s, 2), "layers": sizes, "sweep": sweep,
+            "graph": args.graph, "degree": args.degree, "max_degree": args.max_degree,
+            "root_complete_max": args.root_max}
 
 
 def serving_experiment(hn, idx, Q, gt_dist, dist_rows, sample, args, k_choices=(10, 50),

@@ -46,8 +46,11 @@ typedef enum {
 typedef enum { HENN_L2 = 0, HENN_IP = 1 } henn_metric;
 
 /* Storage of the vectors the search traverses.  F32 is the plain path.
- * BF16 and FP8_E4M3 (OCP, max 448) keep one FP32 scale per vector, compute
- * distances in FP32, and keep an FP32 copy for the final re-rank. */
+ * BF16 and FP8_E4M3 (OCP, max 448) keep one FP32 scale per vector and an
+ * FP32 copy for the final re-rank.  BF16 traversal distances are FP32 sums;
+ * FP8 traversal forms q - s*c in f16 (query rounded to f16, codes scaled by
+ * the converter) and accumulates the squares (or q*c for inner product) in
+ * FP32. */
 typedef enum { HENN_F32 = 0, HENN_BF16 = 1, HENN_FP8_E4M3 = 2 } henn_storage;
 
 /* Navigable graph per layer (App. B.2): exact kNN, or kNN plus reverse
@@ -207,7 +210,8 @@ henn_status henn_build(const float *X, int64_t n, int32_t d, const henn_build_pa
  *   out_ids: device int32 [nq][k_max]; out_dist: device float [nq][k_max].
  *   Row i holds the first k_i results in ascending (distance, id) order,
  *   padded with id -1 and distance +inf (also when fewer than k_i points are
- *   reachable).  nq = 0 is a no-op.  Enqueued on hip_stream; results are
+ *   reachable).  HENN_E_UNSUPPORTED when n * ceil(d / 8) >= 2^32 (rows are
+ *   addressed by a 32-bit chunk index).  nq = 0 is a no-op.  Enqueued on hip_stream; results are
  *   valid once the stream has reached this point.  The index is read-only;
  *   concurrent searches on several streams are safe. */
 henn_status henn_search_batch(const henn_index *idx, const float *Q, int64_t nq,

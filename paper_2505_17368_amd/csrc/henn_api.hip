@@ -270,6 +270,8 @@ static void refresh_root(henn_index* ix, hipStream_t st) {
   if (r.dec_owned) (void)hipFree(r.dec);
   (void)hipFree(r.mean);
   (void)hipFree(r.norm);
+  (void)hipFree(r.rowb);
+  (void)hipFree(r.normp);
   r = RootAux{};
   prepare_root(ix, st);
   HENN_HIP(hipStreamSynchronize(st));
@@ -523,6 +525,8 @@ static void destroy(henn_index* ix) {
   if (ix->root.dec_owned) (void)hipFree(ix->root.dec);
   (void)hipFree(ix->root.mean);
   (void)hipFree(ix->root.norm);
+  (void)hipFree(ix->root.rowb);
+  (void)hipFree(ix->root.normp);
   delete ix;
 }
 
@@ -555,6 +559,7 @@ static void prepare_root(henn_index* ix, hipStream_t st) {
   r.norm = dalloc<float>(R.size);
   launch_row_norms(r.dec, r.mean, R.size, ix->dpad, r.norm, st);
   r.nmax = max_norm(r.norm, R.size, st);
+  prepare_root_bf16(r, ix->dpad, ix->metric, st);
 }
 
 static henn_index* new_index(const float* X, int64_t n, int32_t d, const henn_build_params* p,
@@ -1001,7 +1006,7 @@ static int64_t search_workspace_bytes(const henn_index* idx, int64_t nq,
       break;
     case 2:
       b += (int64_t)sizeof(uint64_t) * nq +
-           (int64_t)root_gram_splits(nq, rs, &per) * nq * 2 * kRootK * 8;
+           root_shortlist_bytes(root_gram_splits(nq, rs, &per), nq, idx->root.kp);
       break;
     default:
       break;
@@ -1077,6 +1082,8 @@ static henn_status search_impl(const henn_index* idx, const float* Q, int64_t nq
     a.out_ids = out_ids;
     a.out_dist = out_dist;
     a.counters = sp->counters;
+    if (!rows_addressable(a))
+      return fail(HENN_E_UNSUPPORTED, "search needs n * ceil(d / 8) < 2^32");
 
     // autotuned shape for this (storage, beam bucket, k bucket), if cached
     int want_lpn = sp->lanes_per_vec, want_wpb = sp->waves_per_block;
@@ -1131,13 +1138,10 @@ static henn_status search_impl(const henn_index* idx, const float* Q, int64_t nq
     if (rmode == 2) {
       int64_t per = 0;
       const int splits = root_gram_splits(nq, idx->root.size, &per);
-      const int64_t nsl = (int64_t)splits * nq * 2 * kRootK;
       uint64_t* root_best = reinterpret_cast<uint64_t*>(ws + 256);
-      float* sl_d = reinterpret_cast<float*>(root_best + nq);
-      int32_t* sl_i = reinterpret_cast<int32_t*>(sl_d + nsl);
-      launch_root_gram(Q, nq, idx->d, idx->root, idx->dpad, idx->metric, splits, per, sl_d, sl_i,
-                       st);
-      if (!launch_root_check(idx->storage, a, idx->root, splits, sl_d, sl_i, root_best, st)) {
+      const RootShortlist sl = root_shortlist_at(root_best + nq, splits, nq, idx->root.kp);
+      launch_root_gram(Q, nq, idx->d, idx->root, idx->dpad, idx->metric, splits, per, sl, st);
+      if (!launch_root_check(idx->storage, a, splits, sl, root_best, st)) {
         if (ws_owned) (void)hipFreeAsync(ws, st);
         return fail(HENN_E_UNSUPPORTED, "no root check kernel for this shape");
       }

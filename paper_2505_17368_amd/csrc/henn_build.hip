@@ -553,11 +553,6 @@ float max_norm(const float* norms, int64_t size, hipStream_t st) {
 // BF16: round-to-nearest-even of each FP32 coordinate (scale 1).
 // FP8:  scale = max|x| / 448 per row (1 for an all-zero row); code =
 //       round-to-nearest-even of x / scale in OCP E4M3 (saturating at 448).
-__device__ inline uint32_t f32_to_bf16_rne(float f) {
-  const uint32_t u = __float_as_uint(f);
-  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
-}
-
 __device__ inline uint32_t f32_to_e4m3_rne(float v) {
   const uint32_t sign = v < 0.0f ? 0x80u : 0u;
   float a = fabsf(v);

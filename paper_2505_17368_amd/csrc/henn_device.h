@@ -149,6 +149,12 @@ enum StoreKind { kF32 = 0, kBF16 = 1, kFP8 = 2 };
 
 __device__ inline float bf16_to_f32(uint32_t h) { return __uint_as_float(h << 16); }
 
+// FP32 -> BF16 bits, round to nearest even (finite inputs).
+__device__ inline uint32_t f32_to_bf16_rne(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+
 // OCP E4M3 (e4m3fn): bias 7, subnormals, max 448.  Exact decode: place the
 // 7 magnitude bits where an FP32 exponent/mantissa would sit, then rescale
 // by 2^120 (exact), which also covers the subnormal codes.

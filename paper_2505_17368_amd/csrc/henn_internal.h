@@ -49,7 +49,12 @@ namespace henn {
 //         rows themselves, decoded BF16, or scale * decoded FP8);
 //   mean: [dpad] mean of dec (L2 only, else nullptr);
 //   norm: [size] |dec - mean|^2 (L2) or |dec|^2 (IP);
-//   nmax: max of norm; mean_n2: |mean|^2.
+//   nmax: max of norm; mean_n2: |mean|^2;
+//   rowb: the BF16 Gram operand, bf16 of dec - mean (L2) or dec (IP),
+//         [rows_pad][kp] with kp = dpad rounded up to 16 and rows_pad = size
+//         rounded up to 32, zero padded;
+//   normp: [rows_pad] the Gram value's norm term, norm (L2) or 0 (IP), +inf
+//         for the padding rows.
 struct RootAux {
   int64_t size = 0;
   float* dec = nullptr;
@@ -57,8 +62,27 @@ struct RootAux {
   float* mean = nullptr;
   float* norm = nullptr;
   float nmax = 0.0f, mean_n2 = 0.0f;
+  uint16_t* rowb = nullptr;
+  float* normp = nullptr;
+  int kp = 0;
 };
-constexpr int kRootK = 8;  // Gram shortlist per (root split, query, lane half)
+// Gram shortlist of a complete-root scan.  Per (root split, query) the
+// rows whose Gram value lies within the query's margin mq of the split's
+// smallest Gram value: up to kRootCap of them in val / row, and their full
+// number in cnt (above kRootCap: the list overflowed and the check scans
+// the root).  qb holds each query's BF16 Gram operand.
+constexpr int kRootCap = 16;
+struct RootShortlist {
+  uint16_t* qb = nullptr;  // [nq][kp]: bf16 of -2 (q - mean) (L2) or -q (IP)
+  float* mq = nullptr;     // [nq]: the margin of each query
+  float* val = nullptr;    // [splits][nq][kRootCap]
+  int32_t* row = nullptr;  // same layout: root positions
+  int32_t* cnt = nullptr;  // [splits][nq]
+};
+// Bytes of a shortlist for (splits, nq, kp), including 256 bytes of slack
+// for aligning its start.
+int64_t root_shortlist_bytes(int splits, int64_t nq, int kp);
+RootShortlist root_shortlist_at(void* base, int splits, int64_t nq, int kp);
 
 // One autotuned launch shape, valid for a (storage, beam bucket, k bucket).
 struct TuneEntry {
@@ -199,12 +223,26 @@ inline int default_vis_bits(int ef_need, int64_t n, bool narrow_ok) {
 // Shared-memory bytes one wave needs for a given list capacity.
 size_t search_lds_per_wave(int ef_cap, int vis_bits, int vis_bytes);
 
+// Whether every layer's rows have 32-bit first-chunk indices
+// (size * chunks per row < 2^32), which the search kernel needs.
+bool rows_addressable(const SearchArgs& a);
+
 // Enqueues the search kernel.  Returns false when no kernel instance
-// matches (storage, lanes_per_vec, chunks_per_lane).
+// matches (storage, lanes_per_vec, chunks_per_lane) or !rows_addressable(a).
 bool launch_search(int storage, const SearchArgs& a, const LaunchShape& s, hipStream_t st);
+// The per-storage halves of launch_search and launch_serve_step.
+bool launch_search_f32(const SearchArgs& a, const LaunchShape& s, hipStream_t st);
+bool launch_search_bf16(const SearchArgs& a, const LaunchShape& s, hipStream_t st);
+bool launch_search_fp8(const SearchArgs& a, const LaunchShape& s, hipStream_t st);
 
 bool launch_serve_step(int storage, const SearchArgs& a, const ServeArgs& sv,
                        const LaunchShape& sh, hipStream_t st);
+bool launch_serve_f32(const SearchArgs& a, const ServeArgs& sv, const LaunchShape& sh,
+                      hipStream_t st);
+bool launch_serve_bf16(const SearchArgs& a, const ServeArgs& sv, const LaunchShape& sh,
+                       hipStream_t st);
+bool launch_serve_fp8(const SearchArgs& a, const ServeArgs& sv, const LaunchShape& sh,
+                      hipStream_t st);
 // root_keys (nullable): the new requests' complete-root keys, copied to
 // slot_root[slot].
 void launch_serve_admit(const float* staged_q, const int32_t* meta, int n_new, int d,
@@ -218,17 +256,19 @@ int root_scan_splits(int64_t nq, int64_t root_size, int64_t* rows_per_split);
 bool launch_root_scan(int storage, const SearchArgs& a, int splits, int64_t rows_per_split,
                       uint64_t* out, hipStream_t st);
 
-// The same scan on matrix cores: a Gram shortlist of kRootK per (split,
-// query, lane half) over the prepared root (launch_root_gram), then per
-// query the exact canonical distances of the rows that can still be the
-// nearest given the Gram error bound, or a full canonical scan when the
-// shortlist cannot prove it (launch_root_check); writes [nq] best keys.
+// The same scan on matrix cores: a BF16 Gram shortlist per (split, query,
+// lane half) over the prepared root (launch_root_gram), then per query the
+// exact canonical distances of the rows that can still be the nearest given
+// the Gram error bound, or a full canonical scan when a list overflowed
+// (launch_root_check); writes [nq] best keys.
 int root_gram_splits(int64_t nq, int64_t root_size, int64_t* rows_per_split);
+// Fills r.rowb / r.normp / r.kp from r.dec, r.mean and r.norm (allocates).
+void prepare_root_bf16(RootAux& r, int dpad, int metric, hipStream_t st);
 void launch_root_gram(const float* Q, int64_t nq, int d, const RootAux& r, int dpad, int metric,
-                      int splits, int64_t rows_per_split, float* sl_d, int32_t* sl_i,
+                      int splits, int64_t rows_per_split, const RootShortlist& sl,
                       hipStream_t st);
-bool launch_root_check(int storage, const SearchArgs& a, const RootAux& r, int splits,
-                       const float* sl_d, const int32_t* sl_i, uint64_t* out, hipStream_t st);
+bool launch_root_check(int storage, const SearchArgs& a, int splits, const RootShortlist& sl,
+                       uint64_t* out, hipStream_t st);
 
 // ---- build ----------------------------------------------------------------
 void launch_copy_rows(const float* src, int64_t src_stride, const int32_t* ids, int64_t count,

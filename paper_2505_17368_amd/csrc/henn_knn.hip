@@ -35,32 +35,27 @@ constexpr int kTileC = 32;  // candidates per LDS tile
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-// Gram shortlist pass (d <= 128), used for two contractions:
-//  * the layer's kNN graph (Alg. 1 builds one graph per layer): queries and
-//    candidates are the layer's rows, a row never lists itself, KS = 32;
-//  * the exhaustive scan of a complete-graph root (Alg. 4 query on the root):
-//    queries are the search batch, candidates the root rows, KS = 8, the
-//    root split over blockIdx.y.
-// A block takes 128 queries (one 32-row MFMA column block per wave) and
-// streams its candidate range through LDS in tiles of kTileC.  The distance
-// is assembled inside the contraction: with y = centred candidate and
-// x = centred query,
+// Gram shortlist pass of the layer's kNN graph (d <= 128; Alg. 1 builds
+// one graph per layer): queries and candidates are the layer's rows and a
+// row never lists itself.  A block takes 128 rows (one 32-row MFMA column
+// block per wave) and streams the layer through LDS in tiles of kTileC.
+// The distance is assembled inside the contraction: with y = centred
+// candidate and x = centred row,
 //   |y - x|^2 = sum_k y_k (-2 x_k) + (|y|^2 + pen) * 1 + 1 * |x|^2
 //   -<y, x>   = sum_k y_k (-x_k)  +  pen * 1         + 0 * 0
 // the last two products being one extra MFMA step over the two lane
-// halves; pen = +inf marks rows past the end of the range (the |x|^2 term
-// is dropped when qnorms is null: it does not change a query's order).
-// Rows are taken as zero-padded to 2 * KH coordinates (dpad <= 2 * KH); the
-// K dimension splits at KH between the lane halves, so each tile is a
-// fixed, branch-free chain of KH + 1 MFMAs and the epilogue is one compare
-// per value, with an insertion into the lane's sorted top-KS only when the
-// value beats the current KS-th.  Output: per (split, query, lane half) the
-// KS smallest (value, candidate index) pairs, ascending.
-template <int KH, int KS, bool SELF>
-__global__ __launch_bounds__(256, 2) void k_gram_topk(
-    const float* qsrc, int64_t nq, int qstride, int qd, const float* qnorms, const float* cand,
-    int64_t csize, int64_t rows_per_split, int dpad, const float* cnorms, const float* mean,
-    int metric, float* sl_d, int32_t* sl_i, int64_t block0) {
+// halves; pen = +inf marks rows past the end of the layer.  Rows are taken
+// as zero-padded to 2 * KH coordinates (dpad <= 2 * KH); the K dimension
+// splits at KH between the lane halves, so each tile is a fixed,
+// branch-free chain of KH + 1 MFMAs and the epilogue is one compare per
+// value, with an insertion into the lane's sorted top-KS only when the
+// value beats the current KS-th.  Output: per (row, lane half) the KS
+// smallest (value, candidate index) pairs, ascending.
+template <int KH, int KS>
+__global__ __launch_bounds__(256, 2) void k_gram_topk(const float* vec, int64_t size, int dpad,
+                                                      const float* norms, const float* mean,
+                                                      int metric, float* sl_d, int32_t* sl_i,
+                                                      int64_t block0) {
   // two LDS buffers of [kTileC][2 * KH + 4] candidates + their norms; the
   // next tile is fetched into registers while the current one is multiplied
   extern __shared__ __align__(16) float tile[];
@@ -69,50 +64,30 @@ __global__ __launch_bounds__(256, 2) void k_gram_topk(
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int qc = lane & 31, h = lane >> 5;
   const int64_t qrow = (block0 + blockIdx.x) * 128 + wave * 32 + qc;
-  const bool qvalid = qrow < nq;
-  // candidate range: the whole matrix for the kNN graph, the blockIdx.y
-  // split for the root scan
-  const int64_t cb = SELF ? 0 : (int64_t)blockIdx.y * rows_per_split;
-  const int64_t ce = SELF ? csize : min(cb + rows_per_split, csize);
+  const bool qvalid = qrow < size;
+  const int64_t cb = 0, ce = size;
   const bool l2 = metric == 0;
   const float qscale = l2 ? -2.0f : -1.0f;
 
-  // the query's coordinates: loads clamped into the row (no branches, all in
+  // the row's coordinates: loads clamped into the row (no branches, all in
   // flight together), out-of-range values dropped afterwards
   float bq[KH];
   {
-    const float* qr = qsrc + (qvalid ? qrow : 0) * qstride;
-    // float4 loads when rows and widths are 16-byte granular (then a float4
-    // starting below qd lies wholly below it).  The kNN graph's blocks scan a
-    // whole layer, so their prologue stays scalar (fewer live registers).
-    const bool vec4 = !SELF && (qstride & 3) == 0 && (qd & 3) == 0 &&
-                      (reinterpret_cast<uintptr_t>(qsrc) & 15) == 0;
-    if (vec4) {
+    const float* qr = vec + (qvalid ? qrow : 0) * dpad;
 #pragma unroll
-      for (int k4 = 0; k4 < KH / 4; ++k4) {
-        const int e = h * KH + 4 * k4;
-        const float4 v = *reinterpret_cast<const float4*>(qr + (e < qd ? e : 0));
-        bq[4 * k4 + 0] = v.x;
-        bq[4 * k4 + 1] = v.y;
-        bq[4 * k4 + 2] = v.z;
-        bq[4 * k4 + 3] = v.w;
-      }
-    } else {
-#pragma unroll
-      for (int kk = 0; kk < KH; ++kk) {
-        const int e = h * KH + kk;
-        bq[kk] = qr[e < qd ? e : 0];
-      }
+    for (int kk = 0; kk < KH; ++kk) {
+      const int e = h * KH + kk;
+      bq[kk] = qr[e < dpad ? e : 0];
     }
 #pragma unroll
     for (int kk = 0; kk < KH; ++kk) {
       const int e = h * KH + kk;
-      const float m = (mean && e < qd) ? mean[e] : 0.0f;
-      bq[kk] = (qvalid && e < qd) ? qscale * (bq[kk] - m) : 0.0f;
+      const float m = (mean && e < dpad) ? mean[e] : 0.0f;
+      bq[kk] = (qvalid && e < dpad) ? qscale * (bq[kk] - m) : 0.0f;
     }
   }
   // B operand of the extra step: row 0 is all ones, row 1 holds |x|^2 (L2)
-  const float b_extra = h == 0 ? 1.0f : (l2 && qnorms && qvalid ? qnorms[qrow] : 0.0f);
+  const float b_extra = h == 0 ? 1.0f : (l2 && qvalid ? norms[qrow] : 0.0f);
   const float a_one = l2 ? 1.0f : 0.0f;
 
   float td[KS];
@@ -158,14 +133,14 @@ __global__ __launch_bounds__(256, 2) void k_gram_topk(
   auto fetch = [&](int64_t c0) {
     const int64_t rem = ce - 1 - c0;
     const int last = rem < kTileC - 1 ? (int)rem : kTileC - 1;  // last valid row of the tile
-    const float* base = cand + c0 * dpad;
+    const float* base = vec + c0 * dpad;
 #pragma unroll
     for (int u = 0; u < kMaxF4; ++u) {
       const int r = src_row[u] < last ? src_row[u] : last;
       pre[u] = reinterpret_cast<const float4*>(base + r * dpad)[src_c4[u]];
     }
     const int r = (int)(threadIdx.x & (kTileC - 1));
-    pnorm = cnorms[c0 + (r < last ? r : last)];
+    pnorm = norms[c0 + (r < last ? r : last)];
     plast = last;
   };
   auto stash = [&](float* buf) {
@@ -221,7 +196,7 @@ __global__ __launch_bounds__(256, 2) void k_gram_topk(
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const int64_t crow = c0 + 8 * (v >> 2) + 4 * h + (v & 3);
-        float nd = (SELF && crow == qrow) ? INFINITY : acc[v];
+        float nd = crow == qrow ? INFINITY : acc[v];
         if (__builtin_amdgcn_ballot_w64(nd < td[KS - 1])) {
           int32_t ni = (int32_t)crow;
 #pragma unroll
@@ -242,7 +217,7 @@ __global__ __launch_bounds__(256, 2) void k_gram_topk(
     cur ^= 1;
   }
   if (qvalid) {
-    const int64_t o = ((int64_t)blockIdx.y * nq + qrow) * (2 * KS) + h * KS;
+    const int64_t o = qrow * (2 * KS) + h * KS;
 #pragma unroll
     for (int j = 0; j < KS; ++j) {
       sl_d[o + j] = td[j];
@@ -553,17 +528,16 @@ __global__ __launch_bounds__(256) void k_knn_exact(const float* vec, int64_t siz
   X(16, 2) X(4, 8) X(16, 4) X(16, 8)
 
 int root_gram_splits(int64_t nq, int64_t root_size, int64_t* rows_per_split) {
-  // Two 256-thread workgroups fit a CU, so 512 run at once.  Pick the split
-  // count with the shortest makespan, (rounds of 512 workgroups) x (tiles per
-  // split), the fewest splits among equals; at least 16 tiles per split so
-  // that a block's query prologue is amortised.
+  // About four 256-thread workgroups of k_root_gram_bf16 fit a CU, so 1024
+  // run at once.  Pick the split count with the shortest makespan, (rounds
+  // of 1024 workgroups) x (tiles per split), the fewest splits among equals;
+  // at least 4 tiles per split.
   const int64_t qblocks = (nq + 127) / 128;
   const int64_t tiles = (root_size + kTileC - 1) / kTileC;
-  const int64_t max_splits =
-      std::min<int64_t>(64, std::max<int64_t>(1, root_size / (16 * kTileC)));
+  const int64_t max_splits = std::min<int64_t>(64, std::max<int64_t>(1, tiles / 4));
   int64_t splits = 1, best = -1;
   for (int64_t sp = 1; sp <= max_splits; ++sp) {
-    const int64_t rounds = (qblocks * sp + 511) / 512;
+    const int64_t rounds = (qblocks * sp + 1023) / 1024;
     const int64_t span = rounds * ((tiles + sp - 1) / sp);
     if (best < 0 || span < best) {
       best = span;
@@ -576,22 +550,262 @@ int root_gram_splits(int64_t nq, int64_t root_size, int64_t* rows_per_split) {
   return (int)((root_size + per - 1) / per);
 }
 
+// ------------------------------------------------------------------------
+// Complete-root scan on BF16 matrix cores (the shortlist half of the root
+// query of Alg. 4 on a complete root; the exact check follows in
+// k_root_check).  The root is prepared once (prepare_root_bf16): rows
+// centred on the root mean (L2) and rounded to BF16, [rows_pad][kp] with kp
+// = dpad rounded up to 16 and rows_pad = size rounded up to 32, and a norm
+// column that is +inf for the padding rows.  A block takes 128 queries, one
+// 32-query column block per wave, and walks its split of the root 32 rows
+// at a time; per tile a wave issues kp / 16 v_mfma_f32_32x32x16_bf16 with
+//   A = 32 root rows (lane: row lane & 31, coordinates 16 s + 8 h .. + 7)
+//   B = the wave's 32 queries, as bf16 of -2 (q - mean) (L2) or -q (IP)
+// so that acc + norm is the Gram value a(y), |y - q|^2 - |q - mean|^2 (L2)
+// or -<y, q> (IP) up to the BF16 rounding, which the margin covers.  Both
+// operands come straight from memory (the root is L2-resident); the next
+// tile's loads are issued before the current tile is multiplied.
+//
+// Two passes over the split: the first keeps only the smallest Gram value,
+// the second appends every row within the query's margin M of the split's
+// smallest (normally a handful) to the lane's list.  The exact nearest is
+// within M of the smallest Gram value over the whole root, hence of every
+// split's, so the lists hold it.  M = (2^-7 + 2^-14 + 32 (dpad + 16) 2^-24)
+// N with N = |q - mean|^2 + max_y |y - mean|^2 + |mean|^2 (twice the sum of
+// the Gram and canonical error bounds, derived at k_root_check).
+// ------------------------------------------------------------------------
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__global__ void k_root_rows_bf16(const float* dec, const float* mean, const float* norm,
+                                 int64_t size, int64_t rows_pad, int dpad, int kp, int metric,
+                                 uint16_t* rowb, float* normp) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= rows_pad * kp) return;
+  const int64_t r = i / kp;
+  const int c = (int)(i - r * kp);
+  float v = 0.0f;
+  if (r < size && c < dpad) v = dec[r * dpad + c] - (mean ? mean[c] : 0.0f);
+  rowb[i] = (uint16_t)f32_to_bf16_rne(v);
+  if (c == 0) normp[r] = r < size ? (metric == 0 ? norm[r] : 0.0f) : INFINITY;
+}
+
+void prepare_root_bf16(RootAux& r, int dpad, int metric, hipStream_t st) {
+  if (dpad > 128) throw HipError{hipErrorInvalidValue, "BF16 root scan supports d <= 128"};
+  r.kp = (dpad + 15) / 16 * 16;
+  const int64_t rows_pad = (r.size + 31) / 32 * 32;
+  HENN_HIP(hipMalloc(&r.rowb, sizeof(uint16_t) * rows_pad * r.kp));
+  HENN_HIP(hipMalloc(&r.normp, sizeof(float) * rows_pad));
+  const int64_t n = rows_pad * r.kp;
+  hipLaunchKernelGGL(k_root_rows_bf16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                     r.dec, r.mean, r.norm, r.size, rows_pad, dpad, r.kp, metric, r.rowb,
+                     r.normp);
+  HENN_HIP(hipGetLastError());
+}
+
+int64_t root_shortlist_bytes(int splits, int64_t nq, int kp) {
+  const int64_t lists = (int64_t)splits * nq;
+  return 256 + nq * kp * 2 + nq * 4 + lists * kRootCap * 8 + lists * 4;
+}
+
+RootShortlist root_shortlist_at(void* base, int splits, int64_t nq, int kp) {
+  const int64_t lists = (int64_t)splits * nq;
+  RootShortlist sl;
+  sl.qb = reinterpret_cast<uint16_t*>((reinterpret_cast<uintptr_t>(base) + 255) & ~uintptr_t(255));
+  sl.mq = reinterpret_cast<float*>(sl.qb + nq * kp);
+  sl.val = sl.mq + nq;
+  sl.row = reinterpret_cast<int32_t*>(sl.val + lists * kRootCap);
+  sl.cnt = sl.row + lists * kRootCap;
+  return sl;
+}
+
+// The Gram pass's query operand, once per query: eight coordinates per
+// thread (16 threads per query), centred on the root mean (L2), scaled by -2
+// (L2) or -1 (IP) and rounded to BF16, zero past d; and the query's margin
+// M = (2^-7 + 2^-14 + 32 (dpad + 16) 2^-24) N with
+// N = |q - mean|^2 + max_y |y - mean|^2 + |mean|^2 (twice the sum of the
+// Gram and canonical error bounds, derived at k_root_check).
+__global__ __launch_bounds__(256) void k_root_query_bf16(const float* Q, int64_t nq, int d,
+                                                         int dpad, int kp, const float* mean,
+                                                         float nmax, float mean_n2, int metric,
+                                                         RootShortlist sl) {
+  const int64_t qi = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
+  const int c = threadIdx.x & 15;
+  const bool live = qi < nq && 8 * c < kp;
+  const float qscale = metric == 0 ? -2.0f : -1.0f;
+  float qn = 0.0f;
+  uint32_t w[4] = {0u, 0u, 0u, 0u};
+  if (live) {
+#pragma unroll
+    for (int j = 0; j < 8; j += 2) {
+      const int e0 = 8 * c + j, e1 = e0 + 1;
+      const float v0 = e0 < d ? Q[qi * d + e0] - (mean ? mean[e0] : 0.0f) : 0.0f;
+      const float v1 = e1 < d ? Q[qi * d + e1] - (mean ? mean[e1] : 0.0f) : 0.0f;
+      qn = __builtin_fmaf(v0, v0, qn);
+      qn = __builtin_fmaf(v1, v1, qn);
+      w[j >> 1] = f32_to_bf16_rne(qscale * v0) | (f32_to_bf16_rne(qscale * v1) << 16);
+    }
+    reinterpret_cast<uint4*>(sl.qb + qi * kp)[c] = make_uint4(w[0], w[1], w[2], w[3]);
+  }
+#pragma unroll
+  for (int m = 8; m >= 1; m >>= 1) qn += __shfl_xor(qn, m);
+  if (qi < nq && c == 0)
+    sl.mq[qi] = (0x1p-7f + 0x1p-14f + 32.0f * (float)(dpad + 16) * 0x1p-24f) *
+                (qn + nmax + mean_n2);
+}
+
+template <int S>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_root_gram_bf16(
+    const uint16_t* rowb, const float* normp, int64_t size, int64_t nq, int64_t rows_per_split,
+    RootShortlist sl) {
+  constexpr int kp = 16 * S;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int qc = lane & 31, h = lane >> 5;
+  const int64_t qrow = (int64_t)blockIdx.x * 128 + wave * 32 + qc;
+  const bool qvalid = qrow < nq;
+  const int64_t cb = (int64_t)blockIdx.y * rows_per_split;
+  const int64_t ce = min(cb + rows_per_split, size);
+
+  // B operand: this lane's query coordinates 16 s + 8 h .. + 7
+  bf16x8 bq[S];
+  {
+    const uint4* src = reinterpret_cast<const uint4*>(sl.qb + (qvalid ? qrow : 0) * kp) + h;
+#pragma unroll
+    for (int s = 0; s < S; ++s) bq[s] = __builtin_bit_cast(bf16x8, src[2 * s]);
+  }
+  const float M = qvalid ? sl.mq[qrow] : 0.0f;
+
+  // Tiles are staged in LDS, shared by the block's four waves, by the
+  // global-to-LDS copy of gfx950 (global_load_lds_dwordx4): instruction j of
+  // a tile moves 64 chunks of 16 bytes, slot p = 64 j + lane.  Slot p holds
+  // chunk (pos - row) mod 2S of tile row p / 2S, pos = p mod 2S: the
+  // rotation spreads the 16-byte reads of one step (one chunk of each of 32
+  // rows) over all banks.  The 32 norms ride along (wave 0, one dword per
+  // lane, lanes 32..63 repeating 0..31).  rows_per_split is a multiple of 32
+  // and the prepared rows are padded to a multiple of 32, so every tile row
+  // below ce rounded up to 32 exists (rows at or past size carry norm +inf
+  // and never enter a list).  Two buffers in turn: the next tile's copy is
+  // in flight while the current one is multiplied.
+  __shared__ uint4 tileA[64 * S], tileB[64 * S];
+  __shared__ float normA[64], normB[64];
+  typedef __attribute__((address_space(3))) void* lds_ptr;
+  auto issue = [&](int64_t c0, uint4* tile, float* nrm) {
+    for (int j = wave; j < S; j += 4) {
+      const int p = 64 * j + lane, row = p / (2 * S), pos = p - row * (2 * S);
+      const int chunk = (pos - row % (2 * S) + 2 * S) % (2 * S);
+      __builtin_amdgcn_global_load_lds(rowb + (c0 + row) * kp + 8 * chunk, (lds_ptr)(tile + 64 * j),
+                                       16, 0, 0);
+    }
+    if (wave == 0)
+      __builtin_amdgcn_global_load_lds(normp + c0 + (lane & 31), (lds_ptr)nrm, 4, 0, 0);
+  };
+  // waits for this wave's copies, then for every wave's (the barrier)
+  auto arrive = [&]() {
+    __builtin_amdgcn_s_waitcnt(0xF70);  // vmcnt(0), other counters untouched
+    __syncthreads();
+  };
+  // one tile's Gram values; val[v] belongs to root row c0 + 8 (v >> 2) + 4 h + (v & 3)
+  auto gram = [&](const uint4* tile, const float* nrm, float (&val)[16]) {
+    floatx16 acc;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int chunk = 2 * s + h;
+      const uint4 a = tile[qc * (2 * S) + (chunk + qc) % (2 * S)];
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), bq[s], acc, 0,
+                                                    0, 0);
+    }
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const float4 nr = reinterpret_cast<const float4*>(nrm)[2 * g + h];
+      val[4 * g + 0] = acc[4 * g + 0] + nr.x;
+      val[4 * g + 1] = acc[4 * g + 1] + nr.y;
+      val[4 * g + 2] = acc[4 * g + 2] + nr.z;
+      val[4 * g + 3] = acc[4 * g + 3] + nr.w;
+    }
+  };
+  // every wave of the block walks the same tiles (the barriers need all of
+  // them, so no wave leaves early)
+  auto scan = [&](auto&& body) {
+    if (cb >= ce) return;
+    issue(cb, tileA, normA);
+    for (int64_t c0 = cb;; c0 += 64) {
+      arrive();
+      if (c0 + 32 < ce) issue(c0 + 32, tileB, normB);
+      body(c0, tileA, normA);
+      if (c0 + 32 >= ce) break;
+      arrive();
+      if (c0 + 64 < ce) issue(c0 + 64, tileA, normA);
+      body(c0 + 32, tileB, normB);
+      if (c0 + 64 >= ce) break;
+    }
+    __syncthreads();  // the next scan refills tileA
+  };
+
+  // pass 1: the split's smallest Gram value of this query
+  float vmin = INFINITY;
+  scan([&](int64_t, const uint4* tile, const float* nrm) {
+    float val[16];
+    gram(tile, nrm, val);
+#pragma unroll
+    for (int v = 0; v < 16; ++v) vmin = fminf(vmin, val[v]);
+  });
+  vmin = fminf(vmin, __shfl_xor(vmin, 32));
+  const float thr = vmin + M;
+
+  // pass 2: the rows within M of it; the query's two lanes (h = 0, 1) fill
+  // one list, h = 0's rows of a tile first
+  const int64_t list = (int64_t)blockIdx.y * nq + qrow;
+  float* lval = sl.val + list * kRootCap;
+  int32_t* lrow = sl.row + list * kRootCap;
+  int cnt = 0;
+  scan([&](int64_t c0, const uint4* tile, const float* nrm) {
+    float val[16];
+    gram(tile, nrm, val);
+    uint32_t hit = 0;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) hit |= (qvalid && val[v] <= thr) ? 1u << v : 0u;
+    if (__builtin_amdgcn_ballot_w64(hit != 0)) {
+      const int n = __popc(hit), n_other = __shfl_xor(n, 32);
+      int pos = cnt + (h ? n_other : 0);
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        if (hit & (1u << v)) {
+          if (pos < kRootCap) {
+            lval[pos] = val[v];
+            lrow[pos] = (int32_t)(c0 + 8 * (v >> 2) + 4 * h + (v & 3));
+          }
+          ++pos;
+        }
+      }
+      cnt += n + n_other;
+    }
+  });
+  if (qvalid && h == 0) sl.cnt[list] = cnt;
+}
+
 void launch_root_gram(const float* Q, int64_t nq, int d, const RootAux& r, int dpad, int metric,
-                      int splits, int64_t rows_per_split, float* sl_d, int32_t* sl_i,
+                      int splits, int64_t rows_per_split, const RootShortlist& sl,
                       hipStream_t st) {
-  const int kh = dpad <= 32 ? 16 : dpad <= 64 ? 32 : 64;
-  const size_t lds = sizeof(float) * (2 * (kTileC * (2 * kh + 4) + kTileC) + dpad);
+  if (!r.rowb || rows_per_split % 32 != 0 || r.kp > 128)
+    throw HipError{hipErrorInvalidValue, "root scan: root not prepared"};
+  hipLaunchKernelGGL(k_root_query_bf16, dim3((unsigned)((nq + 15) / 16)), dim3(256), 0, st, Q, nq,
+                     d, dpad, r.kp, r.mean, r.nmax, r.mean_n2, metric, sl);
   const dim3 grid((unsigned)((nq + 127) / 128), (unsigned)splits);
-#define HENN_RG(KH)                                                                            \
-  hipLaunchKernelGGL((k_gram_topk<KH, kRootK, false>), grid, dim3(256), lds, st, Q, nq, d, d,  \
-                     (const float*)nullptr, r.dec, r.size, rows_per_split, dpad, r.norm, r.mean, \
-                     metric, sl_d, sl_i, (int64_t)0)
-  if (kh == 16)
-    HENN_RG(16);
-  else if (kh == 32)
-    HENN_RG(32);
-  else
-    HENN_RG(64);
+#define HENN_RG(S)                                                                               \
+  hipLaunchKernelGGL((k_root_gram_bf16<S>), grid, dim3(256), 0, st, r.rowb, r.normp, r.size, nq, \
+                     rows_per_split, sl)
+  switch (r.kp / 16) {
+    case 1: HENN_RG(1); break;
+    case 2: HENN_RG(2); break;
+    case 3: HENN_RG(3); break;
+    case 4: HENN_RG(4); break;
+    case 5: HENN_RG(5); break;
+    case 6: HENN_RG(6); break;
+    case 7: HENN_RG(7); break;
+    case 8: HENN_RG(8); break;
+    default: throw HipError{hipErrorInvalidValue, "root scan: unsupported width"};
+  }
 #undef HENN_RG
   HENN_HIP(hipGetLastError());
 }
@@ -632,17 +846,14 @@ int64_t build_knn_graph(const float* vec, int64_t size, int dpad, int nchunks, i
       hipLaunchKernelGGL(k_knn_gram_wide, dim3(nbs), dim3(256), lds, st, vec, size, dpad, mean,
                          norms, metric, sl_d, sl_i, b0);
     else if (kh <= 16)
-      hipLaunchKernelGGL((k_gram_topk<16, kShort, true>), dim3(nbs), dim3(256), lds, st, vec,
-                         size, dpad, dpad, norms, vec, size, size, dpad, norms, mean, metric, sl_d,
-                         sl_i, b0);
+      hipLaunchKernelGGL((k_gram_topk<16, kShort>), dim3(nbs), dim3(256), lds, st, vec, size,
+                         dpad, norms, mean, metric, sl_d, sl_i, b0);
     else if (kh <= 32)
-      hipLaunchKernelGGL((k_gram_topk<32, kShort, true>), dim3(nbs), dim3(256), lds, st, vec,
-                         size, dpad, dpad, norms, vec, size, size, dpad, norms, mean, metric, sl_d,
-                         sl_i, b0);
+      hipLaunchKernelGGL((k_gram_topk<32, kShort>), dim3(nbs), dim3(256), lds, st, vec, size,
+                         dpad, norms, mean, metric, sl_d, sl_i, b0);
     else
-      hipLaunchKernelGGL((k_gram_topk<64, kShort, true>), dim3(nbs), dim3(256), lds, st, vec,
-                         size, dpad, dpad, norms, vec, size, size, dpad, norms, mean, metric, sl_d,
-                         sl_i, b0);
+      hipLaunchKernelGGL((k_gram_topk<64, kShort>), dim3(nbs), dim3(256), lds, st, vec, size,
+                         dpad, norms, mean, metric, sl_d, sl_i, b0);
     HENN_HIP(hipGetLastError());
     if (progress && b0 + (int64_t)nbs < nb) {
       HENN_HIP(hipStreamSynchronize(st));

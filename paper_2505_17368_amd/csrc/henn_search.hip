@@ -20,26 +20,43 @@
 // (henn_device.h), and a merge of the new keys into W by rank computation.
 // Precision forms traverse BF16 / FP8 rows and re-rank the first
 // min(|W|, rerank_factor*k) entries from the FP32 copy at the end.
+//
+// The library compiles this file four times: HENN_PART 0 holds the host
+// functions and root-scan kernels, parts 1 / 2 / 3 the search and serving
+// kernels of FP32 / BF16 / FP8 rows, so that the instantiations build in
+// parallel.  Without HENN_PART one translation unit holds everything.
 #include <math.h>
 
 #include "henn_device.h"
 #include "henn_internal.h"
 
+#ifndef HENN_PART
+#define HENN_PART -1
+#endif
+#define HENN_COMMON_PART (HENN_PART <= 0)
+#define HENN_KIND_PART(kind) (HENN_PART < 0 || HENN_PART == (kind) + 1)
+
 namespace henn {
 
+#if HENN_COMMON_PART
 size_t search_lds_per_wave(int ef_cap, int vis_bits, int vis_bytes) {
-  return (size_t)ef_cap * 8 + 64 * 8 * 2 + ((size_t)1 << vis_bits) * vis_bytes + 64 * 4;
+  return (size_t)ef_cap * 8 + 64 * 8 * 2 + 64 * 4 * 2 + ((size_t)1 << vis_bits) * vis_bytes;
 }
+#endif
 
 // One list W, merged in place.  A merge ranks the kept keys in kstage, then
 // reuses it as the map of the list positions that take a kept key.
+// The fresh neighbours of an expansion, by compacted slot: crow (the row's
+// first chunk index, row * chunks per row) and cidk (id << 1, the low word of
+// its key).
 struct WaveLds {
   uint64_t* W;
   uint64_t* ckey;     // candidate keys (by compacted slot)
   uint64_t* kstage;   // kept keys in arrival order; FP8 scales during the
                       // gather and the merge's slot map after the ranks
+  uint32_t* crow;
+  uint32_t* cidk;
   void* vis;  // 2^vis_bits entries: uint8 or uint16 tags, or int32 ids
-  int32_t* cid;
 };
 
 __device__ inline WaveLds carve(char* base, int ef_cap, int vis_bits, int vis_bytes) {
@@ -47,9 +64,9 @@ __device__ inline WaveLds carve(char* base, int ef_cap, int vis_bits, int vis_by
   s.W = reinterpret_cast<uint64_t*>(base);
   s.ckey = s.W + ef_cap;
   s.kstage = s.ckey + 64;
-  s.vis = s.kstage + 64;
-  s.cid = reinterpret_cast<int32_t*>(static_cast<char*>(s.vis) +
-                                     ((size_t)1 << vis_bits) * vis_bytes);
+  s.crow = reinterpret_cast<uint32_t*>(s.kstage + 64);
+  s.cidk = s.crow + 64;
+  s.vis = s.cidk + 64;
   return s;
 }
 
@@ -185,6 +202,7 @@ __global__ __launch_bounds__(256) void k_root_scan(const float* Q, int64_t nq, i
   if (qv) best_out[(int64_t)blockIdx.y * nq + qi] = best;
 }
 
+#if HENN_COMMON_PART
 template <int KIND>
 static bool launch_root_scan_kind(const SearchArgs& a, int P, int splits, int64_t rows_per_split,
                                   uint64_t* out, hipStream_t st) {
@@ -227,6 +245,8 @@ bool launch_root_scan(int storage, const SearchArgs& a, int splits, int64_t rows
   }
 }
 
+#endif  // HENN_COMMON_PART
+
 // Exhaustive canonical scan of a complete-graph root by one wave (two rows
 // per lane group in flight); every lane returns the best (distance,
 // position) key.
@@ -267,20 +287,23 @@ __device__ uint64_t root_scan_wave(const SearchArgs& a, const SearchLayer& R,
 }
 
 // Exact check after the MFMA root shortlist (one wave per query).  With
-// a(y) the Gram value of root row y (computed on the stored values, the
-// query-norm term dropped) and c(y) the canonical distance, both are within
-// an absolute bound of the exact distance that scales with
+// a(y) the Gram value of root row y (BF16 products of the centred stored
+// values and the centred query, FP32 accumulation, the query-norm term
+// dropped) and c(y) the canonical distance, both are within an absolute
+// bound of the exact distance that scales with
 // N = |q - mean|^2 + max_y |y - mean|^2 + |mean|^2 (L2; uncentred for IP):
-// |a - e| <= 4 (dpad + 8) 2^-24 N and |c - e| <= (10 + log2 chunks) 2^-23 N.
-// A row whose Gram value exceeds a_min + M, M = 32 (dpad + 16) 2^-24 N
-// (above twice the sum of both bounds), has c(y) > c(argmin_a), so the
-// nearest root member under (distance, position) is among the shortlisted
-// rows with a <= a_min + M -- provided every row left out of the
-// shortlists has a > a_min + M, i.e. the smallest cut-off (the kRootK-th
-// value of each list) exceeds it.  Otherwise the wave scans the root.
+//   |a - e| <= (2^-8 + 2^-18 + (3 dpad + 35) 2^-24) N
+// (each BF16 rounding is within 2^-9 relative, so a product of two is
+// within 2^-8 + 2^-18 of 2 |y_k| |q_k|, which sums to at most N; the FP32
+// sums add the rest), and |c - e| <= (10 + log2 chunks) 2^-23 N.  A row
+// whose Gram value exceeds a_min + M, M = (2^-7 + 2^-14 + 32 (dpad + 16)
+// 2^-24) N (above twice the sum of both bounds), has c(y) > c(argmin_a), so
+// the nearest root member under (distance, position) is among the rows with
+// a <= a_min + M.  The Gram pass listed, per split, every row within M of
+// the split's smallest value, which is at least a_min: so the lists hold
+// all of them unless one overflowed, and then the wave scans the root.
 template <int KIND, int LPN, int CPL>
-__global__ __launch_bounds__(256) void k_root_check(SearchArgs a, RootAux r, int splits,
-                                                    const float* sl_d, const int32_t* sl_i,
+__global__ __launch_bounds__(256) void k_root_check(SearchArgs a, int splits, RootShortlist sl,
                                                     uint64_t* out) {
   constexpr int G = 64 / LPN;
   const int lane = lane_id(), t = lane % LPN, g = lane / LPN;
@@ -289,48 +312,46 @@ __global__ __launch_bounds__(256) void k_root_check(SearchArgs a, RootAux r, int
   const SearchLayer& R = a.layer[a.num_layers - 1];
   float q[CPL][8];
   load_query<CPL>(a.Q + qi * a.d, a.d, t, q);
-  // |q - mean|^2 (L2) or |q|^2 (IP): this lane's chunks, summed over the group
-  float qn = 0.0f;
-#pragma unroll
-  for (int i = 0; i < CPL; ++i)
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int e = (t * CPL + i) * 8 + j;
-      const float v = q[i][j] - ((r.mean && e < a.dpad) ? r.mean[e] : 0.0f);
-      qn += v * v;
-    }
-  qn = group_sum<LPN>(qn);
-  const float N = qn + r.nmax + r.mean_n2;
-  const float M = 32.0f * (float)(a.dpad + 16) * 0x1p-24f * N;
 
-  const int nl = 2 * splits;  // lists of kRootK ascending values
-  float amin = INFINITY, cut = INFINITY;
-  for (int l = lane; l < nl; l += 64) {
-    const int64_t o = (((int64_t)(l >> 1) * a.nq + qi) * 2 + (l & 1)) * kRootK;
-    amin = fminf(amin, sl_d[o]);
-    cut = fminf(cut, sl_d[o + kRootK - 1]);
+  // entry e of the query's lists: the list of split e / kRootCap, slot
+  // e % kRootCap, present when below the list's count
+  const int n = splits * kRootCap;
+  auto entry = [&](int e, float& v, int32_t& pos, bool& over) {
+    const int l = e / kRootCap, j = e % kRootCap;
+    const int64_t list = (int64_t)l * a.nq + qi;
+    const int c = sl.cnt[list];
+    over = j == 0 && c > kRootCap;
+    const bool present = j < c;
+    v = present ? sl.val[list * kRootCap + j] : INFINITY;
+    pos = present ? sl.row[list * kRootCap + j] : -1;
+  };
+  float amin = INFINITY;
+  bool over = false;
+  for (int e = lane; e < n; e += 64) {
+    float v;
+    int32_t pos;
+    bool o;
+    entry(e, v, pos, o);
+    amin = fminf(amin, v);
+    over |= o;
   }
 #pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) {
-    amin = fminf(amin, __shfl_xor(amin, m));
-    cut = fminf(cut, __shfl_xor(cut, m));
-  }
-  const float T = amin + M;
+  for (int m = 32; m >= 1; m >>= 1) amin = fminf(amin, __shfl_xor(amin, m));
+  const float T = amin + sl.mq[qi];
   __shared__ int32_t rows_all[4][64];
   int32_t* rows = rows_all[threadIdx.x >> 6];
   uint64_t best = ~0ull;
-  if (!(cut > T)) {
+  if (ballot(over)) {
     best = root_scan_wave<KIND, LPN, CPL>(a, R, q);
   } else {
-    const int n = nl * kRootK;
     for (int base = 0; base < n; base += 64) {
       // compact this chunk's entries with a <= T, then G rows per pass
-      const int e = base + lane;
       int32_t pos = -1;
-      if (e < n) {
-        const int l = e / kRootK, j = e % kRootK;
-        const int64_t o = (((int64_t)(l >> 1) * a.nq + qi) * 2 + (l & 1)) * kRootK + j;
-        if (sl_d[o] <= T) pos = sl_i[o];
+      if (base + lane < n) {
+        float v;
+        bool o;
+        entry(base + lane, v, pos, o);
+        if (!(v <= T)) pos = -1;
       }
       const uint64_t m = ballot(pos >= 0);
       const int cnt = popc64(m);
@@ -408,51 +429,217 @@ __device__ void start_query(const SearchArgs& a, int64_t qi, const float (&q)[CP
   }
 }
 
-// Runs up to `budget` expansions from the current state (layer changes are
-// free).  Returns true once the layer-0 beam has no unexpanded entry; then
-// W (this wave's LDS list) holds the final list (st.wsize entries).
 // Rows each lane group gathers per pass of an expansion.
 constexpr int kGatherRows = 3;
 
+// FP8 traversal distances, one chunk of 8 coordinates at a time.  The
+// converter turns two codes into f16 values multiplied by a power of two:
+// it takes only the exponent of its FP32 scale operand, so with the row
+// scale s = 2^e m (1 <= m < 2) it yields c 2^e exactly, and t = q - m (c 2^e)
+// = q - s c is one packed f16 FMA with the query rounded to f16 (qh); sum t^2
+// is accumulated in FP32 by pairwise dot products (each product exact).
+// Inner products convert the codes unscaled and accumulate sum q c the same
+// way, the caller applying -s.  This is the precision form's arithmetic: f16
+// keeps 11 significant bits against the 4 of an E4M3 code, and the final
+// list is re-ranked in FP32.  Chunk sums then go through the canonical tree,
+// so the result does not depend on the launch shape.
+typedef _Float16 h2_t __attribute__((ext_vector_type(2)));
+
+template <int CPL>
+__device__ inline void query_f16(const float (&q)[CPL][8], h2_t (&qh)[CPL][4]) {
+#pragma unroll
+  for (int i = 0; i < CPL; ++i)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) qh[i][k] = h2_t{(_Float16)q[i][2 * k], (_Float16)q[i][2 * k + 1]};
+}
+
+// The mantissa m of a positive scale s = 2^e m, as an f16 pair.
+__device__ inline h2_t scale_mantissa(float s) {
+  const _Float16 m = (_Float16)__uint_as_float((__float_as_uint(s) & 0x007fffffu) | 0x3f800000u);
+  return h2_t{m, m};
+}
+
+__device__ inline float fp8_chunk_l2(const uint2 w, const h2_t (&qh)[4], float s, h2_t nm) {
+  const h2_t x0 = __builtin_amdgcn_cvt_scalef32_pk_f16_fp8(w.x, s, false);
+  const h2_t x1 = __builtin_amdgcn_cvt_scalef32_pk_f16_fp8(w.x, s, true);
+  const h2_t x2 = __builtin_amdgcn_cvt_scalef32_pk_f16_fp8(w.y, s, false);
+  const h2_t x3 = __builtin_amdgcn_cvt_scalef32_pk_f16_fp8(w.y, s, true);
+  // nm = -m: t = q - m x in one rounding
+  const h2_t t0 = __builtin_elementwise_fma(nm, x0, qh[0]);
+  const h2_t t1 = __builtin_elementwise_fma(nm, x1, qh[1]);
+  const h2_t t2 = __builtin_elementwise_fma(nm, x2, qh[2]);
+  const h2_t t3 = __builtin_elementwise_fma(nm, x3, qh[3]);
+  float acc = __builtin_amdgcn_fdot2(t0, t0, 0.0f, false);
+  acc = __builtin_amdgcn_fdot2(t1, t1, acc, false);
+  acc = __builtin_amdgcn_fdot2(t2, t2, acc, false);
+  return __builtin_amdgcn_fdot2(t3, t3, acc, false);
+}
+
+__device__ inline float fp8_chunk_ip(const uint2 w, const h2_t (&qh)[4]) {
+  const h2_t x0 = __builtin_amdgcn_cvt_scalef32_pk_f16_fp8(w.x, 1.0f, false);
+  const h2_t x1 = __builtin_amdgcn_cvt_scalef32_pk_f16_fp8(w.x, 1.0f, true);
+  const h2_t x2 = __builtin_amdgcn_cvt_scalef32_pk_f16_fp8(w.y, 1.0f, false);
+  const h2_t x3 = __builtin_amdgcn_cvt_scalef32_pk_f16_fp8(w.y, 1.0f, true);
+  float acc = __builtin_amdgcn_fdot2(qh[0], x0, 0.0f, false);
+  acc = __builtin_amdgcn_fdot2(qh[1], x1, acc, false);
+  acc = __builtin_amdgcn_fdot2(qh[2], x2, acc, false);
+  return __builtin_amdgcn_fdot2(qh[3], x3, acc, false);
+}
+
+// One chunk's partial distance in the traversal: the canonical FP32 sum
+// (henn_device.h) for FP32 and BF16 rows, the f16 form above for FP8 rows.
+template <int KIND>
+__device__ inline float traversal_chunk(const ChunkRaw<KIND>& raw, const float (&q)[8],
+                                        const h2_t (&qh)[4], float sc, h2_t nm, int metric) {
+  if constexpr (KIND == kFP8) {
+    return metric == 0 ? fp8_chunk_l2(raw.a, qh, sc, nm) : fp8_chunk_ip(raw.a, qh);
+  } else {
+    float x[8];
+    raw.decode(x);
+    return metric == 0 ? chunk_l2(q, x, 1.0f, false) : chunk_ip(q, x);
+  }
+}
+
 // One gather pass: rows [base, base + NR * G) of this expansion's fresh
-// candidates (cid / csc), their distances, and their keys into ckey.
-template <int KIND, int LPN, int CPL, int NR>
+// candidates (crow / cidk / csc), their distances, and their keys into ckey.
+// FULL: the row has exactly LPN * CPL chunks, so lane t's chunks
+// t * CPL .. t * CPL + CPL - 1 are contiguous and read at constant offsets
+// from one pointer; otherwise chunk indices past the row are clamped to
+// chunk 0 and their sums dropped (group_distances).  Every lane of the
+// wave takes part (butterflies); a slot at or past cnt computes the pass's
+// first row again and writes nothing.  Distances are the canonical sums of
+// henn_device.h.
+template <int KIND, int LPN, int CPL, int NR, bool FULL>
 __device__ inline void gather_pass(const SearchArgs& a, const SearchLayer& L,
-                                   const float (&q)[CPL][8], const WaveLds& s, const float* csc,
-                                   int base, int cnt, int t, int g) {
+                                   const float (&q)[CPL][8], const h2_t (&qh)[CPL][4],
+                                   const WaveLds& s, const float* csc, int base, int cnt, int t,
+                                   int g) {
   constexpr int G = 64 / LPN;
+  constexpr int CB = KIND == kF32 ? 32 : KIND == kBF16 ? 16 : 8;  // bytes per chunk
+  const char* vec = static_cast<const char*>(L.vec);
   const void* rows[NR];
   float sc[NR];
   bool vd[NR];
-  int32_t ids[NR];
+  uint32_t idk[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     const int ci = base + r * G + g;
     vd[r] = ci < cnt;
-    ids[r] = s.cid[vd[r] ? ci : base];
-    sc[r] = (KIND == kFP8) ? csc[vd[r] ? ci : base] : 1.0f;
-    rows[r] = static_cast<const char*>(L.vec) + (int64_t)ids[r] * L.row_bytes;
+    // an empty slot re-reads the pass's first row, which its group reads anyway
+    const int e = vd[r] ? ci : base;
+    const uint32_t ch = s.crow[e] + (FULL ? (uint32_t)(t * CPL) : 0u);
+    rows[r] = vec + (size_t)ch * CB;
+    idk[r] = s.cidk[e];
+    sc[r] = (KIND == kFP8) ? csc[e] : 1.0f;
   }
-  if constexpr (LPN >= 2 && NR >= 2) {
-    // rows 0 and 1 in one butterfly: lane t = 0 writes row 0, t = 1 row 1
-    float d01, d2 = 0.0f;
-    group_distances_paired<KIND, LPN, CPL, NR>(q, rows, sc, t, a.nchunks, a.metric, vd, d01, d2);
-    if (t < 2 && (t ? vd[1] : vd[0])) s.ckey[base + t * G + g] = wkey(d01, t ? ids[1] : ids[0]);
-    if (NR == 3 && t == 0 && vd[NR - 1]) s.ckey[base + (NR - 1) * G + g] = wkey(d2, ids[NR - 1]);
-  } else {
-    float dist[NR];
-    group_distances<KIND, LPN, CPL, NR>(q, rows, sc, t, a.nchunks, a.metric, vd, dist);
-    if (t == 0) {
+  // FP8: minus the mantissa of each row's scale (fp8_chunk_l2)
+  h2_t nm[NR];
 #pragma unroll
-      for (int r = 0; r < NR; ++r)
-        if (vd[r]) s.ckey[base + r * G + g] = wkey(dist[r], ids[r]);
+  for (int r = 0; r < NR; ++r) nm[r] = (KIND == kFP8) ? -scale_mantissa(sc[r]) : h2_t{0, 0};
+  // this lane's chunk sums of each row (tree over its CPL chunks)
+  float ts[NR];
+  if constexpr (FULL) {
+    ChunkRaw<KIND> raw[NR][CPL];
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int i = 0; i < CPL; ++i) raw[r][i].fetch(rows[r], i);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      float part[CPL];
+#pragma unroll
+      for (int i = 0; i < CPL; ++i)
+        part[i] = traversal_chunk<KIND>(raw[r][i], q[i], qh[i], sc[r], nm[r], a.metric);
+      ts[r] = tree_sum<CPL>(part);
+    }
+  } else {
+    ChunkRaw<KIND> raw[NR][CPL];
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int i = 0; i < CPL; ++i) {
+        const int c = t * CPL + i;
+        raw[r][i].fetch(rows[r], c < a.nchunks ? c : 0);
+      }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      float part[CPL];
+#pragma unroll
+      for (int i = 0; i < CPL; ++i) {
+        const int c = t * CPL + i;
+        const float v = traversal_chunk<KIND>(raw[r][i], q[i], qh[i], sc[r], nm[r], a.metric);
+        part[i] = c < a.nchunks ? v : 0.0f;
+      }
+      ts[r] = tree_sum<CPL>(part);
+    }
+  }
+  // lane-group sums; rows 2p and 2p + 1 share one butterfly
+  // (group_distances_paired): the even lanes of a group end with row 2p's
+  // sum, the odd lanes with row 2p + 1's
+  constexpr int NP = (LPN >= 2) ? NR / 2 : 0;  // row pairs
+  const bool odd = (lane_id() & 1) != 0;
+  float d[NR];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    float v = (odd ? ts[2 * p + 1] : ts[2 * p]) + dpp_mov<0xB1>(odd ? ts[2 * p] : ts[2 * p + 1]);
+    d[2 * p] = group_sum_from2<LPN>(v);
+  }
+#pragma unroll
+  for (int r = 2 * NP; r < NR; ++r) d[r] = group_sum<LPN>(ts[r]);
+  // keys: (ordered distance bits << 32) | (id << 1).  Squared L2 distances
+  // are sums of squares, never negative or -0, so their ordered bits are
+  // the float bits with the sign bit set (ordered_bits on that range).
+  auto key_of = [&](float dist, float scale, uint32_t idk_) -> uint64_t {
+    uint32_t ob;
+    if (a.metric == 0) {
+      ob = __float_as_uint(dist) | 0x80000000u;
+    } else {
+      ob = ordered_bits((KIND == kFP8) ? -(scale * dist) : -dist);
+    }
+    return ((uint64_t)ob << 32) | idk_;
+  };
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    const int r = 2 * p + (odd ? 1 : 0);
+    if (t < 2 && vd[r]) s.ckey[base + r * G + g] = key_of(d[2 * p], sc[r], idk[r]);
+  }
+#pragma unroll
+  for (int r = 2 * NP; r < NR; ++r)
+    if (t == 0 && vd[r]) s.ckey[base + r * G + g] = key_of(d[r], sc[r], idk[r]);
+}
+
+// All gather passes of one expansion, each with every load of its rows in
+// flight together: up to kGatherRows * G rows per pass, the last pass sized
+// to the rows left.
+template <int KIND, int LPN, int CPL, bool FULL>
+__device__ inline void gather_all(const SearchArgs& a, const SearchLayer& L,
+                                  const float (&q)[CPL][8], const h2_t (&qh)[CPL][4],
+                                  const WaveLds& s, const float* csc, int cnt, int t, int g) {
+  constexpr int G = 64 / LPN;
+  static_assert(kGatherRows == 3, "pass sizes below");
+  for (int base = 0; base < cnt;) {
+    const int rest = cnt - base;
+    if (rest > 2 * G) {
+      gather_pass<KIND, LPN, CPL, 3, FULL>(a, L, q, qh, s, csc, base, cnt, t, g);
+      base += 3 * G;
+    } else if (rest > G) {
+      gather_pass<KIND, LPN, CPL, 2, FULL>(a, L, q, qh, s, csc, base, cnt, t, g);
+      base += 2 * G;
+    } else {
+      gather_pass<KIND, LPN, CPL, 1, FULL>(a, L, q, qh, s, csc, base, cnt, t, g);
+      base += G;
     }
   }
 }
 
-template <int KIND, int LPN, int CPL>
-__device__ bool advance(const SearchArgs& a, const float (&q)[CPL][8], WaveLds s, uint64_t* W,
-                        QState& st, int budget) {
+// Runs up to `budget` expansions from the current state (layer changes are
+// free).  Returns true once the layer-0 beam has no unexpanded entry; then
+// W (this wave's LDS list) holds the final list (st.wsize entries).  q: this
+// lane's FP32 query slice; qh: the same in f16 pairs (read by the FP8 form
+// only, which then never reads q).
+template <int KIND, int LPN, int CPL, bool FULL>
+__device__ bool advance(const SearchArgs& a, const float (&q)[CPL][8], const h2_t (&qh)[CPL][4],
+                        WaveLds s, uint64_t* W, QState& st, int budget) {
   constexpr int G = 64 / LPN;
   const int lane = lane_id(), t = lane % LPN, g = lane / LPN;
   const int vis_n = 1 << a.vis_bits;
@@ -469,6 +656,21 @@ __device__ bool advance(const SearchArgs& a, const float (&q)[CPL][8], WaveLds s
       const int vis_words = vis_n * a.vis_bytes / 4;
       const uint32_t empty = a.vis_bytes < 4 ? 0u : 0xffffffffu;
       for (int i = lane; i < vis_words; i += 64) static_cast<uint32_t*>(s.vis)[i] = empty;
+      if constexpr (KIND == kFP8) {
+        // the entry's distance in the traversal's own form: the one handed
+        // down (a root scan, or the first distance of the root) is the
+        // canonical FP32 sum, and the list's duplicate check compares keys
+        if (lane == 0) {
+          s.crow[0] = (uint32_t)st.cur * (uint32_t)a.nchunks;
+          s.cidk[0] = (uint32_t)st.cur << 1;
+          reinterpret_cast<float*>(s.kstage)[0] = L.scale[st.cur];
+        }
+        wave_sync();
+        gather_pass<KIND, LPN, CPL, 1, FULL>(a, L, q, qh, s, reinterpret_cast<float*>(s.kstage),
+                                             0, 1, t, g);
+        wave_sync();
+        st.cur_d = wkey_dist(uni_u64(s.ckey[0]));
+      }
       wave_sync();
       if (lane == 0) {
         W[0] = wkey(st.cur_d, st.cur);
@@ -525,29 +727,16 @@ __device__ bool advance(const SearchArgs& a, const float (&q)[CPL][8], WaveLds s
       // the scales ride in kstage, which is free until the merge below
       float* csc = reinterpret_cast<float*>(s.kstage);
       if (fresh) {
-        s.cid[rank_below(fm)] = u;
-        if (KIND == kFP8) csc[rank_below(fm)] = usc;
+        const int rb = rank_below(fm);
+        s.crow[rb] = (uint32_t)u * (uint32_t)a.nchunks;
+        s.cidk[rb] = (uint32_t)u << 1;
+        if (KIND == kFP8) csc[rb] = usc;
       }
       wave_sync();
       st.evals += cnt;
 
-      // gather + distance, kGatherRows * G rows per pass with all their loads
-      // in flight together (an empty slot re-reads the pass's first row); the
-      // last pass takes only as many rows per group as the rest needs
-      static_assert(kGatherRows == 3, "the pass sizes below assume three rows");
-      for (int base = 0; base < cnt;) {
-        const int rest = cnt - base;
-        if (rest > 2 * G) {
-          gather_pass<KIND, LPN, CPL, 3>(a, L, q, s, csc, base, cnt, t, g);
-          base += 3 * G;
-        } else if (rest > G) {
-          gather_pass<KIND, LPN, CPL, 2>(a, L, q, s, csc, base, cnt, t, g);
-          base += 2 * G;
-        } else {
-          gather_pass<KIND, LPN, CPL, 1>(a, L, q, s, csc, base, cnt, t, g);
-          base += G;
-        }
-      }
+      // gather + distance
+      gather_all<KIND, LPN, CPL, FULL>(a, L, q, qh, s, csc, cnt, t, g);
       wave_sync();
 
       // merge the new keys into W (truncated to efl)
@@ -695,15 +884,19 @@ __device__ void finish_query(const SearchArgs& a, const float (&q)[CPL][8], uint
   wave_sync();
 }
 
-template <int KIND, int LPN, int CPL>
+template <int KIND, int LPN, int CPL, bool FULL>
 __device__ void search_one(const SearchArgs& a, int64_t qi, WaveLds s) {
   const int t = lane_id() % LPN;
   float q[CPL][8];
   load_query<CPL>(a.Q + qi * a.d, a.d, t, q);
   QState st;
   start_query<KIND, LPN, CPL>(a, qi, q, st);
+  h2_t qh[CPL][4];
+  if constexpr (KIND == kFP8) query_f16<CPL>(q, qh);
   uint64_t* W = s.W;
-  advance<KIND, LPN, CPL>(a, q, s, W, st, 0x7fffffff);
+  advance<KIND, LPN, CPL, FULL>(a, q, qh, s, W, st, 0x7fffffff);
+  // the FP8 traversal holds only the f16 query; the FP32 re-rank reads it again
+  if constexpr (KIND == kFP8) load_query<CPL>(a.Q + qi * a.d, a.d, t, q);
   finish_query<KIND, LPN, CPL>(a, q, W, st, a.out_ids + qi * a.k_max,
                                a.out_dist + qi * a.k_max,
                                a.counters ? a.counters + qi * 4 : nullptr);
@@ -717,9 +910,9 @@ __device__ void search_one(const SearchArgs& a, int64_t qi, WaveLds s) {
 // finishes appends its slot and result row to the tick's compact completion
 // list.  The traversal is the batch kernel's own code, so
 // a request's result does not depend on which others share its ticks.
-template <int KIND, int LPN, int CPL>
-__global__ __launch_bounds__(512) void k_serve_step(SearchArgs a, ServeArgs sv, int per_wave_bytes,
-                                                    int waves_per_block) {
+template <int KIND, int LPN, int CPL, bool FULL>
+__device__ __forceinline__ void serve_step_body(const SearchArgs& a, const ServeArgs& sv,
+                                                int per_wave_bytes, int waves_per_block) {
   extern __shared__ __align__(16) char smem[];
   const int wave = threadIdx.x >> 6;
   const int64_t idx = (int64_t)blockIdx.x * waves_per_block + wave;
@@ -750,8 +943,11 @@ __global__ __launch_bounds__(512) void k_serve_step(SearchArgs a, ServeArgs sv, 
     wave_sync();
   }
   uint64_t* W = s.W;
-  const bool done = advance<KIND, LPN, CPL>(a, q, s, W, st, sv.budget);
+  h2_t qh[CPL][4];
+  if constexpr (KIND == kFP8) query_f16<CPL>(q, qh);
+  const bool done = advance<KIND, LPN, CPL, FULL>(a, q, qh, s, W, st, sv.budget);
   if (done) {
+    if constexpr (KIND == kFP8) load_query<CPL>(a.Q + (int64_t)slot * a.d, a.d, t, q);
     // finished: append (slot, row) to this tick's compact completion list
     int pos = 0;
     if (lane == 0) pos = atomicAdd(sv.done_count, 1);
@@ -768,7 +964,33 @@ __global__ __launch_bounds__(512) void k_serve_step(SearchArgs a, ServeArgs sv, 
   if (lane == 0) sv.states[slot] = st;
 }
 
-__global__ void k_serve_admit(const float* staged_q, const int32_t* meta, int n_new, int d,
+template <int KIND, int LPN, int CPL, bool FULL>
+__global__ __launch_bounds__(512) void k_serve_step(SearchArgs a, ServeArgs sv, int per_wave_bytes,
+                                                    int waves_per_block) {
+  serve_step_body<KIND, LPN, CPL, FULL>(a, sv, per_wave_bytes, waves_per_block);
+}
+
+// The FP8 form with at most two chunks per lane fits 80 registers without
+// spilling in the traversal loop; held to that, six waves share a SIMD (the
+// LDS of a wave at the usual beam widths also allows six).
+template <int KIND, int CPL>
+constexpr bool six_waves() { return KIND == kFP8 && CPL <= 2; }
+
+template <int KIND, int LPN, int CPL, bool FULL>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6))) void k_serve_step6(
+    SearchArgs a, ServeArgs sv, int per_wave_bytes, int waves_per_block) {
+  serve_step_body<KIND, LPN, CPL, FULL>(a, sv, per_wave_bytes, waves_per_block);
+}
+
+template <int KIND, int LPN, int CPL, bool FULL>
+static auto serve_kernel() {
+  if constexpr (six_waves<KIND, CPL>())
+    return &k_serve_step6<KIND, LPN, CPL, FULL>;
+  else
+    return &k_serve_step<KIND, LPN, CPL, FULL>;
+}
+
+static __global__ void k_serve_admit(const float* staged_q, const int32_t* meta, int n_new, int d,
                               float* slot_q, int32_t* slot_k, int32_t* slot_ef,
                               int64_t* state_off, int32_t* cap, QState* states,
                               const uint64_t* root_keys, uint64_t* slot_root) {
@@ -792,17 +1014,18 @@ __global__ void k_serve_admit(const float* staged_q, const int32_t* meta, int n_
   }
 }
 
-template <int KIND, int LPN, int CPL>
+template <int KIND, int LPN, int CPL, bool FULL>
 static void launch_serve_one(const SearchArgs& a, const ServeArgs& sv, int wpb, hipStream_t st) {
   const size_t per_wave = search_lds_per_wave(a.ef_cap, a.vis_bits, a.vis_bytes);
   const unsigned blocks = (unsigned)((sv.n_active + wpb - 1) / wpb);
-  hipLaunchKernelGGL((k_serve_step<KIND, LPN, CPL>), dim3(blocks), dim3(64 * wpb),
-                     per_wave * wpb, st, a, sv, (int)per_wave, wpb);
+  auto kern = serve_kernel<KIND, LPN, CPL, FULL>();
+  hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * wpb), per_wave * wpb, st, a, sv,
+                     (int)per_wave, wpb);
 }
 
-template <int KIND, int LPN, int CPL>
-__global__ __launch_bounds__(512) void k_search(SearchArgs a, int per_wave_bytes,
-                                                int waves_per_block, int persistent) {
+template <int KIND, int LPN, int CPL, bool FULL>
+__device__ __forceinline__ void search_kernel_body(const SearchArgs& a, int per_wave_bytes,
+                                                   int waves_per_block, int persistent) {
   extern __shared__ __align__(16) char smem[];
   const int wave = threadIdx.x >> 6;
   WaveLds s = carve(smem + (size_t)wave * per_wave_bytes, a.ef_cap, a.vis_bits, a.vis_bytes);
@@ -812,21 +1035,43 @@ __global__ __launch_bounds__(512) void k_search(SearchArgs a, int per_wave_bytes
       if (lane_id() == 0) qi = atomicAdd(a.work_counter, 1u);
       qi = (uint32_t)uni((int32_t)qi);
       if ((int64_t)qi >= a.nq) break;
-      search_one<KIND, LPN, CPL>(a, (int64_t)qi, s);
+      search_one<KIND, LPN, CPL, FULL>(a, (int64_t)qi, s);
     }
   } else {
     const int64_t qi = (int64_t)blockIdx.x * waves_per_block + wave;
-    if (qi < a.nq) search_one<KIND, LPN, CPL>(a, qi, s);
+    if (qi < a.nq) search_one<KIND, LPN, CPL, FULL>(a, qi, s);
   }
 }
 
-__global__ void k_reset_counter(uint32_t* c) { *c = 0u; }
+template <int KIND, int LPN, int CPL, bool FULL>
+__global__ __launch_bounds__(512) void k_search(SearchArgs a, int per_wave_bytes,
+                                                int waves_per_block, int persistent) {
+  search_kernel_body<KIND, LPN, CPL, FULL>(a, per_wave_bytes, waves_per_block, persistent);
+}
 
-template <int KIND, int LPN, int CPL>
+// The same kernel held to 80 registers (see six_waves).
+template <int KIND, int LPN, int CPL, bool FULL>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6))) void k_search6(
+    SearchArgs a, int per_wave_bytes, int waves_per_block, int persistent) {
+  search_kernel_body<KIND, LPN, CPL, FULL>(a, per_wave_bytes, waves_per_block, persistent);
+}
+
+template <int KIND, int LPN, int CPL, bool FULL>
+static auto search_kernel() {
+  if constexpr (six_waves<KIND, CPL>())
+    return &k_search6<KIND, LPN, CPL, FULL>;
+  else
+    return &k_search<KIND, LPN, CPL, FULL>;
+}
+
+static __global__ void k_reset_counter(uint32_t* c) { *c = 0u; }
+
+template <int KIND, int LPN, int CPL, bool FULL>
 static void launch_one(const SearchArgs& a, const LaunchShape& sh, hipStream_t st) {
   const size_t per_wave = search_lds_per_wave(a.ef_cap, a.vis_bits, a.vis_bytes);
   const int wpb = sh.waves_per_block;
   const size_t lds = per_wave * wpb;
+  auto kern = search_kernel<KIND, LPN, CPL, FULL>();
   if (sh.persistent) {
     int blocks = sh.blocks;
     if (blocks <= 0) {
@@ -834,16 +1079,15 @@ static void launch_one(const SearchArgs& a, const LaunchShape& sh, hipStream_t s
       (void)hipGetDevice(&dev);
       (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
       (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &per_cu, reinterpret_cast<const void*>(&k_search<KIND, LPN, CPL>), 64 * wpb, lds);
+          &per_cu, reinterpret_cast<const void*>(kern), 64 * wpb, lds);
       blocks = max(1, cus * max(per_cu, 1));
     }
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, st, a.work_counter);
-    hipLaunchKernelGGL((k_search<KIND, LPN, CPL>), dim3(blocks), dim3(64 * wpb), lds, st, a,
-                       (int)per_wave, wpb, 1);
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * wpb), lds, st, a, (int)per_wave, wpb, 1);
   } else {
     const int64_t blocks = (a.nq + wpb - 1) / wpb;
-    hipLaunchKernelGGL((k_search<KIND, LPN, CPL>), dim3((unsigned)blocks), dim3(64 * wpb), lds,
-                       st, a, (int)per_wave, wpb, 0);
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * wpb), lds, st, a, (int)per_wave,
+                       wpb, 0);
   }
 }
 
@@ -855,7 +1099,10 @@ template <int KIND>
 static bool dispatch(const SearchArgs& a, const LaunchShape& sh, hipStream_t st) {
 #define HENN_TRY(LPN, CPL)                              \
   if (sh.lanes_per_vec == LPN && sh.chunks_per_lane == CPL) { \
-    launch_one<KIND, LPN, CPL>(a, sh, st);              \
+    if (a.nchunks == LPN * CPL)                         \
+      launch_one<KIND, LPN, CPL, true>(a, sh, st);      \
+    else                                                \
+      launch_one<KIND, LPN, CPL, false>(a, sh, st);     \
     return true;                                        \
   }
   HENN_SEARCH_COMBOS(HENN_TRY)
@@ -863,21 +1110,40 @@ static bool dispatch(const SearchArgs& a, const LaunchShape& sh, hipStream_t st)
   return false;
 }
 
-bool launch_search(int storage, const SearchArgs& a, const LaunchShape& s, hipStream_t st) {
-  switch (storage) {
-    case kF32: return dispatch<kF32>(a, s, st);
-    case kBF16: return dispatch<kBF16>(a, s, st);
-    case kFP8: return dispatch<kFP8>(a, s, st);
-    default: return false;
-  }
+#if HENN_COMMON_PART
+// The gather addresses a row by its 32-bit first-chunk index.
+bool rows_addressable(const SearchArgs& a) {
+  for (int i = 0; i < a.num_layers; ++i)
+    if ((int64_t)a.layer[i].size * a.nchunks >= (1ll << 32)) return false;
+  return true;
 }
+#endif
+
+#if HENN_KIND_PART(0)  // kF32
+bool launch_search_f32(const SearchArgs& a, const LaunchShape& s, hipStream_t st) {
+  return dispatch<kF32>(a, s, st);
+}
+#endif
+#if HENN_KIND_PART(1)  // kBF16
+bool launch_search_bf16(const SearchArgs& a, const LaunchShape& s, hipStream_t st) {
+  return dispatch<kBF16>(a, s, st);
+}
+#endif
+#if HENN_KIND_PART(2)  // kFP8
+bool launch_search_fp8(const SearchArgs& a, const LaunchShape& s, hipStream_t st) {
+  return dispatch<kFP8>(a, s, st);
+}
+#endif
 
 template <int KIND>
 static bool dispatch_serve(const SearchArgs& a, const ServeArgs& sv, const LaunchShape& sh,
                            hipStream_t st) {
 #define HENN_TRY(LPN, CPL)                                        \
   if (sh.lanes_per_vec == LPN && sh.chunks_per_lane == CPL) {     \
-    launch_serve_one<KIND, LPN, CPL>(a, sv, sh.waves_per_block, st); \
+    if (a.nchunks == LPN * CPL)                                   \
+      launch_serve_one<KIND, LPN, CPL, true>(a, sv, sh.waves_per_block, st);  \
+    else                                                          \
+      launch_serve_one<KIND, LPN, CPL, false>(a, sv, sh.waves_per_block, st); \
     return true;                                                  \
   }
   HENN_SEARCH_COMBOS(HENN_TRY)
@@ -885,13 +1151,44 @@ static bool dispatch_serve(const SearchArgs& a, const ServeArgs& sv, const Launc
   return false;
 }
 
+#if HENN_KIND_PART(0)  // kF32
+bool launch_serve_f32(const SearchArgs& a, const ServeArgs& sv, const LaunchShape& sh,
+                      hipStream_t st) {
+  return dispatch_serve<kF32>(a, sv, sh, st);
+}
+#endif
+#if HENN_KIND_PART(1)  // kBF16
+bool launch_serve_bf16(const SearchArgs& a, const ServeArgs& sv, const LaunchShape& sh,
+                       hipStream_t st) {
+  return dispatch_serve<kBF16>(a, sv, sh, st);
+}
+#endif
+#if HENN_KIND_PART(2)  // kFP8
+bool launch_serve_fp8(const SearchArgs& a, const ServeArgs& sv, const LaunchShape& sh,
+                      hipStream_t st) {
+  return dispatch_serve<kFP8>(a, sv, sh, st);
+}
+#endif
+
+#if HENN_COMMON_PART
+bool launch_search(int storage, const SearchArgs& a, const LaunchShape& s, hipStream_t st) {
+  if (!rows_addressable(a)) return false;
+  switch (storage) {
+    case kF32: return launch_search_f32(a, s, st);
+    case kBF16: return launch_search_bf16(a, s, st);
+    case kFP8: return launch_search_fp8(a, s, st);
+    default: return false;
+  }
+}
+
 bool launch_serve_step(int storage, const SearchArgs& a, const ServeArgs& sv,
                        const LaunchShape& sh, hipStream_t st) {
   if (sv.n_active <= 0) return true;
+  if (!rows_addressable(a)) return false;
   switch (storage) {
-    case kF32: return dispatch_serve<kF32>(a, sv, sh, st);
-    case kBF16: return dispatch_serve<kBF16>(a, sv, sh, st);
-    case kFP8: return dispatch_serve<kFP8>(a, sv, sh, st);
+    case kF32: return launch_serve_f32(a, sv, sh, st);
+    case kBF16: return launch_serve_bf16(a, sv, sh, st);
+    case kFP8: return launch_serve_fp8(a, sv, sh, st);
     default: return false;
   }
 }
@@ -906,16 +1203,14 @@ void launch_serve_admit(const float* staged_q, const int32_t* meta, int n_new, i
 }
 
 template <int KIND>
-static bool launch_root_check_kind(const SearchArgs& a, const RootAux& r, int splits,
-                                   const float* sl_d, const int32_t* sl_i, uint64_t* out,
-                                   hipStream_t st) {
+static bool launch_root_check_kind(const SearchArgs& a, int splits, const RootShortlist& sl,
+                                   uint64_t* out, hipStream_t st) {
   int lpn = 0, cpl = 0;
   pick_lanes(a.nchunks, 0, &lpn, &cpl);
   const dim3 grid((unsigned)((a.nq + 3) / 4));
 #define HENN_TRY(L, C)                                                                       \
   if (lpn == L && cpl == C) {                                                                \
-    hipLaunchKernelGGL((k_root_check<KIND, L, C>), grid, dim3(256), 0, st, a, r, splits, sl_d, \
-                       sl_i, out);                                                           \
+    hipLaunchKernelGGL((k_root_check<KIND, L, C>), grid, dim3(256), 0, st, a, splits, sl, out); \
     return true;                                                                             \
   }
   HENN_TRY(1, 1) HENN_TRY(2, 1) HENN_TRY(4, 1) HENN_TRY(2, 2) HENN_TRY(4, 2) HENN_TRY(8, 1)
@@ -924,13 +1219,13 @@ static bool launch_root_check_kind(const SearchArgs& a, const RootAux& r, int sp
   return false;
 }
 
-bool launch_root_check(int storage, const SearchArgs& a, const RootAux& r, int splits,
-                       const float* sl_d, const int32_t* sl_i, uint64_t* out, hipStream_t st) {
+bool launch_root_check(int storage, const SearchArgs& a, int splits, const RootShortlist& sl,
+                       uint64_t* out, hipStream_t st) {
   if (a.nq <= 0) return true;
   switch (storage) {
-    case kF32: return launch_root_check_kind<kF32>(a, r, splits, sl_d, sl_i, out, st);
-    case kBF16: return launch_root_check_kind<kBF16>(a, r, splits, sl_d, sl_i, out, st);
-    case kFP8: return launch_root_check_kind<kFP8>(a, r, splits, sl_d, sl_i, out, st);
+    case kF32: return launch_root_check_kind<kF32>(a, splits, sl, out, st);
+    case kBF16: return launch_root_check_kind<kBF16>(a, splits, sl, out, st);
+    case kFP8: return launch_root_check_kind<kFP8>(a, splits, sl, out, st);
     default: return false;
   }
 }
@@ -957,5 +1252,6 @@ void pick_lanes(int nchunks, int requested_lpn, int* lpn, int* cpl) {
   *lpn = best_l;
   *cpl = best_c;
 }
+#endif  // HENN_COMMON_PART
 
 }  // namespace henn

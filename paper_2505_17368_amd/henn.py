@@ -326,7 +326,7 @@ def henn_nsw_insert(V, adj, lo: int, hi: int, degree: int, ef_construction: int,
 def search_params(k=10, ef=32, k_arr=None, ef_arr=None, k_max=None, ef_max=None, ef_upper=1,
                   rerank_factor=4, counters=None, persistent=False, lanes_per_vec=0,
                   waves_per_block=0, root_kernel=True, events=None,
-                  vis_bits=0, vis32=False, vis16=False) -> SearchParams:
+                  vis_bits=0, vis32=False, vis16=False, workspace=None) -> SearchParams:
     sp = SearchParams()
     _check(load_library().henn_default_search_params(ctypes.byref(sp)))
     sp.k_all = k
@@ -353,14 +353,27 @@ def search_params(k=10, ef=32, k_arr=None, ef_arr=None, k_max=None, ef_max=None,
     if events is not None:
         sp.ev_begin = events[0].cuda_event
         sp.ev_end = events[1].cuda_event
+    if workspace is not None:
+        sp.workspace = workspace.data_ptr()
+        sp.workspace_bytes = workspace.numel() * workspace.element_size()
     return sp
+
+
+def workspace_size(index: HennIndex, nq: int, **kw) -> int:
+    """Scratch bytes henn_search_batch needs for nq queries with these
+    search arguments (see search_params)."""
+    sp = search_params(**kw)
+    b = ctypes.c_int64()
+    _check(load_library().henn_search_workspace_size(index.handle, nq, ctypes.byref(sp),
+                                                     ctypes.byref(b)))
+    return b.value
 
 
 def henn_search_batch(index: HennIndex, Q, k=10, ef=32, k_arr=None, ef_arr=None, k_max=None,
                       ef_max=None, ef_upper=1, rerank_factor=4, with_counters=False,
                       persistent=False, lanes_per_vec=0, waves_per_block=0, root_kernel=True,
                       events=None, vis_bits=0, out_ids=None, out_dist=None, stream=None,
-                      vis32=False, vis16=False, noalloc=False):
+                      vis32=False, vis16=False, noalloc=False, workspace=None):
     """Enqueues a batched search; returns (ids, dist[, counters]) device tensors.
     ``noalloc``: call henn_search_batch_noalloc (the library's fixed scratch;
     pass out_ids / out_dist to keep the call free of allocations here too).
@@ -380,7 +393,7 @@ def henn_search_batch(index: HennIndex, Q, k=10, ef=32, k_arr=None, ef_arr=None,
     counters = torch.zeros((nq, 4), dtype=torch.int32, device=Q.device) if with_counters else None
     sp = search_params(k, ef, k_arr, ef_arr, kmax, ef_max, ef_upper, rerank_factor, counters,
                        persistent, lanes_per_vec, waves_per_block, root_kernel, events,
-                       vis_bits, vis32, vis16)
+                       vis_bits, vis32, vis16, workspace)
     entry = load_library().henn_search_batch_noalloc if noalloc else \
         load_library().henn_search_batch
     _check(entry(index.handle, ctypes.c_void_p(Q.data_ptr()), nq, ctypes.byref(sp),
