@@ -994,7 +994,7 @@ static int root_mode(const henn_index* idx, const henn_search_params* sp) {
 
 // Scratch layout: 256 B (persistent work counter), then for mode 1 the
 // [splits][nq] root keys, for mode 2 the [nq] root keys and the Gram
-// shortlists (values, then positions).
+// shortlists (RootShortlist).
 static int64_t search_workspace_bytes(const henn_index* idx, int64_t nq,
                                       const henn_search_params* sp) {
   int64_t b = 256;
@@ -1005,8 +1005,7 @@ static int64_t search_workspace_bytes(const henn_index* idx, int64_t nq,
       b += (int64_t)sizeof(uint64_t) * root_scan_splits(nq, rs, &per) * nq;
       break;
     case 2:
-      b += (int64_t)sizeof(uint64_t) * nq +
-           root_shortlist_bytes(root_gram_splits(nq, rs, &per), nq, idx->root.kp);
+      b += (int64_t)sizeof(uint64_t) * nq + root_shortlist_bytes(nq, idx->root.kp);
       break;
     default:
       break;
@@ -1139,9 +1138,9 @@ static henn_status search_impl(const henn_index* idx, const float* Q, int64_t nq
       int64_t per = 0;
       const int splits = root_gram_splits(nq, idx->root.size, &per);
       uint64_t* root_best = reinterpret_cast<uint64_t*>(ws + 256);
-      const RootShortlist sl = root_shortlist_at(root_best + nq, splits, nq, idx->root.kp);
+      const RootShortlist sl = root_shortlist_at(root_best + nq, nq, idx->root.kp);
       launch_root_gram(Q, nq, idx->d, idx->root, idx->dpad, idx->metric, splits, per, sl, st);
-      if (!launch_root_check(idx->storage, a, splits, sl, root_best, st)) {
+      if (!launch_root_check(idx->storage, a, sl, root_best, st)) {
         if (ws_owned) (void)hipFreeAsync(ws, st);
         return fail(HENN_E_UNSUPPORTED, "no root check kernel for this shape");
       }

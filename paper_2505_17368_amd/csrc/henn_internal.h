@@ -66,23 +66,25 @@ struct RootAux {
   float* normp = nullptr;
   int kp = 0;
 };
-// Gram shortlist of a complete-root scan.  Per (root split, query) the
-// rows whose Gram value lies within the query's margin mq of the split's
-// smallest Gram value: up to kRootCap of them in val / row, and their full
-// number in cnt (above kRootCap: the list overflowed and the check scans
-// the root).  qb holds each query's BF16 Gram operand.
-constexpr int kRootCap = 16;
+// Gram shortlist of a complete-root scan, one per query: the rows whose
+// Gram value lies within the query's margin mq of a threshold at or above
+// the smallest Gram value over the root (each root split's pass uses the
+// smaller of its own smallest value and the query's running minimum qmin).
+// Up to kRootCap (value, root position) entries in ent, in no particular
+// order, and their full number in cnt (above kRootCap: the list overflowed
+// and the check scans the root).  qb holds each query's BF16 Gram operand.
+constexpr int kRootCap = 64;
 struct RootShortlist {
-  uint16_t* qb = nullptr;  // [nq][kp]: bf16 of -2 (q - mean) (L2) or -q (IP)
-  float* mq = nullptr;     // [nq]: the margin of each query
-  float* val = nullptr;    // [splits][nq][kRootCap]
-  int32_t* row = nullptr;  // same layout: root positions
-  int32_t* cnt = nullptr;  // [splits][nq]
+  uint16_t* qb = nullptr;   // [nq][kp]: bf16 of -2 (q - mean) (L2) or -q (IP)
+  float* mq = nullptr;      // [nq]: the margin of each query
+  uint32_t* qmin = nullptr; // [nq]: running minimum Gram value (ordered bits)
+  int32_t* cnt = nullptr;   // [nq]: rows listed
+  uint2* ent = nullptr;     // [nq][kRootCap]: (value bits, root position)
 };
-// Bytes of a shortlist for (splits, nq, kp), including 256 bytes of slack
-// for aligning its start.
-int64_t root_shortlist_bytes(int splits, int64_t nq, int kp);
-RootShortlist root_shortlist_at(void* base, int splits, int64_t nq, int kp);
+// Bytes of a shortlist for (nq, kp), including 256 bytes of slack for
+// aligning its start.
+int64_t root_shortlist_bytes(int64_t nq, int kp);
+RootShortlist root_shortlist_at(void* base, int64_t nq, int kp);
 
 // One autotuned launch shape, valid for a (storage, beam bucket, k bucket).
 struct TuneEntry {
@@ -267,8 +269,8 @@ void prepare_root_bf16(RootAux& r, int dpad, int metric, hipStream_t st);
 void launch_root_gram(const float* Q, int64_t nq, int d, const RootAux& r, int dpad, int metric,
                       int splits, int64_t rows_per_split, const RootShortlist& sl,
                       hipStream_t st);
-bool launch_root_check(int storage, const SearchArgs& a, int splits, const RootShortlist& sl,
-                       uint64_t* out, hipStream_t st);
+bool launch_root_check(int storage, const SearchArgs& a, const RootShortlist& sl, uint64_t* out,
+                       hipStream_t st);
 
 // ---- build ----------------------------------------------------------------
 void launch_copy_rows(const float* src, int64_t src_stride, const int32_t* ids, int64_t count,

@@ -566,13 +566,15 @@ int root_gram_splits(int64_t nq, int64_t root_size, int64_t* rows_per_split) {
 // operands come straight from memory (the root is L2-resident); the next
 // tile's loads are issued before the current tile is multiplied.
 //
-// Two passes over the split: the first keeps only the smallest Gram value,
-// the second appends every row within the query's margin M of the split's
-// smallest (normally a handful) to the lane's list.  The exact nearest is
-// within M of the smallest Gram value over the whole root, hence of every
-// split's, so the lists hold it.  M = (2^-7 + 2^-14 + 32 (dpad + 16) 2^-24)
-// N with N = |q - mean|^2 + max_y |y - mean|^2 + |mean|^2 (twice the sum of
-// the Gram and canonical error bounds, derived at k_root_check).
+// Two passes over the split: the first keeps only the smallest Gram value
+// and merges it into the query's running minimum over the splits; the
+// second appends every row within the query's margin M of the smaller of
+// the two (normally a handful) to the query's list.  The exact nearest is
+// within M of the smallest Gram value over the whole root, hence of any
+// larger threshold, so the list holds it.  M = (2^-7 + 2^-14 +
+// 32 (dpad + 16) 2^-24) N with N = |q - mean|^2 + max_y |y - mean|^2 +
+// |mean|^2 (twice the sum of the Gram and canonical error bounds, derived
+// at k_root_check).
 // ------------------------------------------------------------------------
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
@@ -602,25 +604,24 @@ void prepare_root_bf16(RootAux& r, int dpad, int metric, hipStream_t st) {
   HENN_HIP(hipGetLastError());
 }
 
-int64_t root_shortlist_bytes(int splits, int64_t nq, int kp) {
-  const int64_t lists = (int64_t)splits * nq;
-  return 256 + nq * kp * 2 + nq * 4 + lists * kRootCap * 8 + lists * 4;
+int64_t root_shortlist_bytes(int64_t nq, int kp) {
+  return 256 + nq * kp * 2 + nq * 12 + nq * kRootCap * 8;
 }
 
-RootShortlist root_shortlist_at(void* base, int splits, int64_t nq, int kp) {
-  const int64_t lists = (int64_t)splits * nq;
+RootShortlist root_shortlist_at(void* base, int64_t nq, int kp) {
   RootShortlist sl;
-  sl.qb = reinterpret_cast<uint16_t*>((reinterpret_cast<uintptr_t>(base) + 255) & ~uintptr_t(255));
+  sl.ent = reinterpret_cast<uint2*>((reinterpret_cast<uintptr_t>(base) + 255) & ~uintptr_t(255));
+  sl.qb = reinterpret_cast<uint16_t*>(sl.ent + nq * kRootCap);
   sl.mq = reinterpret_cast<float*>(sl.qb + nq * kp);
-  sl.val = sl.mq + nq;
-  sl.row = reinterpret_cast<int32_t*>(sl.val + lists * kRootCap);
-  sl.cnt = sl.row + lists * kRootCap;
+  sl.qmin = reinterpret_cast<uint32_t*>(sl.mq + nq);
+  sl.cnt = reinterpret_cast<int32_t*>(sl.qmin + nq);
   return sl;
 }
 
 // The Gram pass's query operand, once per query: eight coordinates per
 // thread (16 threads per query), centred on the root mean (L2), scaled by -2
-// (L2) or -1 (IP) and rounded to BF16, zero past d; and the query's margin
+// (L2) or -1 (IP) and rounded to BF16, zero past d; the empty list and the
+// running minimum at +inf; and the query's margin
 // M = (2^-7 + 2^-14 + 32 (dpad + 16) 2^-24) N with
 // N = |q - mean|^2 + max_y |y - mean|^2 + |mean|^2 (twice the sum of the
 // Gram and canonical error bounds, derived at k_root_check).
@@ -635,11 +636,22 @@ __global__ __launch_bounds__(256) void k_root_query_bf16(const float* Q, int64_t
   float qn = 0.0f;
   uint32_t w[4] = {0u, 0u, 0u, 0u};
   if (live) {
+    // loads clamped into the row and issued together; values past d dropped
+    float x[8], m[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) x[j] = Q[qi * d + min(8 * c + j, d - 1)];
+    if (mean) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) m[j] = mean[min(8 * c + j, d - 1)];
+    } else {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) m[j] = 0.0f;
+    }
 #pragma unroll
     for (int j = 0; j < 8; j += 2) {
       const int e0 = 8 * c + j, e1 = e0 + 1;
-      const float v0 = e0 < d ? Q[qi * d + e0] - (mean ? mean[e0] : 0.0f) : 0.0f;
-      const float v1 = e1 < d ? Q[qi * d + e1] - (mean ? mean[e1] : 0.0f) : 0.0f;
+      const float v0 = e0 < d ? x[j] - m[j] : 0.0f;
+      const float v1 = e1 < d ? x[j + 1] - m[j + 1] : 0.0f;
       qn = __builtin_fmaf(v0, v0, qn);
       qn = __builtin_fmaf(v1, v1, qn);
       w[j >> 1] = f32_to_bf16_rne(qscale * v0) | (f32_to_bf16_rne(qscale * v1) << 16);
@@ -648,10 +660,18 @@ __global__ __launch_bounds__(256) void k_root_query_bf16(const float* Q, int64_t
   }
 #pragma unroll
   for (int m = 8; m >= 1; m >>= 1) qn += __shfl_xor(qn, m);
-  if (qi < nq && c == 0)
+  if (qi < nq && c == 0) {
     sl.mq[qi] = (0x1p-7f + 0x1p-14f + 32.0f * (float)(dpad + 16) * 0x1p-24f) *
                 (qn + nmax + mean_n2);
+    sl.qmin[qi] = ordered_bits(INFINITY);
+    sl.cnt[qi] = 0;
+  }
 }
+
+template <int I>
+struct Ic {
+  static constexpr int value = I;
+};
 
 template <int S>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_root_gram_bf16(
@@ -675,113 +695,156 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   const float M = qvalid ? sl.mq[qrow] : 0.0f;
 
   // Tiles are staged in LDS, shared by the block's four waves, by the
-  // global-to-LDS copy of gfx950 (global_load_lds_dwordx4): instruction j of
-  // a tile moves 64 chunks of 16 bytes, slot p = 64 j + lane.  Slot p holds
-  // chunk (pos - row) mod 2S of tile row p / 2S, pos = p mod 2S: the
-  // rotation spreads the 16-byte reads of one step (one chunk of each of 32
-  // rows) over all banks.  The 32 norms ride along (wave 0, one dword per
-  // lane, lanes 32..63 repeating 0..31).  rows_per_split is a multiple of 32
-  // and the prepared rows are padded to a multiple of 32, so every tile row
+  // global-to-LDS copy of gfx950 (global_load_lds_dwordx4): one instruction
+  // moves 64 chunks of 16 bytes into 64 consecutive slots.  A tile row takes
+  // 2S + 1 slots (its 2S chunks, then one pad slot, so that the 32 rows of
+  // one step's reads fall on different banks), S + 1 instructions a tile,
+  // instruction j issued by wave j mod 4; pad slots receive a copy of the
+  // row's first chunk.  Each wave also copies 8 of the tile's 32 norms
+  // (lanes 0..7, one dword each).  rows_per_split is a multiple of 32 and
+  // the prepared rows are padded to a multiple of 32, so every tile row
   // below ce rounded up to 32 exists (rows at or past size carry norm +inf
-  // and never enter a list).  Two buffers in turn: the next tile's copy is
-  // in flight while the current one is multiplied.
-  __shared__ uint4 tileA[64 * S], tileB[64 * S];
-  __shared__ float normA[64], normB[64];
+  // and never enter a list).  Three buffers in a ring (the norms after the
+  // rows): the copies of the next two tiles are in flight while one is
+  // multiplied.
+  constexpr int kRowSlots = 2 * S + 1;
+  constexpr int kTileU4 = 64 * (S + 1);  // >= 32 * kRowSlots
+  constexpr int kBufU4 = kTileU4 + 8;
+  __shared__ uint4 buf0[kBufU4], buf1[kBufU4], buf2[kBufU4];
+  auto buf_of = [&](auto I) -> uint4* {
+    if constexpr (decltype(I)::value == 0) return buf0;
+    else if constexpr (decltype(I)::value == 1) return buf1;
+    else return buf2;
+  };
   typedef __attribute__((address_space(3))) void* lds_ptr;
-  auto issue = [&](int64_t c0, uint4* tile, float* nrm) {
-    for (int j = wave; j < S; j += 4) {
-      const int p = 64 * j + lane, row = p / (2 * S), pos = p - row * (2 * S);
-      const int chunk = (pos - row % (2 * S) + 2 * S) % (2 * S);
-      __builtin_amdgcn_global_load_lds(rowb + (c0 + row) * kp + 8 * chunk, (lds_ptr)(tile + 64 * j),
-                                       16, 0, 0);
-    }
-    if (wave == 0)
-      __builtin_amdgcn_global_load_lds(normp + c0 + (lane & 31), (lds_ptr)nrm, 4, 0, 0);
-  };
-  // waits for this wave's copies, then for every wave's (the barrier)
-  auto arrive = [&]() {
-    __builtin_amdgcn_s_waitcnt(0xF70);  // vmcnt(0), other counters untouched
-    __syncthreads();
-  };
-  // one tile's Gram values; val[v] belongs to root row c0 + 8 (v >> 2) + 4 h + (v & 3)
-  auto gram = [&](const uint4* tile, const float* nrm, float (&val)[16]) {
-    floatx16 acc;
+  // this wave's copy instructions j = wave, wave + 4, ... < S + 1 (at most
+  // three); a lane's source offset within the tile depends on (j, lane) only
+  constexpr int kMaxJ = (S + 4) / 4;
+  const int per_tile = (S + 1 - wave + 3) / 4 + 1;  // copy instructions of this wave per tile
+  auto issue = [&](int64_t c0, uint4* tile) {
+    const uint16_t* src = rowb + c0 * kp;
 #pragma unroll
-    for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-      const int chunk = 2 * s + h;
-      const uint4 a = tile[qc * (2 * S) + (chunk + qc) % (2 * S)];
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), bq[s], acc, 0,
-                                                    0, 0);
+    for (int u = 0; u < kMaxJ; ++u) {
+      const int j = wave + 4 * u;
+      if (j < S + 1) {
+        const int p = 64 * j + lane, r = p / kRowSlots, c = p - r * kRowSlots;
+        const int off = min(r, 31) * kp + 8 * ((p < 32 * kRowSlots && c < 2 * S) ? c : 0);
+        __builtin_amdgcn_global_load_lds(src + off, (lds_ptr)(tile + 64 * j), 16, 0, 0);
+      }
     }
+    if (lane < 8)
+      __builtin_amdgcn_global_load_lds(normp + c0 + 8 * wave + lane,
+                                       (lds_ptr)(reinterpret_cast<float*>(tile + kTileU4) + 8 * wave),
+                                       4, 0, 0);
+  };
+  // waits until at most n of this wave's copies are outstanding (the copies
+  // complete in order, and no other vector memory operation is in flight:
+  // the list stores wait for themselves)
+  auto wait_copies = [](int n) {
+    switch (n) {
+      case 0: __builtin_amdgcn_s_waitcnt(0xF70); break;
+      case 1: __builtin_amdgcn_s_waitcnt(0xF71); break;
+      case 2: __builtin_amdgcn_s_waitcnt(0xF72); break;
+      case 3: __builtin_amdgcn_s_waitcnt(0xF73); break;
+      case 4: __builtin_amdgcn_s_waitcnt(0xF74); break;
+      case 5: __builtin_amdgcn_s_waitcnt(0xF75); break;
+      default: __builtin_amdgcn_s_waitcnt(0xF76); break;
+    }
+  };
+  // one tile's Gram values, the norms entering as the accumulator's start;
+  // val[v] belongs to root row c0 + 8 (v >> 2) + 4 h + (v & 3)
+  auto gram = [&](const uint4* tile, floatx16& val) {
+    const float* nrm = reinterpret_cast<const float*>(tile + kTileU4);
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
       const float4 nr = reinterpret_cast<const float4*>(nrm)[2 * g + h];
-      val[4 * g + 0] = acc[4 * g + 0] + nr.x;
-      val[4 * g + 1] = acc[4 * g + 1] + nr.y;
-      val[4 * g + 2] = acc[4 * g + 2] + nr.z;
-      val[4 * g + 3] = acc[4 * g + 3] + nr.w;
+      val[4 * g + 0] = nr.x;
+      val[4 * g + 1] = nr.y;
+      val[4 * g + 2] = nr.z;
+      val[4 * g + 3] = nr.w;
     }
+    const uint4* arow = tile + qc * kRowSlots + h;
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+      val = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, arow[2 * s]), bq[s],
+                                                    val, 0, 0, 0);
   };
+  auto tile_min = [](const floatx16& val) {
+    float m = val[0];
+#pragma unroll
+    for (int v = 1; v < 16; ++v) m = fminf(m, val[v]);
+    return m;
+  };
+  // Workgroup barrier for the ring.  __syncthreads() would also wait for
+  // every outstanding copy (its release fence), including those of the
+  // tiles ahead; the copies a tile needs were waited for above, and LDS
+  // itself is coherent within the workgroup, so a plain barrier suffices.
+  // The memory clobber keeps the compiler from moving LDS accesses across it.
+  auto lds_barrier = []() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); };
   // every wave of the block walks the same tiles (the barriers need all of
   // them, so no wave leaves early)
   auto scan = [&](auto&& body) {
     if (cb >= ce) return;
-    issue(cb, tileA, normA);
-    for (int64_t c0 = cb;; c0 += 64) {
-      arrive();
-      if (c0 + 32 < ce) issue(c0 + 32, tileB, normB);
-      body(c0, tileA, normA);
-      if (c0 + 32 >= ce) break;
-      arrive();
-      if (c0 + 64 < ce) issue(c0 + 64, tileA, normA);
-      body(c0 + 32, tileB, normB);
-      if (c0 + 64 >= ce) break;
+    const int nt = (int)((ce - cb + 31) / 32);
+    issue(cb, buf0);
+    if (nt > 1) issue(cb + 32, buf1);
+    auto step = [&](int t, auto I) {
+      constexpr int i = decltype(I)::value;
+      // this wave's copies of tile t are done once only those of the tile
+      // issued after it (if any) remain; the barrier covers the other waves'
+      wait_copies(t + 1 < nt ? per_tile : 0);
+      lds_barrier();
+      // into the buffer of tile t - 1, which every wave has finished with
+      if (t + 2 < nt) issue(cb + 32 * (t + 2), buf_of(Ic<(i + 2) % 3>{}));
+      body(cb + 32 * t, buf_of(I));
+    };
+    for (int t = 0; t < nt; t += 3) {
+      step(t, Ic<0>{});
+      if (t + 1 >= nt) break;
+      step(t + 1, Ic<1>{});
+      if (t + 2 >= nt) break;
+      step(t + 2, Ic<2>{});
     }
-    __syncthreads();  // the next scan refills tileA
+    __syncthreads();  // the next scan refills the ring
   };
 
-  // pass 1: the split's smallest Gram value of this query
+  // pass 1: the split's smallest Gram value of this query, merged into the
+  // query's running minimum over the splits
   float vmin = INFINITY;
-  scan([&](int64_t, const uint4* tile, const float* nrm) {
-    float val[16];
-    gram(tile, nrm, val);
-#pragma unroll
-    for (int v = 0; v < 16; ++v) vmin = fminf(vmin, val[v]);
+  scan([&](int64_t, const uint4* tile) {
+    floatx16 val;
+    gram(tile, val);
+    vmin = fminf(vmin, tile_min(val));
   });
   vmin = fminf(vmin, __shfl_xor(vmin, 32));
-  const float thr = vmin + M;
+  if (qvalid && h == 0) atomicMin(sl.qmin + qrow, ordered_bits(vmin));
 
-  // pass 2: the rows within M of it; the query's two lanes (h = 0, 1) fill
-  // one list, h = 0's rows of a tile first
-  const int64_t list = (int64_t)blockIdx.y * nq + qrow;
-  float* lval = sl.val + list * kRootCap;
-  int32_t* lrow = sl.row + list * kRootCap;
-  int cnt = 0;
-  scan([&](int64_t c0, const uint4* tile, const float* nrm) {
-    float val[16];
-    gram(tile, nrm, val);
-    uint32_t hit = 0;
+  // pass 2: the rows within M of the smaller of the split's minimum and the
+  // running minimum as it stands now (both at or above the root's minimum)
+  const float thr = fminf(vmin, qvalid ? from_ordered(sl.qmin[qrow]) : vmin) + M;
+  uint2* lent = sl.ent + (qvalid ? qrow : 0) * kRootCap;
+  scan([&](int64_t c0, const uint4* tile) {
+    floatx16 val;
+    gram(tile, val);
+    if (__builtin_amdgcn_ballot_w64(qvalid && tile_min(val) <= thr)) {
+      uint32_t hit = 0;
 #pragma unroll
-    for (int v = 0; v < 16; ++v) hit |= (qvalid && val[v] <= thr) ? 1u << v : 0u;
-    if (__builtin_amdgcn_ballot_w64(hit != 0)) {
-      const int n = __popc(hit), n_other = __shfl_xor(n, 32);
-      int pos = cnt + (h ? n_other : 0);
+      for (int v = 0; v < 16; ++v) hit |= (qvalid && val[v] <= thr) ? 1u << v : 0u;
+      if (hit) {
+        int pos = atomicAdd(sl.cnt + qrow, __popc(hit));
 #pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        if (hit & (1u << v)) {
-          if (pos < kRootCap) {
-            lval[pos] = val[v];
-            lrow[pos] = (int32_t)(c0 + 8 * (v >> 2) + 4 * h + (v & 3));
+        for (int v = 0; v < 16; ++v) {
+          if (hit & (1u << v)) {
+            if (pos < kRootCap)
+              lent[pos] = make_uint2(__float_as_uint(val[v]),
+                                     (uint32_t)(c0 + 8 * (v >> 2) + 4 * h + (v & 3)));
+            ++pos;
           }
-          ++pos;
         }
       }
-      cnt += n + n_other;
+      wait_copies(0);
     }
   });
-  if (qvalid && h == 0) sl.cnt[list] = cnt;
 }
 
 void launch_root_gram(const float* Q, int64_t nq, int d, const RootAux& r, int dpad, int metric,

@@ -299,90 +299,69 @@ __device__ uint64_t root_scan_wave(const SearchArgs& a, const SearchLayer& R,
 // whose Gram value exceeds a_min + M, M = (2^-7 + 2^-14 + 32 (dpad + 16)
 // 2^-24) N (above twice the sum of both bounds), has c(y) > c(argmin_a), so
 // the nearest root member under (distance, position) is among the rows with
-// a <= a_min + M.  The Gram pass listed, per split, every row within M of
-// the split's smallest value, which is at least a_min: so the lists hold
-// all of them unless one overflowed, and then the wave scans the root.
+// a <= a_min + M.  Each split of the Gram pass listed every row within M of
+// a threshold at or above a_min: so the list holds all of them unless it
+// overflowed, and then the wave scans the root.
 template <int KIND, int LPN, int CPL>
-__global__ __launch_bounds__(256) void k_root_check(SearchArgs a, int splits, RootShortlist sl,
-                                                    uint64_t* out) {
+__device__ uint64_t root_check_wave(const SearchArgs& a, int64_t qi, const float (&q)[CPL][8],
+                                    const RootShortlist& sl, int32_t* rows) {
+  static_assert(kRootCap == 64, "one list entry per lane");
   constexpr int G = 64 / LPN;
   const int lane = lane_id(), t = lane % LPN, g = lane / LPN;
-  const int64_t qi = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (qi >= a.nq) return;  // whole wave
   const SearchLayer& R = a.layer[a.num_layers - 1];
-  float q[CPL][8];
-  load_query<CPL>(a.Q + qi * a.d, a.d, t, q);
-
-  // entry e of the query's lists: the list of split e / kRootCap, slot
-  // e % kRootCap, present when below the list's count
-  const int n = splits * kRootCap;
-  auto entry = [&](int e, float& v, int32_t& pos, bool& over) {
-    const int l = e / kRootCap, j = e % kRootCap;
-    const int64_t list = (int64_t)l * a.nq + qi;
-    const int c = sl.cnt[list];
-    over = j == 0 && c > kRootCap;
-    const bool present = j < c;
-    v = present ? sl.val[list * kRootCap + j] : INFINITY;
-    pos = present ? sl.row[list * kRootCap + j] : -1;
-  };
-  float amin = INFINITY;
-  bool over = false;
-  for (int e = lane; e < n; e += 64) {
-    float v;
-    int32_t pos;
-    bool o;
-    entry(e, v, pos, o);
-    amin = fminf(amin, v);
-    over |= o;
-  }
+  // one entry per lane (slots past the count hold stale values, dropped)
+  const int cnt = uni(sl.cnt[qi]);
+  const uint2 e = sl.ent[qi * kRootCap + lane];
+  if (cnt > kRootCap) return root_scan_wave<KIND, LPN, CPL>(a, R, q);
+  const float v = lane < cnt ? __uint_as_float(e.x) : INFINITY;
+  float amin = v;
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) amin = fminf(amin, __shfl_xor(amin, m));
   const float T = amin + sl.mq[qi];
-  __shared__ int32_t rows_all[4][64];
-  int32_t* rows = rows_all[threadIdx.x >> 6];
+  // the rows with a <= T, gathered into rows[] and evaluated G at a time
+  const bool keep = lane < cnt && v <= T;
+  const uint64_t m = ballot(keep);
+  const int total = popc64(m);
+  wave_sync();
+  if (keep) rows[rank_below(m)] = (int32_t)e.y;
+  wave_sync();
   uint64_t best = ~0ull;
-  if (ballot(over)) {
-    best = root_scan_wave<KIND, LPN, CPL>(a, R, q);
-  } else {
-    for (int base = 0; base < n; base += 64) {
-      // compact this chunk's entries with a <= T, then G rows per pass
-      int32_t pos = -1;
-      if (base + lane < n) {
-        float v;
-        bool o;
-        entry(base + lane, v, pos, o);
-        if (!(v <= T)) pos = -1;
-      }
-      const uint64_t m = ballot(pos >= 0);
-      const int cnt = popc64(m);
-      if (cnt == 0) continue;
-      wave_sync();
-      if (pos >= 0) rows[rank_below(m)] = pos;
-      wave_sync();
-      for (int b = 0; b < cnt; b += G) {
-        const int32_t row = b + g < cnt ? rows[b + g] : -1;
-        const bool valid = row >= 0;
-        const float sc = (KIND == kFP8 && valid) ? R.scale[row] : 1.0f;
-        const char* rp = static_cast<const char*>(R.vec) + (int64_t)(valid ? row : 0) * R.row_bytes;
-        const float dist = group_distance<KIND, LPN, CPL>(q, rp, sc, t, a.nchunks, a.metric, valid);
-        if (valid) {
-          const uint64_t k = wkey(dist, row);
-          best = k < best ? k : best;
-        }
-      }
-    }
-#pragma unroll
-    for (int m2 = 32; m2 >= 1; m2 >>= 1) {
-      const uint64_t o = shfl_xor_u64(best, m2);
-      best = o < best ? o : best;
+  for (int b = 0; b < total; b += G) {
+    const int32_t row = b + g < total ? rows[b + g] : -1;
+    const bool valid = row >= 0;
+    const float sc = (KIND == kFP8 && valid) ? R.scale[row] : 1.0f;
+    const char* rp = static_cast<const char*>(R.vec) + (int64_t)(valid ? row : 0) * R.row_bytes;
+    const float dist = group_distance<KIND, LPN, CPL>(q, rp, sc, t, a.nchunks, a.metric, valid);
+    if (valid) {
+      const uint64_t k = wkey(dist, row);
+      best = k < best ? k : best;
     }
   }
+#pragma unroll
+  for (int m2 = 32; m2 >= 1; m2 >>= 1) {
+    const uint64_t o = shfl_xor_u64(best, m2);
+    best = o < best ? o : best;
+  }
+  return best;
+}
+
+template <int KIND, int LPN, int CPL>
+__global__ __launch_bounds__(256) void k_root_check(SearchArgs a, RootShortlist sl, uint64_t* out) {
+  const int lane = lane_id(), t = lane % LPN;
+  const int64_t qi = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (qi >= a.nq) return;  // whole wave
+  float q[CPL][8];
+  load_query<CPL>(a.Q + qi * a.d, a.d, t, q);
+  __shared__ int32_t rows_all[4][64];
+  const uint64_t best =
+      root_check_wave<KIND, LPN, CPL>(a, qi, q, sl, rows_all[threadIdx.x >> 6]);
   if (lane == 0) out[qi] = best;
 }
 
 // Loads this query's k and beam width and finds the entry of the first
 // searched layer: the root's smallest id, or the exact root nearest when the
-// root carries the complete graph (from k_root_scan's keys when given).
+// root carries the complete graph (from k_root_scan's or k_root_check's keys
+// when given).
 template <int KIND, int LPN, int CPL>
 __device__ void start_query(const SearchArgs& a, int64_t qi, const float (&q)[CPL][8],
                             QState& st) {
@@ -1203,14 +1182,14 @@ void launch_serve_admit(const float* staged_q, const int32_t* meta, int n_new, i
 }
 
 template <int KIND>
-static bool launch_root_check_kind(const SearchArgs& a, int splits, const RootShortlist& sl,
-                                   uint64_t* out, hipStream_t st) {
+static bool launch_root_check_kind(const SearchArgs& a, const RootShortlist& sl, uint64_t* out,
+                                   hipStream_t st) {
   int lpn = 0, cpl = 0;
   pick_lanes(a.nchunks, 0, &lpn, &cpl);
   const dim3 grid((unsigned)((a.nq + 3) / 4));
 #define HENN_TRY(L, C)                                                                       \
   if (lpn == L && cpl == C) {                                                                \
-    hipLaunchKernelGGL((k_root_check<KIND, L, C>), grid, dim3(256), 0, st, a, splits, sl, out); \
+    hipLaunchKernelGGL((k_root_check<KIND, L, C>), grid, dim3(256), 0, st, a, sl, out);         \
     return true;                                                                             \
   }
   HENN_TRY(1, 1) HENN_TRY(2, 1) HENN_TRY(4, 1) HENN_TRY(2, 2) HENN_TRY(4, 2) HENN_TRY(8, 1)
@@ -1219,13 +1198,13 @@ static bool launch_root_check_kind(const SearchArgs& a, int splits, const RootSh
   return false;
 }
 
-bool launch_root_check(int storage, const SearchArgs& a, int splits, const RootShortlist& sl,
-                       uint64_t* out, hipStream_t st) {
+bool launch_root_check(int storage, const SearchArgs& a, const RootShortlist& sl, uint64_t* out,
+                       hipStream_t st) {
   if (a.nq <= 0) return true;
   switch (storage) {
-    case kF32: return launch_root_check_kind<kF32>(a, splits, sl, out, st);
-    case kBF16: return launch_root_check_kind<kBF16>(a, splits, sl, out, st);
-    case kFP8: return launch_root_check_kind<kFP8>(a, splits, sl, out, st);
+    case kF32: return launch_root_check_kind<kF32>(a, sl, out, st);
+    case kBF16: return launch_root_check_kind<kBF16>(a, sl, out, st);
+    case kFP8: return launch_root_check_kind<kFP8>(a, sl, out, st);
     default: return false;
   }
 }

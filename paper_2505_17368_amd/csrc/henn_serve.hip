@@ -242,17 +242,9 @@ henn_status henn_server_create(const henn_index* idx, const henn_server_params* 
     dmalloc(&s->stage_meta_d, M * 7);  // admission metadata [n_new][6], then the active list
     dmalloc(&s->rows_d, M * (1 + 2 * s->k_max));
     if (idx->root.size > 0) {
-      // shortlist bytes for the largest admission batch's split
-      int64_t most = 0;
-      for (int64_t nn = 1; nn <= M; ++nn) {
-        int64_t per = 0;
-        most = std::max<int64_t>(
-            most,
-            root_shortlist_bytes(root_gram_splits(nn, idx->root.size, &per), nn, idx->root.kp));
-      }
       dmalloc(&s->root_keys, M);
       dmalloc(&s->slot_root, M);
-      dmalloc(&s->root_sl, most);
+      dmalloc(&s->root_sl, root_shortlist_bytes(M, idx->root.kp));  // the largest admission
     }
     hmalloc(&s->stage_q_h, M * s->d);
     hmalloc(&s->stage_meta_h, M * 7);
@@ -392,13 +384,13 @@ henn_status henn_server_tick(henn_server* s, int32_t* n_active_out) {
         // the new requests' complete-root scans, on matrix cores
         int64_t per = 0;
         const int splits = root_gram_splits(n_new, idx->root.size, &per);
-        const RootShortlist sl = root_shortlist_at(s->root_sl, splits, n_new, idx->root.kp);
+        const RootShortlist sl = root_shortlist_at(s->root_sl, n_new, idx->root.kp);
         launch_root_gram(s->stage_q_d, n_new, s->d, idx->root, idx->dpad, idx->metric, splits,
                          per, sl, s->st);
         SearchArgs ra = a;
         ra.Q = s->stage_q_d;
         ra.nq = n_new;
-        if (!launch_root_check(idx->storage, ra, splits, sl, s->root_keys, s->st))
+        if (!launch_root_check(idx->storage, ra, sl, s->root_keys, s->st))
           return srv_fail(HENN_E_UNSUPPORTED, "no root check kernel for this shape");
       }
       launch_serve_admit(s->stage_q_d, s->stage_meta_d, n_new, s->d, s->slot_q, s->slot_k,

@@ -532,6 +532,30 @@ def test_root_scan_kernel_matches_in_kernel_scan(hn, ho, storage, metric, d):
     idx.free()
 
 
+@pytest.mark.parametrize("storage", [0, 2])
+def test_root_shortlist_overflow_matches_in_kernel_scan(hn, ho, storage):
+    """A third of the points are copies of one point, so the root holds many
+    rows with equal Gram values: queries near that point list more rows than
+    a shortlist holds, and the check falls back to scanning the root.  The
+    results must still equal the in-kernel scan's, bit for bit."""
+    rng = np.random.default_rng(91)
+    X = (wl.uniform(3000, 48, 60) - 0.5).astype(np.float32)
+    X[:1000] = X[1000]
+    Q = np.concatenate([X[1000] + 1e-3 * rng.standard_normal((200, 48)),
+                        wl.uniform(200, 48, 61) - 0.5]).astype(np.float32)
+    idx = hn.henn_build(to_dev(X), degree=12, metric=0, storage=storage, graph=1,
+                        max_degree=24, root_complete_max=1000)
+    assert idx.num_layers >= 2
+    root = idx.export_layer(idx.num_layers - 1)[0]
+    assert np.sum(root < 1001) > 40, "the root should hold many copies"
+    a_i, a_d = hn.henn_search_batch(idx, to_dev(Q), k=10, ef=40)
+    b_i, b_d = hn.henn_search_batch(idx, to_dev(Q), k=10, ef=40, root_kernel=False)
+    _sync()
+    assert np.array_equal(a_i.cpu().numpy(), b_i.cpu().numpy())
+    assert np.array_equal(a_d.cpu().numpy().view(np.uint32), b_d.cpu().numpy().view(np.uint32))
+    idx.free()
+
+
 def test_autotune_caches_a_shape_and_keeps_results(hn, cfg1_sym_root):
     X, Q, oidx = cfg1_sym_root
     idx = _import(hn, X, oidx, storage=1)
