@@ -122,21 +122,11 @@ typedef struct {
                              large values give the one-by-one insertion */
 } henn_build_params;
 
-/* Search flags */
+/* Search flags (bits 4..32 are taken by the test-only flags of
+ * henn_testing.h) */
 #define HENN_SEARCH_COUNTERS 1u   /* fill counters[] */
 #define HENN_SEARCH_PERSISTENT 2u /* one persistent launch pulling queries from a
                                      device work counter (batched form) */
-#define HENN_SEARCH_NO_ROOT_KERNEL 4u /* scan a complete-graph root inside the search
-                                         kernel instead of a separate scan (same
-                                         results; for tests and tuning) */
-#define HENN_SEARCH_ROOT_VALU 8u      /* scan a complete-graph root with the tiled
-                                         VALU kernel instead of the matrix-core
-                                         shortlist + exact check (same results) */
-#define HENN_SEARCH_VIS32 16u         /* keep full 32-bit ids in the visited table
-                                         even where 8- or 16-bit tags are exact
-                                         (same results; for tests) */
-#define HENN_SEARCH_VIS16 32u         /* keep 16-bit tags where 8-bit tags would be
-                                         exact (same results; for tests) */
 
 typedef struct {
   uint32_t struct_size;   /* = sizeof(henn_search_params) */

@@ -53,13 +53,25 @@ TAG_SAMPLE, TAG_RING_CENTRE, TAG_RING_START, TAG_HALVE, TAG_INSERT = 1, 2, 3, 4,
 L2, IP = 0, 1
 
 
+_CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-shared", "-fPIC"]
+
+
 def build() -> str:
     """Compile the C oracle with gcc (strict FP64: no contraction, no fast-math)."""
-    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-shared",
-           "-fPIC", "-o", _LIB + ".tmp", _SRC, "-lm"]
+    cmd = ["gcc", *_CFLAGS, "-o", _LIB + ".tmp", _SRC, "-lm"]
     subprocess.check_call(cmd)
     os.replace(_LIB + ".tmp", _LIB)
     return _LIB
+
+
+def build_sanitized(path: str) -> str:
+    """The same library with AddressSanitizer and UndefinedBehaviorSanitizer
+    (every report fatal), for the sanitized run of the oracle's pins; load it
+    by setting HENN_ORACLE_LIB to path, with libasan preloaded."""
+    cmd = ["gcc", *_CFLAGS, "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+           "-fno-sanitize-recover=all", "-o", path, _SRC, "-lm"]
+    subprocess.check_call(cmd)
+    return path
 
 
 def _load():
@@ -67,9 +79,12 @@ def _load():
     with _lock:
         if _lib is not None:
             return _lib
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build()
-        lib = ctypes.CDLL(_LIB)
+        path = os.environ.get("HENN_ORACLE_LIB")
+        if not path:
+            path = _LIB
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build()
+        lib = ctypes.CDLL(path)
         P = ctypes.POINTER
         c_i64p, c_i32p, c_f64p, c_f32p = (P(ctypes.c_int64), P(ctypes.c_int32),
                                           P(ctypes.c_double), P(ctypes.c_float))

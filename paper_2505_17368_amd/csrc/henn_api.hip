@@ -13,6 +13,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdlib>
 #include <mutex>
 #include <new>
@@ -32,6 +33,38 @@ void set_error(const std::string& msg) { g_last_error = msg; }
 static henn_status fail(henn_status s, const std::string& msg) {
   set_error(msg);
   return s;
+}
+
+// Allocation-failure injector (henn_testing.h): < 0 off; otherwise the
+// number of device allocations that may still succeed.
+static std::atomic<int64_t> g_alloc_budget{-1};
+
+static bool alloc_allowed() {
+  int64_t b = g_alloc_budget.load();
+  while (b >= 0) {
+    if (b == 0) return false;
+    if (g_alloc_budget.compare_exchange_weak(b, b - 1)) return true;
+  }
+  return true;
+}
+
+}  // namespace henn
+
+extern "C" henn_status henn_testing_fail_alloc_after(int64_t n) {
+  henn::g_alloc_budget.store(n < 0 ? -1 : n);
+  return HENN_OK;
+}
+
+namespace henn {
+
+hipError_t dev_alloc(void** p, size_t bytes) {
+  if (!alloc_allowed()) return hipErrorOutOfMemory;
+  return hipMalloc(p, bytes);
+}
+
+hipError_t dev_alloc_async(void** p, size_t bytes, hipStream_t st) {
+  if (!alloc_allowed()) return hipErrorOutOfMemory;
+  return hipMallocAsync(p, bytes, st);
 }
 
 static henn_status from_hip(const HipError& e) {
@@ -56,7 +89,7 @@ template <typename T>
 static T* dalloc(int64_t count) {
   T* p = nullptr;
   if (count <= 0) count = 1;
-  HENN_HIP(hipMalloc(&p, sizeof(T) * (size_t)count));
+  HENN_HIP(dev_alloc(reinterpret_cast<void**>(&p), sizeof(T) * (size_t)count));
   return p;
 }
 
@@ -1129,7 +1162,7 @@ static henn_status search_impl(const henn_index* idx, const float* Q, int64_t nq
       } else if (sp->workspace && sp->workspace_bytes >= need) {
         ws = static_cast<char*>(sp->workspace);
       } else {
-        HENN_HIP(hipMallocAsync((void**)&ws, need, st));
+        HENN_HIP(dev_alloc_async(reinterpret_cast<void**>(&ws), need, st));
         ws_owned = true;
       }
     }
@@ -1249,7 +1282,7 @@ henn_status henn_autotune(henn_index* idx, const float* Q, int64_t nq,
       henn_search_params cp = c;
       cp.flags |= HENN_SEARCH_PERSISTENT;
       const int64_t wb = search_workspace_bytes(idx, nq, &cp);
-      HENN_HIP(hipMalloc(&ws, wb));
+      HENN_HIP(dev_alloc(reinterpret_cast<void**>(&ws), wb));
       c.workspace = ws;
       c.workspace_bytes = wb;
     }
@@ -1369,7 +1402,7 @@ henn_status henn_search_graph_create(const henn_index* idx, const float* Q, int6
   hipStream_t cs = nullptr;
   try {
     const int64_t need = search_workspace_bytes(idx, nq, sp);
-    HENN_HIP(hipMalloc(&g->workspace, need));
+    HENN_HIP(dev_alloc(reinterpret_cast<void**>(&g->workspace), need));
     HENN_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     henn_search_params c = *sp;
     c.workspace = g->workspace;

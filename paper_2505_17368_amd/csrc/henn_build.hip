@@ -227,9 +227,9 @@ __global__ void k_compact(const uint32_t* bm, int64_t nwords, int64_t nbits, con
 int64_t compact_bitmap(const uint32_t* bitmap, int64_t s, int32_t* out_local, hipStream_t st) {
   const int64_t nwords = (s + 31) / 32;
   const int64_t nb = (nwords + kScanBlock - 1) / kScanBlock;
-  uint32_t *bsum = nullptr, *total = nullptr;
-  HENN_HIP(hipMalloc(&bsum, sizeof(uint32_t) * (nb + 1)));
-  total = bsum + nb;
+  DevBuf<uint32_t> bsum_buf(nb + 1);
+  uint32_t* bsum = bsum_buf.get();
+  uint32_t* total = bsum + nb;
   hipLaunchKernelGGL(k_block_popc, dim3((unsigned)nb), dim3(kScanBlock), 0, st, bitmap, nwords,
                      bsum);
   hipLaunchKernelGGL(k_scan_bsum, dim3(1), dim3(1024), 0, st, bsum, nb, total);
@@ -238,7 +238,6 @@ int64_t compact_bitmap(const uint32_t* bitmap, int64_t s, int32_t* out_local, hi
   uint32_t h_total = 0;
   HENN_HIP(hipMemcpyAsync(&h_total, total, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
   HENN_HIP(hipStreamSynchronize(st));
-  HENN_HIP(hipFree(bsum));
   return (int64_t)h_total;
 }
 
@@ -276,8 +275,8 @@ __global__ void k_block_scan_u32(const uint32_t* in, int64_t n, const uint32_t* 
 
 int64_t exclusive_scan_u32(const uint32_t* in, int64_t n, uint32_t* out, hipStream_t st) {
   const int64_t nb = std::max<int64_t>(1, (n + kScanBlock - 1) / kScanBlock);
-  uint32_t* bsum = nullptr;
-  HENN_HIP(hipMalloc(&bsum, sizeof(uint32_t) * (nb + 1)));
+  DevBuf<uint32_t> bsum_buf(nb + 1);
+  uint32_t* bsum = bsum_buf.get();
   hipLaunchKernelGGL(k_block_sum_u32, dim3((unsigned)nb), dim3(kScanBlock), 0, st, in, n, bsum);
   hipLaunchKernelGGL(k_scan_bsum, dim3(1), dim3(1024), 0, st, bsum, nb, bsum + nb);
   hipLaunchKernelGGL(k_block_scan_u32, dim3((unsigned)nb), dim3(kScanBlock), 0, st, in, n, bsum,
@@ -285,7 +284,6 @@ int64_t exclusive_scan_u32(const uint32_t* in, int64_t n, uint32_t* out, hipStre
   uint32_t total = 0;
   HENN_HIP(hipMemcpyAsync(&total, bsum + nb, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
   HENN_HIP(hipStreamSynchronize(st));
-  HENN_HIP(hipFree(bsum));
   return (int64_t)total;
 }
 
@@ -448,12 +446,12 @@ __global__ void k_radix_pick(uint32_t* hist, uint64_t* prefix, int64_t* rank, in
 void launch_radix_select(const uint64_t* keys, int64_t s, int r, const int64_t* ranks_host,
                          uint64_t* out_keys_host, hipStream_t st) {
   const int nt = 2 * r;
-  uint32_t* hist = nullptr;
-  uint64_t* prefix = nullptr;
-  int64_t* rank = nullptr;
-  HENN_HIP(hipMalloc(&hist, sizeof(uint32_t) * 256 * nt));
-  HENN_HIP(hipMalloc(&prefix, sizeof(uint64_t) * nt));
-  HENN_HIP(hipMalloc(&rank, sizeof(int64_t) * nt));
+  DevBuf<uint32_t> hist_buf(256 * nt);
+  DevBuf<uint64_t> prefix_buf(nt);
+  DevBuf<int64_t> rank_buf(nt);
+  uint32_t* hist = hist_buf.get();
+  uint64_t* prefix = prefix_buf.get();
+  int64_t* rank = rank_buf.get();
   HENN_HIP(hipMemsetAsync(hist, 0, sizeof(uint32_t) * 256 * nt, st));
   HENN_HIP(hipMemsetAsync(prefix, 0, sizeof(uint64_t) * nt, st));
   HENN_HIP(hipMemcpyAsync(rank, ranks_host, sizeof(int64_t) * nt, hipMemcpyHostToDevice, st));
@@ -467,9 +465,6 @@ void launch_radix_select(const uint64_t* keys, int64_t s, int r, const int64_t* 
   HENN_HIP(hipMemcpyAsync(out_keys_host, prefix, sizeof(uint64_t) * nt, hipMemcpyDeviceToHost,
                           st));
   HENN_HIP(hipStreamSynchronize(st));
-  HENN_HIP(hipFree(hist));
-  HENN_HIP(hipFree(prefix));
-  HENN_HIP(hipFree(rank));
 }
 
 // ------------------------------------------------------- mean, norms -----
@@ -488,8 +483,8 @@ void layer_mean(const float* vec, int64_t size, int dpad, float* mean_dev, hipSt
   const int64_t nb = std::min<int64_t>(size, 2048);
   const int64_t per = (size + nb - 1) / nb;
   const int64_t nblk = (size + per - 1) / per;
-  float* partial = nullptr;
-  HENN_HIP(hipMalloc(&partial, sizeof(float) * nblk * dpad));
+  DevBuf<float> partial_buf(nblk * dpad);
+  float* partial = partial_buf.get();
   hipLaunchKernelGGL(k_col_partial, dim3((unsigned)nblk), dim3(256), 0, st, vec, size, dpad, per,
                      partial);
   std::vector<float> h((size_t)(nblk * dpad));
@@ -504,7 +499,6 @@ void layer_mean(const float* vec, int64_t size, int dpad, float* mean_dev, hipSt
   }
   HENN_HIP(hipMemcpyAsync(mean_dev, mean.data(), sizeof(float) * dpad, hipMemcpyHostToDevice, st));
   HENN_HIP(hipStreamSynchronize(st));
-  HENN_HIP(hipFree(partial));
 }
 
 __global__ void k_row_norms(const float* vec, const float* mean, int64_t size, int dpad,
@@ -535,15 +529,14 @@ __global__ void k_max_reduce(const float* v, int64_t n, unsigned int* out) {
 }
 
 float max_norm(const float* norms, int64_t size, hipStream_t st) {
-  unsigned int* d = nullptr;
-  HENN_HIP(hipMalloc(&d, sizeof(unsigned int)));
+  DevBuf<unsigned int> d_buf(1);
+  unsigned int* d = d_buf.get();
   HENN_HIP(hipMemsetAsync(d, 0, sizeof(unsigned int), st));
   const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>((size + 255) / 256, 1024));
   hipLaunchKernelGGL(k_max_reduce, dim3(g), dim3(256), 0, st, norms, size, d);
   unsigned int h = 0;
   HENN_HIP(hipMemcpyAsync(&h, d, sizeof(unsigned int), hipMemcpyDeviceToHost, st));
   HENN_HIP(hipStreamSynchronize(st));
-  HENN_HIP(hipFree(d));
   float f;
   memcpy(&f, &h, sizeof(f));
   return f;

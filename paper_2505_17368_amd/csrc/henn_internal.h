@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/henn.h"
+#include "../../include/henn_testing.h"
 
 namespace henn {
 
@@ -125,6 +126,28 @@ struct HipError {
     hipError_t _e = (call);                              \
     if (_e != hipSuccess) throw ::henn::HipError{_e, #call}; \
   } while (0)
+
+// Device allocation of every library path: hipMalloc / hipMallocAsync behind
+// the allocation-failure injector of henn_testing.h (off unless a test arms
+// it).
+hipError_t dev_alloc(void** p, size_t bytes);
+hipError_t dev_alloc_async(void** p, size_t bytes, hipStream_t st);
+
+// Owning device array for temporaries: freed when its scope ends, also when
+// an exception unwinds it (hipFree waits for the device as usual).
+template <typename T>
+struct DevBuf {
+  T* p = nullptr;
+  explicit DevBuf(int64_t count) {
+    HENN_HIP(dev_alloc(reinterpret_cast<void**>(&p), sizeof(T) * (size_t)(count > 0 ? count : 1)));
+  }
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  T* get() const { return p; }
+};
 
 inline int next_pow2(int v) {
   int p = 1;

@@ -595,8 +595,8 @@ void prepare_root_bf16(RootAux& r, int dpad, int metric, hipStream_t st) {
   if (dpad > 128) throw HipError{hipErrorInvalidValue, "BF16 root scan supports d <= 128"};
   r.kp = (dpad + 15) / 16 * 16;
   const int64_t rows_pad = (r.size + 31) / 32 * 32;
-  HENN_HIP(hipMalloc(&r.rowb, sizeof(uint16_t) * rows_pad * r.kp));
-  HENN_HIP(hipMalloc(&r.normp, sizeof(float) * rows_pad));
+  HENN_HIP(dev_alloc(reinterpret_cast<void**>(&r.rowb), sizeof(uint16_t) * rows_pad * r.kp));
+  HENN_HIP(dev_alloc(reinterpret_cast<void**>(&r.normp), sizeof(float) * rows_pad));
   const int64_t n = rows_pad * r.kp;
   hipLaunchKernelGGL(k_root_rows_bf16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
                      r.dec, r.mean, r.norm, r.size, rows_pad, dpad, r.kp, metric, r.rowb,
@@ -877,19 +877,15 @@ int64_t build_knn_graph(const float* vec, int64_t size, int dpad, int nchunks, i
                         int lpn, int cpl, int32_t* adj, hipStream_t st) {
   if (size <= 0) return 0;
   if (dpad > 1024) throw HipError{hipErrorInvalidValue, "kNN build supports d <= 1024"};
-  float *mean = nullptr, *norms = nullptr, *sl_d = nullptr;
-  int32_t *sl_i = nullptr, *fb_rows = nullptr;
-  uint32_t* fb_count = nullptr;
-  HENN_HIP(hipMalloc(&norms, sizeof(float) * size));
-  HENN_HIP(hipMalloc(&sl_d, sizeof(float) * size * 2 * kShort));
-  HENN_HIP(hipMalloc(&sl_i, sizeof(int32_t) * size * 2 * kShort));
-  HENN_HIP(hipMalloc(&fb_rows, sizeof(int32_t) * size));
-  HENN_HIP(hipMalloc(&fb_count, sizeof(uint32_t)));
+  DevBuf<float> norms_buf(size), sl_d_buf(size * 2 * kShort), mean_buf(metric == 0 ? dpad : 1);
+  DevBuf<int32_t> sl_i_buf(size * 2 * kShort), fb_rows_buf(size);
+  DevBuf<uint32_t> fb_count_buf(1);
+  float *norms = norms_buf.get(), *sl_d = sl_d_buf.get();
+  float* mean = metric == 0 ? mean_buf.get() : nullptr;
+  int32_t *sl_i = sl_i_buf.get(), *fb_rows = fb_rows_buf.get();
+  uint32_t* fb_count = fb_count_buf.get();
   HENN_HIP(hipMemsetAsync(fb_count, 0, sizeof(uint32_t), st));
-  if (metric == 0) {
-    HENN_HIP(hipMalloc(&mean, sizeof(float) * dpad));
-    layer_mean(vec, size, dpad, mean, st);
-  }
+  if (metric == 0) layer_mean(vec, size, dpad, mean, st);
   launch_row_norms(vec, mean, size, dpad, norms, st);
   const float nmax = max_norm(norms, size, st);
 
@@ -960,12 +956,6 @@ int64_t build_knn_graph(const float* vec, int64_t size, int dpad, int nchunks, i
 #undef HENN_TRY
   }
   HENN_HIP(hipStreamSynchronize(st));
-  if (mean) HENN_HIP(hipFree(mean));
-  HENN_HIP(hipFree(norms));
-  HENN_HIP(hipFree(sl_d));
-  HENN_HIP(hipFree(sl_i));
-  HENN_HIP(hipFree(fb_rows));
-  HENN_HIP(hipFree(fb_count));
   return (int64_t)nfb;
 }
 
@@ -1142,11 +1132,10 @@ void symmetrize_graph(const float* vec, int64_t size, int dpad, int nchunks, int
                       const int32_t* adj_knn, int R, int32_t* adj_out, int max_deg, int lpn,
                       int cpl, hipStream_t st) {
   const int64_t edges = size * R;
-  uint32_t *cnt = nullptr, *off = nullptr;
-  int32_t* inl = nullptr;
-  HENN_HIP(hipMalloc(&cnt, sizeof(uint32_t) * (size + 1)));
-  HENN_HIP(hipMalloc(&off, sizeof(uint32_t) * (size + 1)));
-  HENN_HIP(hipMalloc(&inl, sizeof(int32_t) * (edges > 0 ? edges : 1)));
+  DevBuf<uint32_t> cnt_buf(size + 1), off_buf(size + 1);
+  DevBuf<int32_t> inl_buf(edges);
+  uint32_t *cnt = cnt_buf.get(), *off = off_buf.get();
+  int32_t* inl = inl_buf.get();
   HENN_HIP(hipMemsetAsync(cnt, 0, sizeof(uint32_t) * (size + 1), st));
   const unsigned eb = (unsigned)((edges + 255) / 256);
   hipLaunchKernelGGL(k_indeg, dim3(eb), dim3(256), 0, st, adj_knn, edges, cnt);
@@ -1165,9 +1154,6 @@ void symmetrize_graph(const float* vec, int64_t size, int dpad, int nchunks, int
   HENN_KNN_COMBOS(HENN_TRY)
 #undef HENN_TRY
   HENN_HIP(hipStreamSynchronize(st));
-  HENN_HIP(hipFree(cnt));
-  HENN_HIP(hipFree(off));
-  HENN_HIP(hipFree(inl));
   if (!launched) throw HipError{hipErrorInvalidValue, "no merge kernel for this lane shape"};
 }
 

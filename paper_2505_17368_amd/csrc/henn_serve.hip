@@ -157,7 +157,7 @@ static void srv_release(henn_server* s) {
 
 template <typename T>
 static void dmalloc(T** p, int64_t n) {
-  HENN_HIP(hipMalloc(reinterpret_cast<void**>(p), sizeof(T) * (size_t)std::max<int64_t>(n, 1)));
+  HENN_HIP(dev_alloc(reinterpret_cast<void**>(p), sizeof(T) * (size_t)std::max<int64_t>(n, 1)));
 }
 template <typename T>
 static void hmalloc(T** p, int64_t n) {

@@ -17,6 +17,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhenn.so")
 HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "henn.h")
+TESTING_HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "henn_testing.h")
 
 HENN_OK, HENN_E_INVAL, HENN_E_NOMEM, HENN_E_DEVICE, HENN_E_UNSUPPORTED = 0, 1, 2, 3, 4
 HENN_W_NOT_VERIFIED = 100
@@ -25,10 +26,9 @@ HENN_F32, HENN_BF16, HENN_FP8_E4M3 = 0, 1, 2
 HENN_GRAPH_KNN, HENN_GRAPH_KNN_SYM, HENN_GRAPH_PRUNED, HENN_GRAPH_PRUNED_SYM = 0, 1, 2, 3
 GRAPH = {"knn": 0, "knn_sym": 1, "pruned": 2, "pruned_sym": 3, "nsw": 4}
 SAMPLER = {"draws": 0, "halving": 1}
-HENN_SEARCH_COUNTERS, HENN_SEARCH_PERSISTENT, HENN_SEARCH_NO_ROOT_KERNEL = 1, 2, 4
-HENN_SEARCH_ROOT_VALU = 8
-HENN_SEARCH_VIS32 = 16
-HENN_SEARCH_VIS16 = 32
+HENN_SEARCH_COUNTERS, HENN_SEARCH_PERSISTENT = 1, 2
+# test-only flags (include/henn_testing.h)
+HENN_SEARCH_NO_ROOT_KERNEL, HENN_SEARCH_ROOT_VALU, HENN_SEARCH_VIS32, HENN_SEARCH_VIS16 = 4, 8, 16, 32
 STORAGE = {"f32": HENN_F32, "bf16": HENN_BF16, "fp8": HENN_FP8_E4M3}
 METRIC = {"l2": HENN_L2, "ip": HENN_IP}
 
@@ -147,17 +147,27 @@ def load_library(path: str = LIB_PATH):
                  "henn_search_graph_launch", "henn_default_server_params", "henn_server_create",
                  "henn_server_submit", "henn_server_submit_batch", "henn_server_tick",
                  "henn_server_poll",
-                 "henn_server_stats", "henn_nsw_insert", "henn_insert", "henn_delete"):
+                 "henn_server_stats", "henn_nsw_insert", "henn_insert", "henn_delete",
+                 "henn_testing_fail_alloc_after"):
         getattr(lib, name).restype = ctypes.c_int
+    lib.henn_testing_fail_alloc_after.argtypes = [ctypes.c_int64]
     _lib = lib
     return lib
 
 
-def header_symbols(path: str = HEADER_PATH):
-    """Function names declared in include/henn.h."""
-    txt = open(path).read()
-    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(henn_[a-z_0-9]+)\s*\(", txt)))
+def header_symbols(paths=(HEADER_PATH, TESTING_HEADER_PATH)):
+    """Function names declared in include/henn.h and include/henn_testing.h."""
+    names = set()
+    for path in paths:
+        txt = re.sub(r"/\*.*?\*/", "", open(path).read(), flags=re.S)
+        names.update(re.findall(r"\b(henn_[a-z_0-9]+)\s*\(", txt))
+    return sorted(names)
+
+
+def fail_alloc_after(n: int) -> None:
+    """Test-only: the next n device allocations of the library succeed, later
+    ones fail as out of memory; n < 0 turns the injector off."""
+    _check(load_library().henn_testing_fail_alloc_after(int(n)))
 
 
 def last_error() -> str:

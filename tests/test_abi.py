@@ -129,7 +129,9 @@ def test_binding_constants_match_header():
     """Every enumerator and flag the binding mirrors has the header's value."""
     import os
     import re
-    text = open(os.path.join(os.path.dirname(__file__), "..", "include", "henn.h")).read()
+    inc = os.path.join(os.path.dirname(__file__), "..", "include")
+    text = (open(os.path.join(inc, "henn.h")).read() +
+            open(os.path.join(inc, "henn_testing.h")).read())
     values = {m.group(1): int(m.group(2))
               for m in re.finditer(r"\b(HENN_[A-Z0-9_]+)\s*=\s*(\d+)", text)}
     values.update({m.group(1): int(m.group(2))
