@@ -105,7 +105,7 @@ typedef struct {
   double c0;              /* constant of Eq. (1), natural logarithm */
   double eps_override;    /* > 0: use this eps on every layer instead of Eq. (1) */
   int32_t num_rings;      /* r: ring ranges checked per layer (App. G.2) */
-  int32_t max_attempts;   /* Las-Vegas cap of Alg. 2's repeat loop */
+  int32_t max_attempts;   /* Las-Vegas cap of Alg. 2's repeat loop; 0: derived from phi */
   int32_t degree;         /* R: kNN graph degree (kept neighbours for PRUNED) */
   int32_t max_degree;     /* row capacity of the graphs with reverse edges and NSW
                              (>= degree, <= 64) */
@@ -120,6 +120,11 @@ typedef struct {
   int32_t ef_construction;/* NSW: beam width of the insertion searches, [1, 2048] */
   int32_t insert_shift;   /* NSW: batch after lo inserted members = max(1, lo >> shift);
                              large values give the one-by-one insertion */
+  double phi;             /* Alg. 2: probability that one sample is not an eps-net
+                             (Eq. (3)); the repeat loop then runs 1 / (1 - phi) times
+                             in expectation.  With max_attempts = 0 the attempt cap is
+                             the smallest t with phi^t <= 1e-9 (phi in (0, 1));
+                             otherwise only reported */
 } henn_build_params;
 
 /* Search flags (bits 4..32 are taken by the test-only flags of
@@ -127,6 +132,13 @@ typedef struct {
 #define HENN_SEARCH_COUNTERS 1u   /* fill counters[] */
 #define HENN_SEARCH_PERSISTENT 2u /* one persistent launch pulling queries from a
                                      device work counter (batched form) */
+#define HENN_SEARCH_EXACT_VISITED 64u /* remember every evaluated node exactly (a bit
+                                     per member of the largest layer and query,
+                                     nq * ceil(n / 32) * 4 bytes of workspace)
+                                     instead of the LDS table that may forget:
+                                     same results, slower; the evaluation
+                                     counters then count each node once per
+                                     layer, as the method does */
 
 typedef struct {
   uint32_t struct_size;   /* = sizeof(henn_search_params) */
@@ -140,7 +152,11 @@ typedef struct {
   int32_t ef_upper;       /* beam width on layers L..1 (1 = Alg. 4 greedy) */
   int32_t rerank_factor;  /* precision forms: re-rank min(|W|, factor*k) in FP32 */
   int32_t *counters;      /* device [nq][4] or NULL: expansions, distance
-                             evaluations, layer-0 expansions, layer-0 evaluations */
+                             evaluations, layer-0 expansions, layer-0 evaluations
+                             (summed over layers; a complete root counts all its
+                             members; without EXACT_VISITED a node the visited
+                             table forgot and met again is evaluated and counted
+                             again) */
   int32_t lanes_per_vec;  /* 0 = autotuned; else 1, 2, 4, 8 or 16 lanes
                              cooperate on one neighbour vector (those whose
                              chunks per lane, 1 to 8, times lanes equal the
@@ -177,7 +193,8 @@ typedef struct {
 
 /* Fills *p with the defaults: L2, max_layers -1, m 4, c0 1, no override,
  * 64 rings, 64 attempts, degree 16, max_degree 32, kNN graph, F32, seed 0,
- * root_complete_max 0, DRAWS sampler, ef_construction 256, insert_shift 3. */
+ * root_complete_max 0, DRAWS sampler, ef_construction 256, insert_shift 3,
+ * phi 0.5. */
 henn_status henn_default_build_params(henn_build_params *p);
 
 /* Defaults: no per-query arrays, k_all 10, ef_all 32, k_max 10, ef_max 32,

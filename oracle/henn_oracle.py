@@ -221,6 +221,16 @@ class BuildParams:
     root_complete_max: int = 0   # > 0: stop adding layers once a layer holds at most
                                  # this many points and give that root the complete graph
     sampler: int = 0             # 0: Alg. 2 draws with replacement; 1: Alg. 3 halving
+    phi: float = 0.5             # Alg. 2: failure probability of one sample (Eq. (3));
+                                 # sets the attempt cap when max_attempts is 0
+
+
+def attempt_cap(p: BuildParams) -> int:
+    """Attempts of Alg. 2's repeat loop: max_attempts, or with 0 the smallest t
+    with phi^t <= 1e-9 (each attempt fails with probability phi)."""
+    if p.max_attempts > 0:
+        return p.max_attempts
+    return max(1, math.ceil(math.log(1e-9) / math.log(p.phi)))
 
 
 @dataclass
@@ -319,7 +329,8 @@ def sample_layer(X, prev, layer, d, p: BuildParams, threads=None):
                                                 int(starts[j]), w)
     _parallel(r, one, threads)
     best_t, best_hits, best = -1, -1, None
-    for t in range(p.max_attempts):
+    cap = attempt_cap(p)
+    for t in range(cap):
         draws = _candidate(p, layer, t, s, D)
         sel = np.zeros(s, dtype=bool)
         sel[draws] = True
@@ -329,7 +340,7 @@ def sample_layer(X, prev, layer, d, p: BuildParams, threads=None):
         if hits == r:
             return np.unique(draws), LayerInfo(0, D, eps, w, t + 1, hits, "verified",
                                                float(margins.min()))
-    return np.unique(best), LayerInfo(0, D, eps, w, p.max_attempts, best_hits, "not_verified",
+    return np.unique(best), LayerInfo(0, D, eps, w, cap, best_hits, "not_verified",
                                       float(margins.min()))
 
 

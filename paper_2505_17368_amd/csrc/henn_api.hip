@@ -97,6 +97,13 @@ static int storage_bytes(int storage) {
   return storage == HENN_F32 ? 4 : storage == HENN_BF16 ? 2 : 1;
 }
 
+// Attempt cap of Alg. 2's repeat loop: max_attempts, or with 0 the smallest
+// t with phi^t <= 1e-9 (each attempt fails with probability phi).
+static int attempt_cap(const henn_build_params& p) {
+  if (p.max_attempts > 0) return p.max_attempts;
+  return std::max(1, (int)ceil(log(1e-9) / log(p.phi)));
+}
+
 static bool valid_build_params(const henn_build_params* p, std::string* why) {
   if (!p) { *why = "null build params"; return false; }
   if (p->struct_size != sizeof(henn_build_params)) { *why = "build params struct_size mismatch"; return false; }
@@ -104,7 +111,11 @@ static bool valid_build_params(const henn_build_params* p, std::string* why) {
   if (p->m < 1 || p->m > 30) { *why = "m must be in [1, 30]"; return false; }
   if (!(p->c0 > 0.0)) { *why = "c0 must be positive"; return false; }
   if (p->num_rings < 1 || p->num_rings > 4096) { *why = "num_rings in [1, 4096]"; return false; }
-  if (p->max_attempts < 1) { *why = "max_attempts >= 1"; return false; }
+  if (p->max_attempts < 0) { *why = "max_attempts >= 0"; return false; }
+  if (p->max_attempts == 0 && !(p->phi > 0.0 && p->phi < 1.0)) {
+    *why = "max_attempts = 0 needs phi in (0, 1)";
+    return false;
+  }
   if (p->degree < 1 || p->degree > 32) { *why = "degree in [1, 32]"; return false; }
   if (p->graph < HENN_GRAPH_KNN || p->graph > HENN_GRAPH_NSW) { *why = "graph"; return false; }
   const bool sym = p->graph == HENN_GRAPH_KNN_SYM || p->graph == HENN_GRAPH_PRUNED_SYM ||
@@ -495,8 +506,9 @@ static int sample_layer(henn_index* ix, int i, hipStream_t st, int32_t* local_ou
                               hipMemcpyHostToDevice, st));
       int best_t = -1, best_hits = -1;
       std::vector<uint32_t> hits((size_t)r);
+      const int cap = attempt_cap(p);
       int t = 0;
-      for (; t < p.max_attempts; ++t) {
+      for (; t < cap; ++t) {
         HENN_HIP(hipMemsetAsync(d_hits, 0, sizeof(uint32_t) * r, st));
         if (halving && t > 0) launch_halve(p.seed, i, t, s, p.m, local_out, st);
         launch_ring_hits(lpn, cpl, prev.vec32, ix->dpad, ix->nchunks, ix->metric, s, p.seed, i,
@@ -518,7 +530,7 @@ static int sample_layer(henn_index* ix, int i, hipStream_t st, int32_t* local_ou
         info.attempts = t + 1;
       } else {
         info.status = 3;
-        info.attempts = p.max_attempts;
+        info.attempts = cap;
       }
       info.hits = best_hits;
       accepted = best_t;
@@ -658,6 +670,7 @@ henn_status henn_default_build_params(henn_build_params* p) {
   p->seed = 0;
   p->sampler = HENN_SAMPLER_DRAWS;
   p->ef_construction = 256;
+  p->phi = 0.5;
   p->insert_shift = 3;
   return HENN_OK;
 }
@@ -1028,22 +1041,36 @@ static int root_mode(const henn_index* idx, const henn_search_params* sp) {
 // Scratch layout: 256 B (persistent work counter), then for mode 1 the
 // [splits][nq] root keys, for mode 2 the [nq] root keys and the Gram
 // shortlists (RootShortlist).
-static int64_t search_workspace_bytes(const henn_index* idx, int64_t nq,
-                                      const henn_search_params* sp) {
-  int64_t b = 256;
+static int64_t exact_visited_words(const henn_index* idx) {
+  return ((int64_t)idx->L[0].size + 31) / 32;
+}
+
+// Offset of the exact visited sets (HENN_SEARCH_EXACT_VISITED) in the
+// scratch: after the counter and the root-scan data, 256-byte aligned.
+static int64_t search_root_bytes(const henn_index* idx, int64_t nq,
+                                 const henn_search_params* sp) {
   const int64_t rs = idx->L[idx->num_layers - 1].size;
   int64_t per = 0;
   switch (root_mode(idx, sp)) {
     case 1:
-      b += (int64_t)sizeof(uint64_t) * root_scan_splits(nq, rs, &per) * nq;
-      break;
+      return (int64_t)sizeof(uint64_t) * root_scan_splits(nq, rs, &per) * nq;
     case 2:
-      b += (int64_t)sizeof(uint64_t) * nq + root_shortlist_bytes(nq, idx->root.kp);
-      break;
+      return (int64_t)sizeof(uint64_t) * nq + root_shortlist_bytes(nq, idx->root.kp);
     default:
-      break;
+      return 0;
   }
-  return b;
+}
+
+static int64_t exact_visited_offset(const henn_index* idx, int64_t nq,
+                                    const henn_search_params* sp) {
+  return (256 + search_root_bytes(idx, nq, sp) + 255) / 256 * 256;
+}
+
+static int64_t search_workspace_bytes(const henn_index* idx, int64_t nq,
+                                      const henn_search_params* sp) {
+  if (sp->flags & HENN_SEARCH_EXACT_VISITED)
+    return exact_visited_offset(idx, nq, sp) + nq * exact_visited_words(idx) * 4;
+  return 256 + search_root_bytes(idx, nq, sp);
 }
 
 // The search behind henn_search_batch and henn_search_batch_noalloc.
@@ -1149,9 +1176,11 @@ static henn_status search_impl(const henn_index* idx, const float* Q, int64_t nq
     sh.persistent = want_pers;
     sh.blocks = 0;
 
-    // scratch: the persistent work counter (256 B) then the root-scan keys
+    // scratch: the persistent work counter (256 B), the root-scan data, the
+    // exact visited sets
     const int rmode = root_mode(idx, sp);
-    if (sh.persistent || rmode != 0) {
+    const bool exact_vis = (sp->flags & HENN_SEARCH_EXACT_VISITED) != 0;
+    if (sh.persistent || rmode != 0 || exact_vis) {
       const int64_t need = search_workspace_bytes(idx, nq, sp);
       if (fixed) {
         if (fixed_bytes < need)
@@ -1167,6 +1196,10 @@ static henn_status search_impl(const henn_index* idx, const float* Q, int64_t nq
       }
     }
     if (sh.persistent) a.work_counter = reinterpret_cast<uint32_t*>(ws);
+    if (exact_vis) {
+      a.vis_exact = reinterpret_cast<uint32_t*>(ws + exact_visited_offset(idx, nq, sp));
+      a.vis_exact_words = exact_visited_words(idx);
+    }
     if (rmode == 2) {
       int64_t per = 0;
       const int splits = root_gram_splits(nq, idx->root.size, &per);

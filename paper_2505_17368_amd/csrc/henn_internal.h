@@ -185,6 +185,10 @@ struct SearchArgs {
   uint32_t* work_counter;  // persistent form: device query counter
   const uint64_t* root_best;  // [root_splits][nq] best root keys from k_root_scan, or nullptr
   int32_t root_splits;
+  // HENN_SEARCH_EXACT_VISITED: per query vis_exact_words 32-bit words, one
+  // bit per member of the largest layer, replacing the LDS table
+  uint32_t* vis_exact = nullptr;
+  int64_t vis_exact_words = 0;
 };
 
 // Traversal state of one query between expansions (wave-uniform).  The

@@ -616,9 +616,9 @@ __device__ inline void gather_all(const SearchArgs& a, const SearchLayer& L,
 // W (this wave's LDS list) holds the final list (st.wsize entries).  q: this
 // lane's FP32 query slice; qh: the same in f16 pairs (read by the FP8 form
 // only, which then never reads q).
-template <int KIND, int LPN, int CPL, bool FULL>
+template <int KIND, int LPN, int CPL, bool FULL, bool EXACT = false>
 __device__ bool advance(const SearchArgs& a, const float (&q)[CPL][8], const h2_t (&qh)[CPL][4],
-                        WaveLds s, uint64_t* W, QState& st, int budget) {
+                        WaveLds s, uint64_t* W, QState& st, int budget, uint32_t* vis_bm) {
   constexpr int G = 64 / LPN;
   const int lane = lane_id(), t = lane % LPN, g = lane / LPN;
   const int vis_n = 1 << a.vis_bits;
@@ -631,10 +631,17 @@ __device__ bool advance(const SearchArgs& a, const float (&q)[CPL][8], const h2_
         st.evals0 = st.evals;
       }
       st.evals += 1;  // the entry (its distance is carried down, counted per layer)
-      // empty: tag 0 (8 / 16-bit) or id -1 (32-bit); cleared as 32-bit words
-      const int vis_words = vis_n * a.vis_bytes / 4;
-      const uint32_t empty = a.vis_bytes < 4 ? 0u : 0xffffffffu;
-      for (int i = lane; i < vis_words; i += 64) static_cast<uint32_t*>(s.vis)[i] = empty;
+      if constexpr (EXACT) {
+        // the exact set: one bit per member of the layer, in the workspace
+        const int64_t words = ((int64_t)L.size + 31) >> 5;
+        for (int64_t i = lane; i < words; i += 64) vis_bm[i] = 0u;
+        __builtin_amdgcn_s_waitcnt(0);  // cleared before the first bit is set
+      } else {
+        // empty: tag 0 (8 / 16-bit) or id -1 (32-bit); cleared as 32-bit words
+        const int vis_words = vis_n * a.vis_bytes / 4;
+        const uint32_t empty = a.vis_bytes < 4 ? 0u : 0xffffffffu;
+        for (int i = lane; i < vis_words; i += 64) static_cast<uint32_t*>(s.vis)[i] = empty;
+      }
       if constexpr (KIND == kFP8) {
         // the entry's distance in the traversal's own form: the one handed
         // down (a root scan, or the first distance of the root) is the
@@ -653,9 +660,13 @@ __device__ bool advance(const SearchArgs& a, const float (&q)[CPL][8], const h2_
       wave_sync();
       if (lane == 0) {
         W[0] = wkey(st.cur_d, st.cur);
-        uint32_t h0, t0;
-        vis_slot(st.cur, a.vis_bits, a.vis_bytes, h0, t0);
-        vis_put(s.vis, a.vis_bytes, h0, t0);
+        if constexpr (EXACT) {
+          atomicOr(vis_bm + (st.cur >> 5), 1u << (st.cur & 31));
+        } else {
+          uint32_t h0, t0;
+          vis_slot(st.cur, a.vis_bits, a.vis_bytes, h0, t0);
+          vis_put(s.vis, a.vis_bytes, h0, t0);
+        }
       }
       st.wsize = 1;
       st.need_init = 0;
@@ -694,13 +705,22 @@ __device__ bool advance(const SearchArgs& a, const float (&q)[CPL][8], const h2_
         if (KIND == kFP8) usc = L.adj_scale[(int64_t)c * L.deg + lane];
       }
       bool fresh = false;
-      uint32_t h = 0, tag = 0;
-      if (u >= 0) {
-        vis_slot(u, a.vis_bits, a.vis_bytes, h, tag);
-        fresh = vis_get(s.vis, a.vis_bytes, h) != tag;
+      if constexpr (EXACT) {
+        // exact set: the bit's old value says whether u was seen (the
+        // update is atomic, so of lanes holding one id only one finds it new)
+        if (u >= 0) {
+          const uint32_t bit = 1u << (u & 31);
+          fresh = !(atomicOr(vis_bm + (u >> 5), bit) & bit);
+        }
+      } else {
+        uint32_t h = 0, tag = 0;
+        if (u >= 0) {
+          vis_slot(u, a.vis_bits, a.vis_bytes, h, tag);
+          fresh = vis_get(s.vis, a.vis_bytes, h) != tag;
+        }
+        wave_sync();
+        if (fresh) vis_put(s.vis, a.vis_bytes, h, tag);
       }
-      wave_sync();
-      if (fresh) vis_put(s.vis, a.vis_bytes, h, tag);
       const uint64_t fm = ballot(fresh);
       const int cnt = popc64(fm);
       // the scales ride in kstage, which is free until the merge below
@@ -863,7 +883,7 @@ __device__ void finish_query(const SearchArgs& a, const float (&q)[CPL][8], uint
   wave_sync();
 }
 
-template <int KIND, int LPN, int CPL, bool FULL>
+template <int KIND, int LPN, int CPL, bool FULL, bool EXACT>
 __device__ void search_one(const SearchArgs& a, int64_t qi, WaveLds s) {
   const int t = lane_id() % LPN;
   float q[CPL][8];
@@ -873,7 +893,8 @@ __device__ void search_one(const SearchArgs& a, int64_t qi, WaveLds s) {
   h2_t qh[CPL][4];
   if constexpr (KIND == kFP8) query_f16<CPL>(q, qh);
   uint64_t* W = s.W;
-  advance<KIND, LPN, CPL, FULL>(a, q, qh, s, W, st, 0x7fffffff);
+  uint32_t* vis_bm = EXACT ? a.vis_exact + qi * a.vis_exact_words : nullptr;
+  advance<KIND, LPN, CPL, FULL, EXACT>(a, q, qh, s, W, st, 0x7fffffff, vis_bm);
   // the FP8 traversal holds only the f16 query; the FP32 re-rank reads it again
   if constexpr (KIND == kFP8) load_query<CPL>(a.Q + qi * a.d, a.d, t, q);
   finish_query<KIND, LPN, CPL>(a, q, W, st, a.out_ids + qi * a.k_max,
@@ -924,7 +945,7 @@ __device__ __forceinline__ void serve_step_body(const SearchArgs& a, const Serve
   uint64_t* W = s.W;
   h2_t qh[CPL][4];
   if constexpr (KIND == kFP8) query_f16<CPL>(q, qh);
-  const bool done = advance<KIND, LPN, CPL, FULL>(a, q, qh, s, W, st, sv.budget);
+  const bool done = advance<KIND, LPN, CPL, FULL>(a, q, qh, s, W, st, sv.budget, nullptr);
   if (done) {
     if constexpr (KIND == kFP8) load_query<CPL>(a.Q + (int64_t)slot * a.d, a.d, t, q);
     // finished: append (slot, row) to this tick's compact completion list
@@ -1002,7 +1023,7 @@ static void launch_serve_one(const SearchArgs& a, const ServeArgs& sv, int wpb, 
                      (int)per_wave, wpb);
 }
 
-template <int KIND, int LPN, int CPL, bool FULL>
+template <int KIND, int LPN, int CPL, bool FULL, bool EXACT>
 __device__ __forceinline__ void search_kernel_body(const SearchArgs& a, int per_wave_bytes,
                                                    int waves_per_block, int persistent) {
   extern __shared__ __align__(16) char smem[];
@@ -1014,29 +1035,31 @@ __device__ __forceinline__ void search_kernel_body(const SearchArgs& a, int per_
       if (lane_id() == 0) qi = atomicAdd(a.work_counter, 1u);
       qi = (uint32_t)uni((int32_t)qi);
       if ((int64_t)qi >= a.nq) break;
-      search_one<KIND, LPN, CPL, FULL>(a, (int64_t)qi, s);
+      search_one<KIND, LPN, CPL, FULL, EXACT>(a, (int64_t)qi, s);
     }
   } else {
     const int64_t qi = (int64_t)blockIdx.x * waves_per_block + wave;
-    if (qi < a.nq) search_one<KIND, LPN, CPL, FULL>(a, qi, s);
+    if (qi < a.nq) search_one<KIND, LPN, CPL, FULL, EXACT>(a, qi, s);
   }
 }
 
-template <int KIND, int LPN, int CPL, bool FULL>
+template <int KIND, int LPN, int CPL, bool FULL, bool EXACT = false>
 __global__ __launch_bounds__(512) void k_search(SearchArgs a, int per_wave_bytes,
                                                 int waves_per_block, int persistent) {
-  search_kernel_body<KIND, LPN, CPL, FULL>(a, per_wave_bytes, waves_per_block, persistent);
+  search_kernel_body<KIND, LPN, CPL, FULL, EXACT>(a, per_wave_bytes, waves_per_block, persistent);
 }
 
 // The same kernel held to 80 registers (see six_waves).
 template <int KIND, int LPN, int CPL, bool FULL>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6))) void k_search6(
     SearchArgs a, int per_wave_bytes, int waves_per_block, int persistent) {
-  search_kernel_body<KIND, LPN, CPL, FULL>(a, per_wave_bytes, waves_per_block, persistent);
+  search_kernel_body<KIND, LPN, CPL, FULL, false>(a, per_wave_bytes, waves_per_block, persistent);
 }
 
 template <int KIND, int LPN, int CPL, bool FULL>
-static auto search_kernel() {
+static auto search_kernel(bool exact) {
+  // the exact visited set (an analysis form) runs the general-width kernel
+  if (exact) return &k_search<KIND, LPN, CPL, false, true>;
   if constexpr (six_waves<KIND, CPL>())
     return &k_search6<KIND, LPN, CPL, FULL>;
   else
@@ -1050,7 +1073,7 @@ static void launch_one(const SearchArgs& a, const LaunchShape& sh, hipStream_t s
   const size_t per_wave = search_lds_per_wave(a.ef_cap, a.vis_bits, a.vis_bytes);
   const int wpb = sh.waves_per_block;
   const size_t lds = per_wave * wpb;
-  auto kern = search_kernel<KIND, LPN, CPL, FULL>();
+  auto kern = search_kernel<KIND, LPN, CPL, FULL>(a.vis_exact != nullptr);
   if (sh.persistent) {
     int blocks = sh.blocks;
     if (blocks <= 0) {

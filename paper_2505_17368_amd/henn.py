@@ -26,7 +26,7 @@ HENN_F32, HENN_BF16, HENN_FP8_E4M3 = 0, 1, 2
 HENN_GRAPH_KNN, HENN_GRAPH_KNN_SYM, HENN_GRAPH_PRUNED, HENN_GRAPH_PRUNED_SYM = 0, 1, 2, 3
 GRAPH = {"knn": 0, "knn_sym": 1, "pruned": 2, "pruned_sym": 3, "nsw": 4}
 SAMPLER = {"draws": 0, "halving": 1}
-HENN_SEARCH_COUNTERS, HENN_SEARCH_PERSISTENT = 1, 2
+HENN_SEARCH_COUNTERS, HENN_SEARCH_PERSISTENT, HENN_SEARCH_EXACT_VISITED = 1, 2, 64
 # test-only flags (include/henn_testing.h)
 HENN_SEARCH_NO_ROOT_KERNEL, HENN_SEARCH_ROOT_VALU, HENN_SEARCH_VIS32, HENN_SEARCH_VIS16 = 4, 8, 16, 32
 STORAGE = {"f32": HENN_F32, "bf16": HENN_BF16, "fp8": HENN_FP8_E4M3}
@@ -41,7 +41,8 @@ class BuildParams(ctypes.Structure):
                 ("max_degree", ctypes.c_int32), ("graph", ctypes.c_int32),
                 ("storage", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("root_complete_max", ctypes.c_int32), ("sampler", ctypes.c_int32),
-                ("ef_construction", ctypes.c_int32), ("insert_shift", ctypes.c_int32)]
+                ("ef_construction", ctypes.c_int32), ("insert_shift", ctypes.c_int32),
+                ("phi", ctypes.c_double)]
 
 
 class SearchParams(ctypes.Structure):
@@ -336,7 +337,8 @@ def henn_nsw_insert(V, adj, lo: int, hi: int, degree: int, ef_construction: int,
 def search_params(k=10, ef=32, k_arr=None, ef_arr=None, k_max=None, ef_max=None, ef_upper=1,
                   rerank_factor=4, counters=None, persistent=False, lanes_per_vec=0,
                   waves_per_block=0, root_kernel=True, events=None,
-                  vis_bits=0, vis32=False, vis16=False, workspace=None) -> SearchParams:
+                  vis_bits=0, vis32=False, vis16=False, workspace=None,
+                  exact_visited=False) -> SearchParams:
     sp = SearchParams()
     _check(load_library().henn_default_search_params(ctypes.byref(sp)))
     sp.k_all = k
@@ -356,7 +358,8 @@ def search_params(k=10, ef=32, k_arr=None, ef_arr=None, k_max=None, ef_max=None,
         HENN_SEARCH_COUNTERS if counters is not None else 0) | (
         HENN_SEARCH_NO_ROOT_KERNEL if root_kernel is False else 0) | (
         HENN_SEARCH_ROOT_VALU if root_kernel == "valu" else 0) | (
-        HENN_SEARCH_VIS32 if vis32 else 0) | (HENN_SEARCH_VIS16 if vis16 else 0)
+        HENN_SEARCH_VIS32 if vis32 else 0) | (HENN_SEARCH_VIS16 if vis16 else 0) | (
+        HENN_SEARCH_EXACT_VISITED if exact_visited else 0)
     sp.lanes_per_vec = lanes_per_vec
     sp.waves_per_block = waves_per_block
     sp.vis_bits = vis_bits
@@ -383,7 +386,8 @@ def henn_search_batch(index: HennIndex, Q, k=10, ef=32, k_arr=None, ef_arr=None,
                       ef_max=None, ef_upper=1, rerank_factor=4, with_counters=False,
                       persistent=False, lanes_per_vec=0, waves_per_block=0, root_kernel=True,
                       events=None, vis_bits=0, out_ids=None, out_dist=None, stream=None,
-                      vis32=False, vis16=False, noalloc=False, workspace=None):
+                      vis32=False, vis16=False, noalloc=False, workspace=None,
+                      exact_visited=False):
     """Enqueues a batched search; returns (ids, dist[, counters]) device tensors.
     ``noalloc``: call henn_search_batch_noalloc (the library's fixed scratch;
     pass out_ids / out_dist to keep the call free of allocations here too).
@@ -403,7 +407,7 @@ def henn_search_batch(index: HennIndex, Q, k=10, ef=32, k_arr=None, ef_arr=None,
     counters = torch.zeros((nq, 4), dtype=torch.int32, device=Q.device) if with_counters else None
     sp = search_params(k, ef, k_arr, ef_arr, kmax, ef_max, ef_upper, rerank_factor, counters,
                        persistent, lanes_per_vec, waves_per_block, root_kernel, events,
-                       vis_bits, vis32, vis16, workspace)
+                       vis_bits, vis32, vis16, workspace, exact_visited)
     entry = load_library().henn_search_batch_noalloc if noalloc else \
         load_library().henn_search_batch
     _check(entry(index.handle, ctypes.c_void_p(Q.data_ptr()), nq, ctypes.byref(sp),

@@ -198,6 +198,34 @@ def test_counters_match_oracle_on_exact_queries(hn, ho, cfg1):
     idx.free()
 
 
+@pytest.mark.parametrize("storage,persistent", [(0, False), (2, True)])
+def test_exact_visited_counts_equal_oracle_and_keeps_results(hn, ho, cfg1, storage, persistent):
+    """With the exact visited set every node is evaluated once per layer, as
+    the method does: all four counters equal the oracle's on the queries whose
+    traversal decisions are not near ties, and the results are those of the
+    default table bit for bit."""
+    X, Q, oidx = cfg1
+    idx = _import(hn, X, oidx, storage=storage)
+    Qd = to_dev(Q[:300])
+    ei, ed, ec = hn.henn_search_batch(idx, Qd, k=10, ef=32, with_counters=True,
+                                      exact_visited=True, persistent=persistent)
+    di, dd, dc = hn.henn_search_batch(idx, Qd, k=10, ef=32, with_counters=True,
+                                      persistent=persistent)
+    _sync()
+    assert np.array_equal(ei.cpu().numpy(), di.cpu().numpy())
+    assert np.array_equal(ed.cpu().numpy().view(np.uint32), dd.cpu().numpy().view(np.uint32))
+    ec, dc = ec.cpu().numpy(), dc.cpu().numpy()
+    assert (dc[:, 1] >= ec[:, 1]).all() and np.array_equal(dc[:, 0], ec[:, 0])
+    if storage == 0:
+        ores = ho.search(oidx, Q[:300], 10, 32)
+        ok = ~exempt_mask(ores, X.shape[1])
+        print(f"exact-visited counters compared on {ok.sum()} of {len(ok)} queries; "
+              f"the table re-evaluated {int((dc[:, 1] - ec[:, 1]).sum())} rows")
+        assert ok.sum() >= 250
+        assert np.array_equal(ec[ok], ores.counters[ok])
+    idx.free()
+
+
 def test_edge_cases(hn, ho):
     # one point; fewer points than k; empty batch
     X = wl.uniform(5, 8, 30)
@@ -313,8 +341,11 @@ def _ring_outcomes(ho, X, prev, layer, p, window, attempts, d):
     return out
 
 
-@pytest.mark.parametrize("seed,status,attempts", [(4, "verified", 3), (6, "not_verified", 3)])
-def test_ring_check_at_400k_points_matches_oracle(hn, ho, seed, status, attempts):
+@pytest.mark.parametrize("seed,status,attempts,cap", [(4, "verified", 3, dict(max_attempts=3)),
+                                                       (6, "not_verified", 3, dict(max_attempts=3)),
+                                                       (6, "not_verified", 3,
+                                                        dict(max_attempts=0, phi=5e-4))])
+def test_ring_check_at_400k_points_matches_oracle(hn, ho, seed, status, attempts, cap):
     """Layer 1 of 400,000 points: the ring check ranks 400,000 keys per ring
     (the radix histogram's grid-stride loop runs more than once) with windows
     of 49 points, so samples are redrawn (Alg. 2's repeat) or the attempt cap
@@ -323,7 +354,7 @@ def test_ring_check_at_400k_points_matches_oracle(hn, ho, seed, status, attempts
     status, attempts, hits and member list equal the oracle's."""
     n, d = 400_000, 8
     X = wl.uniform(n, d, 90)
-    kw = dict(degree=8, seed=seed, eps_override=1.2e-4, max_layers=1, max_attempts=3)
+    kw = dict(degree=8, seed=seed, eps_override=1.2e-4, max_layers=1, **cap)
     p = ho.BuildParams(**kw)
     olayers, oinfo = ho.build_layers(X, p)
     info = oinfo[1]

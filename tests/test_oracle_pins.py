@@ -172,6 +172,16 @@ def test_layer_sample_verified_las_vegas(oracle):
     assert np.array_equal(members[1], np.unique(draws).astype(np.int32))
 
 
+def test_attempt_cap_from_phi(oracle):
+    """max_attempts 0: the cap is the smallest t with phi^t <= 1e-9, the
+    point where a layer that keeps failing at rate phi has had its chance."""
+    for phi, cap in ((0.5, 30), (0.2, 13), (5e-4, 3), (1e-9, 1), (0.999, 20713)):
+        p = oracle.BuildParams(max_attempts=0, phi=phi)
+        assert oracle.attempt_cap(p) == cap, phi
+        assert phi ** cap <= 1e-9 and (cap == 1 or phi ** (cap - 1) > 1e-9)
+    assert oracle.attempt_cap(oracle.BuildParams(max_attempts=7, phi=0.5)) == 7
+
+
 def test_layer_sample_not_verified_keeps_best(oracle):
     X = wl.uniform(800, 2, 0)
     p = oracle.BuildParams(degree=8, seed=5, eps_override=0.002, num_rings=64,
