@@ -284,7 +284,9 @@ void henn_search_graph_free(henn_search_graph *g);
  * Requests wait in a host FIFO and are admitted at a tick when a slot is
  * free and the device state pool has room for the request's traversal
  * state (list of next_pow2(max(ef, k, ef_upper)) 8-byte keys + the visited
- * table, rounded to 256 B): admission is by memory.  Each tick advances every
+ * table, rounded to 256 B): admission is by memory (a finished request's
+ * block is reused by later requests whose state has the same size; the rest
+ * comes from the unused part of the pool).  Each tick advances every
  * admitted request by at most steps_per_tick expansions in one launch, so
  * new requests join while others are in flight.  Results equal those of
  * henn_search_batch with the same shape (the traversal code is shared and
@@ -303,7 +305,8 @@ typedef struct {
   int32_t ef_max;         /* largest beam width */
   int32_t ef_upper;       /* beam width above layer 0 */
   int32_t rerank_factor;  /* precision forms */
-  int32_t lanes_per_vec;  /* 0 = default shape */
+  int32_t lanes_per_vec;  /* 0 = the shape henn_autotune chose for this index and
+                             storage (its beam bucket first), else the default */
   int32_t waves_per_block;
   int32_t vis_bits;       /* 0 = by beam width, as henn_search_batch chooses */
 } henn_server_params;
@@ -324,9 +327,14 @@ henn_status henn_server_submit(henn_server *s, const float *q_host, int32_t k, i
 /* n requests at once: q_host FP32 [n][d], k[n], ef[n], tags[n] (host). */
 henn_status henn_server_submit_batch(henn_server *s, const float *q_host, const int32_t *k,
                                      const int32_t *ef, const int64_t *tags, int64_t n);
-/* Admits what fits, advances every active request one step, retires the
- * finished ones to the completion queue.  Blocking (one short launch).
- * *n_active (may be NULL): requests in flight during this tick.
+/* Admits what fits, retires the requests the previous tick's step finished
+ * to the completion queue, and launches one step of every active request.
+ * The tick stages its admissions while the previous step still runs and
+ * returns without waiting for its own step, so the caller's work between
+ * ticks overlaps the device: a request's result reaches the completion queue
+ * in the tick after the one whose step finished it (call tick until every
+ * result has been polled).
+ * *n_active (may be NULL): requests in this tick's step.
  * HENN_E_INVAL once the index has been changed by henn_insert / henn_delete
  * since the server was created. */
 henn_status henn_server_tick(henn_server *s, int32_t *n_active);

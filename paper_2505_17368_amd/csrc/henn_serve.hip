@@ -26,50 +26,68 @@
 
 namespace henn {
 
-// first-fit allocator over [0, size) of the device arena (host bookkeeping)
+// Allocator of the device arena [0, size) (host bookkeeping).  A request's
+// state size is one of a few values (list capacity and visited table), so
+// freed blocks go to a free list per size and are reused by requests of the
+// same size; new blocks come from the untouched top of the arena.  Neither
+// operation scans: a lookup among the few sizes in use and a stack push/pop.
 class ArenaAlloc {
  public:
-  explicit ArenaAlloc(int64_t size) { free_[0] = size; }
+  explicit ArenaAlloc(int64_t size) : size_(size) {}
   bool alloc(int64_t len, int64_t* off) {
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-      if (it->second >= len) {
-        *off = it->first;
-        const int64_t rest = it->second - len, start = it->first + len;
-        free_.erase(it);
-        if (rest > 0) free_[start] = rest;
-        used_ += len;
-        return true;
-      }
+    auto it = free_.find(len);
+    if (it != free_.end() && !it->second.empty()) {
+      *off = it->second.back();
+      it->second.pop_back();
+    } else if (top_ + len <= size_) {
+      *off = top_;
+      top_ += len;
+    } else {
+      return false;
     }
-    return false;
+    used_ += len;
+    return true;
   }
   void release(int64_t off, int64_t len) {
     used_ -= len;
-    auto it = free_.emplace(off, len).first;
-    auto nx = std::next(it);
-    if (nx != free_.end() && it->first + it->second == nx->first) {
-      it->second += nx->second;
-      free_.erase(nx);
-    }
-    if (it != free_.begin()) {
-      auto pv = std::prev(it);
-      if (pv->first + pv->second == it->first) {
-        pv->second += it->second;
-        free_.erase(it);
-      }
-    }
+    free_[len].push_back(off);
   }
   int64_t used() const { return used_; }
 
  private:
-  std::map<int64_t, int64_t> free_;
-  int64_t used_ = 0;
+  std::map<int64_t, std::vector<int64_t>> free_;
+  int64_t size_, top_ = 0, used_ = 0;
 };
 
-struct Pending {
+// Requests waiting for admission, in arrival order: entries [head, size)
+// of meta, with their queries at q[d * i] (one contiguous buffer, so that a
+// request costs no allocation of its own).
+struct PendingQueue {
+  struct Meta {
+    int32_t k, ef;
+    int64_t tag;
+  };
+  std::vector<Meta> meta;
   std::vector<float> q;
-  int32_t k, ef;
-  int64_t tag;
+  size_t head = 0;
+  size_t size() const { return meta.size() - head; }
+  bool empty() const { return head == meta.size(); }
+  void push(const float* qv, int d, int32_t k, int32_t ef, int64_t tag) {
+    meta.push_back(Meta{k, ef, tag});
+    q.insert(q.end(), qv, qv + d);
+  }
+  void pop(int d) {
+    ++head;
+    if (head == meta.size()) {
+      meta.clear();
+      q.clear();
+      head = 0;
+    } else if (head > 4096 && head > meta.size() / 2) {
+      meta.erase(meta.begin(), meta.begin() + head);
+      q.erase(q.begin(), q.begin() + head * (size_t)d);
+      head = 0;
+    }
+  }
 };
 
 
@@ -91,32 +109,45 @@ struct henn_server {
   QState* states = nullptr;
   int64_t* state_off = nullptr;
   char* arena = nullptr;
-  // done_d: two completion counters, used by alternate ticks
+  // done_d: two completion counters, used by alternate steps
   int32_t* done_d = nullptr;
   float* stage_q_d = nullptr;
   int32_t* stage_meta_d = nullptr;
-  int32_t* rows_d = nullptr;  // completion rows of a tick (ServeArgs::done_rows)
+  int32_t* rows_d = nullptr;  // device address of rows_h: the kernel writes a tick's
+                              // completion rows straight into host memory
   // complete-graph root on matrix cores (prepared roots only): each admitted
   // request's root key, its shortlist scratch and the per-slot keys
   uint64_t* root_keys = nullptr;
   char* root_sl = nullptr;  // the admission batch's root shortlist
   uint64_t* slot_root = nullptr;
-  // pinned host
-  float* stage_q_h = nullptr;
-  int32_t* stage_meta_h = nullptr;
+  // pinned host; the staging buffers are doubled so that a tick can stage its
+  // admissions while the previous tick's step still runs
+  float* stage_q_h = nullptr;     // [2][max_slots][d]
+  int32_t* stage_meta_h = nullptr;  // [2][max_slots * 7]
   int32_t* done_h = nullptr;
   int32_t* rows_h = nullptr;
   // host state
+  bool inflight = false;  // a launched step whose completions are not yet retired
+  int inflight_parity = 0;
+  int inflight_active = 0;  // requests the launched step advanced
+  // steps launched so far; its parity picks the staging buffer and the
+  // completion counter of the next step (a tick with nothing active launches
+  // nothing and must not flip it: the counter a step counts into is cleared
+  // by the step before it)
+  int64_t launches = 0;
   ArenaAlloc* alloc = nullptr;
-  std::deque<Pending> pending;
+  PendingQueue pending;
   std::vector<int32_t> free_slots;
   std::vector<int32_t> active;
   std::vector<int64_t> slot_tag, slot_off, slot_bytes;
   std::vector<int32_t> slot_kk;
   // completed, not yet polled: tags, and per completion k_max ids then
   // k_max distance bits
-  std::deque<int64_t> done_tags;
-  std::deque<int32_t> done_vals;
+  // completion queue: entries [done_head, done_tags.size()) are waiting to
+  // be polled; entry i's ids and distance bits are done_vals[2 K i ..)
+  std::vector<int64_t> done_tags;
+  std::vector<int32_t> done_vals;
+  size_t done_head = 0;
   int64_t ticks = 0, admitted = 0, completed = 0, max_active = 0;
 };
 
@@ -142,7 +173,6 @@ static void srv_release(henn_server* s) {
   (void)hipFree(s->done_d);
   (void)hipFree(s->stage_q_d);
   (void)hipFree(s->stage_meta_d);
-  (void)hipFree(s->rows_d);
   (void)hipFree(s->root_keys);
   (void)hipFree(s->root_sl);
   (void)hipFree(s->slot_root);
@@ -159,10 +189,17 @@ template <typename T>
 static void dmalloc(T** p, int64_t n) {
   HENN_HIP(dev_alloc(reinterpret_cast<void**>(p), sizeof(T) * (size_t)std::max<int64_t>(n, 1)));
 }
+// Pinned host memory.  coherent: fine-grained memory the device writes
+// straight through (no copy in its caches), so that kernel stores are what
+// the host reads once the stream has completed.
 template <typename T>
-static void hmalloc(T** p, int64_t n) {
-  HENN_HIP(hipHostMalloc(reinterpret_cast<void**>(p), sizeof(T) * (size_t)std::max<int64_t>(n, 1),
-                         hipHostMallocDefault));
+static void hmalloc(T** p, int64_t n, bool coherent = false) {
+  const size_t bytes = sizeof(T) * (size_t)std::max<int64_t>(n, 1);
+  HENN_HIP(hipHostMalloc(reinterpret_cast<void**>(p), bytes,
+                         coherent ? (hipHostMallocCoherent | hipHostMallocMapped)
+                                  : hipHostMallocDefault));
+  // touch every page now, so that no tick pays for first-touch faults
+  memset(*p, 0, bytes);
 }
 
 // List capacity of a request: its layer-0 beam max(ef, k), and the beam of
@@ -216,13 +253,26 @@ henn_status henn_server_create(const henn_index* idx, const henn_server_params* 
                               : default_vis_bits(std::max(std::max(p->ef_max, p->k_max), p->ef_upper),
                                                  idx->n, true);
     if (s->vis_bits < 8 || s->vis_bits > 13) throw HipError{hipErrorInvalidValue, "vis_bits"};
+    // launch shape: the caller's, else the autotuned one of a batched search
+    // on this index with the same storage (the same beam bucket first)
+    int want_lpn = p->lanes_per_vec, want_wpb = p->waves_per_block;
+    {
+      std::lock_guard<std::mutex> lk(const_cast<henn_index*>(idx)->tune_mu);
+      const TuneEntry* pick = nullptr;
+      for (const TuneEntry& te : idx->tune)
+        if (te.storage == idx->storage && (!pick || te.ef_bucket == s->ef_cap)) pick = &te;
+      if (pick) {
+        if (!want_lpn) want_lpn = pick->lanes_per_vec;
+        if (!want_wpb) want_wpb = pick->waves_per_block;
+      }
+    }
     int lpn = 0, cpl = 0;
-    pick_lanes(idx->nchunks, p->lanes_per_vec, &lpn, &cpl);
+    pick_lanes(idx->nchunks, want_lpn, &lpn, &cpl);
     if (!lpn) throw HipError{hipErrorInvalidValue, "lanes_per_vec"};
     s->shape.lanes_per_vec = lpn;
     s->shape.chunks_per_lane = cpl;
     s->shape.vis_bits = s->vis_bits;
-    int wpb = p->waves_per_block ? p->waves_per_block : 4;
+    int wpb = want_wpb ? want_wpb : 4;
     while (wpb > 1 && search_lds_per_wave(s->ef_cap, s->vis_bits, vis_tag_bytes(idx->n, s->vis_bits)) * wpb > 65536) wpb /= 2;
     s->shape.waves_per_block = wpb;
     const int64_t M = p->max_slots;
@@ -240,16 +290,16 @@ henn_status henn_server_create(const henn_index* idx, const henn_server_params* 
     HENN_HIP(hipMemset(s->done_d, 0, sizeof(int32_t) * 2));
     dmalloc(&s->stage_q_d, M * s->d);
     dmalloc(&s->stage_meta_d, M * 7);  // admission metadata [n_new][6], then the active list
-    dmalloc(&s->rows_d, M * (1 + 2 * s->k_max));
     if (idx->root.size > 0) {
       dmalloc(&s->root_keys, M);
       dmalloc(&s->slot_root, M);
       dmalloc(&s->root_sl, root_shortlist_bytes(M, idx->root.kp));  // the largest admission
     }
-    hmalloc(&s->stage_q_h, M * s->d);
-    hmalloc(&s->stage_meta_h, M * 7);
+    hmalloc(&s->stage_q_h, 2 * M * s->d);
+    hmalloc(&s->stage_meta_h, 2 * M * 7);
     hmalloc(&s->done_h, 2);
-    hmalloc(&s->rows_h, M * (1 + 2 * s->k_max));
+    hmalloc(&s->rows_h, M * (1 + 2 * s->k_max), true);
+    HENN_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&s->rows_d), s->rows_h, 0));
     s->alloc = new ArenaAlloc(p->pool_bytes);
     s->slot_tag.assign(M, 0);
     s->slot_off.assign(M, 0);
@@ -273,12 +323,11 @@ henn_status henn_server_submit(henn_server* s, const float* q_host, int32_t k, i
   if (!s || !q_host) return srv_fail(HENN_E_INVAL, "null argument");
   if (k < 1 || k > s->k_max) return srv_fail(HENN_E_INVAL, "k outside [1, k_max]");
   if (ef < 1 || std::max(ef, k) > s->ef_cap) return srv_fail(HENN_E_INVAL, "ef outside [1, ef_max]");
-  Pending r;
-  r.q.assign(q_host, q_host + s->d);
-  r.k = k;
-  r.ef = ef;
-  r.tag = tag;
-  s->pending.push_back(std::move(r));
+  try {
+    s->pending.push(q_host, s->d, k, ef, tag);
+  } catch (const std::bad_alloc&) {
+    return srv_fail(HENN_E_NOMEM, "host allocation failed");
+  }
   return HENN_OK;
 }
 
@@ -289,18 +338,46 @@ henn_status henn_server_submit_batch(henn_server* s, const float* q_host, const 
     if (k[i] < 1 || k[i] > s->k_max || ef[i] < 1 || std::max(ef[i], k[i]) > s->ef_cap)
       return srv_fail(HENN_E_INVAL, "k or ef out of range");
   try {
-    for (int64_t i = 0; i < n; ++i) {
-      Pending r;
-      r.q.assign(q_host + i * s->d, q_host + (i + 1) * s->d);
-      r.k = k[i];
-      r.ef = ef[i];
-      r.tag = tags[i];
-      s->pending.push_back(std::move(r));
-    }
+    s->pending.meta.reserve(s->pending.meta.size() + n);
+    for (int64_t i = 0; i < n; ++i)
+      s->pending.meta.push_back(PendingQueue::Meta{k[i], ef[i], tags[i]});
+    s->pending.q.insert(s->pending.q.end(), q_host, q_host + n * s->d);
   } catch (const std::bad_alloc&) {
     return srv_fail(HENN_E_NOMEM, "host allocation failed");
   }
   return HENN_OK;
+}
+
+// Retires the launched step: waits for the stream, then moves its
+// completions (rows the kernel wrote into host memory) to the poll queue and
+// frees their slots and state bytes.
+static void retire_step(henn_server* s) {
+  if (!s->inflight) return;
+  HENN_HIP(hipStreamSynchronize(s->st));
+  s->inflight = false;
+  const int nd = s->done_h[s->inflight_parity];
+  // each request the step advanced completes at most once in it
+  if (nd > s->inflight_active) throw HipError{hipErrorIllegalState, "completion count"};
+  if (nd <= 0) return;
+  const int words = 1 + 2 * s->k_max;
+  std::vector<char> finished(s->p.max_slots, 0);
+  s->done_tags.reserve(s->done_tags.size() + nd);
+  s->done_vals.reserve(s->done_vals.size() + (size_t)nd * (words - 1));
+  for (int i = 0; i < nd; ++i) {
+    const int32_t* row = s->rows_h + (int64_t)i * words;
+    const int32_t slot = row[0];
+    s->done_tags.push_back(s->slot_tag[slot]);
+    s->done_vals.insert(s->done_vals.end(), row + 1, row + words);
+    s->alloc->release(s->slot_off[slot], s->slot_bytes[slot]);
+    s->free_slots.push_back(slot);
+    finished[slot] = 1;
+    ++s->completed;
+  }
+  std::vector<int32_t> keep;
+  keep.reserve(s->active.size());
+  for (int32_t sl : s->active)
+    if (!finished[sl]) keep.push_back(sl);
+  s->active.swap(keep);
 }
 
 henn_status henn_server_tick(henn_server* s, int32_t* n_active_out) {
@@ -310,17 +387,23 @@ henn_status henn_server_tick(henn_server* s, int32_t* n_active_out) {
   if (s->idx->updates != s->idx_updates)
     return srv_fail(HENN_E_INVAL, "the index was updated after this server was created");
   try {
-    // 1) admission: FIFO, while a slot and arena bytes are free
+    // 1) admission, FIFO, while a slot and arena bytes are free, into this
+    //    step's staging buffer (the previous step may still run)
+    const int64_t M = s->p.max_slots;
+    const int c = (int)(s->launches & 1);
+    float* stage_q = s->stage_q_h + (size_t)c * M * s->d;
+    int32_t* stage_meta = s->stage_meta_h + (size_t)c * M * 7;
     int n_new = 0;
     while (!s->pending.empty() && !s->free_slots.empty()) {
-      const Pending& r = s->pending.front();
+      const PendingQueue::Meta& r = s->pending.meta[s->pending.head];
+      const float* rq = s->pending.q.data() + s->pending.head * (size_t)s->d;
       const int64_t need = state_bytes(s, r.k, r.ef);
       int64_t off = 0;
       if (!s->alloc->alloc(need, &off)) break;
       const int32_t slot = s->free_slots.back();
       s->free_slots.pop_back();
-      memcpy(s->stage_q_h + (int64_t)n_new * s->d, r.q.data(), sizeof(float) * s->d);
-      int32_t* m = s->stage_meta_h + n_new * 6;
+      memcpy(stage_q + (int64_t)n_new * s->d, rq, sizeof(float) * s->d);
+      int32_t* m = stage_meta + n_new * 6;
       m[0] = slot;
       m[1] = r.k;
       m[2] = r.ef;
@@ -332,10 +415,13 @@ henn_status henn_server_tick(henn_server* s, int32_t* n_active_out) {
       s->slot_bytes[slot] = need;
       s->slot_kk[slot] = r.k;
       s->active.push_back(slot);
-      s->pending.pop_front();
+      s->pending.pop(s->d);
       ++n_new;
       ++s->admitted;
     }
+    // 2) the previous step's completions free their slots (for the next tick)
+    retire_step(s);
+    // 3) this tick's launches
     const henn_index* idx = s->idx;
     SearchArgs a;
     memset(&a, 0, sizeof(a));
@@ -369,14 +455,14 @@ henn_status henn_server_tick(henn_server* s, int32_t* n_active_out) {
     a.vis_bytes = vis_tag_bytes(idx->n, s->vis_bits);
     a.root_complete = idx->root_complete ? 1 : 0;
     if (n_new > 0) {
-      HENN_HIP(hipMemcpyAsync(s->stage_q_d, s->stage_q_h, sizeof(float) * n_new * s->d,
+      HENN_HIP(hipMemcpyAsync(s->stage_q_d, stage_q, sizeof(float) * n_new * s->d,
                               hipMemcpyHostToDevice, s->st));
     }
     // one H2D copy: the admission metadata, then the active list
     const int n_active = (int)s->active.size();
-    memcpy(s->stage_meta_h + n_new * 6, s->active.data(), sizeof(int32_t) * n_active);
+    memcpy(stage_meta + n_new * 6, s->active.data(), sizeof(int32_t) * n_active);
     if (n_new + n_active > 0)
-      HENN_HIP(hipMemcpyAsync(s->stage_meta_d, s->stage_meta_h,
+      HENN_HIP(hipMemcpyAsync(s->stage_meta_d, stage_meta,
                               sizeof(int32_t) * (n_new * 6 + n_active), hipMemcpyHostToDevice,
                               s->st));
     if (n_new > 0) {
@@ -399,11 +485,11 @@ henn_status henn_server_tick(henn_server* s, int32_t* n_active_out) {
     }
     s->max_active = std::max<int64_t>(s->max_active, n_active);
     if (n_active_out) *n_active_out = n_active;
+    ++s->ticks;
     if (n_active == 0) return HENN_OK;
-    // 2) one step of every active request; completions are counted in
-    //    done_d[c] (c = tick parity) while the kernel clears done_d[c ^ 1] for
-    //    the next tick
-    const int c = (int)(s->ticks & 1);
+    // one step of every active request; completions are counted in done_d[c]
+    // (c = launch parity) while the kernel clears done_d[c ^ 1] for the next
+    // step
     a.Q = s->slot_q;
     a.nq = s->p.max_slots;
     a.k_arr = s->slot_k;
@@ -426,34 +512,14 @@ henn_status henn_server_tick(henn_server* s, int32_t* n_active_out) {
     if (!launch_serve_step(idx->storage, a, sv, s->shape, s->st))
       return srv_fail(HENN_E_UNSUPPORTED, "no serving kernel for this shape");
     HENN_HIP(hipGetLastError());
-    // 3) completions: count, then the finished slots and their rows
-    HENN_HIP(hipMemcpyAsync(s->done_h, s->done_d + c, sizeof(int32_t), hipMemcpyDeviceToHost,
-                            s->st));
-    HENN_HIP(hipStreamSynchronize(s->st));
-    const int nd = s->done_h[0];
-    ++s->ticks;
-    if (nd > 0) {
-      const int words = 1 + 2 * s->k_max;
-      HENN_HIP(hipMemcpyAsync(s->rows_h, s->rows_d, sizeof(int32_t) * nd * words,
-                              hipMemcpyDeviceToHost, s->st));
-      HENN_HIP(hipStreamSynchronize(s->st));
-      std::vector<char> finished(s->p.max_slots, 0);
-      for (int i = 0; i < nd; ++i) {
-        const int32_t* row = s->rows_h + (int64_t)i * words;
-        const int32_t slot = row[0];
-        s->done_tags.push_back(s->slot_tag[slot]);
-        s->done_vals.insert(s->done_vals.end(), row + 1, row + words);
-        s->alloc->release(s->slot_off[slot], s->slot_bytes[slot]);
-        s->free_slots.push_back(slot);
-        finished[slot] = 1;
-        ++s->completed;
-      }
-      std::vector<int32_t> keep;
-      keep.reserve(s->active.size());
-      for (int32_t sl : s->active)
-        if (!finished[sl]) keep.push_back(sl);
-      s->active.swap(keep);
-    }
+    // the count follows the step on the stream; the next tick (or a drain)
+    // retires the step
+    HENN_HIP(hipMemcpyAsync(s->done_h + c, s->done_d + c, sizeof(int32_t),
+                            hipMemcpyDeviceToHost, s->st));
+    s->inflight = true;
+    s->inflight_parity = c;
+    s->inflight_active = n_active;
+    ++s->launches;
     return HENN_OK;
   } catch (const HipError& e) {
     henn::set_error(std::string("server tick: HIP error ") + hipGetErrorString(e.e) + " in " + e.what);
@@ -466,16 +532,26 @@ henn_status henn_server_tick(henn_server* s, int32_t* n_active_out) {
 henn_status henn_server_poll(henn_server* s, int32_t max_results, int64_t* tags, int32_t* ids,
                              float* dist, int32_t* n_out) {
   if (!s || !n_out) return srv_fail(HENN_E_INVAL, "null argument");
-  int n = 0;
   const int K = s->k_max;
-  while (n < max_results && !s->done_tags.empty()) {
-    if (tags) tags[n] = s->done_tags.front();
-    auto it = s->done_vals.begin();
-    if (ids) std::copy(it, it + K, ids + (int64_t)n * K);
-    if (dist) std::copy(it + K, it + 2 * K, reinterpret_cast<int32_t*>(dist) + (int64_t)n * K);
-    s->done_vals.erase(it, it + 2 * K);
-    s->done_tags.pop_front();
-    ++n;
+  const size_t avail = s->done_tags.size() - s->done_head;
+  const int n = (int)std::min<size_t>(avail, (size_t)std::max(max_results, 0));
+  for (int i = 0; i < n; ++i) {
+    const size_t e = s->done_head + (size_t)i;
+    const int32_t* v = s->done_vals.data() + e * 2 * (size_t)K;
+    if (tags) tags[i] = s->done_tags[e];
+    if (ids) memcpy(ids + (int64_t)i * K, v, sizeof(int32_t) * K);
+    if (dist) memcpy(dist + (int64_t)i * K, v + K, sizeof(float) * K);
+  }
+  s->done_head += (size_t)n;
+  if (s->done_head == s->done_tags.size()) {
+    s->done_tags.clear();
+    s->done_vals.clear();
+    s->done_head = 0;
+  } else if (s->done_head > s->done_tags.size() / 2) {
+    // drop the polled half so the queue does not grow without bound
+    s->done_tags.erase(s->done_tags.begin(), s->done_tags.begin() + s->done_head);
+    s->done_vals.erase(s->done_vals.begin(), s->done_vals.begin() + s->done_head * 2 * K);
+    s->done_head = 0;
   }
   *n_out = n;
   return HENN_OK;
@@ -490,7 +566,7 @@ henn_status henn_server_stats(const henn_server* s, henn_server_stats_t* out) {
   out->ticks = s->ticks;
   out->pool_bytes_used = s->alloc->used();
   out->max_active = s->max_active;
-  out->done_queued = (int64_t)s->done_tags.size();
+  out->done_queued = (int64_t)(s->done_tags.size() - s->done_head);
   return HENN_OK;
 }
 

@@ -98,6 +98,31 @@ def test_mix_with_staggered_arrivals_and_memory_admission(setup):
     srv.close()
 
 
+def test_waves_separated_by_idle_ticks(setup):
+    """A wave that finishes within one step, then ticks with nothing active,
+    then a second wave into the same slots: every request gets its own
+    result (the completion counter a step counts into starts from zero
+    whatever the ticks in between did)."""
+    hn, X, Q, idx = setup
+    ref_i, ref_d = _batch(hn, idx, Q[:32], 10, 64)
+    srv = hn.Server(idx, max_slots=16, k_max=10, ef_max=64, steps_per_tick=100000, vis_bits=10)
+    got = {}
+    for wave in range(2):
+        for j in range(16 * wave, 16 * wave + 16):
+            srv.submit(Q[j], 10, 64, j)
+        for _ in range(4):  # the step, its retirement, then idle ticks
+            srv.tick()
+            tags, ids, dist = srv.poll()
+            for t, i, d in zip(tags, ids, dist):
+                got[int(t)] = (i.copy(), d.copy())
+        assert len(got) == 16 * (wave + 1)
+        assert srv.stats()["active"] == 0
+    srv.close()
+    for j in range(32):
+        assert np.array_equal(got[j][0], ref_i[j]), j
+        assert np.array_equal(got[j][1].view(np.uint32), ref_d[j].view(np.uint32)), j
+
+
 @pytest.mark.parametrize("storage", [0, 2])
 def test_serving_and_captured_graph_after_updates(storage):
     """After Delete(x) and Insert(x) on an NSW index, the serving form and a
