@@ -69,7 +69,13 @@ def parse():
                          "of a mixed-k / mixed-ef persistent batch (10M x 128, FP8 by default); "
                          "worstcase: eps-net against random layers on skewed data; dynamic: "
                          "Insert / Delete on an NSW index")
-    ap.add_argument("--wc-runs", type=int, default=3, help="worstcase: builds per configuration")
+    ap.add_argument("--wc-runs", type=int, default=8, help="worstcase: builds per configuration")
+    ap.add_argument("--wc-rho-runs", type=int, default=100,
+                    help="worstcase: runs per recall-bound configuration")
+    ap.add_argument("--wc-rho-nq", type=int, default=200,
+                    help="worstcase: queries per recall-bound run")
+    ap.add_argument("--wc-parts", default="hops,rho",
+                    help="worstcase: hops (hop and query-time study), rho (recall bound)")
     ap.add_argument("--wc-nq", type=int, default=1000, help="worstcase: queries per configuration")
     ap.add_argument("--wc-c0d", type=float, default=0.32,
                     help="worstcase: c0 * d of Eq. (1) for the eps-net layers")
@@ -114,8 +120,9 @@ def quality(ids, dist, gt_dist, X, Q, sample, metric):
     counts when its FP64 distance is at most the true k-th; the sums run in a
     different order than the oracle's, so 1e-9 relative is allowed), and the
     returned distances' error against FP64 recomputation: max / mean relative
-    error and the mean ratio of the j-th returned FP64 distance to the true
-    j-th (L2; 1 = exact)."""
+    error and, per query, the sum of the returned FP64 distances over the sum
+    of the true ones (L2; 1 = exact), averaged over the queries (a ratio of
+    sums, so that near-zero true distances do not dominate)."""
     k = gt_dist.shape[1]
     I = ids[sample][:, :k]
     ok = I >= 0
@@ -129,11 +136,55 @@ def quality(ids, dist, gt_dist, X, Q, sample, metric):
     ci = float(1.96 * per_q.std(ddof=1) / np.sqrt(len(per_q))) if len(per_q) > 1 else None
     dsel = dist[sample][:, :k].astype(np.float64)
     err = np.abs(dsel - dd)[ok] / np.maximum(np.abs(dd[ok]), 1e-30)
-    ratio = (dd / np.maximum(gt_dist, 1e-30))[ok] if metric == 0 else None
+    ratio = None
+    if metric == 0:
+        got_sum = np.where(ok, dd, 0.0).sum(1)
+        true_sum = np.where(ok, gt_dist, 0.0).sum(1)
+        ratio = got_sum / np.maximum(true_sum, 1e-30)
     return {"recall": rec, "recall_ci95": ci,
             "max_rel_err": float(err.max()) if err.size else 0.0,
             "mean_rel_err": float(err.mean()) if err.size else 0.0,
             "mean_dist_ratio": float(ratio.mean()) if ratio is not None and ratio.size else None}
+
+
+def exact_knn(X, Q, k, metric=0):
+    """Ground truth of the measurements: the exact k nearest neighbours of
+    each query by brute force in FP64 with plain torch on the GPU (L2:
+    squared distance, IP: negated inner product), then the kept distances
+    recomputed directly in FP64 on the host.  Returns host arrays (ids int64,
+    distances float64), rows sorted by distance."""
+    import torch
+    dev = torch.device("cuda:0")
+    X64 = torch.from_numpy(np.ascontiguousarray(X)).to(dev, torch.float64)
+    xn = (X64 * X64).sum(1)
+    n = X.shape[0]
+    chunk = int(max(1, min(256, (1 << 31) // max(n, 1))))
+    ids = np.empty((Q.shape[0], k), np.int64)
+    for s in range(0, Q.shape[0], chunk):
+        q = torch.from_numpy(np.ascontiguousarray(Q[s:s + chunk])).to(dev, torch.float64)
+        g = q @ X64.T
+        dd = xn[None, :] - 2.0 * g + (q * q).sum(1)[:, None] if metric == 0 else -g
+        ids[s:s + chunk] = torch.topk(dd, k, dim=1, largest=False, sorted=True)[1].cpu().numpy()
+        del g, dd
+    del X64, xn
+    xs = X[ids].astype(np.float64)
+    qv = Q.astype(np.float64)[:, None, :]
+    dist = ((xs - qv) ** 2).sum(-1) if metric == 0 else -(xs * qv).sum(-1)
+    order = np.argsort(dist, axis=1, kind="stable")
+    return np.take_along_axis(ids, order, 1), np.take_along_axis(dist, order, 1)
+
+
+def recall_at_k(ids, gt_dist, X, Q, metric=0):
+    """Tie-tolerant Recall@k: a returned id counts when its FP64 distance is
+    at most the true k-th (1e-9 relative for summation order)."""
+    k = gt_dist.shape[1]
+    I = ids[:, :k]
+    ok = I >= 0
+    xs = X[np.maximum(I, 0)].astype(np.float64)
+    qv = Q.astype(np.float64)[:, None, :]
+    dd = ((xs - qv) ** 2).sum(-1) if metric == 0 else -(xs * qv).sum(-1)
+    kth = gt_dist[:, k - 1][:, None]
+    return float((ok & (dd <= kth + 1e-9 * np.abs(kth))).sum() / I.size)
 
 
 def calib_copy():
@@ -247,16 +298,14 @@ def main():
         build_s[f] = build_s["f32"] + time.time() - t
     layers_info = [base.layer_info(i) for i in range(base.num_layers)]
 
-    # ---- CPU leg: exact FP64 ground truth of the queries ----
-    from oracle import henn_oracle as ho
+    # ---- exact FP64 ground truth of the queries ----
     threads, affinity, nproc = cpu_threads()
     rng = np.random.default_rng(123)
     sample = (np.arange(nq) if args.gt_sample <= 0 or args.gt_sample >= nq
               else np.sort(rng.choice(nq, args.gt_sample, replace=False)))
     t = time.time()
-    gt_ids, gt_dist = ho.brute_force_knn_gram(X, Q[sample], k, metric, threads=threads)
-    log(f"oracle ground truth for {len(sample)} queries in {time.time() - t:.1f}s "
-        f"({threads} threads)")
+    gt_ids, gt_dist = exact_knn(X, Q[sample], k, metric)
+    log(f"exact FP64 ground truth for {len(sample)} queries in {time.time() - t:.1f}s")
 
     def dist_rows(qi, ids):
         ok = ids >= 0
@@ -346,17 +395,17 @@ def main():
     ef = head["ef"]
     pers = head["persistent"]
 
-    # ---- counters for the algorithmic byte model (FP32 form, same ef) ----
-    _, _, cnt = hn.henn_search_batch(base, Qd, k=k, ef=ef, k_max=k, ef_max=ef,
-                                     with_counters=True, lanes_per_vec=4, waves_per_block=4,
-                                     vis_bits=10)
+    # ---- counts of the algorithmic byte model: the same search with an exact
+    # visited set, which evaluates each node once per layer as the method does
+    _, _, cnt = hn.henn_search_batch(idx, Qd, k=k, ef=ef, k_max=k, ef_max=ef,
+                                     with_counters=True, exact_visited=True)
     torch.cuda.synchronize()
     cnt = cnt.cpu().numpy().astype(np.float64)
 
     # ---- CPU baseline: the oracle's search on the same index (host cores) ----
     cpu = None
-    oracle_counts = None
     if not args.no_cpu:
+        from oracle import henn_oracle as ho
         ids_l = [e[0] for e in exported]
         adj_l = [e[1] for e in exported]
         oidx = ho.index_from_arrays(X, metric, ids_l, adj_l,
@@ -364,18 +413,15 @@ def main():
         # grow the sample until the oracle has worked ~cpu_seconds
         m = min(nq, 256)
         done, el = 0, 0.0
-        counts = []
         while True:
             sub = Q[done % nq: done % nq + m] if done % nq + m <= nq else Q[:m]
             t = time.time()
-            r = ho.search(oidx, sub, k, ef, 1, threads=threads)
+            ho.search(oidx, sub, k, ef, 1, threads=threads)
             el += time.time() - t
-            counts.append(r.counters)
             done += len(sub)
             if el >= args.cpu_seconds or done >= 64 * nq:
                 break
             m = min(nq, m * 2)
-        oracle_counts = np.concatenate(counts).astype(np.float64)
         # one thread, query by query, on the first 1,000 queries
         n1 = min(nq, 1000)
         lat = np.empty(n1)
@@ -441,7 +487,7 @@ def main():
     # ---- roofline of the search kernel (HBM bound, algorithmic bytes) ----
     b = {"f32": 4, "bf16": 2, "fp8": 1}[head_form]
     bs = 4 if head_form == "fp8" else 0
-    src = oracle_counts if oracle_counts is not None else cnt
+    src = cnt
     # the root's exhaustive scan runs in its own kernels; the roofline is that
     # of the dominant kernel, k_search: the layers below the root, each
     # evaluation a row gather, each expansion an adjacency row
@@ -472,7 +518,7 @@ def main():
                 "bytes_per_query": round(bytes_q, 1), "evals_per_query": round(evals, 1),
                 "expansions_per_query": round(exps, 1), "kernel": "k_search",
                 "kernel_ms": round(kernel_ms, 4),
-                "count_source": "oracle" if oracle_counts is not None else "gpu"}
+                "count_source": "exact-visited search"}
 
     dtype_of = {"f32": "f32", "bf16": "bf16 storage, f32 accumulate",
                 "fp8": "fp8_e4m3 storage, f16 difference, f32 accumulate"}
@@ -528,11 +574,10 @@ def adversarial_experiment(hn, args, threads, wname="curve_1M_d96", storage="bf1
     near the dense end of random periods; BF16 traversal rows and an FP32
     re-rank of 4k = 40 candidates, k = 10.  The smallest swept beam width
     whose Recall@10 (all queries, exact FP64 ground truth) reaches the target
-    is timed; the roofline of k_search uses the oracle's exact-visited counts
-    on 500 of the queries."""
+    is timed; the roofline of k_search uses the counts of the same search
+    with an exact visited set."""
     import torch
     import workloads as wl
-    from oracle import henn_oracle as ho
     dev = torch.device("cuda:0")
     k = 10
     X, Q = wl.make(wname)
@@ -553,7 +598,7 @@ def adversarial_experiment(hn, args, threads, wname="curve_1M_d96", storage="bf1
     idx = hn.henn_import(Xd, [e[0] for e in ex], [e[1] for e in ex], storage=st_code, **bp)
     t = time.time()
     sample = np.arange(nq)
-    _, gt_dist = ho.brute_force_knn_gram(X, Q, k, 0, threads=threads)
+    _, gt_dist = exact_knn(X, Q, k, 0)
     log(f"adversarial: build {build_s:.1f}s, layers {sizes}, ground truth "
         f"{time.time() - t:.1f}s")
     sweep, pick = [], None
@@ -589,12 +634,12 @@ def adversarial_experiment(hn, args, threads, wname="curve_1M_d96", storage="bf1
         ts.append(e0.elapsed_time(e1))
         ks.append(k0.elapsed_time(k1))
     ms, kms = float(np.median(ts)), float(np.mean(ks))
-    oidx = ho.index_from_arrays(X, 0, [e[0] for e in ex], [e[1] for e in ex],
-                                root_complete=args.root_max > 0 and len(ex) >= 2)
-    r = ho.search(oidx, Q[:500], k, ef, 1, threads=threads)
+    _, _, cnt = hn.henn_search_batch(idx, Qd, k=k, ef=ef, with_counters=True,
+                                     exact_visited=True)
+    cnt = cnt.cpu().numpy().astype(np.float64)
     root_n = sizes[-1] if args.root_max > 0 and len(sizes) >= 2 else 0
-    evals = r.counters[:, 1].mean() - root_n
-    exps = r.counters[:, 0].mean()
+    evals = cnt[:, 1].mean() - root_n
+    exps = cnt[:, 0].mean()
     deg = ex[0][1].shape[1]
     bytes_q = evals * d * 2 + exps * deg * 4 + min(ef, 4 * k) * d * 4 + d * 4 + k * 8
     achieved = bytes_q * nq / (kms / 1e3) / 1e9
@@ -611,7 +656,8 @@ def adversarial_experiment(hn, args, threads, wname="curve_1M_d96", storage="bf1
                          "kernel": "k_search", "kernel_ms": round(kms, 4),
                          "bytes_per_query": round(bytes_q, 1),
                          "evals_per_query": round(evals, 1),
-                         "expansions_per_query": round(exps, 1), "count_source": "oracle"},
+                         "expansions_per_query": round(exps, 1),
+                         "count_source": "exact-visited search"},
             "build_s": round(build_s, 2), "layers": sizes, "sweep": sweep,
             "graph": args.graph, "degree": args.degree, "max_degree": args.max_degree,
             "root_complete_max": args.root_max}
@@ -706,7 +752,6 @@ def batched(args):
 
     import paper_2505_17368_amd as hn
     import workloads as wl
-    from oracle import henn_oracle as ho
 
     wname = args.workload if args.workload != "gmm100_1M_d128" else "gmm1000_10M_d128"
     w = wl.WORKLOADS[wname]
@@ -762,12 +807,12 @@ def batched(args):
     wall = time.perf_counter() - t_start
     kms = np.array([a.elapsed_time(b) for a, b in evs])
     ids = g.ids.cpu().numpy()
-    # recall per k class on a sample, against the oracle's FP64 brute force
+    # recall per k class on a sample, against exact FP64 brute force
     rng = np.random.default_rng(123)
     sample = np.sort(rng.choice(nq, min(args.gt_sample, nq), replace=False))
     t = time.time()
-    gt_ids, gt_dist = ho.brute_force_knn(X, Q[sample], 100, metric)
-    log(f"oracle ground truth (k=100) for {len(sample)} queries in {time.time() - t:.1f}s")
+    gt_ids, gt_dist = exact_knn(X, Q[sample], 100, metric) if len(sample) else (None, None)
+    log(f"exact ground truth (k=100) for {len(sample)} queries in {time.time() - t:.1f}s")
     per_k = {}
     for kk in (1, 10, 100):
         sel = [j for j, qi in enumerate(sample) if ks[qi] == kk]
@@ -812,7 +857,6 @@ def serving(args):
 
     import paper_2505_17368_amd as hn
     import workloads as wl
-    from oracle import henn_oracle as ho
 
     wname = args.workload if args.workload != "gmm100_1M_d128" else "spectral_5M_d768"
     w = wl.WORKLOADS[wname]
@@ -849,8 +893,8 @@ def serving(args):
     rng = np.random.default_rng(123)
     sample = np.sort(rng.choice(nq, min(args.gt_sample, nq), replace=False))
     t = time.time()
-    _, gt_dist = ho.brute_force_knn(X, Q[sample], 10, metric)
-    log(f"oracle ground truth for {len(sample)} queries in {time.time() - t:.1f}s")
+    _, gt_dist = exact_knn(X, Q[sample], 10, metric)
+    log(f"exact ground truth for {len(sample)} queries in {time.time() - t:.1f}s")
 
     def dist_rows(qi, ids):
         ok = ids >= 0
@@ -906,22 +950,62 @@ def serving(args):
     print(json.dumps(out), flush=True)
 
 
+def hits_curve(ranks, kmax):
+    """Average hits of the recall-bound experiment (App. G.4): for k = 1 ..
+    kmax, the fraction of greedy searches whose result is among the k
+    nearest points of its query (ranks: 1 = the nearest)."""
+    r = np.asarray(ranks).ravel()
+    return np.array([(r <= k).mean() for k in range(1, kmax + 1)]) if r.size else np.zeros(kmax)
+
+
+def recall_bound(ranks, delta):
+    """rho_delta of Sec. 3 (recall bound): the smallest k such that the
+    greedy result lies among the k nearest points with probability at least
+    delta, the probability taken as the fraction of the searches observed."""
+    r = np.sort(np.asarray(ranks).ravel())
+    if r.size == 0:
+        raise ValueError("no searches")
+    return int(r[int(np.ceil(delta * r.size)) - 1])
+
+
+def ranks_of(Xd, Qd, got):
+    """Rank of each query's result among all points (1 = nearest): one plus
+    the points strictly closer than it, squared L2 in FP64 on the GPU."""
+    import torch
+    X64 = Xd.double()
+    xn = (X64 * X64).sum(1)
+    out = np.empty(Qd.shape[0], np.int64)
+    g_all = torch.from_numpy(np.asarray(got)).to(Xd.device, torch.int64)
+    for s in range(0, Qd.shape[0], 256):
+        q = Qd[s:s + 256].double()
+        dd = xn[None, :] - 2.0 * (q @ X64.T)
+        mine = dd.gather(1, g_all[s:s + 256, None])
+        out[s:s + 256] = ((dd < mine).sum(1) + 1).cpu().numpy()
+    return out
+
+
 def worstcase(args):
     """The paper's synthetic worst-case study (Sec. 4.2 "Synthetic Dataset",
-    App. G.5 recall bounds) on the GPU path: HENN with verified eps-net layers
-    (Eq. (1) with a small c0, so that the ring check of App. B.1 rejects
-    samples) against the same construction with every ring vacuous (random
-    layers, the HNSW-style hierarchy), on skewed exponential data (``expskew``).
-    Both use NSW graphs (App. B.2) and the same build seeds.  Per build:
-    Alg. 4 greedy queries (k = 1, ef = 1) give the hops (expansions over all
-    layers), the batch time, and the rank of the returned point among the exact
-    neighbours (rho_0.9 = its 90th percentile, App. G.5); the n = 50,000, d = 32
-    configurations also sweep ef at k = 10 for Recall@10.  "Worst case" is the
-    maximum over the runs, as in the paper."""
+    "Number of Hops"; App. G.4 recall bounds) on the GPU path.
+
+    Hops and query time: HENN with verified eps-net layers (Eq. (1) with a
+    small c0, so that the ring check of App. B.1 rejects samples), the same
+    with Alg. 3 halving layers, and random layers (every ring vacuous: the
+    HNSW-style hierarchy), on skewed exponential data (``expskew``), NSW
+    graphs (App. B.2), the same build seeds.  Per build, Alg. 4 greedy
+    queries (k = 1, ef = 1) give the hops (expansions over all layers) and
+    each query's time on the device clock; "worst case" is the maximum over
+    the queries and the runs, as in the paper.  The n = 50,000, d = 32
+    configurations also sweep ef at k = 10 for Recall@10.
+
+    Recall bound: rho_0.9 of one navigation graph (kNN or NSW over all n
+    points), per its definition in Sec. 3: greedy search on that graph alone
+    from a start drawn uniformly per run (a two-layer index whose upper
+    layer is the start), the rank of the result among all points, the hits
+    curve pooled over --wc-rho-runs runs with fresh data, queries and start."""
     import torch
     import paper_2505_17368_amd as hn
     import workloads as wl
-    from oracle import henn_oracle as ho
     hn.load_library()
     dev = torch.device("cuda:0")
     nq, runs, lam0 = args.wc_nq, args.wc_runs, args.wc_lam
@@ -946,12 +1030,13 @@ def worstcase(args):
             ts.append(e0.elapsed_time(e1))
         return float(np.median(ts))
 
-    for n, d, lam in configs + recall_configs:
+    parts = set(args.wc_parts.split(","))
+    for n, d, lam in (configs + recall_configs if "hops" in parts else []):
         t0 = time.time()
         X = wl.expskew(n, d, lam, seed=0)
         Q = wl.expskew(nq, d, lam, seed=1)
-        gt_ids, gt_dist = ho.brute_force_knn(X, Q, 100, 0)
         Xd, Qd = torch.from_numpy(X).to(dev), torch.from_numpy(Q).to(dev)
+        gt10 = exact_knn(X, Q, 10, 0)[1] if (n, d, lam) in recall_configs else None
         entry = {"n": n, "d": d, "lam": lam}
         for variant in ("eps_net", "halving", "random"):
             per_run = []
@@ -966,26 +1051,27 @@ def worstcase(args):
                         bp["sampler"] = hn.SAMPLER["halving"]
                 idx = hn.henn_build(Xd, **bp)
                 info = [idx.layer_info(i) for i in range(1, idx.num_layers)]
-                ids, _, cnt = hn.henn_search_batch(idx, Qd, k=1, ef=1, with_counters=True)
+                ids, _, cnt, qns = hn.henn_search_batch(idx, Qd, k=1, ef=1, with_counters=True,
+                                                        with_times=True)
                 torch.cuda.synchronize()
                 hops = cnt[:, 0].cpu().numpy()
-                got = ids[:, 0].cpu().numpy()
-                rank = np.full(nq, 101)
-                hit = gt_ids == got[:, None]
-                rank[hit.any(1)] = hit.argmax(1)[hit.any(1)] + 1
+                qus = qns.cpu().numpy() / 1e3
+                rank = ranks_of(Xd, Qd, ids[:, 0].cpu().numpy())
                 r = {"mean_hops": float(hops.mean()), "max_hops": int(hops.max()),
+                     "query_us_p50": round(float(np.percentile(qus, 50)), 2),
+                     "query_us_p99": round(float(np.percentile(qus, 99)), 2),
+                     "query_us_max": round(float(qus.max()), 2),
                      "greedy_ms": timed(idx, Qd, k=1, ef=1),
-                     "rho_0.9": int(np.sort(rank)[int(np.ceil(0.9 * nq)) - 1]),
                      "exact_nn": float((rank == 1).mean()),
                      "layers": [x["size"] for x in info],
                      "attempts": [x["attempts"] for x in info],
                      "status": [x["status"] for x in info]}
-                if (n, d, lam) in recall_configs:
+                if gt10 is not None:
                     r["sweep"] = []
                     for ef in efs:
                         ids10, _ = hn.henn_search_batch(idx, Qd, k=10, ef=ef)
                         torch.cuda.synchronize()
-                        rec = ho.recall_at_k(ids10.cpu().numpy(), gt_dist[:, :10], X, Q)
+                        rec = recall_at_k(ids10.cpu().numpy(), gt10, X, Q)
                         ms = timed(idx, Qd, k=10, ef=ef)
                         r["sweep"].append({"ef": ef, "recall": round(rec, 4),
                                            "qps": round(nq / (ms / 1e3), 1)})
@@ -994,32 +1080,81 @@ def worstcase(args):
             entry[variant] = {
                 "worst_mean_hops": max(r["mean_hops"] for r in per_run),
                 "worst_max_hops": max(r["max_hops"] for r in per_run),
+                "worst_query_us": max(r["query_us_max"] for r in per_run),
+                "worst_query_us_p99": max(r["query_us_p99"] for r in per_run),
                 "worst_greedy_ms": max(r["greedy_ms"] for r in per_run),
-                "mean_rho_0.9": float(np.mean([r["rho_0.9"] for r in per_run])),
                 "runs": per_run}
         e, hv, r = entry["eps_net"], entry["halving"], entry["random"]
         log(f"n={n} d={d} lam={lam:g}: worst mean hops {e['worst_mean_hops']:.1f} (eps-net) / "
             f"{hv['worst_mean_hops']:.1f} (halving) / {r['worst_mean_hops']:.1f} (random); "
             f"worst max hops {e['worst_max_hops']} / {hv['worst_max_hops']} / "
-            f"{r['worst_max_hops']}; rho_0.9 {e['mean_rho_0.9']:.1f} / "
-            f"{hv['mean_rho_0.9']:.1f} / {r['mean_rho_0.9']:.1f}; {time.time() - t0:.1f}s")
+            f"{r['worst_max_hops']}; worst query {e['worst_query_us']:.1f} / "
+            f"{hv['worst_query_us']:.1f} / {r['worst_query_us']:.1f} us; "
+            f"{time.time() - t0:.1f}s")
         study.append(entry)
+        del Xd, Qd
+
+    # ---- recall bound rho_0.9 of one navigation graph (Sec. 3, App. G.4) ----
+    rho = []
+    rho_q = args.wc_rho_nq
+    for graph in (("knn", "nsw") if "rho" in parts else ()):
+        for lam in (1.0, 32.0):
+            for n in (10_000, 50_000, 200_000):
+                t0 = time.time()
+                ranks, per_run = [], []
+                for run in range(args.wc_rho_runs):
+                    X = wl.expskew(n, 32, lam, seed=10_000 + run)
+                    Q = wl.expskew(rho_q, 32, lam, seed=20_000 + run)
+                    Xd, Qd = torch.from_numpy(X).to(dev), torch.from_numpy(Q).to(dev)
+                    bp = dict(degree=16, max_degree=32, graph=hn.GRAPH[graph], max_layers=0,
+                              ef_construction=256, seed=run)
+                    g = hn.henn_build(Xd, **bp)
+                    _, adj = g.export_layer(0)
+                    g.free()
+                    start = int(np.random.default_rng(30_000 + run).integers(n))
+                    two = hn.henn_import(Xd, [None, np.array([start], np.int32)],
+                                         [adj, -np.ones((1, adj.shape[1]), np.int32)],
+                                         degree=16, max_degree=32, graph=hn.GRAPH[graph])
+                    ids, _ = hn.henn_search_batch(two, Qd, k=1, ef=1)
+                    torch.cuda.synchronize()
+                    two.free()
+                    rk = ranks_of(Xd, Qd, ids[:, 0].cpu().numpy())
+                    ranks.append(rk)
+                    per_run.append(recall_bound(rk, 0.9))
+                    del Xd, Qd
+                ranks = np.concatenate(ranks)
+                hc = hits_curve(ranks, 100)
+                row = {"graph": graph, "n": n, "d": 32, "lam": lam, "runs": args.wc_rho_runs,
+                       "queries_per_run": rho_q, "rho_0.9": recall_bound(ranks, 0.9),
+                       "hits": {f"k={k}": round(float(hc[k - 1]), 4) for k in (1, 5, 10, 15, 50)},
+                       "rho_0.9_per_run": {"min": int(min(per_run)),
+                                           "median": float(np.median(per_run)),
+                                           "max": int(max(per_run))}}
+                rho.append(row)
+                log(f"recall bound {graph} n={n} lam={lam:g}: rho_0.9 {row['rho_0.9']} "
+                    f"(per run {row['rho_0.9_per_run']}), hits@1 {row['hits']['k=1']}, "
+                    f"{time.time() - t0:.1f}s")
+
     ratios = [x["random"]["worst_mean_hops"] / x["eps_net"]["worst_mean_hops"]
               for x in study if (x["n"], x["d"], x["lam"]) in configs]
     ratios_h = [x["random"]["worst_mean_hops"] / x["halving"]["worst_mean_hops"]
                 for x in study if (x["n"], x["d"], x["lam"]) in configs]
+
+    def gmean(v):
+        return round(float(np.exp(np.mean(np.log(v)))), 4) if v else None
     out = {
         "metric": "worst-case Alg. 4 hops, random layers / eps-net layers (geometric mean over "
                   "the n and d sweeps)",
-        "value": round(float(np.exp(np.mean(np.log(ratios)))), 4), "unit": "ratio",
-        "halving_ratio": round(float(np.exp(np.mean(np.log(ratios_h)))), 4),
+        "value": gmean(ratios), "unit": "ratio",
+        "halving_ratio": gmean(ratios_h),
         "n_gpus": 1, "steps": runs, "warmup": 0, "ms_per_step": None,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "expskew", "nq": nq, "runs": runs, "lam": lam0,
                    "c0_times_d": args.wc_c0d, "graph": "nsw", "degree": 16, "max_degree": 32,
-                   "ef_construction": 256},
+                   "ef_construction": 256, "rho_runs": args.wc_rho_runs, "rho_queries": rho_q},
         "study": study,
+        "recall_bound": rho,
     }
     print(json.dumps(out), flush=True)
 
@@ -1035,7 +1170,6 @@ def dynamic(args):
     import torch
     import paper_2505_17368_amd as hn
     import workloads as wl
-    from oracle import henn_oracle as ho
     hn.load_library()
     dev = torch.device("cuda:0")
     X, Q = wl.make("gmm100_1M_d128")
@@ -1050,7 +1184,7 @@ def dynamic(args):
     efs = (64, 128, 192)
 
     def recall(idx, live, id_map=None):
-        _, gt = ho.brute_force_knn(X[live], Q[sample], 10, 0)
+        _, gt = exact_knn(X[live], Q[sample], 10, 0)
         out = {}
         for ef in efs:
             ids, _ = hn.henn_search_batch(idx, Qd, k=10, ef=ef)
@@ -1058,7 +1192,7 @@ def dynamic(args):
             ids = ids.cpu().numpy()[sample]
             if id_map is not None:
                 ids = np.where(ids >= 0, id_map[np.maximum(ids, 0)], -1)
-            out[ef] = round(ho.recall_at_k(ids, gt, X, Q[sample]), 4)
+            out[ef] = round(recall_at_k(ids, gt, X, Q[sample]), 4)
         return out
 
     torch.cuda.synchronize()

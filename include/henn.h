@@ -174,6 +174,14 @@ typedef struct {
                              henn_search_workspace_size() bytes the call allocates
                              nothing (needed under hipGraph capture) */
   int64_t workspace_bytes;
+  int64_t *query_ns;      /* device [nq] or NULL: each query's time inside the main
+                             search kernel, from its wave's first instruction for
+                             the query to its last (all layers, the FP32 re-rank
+                             and the output rows), on the device's constant-rate
+                             clock (10 ns steps on MI355X), in ns.  It counts the
+                             time the wave waits on memory and shares its SIMD
+                             with other waves; the complete-root scan kernels that
+                             run before the search are not included */
 } henn_search_params;
 
 typedef struct {

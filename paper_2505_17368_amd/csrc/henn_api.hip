@@ -1073,6 +1073,21 @@ static int64_t search_workspace_bytes(const henn_index* idx, int64_t nq,
   return 256 + search_root_bytes(idx, nq, sp);
 }
 
+// Rate of the current device's constant clock in kHz (read once per device).
+static int device_clock_khz() {
+  static std::atomic<int> rate[64];
+  int dev = 0;
+  HENN_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) throw HipError{hipErrorInvalidDevice, "device index"};
+  int r = rate[dev].load(std::memory_order_relaxed);
+  if (r <= 0) {
+    HENN_HIP(hipDeviceGetAttribute(&r, hipDeviceAttributeWallClockRate, dev));
+    if (r <= 0) throw HipError{hipErrorInvalidValue, "device clock rate"};
+    rate[dev].store(r, std::memory_order_relaxed);
+  }
+  return r;
+}
+
 // The search behind henn_search_batch and henn_search_batch_noalloc.
 // Scratch (the persistent work counter, then the root-scan keys) comes from
 // `fixed` when given (fixed_bytes must hold search_workspace_bytes), else from
@@ -1141,6 +1156,10 @@ static henn_status search_impl(const henn_index* idx, const float* Q, int64_t nq
     a.out_ids = out_ids;
     a.out_dist = out_dist;
     a.counters = sp->counters;
+    if (sp->query_ns) {
+      a.query_ns = sp->query_ns;
+      a.clock_ns = 1e6 / device_clock_khz();
+    }
     if (!rows_addressable(a))
       return fail(HENN_E_UNSUPPORTED, "search needs n * ceil(d / 8) < 2^32");
 
@@ -1308,6 +1327,7 @@ henn_status henn_autotune(henn_index* idx, const float* Q, int64_t nq,
     }
     henn_search_params c = *sp;
     c.counters = nullptr;
+    c.query_ns = nullptr;
     c.ev_begin = c.ev_end = nullptr;
     // one workspace for every trial, so that no trial times an allocation
     // (its size depends on the flags and nq, not on the launch shape)

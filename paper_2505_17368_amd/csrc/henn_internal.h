@@ -189,6 +189,10 @@ struct SearchArgs {
   // bit per member of the largest layer, replacing the LDS table
   uint32_t* vis_exact = nullptr;
   int64_t vis_exact_words = 0;
+  // per-query time in ns (henn_search_params::query_ns) and the period of
+  // the device's constant clock in ns
+  int64_t* query_ns = nullptr;
+  double clock_ns = 0;
 };
 
 // Traversal state of one query between expansions (wave-uniform).  The
@@ -218,7 +222,8 @@ struct ServeArgs {
   int32_t* done_count;        // completions of this tick
   int32_t* done_clear;        // the next tick's counter, cleared by this kernel
   // completion i of the tick: row i of [max_slots][1 + 2 k_max] words =
-  // its slot, k_max ids, k_max distances (FP32 bits), copied back in one piece
+  // its slot, k_max ids, k_max distances (FP32 bits), written straight into
+  // the host's pinned completion buffer
   int32_t* done_rows;
 };
 

@@ -883,8 +883,25 @@ __device__ void finish_query(const SearchArgs& a, const float (&q)[CPL][8], uint
   wave_sync();
 }
 
+// The per-query time output, read from the kernel's argument segment at the
+// point of use (SearchArgs is the first argument of every kernel that calls
+// search_one, so it starts the segment).  A volatile read: the traversal keeps
+// its scalar registers full, and a pointer held across it would spill.
+__device__ __forceinline__ int64_t* query_ns_arg() {
+  const SearchArgs* ka = reinterpret_cast<const SearchArgs*>(
+      (const char*)__builtin_amdgcn_kernarg_segment_ptr());
+  return *reinterpret_cast<int64_t* const volatile*>(&ka->query_ns);
+}
+
 template <int KIND, int LPN, int CPL, bool FULL, bool EXACT>
 __device__ void search_one(const SearchArgs& a, int64_t qi, WaveLds s) {
+  // the constant-rate clock when times are asked for; the start waits in the
+  // query's output word (volatile: a memory round trip, so no register stays
+  // live across the traversal)
+  if (lane_id() == 0) {
+    int64_t* qt = query_ns_arg();
+    if (qt) *reinterpret_cast<volatile int64_t*>(qt + qi) = (int64_t)wall_clock64();
+  }
   const int t = lane_id() % LPN;
   float q[CPL][8];
   load_query<CPL>(a.Q + qi * a.d, a.d, t, q);
@@ -900,6 +917,12 @@ __device__ void search_one(const SearchArgs& a, int64_t qi, WaveLds s) {
   finish_query<KIND, LPN, CPL>(a, q, W, st, a.out_ids + qi * a.k_max,
                                a.out_dist + qi * a.k_max,
                                a.counters ? a.counters + qi * 4 : nullptr);
+  int64_t* qt = lane_id() == 0 ? query_ns_arg() : nullptr;
+  if (qt) {
+    volatile int64_t* slot = reinterpret_cast<volatile int64_t*>(qt + qi);
+    const uint32_t ticks = (uint32_t)((uint64_t)wall_clock64() - (uint64_t)*slot);
+    *slot = (int64_t)((double)ticks * a.clock_ns);
+  }
 }
 
 // ---------------------------------------------------------- serving ------

@@ -54,7 +54,7 @@ class SearchParams(ctypes.Structure):
                 ("waves_per_block", ctypes.c_int32), ("ev_begin", ctypes.c_void_p),
                 ("ev_end", ctypes.c_void_p), ("vis_bits", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("workspace", ctypes.c_void_p),
-                ("workspace_bytes", ctypes.c_int64)]
+                ("workspace_bytes", ctypes.c_int64), ("query_ns", ctypes.c_void_p)]
 
 
 class LayerInfo(ctypes.Structure):
@@ -338,7 +338,7 @@ def search_params(k=10, ef=32, k_arr=None, ef_arr=None, k_max=None, ef_max=None,
                   rerank_factor=4, counters=None, persistent=False, lanes_per_vec=0,
                   waves_per_block=0, root_kernel=True, events=None,
                   vis_bits=0, vis32=False, vis16=False, workspace=None,
-                  exact_visited=False) -> SearchParams:
+                  exact_visited=False, query_ns=None) -> SearchParams:
     sp = SearchParams()
     _check(load_library().henn_default_search_params(ctypes.byref(sp)))
     sp.k_all = k
@@ -350,6 +350,7 @@ def search_params(k=10, ef=32, k_arr=None, ef_arr=None, k_max=None, ef_max=None,
     sp.ef_upper = ef_upper
     sp.rerank_factor = rerank_factor
     sp.counters = counters.data_ptr() if counters is not None else None
+    sp.query_ns = query_ns.data_ptr() if query_ns is not None else None
     # root_kernel: True (matrix-core scan where available), "valu" (tiled
     # VALU scan) or False (scan inside the search kernel); same results
     if root_kernel not in (True, False, "valu"):
@@ -387,8 +388,9 @@ def henn_search_batch(index: HennIndex, Q, k=10, ef=32, k_arr=None, ef_arr=None,
                       persistent=False, lanes_per_vec=0, waves_per_block=0, root_kernel=True,
                       events=None, vis_bits=0, out_ids=None, out_dist=None, stream=None,
                       vis32=False, vis16=False, noalloc=False, workspace=None,
-                      exact_visited=False):
-    """Enqueues a batched search; returns (ids, dist[, counters]) device tensors.
+                      exact_visited=False, with_times=False):
+    """Enqueues a batched search; returns (ids, dist[, counters][, query_ns])
+    device tensors (query_ns: int64 per-query time in the search kernel).
     ``noalloc``: call henn_search_batch_noalloc (the library's fixed scratch;
     pass out_ids / out_dist to keep the call free of allocations here too).
 
@@ -405,17 +407,18 @@ def henn_search_batch(index: HennIndex, Q, k=10, ef=32, k_arr=None, ef_arr=None,
     if out_dist is None:
         out_dist = torch.empty((nq, kmax), dtype=torch.float32, device=Q.device)
     counters = torch.zeros((nq, 4), dtype=torch.int32, device=Q.device) if with_counters else None
+    times = torch.zeros(nq, dtype=torch.int64, device=Q.device) if with_times else None
     sp = search_params(k, ef, k_arr, ef_arr, kmax, ef_max, ef_upper, rerank_factor, counters,
                        persistent, lanes_per_vec, waves_per_block, root_kernel, events,
-                       vis_bits, vis32, vis16, workspace, exact_visited)
+                       vis_bits, vis32, vis16, workspace, exact_visited, times)
     entry = load_library().henn_search_batch_noalloc if noalloc else \
         load_library().henn_search_batch
     _check(entry(index.handle, ctypes.c_void_p(Q.data_ptr()), nq, ctypes.byref(sp),
                  ctypes.c_void_p(out_ids.data_ptr()), ctypes.c_void_p(out_dist.data_ptr()),
                  _stream_ptr(stream)))
-    if with_counters:
-        return out_ids, out_dist, counters
-    return out_ids, out_dist
+    out = (out_ids, out_dist) + ((counters,) if with_counters else ()) + (
+        (times,) if with_times else ())
+    return out
 
 
 def henn_autotune(index: HennIndex, Q, k=10, ef=32, k_max=None, ef_max=None, ef_upper=1,

@@ -25,7 +25,7 @@ def test_struct_sizes_match_header(lib):
     assert p.struct_size == ctypes.sizeof(hn.BuildParams) == 88
     sp = hn.SearchParams()
     assert lib.henn_default_search_params(ctypes.byref(sp)) == hn.HENN_OK
-    assert sp.struct_size == ctypes.sizeof(hn.SearchParams) == 104
+    assert sp.struct_size == ctypes.sizeof(hn.SearchParams) == 112
     assert ctypes.sizeof(hn.LayerInfo) == 56
 
 
