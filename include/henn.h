@@ -125,6 +125,12 @@ typedef struct {
                              in expectation.  With max_attempts = 0 the attempt cap is
                              the smallest t with phi^t <= 1e-9 (phi in (0, 1));
                              otherwise only reported */
+  int32_t gram;           /* kNN graph kinds, d <= 128: 0 = Gram tiles on BF16 matrix
+                             cores with split operands (hi + lo, three exact products
+                             per coordinate), 1 = FP32 matrix-core tiles.  Both feed the
+                             exact FP32 re-rank and its proven fallback, so the graph is
+                             the same exact kNN graph; 0 does 3/16 of the matrix work.
+                             Rows wider than 128 always take FP32 tiles */
 } henn_build_params;
 
 /* Search flags (bits 4..32 are taken by the test-only flags of
@@ -202,7 +208,7 @@ typedef struct {
 /* Fills *p with the defaults: L2, max_layers -1, m 4, c0 1, no override,
  * 64 rings, 64 attempts, degree 16, max_degree 32, kNN graph, F32, seed 0,
  * root_complete_max 0, DRAWS sampler, ef_construction 256, insert_shift 3,
- * phi 0.5. */
+ * phi 0.5, gram 0 (split BF16). */
 henn_status henn_default_build_params(henn_build_params *p);
 
 /* Defaults: no per-query arrays, k_all 10, ef_all 32, k_max 10, ef_max 32,

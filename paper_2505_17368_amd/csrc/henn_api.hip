@@ -112,6 +112,10 @@ static bool valid_build_params(const henn_build_params* p, std::string* why) {
   if (!(p->c0 > 0.0)) { *why = "c0 must be positive"; return false; }
   if (p->num_rings < 1 || p->num_rings > 4096) { *why = "num_rings in [1, 4096]"; return false; }
   if (p->max_attempts < 0) { *why = "max_attempts >= 0"; return false; }
+  if (p->gram != 0 && p->gram != 1) {
+    *why = "gram must be 0 (split BF16) or 1 (FP32)";
+    return false;
+  }
   if (p->max_attempts == 0 && !(p->phi > 0.0 && p->phi < 1.0)) {
     *why = "max_attempts = 0 needs phi in (0, 1)";
     return false;
@@ -399,7 +403,7 @@ static void finish_layer(henn_index* ix, int i, hipStream_t st) {
     try {
       L.info.fallback_rows =
           (int32_t)build_knn_graph(L.vec32, L.size, ix->dpad, ix->nchunks, ix->metric, C, lpn, cpl,
-                                   cand, st);
+                                   cand, p.gram, st);
       if (pruned) {
         prune_graph(L.vec32, L.size, ix->dpad, ix->nchunks, ix->metric, cand, C, R, adj, lpn, cpl,
                     st);

@@ -343,8 +343,10 @@ void launch_adj_scale(const int32_t* adj, int64_t n, const float* scale, float* 
 // kNN graph of one layer: FP32 MFMA Gram shortlist + exact re-rank + exact
 // fallback for rows whose shortlist cannot be proven to hold the top R.
 // Returns the number of fallback rows.
+// gram: 0 = split-BF16 matrix-core tiles (d <= 128), 1 = FP32 tiles; the
+// graph is the same exact kNN graph either way
 int64_t build_knn_graph(const float* vec, int64_t size, int dpad, int nchunks, int metric, int R,
-                        int lpn, int cpl, int32_t* adj, hipStream_t st);
+                        int lpn, int cpl, int32_t* adj, int gram, hipStream_t st);
 
 // Reverse-edge augmentation (HENN_GRAPH_KNN_SYM): rows become the first
 // max_deg of the deduplicated union of out- and in-neighbours in

@@ -15,8 +15,10 @@
 //  2. k_knn_rerank: one wave per row recomputes the shortlist's distances
 //     in the canonical difference form, sorts the (distance, id) keys and
 //     keeps R.  A row is re-solved exactly when the shortlist cannot be
-//     proven to contain the true top R: when the R-th exact distance plus
-//     the Gram error bound is not below the shortlist cut minus that bound.
+//     proven to contain the true top R: when neither the bound with the
+//     layer's largest norm nor (L2) the bound relative to each candidate's
+//     own distance puts every left-out candidate beyond the R-th exact
+//     distance.
 //  3. k_knn_exact: the exact brute force for those rows.
 #include <math.h>
 #include <stdio.h>
@@ -216,6 +218,220 @@ __global__ __launch_bounds__(256, 2) void k_gram_topk(const float* vec, int64_t 
     __syncthreads();
     cur ^= 1;
   }
+  if (qvalid) {
+    const int64_t o = qrow * (2 * KS) + h * KS;
+#pragma unroll
+    for (int j = 0; j < KS; ++j) {
+      sl_d[o + j] = td[j];
+      sl_i[o + j] = ti[j];
+    }
+  }
+}
+
+// ------------------------------------------------------------------------
+// The same shortlist on BF16 matrix cores with split operands (the default
+// build for d <= 128).  Each centred row x' = fl(x - mean) is stored once as
+// hi = bf16(x') and lo = bf16(x' - hi) (k_split_rows), and every product is
+// taken as y_h b_h + y_h b_l + y_l b_h, three v_mfma_f32_32x32x16_bf16 per
+// 16 coordinates, each product exact in FP32.  Error of one Gram value G
+// against the canonical FP32 distance D that the re-rank computes, with
+// u = 2^-8 the BF16 unit roundoff and b = -2 x' (L2; -x' for IP, which only
+// halves the bound):
+//  - the dropped terms y_l b_l + (y' - y_h - y_l) b + y' (b - b_h - b_l)
+//    are at most (u^2 (1 + u)^2 + 2 u^2) |y'_k| |b_k| per coordinate, so
+//    at most 3.25 2^-16 (|x'|^2 + |y'|^2) summed (|b| = 2 |x'|);
+//  - the FP32 accumulation of 3 kp exact products onto the two norms, in
+//    any order: at most (3 kp + 2) 2^-24 times their absolute sum, itself
+//    at most 2 (|x'|^2 + |y'|^2) up to O(u);
+//  - the norms, the centring and the canonical distance's own rounding:
+//    at most (4 dpad + 20) 2^-24 (|x'|^2 + |y'|^2).
+// So |G - D| <= (3.25 2^-16 + (6 kp + 4 dpad + 24) 2^-24) (|x'|^2 + |y'|^2),
+// and the re-rank proves each row's shortlist with that coefficient times
+// |x'|^2 + max_y |y'|^2 (x3_split_coef).  The products cost 3 / 16 of the
+// FP32 ones on the matrix cores; the shortlist, its output and the re-rank
+// are those of k_gram_topk.
+
+// rows [size][2 kp] BF16 (hi then lo) of the centred rows; zero past dpad
+__global__ void k_split_rows(const float* vec, const float* mean, int64_t size, int dpad,
+                             int kp, uint16_t* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= size * kp) return;
+  const int64_t r = i / kp;
+  const int c = (int)(i - r * kp);
+  const float v = c < dpad ? vec[r * dpad + c] - (mean ? mean[c] : 0.0f) : 0.0f;
+  const uint32_t hi = f32_to_bf16_rne(v);
+  const uint32_t lo = f32_to_bf16_rne(v - bf16_to_f32(hi));
+  out[r * 2 * kp + c] = (uint16_t)hi;
+  out[r * 2 * kp + kp + c] = (uint16_t)lo;
+}
+
+static float x3_split_coef(int dpad) {
+  const int kp = (dpad + 15) / 16 * 16;
+  return 3.25f * 0x1p-16f + (float)(6 * kp + 4 * dpad + 24) * 0x1p-24f;
+}
+
+typedef __bf16 bf16x8v __attribute__((ext_vector_type(8)));
+
+// bf16x8 times a power of two (exact: the significands do not change)
+__device__ inline bf16x8v scale_bf16x8(uint4 w, float f) {
+  uint32_t u[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const uint32_t a = f32_to_bf16_rne(bf16_to_f32(u[i] & 0xffffu) * f);
+    const uint32_t b = f32_to_bf16_rne(bf16_to_f32(u[i] >> 16) * f);
+    u[i] = a | (b << 16);
+  }
+  return __builtin_bit_cast(bf16x8v, make_uint4(u[0], u[1], u[2], u[3]));
+}
+
+// A block takes 128 rows (32 per wave) and streams the layer through LDS in
+// tiles of kTileC split rows, double buffered: the next tile's loads are
+// issued (clamped to valid rows, no branches) before the current tile is
+// multiplied and written to LDS after it.  A staged row is its hi and lo
+// halves plus one pad slot of 16 bytes, so that the 32 rows one
+// instruction reads fall on different banks.  The accumulator starts at
+// |y'|^2 + |x'|^2 (L2) or 0 (IP), +inf for rows past the end.
+template <int S, int KS>
+__global__ __launch_bounds__(256, 2) void k_gram_topk_x3(const uint16_t* rows, int64_t size,
+                                                         const float* norms, int metric,
+                                                         float* sl_d, int32_t* sl_i,
+                                                         int64_t block0) {
+  constexpr int KP = 16 * S;
+  constexpr int kHalfU4 = KP / 8;           // uint4 per half row
+  constexpr int kRowU4 = 2 * kHalfU4 + 1;   // staged row: hi, lo, pad
+  constexpr int kBufU4 = kTileC * kRowU4;
+  constexpr int kTileU4 = kTileC * 2 * kHalfU4;
+  constexpr int kMaxU4 = (kTileU4 + 255) / 256;
+  extern __shared__ __align__(16) uint4 lds_x3[];
+  float* tnorm = reinterpret_cast<float*>(lds_x3 + 2 * kBufU4);  // [2][kTileC]
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int qc = lane & 31, h = lane >> 5;
+  const int64_t qrow = (block0 + blockIdx.x) * 128 + wave * 32 + qc;
+  const bool qvalid = qrow < size;
+  const bool l2 = metric == 0;
+
+  // the row operand: coordinates 16 s + 8 h .. + 8 of row qc, hi and lo,
+  // times -2 (L2) or -1 (IP)
+  bf16x8v bh[S], bl[S];
+  {
+    const uint4* qr = reinterpret_cast<const uint4*>(rows + (qvalid ? qrow : 0) * 2 * KP);
+    const float f = qvalid ? (l2 ? -2.0f : -1.0f) : 0.0f;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      bh[s] = scale_bf16x8(qr[2 * s + h], f);
+      bl[s] = scale_bf16x8(qr[kHalfU4 + 2 * s + h], f);
+    }
+  }
+  const float qn = (l2 && qvalid) ? norms[qrow] : 0.0f;
+
+  float td[KS];
+  int32_t ti[KS];
+#pragma unroll
+  for (int j = 0; j < KS; ++j) {
+    td[j] = INFINITY;
+    ti[j] = -1;
+  }
+
+  static_assert(kMaxU4 <= 4, "at most four uint4 per thread and tile");
+  // this thread's uint4 u of a tile (u < kMaxU4): row sr_u, slot sc_u; the
+  // loads wait in pre_u (named registers: a small array here is kept in
+  // scratch memory by the compiler)
+  int sr0 = 0, sr1 = 0, sr2 = 0, sr3 = 0, sc0 = 0, sc1 = 0, sc2 = 0, sc3 = 0;
+  uint4 pre0 = {}, pre1 = {}, pre2 = {}, pre3 = {};
+#define HENN_X3_SRC(U)                                                                 \
+  if constexpr (U < kMaxU4) {                                                          \
+    const int idx_ = min((int)threadIdx.x + U * 256, kTileU4 - 1);                     \
+    sr##U = idx_ / (2 * kHalfU4);                                                      \
+    sc##U = idx_ - sr##U * (2 * kHalfU4);                                              \
+  }
+  HENN_X3_SRC(0) HENN_X3_SRC(1) HENN_X3_SRC(2) HENN_X3_SRC(3)
+#undef HENN_X3_SRC
+  float pnorm = 0.0f;
+  int plast = 0;
+#define HENN_X3_LOAD(U)                                                                \
+  if constexpr (U < kMaxU4) pre##U = base_[(sr##U < last_ ? sr##U : last_) * 2 * kHalfU4 + sc##U];
+#define HENN_X3_PUT(U)                                                                 \
+  if constexpr (U < kMaxU4)                                                            \
+    if (kTileU4 % 256 == 0 || (int)threadIdx.x + U * 256 < kTileU4)                    \
+      buf_[sr##U * kRowU4 + sc##U] = pre##U;
+#define HENN_X3_FETCH(C0)                                                              \
+  {                                                                                    \
+    const int64_t rem_ = size - 1 - (C0);                                              \
+    const int last_ = rem_ < kTileC - 1 ? (int)rem_ : kTileC - 1;                      \
+    const uint4* base_ = reinterpret_cast<const uint4*>(rows + (C0) * 2 * KP);         \
+    HENN_X3_LOAD(0) HENN_X3_LOAD(1) HENN_X3_LOAD(2) HENN_X3_LOAD(3)                    \
+    const int rr_ = (int)(threadIdx.x & (kTileC - 1));                                 \
+    pnorm = norms[(C0) + (rr_ < last_ ? rr_ : last_)];                                 \
+    plast = last_;                                                                     \
+  }
+#define HENN_X3_STASH(B)                                                               \
+  {                                                                                    \
+    uint4* buf_ = lds_x3 + (B) * kBufU4;                                               \
+    HENN_X3_PUT(0) HENN_X3_PUT(1) HENN_X3_PUT(2) HENN_X3_PUT(3)                        \
+    if (threadIdx.x < kTileC)                                                          \
+      tnorm[(B) * kTileC + threadIdx.x] =                                              \
+          (int)threadIdx.x <= plast ? (l2 ? pnorm : 0.0f) : INFINITY;                  \
+  }
+
+  HENN_X3_FETCH(0)
+  HENN_X3_STASH(0)
+  __syncthreads();
+  int cur = 0;
+  for (int64_t c0 = 0; c0 < size; c0 += kTileC) {
+    const bool more = c0 + kTileC < size;
+    if (more) HENN_X3_FETCH(c0 + kTileC)
+    const uint4* buf = lds_x3 + cur * kBufU4;
+    const float4* tn = reinterpret_cast<const float4*>(tnorm + cur * kTileC);
+    floatx16 acc;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const float4 nr = tn[2 * g + h];  // candidates 8 g + 4 h .. + 3
+      acc[4 * g + 0] = nr.x + qn;
+      acc[4 * g + 1] = nr.y + qn;
+      acc[4 * g + 2] = nr.z + qn;
+      acc[4 * g + 3] = nr.w + qn;
+    }
+    const uint4* arow = buf + qc * kRowU4;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const bf16x8v ah = __builtin_bit_cast(bf16x8v, arow[2 * s + h]);
+      const bf16x8v al = __builtin_bit_cast(bf16x8v, arow[kHalfU4 + 2 * s + h]);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[s], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[s], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[s], acc, 0, 0, 0);
+    }
+
+    bool any = false;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) any |= acc[v] < td[KS - 1];
+    if (__builtin_amdgcn_ballot_w64(any)) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int64_t crow = c0 + 8 * (v >> 2) + 4 * h + (v & 3);
+        float nd = crow == qrow ? INFINITY : acc[v];
+        if (__builtin_amdgcn_ballot_w64(nd < td[KS - 1])) {
+          int32_t ni = (int32_t)crow;
+#pragma unroll
+          for (int j = 0; j < KS; ++j) {
+            const bool sw = nd < td[j];
+            const float od = td[j];
+            const int32_t oi = ti[j];
+            td[j] = sw ? nd : od;
+            ti[j] = sw ? ni : oi;
+            nd = sw ? od : nd;
+            ni = sw ? oi : ni;
+          }
+        }
+      }
+    }
+    if (more) HENN_X3_STASH(cur ^ 1)
+    __syncthreads();
+    cur ^= 1;
+  }
+#undef HENN_X3_FETCH
+#undef HENN_X3_STASH
+#undef HENN_X3_LOAD
+#undef HENN_X3_PUT
   if (qvalid) {
     const int64_t o = qrow * (2 * KS) + h * KS;
 #pragma unroll
@@ -429,7 +645,7 @@ template <int LPN, int CPL>
 __global__ __launch_bounds__(256) void k_knn_rerank(const float* vec, int64_t size, int dpad,
                                                     int nchunks, int metric, const float* sl_d,
                                                     const int32_t* sl_i, const float* norms,
-                                                    float nmax, int R, int32_t* adj,
+                                                    float nmax, float coef, int R, int32_t* adj,
                                                     int32_t* fb_rows, uint32_t* fb_count) {
   constexpr int G = 64 / LPN;
   __shared__ uint64_t keys[4][64];
@@ -453,9 +669,21 @@ __global__ __launch_bounds__(256) void k_knn_rerank(const float* vec, int64_t si
   const float cut = fminf(sl_d[row * (2 * kShort) + kShort - 1], sl_d[row * (2 * kShort) + 2 * kShort - 1]);
   const uint64_t kr = shfl_u64(key, R - 1);
   if (lane == 0 && isfinite(cut)) {
+    // every candidate left out of the shortlist has a Gram value >= cut, and
+    // |G - D| <= coef (|x'|^2 + |y'|^2) for its canonical distance D
     const float exact_r = kr == ~0ull ? INFINITY : from_ordered((uint32_t)(kr >> 32));
-    const float delta = 4.0f * (float)(dpad + 8) * 0x1p-24f * (norms[row] + nmax);
-    if (!(exact_r + delta < cut - delta)) fb_rows[atomicAdd(fb_count, 1u)] = (int32_t)row;
+    const float nrow = norms[row];
+    // (a) with |y'|^2 <= max_y |y'|^2: D >= cut - delta
+    const float delta = coef * (nrow + nmax);
+    const bool proof_a = exact_r + delta < cut - delta;
+    // (b) L2 only, relative to the candidate's own distance: |y'|^2 <=
+    // 2 |x'|^2 + 2 |y - x|^2, so |G - D| <= coef (3 |x'|^2 + 2.1 D) and
+    // D >= (cut - 3 coef |x'|^2) / (1 + 2.1 coef); the factors 3 and 4 below
+    // leave room for the rounding of this test.  Rows of small norm in
+    // multi-scale data pass here where (a) charges them the layer's largest.
+    const bool proof_b =
+        metric == 0 && exact_r * (1.0f + 3.0f * coef) + 4.0f * coef * nrow < cut;
+    if (!(proof_a || proof_b)) fb_rows[atomicAdd(fb_count, 1u)] = (int32_t)row;
   }
 }
 
@@ -874,7 +1102,7 @@ void launch_root_gram(const float* Q, int64_t nq, int d, const RootAux& r, int d
 }
 
 int64_t build_knn_graph(const float* vec, int64_t size, int dpad, int nchunks, int metric, int R,
-                        int lpn, int cpl, int32_t* adj, hipStream_t st) {
+                        int lpn, int cpl, int32_t* adj, int gram, hipStream_t st) {
   if (size <= 0) return 0;
   if (dpad > 1024) throw HipError{hipErrorInvalidValue, "kNN build supports d <= 1024"};
   DevBuf<float> norms_buf(size), sl_d_buf(size * 2 * kShort), mean_buf(metric == 0 ? dpad : 1);
@@ -891,8 +1119,21 @@ int64_t build_knn_graph(const float* vec, int64_t size, int dpad, int nchunks, i
 
   const int kh = dpad <= 32 ? 16 : dpad <= 64 ? 32 : 64;
   const bool wide = dpad > 128;
-  const size_t lds = wide ? sizeof(float) * (4 * kWideC * kSStride + dpad)
-                          : sizeof(float) * (2 * (kTileC * (2 * kh + 4) + kTileC) + dpad);
+  // the split-BF16 form for d <= 128 unless FP32 tiles are asked for
+  const bool split = !wide && gram == 0;
+  const int kp = (dpad + 15) / 16 * 16;
+  // the FP32 tiles' bound: 4 (dpad + 8) 2^-24 (|x'|^2 + max |y'|^2)
+  const float coef = split ? x3_split_coef(dpad) : 4.0f * (float)(dpad + 8) * 0x1p-24f;
+  DevBuf<uint16_t> split_buf(split ? size * 2 * kp : 1);
+  if (split) {
+    const int64_t n = size * kp;
+    hipLaunchKernelGGL(k_split_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, vec,
+                       mean, size, dpad, kp, split_buf.get());
+    HENN_HIP(hipGetLastError());
+  }
+  const size_t lds = wide    ? sizeof(float) * (4 * kWideC * kSStride + dpad)
+                     : split ? sizeof(uint4) * 2 * kTileC * (kp / 4 + 1) + sizeof(float) * 2 * kTileC
+                             : sizeof(float) * (2 * (kTileC * (2 * kh + 4) + kTileC) + dpad);
   const int64_t nb = (size + 127) / 128;
   // Launch in slices of row blocks so that very large layers report progress
   // (HENN_PROGRESS=1) between slices; each slice is a full-width Gram sweep.
@@ -904,7 +1145,19 @@ int64_t build_knn_graph(const float* vec, int64_t size, int dpad, int nchunks, i
     if (wide)
       hipLaunchKernelGGL(k_knn_gram_wide, dim3(nbs), dim3(256), lds, st, vec, size, dpad, mean,
                          norms, metric, sl_d, sl_i, b0);
-    else if (kh <= 16)
+    else if (split) {
+      switch (kp / 16) {
+#define HENN_X3(S_)                                                                           \
+  case S_:                                                                                    \
+    hipLaunchKernelGGL((k_gram_topk_x3<S_, kShort>), dim3(nbs), dim3(256), lds, st,           \
+                       split_buf.get(), size, norms, metric, sl_d, sl_i, b0);                 \
+    break;
+        HENN_X3(1) HENN_X3(2) HENN_X3(3) HENN_X3(4) HENN_X3(5) HENN_X3(6) HENN_X3(7) HENN_X3(8)
+#undef HENN_X3
+        default:
+          throw HipError{hipErrorInvalidValue, "split Gram: d <= 128"};
+      }
+    } else if (kh <= 16)
       hipLaunchKernelGGL((k_gram_topk<16, kShort>), dim3(nbs), dim3(256), lds, st, vec, size,
                          dpad, norms, mean, metric, sl_d, sl_i, b0);
     else if (kh <= 32)
@@ -930,7 +1183,8 @@ int64_t build_knn_graph(const float* vec, int64_t size, int dpad, int nchunks, i
 #define HENN_TRY(L, C)                                                                         \
   if (!launched && lpn == L && cpl == C) {                                                     \
     hipLaunchKernelGGL((k_knn_rerank<L, C>), dim3(nr), dim3(256), 0, st, vec, size, dpad,      \
-                       nchunks, metric, sl_d, sl_i, norms, nmax, R, adj, fb_rows, fb_count);   \
+                       nchunks, metric, sl_d, sl_i, norms, nmax, coef, R, adj, fb_rows,        \
+                       fb_count);                                                              \
     launched = true;                                                                           \
   }
   HENN_KNN_COMBOS(HENN_TRY)

@@ -42,7 +42,7 @@ class BuildParams(ctypes.Structure):
                 ("storage", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("root_complete_max", ctypes.c_int32), ("sampler", ctypes.c_int32),
                 ("ef_construction", ctypes.c_int32), ("insert_shift", ctypes.c_int32),
-                ("phi", ctypes.c_double)]
+                ("phi", ctypes.c_double), ("gram", ctypes.c_int32)]
 
 
 class SearchParams(ctypes.Structure):

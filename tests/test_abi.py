@@ -22,7 +22,7 @@ def test_exports_every_declared_symbol(lib):
 
 def test_struct_sizes_match_header(lib):
     p = hn.default_build_params()
-    assert p.struct_size == ctypes.sizeof(hn.BuildParams) == 88
+    assert p.struct_size == ctypes.sizeof(hn.BuildParams) == 96
     sp = hn.SearchParams()
     assert lib.henn_default_search_params(ctypes.byref(sp)) == hn.HENN_OK
     assert sp.struct_size == ctypes.sizeof(hn.SearchParams) == 112
@@ -33,8 +33,8 @@ def test_defaults(lib):
     p = hn.default_build_params()
     assert (p.metric, p.max_layers, p.m, p.c0, p.num_rings, p.max_attempts, p.degree,
             p.max_degree, p.graph, p.storage, p.seed, p.root_complete_max, p.sampler,
-            p.ef_construction, p.insert_shift, p.phi) == (
-                0, -1, 4, 1.0, 64, 64, 16, 32, 0, 0, 0, 0, 0, 256, 3, 0.5)
+            p.ef_construction, p.insert_shift, p.phi, p.gram) == (
+                0, -1, 4, 1.0, 64, 64, 16, 32, 0, 0, 0, 0, 0, 256, 3, 0.5, 0)
     sp = hn.SearchParams()
     lib.henn_default_search_params(ctypes.byref(sp))
     assert (sp.k_all, sp.ef_all, sp.k_max, sp.ef_upper, sp.rerank_factor) == (10, 32, 10, 1, 4)
@@ -69,6 +69,12 @@ def test_invalid_arguments_rejected_on_host(lib):
         assert lib.henn_build(fake, 10, 4, ctypes.byref(bad), None,
                               ctypes.byref(h)) == hn.HENN_E_INVAL, kw
         assert "max_attempts" in hn.last_error()
+    # Gram tiles: 0 split BF16, 1 FP32
+    for g in (-1, 2):
+        bad = hn.default_build_params(gram=g)
+        assert lib.henn_build(fake, 10, 4, ctypes.byref(bad), None,
+                              ctypes.byref(h)) == hn.HENN_E_INVAL
+        assert "gram" in hn.last_error()
     for kw in (dict(ef_construction=0), dict(ef_construction=2049), dict(insert_shift=-1),
                dict(insert_shift=63)):
         bad = hn.default_build_params(graph="nsw", **kw)

@@ -421,6 +421,45 @@ def test_build_graph_matches_oracle_rows_larger(hn, ho, n, d, metric):
     idx.free()
 
 
+@pytest.mark.parametrize("kind,n,d,metric", [
+    ("gauss", 20000, 128, 0), ("gauss", 6000, 96, 0), ("gauss", 5000, 64, 1),
+    ("gauss", 3000, 36, 0), ("gauss", 2500, 8, 0), ("spectral", 4000, 120, 1),
+    ("curve", 8000, 96, 0), ("expskew", 6000, 32, 0)])
+def test_split_bf16_and_fp32_gram_give_the_same_graph(hn, ho, kind, n, d, metric):
+    """The kNN graph from split-BF16 Gram tiles (the default) and from FP32
+    tiles: both shortlists are proven (or re-solved exactly) against the
+    canonical distance, so the graphs are identical, row for row, including
+    inputs with many near ties (the curve) where rows fall back."""
+    if kind == "gauss":
+        X = wl.gauss_mix(n, d, 20, 0.3, 40)
+        if metric == 1:
+            X /= np.linalg.norm(X, axis=1, keepdims=True)
+    elif kind == "spectral":
+        X = wl.spectral(n, d, 41)
+    elif kind == "curve":
+        X = wl.curve(n, d, 42)
+    else:
+        X = wl.expskew(n, d, 32.0, seed=43)
+    Xd = to_dev(X)
+    out = []
+    for gram in (0, 1):
+        idx = hn.henn_build(Xd, degree=16, metric=metric, max_layers=0, gram=gram)
+        out.append((idx.export_layer(0)[1], idx.layer_info(0)["fallback_rows"]))
+        idx.free()
+    print(f"{kind} {n} x {d}: fallback rows split {out[0][1]}, fp32 {out[1][1]}")
+    assert np.array_equal(out[0][0], out[1][0])
+    # and both are the exact kNN rows (sampled rows against the oracle)
+    adj = out[0][0]
+    rows = np.sort(np.random.default_rng(1).choice(n, 100, replace=False))
+    oadj, cut, order = ho.knn_rows(X, metric, np.arange(n, dtype=np.int32), rows, 16)
+    for j, r in enumerate(rows):
+        if np.array_equal(adj[r], oadj[j]):
+            continue
+        assert order[j] <= exempt_tol(d), f"row {r}: {adj[r]} vs {oadj[j]}"
+        if cut[j] > exempt_tol(d):
+            assert set(adj[r].tolist()) == set(oadj[j].tolist())
+
+
 @pytest.mark.parametrize("d,metric", [(200, 0), (768, 1)])
 def test_wide_rows_end_to_end(hn, ho, d, metric):
     """Rows wider than 128 coordinates (K-sliced Gram build, 16-lane gathers):
