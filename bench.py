@@ -834,7 +834,10 @@ def batched(args):
         "value": round(nq * args.steps / wall, 1), "unit": "queries/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(wall * 1e3 / args.steps, 3), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": {"f32": "f32", "bf16": "bf16 storage, f32 accumulate",
+                  "fp8": "fp8_e4m3 storage, f16 difference, f32 accumulate"}[args.storage],
+        "data": "synthetic",
         "config": {"workload": wname, "n": n, "d": d, "nq": nq, "storage": args.storage,
                    "k": [1, 10, 100], "ef": [32, 64, 128], "graph": args.graph,
                    "sampler": args.sampler,
