@@ -341,13 +341,15 @@ henn_status henn_server_submit(henn_server *s, const float *q_host, int32_t k, i
 /* n requests at once: q_host FP32 [n][d], k[n], ef[n], tags[n] (host). */
 henn_status henn_server_submit_batch(henn_server *s, const float *q_host, const int32_t *k,
                                      const int32_t *ef, const int64_t *tags, int64_t n);
-/* Admits what fits, retires the requests the previous tick's step finished
- * to the completion queue, and launches one step of every active request.
- * The tick stages its admissions while the previous step still runs and
- * returns without waiting for its own step, so the caller's work between
- * ticks overlaps the device: a request's result reaches the completion queue
- * in the tick after the one whose step finished it (call tick until every
- * result has been polled).
+/* Retires the requests the previous tick's step finished to the completion
+ * queue, admits what fits into the freed slots, and launches one step of
+ * every active request.  The queries of the requests that may be admitted
+ * are copied while the previous step still runs, and the tick returns
+ * without waiting for its own step, so the caller's work between ticks
+ * overlaps the device: a request's result reaches the completion queue in
+ * the tick after the one whose step finished it, and its slot is taken by a
+ * waiting request in that same tick (call tick until every result has been
+ * polled).
  * *n_active (may be NULL): requests in this tick's step.
  * HENN_E_INVAL once the index has been changed by henn_insert / henn_delete
  * since the server was created. */

@@ -387,22 +387,31 @@ henn_status henn_server_tick(henn_server* s, int32_t* n_active_out) {
   if (s->idx->updates != s->idx_updates)
     return srv_fail(HENN_E_INVAL, "the index was updated after this server was created");
   try {
-    // 1) admission, FIFO, while a slot and arena bytes are free, into this
-    //    step's staging buffer (the previous step may still run)
+    // 1) while the previous step may still run: copy the queries of the
+    //    requests that could be admitted once it is retired (at most the
+    //    free slots plus the requests it advances) into this step's staging
+    //    buffer; those requests stay at the head of the FIFO until admitted
     const int64_t M = s->p.max_slots;
     const int c = (int)(s->launches & 1);
     float* stage_q = s->stage_q_h + (size_t)c * M * s->d;
     int32_t* stage_meta = s->stage_meta_h + (size_t)c * M * 7;
+    const int64_t could_free = (int64_t)s->free_slots.size() + (s->inflight ? s->inflight_active : 0);
+    const int n_stage = (int)std::min<int64_t>((int64_t)s->pending.size(), std::min(could_free, M));
+    if (n_stage > 0)
+      memcpy(stage_q, s->pending.q.data() + s->pending.head * (size_t)s->d,
+             sizeof(float) * (size_t)n_stage * s->d);
+    // 2) the previous step's completions free their slots
+    retire_step(s);
+    // 3) admission, FIFO, among the staged requests while a slot and arena
+    //    bytes are free (row i of the staging buffer is the i-th admitted)
     int n_new = 0;
-    while (!s->pending.empty() && !s->free_slots.empty()) {
+    while (n_new < n_stage && !s->free_slots.empty()) {
       const PendingQueue::Meta& r = s->pending.meta[s->pending.head];
-      const float* rq = s->pending.q.data() + s->pending.head * (size_t)s->d;
       const int64_t need = state_bytes(s, r.k, r.ef);
       int64_t off = 0;
       if (!s->alloc->alloc(need, &off)) break;
       const int32_t slot = s->free_slots.back();
       s->free_slots.pop_back();
-      memcpy(stage_q + (int64_t)n_new * s->d, rq, sizeof(float) * s->d);
       int32_t* m = stage_meta + n_new * 6;
       m[0] = slot;
       m[1] = r.k;
@@ -419,9 +428,7 @@ henn_status henn_server_tick(henn_server* s, int32_t* n_active_out) {
       ++n_new;
       ++s->admitted;
     }
-    // 2) the previous step's completions free their slots (for the next tick)
-    retire_step(s);
-    // 3) this tick's launches
+    // 4) this tick's launches
     const henn_index* idx = s->idx;
     SearchArgs a;
     memset(&a, 0, sizeof(a));
