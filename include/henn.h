@@ -327,7 +327,7 @@ typedef struct {
 
 typedef struct {
   int64_t pending, active, completed, admitted, ticks, pool_bytes_used, max_active,
-      done_queued;
+      done_queued, cancelled;
 } henn_server_stats_t;
 
 /* Defaults: 4096 slots, 64 MiB pool, 16 steps per tick, k_max 10,
@@ -359,6 +359,18 @@ henn_status henn_server_tick(henn_server *s, int32_t *n_active);
 henn_status henn_server_poll(henn_server *s, int32_t max_results, int64_t *tags, int32_t *ids,
                              float *dist, int32_t *n_out);
 henn_status henn_server_stats(const henn_server *s, henn_server_stats_t *out);
+/* Cancels the request submitted with this tag (tags are meant to be unique;
+ * with repeated tags, a waiting request is taken before an admitted one).
+ * *state (may be NULL):
+ *   0 no such request;
+ *   1 it was waiting for admission: removed, it will not run;
+ *   2 it was admitted: it returns no result, and its slot and state bytes
+ *     are freed by the next tick (the step in flight may still advance it);
+ *   3 it had already finished: its result stays in the completion queue.
+ * Searching a waiting request is linear in the queue length (and removing
+ * one moves the requests behind it), so cancellation is for the occasional
+ * request, not the common path. */
+henn_status henn_server_cancel(henn_server *s, int64_t tag, int32_t *state);
 void henn_server_destroy(henn_server *s);
 
 /* Releases the index.  No enqueued work may still use it.  NULL is a no-op. */

@@ -141,6 +141,7 @@ struct henn_server {
   std::vector<int32_t> active;
   std::vector<int64_t> slot_tag, slot_off, slot_bytes;
   std::vector<int32_t> slot_kk;
+  std::vector<char> slot_cancelled;  // admitted requests cancelled by henn_server_cancel
   // completed, not yet polled: tags, and per completion k_max ids then
   // k_max distance bits
   // completion queue: entries [done_head, done_tags.size()) are waiting to
@@ -148,7 +149,8 @@ struct henn_server {
   std::vector<int64_t> done_tags;
   std::vector<int32_t> done_vals;
   size_t done_head = 0;
-  int64_t ticks = 0, admitted = 0, completed = 0, max_active = 0;
+  int64_t ticks = 0, admitted = 0, completed = 0, max_active = 0, cancelled = 0;
+  int64_t n_slot_cancelled = 0;  // slots marked in slot_cancelled, not yet freed
 };
 
 namespace henn {
@@ -305,6 +307,7 @@ henn_status henn_server_create(const henn_index* idx, const henn_server_params* 
     s->slot_off.assign(M, 0);
     s->slot_bytes.assign(M, 0);
     s->slot_kk.assign(M, 0);
+    s->slot_cancelled.assign(M, 0);
     for (int64_t i = M - 1; i >= 0; --i) s->free_slots.push_back((int32_t)i);
     *out = s;
     return HENN_OK;
@@ -351,14 +354,39 @@ henn_status henn_server_submit_batch(henn_server* s, const float* q_host, const 
 // Retires the launched step: waits for the stream, then moves its
 // completions (rows the kernel wrote into host memory) to the poll queue and
 // frees their slots and state bytes.
+// Frees the slots of admitted requests that were cancelled (no step may be
+// in flight: the device no longer touches them).
+static void free_cancelled(henn_server* s) {
+  if (s->n_slot_cancelled == 0) return;
+  std::vector<int32_t> keep;
+  keep.reserve(s->active.size());
+  for (int32_t sl : s->active) {
+    if (s->slot_cancelled[sl]) {
+      s->slot_cancelled[sl] = 0;
+      s->alloc->release(s->slot_off[sl], s->slot_bytes[sl]);
+      s->free_slots.push_back(sl);
+    } else {
+      keep.push_back(sl);
+    }
+  }
+  s->active.swap(keep);
+  s->n_slot_cancelled = 0;
+}
+
 static void retire_step(henn_server* s) {
-  if (!s->inflight) return;
+  if (!s->inflight) {
+    free_cancelled(s);
+    return;
+  }
   HENN_HIP(hipStreamSynchronize(s->st));
   s->inflight = false;
   const int nd = s->done_h[s->inflight_parity];
   // each request the step advanced completes at most once in it
   if (nd > s->inflight_active) throw HipError{hipErrorIllegalState, "completion count"};
-  if (nd <= 0) return;
+  if (nd <= 0) {
+    free_cancelled(s);
+    return;
+  }
   const int words = 1 + 2 * s->k_max;
   std::vector<char> finished(s->p.max_slots, 0);
   s->done_tags.reserve(s->done_tags.size() + nd);
@@ -366,6 +394,10 @@ static void retire_step(henn_server* s) {
   for (int i = 0; i < nd; ++i) {
     const int32_t* row = s->rows_h + (int64_t)i * words;
     const int32_t slot = row[0];
+    if (s->slot_cancelled[slot]) {
+      // cancelled after admission: no result (the slot is freed below)
+      continue;
+    }
     s->done_tags.push_back(s->slot_tag[slot]);
     s->done_vals.insert(s->done_vals.end(), row + 1, row + words);
     s->alloc->release(s->slot_off[slot], s->slot_bytes[slot]);
@@ -378,6 +410,7 @@ static void retire_step(henn_server* s) {
   for (int32_t sl : s->active)
     if (!finished[sl]) keep.push_back(sl);
   s->active.swap(keep);
+  free_cancelled(s);
 }
 
 henn_status henn_server_tick(henn_server* s, int32_t* n_active_out) {
@@ -564,6 +597,47 @@ henn_status henn_server_poll(henn_server* s, int32_t max_results, int64_t* tags,
   return HENN_OK;
 }
 
+henn_status henn_server_cancel(henn_server* s, int64_t tag, int32_t* state) {
+  if (!s) return srv_fail(HENN_E_INVAL, "null server");
+  int32_t st = 0;
+  // waiting for admission: remove it from the FIFO
+  for (size_t i = s->pending.head; i < s->pending.meta.size(); ++i) {
+    if (s->pending.meta[i].tag != tag) continue;
+    s->pending.meta.erase(s->pending.meta.begin() + i);
+    s->pending.q.erase(s->pending.q.begin() + i * (size_t)s->d,
+                       s->pending.q.begin() + (i + 1) * (size_t)s->d);
+    if (s->pending.head == s->pending.meta.size()) {
+      s->pending.meta.clear();
+      s->pending.q.clear();
+      s->pending.head = 0;
+    }
+    st = 1;
+    break;
+  }
+  // admitted and not finished (as far as the host knows): no result
+  if (st == 0) {
+    for (int32_t sl : s->active) {
+      if (s->slot_tag[sl] == tag && !s->slot_cancelled[sl]) {
+        s->slot_cancelled[sl] = 1;
+        ++s->n_slot_cancelled;
+        st = 2;
+        break;
+      }
+    }
+  }
+  // finished, waiting to be polled
+  if (st == 0) {
+    for (size_t i = s->done_head; i < s->done_tags.size(); ++i)
+      if (s->done_tags[i] == tag) {
+        st = 3;
+        break;
+      }
+  }
+  if (st == 1 || st == 2) ++s->cancelled;
+  if (state) *state = st;
+  return HENN_OK;
+}
+
 henn_status henn_server_stats(const henn_server* s, henn_server_stats_t* out) {
   if (!s || !out) return srv_fail(HENN_E_INVAL, "null argument");
   out->pending = (int64_t)s->pending.size();
@@ -574,6 +648,7 @@ henn_status henn_server_stats(const henn_server* s, henn_server_stats_t* out) {
   out->pool_bytes_used = s->alloc->used();
   out->max_active = s->max_active;
   out->done_queued = (int64_t)(s->done_tags.size() - s->done_head);
+  out->cancelled = s->cancelled;
   return HENN_OK;
 }
 

@@ -76,7 +76,7 @@ class ServerParams(ctypes.Structure):
 class ServerStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in ("pending", "active", "completed", "admitted",
                                               "ticks", "pool_bytes_used", "max_active",
-                                              "done_queued")]
+                                              "done_queued", "cancelled")]
 
 
 STATUS_NAMES = {0: "base", 1: "vacuous", 2: "verified", 3: "not_verified"}
@@ -131,6 +131,7 @@ def load_library(path: str = LIB_PATH):
     lib.henn_server_submit_batch.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int64]
     lib.henn_server_poll.argtypes = [vp, ctypes.c_int32, vp, vp, vp, P(ctypes.c_int32)]
     lib.henn_server_stats.argtypes = [vp, P(ServerStats)]
+    lib.henn_server_cancel.argtypes = [vp, ctypes.c_int64, P(ctypes.c_int32)]
     lib.henn_server_destroy.argtypes = [vp]
     lib.henn_server_destroy.restype = None
     lib.henn_import.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, P(BuildParams), ctypes.c_int32,
@@ -508,6 +509,13 @@ class Server:
         _check(load_library().henn_server_submit_batch(
             self._s, Q.ctypes.data_as(vp), ks.ctypes.data_as(vp), efs.ctypes.data_as(vp),
             tags.ctypes.data_as(vp), Q.shape[0]))
+
+    def cancel(self, tag: int) -> int:
+        """henn_server_cancel: 0 not found, 1 removed before admission,
+        2 admitted (no result will come), 3 already finished."""
+        st = ctypes.c_int32()
+        _check(load_library().henn_server_cancel(self._s, int(tag), ctypes.byref(st)))
+        return st.value
 
     def tick(self) -> int:
         n = ctypes.c_int32()

@@ -135,6 +135,7 @@ def test_server_params_and_validation(lib):
     out = ctypes.c_void_p()
     assert lib.henn_server_create(None, ctypes.byref(p), ctypes.byref(out)) == hn.HENN_E_INVAL
     assert lib.henn_server_tick(None, None) == hn.HENN_E_INVAL
+    assert lib.henn_server_cancel(None, 1, None) == hn.HENN_E_INVAL
     lib.henn_server_destroy(None)
 
 

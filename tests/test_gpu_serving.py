@@ -123,6 +123,39 @@ def test_waves_separated_by_idle_ticks(setup):
         assert np.array_equal(got[j][1].view(np.uint32), ref_d[j].view(np.uint32)), j
 
 
+def test_cancel_waiting_and_admitted_requests(setup):
+    """Cancelled requests return nothing; every other request still equals
+    the batch search, and the freed slots and bytes are reused."""
+    hn, X, Q, idx = setup
+    n = 96
+    ref_i, ref_d = _batch(hn, idx, Q[:n], 10, 64)
+    srv = hn.Server(idx, max_slots=16, k_max=10, ef_max=64, steps_per_tick=4, vis_bits=10)
+    for j in range(n):
+        srv.submit(Q[j], 10, 64, j)
+    waiting = [40, 41, 95]
+    assert [srv.cancel(t) for t in waiting] == [1, 1, 1]
+    srv.tick()  # admits 0..15, launches their first step
+    admitted = [3, 7]
+    assert [srv.cancel(t) for t in admitted] == [2, 2]
+    assert srv.cancel(1000) == 0
+    got = {}
+    for _ in range(100000):
+        srv.tick()
+        tags, ids, dist = srv.poll()
+        for t, i, d in zip(tags, ids, dist):
+            got[int(t)] = (i.copy(), d.copy())
+        if srv.stats()["pending"] == 0 and srv.stats()["active"] == 0 and \
+                len(got) == n - len(waiting) - len(admitted):
+            break
+    st = srv.stats()
+    srv.close()
+    assert st["cancelled"] == 5 and st["pool_bytes_used"] == 0
+    assert set(got) == set(range(n)) - set(waiting) - set(admitted)
+    for j in got:
+        assert np.array_equal(got[j][0], ref_i[j]), j
+        assert np.array_equal(got[j][1].view(np.uint32), ref_d[j].view(np.uint32)), j
+
+
 @pytest.mark.parametrize("storage", [0, 2])
 def test_serving_and_captured_graph_after_updates(storage):
     """After Delete(x) and Insert(x) on an NSW index, the serving form and a
