@@ -53,11 +53,15 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 // value, with an insertion into the lane's sorted top-KS only when the
 // value beats the current KS-th.  Output: per (row, lane half) the KS
 // smallest (value, candidate index) pairs, ascending.
+// row_list: when given, the block's rows are row_list[i] for i < n_rows
+// (the rows the split form could not prove) and the shortlists go to
+// position i; otherwise rows 0 .. size - 1 in order (n_rows = size).
 template <int KH, int KS>
 __global__ __launch_bounds__(256, 2) void k_gram_topk(const float* vec, int64_t size, int dpad,
                                                       const float* norms, const float* mean,
                                                       int metric, float* sl_d, int32_t* sl_i,
-                                                      int64_t block0) {
+                                                      int64_t block0, const int32_t* row_list,
+                                                      int64_t n_rows) {
   // two LDS buffers of [kTileC][2 * KH + 4] candidates + their norms; the
   // next tile is fetched into registers while the current one is multiplied
   extern __shared__ __align__(16) float tile[];
@@ -65,8 +69,9 @@ __global__ __launch_bounds__(256, 2) void k_gram_topk(const float* vec, int64_t 
   constexpr int kBuf = kTileC * kStride + kTileC;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int qc = lane & 31, h = lane >> 5;
-  const int64_t qrow = (block0 + blockIdx.x) * 128 + wave * 32 + qc;
-  const bool qvalid = qrow < size;
+  const int64_t qi = (block0 + blockIdx.x) * 128 + wave * 32 + qc;
+  const bool qvalid = qi < n_rows;
+  const int64_t qrow = !qvalid ? -1 : row_list ? (int64_t)row_list[qi] : qi;
   const int64_t cb = 0, ce = size;
   const bool l2 = metric == 0;
   const float qscale = l2 ? -2.0f : -1.0f;
@@ -219,7 +224,7 @@ __global__ __launch_bounds__(256, 2) void k_gram_topk(const float* vec, int64_t 
     cur ^= 1;
   }
   if (qvalid) {
-    const int64_t o = qrow * (2 * KS) + h * KS;
+    const int64_t o = qi * (2 * KS) + h * KS;
 #pragma unroll
     for (int j = 0; j < KS; ++j) {
       sl_d[o + j] = td[j];
@@ -646,18 +651,21 @@ __global__ __launch_bounds__(256) void k_knn_rerank(const float* vec, int64_t si
                                                     int nchunks, int metric, const float* sl_d,
                                                     const int32_t* sl_i, const float* norms,
                                                     float nmax, float coef, int R, int32_t* adj,
-                                                    int32_t* fb_rows, uint32_t* fb_count) {
+                                                    int32_t* fb_rows, uint32_t* fb_count,
+                                                    const int32_t* row_list, int64_t n_rows) {
   constexpr int G = 64 / LPN;
   __shared__ uint64_t keys[4][64];
   const int wave = threadIdx.x >> 6;
-  const int64_t row = (int64_t)blockIdx.x * 4 + wave;
-  if (row >= size) return;
+  // shortlist i belongs to row row_list[i] (or row i)
+  const int64_t li = (int64_t)blockIdx.x * 4 + wave;
+  if (li >= n_rows) return;
+  const int64_t row = row_list ? (int64_t)row_list[li] : li;
   const int lane = lane_id(), t = lane % LPN, g = lane / LPN;
   float q[CPL][8];
   load_query<CPL>(vec + row * dpad, dpad, t, q);
   for (int base = 0; base < 2 * kShort; base += G) {
     const int ci = base + g;
-    const int32_t id = sl_i[row * (2 * kShort) + ci];
+    const int32_t id = sl_i[li * (2 * kShort) + ci];
     const bool valid = id >= 0;
     const float dist = group_distance<kF32, LPN, CPL>(q, vec + (int64_t)(valid ? id : 0) * dpad,
                                                       1.0f, t, nchunks, metric, valid);
@@ -666,7 +674,8 @@ __global__ __launch_bounds__(256) void k_knn_rerank(const float* vec, int64_t si
   wave_sync();
   const uint64_t key = wave_sort64(keys[wave][lane]);
   if (lane < R) adj[row * R + lane] = key == ~0ull ? -1 : (int32_t)(uint32_t)key;
-  const float cut = fminf(sl_d[row * (2 * kShort) + kShort - 1], sl_d[row * (2 * kShort) + 2 * kShort - 1]);
+  const float cut =
+      fminf(sl_d[li * (2 * kShort) + kShort - 1], sl_d[li * (2 * kShort) + 2 * kShort - 1]);
   const uint64_t kr = shfl_u64(key, R - 1);
   if (lane == 0 && isfinite(cut)) {
     // every candidate left out of the shortlist has a Gram value >= cut, and
@@ -1134,6 +1143,20 @@ int64_t build_knn_graph(const float* vec, int64_t size, int dpad, int nchunks, i
   const size_t lds = wide    ? sizeof(float) * (4 * kWideC * kSStride + dpad)
                      : split ? sizeof(uint4) * 2 * kTileC * (kp / 4 + 1) + sizeof(float) * 2 * kTileC
                              : sizeof(float) * (2 * (kTileC * (2 * kh + 4) + kTileC) + dpad);
+  // FP32 Gram tiles over row blocks [b0, b0 + nbs) of the given rows
+  auto launch_fp32_gram = [&](int64_t b0, unsigned nbs, const int32_t* row_list,
+                              int64_t n_rows) {
+    const size_t lds32 = sizeof(float) * (2 * (kTileC * (2 * kh + 4) + kTileC) + dpad);
+    if (kh <= 16)
+      hipLaunchKernelGGL((k_gram_topk<16, kShort>), dim3(nbs), dim3(256), lds32, st, vec, size,
+                         dpad, norms, mean, metric, sl_d, sl_i, b0, row_list, n_rows);
+    else if (kh <= 32)
+      hipLaunchKernelGGL((k_gram_topk<32, kShort>), dim3(nbs), dim3(256), lds32, st, vec, size,
+                         dpad, norms, mean, metric, sl_d, sl_i, b0, row_list, n_rows);
+    else
+      hipLaunchKernelGGL((k_gram_topk<64, kShort>), dim3(nbs), dim3(256), lds32, st, vec, size,
+                         dpad, norms, mean, metric, sl_d, sl_i, b0, row_list, n_rows);
+  };
   const int64_t nb = (size + 127) / 128;
   // Launch in slices of row blocks so that very large layers report progress
   // (HENN_PROGRESS=1) between slices; each slice is a full-width Gram sweep.
@@ -1157,15 +1180,9 @@ int64_t build_knn_graph(const float* vec, int64_t size, int dpad, int nchunks, i
         default:
           throw HipError{hipErrorInvalidValue, "split Gram: d <= 128"};
       }
-    } else if (kh <= 16)
-      hipLaunchKernelGGL((k_gram_topk<16, kShort>), dim3(nbs), dim3(256), lds, st, vec, size,
-                         dpad, norms, mean, metric, sl_d, sl_i, b0);
-    else if (kh <= 32)
-      hipLaunchKernelGGL((k_gram_topk<32, kShort>), dim3(nbs), dim3(256), lds, st, vec, size,
-                         dpad, norms, mean, metric, sl_d, sl_i, b0);
-    else
-      hipLaunchKernelGGL((k_gram_topk<64, kShort>), dim3(nbs), dim3(256), lds, st, vec, size,
-                         dpad, norms, mean, metric, sl_d, sl_i, b0);
+    } else {
+      launch_fp32_gram(b0, nbs, nullptr, size);
+    }
     HENN_HIP(hipGetLastError());
     if (progress && b0 + (int64_t)nbs < nb) {
       HENN_HIP(hipStreamSynchronize(st));
@@ -1178,28 +1195,53 @@ int64_t build_knn_graph(const float* vec, int64_t size, int dpad, int nchunks, i
     }
   }
 
-  const unsigned nr = (unsigned)((size + 3) / 4);
-  bool launched = false;
+  // re-rank and proof of n_rows shortlists (of rows row_list[i], or row i);
+  // unproven rows are appended to out_rows
+  auto rerank = [&](const int32_t* row_list, int64_t n_rows, float c, int32_t* out_rows,
+                    uint32_t* out_count) {
+    const unsigned nr = (unsigned)((n_rows + 3) / 4);
+    bool launched = false;
 #define HENN_TRY(L, C)                                                                         \
   if (!launched && lpn == L && cpl == C) {                                                     \
     hipLaunchKernelGGL((k_knn_rerank<L, C>), dim3(nr), dim3(256), 0, st, vec, size, dpad,      \
-                       nchunks, metric, sl_d, sl_i, norms, nmax, coef, R, adj, fb_rows,        \
-                       fb_count);                                                              \
+                       nchunks, metric, sl_d, sl_i, norms, nmax, c, R, adj, out_rows,          \
+                       out_count, row_list, n_rows);                                           \
     launched = true;                                                                           \
   }
-  HENN_KNN_COMBOS(HENN_TRY)
+    HENN_KNN_COMBOS(HENN_TRY)
 #undef HENN_TRY
-  if (!launched) throw HipError{hipErrorInvalidValue, "no rerank kernel for this lane shape"};
-  uint32_t nfb = 0;
-  HENN_HIP(hipMemcpyAsync(&nfb, fb_count, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-  HENN_HIP(hipStreamSynchronize(st));
+    if (!launched) throw HipError{hipErrorInvalidValue, "no rerank kernel for this lane shape"};
+  };
+  auto count_of = [&](uint32_t* dev_count) {
+    uint32_t n = 0;
+    HENN_HIP(hipMemcpyAsync(&n, dev_count, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    HENN_HIP(hipStreamSynchronize(st));
+    return n;
+  };
+  rerank(nullptr, size, coef, fb_rows, fb_count);
+  uint32_t nfb = count_of(fb_count);
+  if (nfb > 0 && split) {
+    // the rows the split form could not prove: FP32 tiles on just those rows
+    // (128 rows share each pass over the layer, where the brute force below
+    // reads the whole layer once per row), then the FP32 proof
+    DevBuf<int32_t> fb2_buf(nfb);
+    DevBuf<uint32_t> fb2_count(1);
+    HENN_HIP(hipMemsetAsync(fb2_count.get(), 0, sizeof(uint32_t), st));
+    launch_fp32_gram(0, (unsigned)((nfb + 127) / 128), fb_rows, nfb);
+    HENN_HIP(hipGetLastError());
+    rerank(fb_rows, nfb, 4.0f * (float)(dpad + 8) * 0x1p-24f, fb2_buf.get(), fb2_count.get());
+    nfb = count_of(fb2_count.get());
+    if (nfb > 0)
+      HENN_HIP(hipMemcpyAsync(fb_rows, fb2_buf.get(), sizeof(int32_t) * nfb,
+                              hipMemcpyDeviceToDevice, st));
+  }
   if (nfb > 0) {
     const int G = 64 / lpn;
     const int rpad = R;
     int n2 = 1;
     while (n2 < 4 * G * rpad) n2 <<= 1;
     const size_t lds2 = sizeof(uint64_t) * n2;
-    launched = false;
+    bool launched = false;
 #define HENN_TRY(L, C)                                                                          \
   if (!launched && lpn == L && cpl == C) {                                                      \
     hipLaunchKernelGGL((k_knn_exact<L, C>), dim3(nfb), dim3(256), lds2, st, vec, size, dpad,    \
