@@ -28,6 +28,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+GRAM = {"split": 0, "fp32": 1}  # kNN graph Gram tiles (build param gram)
 HBM_PEAK_GBS = 8000.0
 
 
@@ -59,6 +60,8 @@ def parse():
     ap.add_argument("--insert-shift", type=int, default=3, help="NSW batch = inserted >> shift")
     ap.add_argument("--degree", type=int, default=32)
     ap.add_argument("--max-degree", type=int, default=60)
+    ap.add_argument("--gram", default="split", choices=["split", "fp32"],
+                    help="kNN graph Gram tiles: split BF16 (default) or FP32 matrix cores")
     ap.add_argument("--root-max", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--shape", default=None,
@@ -286,7 +289,8 @@ def main():
     build_s = {}
     torch.cuda.synchronize()
     t = time.time()
-    bparams = dict(degree=args.degree, metric=metric, graph=graph, max_degree=args.max_degree,
+    bparams = dict(gram=GRAM[args.gram], degree=args.degree, metric=metric, graph=graph,
+                   max_degree=args.max_degree,
                    root_complete_max=args.root_max, sampler=hn.SAMPLER[args.sampler],
                    ef_construction=args.ef_construction, insert_shift=args.insert_shift)
     base = hn.henn_build(Xd, storage=0, **bparams)
@@ -593,7 +597,7 @@ def adversarial_experiment(hn, args, threads, wname="curve_1M_d96", storage="bf1
     nq = Q.shape[0]
     Xd = torch.from_numpy(X).to(dev)
     Qd = torch.from_numpy(Q).to(dev)
-    bp = dict(degree=args.degree, metric=0, graph=hn.GRAPH[args.graph],
+    bp = dict(gram=GRAM[args.gram], degree=args.degree, metric=0, graph=hn.GRAPH[args.graph],
               max_degree=args.max_degree, root_complete_max=args.root_max)
     torch.cuda.synchronize()
     t = time.time()
@@ -815,7 +819,7 @@ def batched(args):
     log(f"data {n}x{d}, {nq} queries in {time.time() - t0:.1f}s")
     Xd = torch.from_numpy(X).to(dev)
     Qd = torch.from_numpy(Q).to(dev)
-    bp = dict(degree=args.degree, metric=metric, graph=hn.GRAPH[args.graph],
+    bp = dict(gram=GRAM[args.gram], degree=args.degree, metric=metric, graph=hn.GRAPH[args.graph],
               sampler=hn.SAMPLER[args.sampler], ef_construction=args.ef_construction,
               insert_shift=args.insert_shift,
               max_degree=args.max_degree, root_complete_max=args.root_max)
@@ -922,7 +926,7 @@ def serving(args):
     log(f"data {n}x{d}, {nq} queries in {time.time() - t0:.1f}s")
     Xd = torch.from_numpy(X).to(dev)
     Qd = torch.from_numpy(Q).to(dev)
-    bp = dict(degree=args.degree, metric=metric, graph=hn.GRAPH[args.graph],
+    bp = dict(gram=GRAM[args.gram], degree=args.degree, metric=metric, graph=hn.GRAPH[args.graph],
               sampler=hn.SAMPLER[args.sampler], ef_construction=args.ef_construction,
               insert_shift=args.insert_shift,
               max_degree=args.max_degree, root_complete_max=args.serve_root_max)
