@@ -16,7 +16,6 @@
 #include <algorithm>
 #include <chrono>
 #include <deque>
-#include <map>
 #include <new>
 #include <string>
 #include <vector>
@@ -30,15 +29,16 @@ namespace henn {
 // state size is one of a few values (list capacity and visited table), so
 // freed blocks go to a free list per size and are reused by requests of the
 // same size; new blocks come from the untouched top of the arena.  Neither
-// operation scans: a lookup among the few sizes in use and a stack push/pop.
+// operation scans the blocks: a lookup among the few sizes in use and a
+// stack push / pop.
 class ArenaAlloc {
  public:
   explicit ArenaAlloc(int64_t size) : size_(size) {}
   bool alloc(int64_t len, int64_t* off) {
-    auto it = free_.find(len);
-    if (it != free_.end() && !it->second.empty()) {
-      *off = it->second.back();
-      it->second.pop_back();
+    std::vector<int64_t>* fl = list_of(len);
+    if (fl && !fl->empty()) {
+      *off = fl->back();
+      fl->pop_back();
     } else if (top_ + len <= size_) {
       *off = top_;
       top_ += len;
@@ -50,12 +50,22 @@ class ArenaAlloc {
   }
   void release(int64_t off, int64_t len) {
     used_ -= len;
-    free_[len].push_back(off);
+    std::vector<int64_t>* fl = list_of(len);
+    if (!fl) {
+      free_.emplace_back(len, std::vector<int64_t>());
+      fl = &free_.back().second;
+    }
+    fl->push_back(off);
   }
   int64_t used() const { return used_; }
 
  private:
-  std::map<int64_t, std::vector<int64_t>> free_;
+  std::vector<int64_t>* list_of(int64_t len) {
+    for (auto& e : free_)
+      if (e.first == len) return &e.second;
+    return nullptr;
+  }
+  std::vector<std::pair<int64_t, std::vector<int64_t>>> free_;  // (block size, free blocks)
   int64_t size_, top_ = 0, used_ = 0;
 };
 
@@ -111,10 +121,15 @@ struct henn_server {
   char* arena = nullptr;
   // done_d: two completion counters, used by alternate steps
   int32_t* done_d = nullptr;
-  float* stage_q_d = nullptr;
+  float* stage_q_d = nullptr;  // [2][max_slots][d], by launch parity
+  // the staged queries go to the device on their own stream while the
+  // previous step runs; the admission kernels wait for copy_done[parity]
+  hipStream_t st_copy = nullptr;
+  hipEvent_t copy_done[2] = {nullptr, nullptr};
+  bool copy_pending[2] = {false, false};
   int32_t* stage_meta_d = nullptr;
-  int32_t* rows_d = nullptr;  // device address of rows_h: the kernel writes a tick's
-                              // completion rows straight into host memory
+  int32_t* rows_d = nullptr;  // device address of rows_h: a step writes its completion
+                              // rows straight into host memory, rows_h[parity]
   // complete-graph root on matrix cores (prepared roots only): each admitted
   // request's root key, its shortlist scratch and the per-slot keys
   uint64_t* root_keys = nullptr;
@@ -125,7 +140,7 @@ struct henn_server {
   float* stage_q_h = nullptr;     // [2][max_slots][d]
   int32_t* stage_meta_h = nullptr;  // [2][max_slots * 7]
   int32_t* done_h = nullptr;
-  int32_t* rows_h = nullptr;
+  int32_t* rows_h = nullptr;  // [2][max_slots][1 + 2 k_max], by launch parity
   // host state
   bool inflight = false;  // a launched step whose completions are not yet retired
   int inflight_parity = 0;
@@ -142,6 +157,12 @@ struct henn_server {
   std::vector<int64_t> slot_tag, slot_off, slot_bytes;
   std::vector<int32_t> slot_kk;
   std::vector<char> slot_cancelled;  // admitted requests cancelled by henn_server_cancel
+  std::vector<char> finished;        // scratch of retire_step, per slot
+  // the retired step's result rows whose ids and distances are still to be
+  // copied into done_vals (their tags are queued already): copied after the
+  // next launch, while the device works (rows_h[payload_parity])
+  std::vector<int32_t> payload_rows;
+  int payload_parity = 0;
   // completed, not yet polled: tags, and per completion k_max ids then
   // k_max distance bits
   // completion queue: entries [done_head, done_tags.size()) are waiting to
@@ -183,6 +204,9 @@ static void srv_release(henn_server* s) {
   (void)hipHostFree(s->done_h);
   (void)hipHostFree(s->rows_h);
   if (s->st) (void)hipStreamDestroy(s->st);
+  if (s->st_copy) (void)hipStreamDestroy(s->st_copy);
+  for (hipEvent_t& e : s->copy_done)
+    if (e) (void)hipEventDestroy(e);
   delete s->alloc;
   delete s;
 }
@@ -281,6 +305,9 @@ henn_status henn_server_create(const henn_index* idx, const henn_server_params* 
     if (p->pool_bytes < state_bytes(s, p->k_max, p->ef_max))
       throw HipError{hipErrorInvalidValue, "pool_bytes below one request's state"};
     HENN_HIP(hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking));
+    HENN_HIP(hipStreamCreateWithFlags(&s->st_copy, hipStreamNonBlocking));
+    for (hipEvent_t& e : s->copy_done)
+      HENN_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     dmalloc(&s->slot_q, M * s->d);
     dmalloc(&s->slot_k, M);
     dmalloc(&s->slot_ef, M);
@@ -290,7 +317,7 @@ henn_status henn_server_create(const henn_index* idx, const henn_server_params* 
     dmalloc(&s->arena, p->pool_bytes);
     dmalloc(&s->done_d, 2);
     HENN_HIP(hipMemset(s->done_d, 0, sizeof(int32_t) * 2));
-    dmalloc(&s->stage_q_d, M * s->d);
+    dmalloc(&s->stage_q_d, 2 * M * s->d);
     dmalloc(&s->stage_meta_d, M * 7);  // admission metadata [n_new][6], then the active list
     if (idx->root.size > 0) {
       dmalloc(&s->root_keys, M);
@@ -300,7 +327,7 @@ henn_status henn_server_create(const henn_index* idx, const henn_server_params* 
     hmalloc(&s->stage_q_h, 2 * M * s->d);
     hmalloc(&s->stage_meta_h, 2 * M * 7);
     hmalloc(&s->done_h, 2);
-    hmalloc(&s->rows_h, M * (1 + 2 * s->k_max), true);
+    hmalloc(&s->rows_h, 2 * M * (1 + 2 * s->k_max), true);
     HENN_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&s->rows_d), s->rows_h, 0));
     s->alloc = new ArenaAlloc(p->pool_bytes);
     s->slot_tag.assign(M, 0);
@@ -308,6 +335,7 @@ henn_status henn_server_create(const henn_index* idx, const henn_server_params* 
     s->slot_bytes.assign(M, 0);
     s->slot_kk.assign(M, 0);
     s->slot_cancelled.assign(M, 0);
+    s->finished.assign(M, 0);
     for (int64_t i = M - 1; i >= 0; --i) s->free_slots.push_back((int32_t)i);
     *out = s;
     return HENN_OK;
@@ -373,7 +401,10 @@ static void free_cancelled(henn_server* s) {
   s->n_slot_cancelled = 0;
 }
 
+static void flush_payload(henn_server* s);
+
 static void retire_step(henn_server* s) {
+  flush_payload(s);  // a payload left by a tick that failed after retiring
   if (!s->inflight) {
     free_cancelled(s);
     return;
@@ -388,29 +419,45 @@ static void retire_step(henn_server* s) {
     return;
   }
   const int words = 1 + 2 * s->k_max;
-  std::vector<char> finished(s->p.max_slots, 0);
+  const int32_t* rows = s->rows_h + (int64_t)s->inflight_parity * s->p.max_slots * words;
   s->done_tags.reserve(s->done_tags.size() + nd);
-  s->done_vals.reserve(s->done_vals.size() + (size_t)nd * (words - 1));
+  s->payload_rows.clear();
+  s->payload_parity = s->inflight_parity;
   for (int i = 0; i < nd; ++i) {
-    const int32_t* row = s->rows_h + (int64_t)i * words;
-    const int32_t slot = row[0];
+    const int32_t slot = rows[(int64_t)i * words];
     if (s->slot_cancelled[slot]) {
       // cancelled after admission: no result (the slot is freed below)
       continue;
     }
     s->done_tags.push_back(s->slot_tag[slot]);
-    s->done_vals.insert(s->done_vals.end(), row + 1, row + words);
+    s->payload_rows.push_back(i);
     s->alloc->release(s->slot_off[slot], s->slot_bytes[slot]);
     s->free_slots.push_back(slot);
-    finished[slot] = 1;
+    s->finished[slot] = 1;
     ++s->completed;
   }
   std::vector<int32_t> keep;
   keep.reserve(s->active.size());
   for (int32_t sl : s->active)
-    if (!finished[sl]) keep.push_back(sl);
+    if (!s->finished[sl]) keep.push_back(sl);
+  for (int i = 0; i < nd; ++i) s->finished[rows[(int64_t)i * words]] = 0;
   s->active.swap(keep);
   free_cancelled(s);
+}
+
+// Copies the retired step's ids and distances behind their queued tags.
+// Must run before the next launch with the same parity rewrites those rows
+// (every tick ends with it, and poll / stats start with it).
+static void flush_payload(henn_server* s) {
+  if (s->payload_rows.empty()) return;
+  const int words = 1 + 2 * s->k_max;
+  const int32_t* rows = s->rows_h + (int64_t)s->payload_parity * s->p.max_slots * words;
+  s->done_vals.reserve(s->done_vals.size() + s->payload_rows.size() * (size_t)(words - 1));
+  for (int32_t i : s->payload_rows) {
+    const int32_t* row = rows + (int64_t)i * words;
+    s->done_vals.insert(s->done_vals.end(), row + 1, row + words);
+  }
+  s->payload_rows.clear();
 }
 
 henn_status henn_server_tick(henn_server* s, int32_t* n_active_out) {
@@ -430,9 +477,24 @@ henn_status henn_server_tick(henn_server* s, int32_t* n_active_out) {
     int32_t* stage_meta = s->stage_meta_h + (size_t)c * M * 7;
     const int64_t could_free = (int64_t)s->free_slots.size() + (s->inflight ? s->inflight_active : 0);
     const int n_stage = (int)std::min<int64_t>((int64_t)s->pending.size(), std::min(could_free, M));
-    if (n_stage > 0)
+    float* stage_q_dev = s->stage_q_d + (size_t)c * M * s->d;
+    if (s->copy_pending[c]) {
+      // this buffer's previous copy (two launches ago) has long finished
+      HENN_HIP(hipEventSynchronize(s->copy_done[c]));
+      s->copy_pending[c] = false;
+    }
+    if (n_stage > 0) {
       memcpy(stage_q, s->pending.q.data() + s->pending.head * (size_t)s->d,
              sizeof(float) * (size_t)n_stage * s->d);
+      // row i of the staging buffer is the i-th request admitted below, so
+      // the copy can start now, while the previous step still runs (the
+      // device buffer of this parity was last read by the admission of two
+      // launches ago, which precedes the step retired below)
+      HENN_HIP(hipMemcpyAsync(stage_q_dev, stage_q, sizeof(float) * (size_t)n_stage * s->d,
+                              hipMemcpyHostToDevice, s->st_copy));
+      HENN_HIP(hipEventRecord(s->copy_done[c], s->st_copy));
+      s->copy_pending[c] = true;
+    }
     // 2) the previous step's completions free their slots
     retire_step(s);
     // 3) admission, FIFO, among the staged requests while a slot and arena
@@ -494,10 +556,7 @@ henn_status henn_server_tick(henn_server* s, int32_t* n_active_out) {
     a.vis_bits = s->vis_bits;
     a.vis_bytes = vis_tag_bytes(idx->n, s->vis_bits);
     a.root_complete = idx->root_complete ? 1 : 0;
-    if (n_new > 0) {
-      HENN_HIP(hipMemcpyAsync(s->stage_q_d, stage_q, sizeof(float) * n_new * s->d,
-                              hipMemcpyHostToDevice, s->st));
-    }
+    if (n_new > 0) HENN_HIP(hipStreamWaitEvent(s->st, s->copy_done[c], 0));
     // one H2D copy: the admission metadata, then the active list
     const int n_active = (int)s->active.size();
     memcpy(stage_meta + n_new * 6, s->active.data(), sizeof(int32_t) * n_active);
@@ -511,22 +570,25 @@ henn_status henn_server_tick(henn_server* s, int32_t* n_active_out) {
         int64_t per = 0;
         const int splits = root_gram_splits(n_new, idx->root.size, &per);
         const RootShortlist sl = root_shortlist_at(s->root_sl, n_new, idx->root.kp);
-        launch_root_gram(s->stage_q_d, n_new, s->d, idx->root, idx->dpad, idx->metric, splits,
+        launch_root_gram(stage_q_dev, n_new, s->d, idx->root, idx->dpad, idx->metric, splits,
                          per, sl, s->st);
         SearchArgs ra = a;
-        ra.Q = s->stage_q_d;
+        ra.Q = stage_q_dev;
         ra.nq = n_new;
         if (!launch_root_check(idx->storage, ra, sl, s->root_keys, s->st))
           return srv_fail(HENN_E_UNSUPPORTED, "no root check kernel for this shape");
       }
-      launch_serve_admit(s->stage_q_d, s->stage_meta_d, n_new, s->d, s->slot_q, s->slot_k,
+      launch_serve_admit(stage_q_dev, s->stage_meta_d, n_new, s->d, s->slot_q, s->slot_k,
                          s->slot_ef, s->state_off, s->cap, s->states, s->root_keys,
                          s->slot_root, s->st);
     }
     s->max_active = std::max<int64_t>(s->max_active, n_active);
     if (n_active_out) *n_active_out = n_active;
     ++s->ticks;
-    if (n_active == 0) return HENN_OK;
+    if (n_active == 0) {
+      flush_payload(s);
+      return HENN_OK;
+    }
     // one step of every active request; completions are counted in done_d[c]
     // (c = launch parity) while the kernel clears done_d[c ^ 1] for the next
     // step
@@ -548,7 +610,7 @@ henn_status henn_server_tick(henn_server* s, int32_t* n_active_out) {
     sv.arena = s->arena;
     sv.done_count = s->done_d + c;
     sv.done_clear = s->done_d + (c ^ 1);
-    sv.done_rows = s->rows_d;
+    sv.done_rows = s->rows_d + (int64_t)c * s->p.max_slots * (1 + 2 * s->k_max);
     if (!launch_serve_step(idx->storage, a, sv, s->shape, s->st))
       return srv_fail(HENN_E_UNSUPPORTED, "no serving kernel for this shape");
     HENN_HIP(hipGetLastError());
@@ -560,6 +622,8 @@ henn_status henn_server_tick(henn_server* s, int32_t* n_active_out) {
     s->inflight_parity = c;
     s->inflight_active = n_active;
     ++s->launches;
+    // the previous step's ids and distances, while this step runs
+    flush_payload(s);
     return HENN_OK;
   } catch (const HipError& e) {
     henn::set_error(std::string("server tick: HIP error ") + hipGetErrorString(e.e) + " in " + e.what);
@@ -572,6 +636,11 @@ henn_status henn_server_tick(henn_server* s, int32_t* n_active_out) {
 henn_status henn_server_poll(henn_server* s, int32_t max_results, int64_t* tags, int32_t* ids,
                              float* dist, int32_t* n_out) {
   if (!s || !n_out) return srv_fail(HENN_E_INVAL, "null argument");
+  try {
+    flush_payload(s);  // normally a no-op: every tick ends with it
+  } catch (const std::bad_alloc&) {
+    return srv_fail(HENN_E_NOMEM, "host allocation failed");
+  }
   const int K = s->k_max;
   const size_t avail = s->done_tags.size() - s->done_head;
   const int n = (int)std::min<size_t>(avail, (size_t)std::max(max_results, 0));
@@ -655,6 +724,7 @@ henn_status henn_server_stats(const henn_server* s, henn_server_stats_t* out) {
 void henn_server_destroy(henn_server* s) {
   if (!s) return;
   (void)hipStreamSynchronize(s->st);
+  if (s->st_copy) (void)hipStreamSynchronize(s->st_copy);
   srv_release(s);
 }
 
