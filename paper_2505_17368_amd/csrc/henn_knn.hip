@@ -799,9 +799,9 @@ int root_gram_splits(int64_t nq, int64_t root_size, int64_t* rows_per_split) {
 //   A = 32 root rows (lane: row lane & 31, coordinates 16 s + 8 h .. + 7)
 //   B = the wave's 32 queries, as bf16 of -2 (q - mean) (L2) or -q (IP)
 // so that acc + norm is the Gram value a(y), |y - q|^2 - |q - mean|^2 (L2)
-// or -<y, q> (IP) up to the BF16 rounding, which the margin covers.  Both
-// operands come straight from memory (the root is L2-resident); the next
-// tile's loads are issued before the current tile is multiplied.
+// or -<y, q> (IP) up to the BF16 rounding, which the margin covers.  The
+// query operand stays in registers for the whole scan; the root tiles pass
+// through LDS, copied ahead of the tile being multiplied (see the ring below).
 //
 // Two passes over the split: the first keeps only the smallest Gram value
 // and merges it into the query's running minimum over the splits; the
@@ -873,10 +873,18 @@ __global__ __launch_bounds__(256) void k_root_query_bf16(const float* Q, int64_t
   float qn = 0.0f;
   uint32_t w[4] = {0u, 0u, 0u, 0u};
   if (live) {
-    // loads clamped into the row and issued together; values past d dropped
     float x[8], m[8];
+    if ((d & 3) == 0 && (reinterpret_cast<uintptr_t>(Q) & 15) == 0 && 8 * c + 8 <= d) {
+      // whole 16-byte chunks of the row (every row starts 16-byte aligned)
+      const float4* qr = reinterpret_cast<const float4*>(Q + qi * d + 8 * c);
+      const float4 x0 = qr[0], x1 = qr[1];
+      x[0] = x0.x, x[1] = x0.y, x[2] = x0.z, x[3] = x0.w;
+      x[4] = x1.x, x[5] = x1.y, x[6] = x1.z, x[7] = x1.w;
+    } else {
+      // loads clamped into the row and issued together; values past d dropped
 #pragma unroll
-    for (int j = 0; j < 8; ++j) x[j] = Q[qi * d + min(8 * c + j, d - 1)];
+      for (int j = 0; j < 8; ++j) x[j] = Q[qi * d + min(8 * c + j, d - 1)];
+    }
     if (mean) {
 #pragma unroll
       for (int j = 0; j < 8; ++j) m[j] = mean[min(8 * c + j, d - 1)];
@@ -974,9 +982,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                                        (lds_ptr)(reinterpret_cast<float*>(tile + kTileU4) + 8 * wave),
                                        4, 0, 0);
   };
-  // waits until at most n of this wave's copies are outstanding (the copies
-  // complete in order, and no other vector memory operation is in flight:
-  // the list stores wait for themselves)
+  // waits until at most n of this wave's vector memory operations are
+  // outstanding.  Loads complete in order, so the copies issued before the
+  // last n operations are done.  Inside a scan the only other operations are
+  // the running-minimum atomic and pass 2's list writes, which can only make
+  // the wait longer.
   auto wait_copies = [](int n) {
     switch (n) {
       case 0: __builtin_amdgcn_s_waitcnt(0xF70); break;
@@ -1054,21 +1064,41 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     vmin = fminf(vmin, tile_min(val));
   });
   vmin = fminf(vmin, __shfl_xor(vmin, 32));
-  if (qvalid && h == 0) atomicMin(sl.qmin + qrow, ordered_bits(vmin));
+  // the running minimum before this split's entered it (both lanes of a
+  // query ask); its value is first needed after pass 2's first copies are
+  // issued, so the two latencies overlap
+  const uint32_t run_old = qvalid ? atomicMin(sl.qmin + qrow, ordered_bits(vmin))
+                                  : ordered_bits(INFINITY);
 
   // pass 2: the rows within M of the smaller of the split's minimum and the
-  // running minimum as it stands now (both at or above the root's minimum)
-  const float thr = fminf(vmin, qvalid ? from_ordered(sl.qmin[qrow]) : vmin) + M;
+  // running minimum it met (both at or above the root's minimum).
+  // A lane keeps the rows it finds in registers (up to four; normally one or
+  // two) and publishes them after the scan with one global atomic: a wait
+  // for an atomic's returned value inside the scan also waits for every copy
+  // in flight.  A lane whose rows would not fit publishes at once.
   uint2* lent = sl.ent + (qvalid ? qrow : 0) * kRootCap;
+  int nkept = 0;
+  uint2 f0 = make_uint2(0u, 0u), f1 = f0, f2 = f0, f3 = f0;
+  auto publish_kept = [&]() {
+    const int pos = atomicAdd(sl.cnt + qrow, nkept);
+    if (pos < kRootCap) lent[pos] = f0;
+    if (nkept > 1 && pos + 1 < kRootCap) lent[pos + 1] = f1;
+    if (nkept > 2 && pos + 2 < kRootCap) lent[pos + 2] = f2;
+    if (nkept > 3 && pos + 3 < kRootCap) lent[pos + 3] = f3;
+    nkept = 0;
+  };
   scan([&](int64_t c0, const uint4* tile) {
+    const float thr = fminf(vmin, from_ordered(run_old)) + M;
     floatx16 val;
     gram(tile, val);
     if (__builtin_amdgcn_ballot_w64(qvalid && tile_min(val) <= thr)) {
       uint32_t hit = 0;
 #pragma unroll
       for (int v = 0; v < 16; ++v) hit |= (qvalid && val[v] <= thr) ? 1u << v : 0u;
-      if (hit) {
-        int pos = atomicAdd(sl.cnt + qrow, __popc(hit));
+      const int nh = __popc(hit);
+      if (nh > 0 && nkept + nh > 4) {
+        if (nkept > 0) publish_kept();
+        int pos = atomicAdd(sl.cnt + qrow, nh);
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
           if (hit & (1u << v)) {
@@ -1078,10 +1108,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
             ++pos;
           }
         }
+      } else if (nh > 0) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          if (hit & (1u << v)) {
+            const uint2 e = make_uint2(__float_as_uint(val[v]),
+                                       (uint32_t)(c0 + 8 * (v >> 2) + 4 * h + (v & 3)));
+            f0 = nkept == 0 ? e : f0;
+            f1 = nkept == 1 ? e : f1;
+            f2 = nkept == 2 ? e : f2;
+            f3 = nkept == 3 ? e : f3;
+            ++nkept;
+          }
+        }
       }
-      wait_copies(0);
     }
   });
+  if (nkept > 0) publish_kept();
 }
 
 void launch_root_gram(const float* Q, int64_t nq, int d, const RootAux& r, int dpad, int metric,

@@ -626,6 +626,49 @@ def test_root_shortlist_overflow_matches_in_kernel_scan(hn, ho, storage):
     idx.free()
 
 
+def _knn_positions(X, R):
+    """Positions of each row's R nearest other rows (exact, FP64)."""
+    X = X.astype(np.float64)
+    sq = (X * X).sum(1)
+    D = sq[:, None] + sq[None, :] - 2.0 * (X @ X.T)
+    np.fill_diagonal(D, np.inf)
+    return np.argsort(D, axis=1, kind="stable")[:, :R].astype(np.int32)
+
+
+@pytest.mark.parametrize("storage", [0, 2])
+def test_root_rows_past_a_lanes_room_match_in_kernel_scan(hn, storage):
+    """Groups of near copies in a complete root of 1,000 rows (24 in one
+    tile, one group split over two tiles) give a query more rows within the
+    shortlist margin than one lane of the Gram pass keeps in registers, while
+    the list itself does not overflow.  The results must equal the in-kernel
+    scan's and the tiled scan's, bit for bit."""
+    rng = np.random.default_rng(93)
+    n, d, s, R = 3000, 48, 1000, 12
+    X = (wl.uniform(n, d, 62) - 0.5).astype(np.float32)
+    groups = [list(range(0, 3)) + list(range(96, 102)), list(range(32, 38)),
+              list(range(64, 88)), list(range(200, 205))]
+    centres = []
+    for rows in groups:
+        base = X[rows[0]].copy()
+        X[rows] = base + 1e-5 * rng.standard_normal((len(rows), d)).astype(np.float32)
+        centres.append(base)
+    Q = np.concatenate([c + 1e-3 * rng.standard_normal((20, d)) for c in centres] +
+                       [wl.uniform(100, d, 63) - 0.5]).astype(np.float32)
+    adj0 = _knn_positions(X, R)
+    adj1 = _knn_positions(X[:s], R)
+    idx = hn.henn_import(to_dev(X), [None, np.arange(s, dtype=np.int32)], [adj0, adj1],
+                         storage=storage, degree=R, metric=0, graph=1, max_degree=R,
+                         root_complete_max=s)
+    a_i, a_d = hn.henn_search_batch(idx, to_dev(Q), k=10, ef=40)
+    for mode in (False, "valu"):
+        b_i, b_d = hn.henn_search_batch(idx, to_dev(Q), k=10, ef=40, root_kernel=mode)
+        _sync()
+        assert np.array_equal(a_i.cpu().numpy(), b_i.cpu().numpy()), mode
+        assert np.array_equal(a_d.cpu().numpy().view(np.uint32),
+                              b_d.cpu().numpy().view(np.uint32)), mode
+    idx.free()
+
+
 def test_autotune_caches_a_shape_and_keeps_results(hn, cfg1_sym_root):
     X, Q, oidx = cfg1_sym_root
     idx = _import(hn, X, oidx, storage=1)
