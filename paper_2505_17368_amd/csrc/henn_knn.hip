@@ -34,6 +34,9 @@ namespace henn {
 
 constexpr int kShort = 32;  // shortlist entries per lane half
 constexpr int kTileC = 32;  // candidates per LDS tile
+// candidates a lane of k_gram_topk_x3 stages in LDS before merging them into
+// its list (at most four enter per step of four values)
+constexpr int kX3Cand = 8;
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
@@ -337,6 +340,36 @@ __global__ __launch_bounds__(256, 2) void k_gram_topk_x3(const uint16_t* rows, i
     ti[j] = -1;
   }
 
+  // this lane's staged values (slot i of lane l at i * 64 + l) and their
+  // merge into the sorted list: strict comparisons, so equal values keep
+  // the order in which they were found
+  uint2* cand = reinterpret_cast<uint2*>(tnorm + 2 * kTileC) + wave * (kX3Cand * 64);
+  int ncand = 0;
+  auto merge = [&]() {
+    int m = ncand;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) m = max(m, __shfl_xor(m, o));
+    m = __builtin_amdgcn_readfirstlane(m);
+    for (int i = 0; i < m; ++i) {
+      const uint2 e = cand[i * 64 + lane];
+      float nd = i < ncand ? __uint_as_float(e.x) : INFINITY;
+      if (__builtin_amdgcn_ballot_w64(nd < td[KS - 1])) {
+        int32_t ni = (int32_t)e.y;
+#pragma unroll
+        for (int j = 0; j < KS; ++j) {
+          const bool sw = nd < td[j];
+          const float od = td[j];
+          const int32_t oi = ti[j];
+          td[j] = sw ? nd : od;
+          ti[j] = sw ? ni : oi;
+          nd = sw ? od : nd;
+          ni = sw ? oi : ni;
+        }
+      }
+    }
+    ncand = 0;
+  };
+
   static_assert(kMaxU4 <= 4, "at most four uint4 per thread and tile");
   // this thread's uint4 u of a tile (u < kMaxU4): row sr_u, slot sc_u; the
   // loads wait in pre_u (named registers: a small array here is kept in
@@ -406,25 +439,23 @@ __global__ __launch_bounds__(256, 2) void k_gram_topk_x3(const uint16_t* rows, i
       acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[s], acc, 0, 0, 0);
     }
 
+    // values below the list's last entry (as it stood at the last merge) are
+    // staged; a merge inserts the staged values of all lanes one slot at a
+    // time, so a value that only one lane keeps no longer costs the whole
+    // wave a pass of the insertion network
     bool any = false;
 #pragma unroll
     for (int v = 0; v < 16; ++v) any |= acc[v] < td[KS - 1];
     if (__builtin_amdgcn_ballot_w64(any)) {
 #pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int64_t crow = c0 + 8 * (v >> 2) + 4 * h + (v & 3);
-        float nd = crow == qrow ? INFINITY : acc[v];
-        if (__builtin_amdgcn_ballot_w64(nd < td[KS - 1])) {
-          int32_t ni = (int32_t)crow;
+      for (int g = 0; g < 4; ++g) {
+        if (__builtin_amdgcn_ballot_w64(ncand > kX3Cand - 4)) merge();
 #pragma unroll
-          for (int j = 0; j < KS; ++j) {
-            const bool sw = nd < td[j];
-            const float od = td[j];
-            const int32_t oi = ti[j];
-            td[j] = sw ? nd : od;
-            ti[j] = sw ? ni : oi;
-            nd = sw ? od : nd;
-            ni = sw ? oi : ni;
+        for (int u = 0; u < 4; ++u) {
+          const int64_t crow = c0 + 8 * g + 4 * h + u;  // value 4 g + u
+          if (acc[4 * g + u] < td[KS - 1] && crow != qrow) {
+            cand[ncand * 64 + lane] = make_uint2(__float_as_uint(acc[4 * g + u]), (uint32_t)crow);
+            ++ncand;
           }
         }
       }
@@ -437,6 +468,7 @@ __global__ __launch_bounds__(256, 2) void k_gram_topk_x3(const uint16_t* rows, i
 #undef HENN_X3_STASH
 #undef HENN_X3_LOAD
 #undef HENN_X3_PUT
+  merge();
   if (qvalid) {
     const int64_t o = qrow * (2 * KS) + h * KS;
 #pragma unroll
@@ -1185,6 +1217,7 @@ int64_t build_knn_graph(const float* vec, int64_t size, int dpad, int nchunks, i
   }
   const size_t lds = wide    ? sizeof(float) * (4 * kWideC * kSStride + dpad)
                      : split ? sizeof(uint4) * 2 * kTileC * (kp / 4 + 1) + sizeof(float) * 2 * kTileC
+                                 + sizeof(uint2) * 4 * 64 * kX3Cand
                              : sizeof(float) * (2 * (kTileC * (2 * kh + 4) + kTileC) + dpad);
   // FP32 Gram tiles over row blocks [b0, b0 + nbs) of the given rows
   auto launch_fp32_gram = [&](int64_t b0, unsigned nbs, const int32_t* row_list,
