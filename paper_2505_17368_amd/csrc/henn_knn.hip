@@ -259,18 +259,23 @@ __global__ __launch_bounds__(256, 2) void k_gram_topk(const float* vec, int64_t 
 // FP32 ones on the matrix cores; the shortlist, its output and the re-rank
 // are those of k_gram_topk.
 
-// rows [size][2 kp] BF16 (hi then lo) of the centred rows; zero past dpad
-__global__ void k_split_rows(const float* vec, const float* mean, int64_t size, int dpad,
-                             int kp, uint16_t* out) {
+// rows [size_pad][2 kp] BF16 (hi then lo) of the centred rows, zero past
+// dpad and for the padding rows; tnorm [size_pad]: the tile norm a row enters
+// the Gram with (|x'|^2 for L2, 0 for IP, +inf for the padding rows)
+__global__ void k_split_rows(const float* vec, const float* mean, const float* norms, int metric,
+                             int64_t size, int64_t size_pad, int dpad, int kp, uint16_t* out,
+                             float* tnorm) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= size * kp) return;
+  if (i >= size_pad * kp) return;
   const int64_t r = i / kp;
   const int c = (int)(i - r * kp);
-  const float v = c < dpad ? vec[r * dpad + c] - (mean ? mean[c] : 0.0f) : 0.0f;
+  const float v =
+      (r < size && c < dpad) ? vec[r * dpad + c] - (mean ? mean[c] : 0.0f) : 0.0f;
   const uint32_t hi = f32_to_bf16_rne(v);
   const uint32_t lo = f32_to_bf16_rne(v - bf16_to_f32(hi));
   out[r * 2 * kp + c] = (uint16_t)hi;
   out[r * 2 * kp + kp + c] = (uint16_t)lo;
+  if (c == 0) tnorm[r] = r < size ? (metric == 0 ? norms[r] : 0.0f) : INFINITY;
 }
 
 static float x3_split_coef(int dpad) {
@@ -292,26 +297,40 @@ __device__ inline bf16x8v scale_bf16x8(uint4 w, float f) {
   return __builtin_bit_cast(bf16x8v, make_uint4(u[0], u[1], u[2], u[3]));
 }
 
+// Copy instructions of one staged tile of k_gram_topk_x3 (64 slots of 16
+// bytes each): 32 rows of 4 S + 1 slots (hi, lo, one pad slot).
+__host__ __device__ constexpr int x3_tile_instrs(int S) { return (32 * (4 * S + 1) + 63) / 64; }
+
 // A block takes 128 rows (32 per wave) and streams the layer through LDS in
-// tiles of kTileC split rows, double buffered: the next tile's loads are
-// issued (clamped to valid rows, no branches) before the current tile is
-// multiplied and written to LDS after it.  A staged row is its hi and lo
-// halves plus one pad slot of 16 bytes, so that the 32 rows one
-// instruction reads fall on different banks.  The accumulator starts at
-// |y'|^2 + |x'|^2 (L2) or 0 (IP), +inf for rows past the end.
+// tiles of kTileC split rows.  The tiles arrive by the global-to-LDS copy
+// (global_load_lds_dwordx4: one instruction moves 64 chunks of 16 bytes into
+// 64 consecutive slots), in a ring of three buffers: the copies of the next
+// two tiles are in flight while one is multiplied.  A staged row is its hi
+// and lo halves plus one pad slot (a copy of its first chunk), so that the
+// 32 rows one instruction reads fall on different banks.  The rows and the
+// tile norms are padded to a multiple of 32 (zero rows, norm +inf), so every
+// copy reads inside them.  The accumulator starts at |y'|^2 + |x'|^2 (L2) or
+// 0 (IP), +inf for the padding rows.
 template <int S, int KS>
 __global__ __launch_bounds__(256, 2) void k_gram_topk_x3(const uint16_t* rows, int64_t size,
-                                                         const float* norms, int metric,
-                                                         float* sl_d, int32_t* sl_i,
+                                                         const float* norms, const float* tnorms,
+                                                         int metric, float* sl_d, int32_t* sl_i,
                                                          int64_t block0) {
   constexpr int KP = 16 * S;
   constexpr int kHalfU4 = KP / 8;           // uint4 per half row
   constexpr int kRowU4 = 2 * kHalfU4 + 1;   // staged row: hi, lo, pad
-  constexpr int kBufU4 = kTileC * kRowU4;
-  constexpr int kTileU4 = kTileC * 2 * kHalfU4;
-  constexpr int kMaxU4 = (kTileU4 + 255) / 256;
-  extern __shared__ __align__(16) uint4 lds_x3[];
-  float* tnorm = reinterpret_cast<float*>(lds_x3 + 2 * kBufU4);  // [2][kTileC]
+  constexpr int kJ = x3_tile_instrs(S);     // copy instructions per tile
+  constexpr int kSlots = 64 * kJ;           // >= kTileC * kRowU4
+  constexpr int kBufU4 = kSlots + 8;        // slots, then 32 norms
+  constexpr int kMaxJ = (kJ + 3) / 4;       // copy instructions of one wave per tile
+  static_assert(kTileC == 32, "a tile is one 32-row operand block");
+  static_assert(kMaxJ <= 5, "the waits below count at most six copies per wave and tile");
+  // three tile buffers (slots, then 32 norms) and the staged candidates of
+  // the four waves, as separate objects: the compiler then knows that a
+  // read of one buffer does not depend on the copies into another (69 KB
+  // at S = 8, two blocks a CU)
+  __shared__ uint4 buf0[kBufU4], buf1[kBufU4], buf2[kBufU4];
+  __shared__ uint2 cand_all[4 * 64 * kX3Cand];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int qc = lane & 31, h = lane >> 5;
   const int64_t qrow = (block0 + blockIdx.x) * 128 + wave * 32 + qc;
@@ -342,8 +361,8 @@ __global__ __launch_bounds__(256, 2) void k_gram_topk_x3(const uint16_t* rows, i
 
   // this lane's staged values (slot i of lane l at i * 64 + l) and their
   // merge into the sorted list: strict comparisons, so equal values keep
-  // the order in which they were found
-  uint2* cand = reinterpret_cast<uint2*>(tnorm + 2 * kTileC) + wave * (kX3Cand * 64);
+  // the order in which they were found; the row itself is dropped here
+  uint2* cand = cand_all + wave * (kX3Cand * 64);
   int ncand = 0;
   auto merge = [&]() {
     int m = ncand;
@@ -352,7 +371,7 @@ __global__ __launch_bounds__(256, 2) void k_gram_topk_x3(const uint16_t* rows, i
     m = __builtin_amdgcn_readfirstlane(m);
     for (int i = 0; i < m; ++i) {
       const uint2 e = cand[i * 64 + lane];
-      float nd = i < ncand ? __uint_as_float(e.x) : INFINITY;
+      float nd = (i < ncand && (int64_t)e.y != qrow) ? __uint_as_float(e.x) : INFINITY;
       if (__builtin_amdgcn_ballot_w64(nd < td[KS - 1])) {
         int32_t ni = (int32_t)e.y;
 #pragma unroll
@@ -370,56 +389,55 @@ __global__ __launch_bounds__(256, 2) void k_gram_topk_x3(const uint16_t* rows, i
     ncand = 0;
   };
 
-  static_assert(kMaxU4 <= 4, "at most four uint4 per thread and tile");
-  // this thread's uint4 u of a tile (u < kMaxU4): row sr_u, slot sc_u; the
-  // loads wait in pre_u (named registers: a small array here is kept in
-  // scratch memory by the compiler)
-  int sr0 = 0, sr1 = 0, sr2 = 0, sr3 = 0, sc0 = 0, sc1 = 0, sc2 = 0, sc3 = 0;
-  uint4 pre0 = {}, pre1 = {}, pre2 = {}, pre3 = {};
-#define HENN_X3_SRC(U)                                                                 \
-  if constexpr (U < kMaxU4) {                                                          \
-    const int idx_ = min((int)threadIdx.x + U * 256, kTileU4 - 1);                     \
-    sr##U = idx_ / (2 * kHalfU4);                                                      \
-    sc##U = idx_ - sr##U * (2 * kHalfU4);                                              \
+  // this wave's copy instructions j = wave + 4 u (u < kMaxJ, j < kJ); slot
+  // p = 64 j + lane of a tile takes chunk c of row r (p = r kRowU4 + c), the
+  // row's first chunk for a pad slot or a slot past the rows
+  int off0 = 0, off1 = 0, off2 = 0, off3 = 0, off4 = 0;
+#define HENN_X3_OFF(U)                                                                   \
+  if constexpr (U < kMaxJ) {                                                             \
+    const int p_ = 64 * (wave + 4 * U) + lane, r_ = p_ / kRowU4, c_ = p_ - r_ * kRowU4;  \
+    off##U = min(r_, kTileC - 1) * 2 * kHalfU4 +                                         \
+             ((p_ < kTileC * kRowU4 && c_ < 2 * kHalfU4) ? c_ : 0);                      \
   }
-  HENN_X3_SRC(0) HENN_X3_SRC(1) HENN_X3_SRC(2) HENN_X3_SRC(3)
-#undef HENN_X3_SRC
-  float pnorm = 0.0f;
-  int plast = 0;
-#define HENN_X3_LOAD(U)                                                                \
-  if constexpr (U < kMaxU4) pre##U = base_[(sr##U < last_ ? sr##U : last_) * 2 * kHalfU4 + sc##U];
-#define HENN_X3_PUT(U)                                                                 \
-  if constexpr (U < kMaxU4)                                                            \
-    if (kTileU4 % 256 == 0 || (int)threadIdx.x + U * 256 < kTileU4)                    \
-      buf_[sr##U * kRowU4 + sc##U] = pre##U;
-#define HENN_X3_FETCH(C0)                                                              \
-  {                                                                                    \
-    const int64_t rem_ = size - 1 - (C0);                                              \
-    const int last_ = rem_ < kTileC - 1 ? (int)rem_ : kTileC - 1;                      \
-    const uint4* base_ = reinterpret_cast<const uint4*>(rows + (C0) * 2 * KP);         \
-    HENN_X3_LOAD(0) HENN_X3_LOAD(1) HENN_X3_LOAD(2) HENN_X3_LOAD(3)                    \
-    const int rr_ = (int)(threadIdx.x & (kTileC - 1));                                 \
-    pnorm = norms[(C0) + (rr_ < last_ ? rr_ : last_)];                                 \
-    plast = last_;                                                                     \
-  }
-#define HENN_X3_STASH(B)                                                               \
-  {                                                                                    \
-    uint4* buf_ = lds_x3 + (B) * kBufU4;                                               \
-    HENN_X3_PUT(0) HENN_X3_PUT(1) HENN_X3_PUT(2) HENN_X3_PUT(3)                        \
-    if (threadIdx.x < kTileC)                                                          \
-      tnorm[(B) * kTileC + threadIdx.x] =                                              \
-          (int)threadIdx.x <= plast ? (l2 ? pnorm : 0.0f) : INFINITY;                  \
-  }
+  HENN_X3_OFF(0) HENN_X3_OFF(1) HENN_X3_OFF(2) HENN_X3_OFF(3) HENN_X3_OFF(4)
+#undef HENN_X3_OFF
+  const int per_tile = (kJ - wave + 3) / 4 + 1;  // this wave's copies per tile, norms included
+  typedef __attribute__((address_space(3))) void* lds_ptr;
+  auto issue = [&](int64_t c0, uint4* tile) {
+    const uint4* src = reinterpret_cast<const uint4*>(rows + c0 * 2 * KP);
+#define HENN_X3_COPY(U)                                                                  \
+  if constexpr (U < kMaxJ)                                                               \
+    if (wave + 4 * U < kJ)                                                               \
+      __builtin_amdgcn_global_load_lds(src + off##U, (lds_ptr)(tile + 64 * (wave + 4 * U)), \
+                                       16, 0, 0);
+    HENN_X3_COPY(0) HENN_X3_COPY(1) HENN_X3_COPY(2) HENN_X3_COPY(3) HENN_X3_COPY(4)
+#undef HENN_X3_COPY
+    if (lane < 8)
+      __builtin_amdgcn_global_load_lds(tnorms + c0 + 8 * wave + lane,
+                                       (lds_ptr)(reinterpret_cast<float*>(tile + kSlots) + 8 * wave),
+                                       4, 0, 0);
+  };
+  // waits until at most n of this wave's vector memory operations are
+  // outstanding (loads complete in order and nothing else is issued in the
+  // loop, so the copies issued before the last n are done)
+  auto wait_copies = [](int n) {
+    switch (n) {
+      case 0: __builtin_amdgcn_s_waitcnt(0xF70); break;
+      case 1: __builtin_amdgcn_s_waitcnt(0xF71); break;
+      case 2: __builtin_amdgcn_s_waitcnt(0xF72); break;
+      case 3: __builtin_amdgcn_s_waitcnt(0xF73); break;
+      case 4: __builtin_amdgcn_s_waitcnt(0xF74); break;
+      case 5: __builtin_amdgcn_s_waitcnt(0xF75); break;
+      default: __builtin_amdgcn_s_waitcnt(0xF76); break;
+    }
+  };
+  // a workgroup barrier that does not wait for the copies of the tiles ahead
+  // (LDS is coherent within the workgroup; the memory clobber keeps the
+  // compiler from moving LDS accesses across it)
+  auto lds_barrier = []() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); };
 
-  HENN_X3_FETCH(0)
-  HENN_X3_STASH(0)
-  __syncthreads();
-  int cur = 0;
-  for (int64_t c0 = 0; c0 < size; c0 += kTileC) {
-    const bool more = c0 + kTileC < size;
-    if (more) HENN_X3_FETCH(c0 + kTileC)
-    const uint4* buf = lds_x3 + cur * kBufU4;
-    const float4* tn = reinterpret_cast<const float4*>(tnorm + cur * kTileC);
+  auto body = [&](int64_t c0, const uint4* buf) {
+    const float4* tn = reinterpret_cast<const float4*>(buf + kSlots);
     floatx16 acc;
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
@@ -447,27 +465,42 @@ __global__ __launch_bounds__(256, 2) void k_gram_topk_x3(const uint16_t* rows, i
 #pragma unroll
     for (int v = 0; v < 16; ++v) any |= acc[v] < td[KS - 1];
     if (__builtin_amdgcn_ballot_w64(any)) {
+      const uint32_t cbase = (uint32_t)c0 + 4 * h;
 #pragma unroll
       for (int g = 0; g < 4; ++g) {
         if (__builtin_amdgcn_ballot_w64(ncand > kX3Cand - 4)) merge();
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-          const int64_t crow = c0 + 8 * g + 4 * h + u;  // value 4 g + u
-          if (acc[4 * g + u] < td[KS - 1] && crow != qrow) {
-            cand[ncand * 64 + lane] = make_uint2(__float_as_uint(acc[4 * g + u]), (uint32_t)crow);
+          if (acc[4 * g + u] < td[KS - 1]) {  // value 4 g + u: row c0 + 8 g + 4 h + u
+            cand[ncand * 64 + lane] = make_uint2(__float_as_uint(acc[4 * g + u]), cbase + 8 * g + u);
             ++ncand;
           }
         }
       }
     }
-    if (more) HENN_X3_STASH(cur ^ 1)
-    __syncthreads();
-    cur ^= 1;
+  };
+
+  // every wave of the block walks the same tiles (the barriers need all of
+  // them); the padded layer holds nt whole tiles
+  const int64_t nt = (size + kTileC - 1) / kTileC;
+  issue(0, buf0);
+  if (nt > 1) issue(kTileC, buf1);
+  for (int64_t t = 0; t < nt; t += 3) {
+#define HENN_X3_STEP(I, CUR, NEXT2)                                                      \
+  {                                                                                      \
+    const int64_t tt_ = t + (I);                                                         \
+    wait_copies(tt_ + 1 < nt ? per_tile : 0);                                            \
+    lds_barrier();                                                                       \
+    if (tt_ + 2 < nt) issue((tt_ + 2) * kTileC, NEXT2);                                  \
+    body(tt_ * kTileC, CUR);                                                             \
   }
-#undef HENN_X3_FETCH
-#undef HENN_X3_STASH
-#undef HENN_X3_LOAD
-#undef HENN_X3_PUT
+    HENN_X3_STEP(0, buf0, buf2)
+    if (t + 1 >= nt) break;
+    HENN_X3_STEP(1, buf1, buf0)
+    if (t + 2 >= nt) break;
+    HENN_X3_STEP(2, buf2, buf1)
+#undef HENN_X3_STEP
+  }
   merge();
   if (qvalid) {
     const int64_t o = qrow * (2 * KS) + h * KS;
@@ -1208,16 +1241,19 @@ int64_t build_knn_graph(const float* vec, int64_t size, int dpad, int nchunks, i
   const int kp = (dpad + 15) / 16 * 16;
   // the FP32 tiles' bound: 4 (dpad + 8) 2^-24 (|x'|^2 + max |y'|^2)
   const float coef = split ? x3_split_coef(dpad) : 4.0f * (float)(dpad + 8) * 0x1p-24f;
-  DevBuf<uint16_t> split_buf(split ? size * 2 * kp : 1);
+  // the split rows and their tile norms, padded to whole tiles
+  const int64_t size_pad = (size + kTileC - 1) / kTileC * kTileC;
+  DevBuf<uint16_t> split_buf(split ? size_pad * 2 * kp : 1);
+  DevBuf<float> tnorm_buf(split ? size_pad : 1);
   if (split) {
-    const int64_t n = size * kp;
+    const int64_t n = size_pad * kp;
     hipLaunchKernelGGL(k_split_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, vec,
-                       mean, size, dpad, kp, split_buf.get());
+                       mean, norms, metric, size, size_pad, dpad, kp, split_buf.get(),
+                       tnorm_buf.get());
     HENN_HIP(hipGetLastError());
   }
   const size_t lds = wide    ? sizeof(float) * (4 * kWideC * kSStride + dpad)
-                     : split ? sizeof(uint4) * 2 * kTileC * (kp / 4 + 1) + sizeof(float) * 2 * kTileC
-                                 + sizeof(uint2) * 4 * 64 * kX3Cand
+                     : split ? 0  // static LDS
                              : sizeof(float) * (2 * (kTileC * (2 * kh + 4) + kTileC) + dpad);
   // FP32 Gram tiles over row blocks [b0, b0 + nbs) of the given rows
   auto launch_fp32_gram = [&](int64_t b0, unsigned nbs, const int32_t* row_list,
@@ -1249,7 +1285,7 @@ int64_t build_knn_graph(const float* vec, int64_t size, int dpad, int nchunks, i
 #define HENN_X3(S_)                                                                           \
   case S_:                                                                                    \
     hipLaunchKernelGGL((k_gram_topk_x3<S_, kShort>), dim3(nbs), dim3(256), lds, st,           \
-                       split_buf.get(), size, norms, metric, sl_d, sl_i, b0);                 \
+                       split_buf.get(), size, norms, tnorm_buf.get(), metric, sl_d, sl_i, b0); \
     break;
         HENN_X3(1) HENN_X3(2) HENN_X3(3) HENN_X3(4) HENN_X3(5) HENN_X3(6) HENN_X3(7) HENN_X3(8)
 #undef HENN_X3
