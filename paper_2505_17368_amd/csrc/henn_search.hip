@@ -286,7 +286,7 @@ __device__ uint64_t root_scan_wave(const SearchArgs& a, const SearchLayer& R,
   return best;
 }
 
-// Exact check after the MFMA root shortlist (one wave per query).  With
+// Exact check after the MFMA root shortlist (one query per half wave).  With
 // a(y) the Gram value of root row y (BF16 products of the centred stored
 // values and the centred query, FP32 accumulation, the query-norm term
 // dropped) and c(y) the canonical distance, both are within an absolute
@@ -303,30 +303,60 @@ __device__ uint64_t root_scan_wave(const SearchArgs& a, const SearchLayer& R,
 // a threshold at or above a_min: so the list holds all of them unless it
 // overflowed, and then the wave scans the root.
 template <int KIND, int LPN, int CPL>
-__device__ uint64_t root_check_wave(const SearchArgs& a, int64_t qi, const float (&q)[CPL][8],
-                                    const RootShortlist& sl, int32_t* rows) {
-  static_assert(kRootCap == 64, "one list entry per lane");
-  constexpr int G = 64 / LPN;
-  const int lane = lane_id(), t = lane % LPN, g = lane / LPN;
+__global__ __launch_bounds__(256) void k_root_check(SearchArgs a, RootShortlist sl, uint64_t* out) {
+  // Two queries a wave, one a half wave (lanes 0..31 and 32..63): 10,000
+  // queries fit one round of resident waves.  A half holds its query's 64
+  // list entries two a lane and evaluates the kept rows G at a time.
+  static_assert(kRootCap == 64, "two list entries per lane of a half wave");
+  static_assert(LPN <= 32, "a lane group inside a half wave");
+  constexpr int G = 32 / LPN;
+  const int lane = lane_id(), t = lane % LPN, hl = lane & 31, half = lane >> 5;
+  const int g = hl / LPN;
+  const int64_t qi = (int64_t)blockIdx.x * 8 + (threadIdx.x >> 6) * 2 + half;
+  const bool qv = qi < a.nq;
+  const int64_t qs = qv ? qi : 0;  // reads of a missing second query stay in bounds
+  __shared__ int32_t rows_all[4][2][64];
+  int32_t* rows = rows_all[threadIdx.x >> 6][half];
   const SearchLayer& R = a.layer[a.num_layers - 1];
-  // one entry per lane (slots past the count hold stale values, dropped)
-  const int cnt = uni(sl.cnt[qi]);
-  const uint2 e = sl.ent[qi * kRootCap + lane];
-  if (cnt > kRootCap) return root_scan_wave<KIND, LPN, CPL>(a, R, q);
-  const float v = lane < cnt ? __uint_as_float(e.x) : INFINITY;
-  float amin = v;
+  float q[CPL][8];
+  // an overflowed list: the whole wave loads that query and scans the root
+  // for it (first, so that the scan's registers are free afterwards)
+  const int cnt = qv ? sl.cnt[qs] : 0;
+  const bool over = cnt > kRootCap;
+  const uint64_t ovm = ballot(over);
+  uint64_t best_over = ~0ull;
+#pragma unroll 1
+  for (int hq = 0; hq < 2; ++hq) {
+    if (ovm & (1ull << (32 * hq))) {
+      load_query<CPL>(a.Q + (qi - half + hq) * a.d, a.d, t, q);
+      const uint64_t k = root_scan_wave<KIND, LPN, CPL>(a, R, q);
+      if (half == hq) best_over = k;
+    }
+  }
+  load_query<CPL>(a.Q + qs * a.d, a.d, t, q);
+  // entries past the count hold stale values (dropped)
+  const uint2 e0 = sl.ent[qs * kRootCap + hl], e1 = sl.ent[qs * kRootCap + 32 + hl];
+  const bool l0 = !over && hl < cnt, l1 = !over && hl + 32 < cnt;
+  const float v0 = l0 ? __uint_as_float(e0.x) : INFINITY;
+  const float v1 = l1 ? __uint_as_float(e1.x) : INFINITY;
+  float amin = fminf(v0, v1);
 #pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) amin = fminf(amin, __shfl_xor(amin, m));
-  const float T = amin + sl.mq[qi];
-  // the rows with a <= T, gathered into rows[] and evaluated G at a time
-  const bool keep = lane < cnt && v <= T;
-  const uint64_t m = ballot(keep);
-  const int total = popc64(m);
+  for (int m = 16; m >= 1; m >>= 1) amin = fminf(amin, __shfl_xor(amin, m));
+  const float T = amin + (qv ? sl.mq[qs] : 0.0f);
+  // the rows with a <= T, gathered into rows[] (first entries, then second)
+  const bool k0 = l0 && v0 <= T, k1 = l1 && v1 <= T;
+  const uint32_t h0 = (uint32_t)(ballot(k0) >> (32 * half));
+  const uint32_t h1 = (uint32_t)(ballot(k1) >> (32 * half));
+  const uint32_t below = (1u << hl) - 1u;
+  const int n0 = __popc(h0), total = n0 + __popc(h1);
   wave_sync();
-  if (keep) rows[rank_below(m)] = (int32_t)e.y;
+  if (k0) rows[__popc(h0 & below)] = (int32_t)e0.y;
+  if (k1) rows[n0 + __popc(h1 & below)] = (int32_t)e1.y;
   wave_sync();
+  // the longer list sets the trip count: every lane joins each butterfly
+  const int tmax = max(total, __shfl_xor(total, 32));
   uint64_t best = ~0ull;
-  for (int b = 0; b < total; b += G) {
+  for (int b = 0; b < tmax; b += G) {
     const int32_t row = b + g < total ? rows[b + g] : -1;
     const bool valid = row >= 0;
     const float sc = (KIND == kFP8 && valid) ? R.scale[row] : 1.0f;
@@ -338,24 +368,12 @@ __device__ uint64_t root_check_wave(const SearchArgs& a, int64_t qi, const float
     }
   }
 #pragma unroll
-  for (int m2 = 32; m2 >= 1; m2 >>= 1) {
-    const uint64_t o = shfl_xor_u64(best, m2);
+  for (int m = 16; m >= 1; m >>= 1) {
+    const uint64_t o = shfl_xor_u64(best, m);
     best = o < best ? o : best;
   }
-  return best;
-}
-
-template <int KIND, int LPN, int CPL>
-__global__ __launch_bounds__(256) void k_root_check(SearchArgs a, RootShortlist sl, uint64_t* out) {
-  const int lane = lane_id(), t = lane % LPN;
-  const int64_t qi = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (qi >= a.nq) return;  // whole wave
-  float q[CPL][8];
-  load_query<CPL>(a.Q + qi * a.d, a.d, t, q);
-  __shared__ int32_t rows_all[4][64];
-  const uint64_t best =
-      root_check_wave<KIND, LPN, CPL>(a, qi, q, sl, rows_all[threadIdx.x >> 6]);
-  if (lane == 0) out[qi] = best;
+  if (over) best = best_over;
+  if (qv && hl == 0) out[qi] = best;
 }
 
 // Loads this query's k and beam width and finds the entry of the first
@@ -1232,7 +1250,7 @@ static bool launch_root_check_kind(const SearchArgs& a, const RootShortlist& sl,
                                    hipStream_t st) {
   int lpn = 0, cpl = 0;
   pick_lanes(a.nchunks, 0, &lpn, &cpl);
-  const dim3 grid((unsigned)((a.nq + 3) / 4));
+  const dim3 grid((unsigned)((a.nq + 7) / 8));  // eight queries a block
 #define HENN_TRY(L, C)                                                                       \
   if (lpn == L && cpl == C) {                                                                \
     hipLaunchKernelGGL((k_root_check<KIND, L, C>), grid, dim3(256), 0, st, a, sl, out);         \
