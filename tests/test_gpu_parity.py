@@ -460,6 +460,30 @@ def test_split_bf16_and_fp32_gram_give_the_same_graph(hn, ho, kind, n, d, metric
             assert set(adj[r].tolist()) == set(oadj[j].tolist())
 
 
+@pytest.mark.parametrize("n,d,metric", [(17, 64, 0), (33, 128, 0), (95, 40, 1), (130, 8, 0)])
+def test_split_gram_on_layers_of_one_or_a_few_tiles(hn, ho, n, d, metric):
+    """Layers of one partial tile up to a few tiles (the split-BF16 kernel
+    pads its rows and tile norms to whole 32-row tiles): the graph equals
+    the FP32 tiles' and the oracle's exact kNN rows."""
+    X = wl.gauss_mix(n, d, 4, 0.3, 44)
+    if metric == 1:
+        X /= np.linalg.norm(X, axis=1, keepdims=True)
+    Xd = to_dev(X)
+    out = []
+    for gram in (0, 1):
+        idx = hn.henn_build(Xd, degree=16, metric=metric, max_layers=0, gram=gram)
+        out.append(idx.export_layer(0)[1])
+        idx.free()
+    assert np.array_equal(out[0], out[1])
+    rows = np.arange(n, dtype=np.int64)
+    oadj, cut, order = ho.knn_rows(X, metric, np.arange(n, dtype=np.int32), rows, 16)
+    for r in range(n):
+        if not np.array_equal(out[0][r], oadj[r]):
+            assert order[r] <= exempt_tol(d), f"row {r}: {out[0][r]} vs {oadj[r]}"
+            if cut[r] > exempt_tol(d):
+                assert set(out[0][r].tolist()) == set(oadj[r].tolist())
+
+
 @pytest.mark.parametrize("d,metric", [(200, 0), (768, 1)])
 def test_wide_rows_end_to_end(hn, ho, d, metric):
     """Rows wider than 128 coordinates (K-sliced Gram build, 16-lane gathers):
