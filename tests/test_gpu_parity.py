@@ -626,6 +626,24 @@ def test_root_scan_kernel_matches_in_kernel_scan(hn, ho, storage, metric, d):
     idx.free()
 
 
+@pytest.mark.parametrize("nq", [1, 3, 9])
+def test_root_check_with_a_half_filled_last_wave(hn, nq):
+    """The exact check takes two queries a wave and eight a block: batches of
+    1, 3 and 9 queries leave half waves and whole waves without a query.  The
+    results must equal the in-kernel scan's, bit for bit."""
+    X = wl.uniform(5000, 64, 52) - 0.5
+    Q = wl.uniform(nq, 64, 53) - 0.5
+    idx = hn.henn_build(to_dev(X), degree=12, metric=0, storage=2, graph=1, max_degree=24,
+                        root_complete_max=700)
+    assert idx.num_layers >= 2
+    a_i, a_d = hn.henn_search_batch(idx, to_dev(Q), k=10, ef=40)
+    b_i, b_d = hn.henn_search_batch(idx, to_dev(Q), k=10, ef=40, root_kernel=False)
+    _sync()
+    assert np.array_equal(a_i.cpu().numpy(), b_i.cpu().numpy())
+    assert np.array_equal(a_d.cpu().numpy().view(np.uint32), b_d.cpu().numpy().view(np.uint32))
+    idx.free()
+
+
 @pytest.mark.parametrize("storage", [0, 2])
 def test_root_shortlist_overflow_matches_in_kernel_scan(hn, ho, storage):
     """A third of the points are copies of one point, so the root holds many
