@@ -363,9 +363,9 @@ __global__ __launch_bounds__(256, 2) void k_gram_topk_x3(const uint16_t* rows, i
   static_assert(kTileC == 32, "a tile is one 32-row operand block");
   static_assert(kMaxJ <= 5, "the waits below count at most six copies per wave and tile");
   // three tile buffers (slots, then 32 norms) and the staged candidates of
-  // the four waves, as separate objects: the compiler then knows that a
-  // read of one buffer does not depend on the copies into another (69 KB
-  // at S = 8, two blocks a CU)
+  // the four waves, as separate objects, so that the compiler can tell most
+  // reads of one buffer from the copies into another (69 KB at S = 8, two
+  // blocks a CU)
   __shared__ uint4 buf0[kBufU4], buf1[kBufU4], buf2[kBufU4];
   __shared__ uint2 cand_all[4 * 64 * kX3Cand];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
