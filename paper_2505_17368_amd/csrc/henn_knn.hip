@@ -297,43 +297,6 @@ __device__ inline bf16x8v scale_bf16x8(uint4 w, float f) {
   return __builtin_bit_cast(bf16x8v, make_uint4(u[0], u[1], u[2], u[3]));
 }
 
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-
-// One lane's reads of a staged tile of k_gram_topk_x3 at kp = 128: its row's
-// 16 operand chunks (hi chunks at 32 s bytes from arow, lo chunks 256 bytes
-// further) and the tile's four norm quads (32 g bytes from nrow), as one
-// block that waits for its own reads.  Written as LDS reads the compiler
-// cannot tell them apart from the global-to-LDS copies still in flight into
-// the other ring buffers, and waits for all of those first.
-__device__ inline void x3_read_tile_kp128(uint32_t arow, uint32_t nrow, u32x4 (&a)[16],
-                                          u32x4 (&n)[4]) {
-  asm volatile(
-      "ds_read_b128 %0, %20 offset:0\n\t"
-      "ds_read_b128 %1, %20 offset:32\n\t"
-      "ds_read_b128 %2, %20 offset:64\n\t"
-      "ds_read_b128 %3, %20 offset:96\n\t"
-      "ds_read_b128 %4, %20 offset:128\n\t"
-      "ds_read_b128 %5, %20 offset:160\n\t"
-      "ds_read_b128 %6, %20 offset:192\n\t"
-      "ds_read_b128 %7, %20 offset:224\n\t"
-      "ds_read_b128 %8, %20 offset:256\n\t"
-      "ds_read_b128 %9, %20 offset:288\n\t"
-      "ds_read_b128 %10, %20 offset:320\n\t"
-      "ds_read_b128 %11, %20 offset:352\n\t"
-      "ds_read_b128 %12, %20 offset:384\n\t"
-      "ds_read_b128 %13, %20 offset:416\n\t"
-      "ds_read_b128 %14, %20 offset:448\n\t"
-      "ds_read_b128 %15, %20 offset:480\n\t"
-      "ds_read_b128 %16, %21 offset:0\n\t"
-      "ds_read_b128 %17, %21 offset:32\n\t"
-      "ds_read_b128 %18, %21 offset:64\n\t"
-      "ds_read_b128 %19, %21 offset:96\n\t"
-      "s_waitcnt lgkmcnt(0)"
-      : "=v"(a[0]), "=v"(a[1]), "=v"(a[2]), "=v"(a[3]), "=v"(a[4]), "=v"(a[5]), "=v"(a[6]), "=v"(a[7]), "=v"(a[8]), "=v"(a[9]), "=v"(a[10]), "=v"(a[11]), "=v"(a[12]), "=v"(a[13]), "=v"(a[14]), "=v"(a[15]), "=v"(n[0]), "=v"(n[1]), "=v"(n[2]), "=v"(n[3])
-      : "v"(arow), "v"(nrow)
-      : "memory");
-}
-
 // Copy instructions of one staged tile of k_gram_topk_x3 (64 slots of 16
 // bytes each): 32 rows of 4 S + 1 slots (hi, lo, one pad slot).
 __host__ __device__ constexpr int x3_tile_instrs(int S) { return (32 * (4 * S + 1) + 63) / 64; }
@@ -474,48 +437,24 @@ __global__ __launch_bounds__(256, 2) void k_gram_topk_x3(const uint16_t* rows, i
   auto lds_barrier = []() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); };
 
   auto body = [&](int64_t c0, const uint4* buf) {
+    const float4* tn = reinterpret_cast<const float4*>(buf + kSlots);
     floatx16 acc;
-    if constexpr (S == 8) {
-      typedef __attribute__((address_space(3))) const uint4 lds_u4;
-      const uint32_t at = (uint32_t)(uintptr_t)(lds_u4*)buf;
-      u32x4 ar[16], nq[4];
-      x3_read_tile_kp128(at + (uint32_t)(qc * kRowU4 + h) * 16u,
-                         at + (uint32_t)(kSlots + h) * 16u, ar, nq);
 #pragma unroll
-      for (int g = 0; g < 4; ++g) {  // candidates 8 g + 4 h .. + 3
-        const float4 nr = __builtin_bit_cast(float4, nq[g]);
-        acc[4 * g + 0] = nr.x + qn;
-        acc[4 * g + 1] = nr.y + qn;
-        acc[4 * g + 2] = nr.z + qn;
-        acc[4 * g + 3] = nr.w + qn;
-      }
+    for (int g = 0; g < 4; ++g) {
+      const float4 nr = tn[2 * g + h];  // candidates 8 g + 4 h .. + 3
+      acc[4 * g + 0] = nr.x + qn;
+      acc[4 * g + 1] = nr.y + qn;
+      acc[4 * g + 2] = nr.z + qn;
+      acc[4 * g + 3] = nr.w + qn;
+    }
+    const uint4* arow = buf + qc * kRowU4;
 #pragma unroll
-      for (int s = 0; s < S; ++s) {
-        const bf16x8v ah = __builtin_bit_cast(bf16x8v, ar[s]);
-        const bf16x8v al = __builtin_bit_cast(bf16x8v, ar[8 + s]);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[s], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[s], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[s], acc, 0, 0, 0);
-      }
-    } else {
-      const float4* tn = reinterpret_cast<const float4*>(buf + kSlots);
-#pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        const float4 nr = tn[2 * g + h];  // candidates 8 g + 4 h .. + 3
-        acc[4 * g + 0] = nr.x + qn;
-        acc[4 * g + 1] = nr.y + qn;
-        acc[4 * g + 2] = nr.z + qn;
-        acc[4 * g + 3] = nr.w + qn;
-      }
-      const uint4* arow = buf + qc * kRowU4;
-#pragma unroll
-      for (int s = 0; s < S; ++s) {
-        const bf16x8v ah = __builtin_bit_cast(bf16x8v, arow[2 * s + h]);
-        const bf16x8v al = __builtin_bit_cast(bf16x8v, arow[kHalfU4 + 2 * s + h]);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[s], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[s], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[s], acc, 0, 0, 0);
-      }
+    for (int s = 0; s < S; ++s) {
+      const bf16x8v ah = __builtin_bit_cast(bf16x8v, arow[2 * s + h]);
+      const bf16x8v al = __builtin_bit_cast(bf16x8v, arow[kHalfU4 + 2 * s + h]);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[s], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[s], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[s], acc, 0, 0, 0);
     }
 
     // values below the list's last entry (as it stood at the last merge) are
